@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the EFTofDE particle-mesh gravity step on one MI355X.
+
+Workload: 256^3 grid and 256^3 particles in a 500 Mpc/h box, drawn from a
+lognormal density (log-sigma 1.5, power-law-break spectrum, seed 2), with
+alpha_B0 = -0.2, alpha_M0 = 0, a = 1 (Omega_m0 = 0.3071).  One step is the
+whole hot path: CIC deposit, Poisson multigrid, screened scalar-field
+multigrid to relative residual 1e-7 (both from a zero guess, every step
+solving the same input from scratch), 5-point gradient, CIC interpolation
+and kick.  Inputs are resident in device memory before the timed region.
+
+Modes
+  plain : FP64 everywhere (particles, fields, V-cycles).
+  fp32  : FP32 particles and fields; mixed-precision solves (FP32 V-cycles
+          on the FP64 defect, FP64 residual/test/coarsest solve).
+
+Prints one JSON line (rank 0).  Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--ng 256]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PARAMS = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
+
+
+def smoother_bytes_per_launch(ng, itemsize, with_tau):
+    """Algorithmic bytes of one finest-level half-sweep (one colour, ng^3/2
+    cells): read own colour (edges), other colour (faces), delta (and the FAS
+    source tau on the FP32 level), write own colour."""
+    per_cell = itemsize * (4 + (1 if with_tau else 0))
+    return per_cell * ng**3 // 2
+
+
+def run_mode(P, torch, mode, pos_np, ng, steps, warmup):
+    dt = torch.float64 if mode == "plain" else torch.float32
+    prec = "f64" if mode == "plain" else "mixed"
+    pos0 = torch.from_numpy(pos_np).to(device="cuda", dtype=dt).contiguous()
+    pos = pos0.clone()
+    vel = torch.zeros_like(pos)
+    psi = torch.zeros((ng, ng, ng), dtype=dt, device="cuda")
+    chi = torch.zeros_like(psi)
+    ws = P.Workspace(ng, pos.shape[1], 1 if dt == torch.float64 else 0, "any")
+    opts = P.MgOpts(rel_tol=1e-7, max_vcycles=60, n_pre=2, n_post=2, precision=prec, guess="zero")
+    for _ in range(warmup):
+        P.pm_step(pos, vel, ng, PARAMS, opts, opts, 1e-3, 0.0, psi, chi, ws=ws)
+    torch.cuda.synchronize()
+    P.pm_kernel_timing_read()  # clear
+    P.pm_kernel_timing_enable(True)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        reps.append(P.pm_step(pos, vel, ng, PARAMS, opts, opts, 1e-3, 0.0, psi, chi, ws=ws))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    P.pm_kernel_timing_enable(False)
+    kt = P.pm_kernel_timing_read()
+    last = reps[-1]
+    ok = all(r["status"] == 0 and r["scalar"]["rel_residual"] <= 1e-7 for r in reps)
+    return dict(ms_per_step=wall, converged=ok, scalar_vcycles=last["scalar"]["vcycles"],
+                poisson_vcycles=last["poisson"]["vcycles"], scalar_rel_residual=last["scalar"]["rel_residual"],
+                ms_deposit=last["ms_deposit"], ms_poisson=last["poisson"]["ms"], ms_scalar=last["scalar"]["ms"],
+                ms_force=last["ms_force"], kernel_timing=kt, itemsize=8 if dt == torch.float64 else 4)
+
+
+def roofline(res, ng):
+    """Dominant kernel: the finest-level scalar-field smoother of the mode."""
+    slot = "scalar_f64" if res["itemsize"] == 8 else "scalar_f32"
+    ms, n = res["kernel_timing"][slot]
+    if n == 0:
+        return None
+    bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4)
+    achieved = bytes_launch / (ms / n * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": f"k_smooth<{'double' if res['itemsize'] == 8 else 'float'},true> (finest level, one colour)",
+            "bytes_per_launch": bytes_launch, "avg_launch_us": round(ms / n * 1e3, 2), "launches": n}
+
+
+def cpu_baseline(pos_np, ng):
+    """The oracle on a bounded sample of the same workload, extrapolated to
+    ms per step: deposit and interpolation on 1/8 of the particles (x8),
+    exact FFT Poisson, one FAS V-cycle of the scalar field at full size times
+    the number of oracle V-cycles to 1e-7 on a 64^3 grid of the same
+    statistics, 5-point gradient."""
+    import numpy as np
+
+    import oracle
+    from workloads import lognormal_density
+
+    c = oracle.eft_coefficients(**PARAMS)
+    h = 1.0 / ng
+    sub = pos_np[:, ::8]
+    t0 = time.perf_counter()
+    rho_s = oracle.cic_deposit(sub, ng)
+    t_dep = (time.perf_counter() - t0) * 8
+    delta = oracle.density_contrast(rho_s)
+    t0 = time.perf_counter()
+    psi = oracle.solve_poisson(delta, c, h)
+    t_pois = time.perf_counter() - t0
+    b = c["xi"] * c["s"] * delta
+    t0 = time.perf_counter()
+    oracle.fas_solve(b, h, c["nu"], c["K"], tol=1e-30, max_cycles=1)
+    t_cyc = time.perf_counter() - t0
+    rho64 = lognormal_density(64, 500.0 * 64 / 256, seed=2)
+    _, rep64 = oracle.solve_chi(oracle.density_contrast(rho64), c, 1.0 / 64, tol=1e-7, max_cycles=200)
+    t0 = time.perf_counter()
+    g = oracle.gradient5(psi, h)
+    t_grad = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.cic_interpolate(g, sub)
+    t_interp = (time.perf_counter() - t0) * 8
+    ms = (t_dep + t_pois + rep64["vcycles"] * t_cyc + t_grad + t_interp) * 1e3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle on the {ng}^3 workload: deposit+interpolation on 1/8 of the particles (x8), "
+                       f"FFT Poisson, 1 FAS V-cycle at {ng}^3 ({t_cyc:.2f} s) x {rep64['vcycles']} V-cycles "
+                       f"(oracle count to 1e-7 at 64^3, same statistics), gradient; OpenMP threads {threads}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--ng", type=int, default=256)
+    ap.add_argument("--modes", default="plain,fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2604_15434_amd as P
+    from workloads import lognormal_particles
+
+    ng = args.ng
+    print(f"[bench] generating {ng}^3 lognormal particles", file=sys.stderr, flush=True)
+    pos_np, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=2)
+    results = {}
+    for mode in args.modes.split(","):
+        print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
+        results[mode] = run_mode(P, torch, mode, pos_np, ng, args.steps, args.warmup)
+        print(f"[bench] mode {mode}: {results[mode]['ms_per_step']:.3f} ms/step, "
+              f"V-cycles chi {results[mode]['scalar_vcycles']} psi {results[mode]['poisson_vcycles']}",
+              file=sys.stderr, flush=True)
+    head = "fp32" if "fp32" in results and results["fp32"]["converged"] else next(iter(results))
+    r = results[head]
+    line = {
+        "metric": "ms per 256^3 PM step (scalar MG to rel. residual 1e-7), plain vs learned+FP32",
+        "value": round(r["ms_per_step"], 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "plain" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"PM step, {ng}^3 grid, {ng}^3 lognormal particles (log-sigma 1.5, seed 2), "
+                               f"{500.0 * ng / 256:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7",
+                   "mode": head},
+        "modes": {m: {k: v for k, v in res.items() if k not in ("kernel_timing", "itemsize")}
+                  for m, res in results.items()},
+        "cells_vcycles_per_s": round(ng**3 * r["scalar_vcycles"] / (r["ms_scalar"] * 1e-3), 1)
+        if r["ms_scalar"] > 0 else None,
+        "roofline": roofline(r, ng),
+        "roofline_modes": {m: roofline(res, ng) for m, res in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(pos_np, ng)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+"""MI355X-native particle-mesh gravity step of the cubic-screening EFT of
+dark energy (HIP kernels behind the C ABI of include/pmeft.h).
+
+The Python functions below have the names of the C entry points and only
+marshal arguments: torch tensors on the GPU go in as device pointers with the
+current HIP stream, parameters and options as C structs.  Fields are
+``(ng, ng, ng)`` tensors in C order, particles ``(3, np)`` tensors (structure
+of arrays), float32 or float64.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+from . import _lib as L
+
+__all__ = [
+    "MgOpts", "PmError", "Workspace", "mg_poisson_solve", "mg_scalar_solve", "pm_deposit", "pm_eft_coefficients",
+    "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
+    "pm_strerror", "pm_workspace_bytes",
+]
+
+
+class PmError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {pm_strerror(code)} (code {code})")
+
+
+@dataclass
+class MgOpts:
+    rel_tol: float = 1e-7
+    max_vcycles: int = 50
+    n_pre: int = 2
+    n_post: int = 2
+    precision: str = "f64"  # "f64" | "mixed"
+    guess: str = "zero"     # "zero" | "given" | "linear"
+
+    def c(self):
+        prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED}[self.precision]
+        guess = {"zero": L.PM_GUESS_ZERO, "given": L.PM_GUESS_GIVEN, "linear": L.PM_GUESS_LINEAR}[self.guess]
+        return L.MgOpts(self.rel_tol, self.max_vcycles, self.n_pre, self.n_post, prec, guess)
+
+
+def _params(p):
+    return L.EftParams(float(p["omega_m0"]), float(p["alpha_b0"]), float(p["alpha_m0"]), float(p["a"]),
+                       int(p.get("screening", 1)), int(p.get("alpha_b_dot", 1)))
+
+
+def _dtype_code(t):
+    import torch
+
+    if t.dtype == torch.float64:
+        return L.PM_F64
+    if t.dtype == torch.float32:
+        return L.PM_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _check(t, shape, dt, name):
+    if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape) or _dtype_code(t) != dt:
+        raise ValueError(f"{name}: need a contiguous device tensor of shape {tuple(shape)} and matching dtype")
+
+
+def _stream(stream):
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _report(r):
+    return dict(status=r.status, vcycles=r.vcycles, rel_residual=r.rel_residual,
+                residual_hist=list(r.residual_hist[: min(max(r.vcycles + 1, 1), 64)]), mean_shift=r.mean_shift,
+                clamped_cells=r.clamped_cells, ms=r.ms)
+
+
+def pm_kernel_timing_enable(on=True):
+    rc = L.lib().pm_kernel_timing_enable(int(bool(on)))
+    if rc:
+        raise PmError(rc, "pm_kernel_timing_enable")
+
+
+def pm_kernel_timing_read():
+    """{slot: (total_ms, launches)} for the finest-level smoother launches
+    timed since the last read (slots: scalar_f64, scalar_f32, poisson_f64,
+    poisson_f32)."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_longlong * 4)()
+    rc = L.lib().pm_kernel_timing_read(ms, n)
+    if rc:
+        raise PmError(rc, "pm_kernel_timing_read")
+    names = ("scalar_f64", "scalar_f32", "poisson_f64", "poisson_f32")
+    return {k: (ms[q], n[q]) for q, k in enumerate(names)}
+
+
+def pm_strerror(code):
+    return L.lib().pm_strerror(int(code)).decode()
+
+
+def pm_eft_coefficients(params):
+    c = L.EftCoeffs()
+    rc = L.lib().pm_eft_coefficients(ctypes.byref(_params(params)), ctypes.byref(c))
+    out = {n: getattr(c, n) for n, _ in L.EftCoeffs._fields_}
+    out["lambda"] = out.pop("lambda_")
+    out["status"] = rc
+    return out
+
+
+def pm_grid_levels(ng):
+    return L.lib().pm_grid_levels(int(ng))
+
+
+def pm_workspace_bytes(ng, np_, dtype, precision="any"):
+    prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED, "any": L.PM_PREC_ANY}[precision]
+    return int(L.lib().pm_workspace_bytes(int(ng), int(np_), int(dtype), prec))
+
+
+class Workspace:
+    """Caller-owned scratch for the library (a uint8 device tensor)."""
+
+    def __init__(self, ng, np_=0, dtype=L.PM_F64, precision="any", device="cuda"):
+        import torch
+
+        self.nbytes = pm_workspace_bytes(ng, np_, dtype, precision)
+        if self.nbytes == 0:
+            raise PmError(L.PM_EINVAL, f"workspace for ng={ng}")
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        if self.buf.data_ptr() % 256:
+            raise RuntimeError("workspace is not 256-byte aligned")
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+
+def _ws(ws, ng, np_, dt):
+    return ws if ws is not None else Workspace(ng, np_, dt)
+
+
+def pm_deposit(pos, ng, rho, ws=None, stream=None):
+    dt = _dtype_code(pos)
+    npart = pos.shape[1]
+    _check(pos, (3, npart), dt, "pos")
+    _check(rho, (ng, ng, ng), dt, "rho")
+    ws = _ws(ws, ng, npart, dt)
+    rc = L.lib().pm_deposit(ctypes.c_void_p(pos.data_ptr()), npart, dt, int(ng), ctypes.c_void_p(rho.data_ptr()),
+                          ws.ptr, ws.nbytes, _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_deposit")
+
+
+def _grid_solve(fn, name, rho, params, opts, out, ws, stream):
+    dt = _dtype_code(rho)
+    ng = rho.shape[0]
+    _check(rho, (ng, ng, ng), dt, "rho")
+    _check(out, (ng, ng, ng), dt, "out")
+    ws = _ws(ws, ng, 0, dt)
+    rep = L.MgReport()
+    rc = fn(ctypes.c_void_p(rho.data_ptr()), int(ng), dt, ctypes.byref(_params(params)), ctypes.byref(opts.c()),
+            ctypes.c_void_p(out.data_ptr()), ctypes.byref(rep), ws.ptr, ws.nbytes, _stream(stream))
+    if rc not in (L.PM_OK, L.PM_ENOCONV):
+        raise PmError(rc, name)
+    return _report(rep)
+
+
+def mg_poisson_solve(rho, params, opts, psi, ws=None, stream=None):
+    return _grid_solve(L.lib().mg_poisson_solve, "mg_poisson_solve", rho, params, opts, psi, ws, stream)
+
+
+def mg_scalar_solve(rho, params, opts, chi, ws=None, stream=None):
+    return _grid_solve(L.lib().mg_scalar_solve, "mg_scalar_solve", rho, params, opts, chi, ws, stream)
+
+
+def pm_force_interp(psi, chi, params, pos, vel, dt_kick, acc_out=None, ws=None, stream=None):
+    dt = _dtype_code(pos)
+    ng = psi.shape[0]
+    npart = pos.shape[1]
+    _check(psi, (ng, ng, ng), dt, "psi")
+    if chi is not None:
+        _check(chi, (ng, ng, ng), dt, "chi")
+    _check(pos, (3, npart), dt, "pos")
+    _check(vel, (3, npart), dt, "vel")
+    if acc_out is not None:
+        _check(acc_out, (3, npart), dt, "acc_out")
+    ws = _ws(ws, ng, npart, dt)
+    rc = L.lib().pm_force_interp(ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(chi.data_ptr() if chi is not None else 0),
+                               int(ng), dt, ctypes.byref(_params(params)), ctypes.c_void_p(pos.data_ptr()), npart,
+                               ctypes.c_void_p(vel.data_ptr()), float(dt_kick),
+                               ctypes.c_void_p(acc_out.data_ptr() if acc_out is not None else 0), ws.ptr, ws.nbytes,
+                               _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_force_interp")
+
+
+def pm_step(pos, vel, ng, params, poisson_opts, scalar_opts, dt_kick, dt_drift, psi, chi, ws=None, stream=None):
+    dt = _dtype_code(pos)
+    npart = pos.shape[1]
+    _check(pos, (3, npart), dt, "pos")
+    _check(vel, (3, npart), dt, "vel")
+    _check(psi, (ng, ng, ng), dt, "psi")
+    _check(chi, (ng, ng, ng), dt, "chi")
+    ws = _ws(ws, ng, npart, dt)
+    rep = L.StepReport()
+    rc = L.lib().pm_step(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()), npart, int(ng), dt,
+                       ctypes.byref(_params(params)), ctypes.byref(poisson_opts.c()), ctypes.byref(scalar_opts.c()),
+                       float(dt_kick), float(dt_drift), ctypes.c_void_p(psi.data_ptr()),
+                       ctypes.c_void_p(chi.data_ptr()), ctypes.byref(rep), ws.ptr, ws.nbytes, _stream(stream))
+    if rc not in (L.PM_OK, L.PM_ENOCONV):
+        raise PmError(rc, "pm_step")
+    return dict(poisson=_report(rep.poisson), scalar=_report(rep.scalar), ms_deposit=rep.ms_deposit,
+                ms_force=rep.ms_force, ms_total=rep.ms_total, status=rc)

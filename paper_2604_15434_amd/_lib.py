@@ -1,0 +1,87 @@
+"""ctypes binding of libpmeft.so (the C ABI in include/pmeft.h).
+
+Argument marshalling only: tensors are passed as device pointers with the
+caller's current HIP stream; every step of the computation runs in the
+library's HIP kernels.  The first call fails with an ImportError if the
+library has not been built (``python -m paper_2604_15434_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmeft.so")
+
+PM_OK, PM_EINVAL, PM_EUNSTABLE, PM_ENOCONV, PM_ENONFINITE, PM_EHIP, PM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+PM_F32, PM_F64 = 0, 1
+PM_PREC_F64, PM_PREC_MIXED, PM_PREC_ANY = 0, 1, 2
+PM_GUESS_ZERO, PM_GUESS_GIVEN, PM_GUESS_LINEAR = 0, 1, 2
+
+
+class EftParams(ctypes.Structure):
+    _fields_ = [("omega_m0", ctypes.c_double), ("alpha_b0", ctypes.c_double), ("alpha_m0", ctypes.c_double),
+                ("a", ctypes.c_double), ("screening", ctypes.c_int), ("alpha_b_dot", ctypes.c_int)]
+
+
+class EftCoeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("omega_m_a", "E2", "alpha_b", "alpha_m", "geff", "C2", "C4", "nu",
+                                                "xi", "mu_chi", "mu_psi", "s", "K", "lambda_")]
+
+
+class MgOpts(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_vcycles", ctypes.c_int), ("n_pre", ctypes.c_int),
+                ("n_post", ctypes.c_int), ("precision", ctypes.c_int), ("guess", ctypes.c_int)]
+
+
+class MgReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("vcycles", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("residual_hist", ctypes.c_double * 64), ("mean_shift", ctypes.c_double),
+                ("clamped_cells", ctypes.c_longlong), ("ms", ctypes.c_float)]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [("poisson", MgReport), ("scalar", MgReport), ("ms_deposit", ctypes.c_float),
+                ("ms_force", ctypes.c_float), ("ms_total", ctypes.c_float)]
+
+
+EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_deposit", "mg_poisson_solve",
+           "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
+           "pm_strerror")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_15434_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, ll, i, d = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_longlong, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    lib.pm_eft_coefficients.argtypes = [P(EftParams), P(EftCoeffs)]
+    lib.pm_grid_levels.argtypes = [i]
+    lib.pm_workspace_bytes.argtypes = [i, ll, i, i]
+    lib.pm_workspace_bytes.restype = sz
+    lib.pm_deposit.argtypes = [vp, ll, i, i, vp, vp, sz, vp]
+    lib.mg_poisson_solve.argtypes = [vp, i, i, P(EftParams), P(MgOpts), vp, P(MgReport), vp, sz, vp]
+    lib.mg_scalar_solve.argtypes = [vp, i, i, P(EftParams), P(MgOpts), vp, P(MgReport), vp, sz, vp]
+    lib.pm_force_interp.argtypes = [vp, vp, i, i, P(EftParams), vp, ll, vp, d, vp, vp, sz, vp]
+    lib.pm_step.argtypes = [vp, vp, ll, i, i, P(EftParams), P(MgOpts), P(MgOpts), d, d, vp, vp, P(StepReport),
+                            vp, sz, vp]
+    lib.pm_kernel_timing_enable.argtypes = [i]
+    lib.pm_kernel_timing_read.argtypes = [P(d), P(ll)]
+    lib.pm_strerror.argtypes = [i]
+    lib.pm_strerror.restype = ctypes.c_char_p
+    for name in ("pm_eft_coefficients", "pm_grid_levels", "pm_deposit", "mg_poisson_solve", "mg_scalar_solve",
+                 "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read"):
+        getattr(lib, name).restype = i
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    """The loaded library; raises ImportError if libpmeft.so was not built."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB

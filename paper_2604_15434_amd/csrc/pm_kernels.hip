@@ -1,0 +1,231 @@
+// Particle-mesh kernels: Cloud-in-Cell deposit (Sec. 3.6.2), the 5-point
+// gradient of the total potential (Sec. 3.5.2, eq. force) and the CIC
+// interpolation of the acceleration with the kick.
+//
+// CIC convention: a particle at x lies between the centres of cells i0 and
+// i0 + 1 with u = x ng - 1/2, i0 = floor(u), f = u - i0; weights (1 - f) and f
+// per axis, periodic wrap.  The same kernel is used to deposit and to
+// interpolate, so a lone particle feels no force from itself.
+#include "pmeft_internal.h"
+
+#include <math.h>
+
+namespace pmeft {
+
+__device__ __forceinline__ int wrapn(int i, int n)
+{
+    if (i >= 0 && i < n)
+        return i;
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Base cell and fraction along one axis.  Non-finite or absurd coordinates
+// (beyond +-2^30 cells) return false: the particle is skipped rather than
+// indexing out of range.
+__device__ __forceinline__ bool cic_axis(double x, int ng, int &i0, int &i1, double &f)
+{
+    const double u = x * (double)ng - 0.5;
+    if (!(u > -1073741824.0 && u < 1073741824.0))
+        return false;
+    const double fl = floor(u);
+    f = u - fl;
+    const int ii = (int)fl;
+    i0 = wrapn(ii, ng);
+    i1 = wrapn(ii + 1, ng);
+    return true;
+}
+
+// ------------------------------------------------------------------ deposit
+// Each corner weight w in [0, 1] is added as round(w * 2^40) to a 64-bit
+// integer, which makes the sum independent of particle order (bitwise
+// reproducible) and loses at most 2^-41 per weight.
+template <typename Tp>
+__global__ __launch_bounds__(kBlock) void k_deposit_fixed(const Tp *__restrict__ pos, unsigned np, int ng,
+                                                          unsigned long long *__restrict__ acc, Span sp)
+{
+    PM_SPAN_LOOP(p, sp)
+    {
+        int x0, x1, y0, y1, z0, z1;
+        double fx, fy, fz;
+        if (!cic_axis((double)pos[p], ng, x0, x1, fx) || !cic_axis((double)pos[np + p], ng, y0, y1, fy) ||
+            !cic_axis((double)pos[2 * np + p], ng, z0, z1, fz))
+            continue;
+        const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        const int ix[2] = {x0, x1}, iy[2] = {y0, y1}, iz[2] = {z0, z1};
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    const double w = wx[a] * wy[b] * wz[c];
+                    const unsigned long long q = (unsigned long long)(w * kFixScale + 0.5);
+                    if (q)
+                        atomicAdd(&acc[((unsigned)ix[a] * ng + iy[b]) * ng + iz[c]], q);
+                }
+    }
+}
+
+void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc, hipStream_t st)
+{
+    const Span sp = make_span(np);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_deposit_fixed<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)pos,
+                           (unsigned)np, ng, acc, sp);
+    else
+        hipLaunchKernelGGL((k_deposit_fixed<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)pos,
+                           (unsigned)np, ng, acc, sp);
+}
+
+// fixed point (natural layout) -> packed delta_raw = rho - 1, with its sum.
+__global__ __launch_bounds__(kBlock) void k_fixed_to_delta(const unsigned long long *__restrict__ acc, int n,
+                                                           double rho_scale, double *__restrict__ delta, ReduceSlot rs,
+                                                           Span sp)
+{
+    const int nh = n / 2;
+    const unsigned half = (unsigned)n * n * nh;
+    double s[1] = {0.0};
+    PM_SPAN_LOOP(e, sp)
+    {
+        const int c = e >= half;
+        const unsigned ec = e - (c ? half : 0u);
+        int i, j, kh;
+        split(ec, nh, n, i, j, kh);
+        const int k = 2 * kh + ((i + j + c) & 1);
+        const double rho = (double)acc[((unsigned)i * n + j) * n + k] * (rho_scale / kFixScale);
+        const double d = rho - 1.0;
+        delta[e] = d;
+        s[0] += d;
+    }
+    block_partials<1>(s, rs, sp);
+}
+
+void launch_fixed_to_delta(const unsigned long long *acc, int ng, double rho_scale, double *delta_packed, ReduceSlot rs,
+                           hipStream_t st)
+{
+    const Span sp = make_span((unsigned long long)ng * ng * ng);
+    hipLaunchKernelGGL(k_fixed_to_delta, dim3(sp.nblocks), dim3(kBlock), 0, st, acc, ng, rho_scale, delta_packed, rs,
+                       sp);
+    launch_finalize(rs, sp, 1, rs.out, st);
+}
+
+// ----------------------------------------------------------------- gradient
+__device__ __forceinline__ double ld_packed(const double *f, int n, int nh, long long half, int i, int j, int k)
+{
+    const int c = (i + j + k) & 1;
+    return f[(c ? (unsigned)half : 0u) + ((unsigned)i * n + j) * nh + (k >> 1)];
+}
+
+// g = -D5 Psi_tot, D5 f_i = (f_{i-2} - 8 f_{i-1} + 8 f_{i+1} - f_{i+2}) / (12 h),
+// Psi_tot = Psi_N + xi chi; written as (gx, gy, gz, 0) per cell in natural
+// order.
+template <typename Tg>
+__global__ __launch_bounds__(kBlock) void k_gradient(const double *__restrict__ psi, const double *__restrict__ chi,
+                                                     double xi, int n, Tg *__restrict__ g4, Span sp)
+{
+    const int nh = n / 2;
+    const long long half = (long long)n * n * nh;
+    const double s = -(double)n / 12.0;  // -1/(12 h)
+    PM_SPAN_LOOP(e, sp)
+    {
+        int i, j, k;
+        split((unsigned)e, (unsigned)n, (unsigned)n, i, j, k);
+        auto P = [&](int a, int b, int c) -> double {
+            a = a < 0 ? a + n : (a >= n ? a - n : a);
+            b = b < 0 ? b + n : (b >= n ? b - n : b);
+            c = c < 0 ? c + n : (c >= n ? c - n : c);
+            double v = ld_packed(psi, n, nh, half, a, b, c);
+            if (chi)
+                v += xi * ld_packed(chi, n, nh, half, a, b, c);
+            return v;
+        };
+        const double gx = s * (P(i - 2, j, k) - 8.0 * P(i - 1, j, k) + 8.0 * P(i + 1, j, k) - P(i + 2, j, k));
+        const double gy = s * (P(i, j - 2, k) - 8.0 * P(i, j - 1, k) + 8.0 * P(i, j + 1, k) - P(i, j + 2, k));
+        const double gz = s * (P(i, j, k - 2) - 8.0 * P(i, j, k - 1) + 8.0 * P(i, j, k + 1) - P(i, j, k + 2));
+        Tg *o = g4 + 4 * (size_t)e;
+        o[0] = (Tg)gx;
+        o[1] = (Tg)gy;
+        o[2] = (Tg)gz;
+        o[3] = (Tg)0;
+    }
+}
+
+void launch_gradient(const double *psi, const double *chi, double xi, int ng, void *g4, pm_dtype dt, hipStream_t st)
+{
+    const Span sp = make_span((unsigned long long)ng * ng * ng);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_gradient<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, psi, chi, xi, ng,
+                           (double *)g4, sp);
+    else
+        hipLaunchKernelGGL((k_gradient<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, psi, chi, xi, ng, (float *)g4,
+                           sp);
+}
+
+// ---------------------------------------------------------- interpolation
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_interp_kick(const T *__restrict__ g4, int ng, T *__restrict__ pos,
+                                                        unsigned np, T *__restrict__ vel, double dt_kick,
+                                                        double dt_drift, T *__restrict__ acc_out, Span sp)
+{
+    PM_SPAN_LOOP(p, sp)
+    {
+        int x0, x1, y0, y1, z0, z1;
+        double fx, fy, fz;
+        const bool ok = cic_axis((double)pos[p], ng, x0, x1, fx) && cic_axis((double)pos[np + p], ng, y0, y1, fy) &&
+                        cic_axis((double)pos[2 * np + p], ng, z0, z1, fz);
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        if (ok) {
+            const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+            const int ix[2] = {x0, x1}, iy[2] = {y0, y1}, iz[2] = {z0, z1};
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const double w = wx[a] * wy[b] * wz[c];
+                        const T *gv = g4 + 4 * (((unsigned)ix[a] * ng + iy[b]) * ng + iz[c]);
+                        ax += w * (double)gv[0];
+                        ay += w * (double)gv[1];
+                        az += w * (double)gv[2];
+                    }
+        }
+        const double vx = (double)vel[p] + ax * dt_kick;
+        const double vy = (double)vel[np + p] + ay * dt_kick;
+        const double vz = (double)vel[2 * np + p] + az * dt_kick;
+        vel[p] = (T)vx;
+        vel[np + p] = (T)vy;
+        vel[2 * np + p] = (T)vz;
+        if (acc_out) {
+            acc_out[p] = (T)ax;
+            acc_out[np + p] = (T)ay;
+            acc_out[2 * np + p] = (T)az;
+        }
+        if (dt_drift != 0.0 && ok) {
+            double x = (double)pos[p] + vx * dt_drift;
+            double y = (double)pos[np + p] + vy * dt_drift;
+            double z = (double)pos[2 * np + p] + vz * dt_drift;
+            x -= floor(x);
+            y -= floor(y);
+            z -= floor(z);
+            pos[p] = (T)(x >= 1.0 ? 0.0 : x);
+            pos[np + p] = (T)(y >= 1.0 ? 0.0 : y);
+            pos[2 * np + p] = (T)(z >= 1.0 ? 0.0 : z);
+        }
+    }
+}
+
+void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long long np, void *vel, double dt_kick,
+                        double dt_drift, void *acc_out, hipStream_t st)
+{
+    const Span sp = make_span(np);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_interp_kick<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)g4, ng,
+                           (double *)pos, (unsigned)np, (double *)vel, dt_kick, dt_drift, (double *)acc_out, sp);
+    else
+        hipLaunchKernelGGL((k_interp_kick<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)g4, ng,
+                           (float *)pos, (unsigned)np, (float *)vel, dt_kick, dt_drift, (float *)acc_out, sp);
+}
+
+}  // namespace pmeft

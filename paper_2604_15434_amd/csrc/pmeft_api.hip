@@ -1,0 +1,851 @@
+// Host side of libpmeft.so: coefficients, workspace planning, the multigrid
+// drivers (FP64 and mixed precision) and the C ABI declared in pmeft.h.
+#include "pmeft_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+namespace pmeft {
+
+// ------------------------------------------------------------ coefficients
+// Secs. 2.2-2.5 and 3.1 (see pmeft.h for the definitions).
+static int coefficients(const pm_eft_params &p, pm_eft_coeffs &c)
+{
+    const double om0 = p.omega_m0, a = p.a;
+    if (!(om0 > 0.0 && om0 < 1.0) || !(a > 0.0))
+        return PM_EINVAL;
+    const double om = om0 / (om0 + (1.0 - om0) * a * a * a);
+    const double E2 = om0 / (a * a * a) + 1.0 - om0;
+    const double ab = p.alpha_b0 * (1.0 - om) / (1.0 - om0);
+    const double am = p.alpha_m0 * (1.0 - om) / (1.0 - om0);
+    const double geff = pow(om, p.alpha_m0 / (3.0 * (1.0 - om0)));
+    const double hdot = -1.5 * om;                         // Hdot / H^2
+    const double abdot = p.alpha_b_dot ? 3.0 * om * ab : 0.0;  // d alpha_B / d ln a
+    const double C2 = -am + ab * (1.0 + am) + (1.0 + ab) * hdot + abdot + 1.5 * om * geff;
+    const double C4 = p.screening ? (-4.0 * ab + 2.0 * am) : 0.0;
+    c.omega_m_a = om;
+    c.E2 = E2;
+    c.alpha_b = ab;
+    c.alpha_m = am;
+    c.geff = geff;
+    c.C2 = C2;
+    c.C4 = C4;
+    c.nu = 2.0 * ab * am - ab * ab - C2;
+    c.xi = ab - am;
+    c.s = 1.5 * geff * a * om0;
+    c.K = C4 / (4.0 * E2 * a * a * a * a);
+    c.mu_chi = c.nu != 0.0 ? c.xi / c.nu : 0.0;
+    c.mu_psi = c.nu != 0.0 ? 1.0 + c.xi * c.xi / c.nu : 1.0;
+    c.lambda = c.nu != 0.0 ? c.K * c.s * c.xi / (c.nu * c.nu) : 0.0;
+    if (c.xi != 0.0 && !(c.nu > 0.0))
+        return PM_EUNSTABLE;
+    return PM_OK;
+}
+
+static int grid_levels(int ng)
+{
+    if (ng < 8 || ng > 1024)
+        return 0;
+    int n = ng, l = 1;
+    while (n % 2 == 0 && n / 2 >= 4) {
+        n /= 2;
+        l++;
+    }
+    if (n != 4 && n != 6)
+        return 0;
+    return l;
+}
+
+// ----------------------------------------------------------- workspace plan
+enum { kPrecF64 = 1, kPrecMixed = 2 };
+
+struct Plan {
+    int ng = 0, nlev = 0;
+    long long N = 0, np = 0;
+    int n[kMaxLevels] = {};
+    size_t total = 0;
+    size_t red_partials = 0, red_counter = 0, red_out = 0, csum64 = 0, csum32 = 0, outer_out = 0;
+    size_t delta64[kMaxLevels] = {};
+    size_t psi64 = 0, chi64 = 0;
+    size_t p64[kMaxLevels] = {}, q64[kMaxLevels] = {}, t64[kMaxLevels] = {}, x064[kMaxLevels] = {};
+    size_t d32[kMaxLevels] = {}, p32[kMaxLevels] = {}, q32[kMaxLevels] = {}, t32[kMaxLevels] = {},
+           x032[kMaxLevels] = {};
+    size_t fixacc = 0, g4 = 0;
+    int precs = 0;
+};
+
+static size_t take(size_t &cur, size_t bytes)
+{
+    const size_t o = cur;
+    cur += (bytes + 255) & ~(size_t)255;
+    return o;
+}
+
+static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
+{
+    P = Plan();
+    P.nlev = grid_levels(ng);
+    if (!P.nlev)
+        return false;
+    P.ng = ng;
+    P.np = np;
+    P.precs = precs;
+    P.N = (long long)ng * ng * ng;
+    for (int l = 0, m = ng; l < P.nlev; l++, m /= 2)
+        P.n[l] = m;
+    size_t c = 0;
+    P.red_partials = take(c, sizeof(double) * 8 * kMaxBlocks);
+    P.red_counter = take(c, 256);
+    P.red_out = take(c, sizeof(double) * 8);
+    P.outer_out = take(c, sizeof(double) * 8);
+    P.csum64 = take(c, sizeof(double) * 2 * kMaxLevels);
+    P.csum32 = take(c, sizeof(double) * 2 * kMaxLevels);
+    for (int l = 0; l < P.nlev; l++)
+        P.delta64[l] = take(c, sizeof(double) * (size_t)P.n[l] * P.n[l] * P.n[l]);
+    P.psi64 = take(c, sizeof(double) * P.N);
+    P.chi64 = take(c, sizeof(double) * P.N);
+    if (precs & kPrecF64) {
+        for (int l = 0; l < P.nlev; l++) {
+            const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
+            if (l > 0)
+                P.p64[l] = take(c, sizeof(double) * m3);
+            P.q64[l] = take(c, sizeof(double) * m3);
+            if (l > 0) {
+                P.t64[l] = take(c, sizeof(double) * m3);
+                P.x064[l] = take(c, sizeof(double) * m3);
+            }
+        }
+    }
+    if (precs & kPrecMixed) {
+        for (int l = 0; l < P.nlev; l++) {
+            const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
+            P.d32[l] = take(c, sizeof(float) * m3);
+            P.p32[l] = take(c, sizeof(float) * m3);
+            P.q32[l] = take(c, sizeof(float) * m3);
+            P.t32[l] = take(c, sizeof(float) * m3);
+            P.x032[l] = take(c, sizeof(float) * m3);
+        }
+    }
+    if (np > 0) {
+        P.fixacc = take(c, sizeof(unsigned long long) * P.N);
+        P.g4 = take(c, (dt == PM_F64 ? sizeof(double) : sizeof(float)) * 4 * P.N);
+    }
+    P.total = c + 256;
+    return true;
+}
+
+// ---------------------------------------------------------------- context
+struct Ctx {
+    Plan P;
+    char *ws = nullptr;
+    hipStream_t st = nullptr;
+    ReduceSlot rs;
+    double *csum64 = nullptr, *csum32 = nullptr, *outer_out = nullptr;
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+#define PM_HIP(call)                                                                                                   \
+    do {                                                                                                               \
+        if ((call) != hipSuccess)                                                                                      \
+            return PM_EHIP;                                                                                            \
+    } while (0)
+
+static int launched()
+{
+    return hipGetLastError() == hipSuccess ? PM_OK : PM_EHIP;
+}
+
+static int setup_ctx(Ctx &C, void *ws, size_t ws_bytes, int ng, long long np, pm_dtype dt, int precs,
+                     pm_stream_t stream)
+{
+    if (!ws)
+        return PM_EINVAL;
+    if (!make_plan(C.P, ng, np, dt, precs))
+        return PM_EINVAL;
+    if (ws_bytes < C.P.total)
+        return PM_ENOMEM;
+    // 256-byte alignment of the caller's buffer
+    if (((uintptr_t)ws) & 255)
+        return PM_EINVAL;
+    C.ws = (char *)ws;
+    C.st = (hipStream_t)stream;
+    C.rs.partials = C.at<double>(C.P.red_partials);
+    C.rs.counter = C.at<unsigned>(C.P.red_counter);
+    C.rs.out = C.at<double>(C.P.red_out);
+    C.csum64 = C.at<double>(C.P.csum64);
+    C.csum32 = C.at<double>(C.P.csum32);
+    C.outer_out = C.at<double>(C.P.outer_out);
+    launch_zero(C.ws + C.P.red_counter, 256, C.st);
+    return launched();
+}
+
+static int read_out(Ctx &C, const double *dev, double *host, int count)
+{
+    PM_HIP(hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, C.st));
+    PM_HIP(hipStreamSynchronize(C.st));
+    return PM_OK;
+}
+
+// Hierarchy of one precision: per-level ping-pong buffers and flags telling
+// which buffer holds the current red / black values.
+template <typename R>
+struct Hier {
+    int nlev = 0;
+    LevelView<R> L[kMaxLevels];
+    R *buf[kMaxLevels][2];
+    int cur[kMaxLevels][2];  // [level][colour] -> buffer index
+    double *csum = nullptr;  // [level][2]
+    R *xr(int l) { return buf[l][cur[l][0]]; }
+    R *xb(int l) { return buf[l][cur[l][1]] + L[l].half; }
+};
+
+template <typename R>
+static LevelView<R> make_view(int n, double h, const R *d, R *t, R *x0)
+{
+    LevelView<R> v;
+    v.n = n;
+    v.nh = n / 2;
+    v.half = (long long)n * n * (n / 2);
+    v.h = h;
+    v.dr = d;
+    v.db = d ? d + v.half : nullptr;
+    v.tr = t;
+    v.tb = t ? t + v.half : nullptr;
+    v.x0r = x0;
+    v.x0b = x0 ? x0 + v.half : nullptr;
+    return v;
+}
+
+static void build_hier64(Ctx &C, Hier<double> &H, double *master)
+{
+    const Plan &P = C.P;
+    H.nlev = P.nlev;
+    H.csum = C.csum64;
+    for (int l = 0; l < P.nlev; l++) {
+        const double h = 1.0 / P.n[l];
+        H.L[l] = make_view<double>(P.n[l], h, C.at<double>(P.delta64[l]), l ? C.at<double>(P.t64[l]) : nullptr,
+                                   l ? C.at<double>(P.x064[l]) : nullptr);
+        H.buf[l][0] = l ? C.at<double>(P.p64[l]) : master;
+        H.buf[l][1] = C.at<double>(P.q64[l]);
+        H.cur[l][0] = H.cur[l][1] = 0;
+    }
+}
+
+static void build_hier32(Ctx &C, Hier<float> &H)
+{
+    const Plan &P = C.P;
+    H.nlev = P.nlev;
+    H.csum = C.csum32;
+    for (int l = 0; l < P.nlev; l++) {
+        const double h = 1.0 / P.n[l];
+        H.L[l] = make_view<float>(P.n[l], h, C.at<float>(P.d32[l]), C.at<float>(P.t32[l]), C.at<float>(P.x032[l]));
+        H.buf[l][0] = C.at<float>(P.p32[l]);
+        H.buf[l][1] = C.at<float>(P.q32[l]);
+        H.cur[l][0] = H.cur[l][1] = 0;
+    }
+}
+
+// ------------------------------------------------------- kernel timing
+// Opt-in measurement: while enabled, every launch of the finest-level
+// smoother is bracketed by two HIP events recorded on the launch stream.
+// Slots: 0 scalar field FP64, 1 scalar field FP32, 2 Poisson FP64,
+// 3 Poisson FP32.
+struct KernelTiming {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> slot_of_pair;
+};
+static KernelTiming g_kt;
+constexpr size_t kTimingPairs = 16384;
+
+template <typename R>
+static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool nl)
+{
+    const int own = H.cur[l][colour];
+    const long long half = H.L[l].half;
+    R *src = H.buf[l][own] + (colour ? half : 0);
+    R *dst = H.buf[l][1 - own] + (colour ? half : 0);
+    const R *oth = H.buf[l][H.cur[l][1 - colour]] + (colour ? 0 : half);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (l == 0 && g_kt.on) {
+        std::lock_guard<std::mutex> g(g_kt.mu);
+        if (g_kt.used + 2 <= g_kt.pool.size()) {
+            e0 = g_kt.pool[g_kt.used];
+            e1 = g_kt.pool[g_kt.used + 1];
+            g_kt.used += 2;
+            g_kt.slot_of_pair.push_back((sizeof(R) == 4 ? 1 : 0) + (nl ? 0 : 2));
+        }
+    }
+    if (e0)
+        (void)hipEventRecord(e0, C.st);
+    launch_smooth<R>(H.L[l], colour, src, oth, dst, H.csum + 2 * l, H.csum + 2 * l + colour, C.rs, sc, nl, C.st);
+    if (e1)
+        (void)hipEventRecord(e1, C.st);
+    H.cur[l][colour] = 1 - own;
+}
+
+constexpr int kCoarseSweeps = 100;
+
+// V-cycle below level l (level l's tau and csum are set).  Levels below get
+// their x from restriction into buffer 0.
+template <typename R>
+static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveConsts sc, bool nl)
+{
+    if (l == H.nlev - 1) {
+        launch_coarsest<R>(H.L[l], H.xr(l), H.xb(l), sc, nl, kCoarseSweeps, C.st);
+        return;
+    }
+    for (int s = 0; s < o.n_pre; s++) {
+        smooth(C, H, l, 0, sc, nl);
+        smooth(C, H, l, 1, sc, nl);
+    }
+    H.cur[l + 1][0] = H.cur[l + 1][1] = 0;
+    launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum + 2 * l, H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
+                                sc, nl, C.st);
+    launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum + 2 * (l + 1), C.rs, sc, nl, C.st);
+    vcycle_from(C, H, l + 1, o, sc, nl);
+    launch_prolong_correct<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
+    for (int s = 0; s < o.n_post; s++) {
+        smooth(C, H, l, 0, sc, nl);
+        smooth(C, H, l, 1, sc, nl);
+    }
+}
+
+struct SolveOut {
+    int status = PM_OK, vcycles = 0;
+    double rel = 0.0, hist[64] = {}, mean_shift = 0.0;
+    long long clamped = 0;
+};
+
+static void record(SolveOut &so, int i, double rel)
+{
+    if (i < 64)
+        so.hist[i] = rel;
+    so.rel = rel;
+}
+
+// FP64 solve of one field held packed in `master` (initial guess in, solution
+// out).  src_norm = ||beta delta / nu||_2.
+static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
+                     SolveOut &so)
+{
+    Hier<double> H;
+    build_hier64(C, H, master);
+    const long long N = C.P.N;
+    // exact mean of Lq on the fine level for the first half-sweep
+    launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum, C.rs, sc, nl, C.st);
+    double out[8];
+    int it = 0;
+    for (;; it++) {
+        for (int s = 0; s < o.n_pre; s++) {
+            smooth(C, H, 0, 0, sc, nl);
+            smooth(C, H, 0, 1, sc, nl);
+        }
+        H.cur[1][0] = H.cur[1][1] = 0;
+        launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum, H.L[1], H.xr(1), H.xb(1), C.rs, sc, nl,
+                                         C.st);
+        int e = read_out(C, C.rs.out, out, 4);
+        if (e)
+            return e;
+        const double r2 = fmax(out[0] - out[1] * out[1] / (double)N, 0.0);
+        const double rel = sqrt(r2) / src_norm;
+        record(so, it, rel);
+        so.mean_shift = out[2] / (double)N;
+        so.clamped = (long long)out[3];
+        if (!isfinite(rel)) {
+            so.status = PM_ENONFINITE;
+            break;
+        }
+        if (rel <= o.rel_tol) {
+            so.status = PM_OK;
+            break;
+        }
+        if (it >= o.max_vcycles) {
+            so.status = PM_ENOCONV;
+            break;
+        }
+        launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum + 2, C.rs, sc, nl, C.st);
+        vcycle_from(C, H, 1, o, sc, nl);
+        launch_prolong_correct<double>(H.L[0], H.xr(0), H.xb(0), H.L[1], H.xr(1), H.xb(1), C.st);
+        for (int s = 0; s < o.n_post; s++) {
+            smooth(C, H, 0, 0, sc, nl);
+            smooth(C, H, 0, 1, sc, nl);
+        }
+    }
+    so.vcycles = it;
+    // bring both colours back into the master buffer
+    const long long half = H.L[0].half;
+    if (H.cur[0][0])
+        PM_HIP(hipMemcpyAsync(master, H.buf[0][1], sizeof(double) * half, hipMemcpyDeviceToDevice, C.st));
+    if (H.cur[0][1])
+        PM_HIP(hipMemcpyAsync(master + half, H.buf[0][1] + half, sizeof(double) * half, hipMemcpyDeviceToDevice, C.st));
+    (void)N;
+    return launched();
+}
+
+// Mixed precision.  Every outer step evaluates the FP64 residual of the FP64
+// iterate (convergence test included) and hands the defect to an FP32
+// V-cycle whose result corrects the FP64 iterate.
+//  - Linear problems (Poisson, linearised option): the FP32 V-cycle solves
+//    the correction equation lap e = r from e = 0, so the iteration has no
+//    FP32 floor.
+//  - The nonlinear scalar field: the FP32 level carries the full
+//    approximation (FAS), which is accurate only down to the FP32 rounding
+//    of the iterate's Laplacian (~1e-6 relative residual on fine grids).
+//    Once the FP64 residual is within `kMixedSwitch` of that floor, or a
+//    cycle stops paying (reduction worse than 0.6), the remaining V-cycles
+//    run in FP64.
+constexpr double kMixedSwitchNL = 3e-5;
+
+static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
+                       SolveOut &so)
+{
+    Hier<float> H;
+    build_hier32(C, H);
+    const long long N = C.P.N;
+    LevelView<double> F64 = make_view<double>(C.P.n[0], 1.0 / C.P.n[0], C.at<double>(C.P.delta64[0]), nullptr, nullptr);
+    const long long half = F64.half;
+    // exact initial mean of Lq64
+    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, C.st);
+    ReduceSlot ro = C.rs;
+    ro.out = C.outer_out;
+    // the FP32 correction equation of a linear problem has no source term
+    const SolveConsts sc32 = nl ? sc : SolveConsts{sc.nu, 0.0, 0.0};
+    const double switch_tol = fmax(kMixedSwitchNL, 30.0 * o.rel_tol);
+    double out[8];
+    int it = 0;
+    double prev = 0.0;
+    bool to_f64 = false;
+    for (;; it++) {
+        H.cur[0][0] = H.cur[0][1] = 0;
+        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), C.csum32, ro, sc,
+                                    nl, C.st);
+        // lagged means for the next outer residual and the FP32 level 0
+        PM_HIP(hipMemcpyAsync(C.csum64, C.outer_out + 2, sizeof(double), hipMemcpyDeviceToDevice, C.st));
+        launch_zero(C.csum64 + 1, sizeof(double), C.st);
+        PM_HIP(hipMemcpyAsync(C.csum32, C.outer_out + 4, 2 * sizeof(double), hipMemcpyDeviceToDevice, C.st));
+        int e = read_out(C, C.outer_out, out, 4);
+        if (e)
+            return e;
+        const double r2 = fmax(out[0] - out[1] * out[1] / (double)N, 0.0);
+        const double rel = sqrt(r2) / src_norm;
+        record(so, it, rel);
+        so.mean_shift = out[2] / (double)N;
+        so.clamped = (long long)out[3];
+        if (!isfinite(rel)) {
+            so.status = PM_ENONFINITE;
+            break;
+        }
+        if (rel <= o.rel_tol) {
+            so.status = PM_OK;
+            break;
+        }
+        if (it >= o.max_vcycles) {
+            so.status = PM_ENOCONV;
+            break;
+        }
+        if (nl && (rel <= switch_tol || (it > 0 && rel > 0.6 * prev))) {
+            to_f64 = true;
+            break;
+        }
+        prev = rel;
+        vcycle_from<float>(C, H, 0, o, sc32, nl);
+        launch_mixed_correct(master, H.xr(0), H.xb(0), H.L[0].x0r, H.L[0].x0b, half, C.st);
+    }
+    so.vcycles = it;
+    int e = launched();
+    if (e || !to_f64)
+        return e;
+    // finish in FP64 from the current iterate
+    pm_mg_opts o64 = o;
+    o64.max_vcycles = o.max_vcycles - it;
+    SolveOut s64;
+    e = solve_f64(C, master, sc, nl, o64, src_norm, s64);
+    if (e)
+        return e;
+    for (int i = 0; i <= s64.vcycles && it + i < 64; i++)
+        so.hist[it + i] = s64.hist[i];
+    so.vcycles = it + s64.vcycles;
+    so.rel = s64.rel;
+    so.status = s64.status;
+    so.mean_shift = s64.mean_shift;
+    so.clamped = s64.clamped;
+    return PM_OK;
+}
+
+// delta hierarchy from the packed fine delta (mean removed here) + FP32 copy
+static int prepare_delta(Ctx &C, double *delta_sq_sum)
+{
+    const Plan &P = C.P;
+    double *d0 = C.at<double>(P.delta64[0]);
+    launch_field_sum(d0, P.N, C.rs, C.st);
+    launch_subtract_mean(d0, P.N, C.rs.out, C.st);
+    for (int l = 1; l < P.nlev; l++) {
+        const long long fh = (long long)P.n[l - 1] * P.n[l - 1] * (P.n[l - 1] / 2);
+        const long long ch = (long long)P.n[l] * P.n[l] * (P.n[l] / 2);
+        double *f = C.at<double>(P.delta64[l - 1]);
+        double *c = C.at<double>(P.delta64[l]);
+        launch_restrict_field<double>(P.n[l], f, f + fh, c, c + ch, C.st);
+    }
+    if (P.precs & kPrecMixed)
+        for (int l = 0; l < P.nlev; l++)
+            launch_cast_f64_f32(C.at<double>(P.delta64[l]), C.at<float>(P.d32[l]),
+                                (long long)P.n[l] * P.n[l] * P.n[l], C.st);
+    launch_field_sum(d0, P.N, C.rs, C.st);
+    double out[2];
+    int e = read_out(C, C.rs.out, out, 2);
+    if (e)
+        return e;
+    *delta_sq_sum = out[1];
+    if (!isfinite(out[0]) || !isfinite(out[1]))
+        return PM_ENONFINITE;
+    return launched();
+}
+
+static void fill_report(pm_mg_report *rep, const SolveOut &so, float ms)
+{
+    if (!rep)
+        return;
+    memset(rep, 0, sizeof(*rep));
+    rep->status = so.status;
+    rep->vcycles = so.vcycles;
+    rep->rel_residual = so.rel;
+    for (int i = 0; i < 64; i++)
+        rep->residual_hist[i] = so.hist[i];
+    rep->mean_shift = so.mean_shift;
+    rep->clamped_cells = so.clamped;
+    rep->ms = ms;
+}
+
+static bool opts_ok(const pm_mg_opts *o)
+{
+    return o && o->rel_tol > 0.0 && o->max_vcycles >= 0 && o->n_pre >= 0 && o->n_post >= 0 && o->n_pre + o->n_post > 0 &&
+           (o->precision == PM_PREC_F64 || o->precision == PM_PREC_MIXED) && o->guess >= PM_GUESS_ZERO &&
+           o->guess <= PM_GUESS_LINEAR;
+}
+
+// The mixed path also needs the FP64 hierarchy: the nonlinear solve finishes
+// its last V-cycles in FP64.
+static int prec_bits(const pm_mg_opts *o) { return o->precision == PM_PREC_MIXED ? (kPrecMixed | kPrecF64) : kPrecF64; }
+
+static int run_solve(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
+                     SolveOut &so)
+{
+    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so)
+                                        : solve_f64(C, master, sc, nl, o, src_norm, so);
+}
+
+// Poisson: lap psi = s delta (nu = 1, K = 0, beta = s).
+static int poisson_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so, double dsq)
+{
+    double *m = C.at<double>(C.P.psi64);
+    if (o.guess != PM_GUESS_GIVEN)
+        launch_zero(m, sizeof(double) * C.P.N, C.st);
+    SolveConsts sc{1.0, 0.0, cf.s};
+    const double src = fabs(cf.s) * sqrt(dsq);
+    if (src == 0.0) {
+        launch_zero(m, sizeof(double) * C.P.N, C.st);
+        so = SolveOut();
+        return launched();
+    }
+    return run_solve(C, m, sc, false, o, src, so);
+}
+
+// Scalar field: nu lap chi - xi s delta - K N(chi) = 0 (beta = xi s).
+static int scalar_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so, double dsq)
+{
+    double *m = C.at<double>(C.P.chi64);
+    so = SolveOut();
+    if (cf.xi == 0.0) {
+        launch_zero(m, sizeof(double) * C.P.N, C.st);
+        return launched();
+    }
+    const bool nl = cf.K != 0.0;
+    const double src = fabs(cf.xi * cf.s / cf.nu) * sqrt(dsq);
+    if (src == 0.0) {
+        launch_zero(m, sizeof(double) * C.P.N, C.st);
+        return launched();
+    }
+    SolveConsts sc{cf.nu, cf.K, cf.xi * cf.s};
+    if (o.guess == PM_GUESS_ZERO || o.guess == PM_GUESS_LINEAR)
+        launch_zero(m, sizeof(double) * C.P.N, C.st);
+    if (o.guess == PM_GUESS_LINEAR && nl) {
+        pm_mg_opts lo = o;
+        lo.rel_tol = 1e-3;
+        lo.max_vcycles = 4;
+        SolveOut tmp;
+        SolveConsts lin{cf.nu, 0.0, cf.xi * cf.s};
+        int e = run_solve(C, m, lin, false, lo, src, tmp);
+        if (e)
+            return e;
+    }
+    return run_solve(C, m, sc, nl, o, src, so);
+}
+
+struct Timer {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t st;
+    explicit Timer(hipStream_t s) : st(s)
+    {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, st);
+    }
+    float stop()
+    {
+        float ms = 0.f;
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer()
+    {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+static int grid_solve(const void *rho, int ng, pm_dtype dt, const pm_eft_params *p, const pm_mg_opts *o, void *out,
+                      pm_mg_report *rep, void *ws, size_t wsb, pm_stream_t stream, bool scalar)
+{
+    if (!rho || !p || !out || !opts_ok(o) || (dt != PM_F32 && dt != PM_F64))
+        return PM_EINVAL;
+    pm_eft_coeffs cf;
+    int e = coefficients(*p, cf);
+    if (e == PM_EINVAL || (scalar && e == PM_EUNSTABLE))
+        return e;
+    Ctx C;
+    e = setup_ctx(C, ws, wsb, ng, 0, dt, prec_bits(o), stream);
+    if (e)
+        return e;
+    Timer tm(C.st);
+    // rho -> packed delta = rho - 1 (mean removed in prepare_delta)
+    launch_natural_to_packed(rho, dt, C.at<double>(C.P.delta64[0]), ng, 1.0, -1.0, C.st);
+    double dsq = 0.0;
+    e = prepare_delta(C, &dsq);
+    if (e)
+        return e;
+    double *m = C.at<double>(scalar ? C.P.chi64 : C.P.psi64);
+    if (o->guess == PM_GUESS_GIVEN)
+        launch_natural_to_packed(out, dt, m, ng, 1.0, 0.0, C.st);
+    SolveOut so;
+    e = scalar ? scalar_core(C, cf, *o, so, dsq) : poisson_core(C, cf, *o, so, dsq);
+    if (e)
+        return e;
+    launch_field_sum(m, C.P.N, C.rs, C.st);
+    launch_packed_to_natural(m, out, dt, ng, 0.0, C.rs.out, C.st);
+    e = launched();
+    if (e)
+        return e;
+    fill_report(rep, so, tm.stop());
+    return so.status;
+}
+
+}  // namespace pmeft
+
+using namespace pmeft;
+
+extern "C" {
+
+int pm_eft_coefficients(const pm_eft_params *p, pm_eft_coeffs *out)
+{
+    if (!p || !out)
+        return PM_EINVAL;
+    return coefficients(*p, *out);
+}
+
+int pm_grid_levels(int ng) { return grid_levels(ng); }
+
+size_t pm_workspace_bytes(int ng, long long np, pm_dtype dtype, pm_prec prec)
+{
+    Plan P;
+    const int bits = prec == PM_PREC_F64 ? kPrecF64 : (kPrecF64 | kPrecMixed);
+    if (!make_plan(P, ng, np < 0 ? 0 : np, dtype, bits))
+        return 0;
+    return P.total;
+}
+
+int pm_deposit(const void *pos, long long np, pm_dtype dtype, int ng, void *rho, void *ws, size_t ws_bytes,
+               pm_stream_t stream)
+{
+    if (!pos || !rho || np <= 0 || np > (1LL << 30) || (dtype != PM_F32 && dtype != PM_F64))
+        return PM_EINVAL;
+    Ctx C;
+    int e = setup_ctx(C, ws, ws_bytes, ng, np, dtype, 0, stream);
+    if (e)
+        return e;
+    unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
+    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
+    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
+    double *d0 = C.at<double>(C.P.delta64[0]);
+    launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, d0, C.rs, C.st);
+    // rho = delta_raw + 1 in natural order
+    launch_packed_to_natural(d0, rho, dtype, ng, 1.0, nullptr, C.st);
+    e = launched();
+    if (e)
+        return e;
+    return PM_OK;
+}
+
+int mg_poisson_solve(const void *rho, int ng, pm_dtype dtype, const pm_eft_params *p, const pm_mg_opts *opts,
+                     void *psi, pm_mg_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    return grid_solve(rho, ng, dtype, p, opts, psi, rep, ws, ws_bytes, stream, false);
+}
+
+int mg_scalar_solve(const void *rho, int ng, pm_dtype dtype, const pm_eft_params *p, const pm_mg_opts *opts,
+                    void *chi, pm_mg_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    return grid_solve(rho, ng, dtype, p, opts, chi, rep, ws, ws_bytes, stream, true);
+}
+
+int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, const pm_eft_params *p, const void *pos,
+                    long long np, void *vel, double dt_kick, void *acc_out, void *ws, size_t ws_bytes,
+                    pm_stream_t stream)
+{
+    if (!psi || !pos || !vel || !p || np <= 0 || np > (1LL << 30) || (dtype != PM_F32 && dtype != PM_F64))
+        return PM_EINVAL;
+    pm_eft_coeffs cf;
+    int e = coefficients(*p, cf);
+    if (e == PM_EINVAL)
+        return e;
+    Ctx C;
+    e = setup_ctx(C, ws, ws_bytes, ng, np, dtype, 0, stream);
+    if (e)
+        return e;
+    double *ps = C.at<double>(C.P.psi64), *ch = C.at<double>(C.P.chi64);
+    launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
+    if (chi)
+        launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
+    void *g4 = C.ws + C.P.g4;
+    launch_gradient(ps, chi ? ch : nullptr, cf.xi, ng, g4, dtype, C.st);
+    launch_interp_kick(g4, ng, dtype, const_cast<void *>(pos), np, vel, dt_kick, 0.0, acc_out, C.st);
+    return launched();
+}
+
+int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p,
+            const pm_mg_opts *poisson_opts, const pm_mg_opts *scalar_opts, double dt_kick, double dt_drift, void *psi,
+            void *chi, pm_step_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!pos || !vel || !psi || !chi || !p || np <= 0 || np > (1LL << 30) || !opts_ok(poisson_opts) || !opts_ok(scalar_opts) ||
+        (dtype != PM_F32 && dtype != PM_F64))
+        return PM_EINVAL;
+    pm_eft_coeffs cf;
+    int e = coefficients(*p, cf);
+    if (e)
+        return e;
+    Ctx C;
+    e = setup_ctx(C, ws, ws_bytes, ng, np, dtype, prec_bits(poisson_opts) | prec_bits(scalar_opts), stream);
+    if (e)
+        return e;
+    Timer tall(C.st);
+    // deposit -> packed delta
+    Timer tdep(C.st);
+    unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
+    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
+    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
+    launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, C.at<double>(C.P.delta64[0]), C.rs, C.st);
+    double dsq = 0.0;
+    e = prepare_delta(C, &dsq);
+    if (e)
+        return e;
+    const float ms_dep = tdep.stop();
+    double *ps = C.at<double>(C.P.psi64), *ch = C.at<double>(C.P.chi64);
+    if (poisson_opts->guess == PM_GUESS_GIVEN)
+        launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
+    if (scalar_opts->guess == PM_GUESS_GIVEN)
+        launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
+    SolveOut sp, sx;
+    Timer tp(C.st);
+    e = poisson_core(C, cf, *poisson_opts, sp, dsq);
+    if (e)
+        return e;
+    const float ms_p = tp.stop();
+    Timer tx(C.st);
+    e = scalar_core(C, cf, *scalar_opts, sx, dsq);
+    if (e)
+        return e;
+    const float ms_x = tx.stop();
+    Timer tf(C.st);
+    void *g4 = C.ws + C.P.g4;
+    launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
+    launch_interp_kick(g4, ng, dtype, pos, np, vel, dt_kick, dt_drift, nullptr, C.st);
+    const float ms_f = tf.stop();
+    launch_field_sum(ps, C.P.N, C.rs, C.st);
+    launch_packed_to_natural(ps, psi, dtype, ng, 0.0, C.rs.out, C.st);
+    launch_field_sum(ch, C.P.N, C.rs, C.st);
+    launch_packed_to_natural(ch, chi, dtype, ng, 0.0, C.rs.out, C.st);
+    e = launched();
+    if (e)
+        return e;
+    const float ms_all = tall.stop();
+    if (rep) {
+        memset(rep, 0, sizeof(*rep));
+        fill_report(&rep->poisson, sp, ms_p);
+        fill_report(&rep->scalar, sx, ms_x);
+        rep->ms_deposit = ms_dep;
+        rep->ms_force = ms_f;
+        rep->ms_total = ms_all;
+    }
+    if (sp.status)
+        return sp.status;
+    return sx.status;
+}
+
+int pm_kernel_timing_enable(int on)
+{
+    std::lock_guard<std::mutex> g(g_kt.mu);
+    if (on && g_kt.pool.empty()) {
+        g_kt.pool.resize(2 * kTimingPairs);
+        for (auto &e : g_kt.pool)
+            if (hipEventCreate(&e) != hipSuccess)
+                return PM_EHIP;
+    }
+    g_kt.on = on != 0;
+    return PM_OK;
+}
+
+int pm_kernel_timing_read(double *total_ms /* HOST [4] */, long long *launches /* HOST [4] */)
+{
+    if (!total_ms || !launches)
+        return PM_EINVAL;
+    std::lock_guard<std::mutex> g(g_kt.mu);
+    for (int q = 0; q < 4; q++) {
+        total_ms[q] = 0.0;
+        launches[q] = 0;
+    }
+    for (size_t k = 0; k < g_kt.slot_of_pair.size(); k++) {
+        float ms = 0.f;
+        if (hipEventSynchronize(g_kt.pool[2 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&ms, g_kt.pool[2 * k], g_kt.pool[2 * k + 1]) != hipSuccess)
+            return PM_EHIP;
+        total_ms[g_kt.slot_of_pair[k]] += ms;
+        launches[g_kt.slot_of_pair[k]] += 1;
+    }
+    g_kt.used = 0;
+    g_kt.slot_of_pair.clear();
+    return PM_OK;
+}
+
+const char *pm_strerror(int code)
+{
+    switch (code) {
+    case PM_OK: return "ok";
+    case PM_EINVAL: return "invalid argument (null pointer, unsupported grid size or option)";
+    case PM_EUNSTABLE: return "unstable model: nu <= 0 with xi != 0";
+    case PM_ENOCONV: return "multigrid did not reach the tolerance within max_vcycles";
+    case PM_ENONFINITE: return "non-finite value in the input or the residual";
+    case PM_EHIP: return "HIP runtime error";
+    case PM_ENOMEM: return "workspace too small";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// Internal declarations shared by the HIP sources of libpmeft.so.
+//
+// Grid storage inside the library ("packed red/black"): a level with n cells
+// per side (n even) stores its n^3 values as two colour blocks of n^3/2
+// elements, colour c = (i + j + k) & 1.  Within a colour block the element
+// (i, j, kh) holds the cell (i, j, k = 2 kh + ((i + j + c) & 1)), with kh
+// fastest.  Consecutive threads then touch consecutive addresses, a half-sweep
+// of red-black Gauss-Seidel reads and writes dense arrays, and the 8 children
+// of a coarse cell (I, J, K) sit at kh = K in rows (2I+a, 2J+b) of both
+// colours.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/pmeft.h"
+
+namespace pmeft {
+
+constexpr int kBlock = 256;          // threads per block of the grid kernels
+constexpr int kMaxLevels = 12;
+constexpr double kFixScale = 1099511627776.0;  // 2^40: deposit fixed point
+
+// Index arithmetic is 32-bit (grids are capped at 1024^3, so n^3 < 2^31):
+// 64-bit integer division is emulated on the GPU and would dominate these
+// bandwidth-bound kernels.  split() decodes a linear index over rows of
+// length nh and planes of n rows.
+__device__ __forceinline__ void split(unsigned e, unsigned nh, unsigned n, int &i, int &j, int &kh)
+{
+    const unsigned row = e / nh;
+    kh = (int)(e - row * nh);
+    const unsigned ii = row / n;
+    j = (int)(row - ii * n);
+    i = (int)ii;
+}
+
+// Work distribution of the grid kernels.  The hardware hands block b to
+// XCD b mod 8, and each XCD has its own L2.  A block therefore works on one
+// contiguous chunk of `chunk` elements, and the chunks are ordered so that
+// the blocks an XCD receives cover one contiguous slab of the grid: the
+// planes a stencil reads around a cell are then mostly in that XCD's L2
+// instead of being fetched once per XCD.
+struct Span {
+    unsigned total;    // elements
+    unsigned chunk;    // elements per block (multiple of kBlock)
+    unsigned nblocks;  // launched blocks (multiple of 8 when >= 8)
+};
+
+constexpr int kMaxBlocks = 2048;  // 8 blocks per CU on 256 CUs
+
+inline Span make_span(unsigned long long total, unsigned max_blocks = kMaxBlocks)
+{
+    Span sp;
+    sp.total = (unsigned)total;
+    if (total == 0) {
+        sp.chunk = kBlock;
+        sp.nblocks = 1;
+        return sp;
+    }
+    unsigned long long b = (total + kBlock - 1) / kBlock;
+    if (b > max_blocks)
+        b = max_blocks;
+    if (b >= 8)
+        b -= b % 8;
+    if (b < 1)
+        b = 1;
+    unsigned long long ch = (total + b - 1) / b;
+    ch = (ch + kBlock - 1) / kBlock * kBlock;
+    sp.chunk = (unsigned)ch;
+    sp.nblocks = (unsigned)((total + ch - 1) / ch);
+    if (sp.nblocks >= 8 && sp.nblocks % 8)
+        sp.nblocks += 8 - sp.nblocks % 8;  // trailing blocks get empty chunks
+    if (sp.nblocks < 1)
+        sp.nblocks = 1;
+    return sp;
+}
+
+__device__ __forceinline__ unsigned span_block(const Span &sp)
+{
+    const unsigned b = blockIdx.x;
+    if (sp.nblocks % 8)
+        return b;
+    const unsigned per = sp.nblocks / 8;
+    return (b % 8) * per + b / 8;
+}
+
+#define PM_SPAN_LOOP(e, sp)                                                                                            \
+    for (unsigned e##_end_ = min((sp).total, (span_block(sp) + 1) * (sp).chunk),                                     \
+                  e = span_block(sp) * (sp).chunk + threadIdx.x;                                                      \
+         e < e##_end_; e += kBlock)
+
+// Scalars of one solve, by value into every kernel.
+struct SolveConsts {
+    double nu;     // coefficient of lap chi (1 for the Poisson solve)
+    double K;      // screening prefactor (0 for Poisson or the linearised option)
+    double beta;   // source b = beta * delta (s for Poisson, xi s for chi)
+};
+
+// Device view of one multigrid level (pointers are to packed arrays).
+template <typename R>
+struct LevelView {
+    int n;           // cells per side
+    int nh;          // n / 2
+    long long half;  // n^3 / 2
+    double h;        // cell size
+    const R *dr, *db;   // delta, red / black blocks
+    R *tr, *tb;         // FAS source tau (null on the finest level of an F64 solve)
+    R *x0r, *x0b;       // restricted fine iterate (coarse levels)
+};
+
+// Reduction scratch inside the workspace: every block of a reducing kernel
+// writes its partial sums (8 slots per block); a one-block finalize kernel
+// launched right after adds them in block order (deterministic, and no
+// device-scope fence inside the reducing kernel).
+struct ReduceSlot {
+    double *partials;   // kMaxBlocks * 8
+    unsigned *counter;  // unused (kept zero)
+    double *out;        // finalised sums
+};
+
+// Block reduction of NV doubles; thread 0 stores the block's sums at
+// partials[logical block * 8 + q].  The k_finalize launch that follows adds
+// the partials in block order, so results do not depend on scheduling.
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], const ReduceSlot &rs, const Span &sp)
+{
+    __shared__ double sm[NV][kBlock / 64];
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1)
+            x += __shfl_down(x, off, 64);
+        v[q] = x;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; q++)
+            sm[q][wid] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned lb = span_block(sp);
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            double t = 0.0;
+            for (int w = 0; w < kBlock / 64; w++)
+                t += sm[q][w];
+            rs.partials[(size_t)lb * 8 + q] = t;
+        }
+    }
+}
+
+// Sums the partials of the preceding reducing launch (nv values) into out.
+void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, hipStream_t st);
+
+// ---- launchers (mg_kernels.hip) ------------------------------------------
+template <typename R>
+void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new,
+                   const double *csum, double *csum_out_colour, ReduceSlot rs, SolveConsts sc, bool nonlinear,
+                   hipStream_t st);
+
+// Fine-level residual r = Lq + tau - c - lap x fused with the 8-child
+// restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
+// into x0).  Accumulates sum r^2, sum r, sum Lq+tau into rs.out[0..2] and the
+// void-cell count into rs.out[3].
+template <typename R>
+void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
+                              const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
+                              hipStream_t st);
+
+// Coarse FAS source: tau += lap x - Lq(x); writes sum(Lq + tau) per colour
+// into csum[0..1].
+template <typename R>
+void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
+                    bool nonlinear, hipStream_t st);
+
+// Fine x += P (x_H - x0_H), trilinear cell-centred prolongation.
+template <typename R>
+void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr,
+                            const R *cxb, hipStream_t st);
+
+// Coarsest level solved by one workgroup in FP64.
+template <typename R>
+void launch_coarsest(const LevelView<R> &C, R *xr, R *xb, SolveConsts sc, bool nonlinear, int sweeps,
+                     hipStream_t st);
+
+// delta hierarchy: coarse = 8-child average of fine.
+template <typename R>
+void launch_restrict_field(int nc, const R *fr, const R *fb, R *cr, R *cb, hipStream_t st);
+
+// FP64 fine delta -> FP32 copy (mixed precision hierarchy).
+void launch_cast_f64_f32(const double *src, float *dst, long long n, hipStream_t st);
+
+// Natural [i][j][k] <-> packed red/black conversion; dtype of the natural
+// array is float or double, the packed array is double.
+void launch_natural_to_packed(const void *nat, pm_dtype dt, double *packed, int n, double scale, double shift,
+                              hipStream_t st);
+// nat = packed - (sum_ptr ? sum_ptr[0] / n^3 : 0) + add
+void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int n, double add, const double *sum_ptr,
+                              hipStream_t st);
+
+// Mixed precision outer step: FP64 residual of (x64, delta64) with norm
+// partials, cast x32 = fl(x64) (into level-0 x and x0) and the FP32 FAS
+// target tau32 = fl(r64) + lap32 x32 - Lq32(x32); per-colour sums of
+// Lq32 + tau32 into csum32.
+void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
+                                 const double *csum64, const LevelView<float> &F32, float *x32r, float *x32b,
+                                 double *csum32, ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st);
+// x64 += x32 - x0_32
+void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, const float *x0r, const float *x0b,
+                          long long half, hipStream_t st);
+
+// Plain FP64 residual norm (no restriction) of the finest level.
+void launch_residual_norm(const LevelView<double> &F, const double *xr, const double *xb, const double *csum,
+                          ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st);
+
+// Sum of a packed double field (rs.out[0]).
+void launch_field_sum(const double *x, long long n, ReduceSlot rs, hipStream_t st);
+// x -= shift (shift read from device *shift_sum / n)
+void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStream_t st);
+// y = a * x
+void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st);
+void launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// ---- particle kernels (pm_kernels.hip) -----------------------------------
+void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc,
+                          hipStream_t st);
+// acc (fixed point) -> packed delta = rho - 1 (FP64); sum into rs.out[0]
+void launch_fixed_to_delta(const unsigned long long *acc, int ng, double rho_scale, double *delta_packed,
+                           ReduceSlot rs, hipStream_t st);
+// g = -D5 (psi + xi chi) from packed FP64 fields -> interleaved (gx, gy, gz, 0)
+void launch_gradient(const double *psi, const double *chi, double xi, int ng, void *g4, pm_dtype dt,
+                     hipStream_t st);
+void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long long np, void *vel,
+                        double dt_kick, double dt_drift, void *acc_out, hipStream_t st);
+
+}  // namespace pmeft

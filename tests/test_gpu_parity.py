@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances: relative scalar-field error 1e-10 (FP64
+path, both sides solved to relative residual 1e-12) and 1e-5 (mixed
+precision at 1e-7), force RMS error 1e-4 relative."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config_params, lattice_displacement_ics, lognormal_density, lognormal_particles
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2604_15434_amd as P
+
+    return P
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _mean_free(x):
+    x = np.asarray(x, dtype=np.float64)
+    return x - x.mean()
+
+
+CFG0 = config_params("cfg0")[0]
+
+
+# ------------------------------------------------------------------ deposit
+@pytest.mark.parametrize("ng,kind", [(32, "lattice"), (64, "lognormal"), (24, "lattice")])
+def test_deposit_matches_oracle(P, ng, kind):
+    if kind == "lattice":
+        pos = lattice_displacement_ics(ng, 100.0, seed=0)
+    else:
+        pos, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=2)
+    ref = oracle.cic_deposit(pos, ng)
+    rho = torch.empty((ng, ng, ng), dtype=torch.float64, device="cuda")
+    P.pm_deposit(dev(pos), ng, rho)
+    got = rho.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-10
+    # order independence: a permuted particle list gives bitwise the same grid
+    perm = np.random.default_rng(0).permutation(pos.shape[1])
+    rho2 = torch.empty_like(rho)
+    P.pm_deposit(dev(pos[:, perm]), ng, rho2)
+    assert torch.equal(rho, rho2)
+    rho32 = torch.empty((ng, ng, ng), dtype=torch.float32, device="cuda")
+    P.pm_deposit(dev(pos, torch.float32), ng, rho32)
+    assert np.abs(rho32.cpu().numpy() - ref).max() < 2e-5 * max(1.0, ref.max())
+
+
+# ------------------------------------------------------------------ Poisson
+@pytest.mark.parametrize("ng", [32, 48])
+def test_poisson_matches_fft_solution(P, ng):
+    pos = lattice_displacement_ics(ng, 100.0, seed=0, rms_cells=0.6)
+    rho = oracle.cic_deposit(pos, ng)
+    c = oracle.eft_coefficients(**CFG0)
+    ref = oracle.solve_poisson(oracle.density_contrast(rho), c, 1.0 / ng)
+    psi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_poisson_solve(dev(rho), CFG0, P.MgOpts(rel_tol=1e-12, max_vcycles=60), psi)
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-12
+    assert rel(_mean_free(psi.cpu().numpy()), ref) < 1e-10
+
+
+# ------------------------------------------------------------------ scalar field
+def _scalar_case(ng, kind, ab0, am0=0.0, a=1.0):
+    if kind == "cfg0":
+        rho = oracle.cic_deposit(lattice_displacement_ics(ng, 100.0, seed=0), ng)
+        p = dict(CFG0)
+    else:
+        rho = lognormal_density(ng, 500.0 * ng / 256, seed=2)
+        p = dict(omega_m0=0.3071, alpha_b0=ab0, alpha_m0=am0, a=a)
+    return rho, p
+
+
+@pytest.mark.parametrize("ng,kind,ab0,am0,a", [
+    (32, "cfg0", -0.4, 0.0, 0.5),
+    (32, "lognormal", -0.2, 0.0, 1.0),
+    (32, "lognormal", -0.6, 0.1, 1.0),
+    (64, "lognormal", -0.6, 0.0, 1.0),
+])
+def test_scalar_f64_matches_oracle(P, ng, kind, ab0, am0, a):
+    rho, p = _scalar_case(ng, kind, ab0, am0, a)
+    c = oracle.eft_coefficients(**p)
+    delta = oracle.density_contrast(rho)
+    ref, orep = oracle.solve_chi(delta, c, 1.0 / ng, tol=1e-12, max_cycles=200)
+    assert orep["status"] == 0
+    chi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-12, max_vcycles=80), chi)
+    assert rep["status"] == 0, rep
+    assert rep["clamped_cells"] == orep["clamped"]
+    got = chi.cpu().numpy()
+    assert rel(_mean_free(got), ref) < 1e-10
+    # the GPU solution satisfies the oracle's discrete system
+    assert oracle.relative_residual(got, delta, c, 1.0 / ng) < 1e-11
+
+
+def test_scalar_screening_off_matches_fft(P):
+    ng = 32
+    rho, _ = _scalar_case(ng, "cfg0", -0.4)
+    p = dict(CFG0, screening=0)
+    c = oracle.eft_coefficients(**p)
+    ref = oracle.solve_chi_linear(oracle.density_contrast(rho), c, 1.0 / ng)
+    chi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-12, max_vcycles=60), chi)
+    assert rep["status"] == 0 and rep["clamped_cells"] == 0
+    assert rel(_mean_free(chi.cpu().numpy()), ref) < 1e-10
+
+
+@pytest.mark.parametrize("ab0", [-0.2, -0.6])
+def test_scalar_mixed_precision(P, ab0):
+    ng = 64
+    rho, p = _scalar_case(ng, "lognormal", ab0)
+    c = oracle.eft_coefficients(**p)
+    delta = oracle.density_contrast(rho)
+    ref, _ = oracle.solve_chi(delta, c, 1.0 / ng, tol=1e-12, max_cycles=200)
+    chi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-7, max_vcycles=60, precision="mixed"), chi)
+    assert rep["status"] == 0 and rep["rel_residual"] <= 1e-7, rep
+    got = chi.cpu().numpy()
+    assert rel(_mean_free(got), ref) < 1e-5
+    assert oracle.relative_residual(got, delta, c, 1.0 / ng) < 2e-7
+    # FP32 in/out arrays on the same path
+    chi32 = torch.zeros((ng, ng, ng), dtype=torch.float32, device="cuda")
+    rep32 = P.mg_scalar_solve(dev(rho, torch.float32), p,
+                              P.MgOpts(rel_tol=1e-7, max_vcycles=60, precision="mixed"), chi32)
+    assert rep32["status"] == 0
+    assert rel(_mean_free(chi32.cpu().numpy()), ref) < 1e-5
+
+
+def test_scalar_guesses_reach_same_solution(P):
+    ng = 32
+    rho, p = _scalar_case(ng, "lognormal", -0.6)
+    base = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    r0 = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-11, max_vcycles=80), base)
+    lin = torch.zeros_like(base)
+    r1 = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-11, max_vcycles=80, guess="linear"), lin)
+    given = base.clone()
+    r2 = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=1e-11, max_vcycles=80, guess="given"), given)
+    assert r0["status"] == r1["status"] == r2["status"] == 0
+    assert r2["vcycles"] == 0
+    b = base.cpu().numpy()
+    assert rel(lin.cpu().numpy(), b) < 1e-9
+    assert rel(given.cpu().numpy(), b) < 1e-9
+
+
+# ------------------------------------------------------------------ full step
+@pytest.mark.parametrize("dtype,prec,ftol", [(torch.float64, "f64", 1e-9), (torch.float32, "mixed", 1e-4)])
+def test_pm_step_cfg0_matches_oracle(P, dtype, prec, ftol):
+    ng = 32
+    pos = lattice_displacement_ics(ng, 100.0, seed=0)
+    vel = np.zeros_like(pos)
+    ref = oracle.pm_step(pos, vel, ng, CFG0, dt_kick=1.0, tol=1e-12)
+    tol = 1e-12 if prec == "f64" else 1e-7
+    gp, gv = dev(pos, dtype), dev(vel, dtype)
+    psi = torch.zeros((ng, ng, ng), dtype=dtype, device="cuda")
+    chi = torch.zeros_like(psi)
+    rep = P.pm_step(gp, gv, ng, CFG0, P.MgOpts(rel_tol=tol, max_vcycles=80, precision=prec),
+                    P.MgOpts(rel_tol=tol, max_vcycles=80, precision=prec), 1.0, 0.0, psi, chi)
+    assert rep["status"] == 0, rep
+    acc = gv.cpu().numpy().astype(np.float64)
+    err = np.sqrt(np.mean(np.sum((acc - ref["acc"]) ** 2, 0)) / np.mean(np.sum(ref["acc"] ** 2, 0)))
+    assert err < ftol
+    assert rel(_mean_free(chi.cpu().numpy()), ref["chi"]) < (1e-10 if prec == "f64" else 1e-5)
+    assert np.array_equal(gp.cpu().numpy(), pos.astype(gp.cpu().numpy().dtype))  # no drift requested
+
+
+def test_force_interp_and_drift(P):
+    ng = 16
+    rng = np.random.default_rng(4)
+    pos = rng.random((3, 500))
+    vel = rng.standard_normal((3, 500)) * 0.01
+    psi = rng.standard_normal((ng, ng, ng))
+    chi = rng.standard_normal((ng, ng, ng))
+    p = dict(omega_m0=0.3071, alpha_b0=-0.3, alpha_m0=0.1, a=0.8)
+    c = oracle.eft_coefficients(**p)
+    g = oracle.gradient5(psi + c["xi"] * chi, 1.0 / ng)
+    acc_ref = oracle.cic_interpolate(g, pos)
+    gv = dev(vel)
+    acc = torch.zeros_like(gv)
+    P.pm_force_interp(dev(psi), dev(chi), p, dev(pos), gv, 0.5, acc_out=acc)
+    np.testing.assert_allclose(acc.cpu().numpy(), acc_ref, rtol=1e-11, atol=1e-11 * np.abs(acc_ref).max())
+    np.testing.assert_allclose(gv.cpu().numpy(), vel + 0.5 * acc_ref, rtol=1e-11, atol=1e-12)
+
+
+# ------------------------------------------------------------------ edge cases
+def test_lcdm_gives_zero_scalar_field(P):
+    ng = 16
+    rho = lognormal_density(ng, 30.0, seed=1)
+    chi = torch.ones((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_scalar_solve(dev(rho), dict(omega_m0=0.3, alpha_b0=0.0, alpha_m0=0.0, a=1.0), P.MgOpts(), chi)
+    assert rep["status"] == 0 and float(chi.abs().max()) == 0.0
+
+
+def test_error_codes(P):
+    ng = 16
+    rho = dev(lognormal_density(ng, 30.0, seed=1))
+    chi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PmError) as e:
+        P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=0.5, alpha_m0=0.0, a=1.0), P.MgOpts(), chi)
+    assert e.value.code == -2
+    rep = P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=1.0),
+                            P.MgOpts(rel_tol=1e-15, max_vcycles=1), chi)
+    assert rep["status"] == -3 and rep["vcycles"] == 1
+    bad = rho.clone()
+    bad[3, 4, 5] = float("nan")
+    with pytest.raises(P.PmError) as e:
+        P.mg_scalar_solve(bad, dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=1.0), P.MgOpts(), chi)
+    assert e.value.code == -4
+    r10 = torch.ones((10, 10, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PmError) as e:
+        P.mg_poisson_solve(r10, CFG0, P.MgOpts(), torch.zeros_like(r10), ws=P.Workspace(16))
+    assert e.value.code == -1
+    small = P.Workspace(8)
+    with pytest.raises(P.PmError) as e:
+        P.mg_scalar_solve(rho, CFG0, P.MgOpts(), chi, ws=small)
+    assert e.value.code == -6
+
+
+def test_empty_density_gives_zero_fields(P):
+    """rho = 1 everywhere (uniform lattice): delta = 0, all fields vanish."""
+    ng = 16
+    rho = torch.ones((ng, ng, ng), dtype=torch.float64, device="cuda")
+    psi = torch.ones_like(rho)
+    chi = torch.ones_like(rho)
+    assert P.mg_poisson_solve(rho, CFG0, P.MgOpts(), psi)["status"] == 0
+    assert P.mg_scalar_solve(rho, CFG0, P.MgOpts(), chi)["status"] == 0
+    assert float(psi.abs().max()) == 0.0 and float(chi.abs().max()) == 0.0
