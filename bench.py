@@ -50,7 +50,7 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup):
     psi = torch.zeros((ng, ng, ng), dtype=dt, device="cuda")
     chi = torch.zeros_like(psi)
     ws = P.Workspace(ng, pos.shape[1], 1 if dt == torch.float64 else 0, "any")
-    opts = P.MgOpts(rel_tol=1e-7, max_vcycles=60, n_pre=2, n_post=2, precision=prec, guess="zero")
+    opts = P.MgOpts(rel_tol=1e-7, max_vcycles=60, n_pre=1, n_post=2, precision=prec, guess="zero")
     for _ in range(warmup):
         P.pm_step(pos, vel, ng, PARAMS, opts, opts, 1e-3, 0.0, psi, chi, ws=ws)
     torch.cuda.synchronize()

@@ -31,7 +31,7 @@ class PmError(RuntimeError):
 class MgOpts:
     rel_tol: float = 1e-7
     max_vcycles: int = 50
-    n_pre: int = 2
+    n_pre: int = 1
     n_post: int = 2
     precision: str = "f64"  # "f64" | "mixed"
     guess: str = "zero"     # "zero" | "given" | "linear"

@@ -119,23 +119,33 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 }
 
 // ---------------------------------------------------------------- smoothing
+// One half-sweep of colour `colour`.  The lagged mean c = <Lq + tau> comes
+// from csum_in (per-colour sums).  Block 0 also folds the partial sums of the
+// previous half-sweep at this level (prev, prev_nblocks, prev_colour; colour
+// -1 = none) into csum_out, which the next half-sweep reads: the mean thus
+// lags by about one sweep, needs no extra launch, and stays deterministic
+// (every launch reads only values completed by earlier launches).
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, const R *__restrict__ xc_old,
                                                    const R *__restrict__ xo, R *__restrict__ xc_new,
-                                                   const double *__restrict__ csum, ReduceSlot rs, SolveConsts sc,
-                                                   Span sp)
+                                                   const double *__restrict__ csum_in, double *__restrict__ csum_out,
+                                                   const double *__restrict__ prev, int prev_nblocks, int prev_colour,
+                                                   ReduceSlot rs, SolveConsts sc, Span sp)
 {
     const int n = L.n, nh = L.nh;
-    const R cmean = (R)((csum[0] + csum[1]) / (2.0 * (double)L.half));
+    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
     const R h2 = (R)(L.h * L.h);
     const R ih2 = (R)(1.0 / (L.h * L.h));
     const R *dc = colour ? L.db : L.dr;
     const R *tc = colour ? L.tb : L.tr;
     double acc[1] = {0.0};
-    PM_SPAN_LOOP(e, sp)
-    {
-        int i, j, kh;
-        split(e, nh, n, i, j, kh);
+    const unsigned lb = span_block(sp);
+    const unsigned e0 = lb * sp.chunk + threadIdx.x;
+    const unsigned e1 = min(sp.total, (lb + 1) * sp.chunk);
+    int i, j, kh;
+    if (e0 < e1)
+        split(e0, nh, n, i, j, kh);
+    for (unsigned e = e0; e < e1;) {
         R tsh;
         const R S = stencil_terms<R, R>(xc_old, xo, n, nh, colour, i, j, kh, NL, tsh);
         const R b = (R)sc.beta * dc[e];
@@ -144,22 +154,55 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, c
         const R v = lq + (tc ? tc[e] : (R)0);
         xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
         acc[0] += (double)v;
+        e += kBlock;
+        if (e < e1) {  // step (i, j, kh) by kBlock cells without dividing
+            kh += kBlock;
+            while (kh >= nh) {
+                kh -= nh;
+                if (++j == n) {
+                    j = 0;
+                    ++i;
+                }
+            }
+        }
     }
     block_partials<1>(acc, rs, sp);
+    if (blockIdx.x == 0) {
+        __shared__ double fin[kBlock / 64];
+        double t = 0.0;
+        if (prev_colour >= 0)
+            for (int q = threadIdx.x; q < prev_nblocks; q += kBlock)
+                t += prev[(size_t)q * 8];
+        for (int off = 32; off > 0; off >>= 1)
+            t += __shfl_down(t, off, 64);
+        if ((threadIdx.x & 63) == 0)
+            fin[threadIdx.x >> 6] = t;
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            double v = csum_in[threadIdx.x];
+            if ((int)threadIdx.x == prev_colour) {
+                v = 0.0;
+                for (int w = 0; w < kBlock / 64; w++)
+                    v += fin[w];
+            }
+            csum_out[threadIdx.x] = v;
+        }
+    }
 }
 
 template <typename R>
-void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum,
-                   double *csum_out_colour, ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st)
+void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
+                   double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out)
 {
     const Span sp = make_span(L.half);
+    *nblocks_out = (int)sp.nblocks;
     if (nonlinear)
         hipLaunchKernelGGL((k_smooth<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum, rs, sc, sp);
+                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
     else
         hipLaunchKernelGGL((k_smooth<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum, rs, sc, sp);
-    launch_finalize(rs, sp, 1, csum_out_colour, st);
+                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
 }
 
 // ------------------------------------------------------- residual/restrict
@@ -181,8 +224,10 @@ __device__ __forceinline__ T cell_residual(const LevelView<R> &F, const R *xr, c
     return v - cmean - lap;
 }
 
-// One thread per coarse cell: residual of its 8 children, their average into
-// the coarse tau, the average of the children's x into the coarse x and x0.
+// One thread per coarse cell, in natural (I, J, K) order so that
+// consecutive threads read consecutive fine elements: residual of its 8
+// children, their average into the coarse tau, the average of the
+// children's x into the coarse x and x0.
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, const R *__restrict__ xr,
                                                               const R *__restrict__ xb, const double *__restrict__ csum,
@@ -192,15 +237,13 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, co
 {
     const double cm = (csum[0] + csum[1]) / (2.0 * (double)F.half);
     const int nc = C.n, nch = C.nh;
-    const unsigned chalf = (unsigned)C.half;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
     {
-        const int cc = e >= chalf;
-        const unsigned ec = e - (cc ? chalf : 0u);
-        int I, J, KH;
-        split(ec, nch, nc, I, J, KH);
-        const int K = 2 * KH + ((I + J + cc) & 1);
+        int I, J, K;
+        split(e, nc, nc, I, J, K);
+        const int cc = (I + J + K) & 1;
+        const unsigned ec = ((unsigned)I * nc + J) * nch + (K >> 1);
         double sr = 0.0, sx = 0.0;
 #pragma unroll
         for (int a = 0; a < 2; a++)
@@ -283,10 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau(LevelView<R> C, const R *__r
 
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, hipStream_t st)
+                    bool nonlinear, bool accumulate_only, hipStream_t st)
 {
     const Span sp = make_span(2 * C.half);
-    const int acc_only = (C.tr == nullptr);
+    const int acc_only = (accumulate_only || C.tr == nullptr) ? 1 : 0;
     if (nonlinear)
         hipLaunchKernelGGL((k_fas_tau<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
                            acc_only);
@@ -298,43 +341,65 @@ void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csu
 
 // ------------------------------------------------------------- prolongation
 template <typename R>
-__device__ __forceinline__ double coarse_corr(const R *cxr, const R *cxb, const R *x0r, const R *x0b, int nc, int nch,
-                                              int I, int J, int K)
+__device__ __forceinline__ double coarse_at(const R *cr, const R *cb, int nc, int nch, int I, int J, int K)
 {
-    const int c = (I + J + K) & 1;
     const unsigned o = ((unsigned)I * nc + J) * nch + (K >> 1);
-    return c ? (double)cxb[o] - (double)x0b[o] : (double)cxr[o] - (double)x0r[o];
+    return (double)(((I + J + K) & 1) ? cb[o] : cr[o]);
 }
 
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_prolong_correct(LevelView<R> F, R *__restrict__ xr, R *__restrict__ xb,
-                                                            LevelView<R> C, const R *__restrict__ cxr,
-                                                            const R *__restrict__ cxb, Span sp)
+// Cell-centred trilinear prolongation, one thread per coarse cell (natural
+// order): the 27 coarse values around it are interpolated axis by axis
+// (weights 3/4, 1/4) to its 8 children.  CORR: add P (x_H - x0_H) to the
+// fine iterate (coarse-grid correction); !CORR: write P x_H (full
+// approximation, used to start full multigrid).
+template <typename R, bool CORR>
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelView<R> F, R *__restrict__ xr, R *__restrict__ xb,
+                                                    LevelView<R> C, const R *__restrict__ cxr,
+                                                    const R *__restrict__ cxb, Span sp)
 {
     const int nc = C.n, nch = C.nh;
-    const unsigned half = (unsigned)F.half;
     PM_SPAN_LOOP(e, sp)
     {
-        const int c = e >= half;
-        const unsigned ef = e - (c ? half : 0u);
-        int i, j, kh;
-        split(ef, F.nh, F.n, i, j, kh);
-        const int k = 2 * kh + ((i + j + c) & 1);
-        const int I = i >> 1, J = j >> 1, K = k >> 1;
-        const int I2 = (i & 1) ? wrap_up(I + 1, nc) : wrap_dn(I - 1, nc);
-        const int J2 = (j & 1) ? wrap_up(J + 1, nc) : wrap_dn(J - 1, nc);
-        const int K2 = (k & 1) ? wrap_up(K + 1, nc) : wrap_dn(K - 1, nc);
-        // weights 3/4 (own coarse cell) and 1/4 (neighbour) per axis
-        const double v = 0.421875 * coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I, J, K) +
-                         0.140625 * (coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I2, J, K) +
-                                     coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I, J2, K) +
-                                     coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I, J, K2)) +
-                         0.046875 * (coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I2, J2, K) +
-                                     coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I2, J, K2) +
-                                     coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I, J2, K2)) +
-                         0.015625 * coarse_corr(cxr, cxb, C.x0r, C.x0b, nc, nch, I2, J2, K2);
-        R *x = c ? xb : xr;
-        x[ef] = (R)((double)x[ef] + v);
+        int I, J, K;
+        split(e, nc, nc, I, J, K);
+        const int Is[3] = {wrap_dn(I - 1, nc), I, wrap_up(I + 1, nc)};
+        const int Js[3] = {wrap_dn(J - 1, nc), J, wrap_up(J + 1, nc)};
+        const int Ks[3] = {wrap_dn(K - 1, nc), K, wrap_up(K + 1, nc)};
+        double lk[3][3][2];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int b = 0; b < 3; b++) {
+                double v[3];
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    v[c] = coarse_at(cxr, cxb, nc, nch, Is[a], Js[b], Ks[c]);
+                    if (CORR)
+                        v[c] -= coarse_at(C.x0r, C.x0b, nc, nch, Is[a], Js[b], Ks[c]);
+                }
+                lk[a][b][0] = 0.75 * v[1] + 0.25 * v[0];
+                lk[a][b][1] = 0.75 * v[1] + 0.25 * v[2];
+            }
+#pragma unroll
+        for (int aa = 0; aa < 2; aa++)
+#pragma unroll
+            for (int bb = 0; bb < 2; bb++) {
+                const int i = 2 * I + aa, j = 2 * J + bb;
+                const unsigned ef = ((unsigned)i * F.n + j) * F.nh + K;
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    double lj[3];
+#pragma unroll
+                    for (int a = 0; a < 3; a++)
+                        lj[a] = 0.75 * lk[a][1][c] + 0.25 * lk[a][bb ? 2 : 0][c];
+                    const double v = 0.75 * lj[1] + 0.25 * lj[aa ? 2 : 0];
+                    R *x = ((aa + bb + c) & 1) ? xb : xr;
+                    if (CORR)
+                        x[ef] = (R)((double)x[ef] + v);
+                    else
+                        x[ef] = (R)v;
+                }
+            }
     }
 }
 
@@ -342,8 +407,16 @@ template <typename R>
 void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
                             hipStream_t st)
 {
-    const Span sp = make_span(2 * F.half);
-    hipLaunchKernelGGL((k_prolong_correct<R>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
+    const Span sp = make_span(2 * C.half);
+    hipLaunchKernelGGL((k_prolong<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
+}
+
+template <typename R>
+void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
+                         hipStream_t st)
+{
+    const Span sp = make_span(2 * C.half);
+    hipLaunchKernelGGL((k_prolong<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
 }
 
 // ------------------------------------------------------------- coarsest
@@ -461,21 +534,18 @@ __global__ __launch_bounds__(kBlock) void k_restrict_field(int nc, const R *__re
                                                            R *__restrict__ cr, R *__restrict__ cb, Span sp)
 {
     const int nch = nc / 2, nf = 2 * nc, nfh = nc;
-    const unsigned chalf = (unsigned)nc * nc * nch;
     PM_SPAN_LOOP(e, sp)
     {
-        const int c = e >= chalf;
-        const unsigned ec = e - (c ? chalf : 0u);
-        int I, J, KH;
-        split(ec, nch, nc, I, J, KH);
-        const int K = 2 * KH + ((I + J + c) & 1);
+        int I, J, K;
+        split(e, nc, nc, I, J, K);
         double t = 0.0;
         for (int a = 0; a < 2; a++)
             for (int b = 0; b < 2; b++) {
                 const unsigned ef = ((unsigned)(2 * I + a) * nf + (2 * J + b)) * nfh + K;
                 t += (double)fr[ef] + (double)fb[ef];
             }
-        (c ? cb : cr)[ec] = (R)(0.125 * t);
+        const unsigned ec = ((unsigned)I * nc + J) * nch + (K >> 1);
+        (((I + J + K) & 1) ? cb : cr)[ec] = (R)(0.125 * t);
     }
 }
 
@@ -751,9 +821,11 @@ void launch_zero(void *p, size_t bytes, hipStream_t st)
 
 // explicit instantiations
 template void launch_smooth<double>(const LevelView<double> &, int, const double *, const double *, double *,
-                                    const double *, double *, ReduceSlot, SolveConsts, bool, hipStream_t);
+                                    const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
+                                    hipStream_t, int *);
 template void launch_smooth<float>(const LevelView<float> &, int, const float *, const float *, float *,
-                                   const double *, double *, ReduceSlot, SolveConsts, bool, hipStream_t);
+                                   const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
+                                   hipStream_t, int *);
 template void launch_residual_restrict<double>(const LevelView<double> &, const double *, const double *,
                                                const double *, const LevelView<double> &, double *, double *,
                                                ReduceSlot, SolveConsts, bool, hipStream_t);
@@ -761,13 +833,17 @@ template void launch_residual_restrict<float>(const LevelView<float> &, const fl
                                               const LevelView<float> &, float *, float *, ReduceSlot, SolveConsts,
                                               bool, hipStream_t);
 template void launch_fas_tau<double>(const LevelView<double> &, const double *, const double *, double *, ReduceSlot,
-                                     SolveConsts, bool, hipStream_t);
+                                     SolveConsts, bool, bool, hipStream_t);
 template void launch_fas_tau<float>(const LevelView<float> &, const float *, const float *, double *, ReduceSlot,
-                                    SolveConsts, bool, hipStream_t);
+                                    SolveConsts, bool, bool, hipStream_t);
 template void launch_prolong_correct<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
                                              const double *, const double *, hipStream_t);
 template void launch_prolong_correct<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,
                                             const float *, const float *, hipStream_t);
+template void launch_prolong_full<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
+                                          const double *, const double *, hipStream_t);
+template void launch_prolong_full<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,
+                                         const float *, const float *, hipStream_t);
 template void launch_coarsest<double>(const LevelView<double> &, double *, double *, SolveConsts, bool, int,
                                       hipStream_t);
 template void launch_coarsest<float>(const LevelView<float> &, float *, float *, SolveConsts, bool, int, hipStream_t);

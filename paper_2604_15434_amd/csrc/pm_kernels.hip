@@ -40,42 +40,107 @@ __device__ __forceinline__ bool cic_axis(double x, int ng, int &i0, int &i1, dou
 // Each corner weight w in [0, 1] is added as round(w * 2^40) to a 64-bit
 // integer, which makes the sum independent of particle order (bitwise
 // reproducible) and loses at most 2^-41 per weight.
+//
+// A block takes a chunk of kDepChunk consecutive particles.  Particles of a
+// PM code are stored in (roughly) spatial order, so a chunk's CIC footprint
+// is a small box: the block accumulates it in LDS with 64-bit LDS atomics and
+// then adds each touched cell to the grid with one global atomic, instead of
+// 8 contended global atomics per particle.  A chunk whose box does not fit
+// the LDS tile (scattered order, or a chunk that straddles the periodic
+// boundary) falls back to direct global atomics.
+constexpr int kDepChunk = 1024;
+constexpr int kDepTile = 8192;  // 64 KB of 64-bit counters
+
 template <typename Tp>
-__global__ __launch_bounds__(kBlock) void k_deposit_fixed(const Tp *__restrict__ pos, unsigned np, int ng,
-                                                          unsigned long long *__restrict__ acc, Span sp)
+__global__ __launch_bounds__(kBlock) void k_deposit_tiled(const Tp *__restrict__ pos, unsigned np, int ng,
+                                                          unsigned long long *__restrict__ acc, unsigned nchunks)
 {
-    PM_SPAN_LOOP(p, sp)
-    {
+    __shared__ unsigned long long tile[kDepTile];
+    __shared__ int bmin[3], bmax[3];
+    const unsigned b = blockIdx.x;
+    const unsigned chunk = (gridDim.x % 8) ? b : (b % 8) * (gridDim.x / 8) + b / 8;
+    if (chunk >= nchunks)
+        return;
+    const unsigned p0 = chunk * kDepChunk;
+    const unsigned p1 = min(np, p0 + kDepChunk);
+    if (threadIdx.x < 3) {
+        bmin[threadIdx.x] = 0x7fffffff;
+        bmax[threadIdx.x] = -1;
+    }
+    __syncthreads();
+    int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+    for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
+        for (int d = 0; d < 3; d++) {
+            int i0, i1;
+            double f;
+            if (cic_axis((double)pos[(size_t)d * np + p], ng, i0, i1, f)) {
+                mn[d] = min(mn[d], i0);
+                mx[d] = max(mx[d], i0);
+            }
+        }
+    }
+    for (int d = 0; d < 3; d++) {
+        atomicMin(&bmin[d], mn[d]);
+        atomicMax(&bmax[d], mx[d]);
+    }
+    __syncthreads();
+    // box of base cells [bmin, bmax] plus one for the upper corners
+    const int ex = bmax[0] - bmin[0] + 2, ey = bmax[1] - bmin[1] + 2, ez = bmax[2] - bmin[2] + 2;
+    const bool use_tile = bmax[0] >= 0 && (long long)ex * ey * ez <= kDepTile;
+    const int vol = use_tile ? ex * ey * ez : 0;
+    for (int t = threadIdx.x; t < vol; t += kBlock)
+        tile[t] = 0ull;
+    __syncthreads();
+    for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
         int x0, x1, y0, y1, z0, z1;
         double fx, fy, fz;
-        if (!cic_axis((double)pos[p], ng, x0, x1, fx) || !cic_axis((double)pos[np + p], ng, y0, y1, fy) ||
-            !cic_axis((double)pos[2 * np + p], ng, z0, z1, fz))
+        if (!cic_axis((double)pos[p], ng, x0, x1, fx) || !cic_axis((double)pos[(size_t)np + p], ng, y0, y1, fy) ||
+            !cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz))
             continue;
         const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-        const int ix[2] = {x0, x1}, iy[2] = {y0, y1}, iz[2] = {z0, z1};
 #pragma unroll
         for (int a = 0; a < 2; a++)
 #pragma unroll
-            for (int b = 0; b < 2; b++)
+            for (int bb = 0; bb < 2; bb++)
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
-                    const double w = wx[a] * wy[b] * wz[c];
+                    const double w = wx[a] * wy[bb] * wz[c];
                     const unsigned long long q = (unsigned long long)(w * kFixScale + 0.5);
-                    if (q)
-                        atomicAdd(&acc[((unsigned)ix[a] * ng + iy[b]) * ng + iz[c]], q);
+                    if (!q)
+                        continue;
+                    if (use_tile) {
+                        const int li = ((x0 - bmin[0] + a) * ey + (y0 - bmin[1] + bb)) * ez + (z0 - bmin[2] + c);
+                        atomicAdd(&tile[li], q);
+                    } else {
+                        const int gi = a ? x1 : x0, gj = bb ? y1 : y0, gk = c ? z1 : z0;
+                        atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], q);
+                    }
                 }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < vol; t += kBlock) {
+        const unsigned long long v = tile[t];
+        if (!v)
+            continue;
+        const int kk = t % ez, r = t / ez, jj = r % ey, ii = r / ey;
+        int gi = bmin[0] + ii, gj = bmin[1] + jj, gk = bmin[2] + kk;
+        gi = gi >= ng ? gi - ng : gi;
+        gj = gj >= ng ? gj - ng : gj;
+        gk = gk >= ng ? gk - ng : gk;
+        atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], v);
     }
 }
 
 void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc, hipStream_t st)
 {
-    const Span sp = make_span(np);
+    const unsigned nchunks = (unsigned)((np + kDepChunk - 1) / kDepChunk);
+    unsigned nb = nchunks >= 8 ? (nchunks + 7) / 8 * 8 : nchunks;
     if (dt == PM_F64)
-        hipLaunchKernelGGL((k_deposit_fixed<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)pos,
-                           (unsigned)np, ng, acc, sp);
+        hipLaunchKernelGGL((k_deposit_tiled<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)pos,
+                           (unsigned)np, ng, acc, nchunks);
     else
-        hipLaunchKernelGGL((k_deposit_fixed<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)pos,
-                           (unsigned)np, ng, acc, sp);
+        hipLaunchKernelGGL((k_deposit_tiled<float>), dim3(nb), dim3(kBlock), 0, st, (const float *)pos, (unsigned)np,
+                           ng, acc, nchunks);
 }
 
 // fixed point (natural layout) -> packed delta_raw = rho - 1, with its sum.

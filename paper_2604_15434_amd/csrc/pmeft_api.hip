@@ -67,7 +67,7 @@ struct Plan {
     long long N = 0, np = 0;
     int n[kMaxLevels] = {};
     size_t total = 0;
-    size_t red_partials = 0, red_counter = 0, red_out = 0, csum64 = 0, csum32 = 0, outer_out = 0;
+    size_t red_partials = 0, red_counter = 0, red_out = 0, csum64 = 0, csum32 = 0, outer_out = 0, sm_partials = 0;
     size_t delta64[kMaxLevels] = {};
     size_t psi64 = 0, chi64 = 0;
     size_t p64[kMaxLevels] = {}, q64[kMaxLevels] = {}, t64[kMaxLevels] = {}, x064[kMaxLevels] = {};
@@ -101,8 +101,9 @@ static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
     P.red_counter = take(c, 256);
     P.red_out = take(c, sizeof(double) * 8);
     P.outer_out = take(c, sizeof(double) * 8);
-    P.csum64 = take(c, sizeof(double) * 2 * kMaxLevels);
-    P.csum32 = take(c, sizeof(double) * 2 * kMaxLevels);
+    P.csum64 = take(c, sizeof(double) * 2 * 2 * kMaxLevels);
+    P.csum32 = take(c, sizeof(double) * 2 * 2 * kMaxLevels);
+    P.sm_partials = take(c, sizeof(double) * 8 * kMaxBlocks * 2 * kMaxLevels);
     for (int l = 0; l < P.nlev; l++)
         P.delta64[l] = take(c, sizeof(double) * (size_t)P.n[l] * P.n[l] * P.n[l]);
     P.psi64 = take(c, sizeof(double) * P.N);
@@ -143,7 +144,7 @@ struct Ctx {
     char *ws = nullptr;
     hipStream_t st = nullptr;
     ReduceSlot rs;
-    double *csum64 = nullptr, *csum32 = nullptr, *outer_out = nullptr;
+    double *csum64 = nullptr, *csum32 = nullptr, *outer_out = nullptr, *sm_partials = nullptr;
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
 };
@@ -179,6 +180,7 @@ static int setup_ctx(Ctx &C, void *ws, size_t ws_bytes, int ng, long long np, pm
     C.csum64 = C.at<double>(C.P.csum64);
     C.csum32 = C.at<double>(C.P.csum32);
     C.outer_out = C.at<double>(C.P.outer_out);
+    C.sm_partials = C.at<double>(C.P.sm_partials);
     launch_zero(C.ws + C.P.red_counter, 256, C.st);
     return launched();
 }
@@ -191,16 +193,34 @@ static int read_out(Ctx &C, const double *dev, double *host, int count)
 }
 
 // Hierarchy of one precision: per-level ping-pong buffers and flags telling
-// which buffer holds the current red / black values.
+// which buffer holds the current red / black values, double-buffered
+// per-colour sums of Lq + tau (the lagged mean) and the partial sums of the
+// last half-sweep still to be folded into them.
 template <typename R>
 struct Hier {
     int nlev = 0;
     LevelView<R> L[kMaxLevels];
     R *buf[kMaxLevels][2];
     int cur[kMaxLevels][2];  // [level][colour] -> buffer index
-    double *csum = nullptr;  // [level][2]
+    double *csum = nullptr;  // [2][kMaxLevels][2]
+    double *parts = nullptr; // [kMaxLevels][2][kMaxBlocks * 8]
+    int cs[kMaxLevels];      // current csum buffer per level
+    int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
     R *xr(int l) { return buf[l][cur[l][0]]; }
     R *xb(int l) { return buf[l][cur[l][1]] + L[l].half; }
+    double *csum_cur(int l) { return csum + ((size_t)cs[l] * kMaxLevels + l) * 2; }
+    double *csum_alt(int l) { return csum + ((size_t)(cs[l] ^ 1) * kMaxLevels + l) * 2; }
+    double *part(int l, int k) { return parts + ((size_t)l * 2 + k) * 8 * kMaxBlocks; }
+    // the level's mean was just set exactly (csum_cur); nothing pending
+    void fresh(int l) { pend_col[l] = -1; }
+    void init_state(int l)
+    {
+        cur[l][0] = cur[l][1] = 0;
+        cs[l] = 0;
+        pend_col[l] = -1;
+        pend_nb[l] = 0;
+        next_part[l] = 0;
+    }
 };
 
 template <typename R>
@@ -231,8 +251,9 @@ static void build_hier64(Ctx &C, Hier<double> &H, double *master)
                                    l ? C.at<double>(P.x064[l]) : nullptr);
         H.buf[l][0] = l ? C.at<double>(P.p64[l]) : master;
         H.buf[l][1] = C.at<double>(P.q64[l]);
-        H.cur[l][0] = H.cur[l][1] = 0;
+        H.init_state(l);
     }
+    H.parts = C.sm_partials;
 }
 
 static void build_hier32(Ctx &C, Hier<float> &H)
@@ -245,8 +266,9 @@ static void build_hier32(Ctx &C, Hier<float> &H)
         H.L[l] = make_view<float>(P.n[l], h, C.at<float>(P.d32[l]), C.at<float>(P.t32[l]), C.at<float>(P.x032[l]));
         H.buf[l][0] = C.at<float>(P.p32[l]);
         H.buf[l][1] = C.at<float>(P.q32[l]);
-        H.cur[l][0] = H.cur[l][1] = 0;
+        H.init_state(l);
     }
+    H.parts = C.sm_partials;
 }
 
 // ------------------------------------------------------- kernel timing
@@ -284,10 +306,19 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     }
     if (e0)
         (void)hipEventRecord(e0, C.st);
-    launch_smooth<R>(H.L[l], colour, src, oth, dst, H.csum + 2 * l, H.csum + 2 * l + colour, C.rs, sc, nl, C.st);
+    ReduceSlot rs = C.rs;
+    const int k = H.next_part[l];
+    rs.partials = H.part(l, k);
+    int nb = 0;
+    launch_smooth<R>(H.L[l], colour, src, oth, dst, H.csum_cur(l), H.csum_alt(l), H.part(l, k ^ 1), H.pend_nb[l],
+                     H.pend_col[l], rs, sc, nl, C.st, &nb);
     if (e1)
         (void)hipEventRecord(e1, C.st);
     H.cur[l][colour] = 1 - own;
+    H.cs[l] ^= 1;
+    H.pend_col[l] = colour;
+    H.pend_nb[l] = nb;
+    H.next_part[l] = k ^ 1;
 }
 
 constexpr int kCoarseSweeps = 100;
@@ -306,14 +337,42 @@ static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveCon
         smooth(C, H, l, 1, sc, nl);
     }
     H.cur[l + 1][0] = H.cur[l + 1][1] = 0;
-    launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum + 2 * l, H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
+    launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
                                 sc, nl, C.st);
-    launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum + 2 * (l + 1), C.rs, sc, nl, C.st);
+    launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum_cur(l + 1), C.rs, sc, nl, false, C.st);
+    H.fresh(l + 1);
     vcycle_from(C, H, l + 1, o, sc, nl);
     launch_prolong_correct<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
     for (int s = 0; s < o.n_post; s++) {
         smooth(C, H, l, 0, sc, nl);
         smooth(C, H, l, 1, sc, nl);
+    }
+}
+
+// Full multigrid start from a zero iterate: each level's problem takes the
+// restricted source of the level above (the level-0 tau, if any, restricted
+// down; zero otherwise), the coarsest is solved, and each finer level starts
+// from the prolongated solution of the coarser one and gets one V-cycle.
+template <typename R>
+static void fmg_start(Ctx &C, Hier<R> &H, const pm_mg_opts &o, SolveConsts sc, bool nl)
+{
+    const int L = H.nlev;
+    for (int l = 1; l < L; l++) {
+        LevelView<R> &F = H.L[l - 1], &G = H.L[l];
+        if (F.tr)
+            launch_restrict_field<R>(G.n, F.tr, F.tb, G.tr, G.tb, C.st);
+        else
+            launch_zero(G.tr, sizeof(R) * 2 * G.half, C.st);
+    }
+    H.cur[L - 1][0] = H.cur[L - 1][1] = 0;
+    launch_zero(H.buf[L - 1][0], sizeof(R) * 2 * H.L[L - 1].half, C.st);
+    launch_coarsest<R>(H.L[L - 1], H.xr(L - 1), H.xb(L - 1), sc, nl, kCoarseSweeps, C.st);
+    for (int l = L - 2; l >= 0; l--) {
+        H.cur[l][0] = H.cur[l][1] = 0;
+        launch_prolong_full<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
+        launch_fas_tau<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), C.rs, sc, nl, true, C.st);
+        H.fresh(l);
+        vcycle_from(C, H, l, o, sc, nl);
     }
 }
 
@@ -333,29 +392,36 @@ static void record(SolveOut &so, int i, double rel)
 // FP64 solve of one field held packed in `master` (initial guess in, solution
 // out).  src_norm = ||beta delta / nu||_2.
 static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                     SolveOut &so)
+                     SolveOut &so, bool zero_start)
 {
     Hier<double> H;
     build_hier64(C, H, master);
     const long long N = C.P.N;
-    // exact mean of Lq on the fine level for the first half-sweep
-    launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum, C.rs, sc, nl, C.st);
+    int fmg = 0;
+    if (zero_start && o.max_vcycles > 0) {
+        fmg_start<double>(C, H, o, sc, nl);  // counts as the first V-cycle
+        fmg = 1;
+    } else {
+        // exact mean of Lq on the fine level for the first half-sweep
+        launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st);
+        H.fresh(0);
+    }
     double out[8];
-    int it = 0;
+    int it = fmg;
     for (;; it++) {
         for (int s = 0; s < o.n_pre; s++) {
             smooth(C, H, 0, 0, sc, nl);
             smooth(C, H, 0, 1, sc, nl);
         }
         H.cur[1][0] = H.cur[1][1] = 0;
-        launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum, H.L[1], H.xr(1), H.xb(1), C.rs, sc, nl,
-                                         C.st);
+        launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), H.L[1], H.xr(1), H.xb(1), C.rs, sc,
+                                         nl, C.st);
         int e = read_out(C, C.rs.out, out, 4);
         if (e)
             return e;
         const double r2 = fmax(out[0] - out[1] * out[1] / (double)N, 0.0);
         const double rel = sqrt(r2) / src_norm;
-        record(so, it, rel);
+        record(so, it - fmg, rel);
         so.mean_shift = out[2] / (double)N;
         so.clamped = (long long)out[3];
         if (!isfinite(rel)) {
@@ -370,7 +436,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
             so.status = PM_ENOCONV;
             break;
         }
-        launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum + 2, C.rs, sc, nl, C.st);
+        launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum_cur(1), C.rs, sc, nl, false, C.st);
+        H.fresh(1);
         vcycle_from(C, H, 1, o, sc, nl);
         launch_prolong_correct<double>(H.L[0], H.xr(0), H.xb(0), H.L[1], H.xr(1), H.xb(1), C.st);
         for (int s = 0; s < o.n_post; s++) {
@@ -404,7 +471,7 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
 constexpr double kMixedSwitchNL = 3e-5;
 
 static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                       SolveOut &so)
+                       SolveOut &so, bool zero_start)
 {
     Hier<float> H;
     build_hier32(C, H);
@@ -412,7 +479,7 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     LevelView<double> F64 = make_view<double>(C.P.n[0], 1.0 / C.P.n[0], C.at<double>(C.P.delta64[0]), nullptr, nullptr);
     const long long half = F64.half;
     // exact initial mean of Lq64
-    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, C.st);
+    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, true, C.st);
     ReduceSlot ro = C.rs;
     ro.out = C.outer_out;
     // the FP32 correction equation of a linear problem has no source term
@@ -424,12 +491,13 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     bool to_f64 = false;
     for (;; it++) {
         H.cur[0][0] = H.cur[0][1] = 0;
-        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), C.csum32, ro, sc,
-                                    nl, C.st);
+        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), nullptr, ro, sc, nl,
+                                    C.st);
         // lagged means for the next outer residual and the FP32 level 0
         PM_HIP(hipMemcpyAsync(C.csum64, C.outer_out + 2, sizeof(double), hipMemcpyDeviceToDevice, C.st));
         launch_zero(C.csum64 + 1, sizeof(double), C.st);
-        PM_HIP(hipMemcpyAsync(C.csum32, C.outer_out + 4, 2 * sizeof(double), hipMemcpyDeviceToDevice, C.st));
+        PM_HIP(hipMemcpyAsync(H.csum_cur(0), C.outer_out + 4, 2 * sizeof(double), hipMemcpyDeviceToDevice, C.st));
+        H.fresh(0);
         int e = read_out(C, C.outer_out, out, 4);
         if (e)
             return e;
@@ -455,7 +523,10 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
             break;
         }
         prev = rel;
-        vcycle_from<float>(C, H, 0, o, sc32, nl);
+        if (it == 0 && zero_start)
+            fmg_start<float>(C, H, o, sc32, nl);
+        else
+            vcycle_from<float>(C, H, 0, o, sc32, nl);
         launch_mixed_correct(master, H.xr(0), H.xb(0), H.L[0].x0r, H.L[0].x0b, half, C.st);
     }
     so.vcycles = it;
@@ -466,7 +537,7 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     pm_mg_opts o64 = o;
     o64.max_vcycles = o.max_vcycles - it;
     SolveOut s64;
-    e = solve_f64(C, master, sc, nl, o64, src_norm, s64);
+    e = solve_f64(C, master, sc, nl, o64, src_norm, s64, false);
     if (e)
         return e;
     for (int i = 0; i <= s64.vcycles && it + i < 64; i++)
@@ -535,10 +606,10 @@ static bool opts_ok(const pm_mg_opts *o)
 static int prec_bits(const pm_mg_opts *o) { return o->precision == PM_PREC_MIXED ? (kPrecMixed | kPrecF64) : kPrecF64; }
 
 static int run_solve(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                     SolveOut &so)
+                     SolveOut &so, bool zero_start)
 {
-    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so)
-                                        : solve_f64(C, master, sc, nl, o, src_norm, so);
+    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so, zero_start)
+                                        : solve_f64(C, master, sc, nl, o, src_norm, so, zero_start);
 }
 
 // Poisson: lap psi = s delta (nu = 1, K = 0, beta = s).
@@ -554,7 +625,7 @@ static int poisson_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, So
         so = SolveOut();
         return launched();
     }
-    return run_solve(C, m, sc, false, o, src, so);
+    return run_solve(C, m, sc, false, o, src, so, o.guess != PM_GUESS_GIVEN);
 }
 
 // Scalar field: nu lap chi - xi s delta - K N(chi) = 0 (beta = xi s).
@@ -581,11 +652,11 @@ static int scalar_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, Sol
         lo.max_vcycles = 4;
         SolveOut tmp;
         SolveConsts lin{cf.nu, 0.0, cf.xi * cf.s};
-        int e = run_solve(C, m, lin, false, lo, src, tmp);
+        int e = run_solve(C, m, lin, false, lo, src, tmp, true);
         if (e)
             return e;
     }
-    return run_solve(C, m, sc, nl, o, src, so);
+    return run_solve(C, m, sc, nl, o, src, so, o.guess == PM_GUESS_ZERO);
 }
 
 struct Timer {

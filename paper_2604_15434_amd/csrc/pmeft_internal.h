@@ -156,10 +156,12 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], const ReduceSlot
 void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, hipStream_t st);
 
 // ---- launchers (mg_kernels.hip) ------------------------------------------
+// One red-black half-sweep (see k_smooth).  Writes its per-block partial
+// sums of Lq + tau to rs.partials and returns the block count.
 template <typename R>
-void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new,
-                   const double *csum, double *csum_out_colour, ReduceSlot rs, SolveConsts sc, bool nonlinear,
-                   hipStream_t st);
+void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
+                   double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out);
 
 // Fine-level residual r = Lq + tau - c - lap x fused with the 8-child
 // restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
@@ -170,16 +172,21 @@ void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, c
                               const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
                               hipStream_t st);
 
-// Coarse FAS source: tau += lap x - Lq(x); writes sum(Lq + tau) per colour
-// into csum[0..1].
+// Coarse FAS source: tau += lap x - Lq(x) (unless accumulate_only or the
+// level has no tau); writes sum(Lq + tau) per colour into csum[0..1].
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, hipStream_t st);
+                    bool nonlinear, bool accumulate_only, hipStream_t st);
 
 // Fine x += P (x_H - x0_H), trilinear cell-centred prolongation.
 template <typename R>
 void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr,
                             const R *cxb, hipStream_t st);
+
+// Fine x = P x_H (full-approximation prolongation, to start full multigrid).
+template <typename R>
+void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
+                         hipStream_t st);
 
 // Coarsest level solved by one workgroup in FP64.
 template <typename R>

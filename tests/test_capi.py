@@ -1,0 +1,68 @@
+"""The C ABI library: every function declared in include/pmeft.h is exported,
+and the host-only entry points behave (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmeft.h")
+LIB = os.path.join(ROOT, "paper_2604_15434_amd", "libpmeft.so")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", src, flags=re.M)
+    return sorted({n for n in names if n.startswith(("pm_", "mg_"))})
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpmeft.so is not built (python -m paper_2604_15434_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_symbols_are_exported(lib):
+    names = _declared()
+    assert {"pm_deposit", "mg_poisson_solve", "mg_scalar_solve", "pm_force_interp", "pm_step"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_coefficients_match_oracle():
+    import paper_2604_15434_amd as P
+
+    for p in (dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=0.5),
+              dict(omega_m0=0.3071, alpha_b0=-0.6, alpha_m0=0.1, a=1.0),
+              dict(omega_m0=0.3, alpha_b0=-0.5, alpha_m0=0.0, a=1.0, alpha_b_dot=0),
+              dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.1, a=0.33, screening=0)):
+        got = P.pm_eft_coefficients(p)
+        ref = oracle.eft_coefficients(p["omega_m0"], p["alpha_b0"], p["alpha_m0"], p["a"],
+                                      screening=bool(p.get("screening", 1)), alpha_b_dot=bool(p.get("alpha_b_dot", 1)))
+        for k in ("nu", "xi", "C2", "C4", "K", "s", "geff", "mu_chi", "mu_psi", "lam"):
+            kk = "lambda" if k == "lam" else k
+            assert got[kk] == pytest.approx(ref[k], rel=1e-13, abs=1e-15), k
+        assert got["status"] == 0
+
+
+def test_unstable_model_reported():
+    import paper_2604_15434_amd as P
+
+    assert P.pm_eft_coefficients(dict(omega_m0=0.3071, alpha_b0=0.5, alpha_m0=0.0, a=1.0))["status"] == -2
+
+
+def test_grid_levels_and_workspace():
+    import paper_2604_15434_amd as P
+
+    assert [P.pm_grid_levels(n) for n in (4, 8, 10, 12, 24, 32, 40, 192, 256, 512, 1024, 2048)] == \
+        [0, 2, 0, 2, 3, 4, 0, 6, 7, 8, 9, 0]
+    assert P.pm_workspace_bytes(10, 0, 1) == 0
+    b64 = P.pm_workspace_bytes(64, 0, 1, "f64")
+    bany = P.pm_workspace_bytes(64, 64**3, 1, "any")
+    assert 0 < b64 < bany
+    assert P.pm_strerror(-6) == "workspace too small"
