@@ -163,6 +163,51 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,
             void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* ---- Learned warm start ------------------------------------------------
+ * A 3-level 3D U-Net maps the density and (alpha_B0, alpha_M0, a) to an
+ * initial scalar field; multigrid then finishes the solve as usual (pass the
+ * result with PM_GUESS_GIVEN).  Input channels: standardised ln(rho + 1e-3)
+ * and the three parameters broadcast; 3x3x3 periodic convolutions with ReLU
+ * (16-16 / 32-32 / 64-64 channels on grids n, n/2, n/4), 2x2x2 average
+ * pooling, nearest-neighbour upsampling, skip concatenations (96 -> 32,
+ * 48 -> 16) and a 1x1x1 head.  The output yhat is the field in units of
+ * h^2 s mu_chi: chi0 = h^2 s mu_chi (yhat - <yhat>).  Convolutions run on the
+ * matrix cores in BF16 with FP32 accumulation; activations are BF16.
+ *
+ * Parameters: one FP32 device array of ws_unet_param_count() values: for each
+ * convolution in order (l1a 4->16, l1b 16->16, l2a 16->32, l2b 32->32, l3a
+ * 32->64, l3b 64->64, l4a 96->32, l4b 32->32, l5a 48->16, l5b 16->16) its
+ * weight W[27][cin][cout] (tap t = (di+1)*9 + (dj+1)*3 + (dk+1) for the
+ * neighbour offset (di, dj, dk)) followed by its bias[cout]; then the head's
+ * 16 weights and 1 bias.  ng must be a multiple of 64. */
+long long ws_unet_param_count(void);
+size_t ws_unet_workspace_bytes(int ng, int training);
+
+/* Forward pass.  rho: ng^3 FP64 density (natural order); yhat_out: ng^3 FP32
+ * or NULL; chi_out: ng^3 of `dtype` (the initial field chi0) or NULL. */
+int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
+                    float *yhat_out, void *chi_out, pm_dtype dtype, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* One training step on one sample: forward, MSE loss against the target
+ * field chi_target (ng^3 FP64, converted to units of h^2 s mu_chi),
+ * backward, and (if lr > 0) an Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias correction with `step` >= 1) on the FP32 params with moment arrays
+ * adam_m, adam_v.  grad_out (param_count FP32, nullable) receives the
+ * gradients; *loss (HOST, nullable) the sample's loss (this call then
+ * synchronises the stream).  Weight gradients accumulate with FP32 atomics,
+ * so their last bits depend on scheduling. */
+int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, const double *rho,
+                       const double *chi_target, int ng, const pm_eft_params *p /* HOST */, float *grad_out,
+                       double *loss /* HOST */, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* One 3x3x3 periodic convolution on BF16 channels-last tensors with FP32
+ * output (for testing the kernels): mode 0 forward out[n^3][cout] =
+ * b + conv(x); mode 1 input gradient out[n^3][cin] from dy[n^3][cout]; mode
+ * 2 weight gradient out[27][cin][cout] from x and dy.  w: FP32 W[27][cin][cout]
+ * (device); ws: at least 2 * 27 * pad16(cin) * pad16(cout) * 2 + 512 bytes. */
+int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
+             const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream);
+
 /* Measurement hooks.  While enabled, each launch of the finest-level
  * red-black smoother (one colour per launch) is bracketed by HIP events on
  * the stream it runs on (a fixed pool of 16384 launches; later launches go

@@ -47,7 +47,8 @@ class StepReport(ctypes.Structure):
 
 EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_deposit", "mg_poisson_solve",
            "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
-           "pm_strerror")
+           "pm_strerror", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
+           "ws_conv3")
 
 
 def _load():
@@ -68,6 +69,14 @@ def _load():
                             vp, sz, vp]
     lib.pm_kernel_timing_enable.argtypes = [i]
     lib.pm_kernel_timing_read.argtypes = [P(d), P(ll)]
+    lib.ws_unet_param_count.restype = ll
+    lib.ws_unet_workspace_bytes.argtypes = [i, i]
+    lib.ws_unet_workspace_bytes.restype = sz
+    lib.ws_unet_forward.argtypes = [vp, vp, i, P(EftParams), vp, vp, i, vp, sz, vp]
+    lib.ws_unet_train_step.argtypes = [vp, vp, vp, ll, d, vp, vp, i, P(EftParams), vp, P(d), vp, sz, vp]
+    lib.ws_conv3.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp, sz, vp]
+    for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3"):
+        getattr(lib, name).restype = i
     lib.pm_strerror.argtypes = [i]
     lib.pm_strerror.restype = ctypes.c_char_p
     for name in ("pm_eft_coefficients", "pm_grid_levels", "pm_deposit", "mg_poisson_solve", "mg_scalar_solve",

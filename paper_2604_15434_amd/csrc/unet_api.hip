@@ -1,0 +1,377 @@
+// Native executor of the learned warm start (a 3-level 3D U-Net): parameter
+// layout, workspace planning, forward, backward, Adam, and the C ABI entry
+// points ws_* declared in pmeft.h.
+#include "pmeft_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace pmeft {
+
+// kernels (unet_kernels.hip)
+void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
+                  const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
+                  bool relu, hipStream_t st);
+void launch_conv3_wgrad(const uint16_t *x, int x_stride, int x_off, int cin, const uint16_t *dy, int dy_stride,
+                        int dy_off, int cout, float *dw, int n, hipStream_t st);
+void launch_bias_grad(const uint16_t *dy, int stride, int off, int cout, unsigned nvox, float *db, hipStream_t st);
+void launch_relu_bwd(uint16_t *dy, int dstride, int doff, const uint16_t *y, int ystride, int yoff, int C,
+                     unsigned nvox, hipStream_t st);
+void launch_pool(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nc,
+                 hipStream_t st);
+void launch_pool_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nf,
+                     hipStream_t st);
+void launch_up(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nf,
+               hipStream_t st);
+void launch_up_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nc,
+                   hipStream_t st);
+void launch_lnrho_stats(const double *rho, unsigned long long n, ReduceSlot rs, hipStream_t st);
+void launch_unet_input(const double *rho, unsigned nvox, const double *stats, float ab0, float am0, float a,
+                       uint16_t *x0, hipStream_t st);
+void launch_head(const uint16_t *b5, const float *hw, const float *hb, unsigned nvox, float *yhat, hipStream_t st);
+void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5, const float *hw, unsigned nvox,
+                          uint16_t *db5, float *ghw, float *ghb, float *loss, hipStream_t st);
+void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
+                      hipStream_t st);
+void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st);
+void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st);
+void launch_yhat_to_chi(const float *yhat, unsigned n, double scale, void *chi, pm_dtype dt, ReduceSlot rs,
+                        hipStream_t st);
+
+namespace {
+
+struct ConvSpec {
+    int cin, cout;
+};
+// l1a l1b l2a l2b l3a l3b l4a l4b l5a l5b
+constexpr ConvSpec kConv[10] = {{4, 16},  {16, 16}, {16, 32}, {32, 32}, {32, 64},
+                                {64, 64}, {96, 32}, {32, 32}, {48, 16}, {16, 16}};
+
+inline int pad16(int c) { return (c + 15) / 16 * 16; }
+
+struct ParamLayout {
+    long long w[10], b[10], hw, hb, total;
+};
+
+ParamLayout param_layout()
+{
+    ParamLayout L;
+    long long o = 0;
+    for (int l = 0; l < 10; l++) {
+        L.w[l] = o;
+        o += 27LL * kConv[l].cin * kConv[l].cout;
+        L.b[l] = o;
+        o += kConv[l].cout;
+    }
+    L.hw = o;
+    o += 16;
+    L.hb = o;
+    o += 1;
+    L.total = o;
+    return L;
+}
+
+// activation tensors: name, level (0: n, 1: n/2, 2: n/4), channels
+enum { X0, A1, C1, P1, A2, C2, P2, A3, B3, A4, B4, A5, B5, NT };
+constexpr int kTLevel[NT] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 0, 0};
+constexpr int kTChan[NT] = {16, 16, 48, 16, 32, 96, 32, 64, 64, 32, 32, 16, 16};
+
+struct NetPlan {
+    int n = 0;
+    bool training = false;
+    size_t total = 0;
+    size_t red_partials = 0, red_out = 0;
+    size_t wf[10] = {}, wd[10] = {};
+    size_t act[NT] = {}, grad[NT] = {};
+    size_t yhat = 0, target = 0, pgrad = 0, loss = 0;
+};
+
+size_t take(size_t &cur, size_t bytes)
+{
+    const size_t o = cur;
+    cur += (bytes + 255) & ~(size_t)255;
+    return o;
+}
+
+bool net_plan(NetPlan &P, int n, bool training)
+{
+    if (n < 64 || n > 1024 || n % 64)
+        return false;
+    P = NetPlan();
+    P.n = n;
+    P.training = training;
+    size_t c = 0;
+    P.red_partials = take(c, sizeof(double) * 8 * kMaxBlocks);
+    P.red_out = take(c, sizeof(double) * 8);
+    for (int l = 0; l < 10; l++) {
+        const size_t sz = sizeof(uint16_t) * 27 * pad16(kConv[l].cin) * pad16(kConv[l].cout);
+        P.wf[l] = take(c, sz);
+        if (training && l > 0)
+            P.wd[l] = take(c, sz);
+    }
+    for (int t = 0; t < NT; t++) {
+        const size_t m = (size_t)(n >> kTLevel[t]);
+        const size_t sz = sizeof(uint16_t) * m * m * m * kTChan[t];
+        P.act[t] = take(c, sz);
+        if (training && t != X0)
+            P.grad[t] = take(c, sz);
+    }
+    const size_t n3 = (size_t)n * n * n;
+    P.yhat = take(c, sizeof(float) * n3);
+    if (training) {
+        P.target = take(c, sizeof(float) * n3);
+        P.pgrad = take(c, sizeof(float) * param_layout().total);
+        P.loss = take(c, 256);
+    }
+    P.total = c + 256;
+    return true;
+}
+
+struct Net {
+    NetPlan P;
+    char *ws;
+    hipStream_t st;
+    ReduceSlot rs;
+    uint16_t *act(int t) const { return (uint16_t *)(ws + P.act[t]); }
+    uint16_t *grad(int t) const { return (uint16_t *)(ws + P.grad[t]); }
+    int dim(int t) const { return P.n >> kTLevel[t]; }
+    unsigned nvox(int t) const { return (unsigned)dim(t) * dim(t) * dim(t); }
+};
+
+int launched() { return hipGetLastError() == hipSuccess ? PM_OK : PM_EHIP; }
+
+void pack_all(Net &N, const float *params)
+{
+    const ParamLayout L = param_layout();
+    for (int l = 0; l < 10; l++)
+        launch_pack_conv(params + L.w[l], kConv[l].cin, kConv[l].cout, pad16(kConv[l].cin), pad16(kConv[l].cout),
+                         (uint16_t *)(N.ws + N.P.wf[l]), N.P.wd[l] ? (uint16_t *)(N.ws + N.P.wd[l]) : nullptr, N.st);
+}
+
+// conv layer l: input tensor (ti, channel offset), output (to, offset)
+void conv_fwd(Net &N, const float *params, int l, int ti, int ioff, int to, int ooff)
+{
+    const ParamLayout L = param_layout();
+    launch_conv3(N.act(ti), kTChan[ti], ioff, pad16(kConv[l].cin), (const uint16_t *)(N.ws + N.P.wf[l]),
+                 pad16(kConv[l].cout), params + L.b[l], kConv[l].cout, N.act(to), kTChan[to], ooff, false, N.dim(to),
+                 false, true, N.st);
+}
+
+void forward(Net &N, const float *params, const double *rho, const pm_eft_params &p)
+{
+    const int n = N.P.n;
+    const unsigned nv = (unsigned)n * n * n;
+    launch_lnrho_stats(rho, nv, N.rs, N.st);
+    launch_unet_input(rho, nv, N.rs.out, (float)p.alpha_b0, (float)p.alpha_m0, (float)p.a, N.act(X0), N.st);
+    conv_fwd(N, params, 0, X0, 0, A1, 0);
+    conv_fwd(N, params, 1, A1, 0, C1, 32);  // skip 1 -> C1[32:48]
+    launch_pool(N.act(C1), 48, 32, N.act(P1), 16, 0, 16, n / 2, N.st);
+    conv_fwd(N, params, 2, P1, 0, A2, 0);
+    conv_fwd(N, params, 3, A2, 0, C2, 64);  // skip 2 -> C2[64:96]
+    launch_pool(N.act(C2), 96, 64, N.act(P2), 32, 0, 32, n / 4, N.st);
+    conv_fwd(N, params, 4, P2, 0, A3, 0);
+    conv_fwd(N, params, 5, A3, 0, B3, 0);
+    launch_up(N.act(B3), 64, 0, N.act(C2), 96, 0, 64, n / 2, N.st);
+    conv_fwd(N, params, 6, C2, 0, A4, 0);
+    conv_fwd(N, params, 7, A4, 0, B4, 0);
+    launch_up(N.act(B4), 32, 0, N.act(C1), 48, 0, 32, n, N.st);
+    conv_fwd(N, params, 8, C1, 0, A5, 0);
+    conv_fwd(N, params, 9, A5, 0, B5, 0);
+    const ParamLayout L = param_layout();
+    launch_head(N.act(B5), params + L.hw, params + L.hb, nv, (float *)(N.ws + N.P.yhat), N.st);
+}
+
+// backward of conv layer l given the (already ReLU-masked) output gradient
+// (tg, goff): weight and bias gradients, and the input gradient into
+// (gi, gioff) unless gi < 0.
+void conv_bwd(Net &N, int l, int ti, int ioff, int tg, int goff, int gi, int gioff)
+{
+    const ParamLayout L = param_layout();
+    float *pg = (float *)(N.ws + N.P.pgrad);
+    launch_conv3_wgrad(N.act(ti), kTChan[ti], ioff, kConv[l].cin, N.grad(tg), kTChan[tg], goff, kConv[l].cout,
+                       pg + L.w[l], N.dim(tg), N.st);
+    launch_bias_grad(N.grad(tg), kTChan[tg], goff, kConv[l].cout, N.nvox(tg), pg + L.b[l], N.st);
+    if (gi >= 0)
+        launch_conv3(N.grad(tg), kTChan[tg], goff, pad16(kConv[l].cout), (const uint16_t *)(N.ws + N.P.wd[l]),
+                     pad16(kConv[l].cin), nullptr, kConv[l].cin, N.grad(gi), kTChan[gi], gioff, false, N.dim(gi),
+                     true, false, N.st);
+}
+
+void mask(Net &N, int tg, int goff, int ta, int aoff, int C)
+{
+    launch_relu_bwd(N.grad(tg), kTChan[tg], goff, N.act(ta), kTChan[ta], aoff, C, N.nvox(ta), N.st);
+}
+
+void backward(Net &N, const float *params)
+{
+    const int n = N.P.n;
+    const unsigned nv = (unsigned)n * n * n;
+    const ParamLayout L = param_layout();
+    float *pg = (float *)(N.ws + N.P.pgrad);
+    launch_zero(pg, sizeof(float) * L.total, N.st);
+    launch_zero(N.ws + N.P.loss, 256, N.st);
+    launch_head_loss_bwd((const float *)(N.ws + N.P.yhat), (const float *)(N.ws + N.P.target), N.act(B5),
+                         params + L.hw, nv, N.grad(B5), pg + L.hw, pg + L.hb, (float *)(N.ws + N.P.loss), N.st);
+    conv_bwd(N, 9, A5, 0, B5, 0, A5, 0);
+    mask(N, A5, 0, A5, 0, 16);
+    conv_bwd(N, 8, C1, 0, A5, 0, C1, 0);
+    launch_up_bwd(N.grad(C1), 48, 0, N.grad(B4), 32, 0, 32, n / 2, N.st);
+    mask(N, B4, 0, B4, 0, 32);
+    conv_bwd(N, 7, A4, 0, B4, 0, A4, 0);
+    mask(N, A4, 0, A4, 0, 32);
+    conv_bwd(N, 6, C2, 0, A4, 0, C2, 0);
+    launch_up_bwd(N.grad(C2), 96, 0, N.grad(B3), 64, 0, 64, n / 4, N.st);
+    mask(N, B3, 0, B3, 0, 64);
+    conv_bwd(N, 5, A3, 0, B3, 0, A3, 0);
+    mask(N, A3, 0, A3, 0, 64);
+    conv_bwd(N, 4, P2, 0, A3, 0, P2, 0);
+    launch_pool_bwd(N.grad(P2), 32, 0, N.grad(C2), 96, 64, 32, n / 2, N.st);  // + skip 2
+    mask(N, C2, 64, C2, 64, 32);
+    conv_bwd(N, 3, A2, 0, C2, 64, A2, 0);
+    mask(N, A2, 0, A2, 0, 32);
+    conv_bwd(N, 2, P1, 0, A2, 0, P1, 0);
+    launch_pool_bwd(N.grad(P1), 16, 0, N.grad(C1), 48, 32, 16, n, N.st);  // + skip 1
+    mask(N, C1, 32, C1, 32, 16);
+    conv_bwd(N, 1, A1, 0, C1, 32, A1, 0);
+    mask(N, A1, 0, A1, 0, 16);
+    conv_bwd(N, 0, X0, 0, A1, 0, -1, 0);
+}
+
+int setup(Net &N, int n, bool training, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!ws || ((uintptr_t)ws & 255))
+        return PM_EINVAL;
+    if (!net_plan(N.P, n, training))
+        return PM_EINVAL;
+    if (ws_bytes < N.P.total)
+        return PM_ENOMEM;
+    N.ws = (char *)ws;
+    N.st = (hipStream_t)stream;
+    N.rs.partials = (double *)(N.ws + N.P.red_partials);
+    N.rs.counter = nullptr;
+    N.rs.out = (double *)(N.ws + N.P.red_out);
+    return PM_OK;
+}
+
+// target yhat = chi / (h^2 s mu_chi): the solution in normalised units
+__global__ void k_chi_to_target(const double *__restrict__ chi, unsigned n, double inv_scale, float *__restrict__ y)
+{
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256)
+        y[v] = (float)(chi[v] * inv_scale);
+}
+
+double chi_scale(int n, const pm_eft_params &p)
+{
+    pm_eft_coeffs c;
+    pm_eft_coefficients(&p, &c);
+    const double h = 1.0 / n;
+    return h * h * c.s * c.mu_chi;
+}
+
+}  // namespace
+}  // namespace pmeft
+
+using namespace pmeft;
+
+extern "C" {
+
+long long ws_unet_param_count(void) { return param_layout().total; }
+
+size_t ws_unet_workspace_bytes(int ng, int training)
+{
+    NetPlan P;
+    return net_plan(P, ng, training != 0) ? P.total : 0;
+}
+
+int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p, float *yhat_out,
+                    void *chi_out, pm_dtype dtype, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!params || !rho || !p || (dtype != PM_F32 && dtype != PM_F64))
+        return PM_EINVAL;
+    Net N;
+    int e = setup(N, ng, false, ws, ws_bytes, stream);
+    if (e)
+        return e;
+    pack_all(N, params);
+    forward(N, params, rho, *p);
+    const unsigned nv = (unsigned)ng * ng * ng;
+    const float *yh = (const float *)(N.ws + N.P.yhat);
+    if (yhat_out && hipMemcpyAsync(yhat_out, yh, sizeof(float) * nv, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
+        return PM_EHIP;
+    if (chi_out)
+        launch_yhat_to_chi(yh, nv, chi_scale(ng, *p), chi_out, dtype, N.rs, N.st);
+    return launched();
+}
+
+int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, const double *rho,
+                       const double *chi_target, int ng, const pm_eft_params *p, float *grad_out, double *loss,
+                       void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!params || !rho || !chi_target || !p || (lr > 0.0 && (!adam_m || !adam_v || step < 1)))
+        return PM_EINVAL;
+    Net N;
+    int e = setup(N, ng, true, ws, ws_bytes, stream);
+    if (e)
+        return e;
+    const unsigned nv = (unsigned)ng * ng * ng;
+    const double sc = chi_scale(ng, *p);
+    if (!(sc != 0.0) || !isfinite(sc))
+        return PM_EINVAL;
+    hipLaunchKernelGGL(k_chi_to_target, dim3(1024), dim3(256), 0, N.st, chi_target, nv, 1.0 / sc,
+                       (float *)(N.ws + N.P.target));
+    pack_all(N, params);
+    forward(N, params, rho, *p);
+    backward(N, params);
+    const long long np = param_layout().total;
+    const float *pg = (const float *)(N.ws + N.P.pgrad);
+    if (grad_out && hipMemcpyAsync(grad_out, pg, sizeof(float) * np, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
+        return PM_EHIP;
+    if (lr > 0.0) {
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+        launch_adam(params, pg, adam_m, adam_v, np, (float)lr, b1, b2, 1e-8f, c1, c2, N.st);
+    }
+    if (loss) {
+        float l = 0.f;
+        if (hipMemcpyAsync(&l, N.ws + N.P.loss, sizeof(float), hipMemcpyDeviceToHost, N.st) != hipSuccess ||
+            hipStreamSynchronize(N.st) != hipSuccess)
+            return PM_EHIP;
+        *loss = l;
+    }
+    return launched();
+}
+
+int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
+             const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (mode < 0 || mode > 2 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws)
+        return PM_EINVAL;
+    const size_t need = sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout) * 2 + 512;
+    if (ws_bytes < need)
+        return PM_ENOMEM;
+    hipStream_t st = (hipStream_t)stream;
+    uint16_t *wf = (uint16_t *)ws;
+    uint16_t *wd = (uint16_t *)((char *)ws + (((sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout)) + 255) & ~(size_t)255));
+    launch_pack_conv(w, cin, cout, pad16(cin), pad16(cout), wf, wd, st);
+    if (mode == 0) {
+        if (!x_bf16 || cin % 16)
+            return PM_EINVAL;
+        launch_conv3((const uint16_t *)x_bf16, cin, 0, cin, wf, pad16(cout), b, cout, out, cout, 0, true, n, false,
+                     false, st);
+    } else if (mode == 1) {
+        if (!dy_bf16 || cout % 16)
+            return PM_EINVAL;
+        launch_conv3((const uint16_t *)dy_bf16, cout, 0, cout, wd, pad16(cin), nullptr, cin, out, cin, 0, true, n,
+                     true, false, st);
+    } else {
+        if (!x_bf16 || !dy_bf16)
+            return PM_EINVAL;
+        launch_zero(out, sizeof(float) * 27 * cin * cout, st);
+        launch_conv3_wgrad((const uint16_t *)x_bf16, cin, 0, cin, (const uint16_t *)dy_bf16, cout, 0, cout, out, n,
+                           st);
+    }
+    return launched();
+}
+
+}  // extern "C"

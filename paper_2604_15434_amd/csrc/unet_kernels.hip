@@ -1,0 +1,546 @@
+// Kernels of the learned warm start: a 3-level 3D U-Net on the periodic grid.
+//
+// Activations are channels-last bf16 tensors (voxel-major, channels
+// contiguous); a tensor view is (pointer, row stride in elements, channel
+// offset), so a convolution can read or write one slice of a concatenation
+// buffer.  Convolutions are implicit GEMMs on the MFMA unit
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation): a wave computes 16
+// consecutive voxels along k times 16 output channels per tile and runs the
+// K loop over the 27 taps (periodic neighbours) and 16-channel input slices.
+// MFMA operand layout (16x16x16): lane l supplies A[l%16][4(l/16)+i] and
+// B[4(l/16)+i][l%16], i = 0..3, and receives D[4(l/16)+i][l%16].
+#include "pmeft_internal.h"
+
+#include <math.h>
+
+namespace pmeft {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)  // inf / nan: truncate, keep nan quiet
+        return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ void tap_offsets(int t, int &di, int &dj, int &dk)
+{
+    di = t / 9 - 1;
+    dj = (t / 3) % 3 - 1;
+    dk = t % 3 - 1;
+}
+
+static inline unsigned xcd_blocks(unsigned nb) { return nb >= 8 ? (nb + 7) / 8 * 8 : nb; }
+
+__device__ __forceinline__ unsigned xcd_block(unsigned nb_real)
+{
+    const unsigned b = blockIdx.x, g = gridDim.x;
+    if (g % 8)
+        return b;
+    return (b % 8) * (g / 8) + b / 8;
+}
+
+// ---------------------------------------------------------------- convolution
+// out[v][out_off + o] = act(bias[o] + sum_t sum_c in[v + s d_t][in_off + c] * Wp[t][o][c])
+// with s = +1 (forward) or -1 (input gradient, Wp packed as the transpose).
+// cin_pad, cout_pad: multiples of 16; only o < cout is written.
+template <int COT>
+__global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, int in_stride, int in_off, int cin_pad,
+                                               const uint16_t *__restrict__ wp, int cout_pad,
+                                               const float *__restrict__ bias, int cout, void *__restrict__ out,
+                                               int out_stride, int out_off, int out_f32, int n, int flip, int relu,
+                                               unsigned nseg)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned seg = xcd_block(0) * 4 + wave;
+    if (seg >= nseg)
+        return;
+    const int segs_row = n / 16;
+    const unsigned row = seg / segs_row;
+    const int k0 = (seg - row * segs_row) * 16;
+    const int i = row / n, j = row - (row / n) * n;
+    const int r = lane & 15, q = lane >> 4;
+    const int co_base = blockIdx.y * COT * 16;
+    f32x4 acc[COT];
+#pragma unroll
+    for (int t = 0; t < COT; t++)
+        acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 27; tap++) {
+        int di, dj, dk;
+        tap_offsets(tap, di, dj, dk);
+        if (flip) {
+            di = -di;
+            dj = -dj;
+            dk = -dk;
+        }
+        const int ii = wrapi(i + di, n), jj = wrapi(j + dj, n), kk = wrapi(k0 + r + dk, n);
+        const uint16_t *ap = in + ((size_t)((ii * n + jj) * n + kk)) * in_stride + in_off + 4 * q;
+        const uint16_t *bp = wp + ((size_t)tap * cout_pad + co_base + r) * cin_pad + 4 * q;
+        for (int c0 = 0; c0 < cin_pad; c0 += 16) {
+            const bf16x4 a = *(const bf16x4 *)(ap + c0);
+#pragma unroll
+            for (int t = 0; t < COT; t++) {
+                const bf16x4 b = *(const bf16x4 *)(bp + (size_t)t * 16 * cin_pad + c0);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            }
+        }
+    }
+    const size_t vbase = (size_t)((i * n + j) * n + k0);
+#pragma unroll
+    for (int t = 0; t < COT; t++) {
+        const int o = co_base + t * 16 + r;
+        if (o >= cout)
+            continue;
+        const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            float v = acc[t][e] + bo;
+            if (relu)
+                v = fmaxf(v, 0.f);
+            const size_t idx = (vbase + 4 * q + e) * out_stride + out_off + o;
+            if (out_f32)
+                ((float *)out)[idx] = v;
+            else
+                ((uint16_t *)out)[idx] = f2bf(v);
+        }
+    }
+}
+
+void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
+                  const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
+                  bool relu, hipStream_t st)
+{
+    const unsigned nseg = (unsigned)n * n * (n / 16);
+    const unsigned nbx = xcd_blocks((nseg + 3) / 4);
+    // output tiles per wave: the largest of 4, 3, 2, 1 that divides the tile count
+    const int tiles = cout_pad / 16;
+    const int cot = tiles % 4 == 0 ? 4 : (tiles % 3 == 0 ? 3 : (tiles % 2 == 0 ? 2 : 1));
+    dim3 grid(nbx, cout_pad / (cot * 16));
+#define PM_CONV(C)                                                                                                     \
+    hipLaunchKernelGGL((k_conv3<C>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout,  \
+                       out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, nseg)
+    if (cot == 4)
+        PM_CONV(4);
+    else if (cot == 3)
+        PM_CONV(3);
+    else if (cot == 2)
+        PM_CONV(2);
+    else
+        PM_CONV(1);
+#undef PM_CONV
+}
+
+// dW[t][c][o] += sum_v x[v + d_t][x_off + c] * dy[v][dy_off + o] over a chunk
+// of voxels per block, accumulated with FP32 atomics into dw (which the caller
+// zeroes).  grid: x = voxel chunk, y = tap, z = (c tile, o tile).
+constexpr int kWgChunk = 8192;
+
+__global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t *__restrict__ x, int x_stride, int x_off, int cin,
+                                                     const uint16_t *__restrict__ dy, int dy_stride, int dy_off,
+                                                     int cout, float *__restrict__ dw, int n)
+{
+    __shared__ float red[4][64][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int tap = blockIdx.y;
+    const int otiles = (cout + 15) / 16;
+    const int ct = blockIdx.z / otiles, ot = blockIdx.z % otiles;
+    const int c = ct * 16 + r, o0 = ot * 16;
+    int di, dj, dk;
+    tap_offsets(tap, di, dj, dk);
+    const unsigned nvox = (unsigned)n * n * n;
+    const unsigned v0 = blockIdx.x * kWgChunk + wave * (kWgChunk / 4);
+    const unsigned v1 = min(nvox, v0 + kWgChunk / 4);
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (unsigned vb = v0; vb < v1; vb += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const unsigned v = vb + 4 * q + e;  // v < v1 since chunks are multiples of 16
+            const int k = v % n, jrow = (v / n) % n, irow = v / (n * n);
+            const int ii = wrapi(irow + di, n), jj = wrapi(jrow + dj, n), kk = wrapi(k + dk, n);
+            const uint16_t xa = c < cin ? x[(size_t)((ii * n + jj) * n + kk) * x_stride + x_off + c] : (uint16_t)0;
+            const int o = o0 + r;
+            const uint16_t yb = o < cout ? dy[(size_t)v * dy_stride + dy_off + o] : (uint16_t)0;
+            a[e] = (short)xa;
+            b[e] = (short)yb;
+        }
+        // A[m = c][k = voxel] from lane (m = r, k = 4q + e); B[k = voxel][n = o]
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        red[wave][lane][e] = acc[e];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const float s = red[0][lane][e] + red[1][lane][e] + red[2][lane][e] + red[3][lane][e];
+            const int cc = ct * 16 + 4 * q + e, oo = o0 + r;
+            if (cc < cin && oo < cout)
+                atomicAdd(&dw[((size_t)tap * cin + cc) * cout + oo], s);
+        }
+    }
+}
+
+void launch_conv3_wgrad(const uint16_t *x, int x_stride, int x_off, int cin, const uint16_t *dy, int dy_stride,
+                        int dy_off, int cout, float *dw, int n, hipStream_t st)
+{
+    const unsigned nvox = (unsigned)n * n * n;
+    dim3 grid((nvox + kWgChunk - 1) / kWgChunk, 27, ((cin + 15) / 16) * ((cout + 15) / 16));
+    hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(256), 0, st, x, x_stride, x_off, cin, dy, dy_stride, dy_off, cout, dw,
+                       n);
+}
+
+// db[o] += sum_v dy[v][dy_off + o]
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dy, int stride, int off, int cout,
+                                                   unsigned nvox, float *__restrict__ db)
+{
+    const int o = threadIdx.x % 64;
+    const int part = threadIdx.x / 64;
+    if (o >= cout)
+        return;
+    float s = 0.f;
+    for (unsigned v = blockIdx.x * 4 + part; v < nvox; v += gridDim.x * 4)
+        s += bf2f(dy[(size_t)v * stride + off + o]);
+    atomicAdd(&db[o], s);
+}
+
+void launch_bias_grad(const uint16_t *dy, int stride, int off, int cout, unsigned nvox, float *db, hipStream_t st)
+{
+    unsigned nb = (nvox + 4095) / 4096;
+    if (nb > 1024)
+        nb = 1024;
+    hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, dy, stride, off, cout, nvox, db);
+}
+
+// ---------------------------------------------------------------- elementwise
+// dy[v][off + c] *= (y[v][y_off + c] > 0)
+__global__ __launch_bounds__(256) void k_relu_bwd(uint16_t *__restrict__ dy, int dstride, int doff,
+                                                  const uint16_t *__restrict__ y, int ystride, int yoff, int C,
+                                                  unsigned nvox)
+{
+    const unsigned total = nvox * (unsigned)C;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / C;
+        const int c = (int)(e - v * C);
+        if (!(bf2f(y[(size_t)v * ystride + yoff + c]) > 0.f))
+            dy[(size_t)v * dstride + doff + c] = 0;
+    }
+}
+
+void launch_relu_bwd(uint16_t *dy, int dstride, int doff, const uint16_t *y, int ystride, int yoff, int C,
+                     unsigned nvox, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_relu_bwd, dim3(2048), dim3(256), 0, st, dy, dstride, doff, y, ystride, yoff, C, nvox);
+}
+
+// 2x2x2 average pooling: out (n/2)^3 x C from in n^3 (slice in_off..)
+__global__ __launch_bounds__(256) void k_pool(const uint16_t *__restrict__ in, int istride, int ioff,
+                                              uint16_t *__restrict__ out, int ostride, int ooff, int C, int nc)
+{
+    const unsigned total = (unsigned)nc * nc * nc * C;
+    const int nf = 2 * nc;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / C;
+        const int c = (int)(e - v * C);
+        const int K = (int)(v % nc), J = (int)((v / nc) % nc), I = (int)(v / ((unsigned)nc * nc));
+        float s = 0.f;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int d = 0; d < 2; d++)
+                    s += bf2f(in[((size_t)((2 * I + a) * nf + 2 * J + b) * nf + 2 * K + d) * istride + ioff + c]);
+        out[(size_t)v * ostride + ooff + c] = f2bf(0.125f * s);
+    }
+}
+
+// d_in[child] += d_out[parent] / 8 (accumulating into the existing gradient)
+__global__ __launch_bounds__(256) void k_pool_bwd(const uint16_t *__restrict__ dout, int ostride, int ooff,
+                                                  uint16_t *__restrict__ din, int istride, int ioff, int C, int nf)
+{
+    const unsigned total = (unsigned)nf * nf * nf * C;
+    const int nc = nf / 2;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / C;
+        const int c = (int)(e - v * C);
+        const int k = (int)(v % nf), j = (int)((v / nf) % nf), i = (int)(v / ((unsigned)nf * nf));
+        const size_t p = (size_t)((i / 2) * nc + j / 2) * nc + k / 2;
+        const size_t di = (size_t)v * istride + ioff + c;
+        din[di] = f2bf(bf2f(din[di]) + 0.125f * bf2f(dout[p * ostride + ooff + c]));
+    }
+}
+
+// nearest-neighbour upsampling into a slice: out[child][ooff + c] = in[parent][c]
+__global__ __launch_bounds__(256) void k_up(const uint16_t *__restrict__ in, int istride, int ioff,
+                                            uint16_t *__restrict__ out, int ostride, int ooff, int C, int nf)
+{
+    const unsigned total = (unsigned)nf * nf * nf * C;
+    const int nc = nf / 2;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / C;
+        const int c = (int)(e - v * C);
+        const int k = (int)(v % nf), j = (int)((v / nf) % nf), i = (int)(v / ((unsigned)nf * nf));
+        const size_t p = (size_t)((i / 2) * nc + j / 2) * nc + k / 2;
+        out[(size_t)v * ostride + ooff + c] = in[p * istride + ioff + c];
+    }
+}
+
+// d_in[parent][c] = sum over children of d_out[child][ooff + c]
+__global__ __launch_bounds__(256) void k_up_bwd(const uint16_t *__restrict__ dout, int ostride, int ooff,
+                                                uint16_t *__restrict__ din, int istride, int ioff, int C, int nc)
+{
+    const unsigned total = (unsigned)nc * nc * nc * C;
+    const int nf = 2 * nc;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / C;
+        const int c = (int)(e - v * C);
+        const int K = (int)(v % nc), J = (int)((v / nc) % nc), I = (int)(v / ((unsigned)nc * nc));
+        float s = 0.f;
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int d = 0; d < 2; d++)
+                    s += bf2f(dout[((size_t)((2 * I + a) * nf + 2 * J + b) * nf + 2 * K + d) * ostride + ooff + c]);
+        din[(size_t)v * istride + ioff + c] = f2bf(s);
+    }
+}
+
+void launch_pool(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nc,
+                 hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nc);
+}
+void launch_pool_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nf,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pool_bwd, dim3(2048), dim3(256), 0, st, dout, ostride, ooff, din, istride, ioff, C, nf);
+}
+void launch_up(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nf,
+               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_up, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nf);
+}
+void launch_up_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nc,
+                   hipStream_t st)
+{
+    hipLaunchKernelGGL(k_up_bwd, dim3(2048), dim3(256), 0, st, dout, ostride, ooff, din, istride, ioff, C, nc);
+}
+
+// ---------------------------------------------------------------- input / head
+// partial sums of l = ln(rho + 1e-3) and l^2 (natural-order double rho)
+__global__ __launch_bounds__(kBlock) void k_lnrho_stats(const double *__restrict__ rho, ReduceSlot rs, Span sp)
+{
+    double acc[2] = {0.0, 0.0};
+    PM_SPAN_LOOP(e, sp)
+    {
+        const double l = log(rho[e] + 1e-3);
+        acc[0] += l;
+        acc[1] += l * l;
+    }
+    block_partials<2>(acc, rs, sp);
+}
+
+void launch_lnrho_stats(const double *rho, unsigned long long n, ReduceSlot rs, hipStream_t st)
+{
+    const Span sp = make_span(n);
+    hipLaunchKernelGGL(k_lnrho_stats, dim3(sp.nblocks), dim3(kBlock), 0, st, rho, rs, sp);
+    launch_finalize(rs, sp, 2, rs.out, st);
+}
+
+// x0[v][0..15] = (standardised ln(rho + 1e-3), alpha_B0, alpha_M0, a, 0 ...)
+__global__ __launch_bounds__(256) void k_unet_input(const double *__restrict__ rho, unsigned nvox,
+                                                    const double *__restrict__ stats, float ab0, float am0, float a,
+                                                    uint16_t *__restrict__ x0)
+{
+    const double mean = stats[0] / nvox;
+    const double var = fmax(stats[1] / nvox - mean * mean, 1e-30);
+    const double inv = 1.0 / sqrt(var);
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
+        const float l = (float)((log(rho[v] + 1e-3) - mean) * inv);
+        uint16_t *o = x0 + (size_t)v * 16;
+        o[0] = f2bf(l);
+        o[1] = f2bf(ab0);
+        o[2] = f2bf(am0);
+        o[3] = f2bf(a);
+        for (int c = 4; c < 16; c++)
+            o[c] = 0;
+    }
+}
+
+void launch_unet_input(const double *rho, unsigned nvox, const double *stats, float ab0, float am0, float a,
+                       uint16_t *x0, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unet_input, dim3(2048), dim3(256), 0, st, rho, nvox, stats, ab0, am0, a, x0);
+}
+
+// yhat[v] = hb + sum_c hw[c] * b5[v][c]
+__global__ __launch_bounds__(256) void k_head(const uint16_t *__restrict__ b5, const float *__restrict__ hw,
+                                              const float *__restrict__ hb, unsigned nvox, float *__restrict__ yhat)
+{
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
+        float s = hb[0];
+        const uint16_t *h = b5 + (size_t)v * 16;
+        for (int c = 0; c < 16; c++)
+            s += hw[c] * bf2f(h[c]);
+        yhat[v] = s;
+    }
+}
+
+void launch_head(const uint16_t *b5, const float *hw, const float *hb, unsigned nvox, float *yhat, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_head, dim3(2048), dim3(256), 0, st, b5, hw, hb, nvox, yhat);
+}
+
+// MSE loss L = mean (yhat - y)^2: dyhat = 2 (yhat - y) / N; db5 = dyhat hw
+// (masked by b5 > 0); grads of hw, hb and the loss accumulated with atomics.
+__global__ __launch_bounds__(256) void k_head_loss_bwd(const float *__restrict__ yhat, const float *__restrict__ y,
+                                                       const uint16_t *__restrict__ b5, const float *__restrict__ hw,
+                                                       unsigned nvox, uint16_t *__restrict__ db5,
+                                                       float *__restrict__ ghw, float *__restrict__ ghb,
+                                                       float *__restrict__ loss)
+{
+    __shared__ float sm[18][4];
+    float gw[16], gb = 0.f, ls = 0.f;
+    for (int c = 0; c < 16; c++)
+        gw[c] = 0.f;
+    const float sc = 2.0f / (float)nvox;
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
+        const float d = yhat[v] - y[v];
+        ls += d * d;
+        const float g = sc * d;
+        gb += g;
+        const uint16_t *h = b5 + (size_t)v * 16;
+        uint16_t *dh = db5 + (size_t)v * 16;
+        for (int c = 0; c < 16; c++) {
+            const float hv = bf2f(h[c]);
+            gw[c] += g * hv;
+            dh[c] = hv > 0.f ? f2bf(g * hw[c]) : (uint16_t)0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = 0; q < 18; q++) {
+        float x = q < 16 ? gw[q] : (q == 16 ? gb : ls);
+        for (int off = 32; off > 0; off >>= 1)
+            x += __shfl_down(x, off, 64);
+        if (lane == 0)
+            sm[q][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 18) {
+        const float t = sm[threadIdx.x][0] + sm[threadIdx.x][1] + sm[threadIdx.x][2] + sm[threadIdx.x][3];
+        if (threadIdx.x < 16)
+            atomicAdd(&ghw[threadIdx.x], t);
+        else if (threadIdx.x == 16)
+            atomicAdd(ghb, t);
+        else
+            atomicAdd(loss, t / (float)nvox);
+    }
+}
+
+void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5, const float *hw, unsigned nvox,
+                          uint16_t *db5, float *ghw, float *ghb, float *loss, hipStream_t st)
+{
+    unsigned nb = (nvox + 255) / 256;
+    if (nb > 1024)
+        nb = 1024;
+    hipLaunchKernelGGL(k_head_loss_bwd, dim3(nb), dim3(256), 0, st, yhat, y, b5, hw, nvox, db5, ghw, ghb, loss);
+}
+
+// ---------------------------------------------------------------- parameters
+// Pack fp32 W[27][cin][cout] into bf16 Wf[27][cout_pad][cin_pad] (forward)
+// and Wd[27][cin_pad][cout_pad] (input gradient: output channels = cin).
+__global__ __launch_bounds__(256) void k_pack_conv(const float *__restrict__ w, int cin, int cout, int cin_pad,
+                                                   int cout_pad, uint16_t *__restrict__ wf, uint16_t *__restrict__ wd)
+{
+    const size_t total = (size_t)27 * cin_pad * cout_pad;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const int t = (int)(e / ((size_t)cin_pad * cout_pad));
+        const int rem = (int)(e - (size_t)t * cin_pad * cout_pad);
+        const int c = rem / cout_pad, o = rem % cout_pad;
+        const float v = (c < cin && o < cout) ? w[((size_t)t * cin + c) * cout + o] : 0.f;
+        const uint16_t b = f2bf(v);
+        wf[((size_t)t * cout_pad + o) * cin_pad + c] = b;
+        if (wd)
+            wd[((size_t)t * cin_pad + c) * cout_pad + o] = b;
+    }
+}
+
+void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_conv, dim3(256), dim3(256), 0, st, w, cin, cout, cin_pad, cout_pad, wf, wd);
+}
+
+// Adam (Kingma & Ba) with bias correction on FP32 master weights.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                                              float *__restrict__ v, long long n, float lr, float b1, float b2,
+                                              float eps, float c1, float c2)
+{
+    for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
+        const float gg = g[e];
+        const float mm = b1 * m[e] + (1.f - b1) * gg;
+        const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+        m[e] = mm;
+        v[e] = vv;
+        w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    }
+}
+
+void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+// bf16 <-> f32 helpers for tests and the output path
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float *__restrict__ s, uint16_t *__restrict__ d, size_t n)
+{
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
+        d[e] = f2bf(s[e]);
+}
+
+void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, s, d, n);
+}
+
+// chi0 (natural, dtype) = scale * (yhat - <yhat>), mean from stats[0] / n
+template <typename T>
+__global__ __launch_bounds__(256) void k_yhat_to_chi(const float *__restrict__ yhat, unsigned n, double scale,
+                                                     const double *__restrict__ stats, T *__restrict__ chi)
+{
+    const double mean = stats[0] / n;
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256)
+        chi[v] = (T)(scale * ((double)yhat[v] - mean));
+}
+
+__global__ __launch_bounds__(kBlock) void k_f32_sum(const float *__restrict__ x, ReduceSlot rs, Span sp)
+{
+    double acc[1] = {0.0};
+    PM_SPAN_LOOP(e, sp)
+    acc[0] += (double)x[e];
+    block_partials<1>(acc, rs, sp);
+}
+
+void launch_yhat_to_chi(const float *yhat, unsigned n, double scale, void *chi, pm_dtype dt, ReduceSlot rs,
+                        hipStream_t st)
+{
+    const Span sp = make_span(n);
+    hipLaunchKernelGGL(k_f32_sum, dim3(sp.nblocks), dim3(kBlock), 0, st, yhat, rs, sp);
+    launch_finalize(rs, sp, 1, rs.out, st);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_yhat_to_chi<double>), dim3(2048), dim3(256), 0, st, yhat, n, scale,
+                           (const double *)rs.out, (double *)chi);
+    else
+        hipLaunchKernelGGL((k_yhat_to_chi<float>), dim3(2048), dim3(256), 0, st, yhat, n, scale,
+                           (const double *)rs.out, (float *)chi);
+}
+
+}  // namespace pmeft

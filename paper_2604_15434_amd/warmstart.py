@@ -1,0 +1,118 @@
+"""Learned warm start: the U-Net of the C ABI (ws_* in include/pmeft.h)
+driven from Python.  The network maps the density and (alpha_B0, alpha_M0,
+a) to an initial scalar field; multigrid finishes the solve from it
+(PM_GUESS_GIVEN), so the answer never depends on the network.
+
+This module only marshals arguments and keeps the parameter and optimizer
+arrays (torch device tensors); every layer, the loss, the gradients and the
+Adam update run in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+from . import _lib as L
+from . import PmError, _params, _stream
+
+CONV_SHAPES = [(4, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32), (32, 32), (48, 16), (16, 16)]
+
+
+def param_count():
+    return int(L.lib().ws_unet_param_count())
+
+
+def init_params(seed=0):
+    """He-normal convolution weights, zero biases, head weights ~ N(0, 1/16)
+    (flat FP32 array in the layout of include/pmeft.h)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in CONV_SHAPES:
+        parts.append(rng.standard_normal(27 * ci * co) * np.sqrt(2.0 / (27 * ci)))
+        parts.append(np.zeros(co))
+    parts.append(rng.standard_normal(16) * 0.25)
+    parts.append(np.zeros(1))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == param_count()
+    return flat
+
+
+class WarmStart:
+    def __init__(self, params=None, seed=0, device="cuda"):
+        import torch
+
+        flat = init_params(seed) if params is None else np.asarray(params, dtype=np.float32)
+        self.params = torch.from_numpy(flat.copy()).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = {}
+
+    def _workspace(self, ng, training):
+        import torch
+
+        key = (ng, bool(training))
+        if key not in self._ws:
+            nb = int(L.lib().ws_unet_workspace_bytes(int(ng), int(bool(training))))
+            if nb == 0:
+                raise PmError(L.PM_EINVAL, f"warm start workspace for ng={ng}")
+            self._ws[key] = torch.empty(nb, dtype=torch.uint8, device=self.params.device)
+        return self._ws[key]
+
+    def predict(self, rho, params, chi_out, yhat_out=None, stream=None):
+        """chi0 of the network for the FP64 density rho (ng^3) into chi_out."""
+        import torch
+
+        ng = rho.shape[0]
+        assert rho.dtype == torch.float64 and rho.is_contiguous()
+        dt = L.PM_F64 if chi_out.dtype == torch.float64 else L.PM_F32
+        ws = self._workspace(ng, False)
+        rc = L.lib().ws_unet_forward(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                     int(ng), ctypes.byref(_params(params)),
+                                     ctypes.c_void_p(yhat_out.data_ptr() if yhat_out is not None else 0),
+                                     ctypes.c_void_p(chi_out.data_ptr()), dt, ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_forward")
+        return chi_out
+
+    def train_step(self, rho, chi_target, params, lr, grad_out=None, stream=None):
+        """One Adam step on one sample (lr = 0: gradients only); returns the loss."""
+        ng = rho.shape[0]
+        ws = self._workspace(ng, True)
+        if lr > 0:
+            self.step += 1
+        loss = ctypes.c_double(0.0)
+        rc = L.lib().ws_unet_train_step(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(self.m.data_ptr()),
+                                        ctypes.c_void_p(self.v.data_ptr()), max(self.step, 1), float(lr),
+                                        ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(chi_target.data_ptr()),
+                                        int(ng), ctypes.byref(_params(params)),
+                                        ctypes.c_void_p(grad_out.data_ptr() if grad_out is not None else 0),
+                                        ctypes.byref(loss), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_train_step")
+        return loss.value
+
+    def save(self, path, meta=None):
+        flat = self.params.detach().cpu().numpy().astype("<f4")
+        with open(path, "wb") as f:
+            f.write(flat.tobytes())
+        with open(path + ".json", "w") as f:
+            json.dump(dict(meta or {}, param_count=int(flat.size), dtype="float32-le", step=self.step), f, indent=1)
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        meta = json.load(open(path + ".json"))
+        flat = np.fromfile(path, dtype="<f4")
+        if flat.size != meta["param_count"] or flat.size != param_count():
+            raise ValueError(f"{path}: parameter count mismatch")
+        ws = cls(params=flat, device=device)
+        ws.step = int(meta.get("step", 0))
+        return ws
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.f32")
