@@ -59,9 +59,13 @@ typedef enum { PM_F32 = 0, PM_F64 = 1 } pm_dtype;
 typedef enum { PM_PREC_F64 = 0, PM_PREC_MIXED = 1 } pm_prec;
 
 /* Initial guess of a solve: zero; the values passed in the output array
- * (e.g. the previous time step, Sec. 3.5.1); or the linearised solution
- * lap chi = mu_chi s delta (Sec. 3.5.1, first time step). */
-typedef enum { PM_GUESS_ZERO = 0, PM_GUESS_GIVEN = 1, PM_GUESS_LINEAR = 2 } pm_guess;
+ * (e.g. the previous time step, Sec. 3.5.1); the linearised solution
+ * lap chi = mu_chi s delta (Sec. 3.5.1, first time step); or the learned
+ * warm start (scalar field only): the network of ws_unet_forward predicts the
+ * nonlinear part t of the normalised source lap chi / (s mu_chi) = delta + t,
+ * and one linear full-multigrid pass on lap chi0 = s mu_chi (delta + t - <t>)
+ * gives the guess.  The guess sets the cost of a solve, never its answer. */
+typedef enum { PM_GUESS_ZERO = 0, PM_GUESS_GIVEN = 1, PM_GUESS_LINEAR = 2, PM_GUESS_LEARNED = 3 } pm_guess;
 
 /* Model parameters as the paper states them (eq. alpha-a, Sec. 2.4). */
 typedef struct {
@@ -90,6 +94,13 @@ typedef struct {
     int n_pre, n_post; /* red-black Gauss-Seidel sweeps before / after the coarse correction */
     int precision;     /* pm_prec */
     int guess;         /* pm_guess */
+    /* PM_GUESS_LEARNED only (else ignored): the network's FP32 parameters
+     * (ws_unet_param_count values, device) and a device workspace of at least
+     * ws_unet_workspace_bytes(ng, 0) bytes, 256-byte aligned.  ng must be a
+     * multiple of 64; otherwise the solve returns PM_EINVAL. */
+    const float *learned_params;
+    void *learned_ws;
+    size_t learned_ws_bytes;
 } pm_mg_opts;
 
 typedef struct {
@@ -163,48 +174,103 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,
             void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* ---- Batched solves ------------------------------------------------------
+ * Many independent scalar-field problems (a parameter scan, several boxes)
+ * in one call.  Each problem has its own grid size, precision of its arrays,
+ * parameters and hierarchy; its result and report equal those of
+ * mg_scalar_solve on the same problem bit for bit.  The problems run
+ * concurrently on internal streams (host worker threads, largest grid first);
+ * the call waits for work already queued on `stream`, and returns when every
+ * problem is solved (all output arrays are complete).  opts apply to every
+ * problem (PM_GUESS_LEARNED is not accepted here).  Returns PM_OK, PM_ENOCONV
+ * if some problem stopped at max_vcycles, or the first hard error; reps
+ * (HOST, nprob entries, nullable) receive the per-problem reports. */
+typedef struct {
+    const void *rho;     /* ng^3 density (device), natural order */
+    void *chi;           /* ng^3 out (guess in if GIVEN) */
+    int ng;
+    pm_dtype dtype;      /* of rho and chi */
+    pm_eft_params p;
+} pm_problem;
+
+size_t mg_batched_workspace_bytes(const pm_problem *probs /* HOST */, int nprob, int precision);
+int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const pm_mg_opts *opts /* HOST */,
+                            pm_mg_report *reps /* HOST, nullable */, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* ---- Launch shapes and the autotuner --------------------------------------
+ * The coarse end of every V-cycle (and of full multigrid) runs as one
+ * single-workgroup launch from the first level whose grid is at most
+ * block_cycle_grid (0: every level launches its own kernels).  The value is
+ * kept per (finest grid ng, word size of the hierarchy: 8 for FP64 levels, 4
+ * for the FP32 levels of PM_PREC_MIXED); default 32.  It changes the cost of
+ * a cycle, and the rounding of the lagged means, not the converged answer.
+ * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a
+ * synthetic density for each candidate (off, 8, 16, 32, 64) and keeps the
+ * fastest for (ng, precision); its workspace is pm_autotune_workspace_bytes.
+ * pm_tune_save / pm_tune_load write and read the table as text lines
+ * "ng word_bytes block_cycle_grid".  The table is process-wide. */
+size_t pm_autotune_workspace_bytes(int ng, int precision);
+int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t stream);
+int pm_launch_shape(int ng, int word_bytes);
+int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid);
+int pm_tune_save(const char *path);
+int pm_tune_load(const char *path);
+
 /* ---- Learned warm start ------------------------------------------------
- * A 3-level 3D U-Net maps the density and (alpha_B0, alpha_M0, a) to an
- * initial scalar field; multigrid then finishes the solve as usual (pass the
- * result with PM_GUESS_GIVEN).  Input channels: standardised ln(rho + 1e-3)
- * and the three parameters broadcast; 3x3x3 periodic convolutions with ReLU
- * (16-16 / 32-32 / 64-64 channels on grids n, n/2, n/4), 2x2x2 average
+ * A 3-level 3D U-Net maps the density contrast and (alpha_B0, alpha_M0, a)
+ * to the nonlinear part of the scalar field's normalised source,
+ *   t = lap_h chi / (s mu_chi) - delta,
+ * which vanishes where the field is unscreened (lap chi = mu_chi s delta in
+ * linear theory, eq. linearised) and carries the Vainshtein suppression in
+ * dense cells.  The source is local where chi is not, so the network predicts
+ * t and a linear multigrid pass turns delta + t into the guess
+ * (PM_GUESS_LEARNED above).  Input channels: standardised ln(1 + delta +
+ * 1e-3) and the three parameters broadcast; 3x3x3 periodic convolutions with
+ * ReLU (16-16 / 32-32 / 64-64 channels on grids n, n/2, n/4), 2x2x2 average
  * pooling, nearest-neighbour upsampling, skip concatenations (96 -> 32,
- * 48 -> 16) and a 1x1x1 head.  The output yhat is the field in units of
- * h^2 s mu_chi: chi0 = h^2 s mu_chi (yhat - <yhat>).  Convolutions run on the
- * matrix cores in BF16 with FP32 accumulation; activations are BF16.
+ * 48 -> 16) and a 1x1x1 head.  Convolutions run on the matrix cores in BF16
+ * with FP32 accumulation; activations are BF16.  delta = rho - <rho>.
  *
  * Parameters: one FP32 device array of ws_unet_param_count() values: for each
  * convolution in order (l1a 4->16, l1b 16->16, l2a 16->32, l2b 32->32, l3a
  * 32->64, l3b 64->64, l4a 96->32, l4b 32->32, l5a 48->16, l5b 16->16) its
  * weight W[27][cin][cout] (tap t = (di+1)*9 + (dj+1)*3 + (dk+1) for the
  * neighbour offset (di, dj, dk)) followed by its bias[cout]; then the head's
- * 16 weights and 1 bias.  ng must be a multiple of 64. */
+ * 16 weights and 1 bias.  ng must be a multiple of 64 (64..1024).  Workspaces
+ * are device memory, 256-byte aligned, owned by the caller; sizes from
+ * ws_unet_workspace_bytes (training = 0: inference, also enough for
+ * PM_GUESS_LEARNED; 1: training).  Errors: PM_EINVAL (null pointer, bad ng,
+ * misaligned workspace), PM_ENOMEM (workspace too small), PM_EHIP. */
 long long ws_unet_param_count(void);
 size_t ws_unet_workspace_bytes(int ng, int training);
 
-/* Forward pass.  rho: ng^3 FP64 density (natural order); yhat_out: ng^3 FP32
- * or NULL; chi_out: ng^3 of `dtype` (the initial field chi0) or NULL. */
+/* Forward pass.  rho: ng^3 FP64 density (natural order); yhat_out: ng^3 FP32,
+ * the predicted t (natural order). */
 int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
-                    float *yhat_out, void *chi_out, pm_dtype dtype, void *ws, size_t ws_bytes, pm_stream_t stream);
+                    float *yhat_out, void *ws, size_t ws_bytes, pm_stream_t stream);
 
-/* One training step on one sample: forward, MSE loss against the target
- * field chi_target (ng^3 FP64, converted to units of h^2 s mu_chi),
- * backward, and (if lr > 0) an Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
- * bias correction with `step` >= 1) on the FP32 params with moment arrays
- * adam_m, adam_v.  grad_out (param_count FP32, nullable) receives the
- * gradients; *loss (HOST, nullable) the sample's loss (this call then
- * synchronises the stream).  Weight gradients accumulate with FP32 atomics,
- * so their last bits depend on scheduling. */
-int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, const double *rho,
-                       const double *chi_target, int ng, const pm_eft_params *p /* HOST */, float *grad_out,
-                       double *loss /* HOST */, void *ws, size_t ws_bytes, pm_stream_t stream);
+/* One training step on one sample: forward, MSE loss mean (yhat - t)^2
+ * against the target t = lap_h chi / (s mu_chi) - delta of the solved field
+ * chi_target (ng^3 FP64, natural order; 7-point Laplacian), backward, and
+ * (if lr > 0) an Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * correction with `step` >= 1) on the FP32 params with moment arrays adam_m,
+ * adam_v, the gradient scaled by min(1, grad_clip / ||g||_2) when
+ * grad_clip > 0 (global-norm clipping).  grad_out (param_count FP32,
+ * nullable) receives the unclipped gradients; *loss and *grad_norm (HOST,
+ * nullable) the sample's loss and ||g||_2 (either makes the call synchronise
+ * the stream).  Gradients are summed in a fixed order (deterministic). */
+int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, double grad_clip,
+                       const double *rho, const double *chi_target, int ng, const pm_eft_params *p /* HOST */,
+                       float *grad_out, double *loss /* HOST */, double *grad_norm /* HOST */, void *ws,
+                       size_t ws_bytes, pm_stream_t stream);
 
 /* One 3x3x3 periodic convolution on BF16 channels-last tensors with FP32
  * output (for testing the kernels): mode 0 forward out[n^3][cout] =
  * b + conv(x); mode 1 input gradient out[n^3][cin] from dy[n^3][cout]; mode
- * 2 weight gradient out[27][cin][cout] from x and dy.  w: FP32 W[27][cin][cout]
- * (device); ws: at least 2 * 27 * pad16(cin) * pad16(cout) * 2 + 512 bytes. */
+ * 2 weight gradient out[27][cin][cout] from x and dy (summed in a fixed
+ * order: deterministic).  w: FP32 W[27][cin][cout] (device); n a multiple of
+ * 16; ws: 256-byte aligned, at least 2 * W + 4 * 240 * (27 cin cout + cout)
+ * bytes with W = 54 * pad16(cin) * pad16(cout) rounded up to 256. */
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
              const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream);
 

@@ -149,9 +149,11 @@ def backward(p, c, dy):
 
 
 def input_features(rho, alpha_b0, alpha_m0, a):
-    """Input channels: standardised ln(rho + 1e-3) and the three broadcast
-    parameters alpha_B0, alpha_M0, a."""
-    lr = np.log(np.asarray(rho, dtype=np.float64) + 1e-3)
+    """Input channels: standardised l = ln(1 + delta + 1e-3), delta = rho -
+    <rho>, and the three broadcast parameters alpha_B0, alpha_M0, a."""
+    rho = np.asarray(rho, dtype=np.float64)
+    delta = rho - rho.mean()
+    lr = np.log(np.maximum(1.0 + delta, 0.0) + 1e-3)
     lr = (lr - lr.mean()) / lr.std()
     n = lr.shape[0]
     x = np.empty((n, n, n, 4))
@@ -160,3 +162,16 @@ def input_features(rho, alpha_b0, alpha_m0, a):
     x[..., 2] = alpha_m0
     x[..., 3] = a
     return x
+
+
+def source_target(chi, rho, s_mu_chi):
+    """The nonlinear part of the scalar field's normalised source,
+    t = lap_h chi / (s mu_chi) - delta (7-point periodic Laplacian, h = 1/n):
+    zero where chi obeys the linearised equation lap chi = mu_chi s delta."""
+    chi = np.asarray(chi, dtype=np.float64)
+    n = chi.shape[0]
+    lap = -6.0 * chi
+    for ax in range(3):
+        lap += np.roll(chi, 1, ax) + np.roll(chi, -1, ax)
+    rho = np.asarray(rho, dtype=np.float64)
+    return lap * n * n / s_mu_chi - (rho - rho.mean())

@@ -15,7 +15,9 @@ from dataclasses import dataclass
 from . import _lib as L
 
 __all__ = [
-    "MgOpts", "PmError", "Workspace", "mg_poisson_solve", "mg_scalar_solve", "pm_deposit", "pm_eft_coefficients",
+    "MgOpts", "PmError", "Workspace", "mg_batched_workspace_bytes", "mg_poisson_solve", "mg_scalar_solve",
+    "mg_scalar_solve_batched", "pm_autotune", "pm_deposit", "pm_eft_coefficients", "pm_launch_shape",
+    "pm_set_launch_shape", "pm_tune_load", "pm_tune_save",
     "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
     "pm_strerror", "pm_workspace_bytes",
 ]
@@ -34,12 +36,22 @@ class MgOpts:
     n_pre: int = 1
     n_post: int = 2
     precision: str = "f64"  # "f64" | "mixed"
-    guess: str = "zero"     # "zero" | "given" | "linear"
+    guess: str = "zero"     # "zero" | "given" | "linear" | "learned"
+    learned: object = None  # warmstart.WarmStart, for guess "learned"
 
-    def c(self):
+    def c(self, ng=None):
         prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED}[self.precision]
-        guess = {"zero": L.PM_GUESS_ZERO, "given": L.PM_GUESS_GIVEN, "linear": L.PM_GUESS_LINEAR}[self.guess]
-        return L.MgOpts(self.rel_tol, self.max_vcycles, self.n_pre, self.n_post, prec, guess)
+        guess = {"zero": L.PM_GUESS_ZERO, "given": L.PM_GUESS_GIVEN, "linear": L.PM_GUESS_LINEAR,
+                 "learned": L.PM_GUESS_LEARNED}[self.guess]
+        o = L.MgOpts(self.rel_tol, self.max_vcycles, self.n_pre, self.n_post, prec, guess)
+        if self.guess == "learned":
+            if self.learned is None or ng is None:
+                raise ValueError("guess 'learned' needs MgOpts.learned (a WarmStart) and the grid size")
+            ws = self.learned.inference_workspace(ng)
+            o.learned_params = self.learned.params.data_ptr()
+            o.learned_ws = ws.data_ptr()
+            o.learned_ws_bytes = ws.numel()
+        return o
 
 
 def _params(p):
@@ -157,7 +169,7 @@ def _grid_solve(fn, name, rho, params, opts, out, ws, stream):
     _check(out, (ng, ng, ng), dt, "out")
     ws = _ws(ws, ng, 0, dt)
     rep = L.MgReport()
-    rc = fn(ctypes.c_void_p(rho.data_ptr()), int(ng), dt, ctypes.byref(_params(params)), ctypes.byref(opts.c()),
+    rc = fn(ctypes.c_void_p(rho.data_ptr()), int(ng), dt, ctypes.byref(_params(params)), ctypes.byref(opts.c(ng)),
             ctypes.c_void_p(out.data_ptr()), ctypes.byref(rep), ws.ptr, ws.nbytes, _stream(stream))
     if rc not in (L.PM_OK, L.PM_ENOCONV):
         raise PmError(rc, name)
@@ -170,6 +182,86 @@ def mg_poisson_solve(rho, params, opts, psi, ws=None, stream=None):
 
 def mg_scalar_solve(rho, params, opts, chi, ws=None, stream=None):
     return _grid_solve(L.lib().mg_scalar_solve, "mg_scalar_solve", rho, params, opts, chi, ws, stream)
+
+
+def mg_batched_workspace_bytes(problems, precision="f64"):
+    arr = _problems(problems)
+    prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED}[precision]
+    return int(L.lib().mg_batched_workspace_bytes(arr, len(problems), prec))
+
+
+def _problems(problems):
+    arr = (L.Problem * len(problems))()
+    for k, pr in enumerate(problems):
+        rho, chi = pr["rho"], pr["chi"]
+        dt = _dtype_code(rho)
+        ng = rho.shape[0]
+        _check(rho, (ng, ng, ng), dt, "rho")
+        _check(chi, (ng, ng, ng), dt, "chi")
+        arr[k] = L.Problem(rho.data_ptr(), chi.data_ptr(), ng, dt, _params(pr["params"]))
+    return arr
+
+
+def mg_scalar_solve_batched(problems, opts, ws=None, stream=None):
+    """Solve many scalar-field problems in one call.  problems: list of dicts
+    with device tensors ``rho`` and ``chi`` (ng^3, either dtype, ng may
+    differ) and ``params``; returns the list of per-problem reports."""
+    import torch
+
+    arr = _problems(problems)
+    n = len(problems)
+    need = mg_batched_workspace_bytes(problems, opts.precision)
+    if need == 0:
+        raise PmError(L.PM_EINVAL, "mg_scalar_solve_batched")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=problems[0]["rho"].device)
+    reps = (L.MgReport * n)()
+    rc = L.lib().mg_scalar_solve_batched(arr, n, ctypes.byref(opts.c()), reps, ctypes.c_void_p(ws.data_ptr()),
+                                         ws.numel(), _stream(stream))
+    if rc not in (L.PM_OK, L.PM_ENOCONV):
+        raise PmError(rc, "mg_scalar_solve_batched")
+    return [_report(r) for r in reps]
+
+
+def pm_autotune(ng, precision="f64", ws=None, stream=None):
+    """Time the launch-shape candidates for (ng, precision) and keep the fastest."""
+    import torch
+
+    prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED}[precision]
+    need = int(L.lib().pm_autotune_workspace_bytes(int(ng), prec))
+    if need == 0:
+        raise PmError(L.PM_EINVAL, "pm_autotune")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    rc = L.lib().pm_autotune(int(ng), prec, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_autotune")
+    return pm_launch_shape(ng, 4 if precision == "mixed" else 8)
+
+
+def pm_launch_shape(ng, word_bytes):
+    rc = int(L.lib().pm_launch_shape(int(ng), int(word_bytes)))
+    if rc < 0:
+        raise PmError(rc, "pm_launch_shape")
+    return rc
+
+
+def pm_set_launch_shape(ng, word_bytes, block_cycle_grid):
+    rc = L.lib().pm_set_launch_shape(int(ng), int(word_bytes), int(block_cycle_grid))
+    if rc:
+        raise PmError(rc, "pm_set_launch_shape")
+
+
+def pm_tune_save(path):
+    rc = L.lib().pm_tune_save(str(path).encode())
+    if rc:
+        raise PmError(rc, "pm_tune_save")
+
+
+def pm_tune_load(path):
+    rc = L.lib().pm_tune_load(str(path).encode())
+    if rc:
+        raise PmError(rc, "pm_tune_load")
 
 
 def pm_force_interp(psi, chi, params, pos, vel, dt_kick, acc_out=None, ws=None, stream=None):
@@ -203,7 +295,7 @@ def pm_step(pos, vel, ng, params, poisson_opts, scalar_opts, dt_kick, dt_drift, 
     ws = _ws(ws, ng, npart, dt)
     rep = L.StepReport()
     rc = L.lib().pm_step(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()), npart, int(ng), dt,
-                       ctypes.byref(_params(params)), ctypes.byref(poisson_opts.c()), ctypes.byref(scalar_opts.c()),
+                       ctypes.byref(_params(params)), ctypes.byref(poisson_opts.c(ng)), ctypes.byref(scalar_opts.c(ng)),
                        float(dt_kick), float(dt_drift), ctypes.c_void_p(psi.data_ptr()),
                        ctypes.c_void_p(chi.data_ptr()), ctypes.byref(rep), ws.ptr, ws.nbytes, _stream(stream))
     if rc not in (L.PM_OK, L.PM_ENOCONV):

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libpmeft.so")
 PM_OK, PM_EINVAL, PM_EUNSTABLE, PM_ENOCONV, PM_ENONFINITE, PM_EHIP, PM_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 PM_F32, PM_F64 = 0, 1
 PM_PREC_F64, PM_PREC_MIXED, PM_PREC_ANY = 0, 1, 2
-PM_GUESS_ZERO, PM_GUESS_GIVEN, PM_GUESS_LINEAR = 0, 1, 2
+PM_GUESS_ZERO, PM_GUESS_GIVEN, PM_GUESS_LINEAR, PM_GUESS_LEARNED = 0, 1, 2, 3
 
 
 class EftParams(ctypes.Structure):
@@ -31,7 +31,14 @@ class EftCoeffs(ctypes.Structure):
 
 class MgOpts(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_vcycles", ctypes.c_int), ("n_pre", ctypes.c_int),
-                ("n_post", ctypes.c_int), ("precision", ctypes.c_int), ("guess", ctypes.c_int)]
+                ("n_post", ctypes.c_int), ("precision", ctypes.c_int), ("guess", ctypes.c_int),
+                ("learned_params", ctypes.c_void_p), ("learned_ws", ctypes.c_void_p),
+                ("learned_ws_bytes", ctypes.c_size_t)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_void_p), ("chi", ctypes.c_void_p), ("ng", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("p", EftParams)]
 
 
 class MgReport(ctypes.Structure):
@@ -47,7 +54,8 @@ class StepReport(ctypes.Structure):
 
 EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_deposit", "mg_poisson_solve",
            "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
-           "pm_strerror", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
+           "pm_strerror", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
+           "pm_autotune", "pm_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
            "ws_conv3")
 
 
@@ -69,11 +77,24 @@ def _load():
                             vp, sz, vp]
     lib.pm_kernel_timing_enable.argtypes = [i]
     lib.pm_kernel_timing_read.argtypes = [P(d), P(ll)]
+    lib.pm_autotune_workspace_bytes.argtypes = [i, i]
+    lib.pm_autotune_workspace_bytes.restype = sz
+    lib.pm_autotune.argtypes = [i, i, vp, sz, vp]
+    lib.pm_launch_shape.argtypes = [i, i]
+    lib.pm_set_launch_shape.argtypes = [i, i, i]
+    lib.pm_tune_save.argtypes = [ctypes.c_char_p]
+    lib.pm_tune_load.argtypes = [ctypes.c_char_p]
+    for name in ("pm_autotune", "pm_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load"):
+        getattr(lib, name).restype = i
+    lib.mg_batched_workspace_bytes.argtypes = [P(Problem), i, i]
+    lib.mg_batched_workspace_bytes.restype = sz
+    lib.mg_scalar_solve_batched.argtypes = [P(Problem), i, P(MgOpts), P(MgReport), vp, sz, vp]
+    lib.mg_scalar_solve_batched.restype = i
     lib.ws_unet_param_count.restype = ll
     lib.ws_unet_workspace_bytes.argtypes = [i, i]
     lib.ws_unet_workspace_bytes.restype = sz
-    lib.ws_unet_forward.argtypes = [vp, vp, i, P(EftParams), vp, vp, i, vp, sz, vp]
-    lib.ws_unet_train_step.argtypes = [vp, vp, vp, ll, d, vp, vp, i, P(EftParams), vp, P(d), vp, sz, vp]
+    lib.ws_unet_forward.argtypes = [vp, vp, i, P(EftParams), vp, vp, sz, vp]
+    lib.ws_unet_train_step.argtypes = [vp, vp, vp, ll, d, d, vp, vp, i, P(EftParams), vp, P(d), P(d), vp, sz, vp]
     lib.ws_conv3.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp, sz, vp]
     for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3"):
         getattr(lib, name).restype = i

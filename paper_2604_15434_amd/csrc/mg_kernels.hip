@@ -119,6 +119,23 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 }
 
 // ---------------------------------------------------------------- smoothing
+// Local update of one cell of colour `colour` (element e = (i, j, kh)):
+// x_new = (S - h^2 (Lq + tau - cmean)) / 6; returns Lq + tau.
+template <typename R, bool NL>
+__device__ __forceinline__ R smooth_cell(const R *__restrict__ xc_old, const R *__restrict__ xo, R *__restrict__ xc_new,
+                                         const R *__restrict__ dc, const R *__restrict__ tc, int n, int nh, int colour,
+                                         int i, int j, int kh, unsigned e, R cmean, R h2, R ih2, const SolveConsts &sc)
+{
+    R tsh;
+    const R S = stencil_terms<R, R>(xc_old, xo, n, nh, colour, i, j, kh, NL, tsh);
+    const R b = (R)sc.beta * dc[e];
+    int isv;
+    const R lq = root_lap<R>(b, tsh * ih2 * ih2, sc, NL, isv);
+    const R v = lq + (tc ? tc[e] : (R)0);
+    xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
+    return v;
+}
+
 // One half-sweep of colour `colour`.  The lagged mean c = <Lq + tau> comes
 // from csum_in (per-colour sums).  Block 0 also folds the partial sums of the
 // previous half-sweep at this level (prev, prev_nblocks, prev_colour; colour
@@ -146,14 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, c
     if (e0 < e1)
         split(e0, nh, n, i, j, kh);
     for (unsigned e = e0; e < e1;) {
-        R tsh;
-        const R S = stencil_terms<R, R>(xc_old, xo, n, nh, colour, i, j, kh, NL, tsh);
-        const R b = (R)sc.beta * dc[e];
-        int isv;
-        const R lq = root_lap<R>(b, tsh * ih2 * ih2, sc, NL, isv);
-        const R v = lq + (tc ? tc[e] : (R)0);
-        xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
-        acc[0] += (double)v;
+        acc[0] += (double)smooth_cell<R, NL>(xc_old, xo, xc_new, dc, tc, n, nh, colour, i, j, kh, e, cmean, h2, ih2, sc);
         e += kBlock;
         if (e < e1) {  // step (i, j, kh) by kBlock cells without dividing
             kh += kBlock;
@@ -224,6 +234,45 @@ __device__ __forceinline__ T cell_residual(const LevelView<R> &F, const R *xr, c
     return v - cmean - lap;
 }
 
+// Coarse cell e (natural order): residual of its 8 children, their average
+// into the coarse tau, the average of the children's x into the coarse x and
+// x0; acc += (sum r^2, sum r, sum Lq + tau, void cells).
+template <typename R, bool NL>
+__device__ __forceinline__ void restrict_cell(const LevelView<R> &F, const R *__restrict__ xr, const R *__restrict__ xb,
+                                              double cm, const LevelView<R> &C, R *__restrict__ cxr,
+                                              R *__restrict__ cxb, const SolveConsts &sc, unsigned e, double acc[4])
+{
+    const int nc = C.n, nch = C.nh;
+    int I, J, K;
+    split(e, nc, nc, I, J, K);
+    const int cc = (I + J + K) & 1;
+    const unsigned ec = ((unsigned)I * nc + J) * nch + (K >> 1);
+    double sr = 0.0, sx = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const int i = 2 * I + a, j = 2 * J + b;
+            const unsigned ef = ((unsigned)i * F.n + j) * F.nh + K;
+#pragma unroll
+            for (int fc = 0; fc < 2; fc++) {
+                double lqt;
+                int isv;
+                const double r = cell_residual<double, R, NL>(F, xr, xb, fc, i, j, K, ef, cm, sc, lqt, isv);
+                sr += r;
+                sx += (double)(fc ? xb : xr)[ef];
+                acc[0] += r * r;
+                acc[1] += r;
+                acc[2] += lqt;
+                acc[3] += (double)isv;
+            }
+        }
+    const R rx = (R)(0.125 * sx);
+    (cc ? C.tb : C.tr)[ec] = (R)(0.125 * sr);
+    (cc ? cxb : cxr)[ec] = rx;
+    (cc ? C.x0b : C.x0r)[ec] = rx;
+}
+
 // One thread per coarse cell, in natural (I, J, K) order so that
 // consecutive threads read consecutive fine elements: residual of its 8
 // children, their average into the coarse tau, the average of the
@@ -236,39 +285,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, co
                                                               Span sp)
 {
     const double cm = (csum[0] + csum[1]) / (2.0 * (double)F.half);
-    const int nc = C.n, nch = C.nh;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
-    {
-        int I, J, K;
-        split(e, nc, nc, I, J, K);
-        const int cc = (I + J + K) & 1;
-        const unsigned ec = ((unsigned)I * nc + J) * nch + (K >> 1);
-        double sr = 0.0, sx = 0.0;
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int b = 0; b < 2; b++) {
-                const int i = 2 * I + a, j = 2 * J + b;
-                const unsigned ef = ((unsigned)i * F.n + j) * F.nh + K;
-#pragma unroll
-                for (int fc = 0; fc < 2; fc++) {
-                    double lqt;
-                    int isv;
-                    const double r = cell_residual<double, R, NL>(F, xr, xb, fc, i, j, K, ef, cm, sc, lqt, isv);
-                    sr += r;
-                    sx += (double)(fc ? xb : xr)[ef];
-                    acc[0] += r * r;
-                    acc[1] += r;
-                    acc[2] += lqt;
-                    acc[3] += (double)isv;
-                }
-            }
-        const R rx = (R)(0.125 * sx);
-        (cc ? C.tb : C.tr)[ec] = (R)(0.125 * sr);
-        (cc ? cxb : cxr)[ec] = rx;
-        (cc ? C.x0b : C.x0r)[ec] = rx;
-    }
+    restrict_cell<R, NL>(F, xr, xb, cm, C, cxr, cxb, sc, e, acc);
     block_partials<4>(acc, rs, sp);
 }
 
@@ -288,6 +307,36 @@ void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, c
 }
 
 // ------------------------------------------------------------ FAS source
+// Element e of the level (both colours, colour 1 from half on): tau += lap x
+// - Lq(x) unless accumulate_only; acc[colour] += Lq + tau.
+template <typename R, bool NL>
+__device__ __forceinline__ void fas_cell(const LevelView<R> &C, const R *__restrict__ xr, const R *__restrict__ xb,
+                                         const SolveConsts &sc, unsigned e, int accumulate_only, double acc[2])
+{
+    const double ih2 = 1.0 / (C.h * C.h);
+    const unsigned half = (unsigned)C.half;
+    const int c = e >= half;
+    const unsigned ec = e - (c ? half : 0u);
+    int i, j, kh;
+    split(ec, C.nh, C.n, i, j, kh);
+    const R *own = c ? xb : xr;
+    const R *oth = c ? xr : xb;
+    double tsh;
+    const double S = stencil_terms<double, R>(own, oth, C.n, C.nh, c, i, j, kh, NL, tsh);
+    const double b = sc.beta * (double)(c ? C.db : C.dr)[ec];
+    int isv;
+    const double lq = root_lap<double>(b, tsh * ih2 * ih2, sc, NL, isv);
+    R *tc = c ? C.tb : C.tr;
+    double t = tc ? (double)tc[ec] : 0.0;
+    if (!accumulate_only) {
+        const double lap = (S - 6.0 * (double)own[ec]) * ih2;
+        t += lap - lq;
+        tc[ec] = (R)t;
+        t = (double)(R)t;
+    }
+    acc[c] += lq + t;
+}
+
 // tau += lap x - Lq(x) (or, with accumulate_only, leave tau) and store the
 // per-colour sums of Lq + tau.
 template <typename R, bool NL>
@@ -296,31 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau(LevelView<R> C, const R *__r
                                                     int accumulate_only)
 {
     double acc[2] = {0.0, 0.0};
-    const double ih2 = 1.0 / (C.h * C.h);
-    const unsigned half = (unsigned)C.half;
     PM_SPAN_LOOP(e, sp)
-    {
-        const int c = e >= half;
-        const unsigned ec = e - (c ? half : 0u);
-        int i, j, kh;
-        split(ec, C.nh, C.n, i, j, kh);
-        const R *own = c ? xb : xr;
-        const R *oth = c ? xr : xb;
-        double tsh;
-        const double S = stencil_terms<double, R>(own, oth, C.n, C.nh, c, i, j, kh, NL, tsh);
-        const double b = sc.beta * (double)(c ? C.db : C.dr)[ec];
-        int isv;
-        const double lq = root_lap<double>(b, tsh * ih2 * ih2, sc, NL, isv);
-        R *tc = c ? C.tb : C.tr;
-        double t = tc ? (double)tc[ec] : 0.0;
-        if (!accumulate_only) {
-            const double lap = (S - 6.0 * (double)own[ec]) * ih2;
-            t += lap - lq;
-            tc[ec] = (R)t;
-            t = (double)(R)t;
-        }
-        acc[c] += lq + t;
-    }
+    fas_cell<R, NL>(C, xr, xb, sc, e, accumulate_only, acc);
     block_partials<2>(acc, rs, sp);
 }
 
@@ -353,12 +379,25 @@ __device__ __forceinline__ double coarse_at(const R *cr, const R *cb, int nc, in
 // fine iterate (coarse-grid correction); !CORR: write P x_H (full
 // approximation, used to start full multigrid).
 template <typename R, bool CORR>
+__device__ __forceinline__ void prolong_cell(const LevelView<R> &F, R *__restrict__ xr, R *__restrict__ xb,
+                                             const LevelView<R> &C, const R *__restrict__ cxr,
+                                             const R *__restrict__ cxb, unsigned e);
+
+template <typename R, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<R> F, R *__restrict__ xr, R *__restrict__ xb,
                                                     LevelView<R> C, const R *__restrict__ cxr,
                                                     const R *__restrict__ cxb, Span sp)
 {
-    const int nc = C.n, nch = C.nh;
     PM_SPAN_LOOP(e, sp)
+    prolong_cell<R, CORR>(F, xr, xb, C, cxr, cxb, e);
+}
+
+template <typename R, bool CORR>
+__device__ __forceinline__ void prolong_cell(const LevelView<R> &F, R *__restrict__ xr, R *__restrict__ xb,
+                                             const LevelView<R> &C, const R *__restrict__ cxr,
+                                             const R *__restrict__ cxb, unsigned e)
+{
+    const int nc = C.n, nch = C.nh;
     {
         int I, J, K;
         split(e, nc, nc, I, J, K);
@@ -424,14 +463,17 @@ void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R>
 // mean of Lq + tau recomputed before every half-sweep, until the largest
 // update falls below 1e-14 of the largest value or `sweeps` sweeps are done.
 constexpr int kCoarseMax = 216;
+constexpr double kCoarseTol = 1e-14;
 
+// Device part, for any block size >= n^3 that is a multiple of 64 (all
+// threads of the block must call it).
 template <typename R, bool NL>
-__global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *xb, SolveConsts sc, int sweeps)
+__device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveConsts &sc, int sweeps, double tol)
 {
     __shared__ double x[kCoarseMax], d[kCoarseMax], t[kCoarseMax];
-    __shared__ double red[kBlock / 64][2];
+    __shared__ double red[16][2];
     const int n = C.n, nh = C.nh, N = n * n * n;
-    const int q = threadIdx.x;
+    const int q = threadIdx.x, nw = blockDim.x >> 6;
     int i = 0, j = 0, k = 0, col = 0;
     long long off = 0;
     if (q < N) {
@@ -481,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *x
                 red[wid][0] = s;
             __syncthreads();
             double tot = 0.0;
-            for (int w = 0; w < kBlock / 64; w++)
+            for (int w = 0; w < nw; w++)
                 tot += red[w][0];
             const double cmean = tot / (double)N;
             double nx = 0.0;
@@ -507,25 +549,33 @@ __global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *x
         }
         __syncthreads();
         double gx = 0.0, gd = 0.0;
-        for (int w = 0; w < kBlock / 64; w++) {
+        for (int w = 0; w < nw; w++) {
             gx = fmax(gx, red[w][0]);
             gd = fmax(gd, red[w][1]);
         }
         __syncthreads();
-        if (gd <= 1e-14 * gx)
+        if (gd <= tol * gx)
             break;
     }
     if (q < N)
         (col ? xb : xr)[off] = (R)x[q];
+    __syncthreads();
+}
+
+template <typename R, bool NL>
+__global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *xb, SolveConsts sc, int sweeps,
+                                                     double tol)
+{
+    coarsest_solve<R, NL>(C, xr, xb, sc, sweeps, tol);
 }
 
 template <typename R>
 void launch_coarsest(const LevelView<R> &C, R *xr, R *xb, SolveConsts sc, bool nonlinear, int sweeps, hipStream_t st)
 {
     if (nonlinear)
-        hipLaunchKernelGGL((k_coarsest<R, true>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps);
+        hipLaunchKernelGGL((k_coarsest<R, true>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol);
     else
-        hipLaunchKernelGGL((k_coarsest<R, false>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps);
+        hipLaunchKernelGGL((k_coarsest<R, false>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol);
 }
 
 // ------------------------------------------------------------- transfers
@@ -849,5 +899,179 @@ template void launch_coarsest<double>(const LevelView<double> &, double *, doubl
 template void launch_coarsest<float>(const LevelView<float> &, float *, float *, SolveConsts, bool, int, hipStream_t);
 template void launch_restrict_field<double>(int, const double *, const double *, double *, double *, hipStream_t);
 template void launch_restrict_field<float>(int, const float *, const float *, float *, float *, hipStream_t);
+
+// ------------------------------------------------------------ block cycle
+// The V-cycle (or the coarse part of full multigrid) from level l0 down, run
+// by one workgroup: on coarse grids a launch per operation costs more than
+// the operation, so the whole sub-cycle becomes one launch.  The cell updates
+// are the functions of the grid-wide kernels; the lagged mean of a level is
+// the exact per-colour sum of its last half-sweeps (no deferred fold).
+template <typename R>
+__device__ __forceinline__ void block_sum2(double a, double b, double *out2, double (*red)[2])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o, 64);
+        b += __shfl_down(b, o, 64);
+    }
+    if (lane == 0) {
+        red[wid][0] = a;
+        red[wid][1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int w = 0; w < nw; w++) {
+            sa += red[w][0];
+            sb += red[w][1];
+        }
+        out2[0] = sa;
+        out2[1] = sb;
+    }
+    __syncthreads();
+}
+
+template <typename R, bool NL>
+__global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R> Barg, int l0, int fmg, int n_pre,
+                                                                    int n_post, SolveConsts sc,
+                                                                    const double *__restrict__ csum_l0, int cur_bits,
+                                                                    int coarse_sweeps)
+{
+    // the level table lives in LDS: indexed by level at run time, a kernel
+    // argument would be copied to private memory
+    __shared__ BlockHier<R> B;
+    if (threadIdx.x == 0)
+        B = Barg;
+    __shared__ int cur[kMaxLevels][2];
+    __shared__ double cs[kMaxLevels][2];
+    __shared__ double red[16][2];
+    __shared__ double tmp2[2];
+    const unsigned tid = threadIdx.x, nt = blockDim.x;
+    const int L = Barg.nlev;  // B is read only after the barrier below
+    if (tid == 0) {
+        for (int l = 0; l < kMaxLevels; l++) {
+            cur[l][0] = cur[l][1] = 0;
+            cs[l][0] = cs[l][1] = 0.0;
+        }
+        if (!fmg) {
+            cur[l0][0] = cur_bits & 1;
+            cur[l0][1] = (cur_bits >> 1) & 1;
+            cs[l0][0] = csum_l0[0];
+            cs[l0][1] = csum_l0[1];
+        }
+    }
+    __syncthreads();
+    auto xr = [&](int l) -> R * { return B.buf[l][cur[l][0]]; };
+    auto xb = [&](int l) -> R * { return B.buf[l][cur[l][1]] + B.L[l].half; };
+    auto half_sweep = [&](int m, int colour) {
+        const LevelView<R> &Lv = B.L[m];
+        const int own = cur[m][colour];
+        const unsigned half = (unsigned)Lv.half;
+        R *src = B.buf[m][own] + (colour ? half : 0u);
+        R *dst = B.buf[m][1 - own] + (colour ? half : 0u);
+        const R *oth = B.buf[m][cur[m][1 - colour]] + (colour ? 0u : half);
+        const R cmean = (R)((cs[m][0] + cs[m][1]) / (2.0 * (double)half));
+        const R h2 = (R)(Lv.h * Lv.h), ih2 = (R)(1.0 / (Lv.h * Lv.h));
+        const R *dc = colour ? Lv.db : Lv.dr;
+        const R *tc = colour ? Lv.tb : Lv.tr;
+        double acc = 0.0;
+        for (unsigned e = tid; e < half; e += nt) {
+            int i, j, kh;
+            split(e, Lv.nh, Lv.n, i, j, kh);
+            acc += (double)smooth_cell<R, NL>(src, oth, dst, dc, tc, Lv.n, Lv.nh, colour, i, j, kh, e, cmean, h2, ih2,
+                                             sc);
+        }
+        block_sum2<R>(acc, 0.0, tmp2, red);
+        if (tid == 0) {
+            cs[m][colour] = tmp2[0];
+            cur[m][colour] = 1 - own;
+        }
+        __syncthreads();
+    };
+    auto fas = [&](int m, int acc_only) {
+        double acc[2] = {0.0, 0.0};
+        const unsigned tot = 2u * (unsigned)B.L[m].half;
+        R *x_r = xr(m), *x_b = xb(m);
+        for (unsigned e = tid; e < tot; e += nt)
+            fas_cell<R, NL>(B.L[m], x_r, x_b, sc, e, acc_only, acc);
+        block_sum2<R>(acc[0], acc[1], tmp2, red);
+        if (tid == 0) {
+            cs[m][0] = tmp2[0];
+            cs[m][1] = tmp2[1];
+        }
+        __syncthreads();
+    };
+    auto vcycle = [&](int l) {
+        for (int m = l; m < L - 1; m++) {
+            for (int s = 0; s < n_pre; s++) {
+                half_sweep(m, 0);
+                half_sweep(m, 1);
+            }
+            const double cm = (cs[m][0] + cs[m][1]) / (2.0 * (double)B.L[m].half);
+            R *cxr = B.buf[m + 1][0], *cxb = B.buf[m + 1][0] + B.L[m + 1].half;
+            const unsigned tot = 2u * (unsigned)B.L[m + 1].half;
+            R *x_r = xr(m), *x_b = xb(m);
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            for (unsigned e = tid; e < tot; e += nt)
+                restrict_cell<R, NL>(B.L[m], x_r, x_b, cm, B.L[m + 1], cxr, cxb, sc, e, acc);
+            __syncthreads();
+            if (tid == 0)
+                cur[m + 1][0] = cur[m + 1][1] = 0;
+            __syncthreads();
+            fas(m + 1, 0);
+        }
+        coarsest_solve<R, NL>(B.L[L - 1], xr(L - 1), xb(L - 1), sc, coarse_sweeps, kCoarseTol);
+        for (int m = L - 2; m >= l; m--) {
+            const unsigned tot = 2u * (unsigned)B.L[m + 1].half;
+            R *x_r = xr(m), *x_b = xb(m), *c_r = xr(m + 1), *c_b = xb(m + 1);
+            for (unsigned e = tid; e < tot; e += nt)
+                prolong_cell<R, true>(B.L[m], x_r, x_b, B.L[m + 1], c_r, c_b, e);
+            __syncthreads();
+            for (int s = 0; s < n_post; s++) {
+                half_sweep(m, 0);
+                half_sweep(m, 1);
+            }
+        }
+    };
+    if (fmg) {
+        R *xc = B.buf[L - 1][0];
+        const unsigned totc = 2u * (unsigned)B.L[L - 1].half;
+        for (unsigned e = tid; e < totc; e += nt)
+            xc[e] = (R)0;
+        __syncthreads();
+        coarsest_solve<R, NL>(B.L[L - 1], xc, xc + B.L[L - 1].half, sc, coarse_sweeps, kCoarseTol);
+        for (int l = L - 2; l >= l0; l--) {
+            const unsigned tot = 2u * (unsigned)B.L[l + 1].half;
+            R *x_r = B.buf[l][0], *x_b = B.buf[l][0] + B.L[l].half, *c_r = xr(l + 1), *c_b = xb(l + 1);
+            for (unsigned e = tid; e < tot; e += nt)
+                prolong_cell<R, false>(B.L[l], x_r, x_b, B.L[l + 1], c_r, c_b, e);
+            __syncthreads();
+            if (tid == 0)
+                cur[l][0] = cur[l][1] = 0;
+            __syncthreads();
+            fas(l, 1);
+            vcycle(l);
+        }
+    } else {
+        vcycle(l0);
+    }
+}
+
+template <typename R>
+void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
+                        const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st)
+{
+    if (nonlinear)
+        hipLaunchKernelGGL((k_block_cycle<R, true>), dim3(1), dim3(kBlockCycleThreads), 0, st, B, l0, fmg ? 1 : 0,
+                           n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps);
+    else
+        hipLaunchKernelGGL((k_block_cycle<R, false>), dim3(1), dim3(kBlockCycleThreads), 0, st, B, l0, fmg ? 1 : 0,
+                           n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps);
+}
+
+template void launch_block_cycle<float>(const BlockHier<float> &, int, bool, int, int, SolveConsts, bool,
+                                        const double *, int, int, hipStream_t);
+template void launch_block_cycle<double>(const BlockHier<double> &, int, bool, int, int, SolveConsts, bool,
+                                         const double *, int, int, hipStream_t);
 
 }  // namespace pmeft

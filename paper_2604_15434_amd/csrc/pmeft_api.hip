@@ -3,9 +3,14 @@
 #include "pmeft_internal.h"
 
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <array>
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 namespace pmeft {
@@ -206,6 +211,18 @@ struct Hier {
     double *parts = nullptr; // [kMaxLevels][2][kMaxBlocks * 8]
     int cs[kMaxLevels];      // current csum buffer per level
     int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
+    int block_l0 = kMaxLevels;  // levels from here down run as one block cycle
+    BlockHier<R> block() const
+    {
+        BlockHier<R> B;
+        B.nlev = nlev;
+        for (int l = 0; l < kMaxLevels; l++) {
+            B.L[l] = L[l];
+            B.buf[l][0] = buf[l][0];
+            B.buf[l][1] = buf[l][1];
+        }
+        return B;
+    }
     R *xr(int l) { return buf[l][cur[l][0]]; }
     R *xb(int l) { return buf[l][cur[l][1]] + L[l].half; }
     double *csum_cur(int l) { return csum + ((size_t)cs[l] * kMaxLevels + l) * 2; }
@@ -240,6 +257,48 @@ static LevelView<R> make_view(int n, double h, const R *d, R *t, R *x0)
     return v;
 }
 
+// ---- launch-shape table --------------------------------------------------
+// Largest grid of the levels that run as one block cycle, per (finest grid,
+// word size); set by pm_autotune, default kBlockCycleDefault.
+constexpr int kBlockCycleDefault = 32;
+struct TuneTable {
+    std::mutex mu;
+    std::vector<std::array<int, 3>> block_n;  // (ng, word size, max n; 0 = off)
+};
+static TuneTable g_tune;
+
+static int block_cycle_n(int ng, int word)
+{
+    std::lock_guard<std::mutex> g(g_tune.mu);
+    for (const auto &e : g_tune.block_n)
+        if (e[0] == ng && e[1] == word)
+            return e[2];
+    return kBlockCycleDefault;
+}
+
+static void set_block_cycle_n(int ng, int word, int n)
+{
+    std::lock_guard<std::mutex> g(g_tune.mu);
+    for (auto &e : g_tune.block_n)
+        if (e[0] == ng && e[1] == word) {
+            e[2] = n;
+            return;
+        }
+    g_tune.block_n.push_back({ng, word, n});
+}
+
+template <typename R>
+static void set_block_level(Hier<R> &H, int ng)
+{
+    const int nmax = block_cycle_n(ng, (int)sizeof(R));
+    H.block_l0 = kMaxLevels;
+    for (int l = 0; l < H.nlev - 1; l++)
+        if (H.L[l].n <= nmax) {
+            H.block_l0 = l;
+            break;
+        }
+}
+
 static void build_hier64(Ctx &C, Hier<double> &H, double *master)
 {
     const Plan &P = C.P;
@@ -254,6 +313,7 @@ static void build_hier64(Ctx &C, Hier<double> &H, double *master)
         H.init_state(l);
     }
     H.parts = C.sm_partials;
+    set_block_level(H, P.ng);
 }
 
 static void build_hier32(Ctx &C, Hier<float> &H)
@@ -269,6 +329,7 @@ static void build_hier32(Ctx &C, Hier<float> &H)
         H.init_state(l);
     }
     H.parts = C.sm_partials;
+    set_block_level(H, P.ng);
 }
 
 // ------------------------------------------------------- kernel timing
@@ -328,6 +389,15 @@ constexpr int kCoarseSweeps = 100;
 template <typename R>
 static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveConsts sc, bool nl)
 {
+    if (l >= H.block_l0 && l < H.nlev - 1) {
+        const int bits = H.cur[l][0] | (H.cur[l][1] << 1);
+        launch_block_cycle<R>(H.block(), l, false, o.n_pre, o.n_post, sc, nl, H.csum_cur(l), bits, kCoarseSweeps,
+                              C.st);
+        const int f = (o.n_pre + o.n_post) & 1;
+        H.cur[l][0] ^= f;
+        H.cur[l][1] ^= f;
+        return;
+    }
     if (l == H.nlev - 1) {
         launch_coarsest<R>(H.L[l], H.xr(l), H.xb(l), sc, nl, kCoarseSweeps, C.st);
         return;
@@ -364,10 +434,23 @@ static void fmg_start(Ctx &C, Hier<R> &H, const pm_mg_opts &o, SolveConsts sc, b
         else
             launch_zero(G.tr, sizeof(R) * 2 * G.half, C.st);
     }
-    H.cur[L - 1][0] = H.cur[L - 1][1] = 0;
-    launch_zero(H.buf[L - 1][0], sizeof(R) * 2 * H.L[L - 1].half, C.st);
-    launch_coarsest<R>(H.L[L - 1], H.xr(L - 1), H.xb(L - 1), sc, nl, kCoarseSweeps, C.st);
-    for (int l = L - 2; l >= 0; l--) {
+    int top = L - 2;
+    if (H.block_l0 < L - 1) {
+        launch_block_cycle<R>(H.block(), H.block_l0, true, o.n_pre, o.n_post, sc, nl, nullptr, 0, kCoarseSweeps, C.st);
+        const int f = (o.n_pre + o.n_post) & 1;
+        H.cur[H.block_l0][0] = H.cur[H.block_l0][1] = f;
+        top = H.block_l0 - 1;
+        if (H.block_l0 == 0) {
+            // the caller smooths level 0 next: set its per-colour sums exactly
+            launch_fas_tau<R>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st);
+            H.fresh(0);
+        }
+    } else {
+        H.cur[L - 1][0] = H.cur[L - 1][1] = 0;
+        launch_zero(H.buf[L - 1][0], sizeof(R) * 2 * H.L[L - 1].half, C.st);
+        launch_coarsest<R>(H.L[L - 1], H.xr(L - 1), H.xb(L - 1), sc, nl, kCoarseSweeps, C.st);
+    }
+    for (int l = top; l >= 0; l--) {
         H.cur[l][0] = H.cur[l][1] = 0;
         launch_prolong_full<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
         launch_fas_tau<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), C.rs, sc, nl, true, C.st);
@@ -550,13 +633,10 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     return PM_OK;
 }
 
-// delta hierarchy from the packed fine delta (mean removed here) + FP32 copy
-static int prepare_delta(Ctx &C, double *delta_sq_sum)
+// coarse delta levels (8-cell averages) and FP32 copies from the fine level
+static void delta_levels(Ctx &C)
 {
     const Plan &P = C.P;
-    double *d0 = C.at<double>(P.delta64[0]);
-    launch_field_sum(d0, P.N, C.rs, C.st);
-    launch_subtract_mean(d0, P.N, C.rs.out, C.st);
     for (int l = 1; l < P.nlev; l++) {
         const long long fh = (long long)P.n[l - 1] * P.n[l - 1] * (P.n[l - 1] / 2);
         const long long ch = (long long)P.n[l] * P.n[l] * (P.n[l] / 2);
@@ -568,6 +648,16 @@ static int prepare_delta(Ctx &C, double *delta_sq_sum)
         for (int l = 0; l < P.nlev; l++)
             launch_cast_f64_f32(C.at<double>(P.delta64[l]), C.at<float>(P.d32[l]),
                                 (long long)P.n[l] * P.n[l] * P.n[l], C.st);
+}
+
+// delta hierarchy from the packed fine delta (mean removed here) + FP32 copy
+static int prepare_delta(Ctx &C, double *delta_sq_sum)
+{
+    const Plan &P = C.P;
+    double *d0 = C.at<double>(P.delta64[0]);
+    launch_field_sum(d0, P.N, C.rs, C.st);
+    launch_subtract_mean(d0, P.N, C.rs.out, C.st);
+    delta_levels(C);
     launch_field_sum(d0, P.N, C.rs, C.st);
     double out[2];
     int e = read_out(C, C.rs.out, out, 2);
@@ -598,7 +688,8 @@ static bool opts_ok(const pm_mg_opts *o)
 {
     return o && o->rel_tol > 0.0 && o->max_vcycles >= 0 && o->n_pre >= 0 && o->n_post >= 0 && o->n_pre + o->n_post > 0 &&
            (o->precision == PM_PREC_F64 || o->precision == PM_PREC_MIXED) && o->guess >= PM_GUESS_ZERO &&
-           o->guess <= PM_GUESS_LINEAR;
+           o->guess <= PM_GUESS_LEARNED &&
+           (o->guess != PM_GUESS_LEARNED || (o->learned_params && o->learned_ws));
 }
 
 // The mixed path also needs the FP64 hierarchy: the nonlinear solve finishes
@@ -628,8 +719,37 @@ static int poisson_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, So
     return run_solve(C, m, sc, false, o, src, so, o.guess != PM_GUESS_GIVEN);
 }
 
+// Learned warm start: one linear full-multigrid pass on
+// nu lap chi0 = xi s (delta + t - <t>), t from the network; delta is restored
+// afterwards.
+static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, double src)
+{
+    const int ng = C.P.ng;
+    if (ng % 64 || ng < 64)
+        return PM_EINVAL;
+    if (o.learned_ws_bytes < ws_unet_workspace_bytes(ng, 0))
+        return PM_ENOMEM;
+    double *d0 = C.at<double>(C.P.delta64[0]);
+    double *save = unet_save_area(o.learned_ws, ng);
+    int e = unet_learned_source(o.learned_params, d0, save, ng, p, o.learned_ws, o.learned_ws_bytes, C.st);
+    if (e)
+        return e;
+    delta_levels(C);
+    pm_mg_opts lo = o;
+    lo.rel_tol = 1e-30;  // the pass itself, no convergence test
+    lo.max_vcycles = 1;
+    SolveOut tmp;
+    e = run_solve(C, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true);
+    if (e)
+        return e;
+    PM_HIP(hipMemcpyAsync(d0, save, sizeof(double) * C.P.N, hipMemcpyDeviceToDevice, C.st));
+    delta_levels(C);
+    return launched();
+}
+
 // Scalar field: nu lap chi - xi s delta - K N(chi) = 0 (beta = xi s).
-static int scalar_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so, double dsq)
+static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so,
+                       double dsq)
 {
     double *m = C.at<double>(C.P.chi64);
     so = SolveOut();
@@ -644,8 +764,14 @@ static int scalar_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, Sol
         return launched();
     }
     SolveConsts sc{cf.nu, cf.K, cf.xi * cf.s};
-    if (o.guess == PM_GUESS_ZERO || o.guess == PM_GUESS_LINEAR)
+    if (o.guess != PM_GUESS_GIVEN)
         launch_zero(m, sizeof(double) * C.P.N, C.st);
+    if (o.guess == PM_GUESS_LEARNED && nl) {
+        int e = learned_guess(C, p, cf, o, src);
+        if (e)
+            return e;
+        return run_solve(C, m, sc, nl, o, src, so, false);
+    }
     if (o.guess == PM_GUESS_LINEAR && nl) {
         pm_mg_opts lo = o;
         lo.rel_tol = 1e-3;
@@ -656,7 +782,7 @@ static int scalar_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, Sol
         if (e)
             return e;
     }
-    return run_solve(C, m, sc, nl, o, src, so, o.guess == PM_GUESS_ZERO);
+    return run_solve(C, m, sc, nl, o, src, so, o.guess == PM_GUESS_ZERO || o.guess == PM_GUESS_LEARNED);
 }
 
 struct Timer {
@@ -707,7 +833,7 @@ static int grid_solve(const void *rho, int ng, pm_dtype dt, const pm_eft_params 
     if (o->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(out, dt, m, ng, 1.0, 0.0, C.st);
     SolveOut so;
-    e = scalar ? scalar_core(C, cf, *o, so, dsq) : poisson_core(C, cf, *o, so, dsq);
+    e = scalar ? scalar_core(C, *p, cf, *o, so, dsq) : poisson_core(C, cf, *o, so, dsq);
     if (e)
         return e;
     launch_field_sum(m, C.P.N, C.rs, C.st);
@@ -777,6 +903,243 @@ int mg_scalar_solve(const void *rho, int ng, pm_dtype dtype, const pm_eft_params
     return grid_solve(rho, ng, dtype, p, opts, chi, rep, ws, ws_bytes, stream, true);
 }
 
+// ---- batched solve ---------------------------------------------------------
+// Host workers, each with its own stream and workspace slice, take the
+// problems largest grid first from a shared counter and run the single-problem
+// solve on them; the kernel sequence of a problem does not depend on the
+// worker, so each result equals the problem's own solve bit for bit.
+static constexpr int kBatchWorkers = 4;
+
+static size_t batch_slice_bytes(const pm_problem *probs, int nprob, int precision)
+{
+    int ng = 0;
+    pm_dtype dt = PM_F32;
+    for (int i = 0; i < nprob; i++) {
+        ng = std::max(ng, probs[i].ng);
+        if (probs[i].dtype == PM_F64)
+            dt = PM_F64;
+    }
+    const size_t b = pm_workspace_bytes(ng, 0, dt, (pm_prec)precision);
+    return (b + 255) & ~(size_t)255;
+}
+
+static int batch_workers(int nprob) { return std::min(kBatchWorkers, std::max(nprob, 1)); }
+
+size_t mg_batched_workspace_bytes(const pm_problem *probs, int nprob, int precision)
+{
+    if (!probs || nprob <= 0 || (precision != PM_PREC_F64 && precision != PM_PREC_MIXED))
+        return 0;
+    for (int i = 0; i < nprob; i++) {
+        Plan P;
+        if (!make_plan(P, probs[i].ng, 0, probs[i].dtype, kPrecF64))
+            return 0;
+    }
+    return batch_slice_bytes(probs, nprob, precision) * batch_workers(nprob);
+}
+
+int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts *opts, pm_mg_report *reps, void *ws,
+                            size_t ws_bytes, pm_stream_t stream)
+{
+    if (!probs || nprob <= 0 || !opts_ok(opts) || opts->guess == PM_GUESS_LEARNED || !ws || ((uintptr_t)ws & 255))
+        return PM_EINVAL;
+    for (int i = 0; i < nprob; i++)
+        if (!probs[i].rho || !probs[i].chi || (probs[i].dtype != PM_F32 && probs[i].dtype != PM_F64))
+            return PM_EINVAL;
+    const size_t need = mg_batched_workspace_bytes(probs, nprob, opts->precision);
+    if (need == 0)
+        return PM_EINVAL;
+    if (ws_bytes < need)
+        return PM_ENOMEM;
+    const size_t slice = batch_slice_bytes(probs, nprob, opts->precision);
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].ng > probs[b].ng; });
+    int dev = 0;
+    PM_HIP(hipGetDevice(&dev));
+    hipEvent_t ready;
+    PM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return PM_EHIP;
+    }
+    std::vector<int> codes(nprob, PM_OK);
+    std::vector<pm_mg_report> local(nprob);
+    std::atomic<int> next{0};
+    std::atomic<int> setup_err{PM_OK};
+    auto work = [&](int w) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            setup_err = PM_EHIP;
+            return;
+        }
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            setup_err = PM_EHIP;
+            return;
+        }
+        if (hipStreamWaitEvent(st, ready, 0) == hipSuccess) {
+            char *mine = (char *)ws + (size_t)w * slice;
+            for (int k = next.fetch_add(1); k < nprob; k = next.fetch_add(1)) {
+                const int i = order[k];
+                codes[i] = grid_solve(probs[i].rho, probs[i].ng, probs[i].dtype, &probs[i].p, opts, probs[i].chi,
+                                      &local[i], mine, slice, st, true);
+            }
+        } else {
+            setup_err = PM_EHIP;
+        }
+        if (hipStreamSynchronize(st) != hipSuccess)
+            setup_err = PM_EHIP;
+        (void)hipStreamDestroy(st);
+    };
+    const int nw = batch_workers(nprob);
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nw; w++)
+        pool.emplace_back(work, w);
+    for (auto &t : pool)
+        t.join();
+    (void)hipEventDestroy(ready);
+    if (setup_err != PM_OK)
+        return setup_err;
+    int rc = PM_OK;
+    for (int i = 0; i < nprob; i++) {
+        if (reps)
+            reps[i] = local[i];
+        if (codes[i] != PM_OK && codes[i] != PM_ENOCONV && (rc == PM_OK || rc == PM_ENOCONV))
+            rc = codes[i];
+        else if (codes[i] == PM_ENOCONV && rc == PM_OK)
+            rc = PM_ENOCONV;
+    }
+    return rc;
+}
+
+// ---- autotuner ------------------------------------------------------------
+// Synthetic density for timing: rho = 1 + 0.9 sin(2 pi x) sin(2 pi y) sin(2 pi z)
+// on cell centres (natural order).
+__global__ void k_synth_rho(double *rho, int n)
+{
+    const unsigned long long n3 = (unsigned long long)n * n * n;
+    for (unsigned long long e = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
+         e += (unsigned long long)gridDim.x * blockDim.x) {
+        const int k = (int)(e % n), j = (int)((e / n) % n), i = (int)(e / ((unsigned long long)n * n));
+        const double tp = 6.283185307179586 / n;
+        rho[e] = 1.0 + 0.9 * sin(tp * (i + 0.5)) * sin(tp * (j + 0.5)) * sin(tp * (k + 0.5));
+    }
+}
+
+size_t pm_autotune_workspace_bytes(int ng, int precision)
+{
+    if (precision != PM_PREC_F64 && precision != PM_PREC_MIXED)
+        return 0;
+    const size_t b = pm_workspace_bytes(ng, 0, PM_F64, (pm_prec)precision);
+    if (b == 0)
+        return 0;
+    return ((b + 255) & ~(size_t)255) + 2 * (((sizeof(double) * (size_t)ng * ng * ng) + 255) & ~(size_t)255);
+}
+
+int pm_launch_shape(int ng, int word_bytes)
+{
+    if (word_bytes != 4 && word_bytes != 8)
+        return PM_EINVAL;
+    return block_cycle_n(ng, word_bytes);
+}
+
+int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid)
+{
+    if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8)
+        return PM_EINVAL;
+    set_block_cycle_n(ng, word_bytes, block_cycle_grid);
+    return PM_OK;
+}
+
+int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    const size_t need = pm_autotune_workspace_bytes(ng, precision);
+    if (need == 0 || !ws || ((uintptr_t)ws & 255))
+        return PM_EINVAL;
+    if (ws_bytes < need)
+        return PM_ENOMEM;
+    const size_t solver = (pm_workspace_bytes(ng, 0, PM_F64, (pm_prec)precision) + 255) & ~(size_t)255;
+    const size_t field = ((sizeof(double) * (size_t)ng * ng * ng) + 255) & ~(size_t)255;
+    double *rho = (double *)((char *)ws + solver);
+    double *chi = (double *)((char *)ws + solver + field);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_synth_rho, dim3(1024), dim3(256), 0, st, rho, ng);
+    PM_HIP(hipGetLastError());
+    const pm_eft_params p{0.3071, -0.5, 0.1, 1.0, 1, 1};
+    pm_mg_opts o{};
+    o.rel_tol = 1e-30;  // fixed work: full multigrid + 3 V-cycles
+    o.max_vcycles = 4;
+    o.n_pre = 1;
+    o.n_post = 2;
+    o.precision = precision;
+    o.guess = PM_GUESS_ZERO;
+    const int word = precision == PM_PREC_MIXED ? 4 : 8;
+    const int cands[5] = {0, 8, 16, 32, 64};
+    int best_n = block_cycle_n(ng, word);
+    float best_ms = 1e30f;
+    for (int c = 0; c < 5; c++) {
+        const int n = cands[c];
+        if (n >= ng)
+            continue;
+        set_block_cycle_n(ng, word, n);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; rep++) {  // first run warms up
+            pm_mg_report r;
+            const int e = grid_solve(rho, ng, PM_F64, &p, &o, chi, &r, ws, solver, stream, true);
+            if (e != PM_OK && e != PM_ENOCONV) {
+                set_block_cycle_n(ng, word, best_n);
+                return e;
+            }
+            if (rep > 0)
+                ms = std::min(ms, r.ms);
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_n = n;
+        }
+    }
+    set_block_cycle_n(ng, word, best_n);
+    return PM_OK;
+}
+
+int pm_tune_save(const char *path)
+{
+    if (!path)
+        return PM_EINVAL;
+    FILE *f = fopen(path, "w");
+    if (!f)
+        return PM_EINVAL;
+    std::lock_guard<std::mutex> g(g_tune.mu);
+    fprintf(f, "# pmeft launch shapes: ng word_bytes block_cycle_grid\n");
+    for (const auto &e : g_tune.block_n)
+        fprintf(f, "%d %d %d\n", e[0], e[1], e[2]);
+    fclose(f);
+    return PM_OK;
+}
+
+int pm_tune_load(const char *path)
+{
+    if (!path)
+        return PM_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f)
+        return PM_EINVAL;
+    char line[256];
+    int rc = PM_OK;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n')
+            continue;
+        int ng, word, n;
+        if (sscanf(line, "%d %d %d", &ng, &word, &n) != 3 || (word != 4 && word != 8) || n < 0 || ng < 8) {
+            rc = PM_EINVAL;
+            break;
+        }
+        set_block_cycle_n(ng, word, n);
+    }
+    fclose(f);
+    return rc;
+}
+
 int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, const pm_eft_params *p, const void *pos,
                     long long np, void *vel, double dt_kick, void *acc_out, void *ws, size_t ws_bytes,
                     pm_stream_t stream)
@@ -840,7 +1203,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         return e;
     const float ms_p = tp.stop();
     Timer tx(C.st);
-    e = scalar_core(C, cf, *scalar_opts, sx, dsq);
+    e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq);
     if (e)
         return e;
     const float ms_x = tx.stop();

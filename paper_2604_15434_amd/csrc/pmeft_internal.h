@@ -231,6 +231,30 @@ void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStre
 void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
 
+// ---- block cycle: the coarse part of a V-cycle in one workgroup ---------
+constexpr int kBlockCycleThreads = 512;
+template <typename R>
+struct BlockHier {
+    int nlev;
+    LevelView<R> L[kMaxLevels];
+    R *buf[kMaxLevels][2];
+};
+// fmg = false: V-cycle from level l0 (its tau set, its per-colour sums in
+// csum_l0, its colour buffers cur_bits (bit c = buffer of colour c)); each
+// colour of level l0 ends in buffer cur ^ ((n_pre + n_post) & 1).
+// fmg = true: full multigrid from the coarsest level up to l0 (taus set);
+// level l0 ends in buffer (n_pre + n_post) & 1.
+template <typename R>
+void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
+                        const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st);
+
+// ---- learned warm start (unet_api.hip) -----------------------------------
+// delta (packed, mean-free) -> delta + t - <t> with t the network's source
+// prediction; the original delta is copied to `save` first.
+int unet_learned_source(const float *params, double *delta_packed, double *save, int ng, const pm_eft_params &p,
+                        void *ws, size_t ws_bytes, hipStream_t st);
+double *unet_save_area(void *ws, int ng);
+
 // ---- particle kernels (pm_kernels.hip) -----------------------------------
 void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc,
                           hipStream_t st);

@@ -13,8 +13,8 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
                   const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
                   bool relu, hipStream_t st);
 void launch_conv3_wgrad(const uint16_t *x, int x_stride, int x_off, int cin, const uint16_t *dy, int dy_stride,
-                        int dy_off, int cout, float *dw, int n, hipStream_t st);
-void launch_bias_grad(const uint16_t *dy, int stride, int off, int cout, unsigned nvox, float *db, hipStream_t st);
+                        int dy_off, int cout, float *dw, float *db, float *part, int n, hipStream_t st);
+size_t wgrad_partial_floats(int cin, int cout);
 void launch_relu_bwd(uint16_t *dy, int dstride, int doff, const uint16_t *y, int ystride, int yoff, int C,
                      unsigned nvox, hipStream_t st);
 void launch_pool(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nc,
@@ -25,20 +25,21 @@ void launch_up(const uint16_t *in, int istride, int ioff, uint16_t *out, int ost
                hipStream_t st);
 void launch_up_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nc,
                    hipStream_t st);
-void launch_lnrho_stats(const double *rho, unsigned long long n, ReduceSlot rs, hipStream_t st);
-void launch_unet_input(const double *rho, unsigned nvox, const double *stats, float ab0, float am0, float a,
+void launch_feature_stats(const double *delta_packed, unsigned long long n3, ReduceSlot rs, hipStream_t st);
+void launch_unet_input(const double *delta_packed, int n, const double *stats, float ab0, float am0, float a,
                        uint16_t *x0, hipStream_t st);
+void launch_source_target(const double *chi, const double *delta_packed, int n, double inv_scale, float *t,
+                          hipStream_t st);
+void launch_add_source(const float *yhat, int n, double *delta_packed, ReduceSlot rs, hipStream_t st);
 void launch_head(const uint16_t *b5, const float *hw, const float *hb, unsigned nvox, float *yhat, hipStream_t st);
 void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5, const float *hw, unsigned nvox,
                           uint16_t *db5, float *ghw, float *ghb, float *loss, hipStream_t st);
 void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
                       hipStream_t st);
 void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
-                 float c1, float c2, hipStream_t st);
+                 float c1, float c2, const double *gsq, float clip, hipStream_t st);
+void launch_sumsq(const float *g, long long n, ReduceSlot rs, hipStream_t st);
 void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st);
-void launch_yhat_to_chi(const float *yhat, unsigned n, double scale, void *chi, pm_dtype dt, ReduceSlot rs,
-                        hipStream_t st);
-
 namespace {
 
 struct ConvSpec {
@@ -84,7 +85,7 @@ struct NetPlan {
     size_t red_partials = 0, red_out = 0;
     size_t wf[10] = {}, wd[10] = {};
     size_t act[NT] = {}, grad[NT] = {};
-    size_t yhat = 0, target = 0, pgrad = 0, loss = 0;
+    size_t delta = 0, yhat = 0, target = 0, pgrad = 0, loss = 0, wg_part = 0;
 };
 
 size_t take(size_t &cur, size_t bytes)
@@ -118,11 +119,18 @@ bool net_plan(NetPlan &P, int n, bool training)
             P.grad[t] = take(c, sz);
     }
     const size_t n3 = (size_t)n * n * n;
+    P.delta = take(c, sizeof(double) * n3);
     P.yhat = take(c, sizeof(float) * n3);
     if (training) {
         P.target = take(c, sizeof(float) * n3);
         P.pgrad = take(c, sizeof(float) * param_layout().total);
         P.loss = take(c, 256);
+        size_t wmax = 0;
+        for (int l = 0; l < 10; l++) {
+            const size_t f = wgrad_partial_floats(kConv[l].cin, kConv[l].cout);
+            wmax = wmax > f ? wmax : f;
+        }
+        P.wg_part = take(c, sizeof(float) * wmax);
     }
     P.total = c + 256;
     return true;
@@ -158,12 +166,13 @@ void conv_fwd(Net &N, const float *params, int l, int ti, int ioff, int to, int 
                  false, true, N.st);
 }
 
-void forward(Net &N, const float *params, const double *rho, const pm_eft_params &p)
+// delta: packed, mean-free density contrast
+void forward(Net &N, const float *params, const double *delta, const pm_eft_params &p)
 {
     const int n = N.P.n;
     const unsigned nv = (unsigned)n * n * n;
-    launch_lnrho_stats(rho, nv, N.rs, N.st);
-    launch_unet_input(rho, nv, N.rs.out, (float)p.alpha_b0, (float)p.alpha_m0, (float)p.a, N.act(X0), N.st);
+    launch_feature_stats(delta, nv, N.rs, N.st);
+    launch_unet_input(delta, n, N.rs.out, (float)p.alpha_b0, (float)p.alpha_m0, (float)p.a, N.act(X0), N.st);
     conv_fwd(N, params, 0, X0, 0, A1, 0);
     conv_fwd(N, params, 1, A1, 0, C1, 32);  // skip 1 -> C1[32:48]
     launch_pool(N.act(C1), 48, 32, N.act(P1), 16, 0, 16, n / 2, N.st);
@@ -190,8 +199,7 @@ void conv_bwd(Net &N, int l, int ti, int ioff, int tg, int goff, int gi, int gio
     const ParamLayout L = param_layout();
     float *pg = (float *)(N.ws + N.P.pgrad);
     launch_conv3_wgrad(N.act(ti), kTChan[ti], ioff, kConv[l].cin, N.grad(tg), kTChan[tg], goff, kConv[l].cout,
-                       pg + L.w[l], N.dim(tg), N.st);
-    launch_bias_grad(N.grad(tg), kTChan[tg], goff, kConv[l].cout, N.nvox(tg), pg + L.b[l], N.st);
+                       pg + L.w[l], pg + L.b[l], (float *)(N.ws + N.P.wg_part), N.dim(tg), N.st);
     if (gi >= 0)
         launch_conv3(N.grad(tg), kTChan[tg], goff, pad16(kConv[l].cout), (const uint16_t *)(N.ws + N.P.wd[l]),
                      pad16(kConv[l].cin), nullptr, kConv[l].cin, N.grad(gi), kTChan[gi], gioff, false, N.dim(gi),
@@ -254,14 +262,7 @@ int setup(Net &N, int n, bool training, void *ws, size_t ws_bytes, pm_stream_t s
     return PM_OK;
 }
 
-// target yhat = chi / (h^2 s mu_chi): the solution in normalised units
-__global__ void k_chi_to_target(const double *__restrict__ chi, unsigned n, double inv_scale, float *__restrict__ y)
-{
-    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256)
-        y[v] = (float)(chi[v] * inv_scale);
-}
-
-double chi_scale(int n, const pm_eft_params &p)
+double source_scale(int n, const pm_eft_params &p)
 {
     pm_eft_coeffs c;
     pm_eft_coefficients(&p, &c);
@@ -269,7 +270,50 @@ double chi_scale(int n, const pm_eft_params &p)
     return h * h * c.s * c.mu_chi;
 }
 
+// natural rho -> packed mean-free delta in the workspace
+double *prepare_input(Net &N, const double *rho)
+{
+    const int n = N.P.n;
+    const long long n3 = (long long)n * n * n;
+    double *d = (double *)(N.ws + N.P.delta);
+    launch_natural_to_packed(rho, PM_F64, d, n, 1.0, 0.0, N.st);
+    launch_field_sum(d, n3, N.rs, N.st);
+    launch_subtract_mean(d, n3, N.rs.out, N.st);
+    return d;
+}
+
 }  // namespace
+}  // namespace pmeft
+
+namespace pmeft {
+
+// The learned source for the solver: save the packed delta into `save`
+// (ng^3 doubles) and replace delta by delta + t - <t> (t from the network).
+int unet_learned_source(const float *params, double *delta_packed, double *save, int ng, const pm_eft_params &p,
+                        void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Net N;
+    int e = setup(N, ng, false, ws, ws_bytes, st);
+    if (e)
+        return e;
+    const size_t n3 = (size_t)ng * ng * ng;
+    if (hipMemcpyAsync(save, delta_packed, sizeof(double) * n3, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return PM_EHIP;
+    pack_all(N, params);
+    forward(N, params, delta_packed, p);
+    launch_add_source((const float *)(N.ws + N.P.yhat), ng, delta_packed, N.rs, st);
+    return launched();
+}
+
+// the learned-source workspace's save area (ng^3 doubles)
+double *unet_save_area(void *ws, int ng)
+{
+    NetPlan P;
+    if (!net_plan(P, ng, false))
+        return nullptr;
+    return (double *)((char *)ws + P.delta);
+}
+
 }  // namespace pmeft
 
 using namespace pmeft;
@@ -285,59 +329,63 @@ size_t ws_unet_workspace_bytes(int ng, int training)
 }
 
 int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p, float *yhat_out,
-                    void *chi_out, pm_dtype dtype, void *ws, size_t ws_bytes, pm_stream_t stream)
+                    void *ws, size_t ws_bytes, pm_stream_t stream)
 {
-    if (!params || !rho || !p || (dtype != PM_F32 && dtype != PM_F64))
+    if (!params || !rho || !p || !yhat_out)
         return PM_EINVAL;
     Net N;
     int e = setup(N, ng, false, ws, ws_bytes, stream);
     if (e)
         return e;
+    const double *d = prepare_input(N, rho);
     pack_all(N, params);
-    forward(N, params, rho, *p);
+    forward(N, params, d, *p);
     const unsigned nv = (unsigned)ng * ng * ng;
-    const float *yh = (const float *)(N.ws + N.P.yhat);
-    if (yhat_out && hipMemcpyAsync(yhat_out, yh, sizeof(float) * nv, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
+    if (hipMemcpyAsync(yhat_out, N.ws + N.P.yhat, sizeof(float) * nv, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
         return PM_EHIP;
-    if (chi_out)
-        launch_yhat_to_chi(yh, nv, chi_scale(ng, *p), chi_out, dtype, N.rs, N.st);
     return launched();
 }
 
-int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, const double *rho,
-                       const double *chi_target, int ng, const pm_eft_params *p, float *grad_out, double *loss,
-                       void *ws, size_t ws_bytes, pm_stream_t stream)
+int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, double grad_clip,
+                       const double *rho, const double *chi_target, int ng, const pm_eft_params *p, float *grad_out,
+                       double *loss, double *grad_norm, void *ws, size_t ws_bytes, pm_stream_t stream)
 {
-    if (!params || !rho || !chi_target || !p || (lr > 0.0 && (!adam_m || !adam_v || step < 1)))
+    if (!params || !rho || !chi_target || !p || (lr > 0.0 && (!adam_m || !adam_v || step < 1)) || !(grad_clip >= 0.0))
         return PM_EINVAL;
     Net N;
     int e = setup(N, ng, true, ws, ws_bytes, stream);
     if (e)
         return e;
-    const unsigned nv = (unsigned)ng * ng * ng;
-    const double sc = chi_scale(ng, *p);
+    const double sc = source_scale(ng, *p);
     if (!(sc != 0.0) || !isfinite(sc))
         return PM_EINVAL;
-    hipLaunchKernelGGL(k_chi_to_target, dim3(1024), dim3(256), 0, N.st, chi_target, nv, 1.0 / sc,
-                       (float *)(N.ws + N.P.target));
+    const double *d = prepare_input(N, rho);
+    launch_source_target(chi_target, d, ng, 1.0 / sc, (float *)(N.ws + N.P.target), N.st);
     pack_all(N, params);
-    forward(N, params, rho, *p);
+    forward(N, params, d, *p);
     backward(N, params);
     const long long np = param_layout().total;
     const float *pg = (const float *)(N.ws + N.P.pgrad);
     if (grad_out && hipMemcpyAsync(grad_out, pg, sizeof(float) * np, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
         return PM_EHIP;
+    launch_sumsq(pg, np, N.rs, N.st);
     if (lr > 0.0) {
         const float b1 = 0.9f, b2 = 0.999f;
         const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-        launch_adam(params, pg, adam_m, adam_v, np, (float)lr, b1, b2, 1e-8f, c1, c2, N.st);
+        launch_adam(params, pg, adam_m, adam_v, np, (float)lr, b1, b2, 1e-8f, c1, c2, N.rs.out, (float)grad_clip,
+                    N.st);
     }
-    if (loss) {
+    if (loss || grad_norm) {
         float l = 0.f;
+        double g2 = 0.0;
         if (hipMemcpyAsync(&l, N.ws + N.P.loss, sizeof(float), hipMemcpyDeviceToHost, N.st) != hipSuccess ||
+            hipMemcpyAsync(&g2, N.rs.out, sizeof(double), hipMemcpyDeviceToHost, N.st) != hipSuccess ||
             hipStreamSynchronize(N.st) != hipSuccess)
             return PM_EHIP;
-        *loss = l;
+        if (loss)
+            *loss = l;
+        if (grad_norm)
+            *grad_norm = sqrt(g2);
     }
     return launched();
 }
@@ -345,14 +393,17 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
              const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream)
 {
-    if (mode < 0 || mode > 2 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws)
+    if (mode < 0 || mode > 2 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws ||
+        ((uintptr_t)ws & 255))
         return PM_EINVAL;
-    const size_t need = sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout) * 2 + 512;
+    const size_t wbytes = ((sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout)) + 255) & ~(size_t)255;
+    const size_t need = 2 * wbytes + sizeof(float) * wgrad_partial_floats(cin, cout);
     if (ws_bytes < need)
         return PM_ENOMEM;
     hipStream_t st = (hipStream_t)stream;
     uint16_t *wf = (uint16_t *)ws;
-    uint16_t *wd = (uint16_t *)((char *)ws + (((sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout)) + 255) & ~(size_t)255));
+    uint16_t *wd = (uint16_t *)((char *)ws + wbytes);
+    float *part = (float *)((char *)ws + 2 * wbytes);
     launch_pack_conv(w, cin, cout, pad16(cin), pad16(cout), wf, wd, st);
     if (mode == 0) {
         if (!x_bf16 || cin % 16)
@@ -367,9 +418,8 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
     } else {
         if (!x_bf16 || !dy_bf16)
             return PM_EINVAL;
-        launch_zero(out, sizeof(float) * 27 * cin * cout, st);
-        launch_conv3_wgrad((const uint16_t *)x_bf16, cin, 0, cin, (const uint16_t *)dy_bf16, cout, 0, cout, out, n,
-                           st);
+        launch_conv3_wgrad((const uint16_t *)x_bf16, cin, 0, cin, (const uint16_t *)dy_bf16, cout, 0, cout, out,
+                           nullptr, part, n, st);
     }
     return launched();
 }

@@ -52,7 +52,12 @@ __device__ __forceinline__ unsigned xcd_block(unsigned nb_real)
 // out[v][out_off + o] = act(bias[o] + sum_t sum_c in[v + s d_t][in_off + c] * Wp[t][o][c])
 // with s = +1 (forward) or -1 (input gradient, Wp packed as the transpose).
 // cin_pad, cout_pad: multiples of 16; only o < cout is written.
-template <int COT>
+// A wave computes MT*16 consecutive voxels along k of one (i, j) row times
+// COT*16 output channels.  For each of the 9 (di, dj) neighbour rows and
+// 16-channel input slice it first issues all 3*MT activation and 3*COT weight
+// fragment loads (the three dk taps), then the 3*MT*COT MFMAs, so the loads
+// of a row overlap instead of serialising behind each MFMA.
+template <int MT, int COT>
 __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, int in_stride, int in_off, int cin_pad,
                                                const uint16_t *__restrict__ wp, int cout_pad,
                                                const float *__restrict__ bias, int cout, void *__restrict__ out,
@@ -63,34 +68,49 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, 
     const unsigned seg = xcd_block(0) * 4 + wave;
     if (seg >= nseg)
         return;
-    const int segs_row = n / 16;
+    const int segs_row = n / (16 * MT);
     const unsigned row = seg / segs_row;
-    const int k0 = (seg - row * segs_row) * 16;
-    const int i = row / n, j = row - (row / n) * n;
+    const int k0 = (int)(seg - row * segs_row) * 16 * MT;
+    const int i = (int)(row / n), j = (int)(row - (row / n) * n);
     const int r = lane & 15, q = lane >> 4;
     const int co_base = blockIdx.y * COT * 16;
-    f32x4 acc[COT];
+    const int sgn = flip ? -1 : 1;
+    f32x4 acc[MT][COT];
 #pragma unroll
-    for (int t = 0; t < COT; t++)
-        acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; tap++) {
-        int di, dj, dk;
-        tap_offsets(tap, di, dj, dk);
-        if (flip) {
-            di = -di;
-            dj = -dj;
-            dk = -dk;
-        }
-        const int ii = wrapi(i + di, n), jj = wrapi(j + dj, n), kk = wrapi(k0 + r + dk, n);
-        const uint16_t *ap = in + ((size_t)((ii * n + jj) * n + kk)) * in_stride + in_off + 4 * q;
-        const uint16_t *bp = wp + ((size_t)tap * cout_pad + co_base + r) * cin_pad + 4 * q;
+    for (int m = 0; m < MT; m++)
+#pragma unroll
+        for (int t = 0; t < COT; t++)
+            acc[m][t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    // voxel offsets along k of this lane's rows for dk = -1, 0, +1 (input side)
+    int kk[3][MT];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+#pragma unroll
+        for (int m = 0; m < MT; m++)
+            kk[d][m] = wrapi(k0 + 16 * m + r + sgn * (d - 1), n);
+    for (int dij = 0; dij < 9; dij++) {
+        const int di = sgn * (dij / 3 - 1), dj = sgn * (dij % 3 - 1);
+        const int ii = wrapi(i + di, n), jj = wrapi(j + dj, n);
+        const uint16_t *rowp = in + (size_t)((ii * n + jj) * n) * in_stride + in_off + 4 * q;
+        const uint16_t *wrow = wp + ((size_t)(dij * 3) * cout_pad + co_base + r) * cin_pad + 4 * q;
         for (int c0 = 0; c0 < cin_pad; c0 += 16) {
-            const bf16x4 a = *(const bf16x4 *)(ap + c0);
+            bf16x4 a[3][MT], b[3][COT];
 #pragma unroll
-            for (int t = 0; t < COT; t++) {
-                const bf16x4 b = *(const bf16x4 *)(bp + (size_t)t * 16 * cin_pad + c0);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            for (int d = 0; d < 3; d++) {
+#pragma unroll
+                for (int m = 0; m < MT; m++)
+                    a[d][m] = *(const bf16x4 *)(rowp + (size_t)kk[d][m] * in_stride + c0);
+#pragma unroll
+                for (int t = 0; t < COT; t++)
+                    b[d][t] = *(const bf16x4 *)(wrow + ((size_t)d * cout_pad + t * 16) * cin_pad + c0);
             }
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+#pragma unroll
+                for (int m = 0; m < MT; m++)
+#pragma unroll
+                    for (int t = 0; t < COT; t++)
+                        acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[d][m], b[d][t], acc[m][t], 0, 0, 0);
         }
     }
     const size_t vbase = (size_t)((i * n + j) * n + k0);
@@ -101,32 +121,35 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, 
             continue;
         const float bo = bias ? bias[o] : 0.f;
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            float v = acc[t][e] + bo;
-            if (relu)
-                v = fmaxf(v, 0.f);
-            const size_t idx = (vbase + 4 * q + e) * out_stride + out_off + o;
-            if (out_f32)
-                ((float *)out)[idx] = v;
-            else
-                ((uint16_t *)out)[idx] = f2bf(v);
-        }
+        for (int m = 0; m < MT; m++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                float v = acc[m][t][e] + bo;
+                if (relu)
+                    v = fmaxf(v, 0.f);
+                const size_t idx = (vbase + 16 * m + 4 * q + e) * out_stride + out_off + o;
+                if (out_f32)
+                    ((float *)out)[idx] = v;
+                else
+                    ((uint16_t *)out)[idx] = f2bf(v);
+            }
     }
 }
 
-void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
-                  const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
-                  bool relu, hipStream_t st)
+template <int MT>
+static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp,
+                            int cout_pad, const float *bias, int cout, void *out, int out_stride, int out_off,
+                            bool out_f32, int n, bool flip, bool relu, hipStream_t st)
 {
-    const unsigned nseg = (unsigned)n * n * (n / 16);
+    const unsigned nseg = (unsigned)n * n * (n / (16 * MT));
     const unsigned nbx = xcd_blocks((nseg + 3) / 4);
     // output tiles per wave: the largest of 4, 3, 2, 1 that divides the tile count
     const int tiles = cout_pad / 16;
     const int cot = tiles % 4 == 0 ? 4 : (tiles % 3 == 0 ? 3 : (tiles % 2 == 0 ? 2 : 1));
     dim3 grid(nbx, cout_pad / (cot * 16));
 #define PM_CONV(C)                                                                                                     \
-    hipLaunchKernelGGL((k_conv3<C>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout,  \
-                       out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, nseg)
+    hipLaunchKernelGGL((k_conv3<MT, C>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad, bias,   \
+                       cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, nseg)
     if (cot == 4)
         PM_CONV(4);
     else if (cot == 3)
@@ -138,88 +161,149 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
 #undef PM_CONV
 }
 
-// dW[t][c][o] += sum_v x[v + d_t][x_off + c] * dy[v][dy_off + o] over a chunk
-// of voxels per block, accumulated with FP32 atomics into dw (which the caller
-// zeroes).  grid: x = voxel chunk, y = tap, z = (c tile, o tile).
-constexpr int kWgChunk = 8192;
+void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
+                  const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
+                  bool relu, hipStream_t st)
+{
+    if (n % 64 == 0)
+        launch_conv3_mt<4>(in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout, out, out_stride, out_off,
+                           out_f32, n, flip, relu, st);
+    else if (n % 32 == 0)
+        launch_conv3_mt<2>(in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout, out, out_stride, out_off,
+                           out_f32, n, flip, relu, st);
+    else
+        launch_conv3_mt<1>(in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout, out, out_stride, out_off,
+                           out_f32, n, flip, relu, st);
+}
+
+// Weight and bias gradients:
+//   dW[t][c][o] = sum_v x[v + d_t][x_off + c] dy[v][dy_off + o],  db[o] = sum_v dy[v][dy_off + o].
+// GEMMs with the voxels as the reduction index, on the MFMA unit with
+// A[m = c][k = voxel] and B[k = voxel][n = o].  The voxels are walked in
+// groups of 16 consecutive voxels along k; for each group the dy fragment is
+// loaded once for all 27 taps, and the six x values a lane needs along k
+// (offsets -1 .. 4 of its four voxels) once per (di, dj) row for the three
+// dk taps.  grid: x = voxel chunks (kWgBlocks at most), y = (c tile, o tile).
+// Every block writes its partial sums; k_wgrad_reduce adds them in block
+// order, so the gradients do not depend on scheduling.
+constexpr int kWgBlocks = 240;
+
+static inline unsigned wgrad_blocks(int n)
+{
+    const unsigned groups = (unsigned)n * n * (n / 16);
+    const unsigned nb = (groups + 15) / 16;  // at least 4 groups per wave
+    return nb < (unsigned)kWgBlocks ? (nb ? nb : 1) : (unsigned)kWgBlocks;
+}
+
+size_t wgrad_partial_floats(int cin, int cout) { return (size_t)kWgBlocks * (27 * (size_t)cin * cout + cout); }
 
 __global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t *__restrict__ x, int x_stride, int x_off, int cin,
                                                      const uint16_t *__restrict__ dy, int dy_stride, int dy_off,
-                                                     int cout, float *__restrict__ dw, int n)
+                                                     int cout, float *__restrict__ part, int n)
 {
-    __shared__ float red[4][64][4];
+    __shared__ float red[4][9][64][4];
+    __shared__ float bred[4][16];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
-    const int tap = blockIdx.y;
     const int otiles = (cout + 15) / 16;
-    const int ct = blockIdx.z / otiles, ot = blockIdx.z % otiles;
-    const int c = ct * 16 + r, o0 = ot * 16;
-    int di, dj, dk;
-    tap_offsets(tap, di, dj, dk);
-    const unsigned nvox = (unsigned)n * n * n;
-    const unsigned v0 = blockIdx.x * kWgChunk + wave * (kWgChunk / 4);
-    const unsigned v1 = min(nvox, v0 + kWgChunk / 4);
-    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (unsigned vb = v0; vb < v1; vb += 16) {
-        bf16x4 a, b;
+    const int ct = blockIdx.y / otiles, ot = blockIdx.y - (blockIdx.y / otiles) * otiles;
+    const int c = ct * 16 + r, o = ot * 16 + r;
+    const bool cok = c < cin, ook = o < cout;
+    const unsigned ngk = (unsigned)(n / 16);
+    const unsigned G = (unsigned)n * n * ngk;
+    const unsigned g0 = (unsigned)(((unsigned long long)blockIdx.x * G) / gridDim.x);
+    const unsigned g1 = (unsigned)(((unsigned long long)(blockIdx.x + 1) * G) / gridDim.x);
+    f32x4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++)
+        acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (unsigned g = g0 + wave; g < g1; g += 4) {
+        const unsigned row = g / ngk;
+        const int k0 = (int)(g - row * ngk) * 16;
+        const int i = (int)(row / n), j = (int)(row - (row / n) * n);
+        bf16x4 b;
+        const uint16_t *dyp = dy + ((size_t)row * n + k0 + 4 * q) * dy_stride + dy_off + o;
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const unsigned v = vb + 4 * q + e;  // v < v1 since chunks are multiples of 16
-            const int k = v % n, jrow = (v / n) % n, irow = v / (n * n);
-            const int ii = wrapi(irow + di, n), jj = wrapi(jrow + dj, n), kk = wrapi(k + dk, n);
-            const uint16_t xa = c < cin ? x[(size_t)((ii * n + jj) * n + kk) * x_stride + x_off + c] : (uint16_t)0;
-            const int o = o0 + r;
-            const uint16_t yb = o < cout ? dy[(size_t)v * dy_stride + dy_off + o] : (uint16_t)0;
-            a[e] = (short)xa;
-            b[e] = (short)yb;
+            const uint16_t v = ook ? dyp[(size_t)e * dy_stride] : (uint16_t)0;
+            b[e] = (short)v;
+            bsum += bf2f(v);
         }
-        // A[m = c][k = voxel] from lane (m = r, k = 4q + e); B[k = voxel][n = o]
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+#pragma unroll
+        for (int dij = 0; dij < 9; dij++) {
+            const int ii = wrapi(i + dij / 3 - 1, n), jj = wrapi(j + dij % 3 - 1, n);
+            const uint16_t *xr = x + (size_t)((ii * n + jj) * n) * x_stride + x_off + c;
+            short xv[6];
+#pragma unroll
+            for (int t = 0; t < 6; t++) {
+                const int kk = wrapi(k0 + 4 * q + t - 1, n);
+                xv[t] = cok ? (short)xr[(size_t)kk * x_stride] : (short)0;
+            }
+#pragma unroll
+            for (int dk = 0; dk < 3; dk++) {
+                const bf16x4 a = (bf16x4){xv[dk], xv[dk + 1], xv[dk + 2], xv[dk + 3]};
+                acc[dij * 3 + dk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[dij * 3 + dk], 0, 0, 0);
+            }
+        }
     }
+    // block reduction in three rounds of nine taps; lane (r, q) holds
+    // dW[t][ct*16 + 4q + e][ot*16 + r]
+    float *pb = part + (size_t)blockIdx.x * (27 * (size_t)cin * cout + cout);
 #pragma unroll
-    for (int e = 0; e < 4; e++)
-        red[wave][lane][e] = acc[e];
-    __syncthreads();
-    if (wave == 0) {
+    for (int round = 0; round < 3; round++) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const float s = red[0][lane][e] + red[1][lane][e] + red[2][lane][e] + red[3][lane][e];
-            const int cc = ct * 16 + 4 * q + e, oo = o0 + r;
+        for (int tt = 0; tt < 9; tt++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                red[wave][tt][lane][e] = acc[round * 9 + tt][e];
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 9 * 64 * 4; idx += 256) {
+            const int e = idx & 3, ln = (idx >> 2) & 63, tt = idx >> 8;
+            const float v = red[0][tt][ln][e] + red[1][tt][ln][e] + red[2][tt][ln][e] + red[3][tt][ln][e];
+            const int cc = ct * 16 + 4 * (ln >> 4) + e, oo = ot * 16 + (ln & 15);
             if (cc < cin && oo < cout)
-                atomicAdd(&dw[((size_t)tap * cin + cc) * cout + oo], s);
+                pb[((size_t)(round * 9 + tt) * cin + cc) * cout + oo] = v;
         }
+        __syncthreads();
+    }
+    // bias: lanes r, r+16, r+32, r+48 hold partial sums of column o
+    bsum += __shfl_down(bsum, 32, 64);
+    bsum += __shfl_down(bsum, 16, 64);
+    if (lane < 16)
+        bred[wave][lane] = bsum;
+    __syncthreads();
+    if (ct == 0 && threadIdx.x < 16 && ot * 16 + (int)threadIdx.x < cout)
+        pb[27 * (size_t)cin * cout + ot * 16 + threadIdx.x] =
+            bred[0][threadIdx.x] + bred[1][threadIdx.x] + bred[2][threadIdx.x] + bred[3][threadIdx.x];
+}
+
+// dw[e] = sum_b part[b][e] (e over 27 cin cout), db[o] = sum_b part[b][27 cin cout + o]
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ part, unsigned nb, int cin, int cout,
+                                                      float *__restrict__ dw, float *__restrict__ db)
+{
+    const size_t nw = 27 * (size_t)cin * cout, stride = nw + cout;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < stride; e += (size_t)gridDim.x * 256) {
+        float s = 0.f;
+        for (unsigned b = 0; b < nb; b++)
+            s += part[(size_t)b * stride + e];
+        if (e < nw)
+            dw[e] = s;
+        else if (db)
+            db[e - nw] = s;
     }
 }
 
 void launch_conv3_wgrad(const uint16_t *x, int x_stride, int x_off, int cin, const uint16_t *dy, int dy_stride,
-                        int dy_off, int cout, float *dw, int n, hipStream_t st)
+                        int dy_off, int cout, float *dw, float *db, float *part, int n, hipStream_t st)
 {
-    const unsigned nvox = (unsigned)n * n * n;
-    dim3 grid((nvox + kWgChunk - 1) / kWgChunk, 27, ((cin + 15) / 16) * ((cout + 15) / 16));
-    hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(256), 0, st, x, x_stride, x_off, cin, dy, dy_stride, dy_off, cout, dw,
-                       n);
-}
-
-// db[o] += sum_v dy[v][dy_off + o]
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dy, int stride, int off, int cout,
-                                                   unsigned nvox, float *__restrict__ db)
-{
-    const int o = threadIdx.x % 64;
-    const int part = threadIdx.x / 64;
-    if (o >= cout)
-        return;
-    float s = 0.f;
-    for (unsigned v = blockIdx.x * 4 + part; v < nvox; v += gridDim.x * 4)
-        s += bf2f(dy[(size_t)v * stride + off + o]);
-    atomicAdd(&db[o], s);
-}
-
-void launch_bias_grad(const uint16_t *dy, int stride, int off, int cout, unsigned nvox, float *db, hipStream_t st)
-{
-    unsigned nb = (nvox + 4095) / 4096;
-    if (nb > 1024)
-        nb = 1024;
-    hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, dy, stride, off, cout, nvox, db);
+    const unsigned nb = wgrad_blocks(n);
+    dim3 grid(nb, ((cin + 15) / 16) * ((cout + 15) / 16));
+    hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(256), 0, st, x, x_stride, x_off, cin, dy, dy_stride, dy_off, cout,
+                       part, n);
+    const size_t total = 27 * (size_t)cin * cout + cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nb, cin, cout,
+                       dw, db);
 }
 
 // ---------------------------------------------------------------- elementwise
@@ -334,36 +418,50 @@ void launch_up_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, i
 }
 
 // ---------------------------------------------------------------- input / head
-// partial sums of l = ln(rho + 1e-3) and l^2 (natural-order double rho)
-__global__ __launch_bounds__(kBlock) void k_lnrho_stats(const double *__restrict__ rho, ReduceSlot rs, Span sp)
+// The density contrast comes in the solver's packed red-black layout: voxel
+// (i, j, k) of colour c = (i + j + k) & 1 sits at c * n^3/2 + (i n + j) n/2 + k/2.
+__device__ __forceinline__ unsigned packed_index(unsigned v, int n)
+{
+    const int k = (int)(v % (unsigned)n);
+    const unsigned row = v / (unsigned)n;  // i * n + j
+    const int ij = (int)(row / (unsigned)n) + (int)(row % (unsigned)n);
+    const unsigned half = (unsigned)n * n * (n / 2);
+    return ((ij + k) & 1) * half + row * (unsigned)(n / 2) + (unsigned)(k >> 1);
+}
+
+__device__ __forceinline__ double feature_of(double delta) { return log(fmax(1.0 + delta, 0.0) + 1e-3); }
+
+// partial sums of l = ln(1 + delta + 1e-3) and l^2
+__global__ __launch_bounds__(kBlock) void k_feature_stats(const double *__restrict__ delta, ReduceSlot rs, Span sp)
 {
     double acc[2] = {0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
     {
-        const double l = log(rho[e] + 1e-3);
+        const double l = feature_of(delta[e]);
         acc[0] += l;
         acc[1] += l * l;
     }
     block_partials<2>(acc, rs, sp);
 }
 
-void launch_lnrho_stats(const double *rho, unsigned long long n, ReduceSlot rs, hipStream_t st)
+void launch_feature_stats(const double *delta_packed, unsigned long long n3, ReduceSlot rs, hipStream_t st)
 {
-    const Span sp = make_span(n);
-    hipLaunchKernelGGL(k_lnrho_stats, dim3(sp.nblocks), dim3(kBlock), 0, st, rho, rs, sp);
+    const Span sp = make_span(n3);
+    hipLaunchKernelGGL(k_feature_stats, dim3(sp.nblocks), dim3(kBlock), 0, st, delta_packed, rs, sp);
     launch_finalize(rs, sp, 2, rs.out, st);
 }
 
-// x0[v][0..15] = (standardised ln(rho + 1e-3), alpha_B0, alpha_M0, a, 0 ...)
-__global__ __launch_bounds__(256) void k_unet_input(const double *__restrict__ rho, unsigned nvox,
+// x0[v][0..15] = (standardised l, alpha_B0, alpha_M0, a, 0 ...), natural voxel order
+__global__ __launch_bounds__(256) void k_unet_input(const double *__restrict__ delta, int n,
                                                     const double *__restrict__ stats, float ab0, float am0, float a,
                                                     uint16_t *__restrict__ x0)
 {
+    const unsigned nvox = (unsigned)n * n * n;
     const double mean = stats[0] / nvox;
     const double var = fmax(stats[1] / nvox - mean * mean, 1e-30);
     const double inv = 1.0 / sqrt(var);
     for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
-        const float l = (float)((log(rho[v] + 1e-3) - mean) * inv);
+        const float l = (float)((feature_of(delta[packed_index(v, n)]) - mean) * inv);
         uint16_t *o = x0 + (size_t)v * 16;
         o[0] = f2bf(l);
         o[1] = f2bf(ab0);
@@ -374,10 +472,35 @@ __global__ __launch_bounds__(256) void k_unet_input(const double *__restrict__ r
     }
 }
 
-void launch_unet_input(const double *rho, unsigned nvox, const double *stats, float ab0, float am0, float a,
+void launch_unet_input(const double *delta_packed, int n, const double *stats, float ab0, float am0, float a,
                        uint16_t *x0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_unet_input, dim3(2048), dim3(256), 0, st, rho, nvox, stats, ab0, am0, a, x0);
+    hipLaunchKernelGGL(k_unet_input, dim3(2048), dim3(256), 0, st, delta_packed, n, stats, ab0, am0, a, x0);
+}
+
+// Training target t = lap7(chi) / (h^2 s mu_chi) - delta (natural order out);
+// chi natural FP64, delta packed.
+__global__ __launch_bounds__(256) void k_source_target(const double *__restrict__ chi,
+                                                       const double *__restrict__ delta, int n, double inv_scale,
+                                                       float *__restrict__ t)
+{
+    const unsigned nvox = (unsigned)n * n * n;
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
+        const int k = (int)(v % (unsigned)n), j = (int)((v / n) % (unsigned)n), i = (int)(v / ((unsigned)n * n));
+        const int ip = i + 1 == n ? 0 : i + 1, im = i == 0 ? n - 1 : i - 1;
+        const int jp = j + 1 == n ? 0 : j + 1, jm = j == 0 ? n - 1 : j - 1;
+        const int kp = k + 1 == n ? 0 : k + 1, km = k == 0 ? n - 1 : k - 1;
+        const double lap = chi[((unsigned)ip * n + j) * n + k] + chi[((unsigned)im * n + j) * n + k] +
+                           chi[((unsigned)i * n + jp) * n + k] + chi[((unsigned)i * n + jm) * n + k] +
+                           chi[((unsigned)i * n + j) * n + kp] + chi[((unsigned)i * n + j) * n + km] - 6.0 * chi[v];
+        t[v] = (float)(lap * inv_scale - delta[packed_index(v, n)]);
+    }
+}
+
+void launch_source_target(const double *chi, const double *delta_packed, int n, double inv_scale, float *t,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_source_target, dim3(2048), dim3(256), 0, st, chi, delta_packed, n, inv_scale, t);
 }
 
 // yhat[v] = hb + sum_c hw[c] * b5[v][c]
@@ -478,13 +601,32 @@ void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_p
     hipLaunchKernelGGL(k_pack_conv, dim3(256), dim3(256), 0, st, w, cin, cout, cin_pad, cout_pad, wf, wd);
 }
 
-// Adam (Kingma & Ba) with bias correction on FP32 master weights.
+// sum of squares of the gradient (global-norm clipping)
+__global__ __launch_bounds__(kBlock) void k_sumsq(const float *__restrict__ g, ReduceSlot rs, Span sp)
+{
+    double acc[1] = {0.0};
+    PM_SPAN_LOOP(e, sp)
+    acc[0] += (double)g[e] * (double)g[e];
+    block_partials<1>(acc, rs, sp);
+}
+
+void launch_sumsq(const float *g, long long n, ReduceSlot rs, hipStream_t st)
+{
+    const Span sp = make_span((unsigned long long)n);
+    hipLaunchKernelGGL(k_sumsq, dim3(sp.nblocks), dim3(kBlock), 0, st, g, rs, sp);
+    launch_finalize(rs, sp, 1, rs.out, st);
+}
+
+// Adam (Kingma & Ba) with bias correction on FP32 master weights; the
+// gradient is scaled by min(1, clip / ||g||) when clip > 0 (||g||^2 in gsq).
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                                               float *__restrict__ v, long long n, float lr, float b1, float b2,
-                                              float eps, float c1, float c2)
+                                              float eps, float c1, float c2, const double *__restrict__ gsq, float clip)
 {
+    const double gn = sqrt(gsq[0]);
+    const float scale = (clip > 0.f && gn > (double)clip) ? (float)((double)clip / gn) : 1.f;
     for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
-        const float gg = g[e];
+        const float gg = scale * g[e];
         const float mm = b1 * m[e] + (1.f - b1) * gg;
         const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
         m[e] = mm;
@@ -494,9 +636,9 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float
 }
 
 void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
-                 float c1, float c2, hipStream_t st)
+                 float c1, float c2, const double *gsq, float clip, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2, gsq, clip);
 }
 
 // bf16 <-> f32 helpers for tests and the output path
@@ -511,16 +653,6 @@ void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st)
     hipLaunchKernelGGL(k_f32_to_bf16, dim3(1024), dim3(256), 0, st, s, d, n);
 }
 
-// chi0 (natural, dtype) = scale * (yhat - <yhat>), mean from stats[0] / n
-template <typename T>
-__global__ __launch_bounds__(256) void k_yhat_to_chi(const float *__restrict__ yhat, unsigned n, double scale,
-                                                     const double *__restrict__ stats, T *__restrict__ chi)
-{
-    const double mean = stats[0] / n;
-    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256)
-        chi[v] = (T)(scale * ((double)yhat[v] - mean));
-}
-
 __global__ __launch_bounds__(kBlock) void k_f32_sum(const float *__restrict__ x, ReduceSlot rs, Span sp)
 {
     double acc[1] = {0.0};
@@ -529,18 +661,22 @@ __global__ __launch_bounds__(kBlock) void k_f32_sum(const float *__restrict__ x,
     block_partials<1>(acc, rs, sp);
 }
 
-void launch_yhat_to_chi(const float *yhat, unsigned n, double scale, void *chi, pm_dtype dt, ReduceSlot rs,
-                        hipStream_t st)
+// delta[packed(v)] += yhat[v] - <yhat>: the learned source delta + t
+__global__ __launch_bounds__(256) void k_add_source(const float *__restrict__ yhat, int n,
+                                                    const double *__restrict__ ysum, double *__restrict__ delta)
 {
-    const Span sp = make_span(n);
+    const unsigned nvox = (unsigned)n * n * n;
+    const double mean = ysum[0] / nvox;
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256)
+        delta[packed_index(v, n)] += (double)yhat[v] - mean;
+}
+
+void launch_add_source(const float *yhat, int n, double *delta_packed, ReduceSlot rs, hipStream_t st)
+{
+    const Span sp = make_span((unsigned long long)n * n * n);
     hipLaunchKernelGGL(k_f32_sum, dim3(sp.nblocks), dim3(kBlock), 0, st, yhat, rs, sp);
     launch_finalize(rs, sp, 1, rs.out, st);
-    if (dt == PM_F64)
-        hipLaunchKernelGGL((k_yhat_to_chi<double>), dim3(2048), dim3(256), 0, st, yhat, n, scale,
-                           (const double *)rs.out, (double *)chi);
-    else
-        hipLaunchKernelGGL((k_yhat_to_chi<float>), dim3(2048), dim3(256), 0, st, yhat, n, scale,
-                           (const double *)rs.out, (float *)chi);
+    hipLaunchKernelGGL(k_add_source, dim3(2048), dim3(256), 0, st, yhat, n, (const double *)rs.out, delta_packed);
 }
 
 }  // namespace pmeft

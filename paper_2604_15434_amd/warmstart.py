@@ -1,7 +1,10 @@
 """Learned warm start: the U-Net of the C ABI (ws_* in include/pmeft.h)
-driven from Python.  The network maps the density and (alpha_B0, alpha_M0,
-a) to an initial scalar field; multigrid finishes the solve from it
-(PM_GUESS_GIVEN), so the answer never depends on the network.
+driven from Python.  The network maps the density contrast and (alpha_B0,
+alpha_M0, a) to the nonlinear part t of the scalar field's normalised source
+lap chi / (s mu_chi) = delta + t; a solve with guess "learned" (MgOpts.learned
+= a WarmStart) turns delta + t into its initial field with one linear
+multigrid pass and finishes as usual, so the answer never depends on the
+network.
 
 This module only marshals arguments and keeps the parameter and optimizer
 arrays (torch device tensors); every layer, the loss, the gradients and the
@@ -62,40 +65,51 @@ class WarmStart:
             self._ws[key] = torch.empty(nb, dtype=torch.uint8, device=self.params.device)
         return self._ws[key]
 
-    def predict(self, rho, params, chi_out, yhat_out=None, stream=None):
-        """chi0 of the network for the FP64 density rho (ng^3) into chi_out."""
+    def inference_workspace(self, ng):
+        """Device workspace of the forward pass (also the learned guess's)."""
+        return self._workspace(ng, False)
+
+    def predict(self, rho, params, yhat_out, stream=None):
+        """The network's source prediction t (ng^3 FP32, natural order) for
+        the FP64 density rho."""
         import torch
 
         ng = rho.shape[0]
         assert rho.dtype == torch.float64 and rho.is_contiguous()
-        dt = L.PM_F64 if chi_out.dtype == torch.float64 else L.PM_F32
+        assert yhat_out.dtype == torch.float32 and yhat_out.numel() == ng**3
         ws = self._workspace(ng, False)
         rc = L.lib().ws_unet_forward(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
-                                     int(ng), ctypes.byref(_params(params)),
-                                     ctypes.c_void_p(yhat_out.data_ptr() if yhat_out is not None else 0),
-                                     ctypes.c_void_p(chi_out.data_ptr()), dt, ctypes.c_void_p(ws.data_ptr()),
-                                     ws.numel(), _stream(stream))
+                                     int(ng), ctypes.byref(_params(params)), ctypes.c_void_p(yhat_out.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
         if rc:
             raise PmError(rc, "ws_unet_forward")
-        return chi_out
+        return yhat_out
 
-    def train_step(self, rho, chi_target, params, lr, grad_out=None, stream=None):
-        """One Adam step on one sample (lr = 0: gradients only); returns the loss."""
+    def train_step(self, rho, chi_target, params, lr, grad_clip=0.0, grad_out=None, want_norm=False,
+                   want_loss=True, stream=None):
+        """One Adam step on one sample (lr = 0: gradients only).  Returns the
+        loss, or (loss, gradient norm) with want_norm; with neither wanted the
+        call does not synchronise and returns None."""
         ng = rho.shape[0]
         ws = self._workspace(ng, True)
         if lr > 0:
             self.step += 1
         loss = ctypes.c_double(0.0)
+        gn = ctypes.c_double(0.0)
         rc = L.lib().ws_unet_train_step(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(self.m.data_ptr()),
                                         ctypes.c_void_p(self.v.data_ptr()), max(self.step, 1), float(lr),
-                                        ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(chi_target.data_ptr()),
-                                        int(ng), ctypes.byref(_params(params)),
+                                        float(grad_clip), ctypes.c_void_p(rho.data_ptr()),
+                                        ctypes.c_void_p(chi_target.data_ptr()), int(ng),
+                                        ctypes.byref(_params(params)),
                                         ctypes.c_void_p(grad_out.data_ptr() if grad_out is not None else 0),
-                                        ctypes.byref(loss), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
-                                        _stream(stream))
+                                        ctypes.byref(loss) if want_loss else None,
+                                        ctypes.byref(gn) if want_norm else None,
+                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
         if rc:
             raise PmError(rc, "ws_unet_train_step")
-        return loss.value
+        if want_norm:
+            return loss.value, gn.value
+        return loss.value if want_loss else None
 
     def save(self, path, meta=None):
         flat = self.params.detach().cpu().numpy().astype("<f4")

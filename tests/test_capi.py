@@ -17,7 +17,7 @@ def _declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", src, flags=re.M)
-    return sorted({n for n in names if n.startswith(("pm_", "mg_"))})
+    return sorted({n for n in names if n.startswith(("pm_", "mg_", "ws_"))})
 
 
 @pytest.fixture(scope="module")
@@ -32,6 +32,10 @@ def test_header_symbols_are_exported(lib):
     assert {"pm_deposit", "mg_poisson_solve", "mg_scalar_solve", "pm_force_interp", "pm_step"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
+    from paper_2604_15434_amd import _lib
+
+    # the Python binding declares every entry point of the header
+    assert set(_lib.EXPORTS) == set(names)
 
 
 def test_coefficients_match_oracle():
@@ -66,3 +70,27 @@ def test_grid_levels_and_workspace():
     bany = P.pm_workspace_bytes(64, 64**3, 1, "any")
     assert 0 < b64 < bany
     assert P.pm_strerror(-6) == "workspace too small"
+
+
+def test_launch_shape_table_roundtrip(tmp_path):
+    import paper_2604_15434_amd as P
+
+    assert P.pm_launch_shape(96, 8) == 32  # default
+    P.pm_set_launch_shape(96, 8, 16)
+    P.pm_set_launch_shape(96, 4, 0)
+    assert P.pm_launch_shape(96, 8) == 16 and P.pm_launch_shape(96, 4) == 0
+    path = tmp_path / "tune.txt"
+    P.pm_tune_save(path)
+    P.pm_set_launch_shape(96, 8, 64)
+    P.pm_tune_load(path)
+    assert P.pm_launch_shape(96, 8) == 16 and P.pm_launch_shape(96, 4) == 0
+    with pytest.raises(P.PmError):
+        P.pm_set_launch_shape(96, 2, 16)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("96 3 16\n")
+    with pytest.raises(P.PmError):
+        P.pm_tune_load(bad)
+    with pytest.raises(P.PmError):
+        P.pm_tune_load(tmp_path / "missing.txt")
+    P.pm_set_launch_shape(96, 8, 32)
+    P.pm_set_launch_shape(96, 4, 32)

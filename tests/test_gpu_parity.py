@@ -234,3 +234,102 @@ def test_empty_density_gives_zero_fields(P):
     assert P.mg_poisson_solve(rho, CFG0, P.MgOpts(), psi)["status"] == 0
     assert P.mg_scalar_solve(rho, CFG0, P.MgOpts(), chi)["status"] == 0
     assert float(psi.abs().max()) == 0.0 and float(chi.abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------- batched solves
+def test_batched_equals_single_solves_bitwise(P):
+    """Each problem of a mixed-size batch (32^3 .. 96^3, both precisions of
+    the arrays, several parameter sets) equals its own single solve bit for
+    bit, and the single solves agree with the oracle."""
+    import oracle
+    from workloads import lognormal_density, scan_params
+
+    sizes = [32, 48, 64, 96, 32, 64]
+    prms = scan_params(len(sizes), seed=4, a=1.0)
+    probs = []
+    for k, (n, prm) in enumerate(zip(sizes, prms)):
+        dt = torch.float64 if k % 2 == 0 else torch.float32
+        rho = torch.from_numpy(lognormal_density(n, 500.0 * n / 256, seed=4000 + k)).to("cuda", dt)
+        probs.append(dict(rho=rho, chi=torch.zeros_like(rho), params=prm))
+    opts = P.MgOpts(rel_tol=1e-9, max_vcycles=60, precision="mixed")
+    reps = P.mg_scalar_solve_batched(probs, opts)
+    for k, pr in enumerate(probs):
+        single = torch.zeros_like(pr["chi"])
+        rep = P.mg_scalar_solve(pr["rho"], pr["params"], opts, single)
+        assert torch.equal(single, pr["chi"]), k
+        assert reps[k]["vcycles"] == rep["vcycles"] and reps[k]["rel_residual"] == rep["rel_residual"]
+        assert reps[k]["status"] == 0
+    # the 32^3 FP64 member against the oracle
+    c = oracle.eft_coefficients(**probs[0]["params"])
+    ref, _ = oracle.solve_chi(oracle.density_contrast(probs[0]["rho"].cpu().numpy()), c, 1.0 / 32, tol=1e-12)
+    got = probs[0]["chi"].cpu().numpy()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-7
+
+
+def test_batched_rejects_learned_and_bad_sizes(P):
+    rho = torch.ones((32, 32, 32), dtype=torch.float64, device="cuda")
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
+    import ctypes
+
+    L = P._lib
+    chi = torch.zeros_like(rho)
+    arr = (L.Problem * 1)(L.Problem(rho.data_ptr(), chi.data_ptr(), 32, L.PM_F64, P._params(prm)))
+    o = P.MgOpts().c()
+    o.guess = L.PM_GUESS_LEARNED  # rejected before any pointer is used
+    o.learned_params = o.learned_ws = 256
+    ws = torch.empty(P.mg_batched_workspace_bytes([dict(rho=rho, chi=chi, params=prm)]), dtype=torch.uint8,
+                     device="cuda")
+    rc = L.lib().mg_scalar_solve_batched(arr, 1, ctypes.byref(o), None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == L.PM_EINVAL
+    bad = torch.ones((7, 7, 7), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PmError):
+        P.mg_scalar_solve_batched([dict(rho=bad, chi=torch.zeros_like(bad), params=prm)], P.MgOpts())
+
+
+# ---------------------------------------------------------------- launch shapes
+@pytest.mark.parametrize("ng,precision", [(32, "f64"), (64, "f64"), (64, "mixed"), (96, "mixed")])
+def test_block_cycle_matches_per_level_launches(P, ng, precision):
+    """The single-workgroup coarse cycle and the per-level launches converge
+    to the same field (they differ only in the rounding of the lagged means)."""
+    rho = torch.from_numpy(lognormal_density(ng, 500.0 * ng / 256, seed=21)).cuda()
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.5, alpha_m0=0.05, a=1.0)
+    word = 4 if precision == "mixed" else 8
+    opts = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision=precision)
+    out = {}
+    try:
+        for n in (0, 16, 32):
+            P.pm_set_launch_shape(ng, word, n)
+            if precision == "mixed":
+                P.pm_set_launch_shape(ng, 8, n)
+            chi = torch.zeros_like(rho)
+            rep = P.mg_scalar_solve(rho, prm, opts, chi)
+            assert rep["status"] == 0, (n, rep["rel_residual"])
+            out[n] = (chi, rep)
+    finally:
+        P.pm_set_launch_shape(ng, word, 32)
+        P.pm_set_launch_shape(ng, 8, 32)
+    ref = out[0][0]
+    for n in (16, 32):
+        err = float((out[n][0] - ref).norm() / ref.norm())
+        assert err < 1e-9, (n, err)
+        assert abs(out[n][1]["vcycles"] - out[0][1]["vcycles"]) <= 2
+    # Poisson through the same machinery
+    psi0, psi1 = torch.zeros_like(rho), torch.zeros_like(rho)
+    P.pm_set_launch_shape(ng, word, 0)
+    P.mg_poisson_solve(rho, prm, opts, psi0)
+    P.pm_set_launch_shape(ng, word, 32)
+    P.mg_poisson_solve(rho, prm, opts, psi1)
+    assert float((psi1 - psi0).norm() / psi0.norm()) < 1e-9
+
+
+def test_autotune_picks_a_candidate(P):
+    ng = 64
+    n = P.pm_autotune(ng, "mixed")
+    assert n in (0, 8, 16, 32)
+    rho = torch.from_numpy(lognormal_density(ng, 125.0, seed=22)).cuda()
+    chi = torch.zeros_like(rho)
+    rep = P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.3, alpha_m0=0.0, a=1.0),
+                            P.MgOpts(rel_tol=1e-9, precision="mixed"), chi)
+    assert rep["status"] == 0
+    P.pm_set_launch_shape(ng, 4, 32)

@@ -42,7 +42,8 @@ def _conv(P, mode, n, cin, cout, x=None, dy=None, w=None, b=None):
     L = P._lib
     out_n = {0: n**3 * cout, 1: n**3 * cin, 2: 27 * cin * cout}[mode]
     out = torch.zeros(out_n, dtype=torch.float32, device="cuda")
-    wsz = 2 * 27 * ((cin + 15) // 16 * 16) * ((cout + 15) // 16 * 16) * 2 + 4096
+    wb = (54 * ((cin + 15) // 16 * 16) * ((cout + 15) // 16 * 16) + 255) // 256 * 256
+    wsz = 2 * wb + 4 * 240 * (27 * cin * cout + cout)
     ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
     wd = torch.from_numpy(w.astype(np.float32)).cuda()
     bd = torch.from_numpy(b.astype(np.float32)).cuda() if b is not None else None
@@ -55,7 +56,7 @@ def _conv(P, mode, n, cin, cout, x=None, dy=None, w=None, b=None):
     return out.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (32, 96, 32), (16, 32, 64), (16, 16, 48), (16, 32, 96)])
+@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (32, 96, 32), (16, 32, 64), (16, 16, 48), (16, 32, 96), (64, 16, 16), (64, 48, 16), (64, 32, 64)])
 def test_conv_forward_matches_reference(P, n, cin, cout):
     rng = np.random.default_rng(cin + cout)
     x = rng.standard_normal((n, n, n, cin))
@@ -66,7 +67,7 @@ def test_conv_forward_matches_reference(P, n, cin, cout):
     assert rel(got, ref) < 1e-5
 
 
-@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (16, 32, 64), (16, 4, 16)])
+@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (16, 32, 64), (16, 4, 16), (32, 96, 32), (64, 16, 16)])
 def test_conv_input_and_weight_gradients(P, n, cin, cout):
     rng = np.random.default_rng(7 * cin + cout)
     x = rng.standard_normal((n, n, n, cin))
@@ -79,23 +80,13 @@ def test_conv_input_and_weight_gradients(P, n, cin, cout):
         assert rel(dx, dx_ref) < 1e-5
     dw = _conv(P, 2, n, cin, cout, x=x, dy=dy, w=w).reshape(27, cin, cout)
     assert rel(dw, dw_ref) < 1e-5
+    # fixed-order reduction: a second run is bitwise identical
+    dw2 = _conv(P, 2, n, cin, cout, x=x, dy=dy, w=w).reshape(27, cin, cout)
+    assert np.array_equal(dw, dw2)
 
 
-def test_network_forward_and_gradients_track_reference(P):
-    from paper_2604_15434_amd.warmstart import WarmStart
-
-    n = 64
-    rng = np.random.default_rng(11)
-    from workloads import lognormal_density
-
-    rho = lognormal_density(n, 125.0, seed=5)
-    prm = dict(omega_m0=0.3071, alpha_b0=-0.5, alpha_m0=0.1, a=0.8)
-    net = WarmStart(seed=3)
-    flat = net.params.cpu().numpy().astype(np.float64)
-    # biases non-zero so that every bias gradient is exercised
-    flat = flat + 0.0
-    p = {}
-    o = 0
+def _ref_params(flat):
+    p, o = {}, 0
     for (name, ci, co) in U.LAYERS:
         p[name + ".w"] = flat[o:o + 27 * ci * co].reshape(27, ci, co)
         o += 27 * ci * co
@@ -103,26 +94,40 @@ def test_network_forward_and_gradients_track_reference(P):
         o += co
     p["head.w"] = flat[o:o + 16]
     p["head.b"] = flat[o + 16:o + 17]
+    return p
+
+
+def test_network_forward_and_gradients_track_reference(P):
+    """Whole network on a 64^3 lognormal density: BF16 activations between
+    layers, so the prediction is compared at 3e-2 relative and the gradient
+    of every parameter tensor by its direction (cosine > 0.98)."""
+    import oracle
+    from paper_2604_15434_amd.warmstart import WarmStart
+    from workloads import lognormal_density
+
+    n = 64
+    rho = lognormal_density(n, 125.0, seed=5)
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.5, alpha_m0=0.1, a=0.8)
+    net = WarmStart(seed=3)
+    p = _ref_params(net.params.cpu().numpy().astype(np.float64))
     x0 = U.input_features(rho, prm["alpha_b0"], prm["alpha_m0"], prm["a"])
     y_ref, cache = U.forward(p, x0)
     rho_d = torch.from_numpy(rho).cuda()
     yhat = torch.zeros(n**3, dtype=torch.float32, device="cuda")
-    chi0 = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
-    net.predict(rho_d, prm, chi0, yhat_out=yhat)
+    net.predict(rho_d, prm, yhat)
     got = yhat.cpu().numpy().reshape(n, n, n).astype(np.float64)
     assert rel(got, y_ref) < 3e-2
-    # chi0 = h^2 s mu_chi (yhat - mean)
-    import oracle
-
+    # training target from a smooth stand-in field chi
     c = oracle.eft_coefficients(**prm)
-    sc = c["s"] * c["mu_chi"] / n**2
-    np.testing.assert_allclose(chi0.cpu().numpy(), sc * (got - got.mean()), rtol=1e-5, atol=1e-6 * abs(sc))
-    # gradients of the MSE loss against a target field
-    target = rng.standard_normal((n, n, n))
+    rng = np.random.default_rng(11)
+    chi = np.real(np.fft.ifftn(np.fft.fftn(rng.standard_normal((n, n, n))) *
+                               np.exp(-np.add.outer(np.add.outer(np.fft.fftfreq(n)**2, np.fft.fftfreq(n)**2),
+                                                    np.fft.fftfreq(n)**2) * 200.0))) * 1e-3
+    t_ref = U.source_target(chi, rho, c["s"] * c["mu_chi"])
     grads = torch.zeros(net.params.numel(), dtype=torch.float32, device="cuda")
-    loss = net.train_step(rho_d, torch.from_numpy(target * sc).cuda(), prm, 0.0, grad_out=grads)
-    assert loss == pytest.approx(np.mean((y_ref - target) ** 2), rel=3e-2)
-    g_ref = U.backward(p, cache, 2.0 * (y_ref - target) / n**3)
+    loss = net.train_step(rho_d, torch.from_numpy(chi).cuda(), prm, 0.0, grad_out=grads)
+    assert loss == pytest.approx(np.mean((y_ref - t_ref) ** 2), rel=3e-2)
+    g_ref = U.backward(p, cache, 2.0 * (y_ref - t_ref) / n**3)
     g = grads.cpu().numpy().astype(np.float64)
     o = 0
     for (name, ci, co) in U.LAYERS:
@@ -133,9 +138,11 @@ def test_network_forward_and_gradients_track_reference(P):
             assert cos > 0.98, (name + part, cos)
 
 
-def test_warm_start_guess_reaches_the_same_field(P):
-    """Whatever the network predicts, the solve from it converges to the
-    field of the zero-guess solve (the guess changes the cost, not the answer)."""
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_learned_guess_reaches_the_same_field(P, precision):
+    """Whatever the network predicts, the solve from the learned guess
+    converges to the field of the zero-guess solve (the guess changes the
+    cost, not the answer)."""
     from paper_2604_15434_amd.warmstart import WarmStart
     from workloads import lognormal_density
 
@@ -143,11 +150,24 @@ def test_warm_start_guess_reaches_the_same_field(P):
     rho = torch.from_numpy(lognormal_density(n, 125.0, seed=9)).cuda()
     prm = dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.05, a=0.9)
     net = WarmStart(seed=1)
+    tol = 1e-11 if precision == "f64" else 1e-9
     chi_ref = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
-    P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=1e-11, max_vcycles=60, guess="zero"), chi_ref)
+    P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=tol, max_vcycles=60, precision=precision), chi_ref)
     chi = torch.zeros_like(chi_ref)
-    net.predict(rho, prm, chi)
-    rep = P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=1e-11, max_vcycles=60, guess="given"), chi)
-    assert rep["status"] == 0
+    rep = P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=tol, max_vcycles=60, precision=precision, guess="learned",
+                                               learned=net), chi)
+    assert rep["status"] == 0 and rep["rel_residual"] <= tol
     err = float((chi - chi_ref).norm() / chi_ref.norm())
     assert err < 1e-8, err
+
+
+def test_learned_guess_rejects_bad_grid(P):
+    from paper_2604_15434_amd.warmstart import WarmStart
+    from workloads import lognormal_density
+
+    rho = torch.from_numpy(lognormal_density(48, 94.0, seed=9)).cuda()
+    net = WarmStart(seed=1)
+    chi = torch.zeros_like(rho)
+    with pytest.raises(P.PmError):
+        P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=1.0),
+                          P.MgOpts(guess="learned", learned=net), chi)

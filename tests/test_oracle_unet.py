@@ -74,3 +74,35 @@ def test_unet_backward_finite_differences():
             flat[j] = old
             fd = (fp - fm) / (2 * eps)
             assert grads[name].reshape(-1)[j] == pytest.approx(fd, rel=1e-6, abs=1e-7), name
+
+
+def test_source_target_vanishes_for_the_linear_field():
+    """t = lap chi / (s mu_chi) - delta is zero for the screening-off field
+    (exact FFT solve of eq. linearised) and equals the mean-free source shift
+    when the field solves lap chi = s mu_chi (delta + u)."""
+    import oracle
+    from workloads import lognormal_density
+
+    n = 16
+    rho = lognormal_density(n, 31.25, seed=4)
+    delta = oracle.density_contrast(rho)
+    c = oracle.eft_coefficients(0.3071, -0.3, 0.05, 0.7)
+    chi = oracle.solve_chi_linear(delta, c, 1.0 / n)
+    t = U.source_target(chi, rho, c["s"] * c["mu_chi"])
+    assert np.abs(t).max() < 1e-10 * np.abs(delta).max()
+    u = np.random.default_rng(2).standard_normal((n, n, n))
+    u -= u.mean()
+    chi_u = oracle.poisson_fft(c["s"] * c["mu_chi"] * (delta + u), 1.0 / n)
+    np.testing.assert_allclose(U.source_target(chi_u, rho, c["s"] * c["mu_chi"]), u, atol=1e-10)
+
+
+def test_input_features_standardised():
+    from workloads import lognormal_density
+
+    rho = lognormal_density(16, 31.25, seed=4)
+    x = U.input_features(rho, -0.3, 0.1, 0.5)
+    assert abs(x[..., 0].mean()) < 1e-12 and x[..., 0].std() == pytest.approx(1.0, rel=1e-12)
+    assert np.all(x[..., 1] == -0.3) and np.all(x[..., 2] == 0.1) and np.all(x[..., 3] == 0.5)
+    # lognormal densities have mean 1, so the feature is ln(rho + 1e-3) standardised
+    lr = np.log(rho + 1e-3)
+    np.testing.assert_allclose(x[..., 0], (lr - lr.mean()) / lr.std(), atol=1e-9)
