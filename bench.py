@@ -10,9 +10,15 @@ solving the same input from scratch), 5-point gradient, CIC interpolation
 and kick.  Inputs are resident in device memory before the timed region.
 
 Modes
-  plain : FP64 everywhere (particles, fields, V-cycles).
-  fp32  : FP32 particles and fields; mixed-precision solves (FP32 V-cycles
-          on the FP64 defect, FP64 residual/test/coarsest solve).
+  plain   : FP64 everywhere (particles, fields, V-cycles), zero guess.
+  fp32    : FP32 particles and fields; mixed-precision solves (FP32 V-cycles
+            on the FP64 defect, FP64 residual/test/coarsest solve), zero guess.
+  learned : as fp32, with the learned warm start of the scalar field (the
+            trained weights of paper_2604_15434_amd/weights; the network's
+            forward pass and the linear pass on its source are inside the
+            timed step).
+The headline value is the learned mode when the weights exist, else fp32.
+Launch shapes are autotuned for the grid before timing (--no-tune: defaults).
 
 Prints one JSON line (rank 0).  Usage:
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--ng 256]
@@ -41,7 +47,7 @@ def smoother_bytes_per_launch(ng, itemsize, with_tau):
     return per_cell * ng**3 // 2
 
 
-def run_mode(P, torch, mode, pos_np, ng, steps, warmup):
+def run_mode(P, torch, mode, pos_np, ng, steps, warmup, net=None):
     dt = torch.float64 if mode == "plain" else torch.float32
     prec = "f64" if mode == "plain" else "mixed"
     pos0 = torch.from_numpy(pos_np).to(device="cuda", dtype=dt).contiguous()
@@ -51,8 +57,12 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup):
     chi = torch.zeros_like(psi)
     ws = P.Workspace(ng, pos.shape[1], 1 if dt == torch.float64 else 0, "any")
     opts = P.MgOpts(rel_tol=1e-7, max_vcycles=60, n_pre=1, n_post=2, precision=prec, guess="zero")
+    sopts = opts
+    if mode == "learned":
+        sopts = P.MgOpts(rel_tol=1e-7, max_vcycles=60, n_pre=1, n_post=2, precision=prec, guess="learned",
+                         learned=net)
     for _ in range(warmup):
-        P.pm_step(pos, vel, ng, PARAMS, opts, opts, 1e-3, 0.0, psi, chi, ws=ws)
+        P.pm_step(pos, vel, ng, PARAMS, opts, sopts, 1e-3, 0.0, psi, chi, ws=ws)
     torch.cuda.synchronize()
     P.pm_kernel_timing_read()  # clear
     P.pm_kernel_timing_enable(True)
@@ -60,7 +70,7 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        reps.append(P.pm_step(pos, vel, ng, PARAMS, opts, opts, 1e-3, 0.0, psi, chi, ws=ws))
+        reps.append(P.pm_step(pos, vel, ng, PARAMS, opts, sopts, 1e-3, 0.0, psi, chi, ws=ws))
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) * 1e3 / steps
     P.pm_kernel_timing_enable(False)
@@ -134,8 +144,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--ng", type=int, default=256)
-    ap.add_argument("--modes", default="plain,fp32")
+    ap.add_argument("--modes", default="plain,fp32,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2604_15434_amd", "weights", "unet_warmstart.f32"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -147,16 +161,38 @@ def main():
     from workloads import lognormal_particles
 
     ng = args.ng
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] generating {ng}^3 lognormal particles", file=sys.stderr, flush=True)
     pos_np, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=2)
+    modes = args.modes.split(",")
+    net = None
+    if "learned" in modes:
+        if os.path.exists(args.weights) and ng % 64 == 0:
+            from paper_2604_15434_amd.warmstart import WarmStart
+
+            net = WarmStart.load(args.weights)
+        else:
+            print(f"[bench] no learned mode (weights {args.weights} missing or ng % 64 != 0)", file=sys.stderr,
+                  flush=True)
+            modes.remove("learned")
+    shapes = {}
+    if not args.no_tune:
+        for prec in ("f64", "mixed"):
+            shapes[prec] = P.pm_autotune(ng, prec)
+        print(f"[bench] autotuned block-cycle grids: {shapes}", file=sys.stderr, flush=True)
     results = {}
-    for mode in args.modes.split(","):
+    for mode in modes:
         print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-        results[mode] = run_mode(P, torch, mode, pos_np, ng, args.steps, args.warmup)
+        results[mode] = run_mode(P, torch, mode, pos_np, ng, args.steps, args.warmup, net)
         print(f"[bench] mode {mode}: {results[mode]['ms_per_step']:.3f} ms/step, "
               f"V-cycles chi {results[mode]['scalar_vcycles']} psi {results[mode]['poisson_vcycles']}",
               file=sys.stderr, flush=True)
-    head = "fp32" if "fp32" in results and results["fp32"]["converged"] else next(iter(results))
+    head = next((m for m in ("learned", "fp32") if m in results and results[m]["converged"]), next(iter(results)))
     r = results[head]
     line = {
         "metric": "ms per 256^3 PM step (scalar MG to rel. residual 1e-7), plain vs learned+FP32",
@@ -169,11 +205,14 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "plain" else "f32+f64",
+        "dtype": "f64" if head == "plain" else ("f32+f64+bf16" if head == "learned" else "f32+f64"),
         "data": "synthetic",
         "config": {"workload": f"PM step, {ng}^3 grid, {ng}^3 lognormal particles (log-sigma 1.5, seed 2), "
                                f"{500.0 * ng / 256:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7",
-                   "mode": head},
+                   "mode": head, "launch_shapes": shapes},
+        "plain_ms_per_step": round(results["plain"]["ms_per_step"], 3) if "plain" in results else None,
+        "speedup_vs_plain": round(results["plain"]["ms_per_step"] / r["ms_per_step"], 3) if "plain" in results
+        else None,
         "modes": {m: {k: v for k, v in res.items() if k not in ("kernel_timing", "itemsize")}
                   for m, res in results.items()},
         "cells_vcycles_per_s": round(ng**3 * r["scalar_vcycles"] / (r["ms_scalar"] * 1e-3), 1)

@@ -174,6 +174,20 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,
             void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* Particle sort: reorders the particles (pos, and vel and ids when given)
+ * by the cell of their CIC base corner, key (i0 ng + j0) ng + k0 with
+ * i0 = floor(x ng - 1/2) mod ng per axis (Sec. 3.6.2's CIC), so that
+ * neighbouring particles sit together in memory and the deposit's and
+ * interpolation's footprints stay compact.  Stable (equal keys keep their
+ * order) and deterministic; particles with unusable coordinates take the last
+ * cell.  pos, vel: 3 x np SoA of dtype (vel nullable); ids: np int64
+ * (nullable).  Workspace: pm_sort_workspace_bytes(np, dtype), 256-byte
+ * aligned.  The deposit's result does not depend on the order (it is exact
+ * in fixed point); the sort changes cost only. */
+size_t pm_sort_workspace_bytes(long long np, pm_dtype dtype);
+int pm_sort_particles(void *pos, void *vel, long long *ids, long long np, int ng, pm_dtype dtype, void *ws,
+                      size_t ws_bytes, pm_stream_t stream);
+
 /* ---- Batched solves ------------------------------------------------------
  * Many independent scalar-field problems (a parameter scan, several boxes)
  * in one call.  Each problem has its own grid size, precision of its arrays,
@@ -198,21 +212,26 @@ int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const
                             pm_mg_report *reps /* HOST, nullable */, void *ws, size_t ws_bytes, pm_stream_t stream);
 
 /* ---- Launch shapes and the autotuner --------------------------------------
- * The coarse end of every V-cycle (and of full multigrid) runs as one
- * single-workgroup launch from the first level whose grid is at most
- * block_cycle_grid (0: every level launches its own kernels).  The value is
- * kept per (finest grid ng, word size of the hierarchy: 8 for FP64 levels, 4
- * for the FP32 levels of PM_PREC_MIXED); default 32.  It changes the cost of
- * a cycle, and the rounding of the lagged means, not the converged answer.
+ * Two launch choices are kept per (finest grid ng, word size of the
+ * hierarchy: 8 for FP64 levels, 4 for the FP32 levels of PM_PREC_MIXED):
+ *  - block_cycle_grid: the coarse end of every V-cycle (and of full
+ *    multigrid) runs as one single-workgroup launch from the first level
+ *    whose grid is at most this (0: every level launches its own kernels);
+ *  - tiled_smoother (0/1): the large levels (grid >= 64, divisible by 8 and
+ *    by 64 or 128) use the 2.5D-tiled red-black half-sweep, whose cell
+ *    updates equal the untiled ones bit for bit.
+ * Defaults 8 and 1.  They change the cost of a cycle, and the grouping of
+ * the partial sums behind the lagged means, not the converged answer.
  * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a
- * synthetic density for each candidate (off, 8, 16, 32, 64) and keeps the
- * fastest for (ng, precision); its workspace is pm_autotune_workspace_bytes.
- * pm_tune_save / pm_tune_load write and read the table as text lines
- * "ng word_bytes block_cycle_grid".  The table is process-wide. */
+ * synthetic density for every candidate (block_cycle_grid in off, 8, 16, 32,
+ * 64; tiled off, on) and keeps the fastest for (ng, precision); workspace:
+ * pm_autotune_workspace_bytes.  pm_tune_save / pm_tune_load write and read
+ * the table as text lines "ng word_bytes block_cycle_grid tiled_smoother".
+ * The table is process-wide. */
 size_t pm_autotune_workspace_bytes(int ng, int precision);
 int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t stream);
-int pm_launch_shape(int ng, int word_bytes);
-int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid);
+int pm_get_launch_shape(int ng, int word_bytes, int *block_cycle_grid /* HOST */, int *tiled_smoother /* HOST */);
+int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid, int tiled_smoother);
 int pm_tune_save(const char *path);
 int pm_tune_load(const char *path);
 

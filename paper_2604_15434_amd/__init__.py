@@ -16,8 +16,8 @@ from . import _lib as L
 
 __all__ = [
     "MgOpts", "PmError", "Workspace", "mg_batched_workspace_bytes", "mg_poisson_solve", "mg_scalar_solve",
-    "mg_scalar_solve_batched", "pm_autotune", "pm_deposit", "pm_eft_coefficients", "pm_launch_shape",
-    "pm_set_launch_shape", "pm_tune_load", "pm_tune_save",
+    "mg_scalar_solve_batched", "pm_autotune", "pm_deposit", "pm_eft_coefficients", "pm_get_launch_shape",
+    "pm_set_launch_shape", "pm_sort_particles", "pm_tune_load", "pm_tune_save",
     "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
     "pm_strerror", "pm_workspace_bytes",
 ]
@@ -223,6 +223,32 @@ def mg_scalar_solve_batched(problems, opts, ws=None, stream=None):
     return [_report(r) for r in reps]
 
 
+def pm_sort_particles(pos, ng, vel=None, ids=None, ws=None, stream=None):
+    """Reorder particles (and vel, int64 ids) by the cell of their CIC base
+    corner, stably and deterministically (in place)."""
+    import torch
+
+    dt = _dtype_code(pos)
+    npart = pos.shape[1]
+    _check(pos, (3, npart), dt, "pos")
+    if vel is not None:
+        _check(vel, (3, npart), dt, "vel")
+    if ids is not None and (ids.dtype != torch.int64 or not ids.is_contiguous() or ids.numel() != npart
+                            or not ids.is_cuda):
+        raise ValueError("ids: need a contiguous int64 device tensor of np entries")
+    need = int(L.lib().pm_sort_workspace_bytes(npart, dt))
+    if need == 0:
+        raise PmError(L.PM_EINVAL, "pm_sort_particles")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=pos.device)
+    rc = L.lib().pm_sort_particles(ctypes.c_void_p(pos.data_ptr()),
+                                   ctypes.c_void_p(vel.data_ptr() if vel is not None else 0),
+                                   ctypes.c_void_p(ids.data_ptr() if ids is not None else 0), npart, int(ng), dt,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_sort_particles")
+
+
 def pm_autotune(ng, precision="f64", ws=None, stream=None):
     """Time the launch-shape candidates for (ng, precision) and keep the fastest."""
     import torch
@@ -236,18 +262,20 @@ def pm_autotune(ng, precision="f64", ws=None, stream=None):
     rc = L.lib().pm_autotune(int(ng), prec, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
     if rc:
         raise PmError(rc, "pm_autotune")
-    return pm_launch_shape(ng, 4 if precision == "mixed" else 8)
+    return pm_get_launch_shape(ng, 4 if precision == "mixed" else 8)
 
 
-def pm_launch_shape(ng, word_bytes):
-    rc = int(L.lib().pm_launch_shape(int(ng), int(word_bytes)))
-    if rc < 0:
-        raise PmError(rc, "pm_launch_shape")
-    return rc
+def pm_get_launch_shape(ng, word_bytes):
+    """(block_cycle_grid, tiled_smoother) for (ng, word size)."""
+    b, t = ctypes.c_int(0), ctypes.c_int(0)
+    rc = L.lib().pm_get_launch_shape(int(ng), int(word_bytes), ctypes.byref(b), ctypes.byref(t))
+    if rc:
+        raise PmError(rc, "pm_get_launch_shape")
+    return b.value, t.value
 
 
-def pm_set_launch_shape(ng, word_bytes, block_cycle_grid):
-    rc = L.lib().pm_set_launch_shape(int(ng), int(word_bytes), int(block_cycle_grid))
+def pm_set_launch_shape(ng, word_bytes, block_cycle_grid, tiled_smoother=1):
+    rc = L.lib().pm_set_launch_shape(int(ng), int(word_bytes), int(block_cycle_grid), int(tiled_smoother))
     if rc:
         raise PmError(rc, "pm_set_launch_shape")
 

@@ -54,8 +54,8 @@ class StepReport(ctypes.Structure):
 
 EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_deposit", "mg_poisson_solve",
            "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
-           "pm_strerror", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
-           "pm_autotune", "pm_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
+           "pm_strerror", "pm_sort_workspace_bytes", "pm_sort_particles", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
+           "pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
            "ws_conv3")
 
 
@@ -77,14 +77,18 @@ def _load():
                             vp, sz, vp]
     lib.pm_kernel_timing_enable.argtypes = [i]
     lib.pm_kernel_timing_read.argtypes = [P(d), P(ll)]
+    lib.pm_sort_workspace_bytes.argtypes = [ll, i]
+    lib.pm_sort_workspace_bytes.restype = sz
+    lib.pm_sort_particles.argtypes = [vp, vp, vp, ll, i, i, vp, sz, vp]
+    lib.pm_sort_particles.restype = i
     lib.pm_autotune_workspace_bytes.argtypes = [i, i]
     lib.pm_autotune_workspace_bytes.restype = sz
     lib.pm_autotune.argtypes = [i, i, vp, sz, vp]
-    lib.pm_launch_shape.argtypes = [i, i]
-    lib.pm_set_launch_shape.argtypes = [i, i, i]
+    lib.pm_get_launch_shape.argtypes = [i, i, P(i), P(i)]
+    lib.pm_set_launch_shape.argtypes = [i, i, i, i]
     lib.pm_tune_save.argtypes = [ctypes.c_char_p]
     lib.pm_tune_load.argtypes = [ctypes.c_char_p]
-    for name in ("pm_autotune", "pm_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load"):
+    for name in ("pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load"):
         getattr(lib, name).restype = i
     lib.mg_batched_workspace_bytes.argtypes = [P(Problem), i, i]
     lib.mg_batched_workspace_bytes.restype = sz

@@ -50,10 +50,36 @@ __device__ __forceinline__ T root_lap(T b, T Tsh, const SolveConsts &sc, bool no
     return (T)-2 * G / (nu + sqrt(disc));
 }
 
+// Operator pieces from the 18 neighbour values of a cell: the six face
+// neighbours (other colour: x+, x-, y+, y-, z+, z-) and the twelve edge
+// neighbours (own colour: (i+-1, j+-1) at k; (i+-1) at k+-1; (j+-1) at
+// k+-1).  Returns S (face sum); sets Tsh (squared traceless Hessian times h^4)
+// when nonlinear.
+template <typename T>
+__device__ __forceinline__ T stencil_eval(T oxp, T oxm, T oyp, T oym, T ozp, T ozm, T epp, T epm, T emp, T emm,
+                                          T xpp, T xpm, T xmp, T xmm, T ypp, T ypm, T ymp, T ymm, bool nonlinear,
+                                          T &tsh_h4)
+{
+    const T ax = oxp + oxm;
+    const T ay = oyp + oym;
+    const T az = ozp + ozm;
+    tsh_h4 = (T)0;
+    if (nonlinear) {
+        const T dxy = epp - epm - emp + emm;
+        const T dxz = xpp - xpm - xmp + xmm;
+        const T dyz = ypp - ypm - ymp + ymm;
+        const T exy = ax - ay, eyz = ay - az, ezx = az - ax;
+        // (1/3) sum (D_ll - D_mm)^2 + 2 sum D_lm^2, all times h^4, with
+        // D_lm = d_lm / (4 h^2).
+        tsh_h4 = (exy * exy + eyz * eyz + ezx * ezx) * (T)(1.0 / 3.0) + (dxy * dxy + dxz * dxz + dyz * dyz) * (T)0.125;
+    }
+    return ax + ay + az;
+}
+
 // Operator pieces at cell (i, j, kh) of colour c.  `own` is the colour-c
 // block, `oth` the other block; values are loaded as Ts and computed as T.
-// Returns S (face sum); sets Tsh (squared traceless Hessian times h^4) when
-// nonlinear.
+// In the packed layout the k-neighbours of (i, j, kh) sit at kh - 1 + p and
+// kh + p with p = (i + j + c) & 1.
 template <typename T, typename Ts>
 __device__ __forceinline__ T stencil_terms(const Ts *__restrict__ own, const Ts *__restrict__ oth, int n, int nh, int c,
                                            int i, int j, int kh, bool nonlinear, T &tsh_h4)
@@ -68,24 +94,18 @@ __device__ __forceinline__ T stencil_terms(const Ts *__restrict__ own, const Ts 
     const unsigned rm0 = ((unsigned)im * n + j) * nh;
     const unsigned r0p = ((unsigned)i * n + jp) * nh;
     const unsigned r0m = ((unsigned)i * n + jm) * nh;
-    const T ax = (T)oth[rp0 + kh] + (T)oth[rm0 + kh];
-    const T ay = (T)oth[r0p + kh] + (T)oth[r0m + kh];
-    const T az = (T)oth[r00 + kp] + (T)oth[r00 + km];
-    tsh_h4 = (T)0;
-    if (nonlinear) {
-        const unsigned rpp = ((unsigned)ip * n + jp) * nh;
-        const unsigned rpm = ((unsigned)ip * n + jm) * nh;
-        const unsigned rmp = ((unsigned)im * n + jp) * nh;
-        const unsigned rmm = ((unsigned)im * n + jm) * nh;
-        const T dxy = (T)own[rpp + kh] - (T)own[rpm + kh] - (T)own[rmp + kh] + (T)own[rmm + kh];
-        const T dxz = (T)own[rp0 + kp] - (T)own[rp0 + km] - (T)own[rm0 + kp] + (T)own[rm0 + km];
-        const T dyz = (T)own[r0p + kp] - (T)own[r0p + km] - (T)own[r0m + kp] + (T)own[r0m + km];
-        const T exy = ax - ay, eyz = ay - az, ezx = az - ax;
-        // (1/3) sum (D_ll - D_mm)^2 + 2 sum D_lm^2, all times h^4, with
-        // D_lm = d_lm / (4 h^2).
-        tsh_h4 = (exy * exy + eyz * eyz + ezx * ezx) * (T)(1.0 / 3.0) + (dxy * dxy + dxz * dxz + dyz * dyz) * (T)0.125;
-    }
-    return ax + ay + az;
+    if (!nonlinear)
+        return stencil_eval<T>((T)oth[rp0 + kh], (T)oth[rm0 + kh], (T)oth[r0p + kh], (T)oth[r0m + kh],
+                               (T)oth[r00 + kp], (T)oth[r00 + km], (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0,
+                               (T)0, (T)0, (T)0, (T)0, false, tsh_h4);
+    const unsigned rpp = ((unsigned)ip * n + jp) * nh;
+    const unsigned rpm = ((unsigned)ip * n + jm) * nh;
+    const unsigned rmp = ((unsigned)im * n + jp) * nh;
+    const unsigned rmm = ((unsigned)im * n + jm) * nh;
+    return stencil_eval<T>((T)oth[rp0 + kh], (T)oth[rm0 + kh], (T)oth[r0p + kh], (T)oth[r0m + kh], (T)oth[r00 + kp],
+                           (T)oth[r00 + km], (T)own[rpp + kh], (T)own[rpm + kh], (T)own[rmp + kh], (T)own[rmm + kh],
+                           (T)own[rp0 + kp], (T)own[rp0 + km], (T)own[rm0 + kp], (T)own[rm0 + km], (T)own[r0p + kp],
+                           (T)own[r0p + km], (T)own[r0m + kp], (T)own[r0m + km], true, tsh_h4);
 }
 
 // One block: out[q] = sum over blocks b (in order) of partials[b * 8 + q].
@@ -119,6 +139,33 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 }
 
 // ---------------------------------------------------------------- smoothing
+// Block 0 of a half-sweep: csum_out = csum_in with the colour of the previous
+// half-sweep at this level (prev_colour; -1 none) replaced by the sum of its
+// per-block partials, in block order.
+__device__ __forceinline__ void fold_previous(const double *__restrict__ csum_in, double *__restrict__ csum_out,
+                                              const double *__restrict__ prev, int prev_nblocks, int prev_colour)
+{
+    __shared__ double fin[kBlock / 64];
+    double t = 0.0;
+    if (prev_colour >= 0)
+        for (int q = threadIdx.x; q < prev_nblocks; q += kBlock)
+            t += prev[(size_t)q * 8];
+    for (int off = 32; off > 0; off >>= 1)
+        t += __shfl_down(t, off, 64);
+    if ((threadIdx.x & 63) == 0)
+        fin[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double v = csum_in[threadIdx.x];
+        if ((int)threadIdx.x == prev_colour) {
+            v = 0.0;
+            for (int w = 0; w < kBlock / 64; w++)
+                v += fin[w];
+        }
+        csum_out[threadIdx.x] = v;
+    }
+}
+
 // Local update of one cell of colour `colour` (element e = (i, j, kh)):
 // x_new = (S - h^2 (Lq + tau - cmean)) / 6; returns Lq + tau.
 template <typename R, bool NL>
@@ -177,34 +224,163 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, c
         }
     }
     block_partials<1>(acc, rs, sp);
-    if (blockIdx.x == 0) {
-        __shared__ double fin[kBlock / 64];
-        double t = 0.0;
-        if (prev_colour >= 0)
-            for (int q = threadIdx.x; q < prev_nblocks; q += kBlock)
-                t += prev[(size_t)q * 8];
-        for (int off = 32; off > 0; off >>= 1)
-            t += __shfl_down(t, off, 64);
-        if ((threadIdx.x & 63) == 0)
-            fin[threadIdx.x >> 6] = t;
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            double v = csum_in[threadIdx.x];
-            if ((int)threadIdx.x == prev_colour) {
-                v = 0.0;
-                for (int w = 0; w < kBlock / 64; w++)
-                    v += fin[w];
+    if (blockIdx.x == 0)
+        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
+}
+
+// 2.5D-tiled half-sweep for the large levels: a tile is TJ = 256/TK rows in
+// j by TK elements in kh by kTilePlanes planes in i; its block keeps a
+// three-plane window of both colours (one halo row / element on each side) in
+// LDS and marches along i, issuing the next plane's loads into registers
+// before computing the current plane.  Each cell update is k_smooth's
+// arithmetic on the same operands (bitwise the same value); only the
+// grouping of the per-block partial sums of Lq + tau differs.  Blocks take
+// tiles lb, lb + nblocks, ... so that nblocks <= kMaxBlocks.
+constexpr int kTilePlanes = 8;
+
+template <typename R, bool NL, int TK>
+__global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colour, const R *__restrict__ xc_old,
+                                                        const R *__restrict__ xo, R *__restrict__ xc_new,
+                                                        const double *__restrict__ csum_in, double *__restrict__ csum_out,
+                                                        const double *__restrict__ prev, int prev_nblocks,
+                                                        int prev_colour, ReduceSlot rs, SolveConsts sc, Span sp,
+                                                        unsigned ntiles)
+{
+    constexpr int TJ = kBlock / TK;
+    constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
+    constexpr int PER = (2 * W + kBlock - 1) / kBlock;
+    __shared__ R win[2][3][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour
+    const int n = L.n, nh = L.nh;
+    const int nK = nh / TK, nI = n / kTilePlanes;
+    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
+    const R h2 = (R)(L.h * L.h);
+    const R ih2 = (R)(1.0 / (L.h * L.h));
+    const R *dc = colour ? L.db : L.dr;
+    const R *tc = colour ? L.tb : L.tr;
+    const int tj = threadIdx.x / TK, tk = threadIdx.x % TK;
+    double acc[1] = {0.0};
+    R pre[PER];
+    for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
+        const int ib = (int)(tile % nI), kb = (int)((tile / nI) % nK), jb = (int)(tile / ((unsigned)nI * nK));
+        const int i0 = ib * kTilePlanes, j0 = jb * TJ, k0 = kb * TK;
+        // window element q of a plane: colour q / W, row (q % W) / (TK + 2), column (q % W) % (TK + 2)
+        auto fetch = [&](int ii) {
+            ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int q = threadIdx.x + u * kBlock;
+                if (q < 2 * W) {
+                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
+                    int jj = j0 - 1 + r, kk = k0 - 1 + c;
+                    jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
+                    kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
+                    pre[u] = (which ? xo : xc_old)[((unsigned)ii * n + jj) * nh + kk];
+                }
             }
-            csum_out[threadIdx.x] = v;
+        };
+        auto store = [&](int slot) {
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int q = threadIdx.x + u * kBlock;
+                if (q < 2 * W) {
+                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
+                    win[which][slot][r][c] = pre[u];
+                }
+            }
+        };
+        fetch(i0 - 1);
+        store(0);
+        fetch(i0);
+        store(1);
+        fetch(i0 + 1);
+        store(2);
+        __syncthreads();
+        for (int t = 0; t < kTilePlanes; t++) {
+            const int i = i0 + t;
+            const int sm = t % 3, s0 = (t + 1) % 3, sp1 = (t + 2) % 3;  // planes i - 1, i, i + 1
+            if (t + 1 < kTilePlanes)
+                fetch(i + 2);  // into registers, stored after this plane
+            const int j = j0 + tj, kh = k0 + tk;
+            const int p = (i + j + colour) & 1;
+            const int a = tj + 1, b = tk + 1;        // window coordinates of the cell
+            const int bm = tk + p, bp = tk + 1 + p;  // its kh - 1 + p and kh + p neighbours
+            R tsh;
+            R S;
+            if (NL)
+                S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b], win[1][s0][a - 1][b],
+                                    win[1][s0][a][bp], win[1][s0][a][bm], win[0][sp1][a + 1][b], win[0][sp1][a - 1][b],
+                                    win[0][sm][a + 1][b], win[0][sm][a - 1][b], win[0][sp1][a][bp],
+                                    win[0][sp1][a][bm], win[0][sm][a][bp], win[0][sm][a][bm], win[0][s0][a + 1][bp],
+                                    win[0][s0][a + 1][bm], win[0][s0][a - 1][bp], win[0][s0][a - 1][bm], true, tsh);
+            else
+                S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b], win[1][s0][a - 1][b],
+                                    win[1][s0][a][bp], win[1][s0][a][bm], (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0,
+                                    (R)0, (R)0, (R)0, (R)0, (R)0, false, tsh);
+            const unsigned e = ((unsigned)i * n + j) * nh + kh;
+            const R bsrc = (R)sc.beta * dc[e];
+            int isv;
+            const R lq = root_lap<R>(bsrc, tsh * ih2 * ih2, sc, NL, isv);
+            const R v = lq + (tc ? tc[e] : (R)0);
+            xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
+            acc[0] += (double)v;
+            __syncthreads();
+            if (t + 1 < kTilePlanes)
+                store(sm);  // plane i + 2 replaces plane i - 1
+            __syncthreads();
         }
     }
+    block_partials<1>(acc, rs, sp);
+    if (blockIdx.x == 0)
+        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
+}
+
+// Whether the tiled half-sweep applies to a level (and with which TK).
+static inline int tile_width(int n)
+{
+    if (n < 64 || n % kTilePlanes)
+        return 0;
+    const int nh = n / 2;
+    if (nh % 64 == 0 && n % (kBlock / 64) == 0)
+        return 64;
+    if (nh % 32 == 0 && n % (kBlock / 32) == 0)
+        return 32;
+    return 0;
 }
 
 template <typename R>
 void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
                    double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
-                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out)
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, bool tiled)
 {
+    const int tk = tiled ? tile_width(L.n) : 0;
+    if (tk) {
+        // Span only carries the block count (XCD mapping, partials)
+        const unsigned ntiles = (unsigned)((L.n / (kBlock / tk)) * (L.nh / tk) * (L.n / kTilePlanes));
+        Span sp;
+        unsigned nb = ntiles < (unsigned)kMaxBlocks ? ntiles : (unsigned)kMaxBlocks;
+        if (nb >= 8)
+            nb -= nb % 8;
+        sp.nblocks = nb;
+        sp.chunk = kBlock;
+        sp.total = nb * kBlock;
+        *nblocks_out = (int)nb;
+#define PM_TILE(NLV, TKV)                                                                                              \
+    hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV>), dim3(nb), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,      \
+                       csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
+        if (nonlinear) {
+            if (tk == 64)
+                PM_TILE(true, 64);
+            else
+                PM_TILE(true, 32);
+        } else {
+            if (tk == 64)
+                PM_TILE(false, 64);
+            else
+                PM_TILE(false, 32);
+        }
+#undef PM_TILE
+        return;
+    }
     const Span sp = make_span(L.half);
     *nblocks_out = (int)sp.nblocks;
     if (nonlinear)
@@ -872,10 +1048,10 @@ void launch_zero(void *p, size_t bytes, hipStream_t st)
 // explicit instantiations
 template void launch_smooth<double>(const LevelView<double> &, int, const double *, const double *, double *,
                                     const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
-                                    hipStream_t, int *);
+                                    hipStream_t, int *, bool);
 template void launch_smooth<float>(const LevelView<float> &, int, const float *, const float *, float *,
                                    const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
-                                   hipStream_t, int *);
+                                   hipStream_t, int *, bool);
 template void launch_residual_restrict<double>(const LevelView<double> &, const double *, const double *,
                                                const double *, const LevelView<double> &, double *, double *,
                                                ReduceSlot, SolveConsts, bool, hipStream_t);

@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace pmeft {
 
 __device__ __forceinline__ int wrapn(int i, int n)
@@ -291,6 +293,248 @@ void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long lon
     else
         hipLaunchKernelGGL((k_interp_kick<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)g4, ng,
                            (float *)pos, (unsigned)np, (float *)vel, dt_kick, dt_drift, (float *)acc_out, sp);
+}
+
+// ------------------------------------------------------------ particle sort
+// Stable LSD radix sort of the particles by the cell of their CIC base
+// corner, key = (i0 ng + j0) ng + k0 (particles with unusable coordinates
+// take the last cell).  8-bit digits; per pass: per-tile digit histograms,
+// one exclusive scan over (digit, tile), and a scatter in which each element's
+// rank among equal digits of its tile comes from wave ballots, so the order
+// of equal keys is the input order and the result is deterministic.
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlock * kSortItems;  // elements per tile
+constexpr int kScanChunk = 2048;                // entries per scan block
+
+template <typename Tp>
+__global__ __launch_bounds__(kBlock) void k_sort_keys(const Tp *__restrict__ pos, unsigned np, int ng,
+                                                      unsigned *__restrict__ keys, unsigned *__restrict__ vals)
+{
+    const unsigned last = (unsigned)ng * ng * ng - 1u;
+    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < np; p += gridDim.x * kBlock) {
+        int x0, x1, y0, y1, z0, z1;
+        double fx, fy, fz;
+        const bool ok = cic_axis((double)pos[p], ng, x0, x1, fx) && cic_axis((double)pos[np + p], ng, y0, y1, fy) &&
+                        cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz);
+        keys[p] = ok ? ((unsigned)x0 * ng + y0) * ng + z0 : last;
+        vals[p] = p;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const unsigned *__restrict__ keys, unsigned n, int shift,
+                                                       unsigned ntiles, unsigned *__restrict__ hist)
+{
+    __shared__ unsigned h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned t0 = blockIdx.x * kSortTile;
+    for (unsigned e = t0 + threadIdx.x; e < min(n, t0 + kSortTile); e += kBlock)
+        atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[(size_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of x[0..n) in chunks: each block scans its chunk and writes the chunk total
+__global__ __launch_bounds__(kBlock) void k_scan_chunks(unsigned *__restrict__ x, unsigned n,
+                                                        unsigned *__restrict__ totals)
+{
+    __shared__ unsigned s[kBlock];
+    constexpr int per = kScanChunk / kBlock;
+    const unsigned base = blockIdx.x * kScanChunk + threadIdx.x * per;
+    unsigned v[per], sum = 0;
+    for (int q = 0; q < per; q++) {
+        v[q] = base + q < n ? x[base + q] : 0u;
+        sum += v[q];
+    }
+    s[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {  // inclusive Hillis-Steele scan of the thread sums
+        const unsigned t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    unsigned run = s[threadIdx.x] - sum;
+    for (int q = 0; q < per; q++) {
+        if (base + q < n)
+            x[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == kBlock - 1)
+        totals[blockIdx.x] = s[kBlock - 1];
+}
+
+// one block: exclusive scan of the chunk totals (any count), then add to the chunks
+__global__ __launch_bounds__(kBlock) void k_scan_totals(unsigned *__restrict__ totals, unsigned nchunks)
+{
+    __shared__ unsigned s[kBlock];
+    __shared__ unsigned carry;
+    if (threadIdx.x == 0)
+        carry = 0;
+    __syncthreads();
+    for (unsigned b0 = 0; b0 < nchunks; b0 += kBlock) {
+        const unsigned i = b0 + threadIdx.x;
+        const unsigned v = i < nchunks ? totals[i] : 0u;
+        s[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            const unsigned t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nchunks)
+            totals[i] = carry + s[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            carry += s[kBlock - 1];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(unsigned *__restrict__ x, unsigned n,
+                                                     const unsigned *__restrict__ totals)
+{
+    const unsigned add = totals[blockIdx.x];
+    for (unsigned e = blockIdx.x * kScanChunk + threadIdx.x; e < min(n, (blockIdx.x + 1) * kScanChunk); e += kBlock)
+        x[e] += add;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const unsigned *__restrict__ kin,
+                                                          const unsigned *__restrict__ vin, unsigned n, int shift,
+                                                          unsigned ntiles, const unsigned *__restrict__ offs,
+                                                          unsigned *__restrict__ kout, unsigned *__restrict__ vout)
+{
+    __shared__ unsigned run[256];        // elements of each digit already placed by this tile
+    __shared__ unsigned wc[kBlock / 64][256];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    run[threadIdx.x] = 0;
+    const unsigned t0 = blockIdx.x * kSortTile;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kSortItems; r++) {
+        for (int w = 0; w < kBlock / 64; w++)
+            wc[w][threadIdx.x] = 0;
+        __syncthreads();
+        const unsigned e = t0 + r * kBlock + threadIdx.x;
+        const bool valid = e < n;
+        const unsigned key = valid ? kin[e] : 0u;
+        const unsigned val = valid ? vin[e] : 0u;
+        const unsigned d = (key >> shift) & 255u;
+        unsigned long long m = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        // m: valid lanes of this wave with digit d
+        const unsigned rank_w = (unsigned)__popcll(m & lt);
+        if (valid && rank_w == 0)
+            wc[wave][d] = (unsigned)__popcll(m);
+        __syncthreads();
+        if (valid) {
+            unsigned before = run[d] + rank_w;
+            for (int w = 0; w < wave; w++)
+                before += wc[w][d];
+            const unsigned pos = offs[(size_t)d * ntiles + blockIdx.x] + before;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        unsigned add = 0;
+        for (int w = 0; w < kBlock / 64; w++)
+            add += wc[w][threadIdx.x];
+        run[threadIdx.x] += add;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_permute3(const T *__restrict__ src, T *__restrict__ dst,
+                                                     const unsigned *__restrict__ perm, unsigned np)
+{
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < np; i += gridDim.x * kBlock) {
+        const unsigned p = perm[i];
+        dst[i] = src[p];
+        dst[(size_t)np + i] = src[(size_t)np + p];
+        dst[2 * (size_t)np + i] = src[2 * (size_t)np + p];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute_ids(const long long *__restrict__ src, long long *__restrict__ dst,
+                                                        const unsigned *__restrict__ perm, unsigned np)
+{
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < np; i += gridDim.x * kBlock)
+        dst[i] = src[perm[i]];
+}
+
+static unsigned sort_tiles(unsigned long long np) { return (unsigned)((np + kSortTile - 1) / kSortTile); }
+
+size_t sort_workspace_bytes(unsigned long long np, int word)
+{
+    const unsigned nt = sort_tiles(np);
+    const size_t nh = (size_t)256 * nt;
+    const size_t nchunks = (nh + kScanChunk - 1) / kScanChunk;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return 4 * al(sizeof(unsigned) * np) + al(sizeof(unsigned) * nh) + al(sizeof(unsigned) * nchunks) +
+           al((size_t)3 * word * np);
+}
+
+// Sort; pos, vel (nullable) 3 x np SoA of dtype; ids (nullable) np int64.
+int launch_sort_particles(void *pos, void *vel, long long *ids, unsigned np, int ng, pm_dtype dt, char *ws,
+                          hipStream_t st)
+{
+    const unsigned nt = sort_tiles(np);
+    const size_t nh = (size_t)256 * nt;
+    const unsigned nchunks = (unsigned)((nh + kScanChunk - 1) / kScanChunk);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    unsigned *k0 = (unsigned *)ws;
+    unsigned *v0 = (unsigned *)(ws + al(sizeof(unsigned) * np));
+    unsigned *k1 = (unsigned *)(ws + 2 * al(sizeof(unsigned) * np));
+    unsigned *v1 = (unsigned *)(ws + 3 * al(sizeof(unsigned) * np));
+    unsigned *hist = (unsigned *)(ws + 4 * al(sizeof(unsigned) * np));
+    unsigned *tot = (unsigned *)((char *)hist + al(sizeof(unsigned) * nh));
+    char *scratch = (char *)tot + al(sizeof(unsigned) * nchunks);
+    const unsigned nb = std::min(4096u, (np + kBlock - 1) / kBlock);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_sort_keys<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)pos, np, ng, k0, v0);
+    else
+        hipLaunchKernelGGL((k_sort_keys<float>), dim3(nb), dim3(kBlock), 0, st, (const float *)pos, np, ng, k0, v0);
+    const unsigned long long maxkey = (unsigned long long)ng * ng * ng - 1ull;
+    int bits = 0;
+    while ((maxkey >> bits) != 0ull)
+        bits++;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nt), dim3(kBlock), 0, st, k0, np, shift, nt, hist);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(kBlock), 0, st, hist, (unsigned)nh, tot);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kBlock), 0, st, tot, nchunks);
+        hipLaunchKernelGGL(k_scan_add, dim3(nchunks), dim3(kBlock), 0, st, hist, (unsigned)nh, tot);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nt), dim3(kBlock), 0, st, k0, v0, np, shift, nt, hist, k1, v1);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    // v0: the permutation (sorted position -> original index)
+    const size_t word = dt == PM_F64 ? 8 : 4;
+    void *arrays[2] = {pos, vel};
+    for (int a = 0; a < 2; a++) {
+        if (!arrays[a])
+            continue;
+        if (dt == PM_F64)
+            hipLaunchKernelGGL((k_permute3<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)arrays[a],
+                               (double *)scratch, v0, np);
+        else
+            hipLaunchKernelGGL((k_permute3<float>), dim3(nb), dim3(kBlock), 0, st, (const float *)arrays[a],
+                               (float *)scratch, v0, np);
+        if (hipMemcpyAsync(arrays[a], scratch, 3 * word * np, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PM_EHIP;
+    }
+    if (ids) {
+        // the key buffer k1 (np words) and v1 are free now: 8 * np bytes from k1 on
+        long long *tmp = (long long *)k1;
+        hipLaunchKernelGGL(k_permute_ids, dim3(nb), dim3(kBlock), 0, st, ids, tmp, v0, np);
+        if (hipMemcpyAsync(ids, tmp, sizeof(long long) * np, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return PM_EHIP;
+    }
+    return hipGetLastError() == hipSuccess ? PM_OK : PM_EHIP;
 }
 
 }  // namespace pmeft

@@ -7,7 +7,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <array>
 #include <atomic>
 #include <mutex>
 #include <thread>
@@ -212,6 +211,7 @@ struct Hier {
     int cs[kMaxLevels];      // current csum buffer per level
     int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
     int block_l0 = kMaxLevels;  // levels from here down run as one block cycle
+    bool tiled = true;          // 2.5D-tiled smoother on the levels it fits
     BlockHier<R> block() const
     {
         BlockHier<R> B;
@@ -258,42 +258,47 @@ static LevelView<R> make_view(int n, double h, const R *d, R *t, R *x0)
 }
 
 // ---- launch-shape table --------------------------------------------------
-// Largest grid of the levels that run as one block cycle, per (finest grid,
-// word size); set by pm_autotune, default kBlockCycleDefault.
-constexpr int kBlockCycleDefault = 32;
+// Per (finest grid, word size): the largest grid of the levels that run as
+// one block cycle, and whether the large levels use the 2.5D-tiled smoother;
+// set by pm_autotune, defaults kBlockCycleDefault and tiled.
+constexpr int kBlockCycleDefault = 8;
+struct Shape {
+    int ng, word, block_n, tiled;
+};
 struct TuneTable {
     std::mutex mu;
-    std::vector<std::array<int, 3>> block_n;  // (ng, word size, max n; 0 = off)
+    std::vector<Shape> rows;
 };
 static TuneTable g_tune;
 
-static int block_cycle_n(int ng, int word)
+static Shape launch_shape(int ng, int word)
 {
     std::lock_guard<std::mutex> g(g_tune.mu);
-    for (const auto &e : g_tune.block_n)
-        if (e[0] == ng && e[1] == word)
-            return e[2];
-    return kBlockCycleDefault;
+    for (const auto &e : g_tune.rows)
+        if (e.ng == ng && e.word == word)
+            return e;
+    return Shape{ng, word, kBlockCycleDefault, 1};
 }
 
-static void set_block_cycle_n(int ng, int word, int n)
+static void set_shape(const Shape &sh)
 {
     std::lock_guard<std::mutex> g(g_tune.mu);
-    for (auto &e : g_tune.block_n)
-        if (e[0] == ng && e[1] == word) {
-            e[2] = n;
+    for (auto &e : g_tune.rows)
+        if (e.ng == sh.ng && e.word == sh.word) {
+            e = sh;
             return;
         }
-    g_tune.block_n.push_back({ng, word, n});
+    g_tune.rows.push_back(sh);
 }
 
 template <typename R>
 static void set_block_level(Hier<R> &H, int ng)
 {
-    const int nmax = block_cycle_n(ng, (int)sizeof(R));
+    const Shape sh = launch_shape(ng, (int)sizeof(R));
+    H.tiled = sh.tiled != 0;
     H.block_l0 = kMaxLevels;
     for (int l = 0; l < H.nlev - 1; l++)
-        if (H.L[l].n <= nmax) {
+        if (H.L[l].n <= sh.block_n) {
             H.block_l0 = l;
             break;
         }
@@ -372,7 +377,7 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     rs.partials = H.part(l, k);
     int nb = 0;
     launch_smooth<R>(H.L[l], colour, src, oth, dst, H.csum_cur(l), H.csum_alt(l), H.part(l, k ^ 1), H.pend_nb[l],
-                     H.pend_col[l], rs, sc, nl, C.st, &nb);
+                     H.pend_col[l], rs, sc, nl, C.st, &nb, H.tiled);
     if (e1)
         (void)hipEventRecord(e1, C.st);
     H.cur[l][colour] = 1 - own;
@@ -869,6 +874,24 @@ size_t pm_workspace_bytes(int ng, long long np, pm_dtype dtype, pm_prec prec)
     return P.total;
 }
 
+size_t pm_sort_workspace_bytes(long long np, pm_dtype dtype)
+{
+    if (np <= 0 || np > (1LL << 30) || (dtype != PM_F32 && dtype != PM_F64))
+        return 0;
+    return sort_workspace_bytes((unsigned long long)np, dtype == PM_F64 ? 8 : 4);
+}
+
+int pm_sort_particles(void *pos, void *vel, long long *ids, long long np, int ng, pm_dtype dtype, void *ws,
+                      size_t ws_bytes, pm_stream_t stream)
+{
+    if (!pos || !ws || ((uintptr_t)ws & 255) || np <= 0 || np > (1LL << 30) || ng < 8 || ng > 1024 ||
+        (dtype != PM_F32 && dtype != PM_F64))
+        return PM_EINVAL;
+    if (ws_bytes < pm_sort_workspace_bytes(np, dtype))
+        return PM_ENOMEM;
+    return launch_sort_particles(pos, vel, ids, (unsigned)np, ng, dtype, (char *)ws, (hipStream_t)stream);
+}
+
 int pm_deposit(const void *pos, long long np, pm_dtype dtype, int ng, void *rho, void *ws, size_t ws_bytes,
                pm_stream_t stream)
 {
@@ -1036,18 +1059,22 @@ size_t pm_autotune_workspace_bytes(int ng, int precision)
     return ((b + 255) & ~(size_t)255) + 2 * (((sizeof(double) * (size_t)ng * ng * ng) + 255) & ~(size_t)255);
 }
 
-int pm_launch_shape(int ng, int word_bytes)
+int pm_get_launch_shape(int ng, int word_bytes, int *block_cycle_grid, int *tiled_smoother)
 {
-    if (word_bytes != 4 && word_bytes != 8)
+    if ((word_bytes != 4 && word_bytes != 8) || !block_cycle_grid || !tiled_smoother)
         return PM_EINVAL;
-    return block_cycle_n(ng, word_bytes);
+    const Shape sh = launch_shape(ng, word_bytes);
+    *block_cycle_grid = sh.block_n;
+    *tiled_smoother = sh.tiled;
+    return PM_OK;
 }
 
-int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid)
+int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid, int tiled_smoother)
 {
-    if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8)
+    if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8 ||
+        (tiled_smoother != 0 && tiled_smoother != 1))
         return PM_EINVAL;
-    set_block_cycle_n(ng, word_bytes, block_cycle_grid);
+    set_shape(Shape{ng, word_bytes, block_cycle_grid, tiled_smoother});
     return PM_OK;
 }
 
@@ -1075,30 +1102,32 @@ int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t st
     o.guess = PM_GUESS_ZERO;
     const int word = precision == PM_PREC_MIXED ? 4 : 8;
     const int cands[5] = {0, 8, 16, 32, 64};
-    int best_n = block_cycle_n(ng, word);
+    Shape best = launch_shape(ng, word);
     float best_ms = 1e30f;
-    for (int c = 0; c < 5; c++) {
-        const int n = cands[c];
-        if (n >= ng)
-            continue;
-        set_block_cycle_n(ng, word, n);
-        float ms = 1e30f;
-        for (int rep = 0; rep < 3; rep++) {  // first run warms up
-            pm_mg_report r;
-            const int e = grid_solve(rho, ng, PM_F64, &p, &o, chi, &r, ws, solver, stream, true);
-            if (e != PM_OK && e != PM_ENOCONV) {
-                set_block_cycle_n(ng, word, best_n);
-                return e;
+    for (int tiled = 0; tiled < 2; tiled++)
+        for (int c = 0; c < 5; c++) {
+            const int n = cands[c];
+            if (n >= ng)
+                continue;
+            const Shape sh{ng, word, n, tiled};
+            set_shape(sh);
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3; rep++) {  // first run warms up
+                pm_mg_report r;
+                const int e = grid_solve(rho, ng, PM_F64, &p, &o, chi, &r, ws, solver, stream, true);
+                if (e != PM_OK && e != PM_ENOCONV) {
+                    set_shape(best);
+                    return e;
+                }
+                if (rep > 0)
+                    ms = std::min(ms, r.ms);
             }
-            if (rep > 0)
-                ms = std::min(ms, r.ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = sh;
+            }
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_n = n;
-        }
-    }
-    set_block_cycle_n(ng, word, best_n);
+    set_shape(best);
     return PM_OK;
 }
 
@@ -1110,9 +1139,9 @@ int pm_tune_save(const char *path)
     if (!f)
         return PM_EINVAL;
     std::lock_guard<std::mutex> g(g_tune.mu);
-    fprintf(f, "# pmeft launch shapes: ng word_bytes block_cycle_grid\n");
-    for (const auto &e : g_tune.block_n)
-        fprintf(f, "%d %d %d\n", e[0], e[1], e[2]);
+    fprintf(f, "# pmeft launch shapes: ng word_bytes block_cycle_grid tiled_smoother\n");
+    for (const auto &e : g_tune.rows)
+        fprintf(f, "%d %d %d %d\n", e.ng, e.word, e.block_n, e.tiled);
     fclose(f);
     return PM_OK;
 }
@@ -1129,12 +1158,13 @@ int pm_tune_load(const char *path)
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n')
             continue;
-        int ng, word, n;
-        if (sscanf(line, "%d %d %d", &ng, &word, &n) != 3 || (word != 4 && word != 8) || n < 0 || ng < 8) {
+        int ng, word, n, tiled;
+        if (sscanf(line, "%d %d %d %d", &ng, &word, &n, &tiled) != 4 || (word != 4 && word != 8) || n < 0 ||
+            ng < 8 || (tiled != 0 && tiled != 1)) {
             rc = PM_EINVAL;
             break;
         }
-        set_block_cycle_n(ng, word, n);
+        set_shape(Shape{ng, word, n, tiled});
     }
     fclose(f);
     return rc;

@@ -161,7 +161,7 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 template <typename R>
 void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
                    double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
-                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out);
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, bool tiled);
 
 // Fine-level residual r = Lq + tau - c - lap x fused with the 8-child
 // restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
@@ -230,6 +230,11 @@ void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStre
 // y = a * x
 void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
+
+// ---- particle sort (pm_kernels.hip) --------------------------------------
+size_t sort_workspace_bytes(unsigned long long np, int word);
+int launch_sort_particles(void *pos, void *vel, long long *ids, unsigned np, int ng, pm_dtype dt, char *ws,
+                          hipStream_t st);
 
 // ---- block cycle: the coarse part of a V-cycle in one workgroup ---------
 constexpr int kBlockCycleThreads = 512;

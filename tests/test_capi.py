@@ -75,22 +75,24 @@ def test_grid_levels_and_workspace():
 def test_launch_shape_table_roundtrip(tmp_path):
     import paper_2604_15434_amd as P
 
-    assert P.pm_launch_shape(96, 8) == 32  # default
-    P.pm_set_launch_shape(96, 8, 16)
-    P.pm_set_launch_shape(96, 4, 0)
-    assert P.pm_launch_shape(96, 8) == 16 and P.pm_launch_shape(96, 4) == 0
+    assert P.pm_get_launch_shape(96, 8) == (8, 1)  # defaults
+    P.pm_set_launch_shape(96, 8, 16, 0)
+    P.pm_set_launch_shape(96, 4, 0, 1)
+    assert P.pm_get_launch_shape(96, 8) == (16, 0) and P.pm_get_launch_shape(96, 4) == (0, 1)
     path = tmp_path / "tune.txt"
     P.pm_tune_save(path)
-    P.pm_set_launch_shape(96, 8, 64)
+    P.pm_set_launch_shape(96, 8, 64, 1)
     P.pm_tune_load(path)
-    assert P.pm_launch_shape(96, 8) == 16 and P.pm_launch_shape(96, 4) == 0
+    assert P.pm_get_launch_shape(96, 8) == (16, 0) and P.pm_get_launch_shape(96, 4) == (0, 1)
     with pytest.raises(P.PmError):
         P.pm_set_launch_shape(96, 2, 16)
+    with pytest.raises(P.PmError):
+        P.pm_set_launch_shape(96, 8, 16, 2)
     bad = tmp_path / "bad.txt"
-    bad.write_text("96 3 16\n")
+    bad.write_text("96 3 16 1\n")
     with pytest.raises(P.PmError):
         P.pm_tune_load(bad)
     with pytest.raises(P.PmError):
         P.pm_tune_load(tmp_path / "missing.txt")
-    P.pm_set_launch_shape(96, 8, 32)
-    P.pm_set_launch_shape(96, 4, 32)
+    P.pm_set_launch_shape(96, 8, 32, 1)
+    P.pm_set_launch_shape(96, 4, 32, 1)

@@ -173,6 +173,56 @@ def test_pm_step_cfg0_matches_oracle(P, dtype, prec, ftol):
     assert np.array_equal(gp.cpu().numpy(), pos.astype(gp.cpu().numpy().dtype))  # no drift requested
 
 
+_CFG1_CACHE = {}
+
+
+def _cfg1_ref(k):
+    """Oracle step of the 128^3 Zel'dovich workload (250 Mpc/h, seed 1) for
+    parameter set k (cached across precisions)."""
+    if "pos" not in _CFG1_CACHE:
+        from workloads import zeldovich_ics
+
+        _CFG1_CACHE["pos"] = zeldovich_ics(128, 250.0, seed=1)
+    if k not in _CFG1_CACHE:
+        pos = _CFG1_CACHE["pos"]
+        _CFG1_CACHE[k] = oracle.pm_step(pos, np.zeros_like(pos), 128, config_params("cfg1")[k], dt_kick=1.0,
+                                        tol=1e-12)
+    return _CFG1_CACHE["pos"], _CFG1_CACHE[k]
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+@pytest.mark.parametrize("k", range(8))
+def test_pm_step_cfg1_matches_oracle(P, k, prec):
+    """128^3 Zel'dovich step for the 8 parameter sets (alpha_B0 in {-0.2, -0.6},
+    alpha_M0 in {0, 0.1}, a in {0.33, 1}): FP64 at 1e-12 and FP32 particles
+    with mixed-precision solves at 1e-7, against the oracle at 1e-12.  Checks
+    the force RMS error, the scalar field and its power spectrum per bin."""
+    ng = 128
+    pos, ref = _cfg1_ref(k)
+    prm = config_params("cfg1")[k]
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    tol = 1e-12 if prec == "f64" else 1e-7
+    gp, gv = dev(pos, dtype), torch.zeros((3, pos.shape[1]), dtype=dtype, device="cuda")
+    psi = torch.zeros((ng, ng, ng), dtype=dtype, device="cuda")
+    chi = torch.zeros_like(psi)
+    opts = P.MgOpts(rel_tol=tol, max_vcycles=80, precision=prec)
+    rep = P.pm_step(gp, gv, ng, prm, opts, opts, 1.0, 0.0, psi, chi)
+    assert rep["status"] == 0, rep
+    acc = gv.cpu().numpy().astype(np.float64)
+    ferr = np.sqrt(np.mean(np.sum((acc - ref["acc"]) ** 2, 0)) / np.mean(np.sum(ref["acc"] ** 2, 0)))
+    chi_g = _mean_free(chi.cpu().numpy())
+    cerr = rel(chi_g, ref["chi"])
+    _, pk_g, _ = oracle.power_spectrum(chi_g, 250.0)
+    _, pk_r, _ = oracle.power_spectrum(ref["chi"], 250.0)
+    perr = float(np.max(np.abs(pk_g / pk_r - 1.0)))
+    print(f"cfg1[{k}] {prec}: force {ferr:.2e} chi {cerr:.2e} P_chi(k) max {perr:.2e} "
+          f"V-cycles {rep['scalar']['vcycles']}/{rep['poisson']['vcycles']}")
+    if prec == "f64":
+        assert ferr < 1e-9 and cerr < 1e-10 and perr < 1e-9
+    else:
+        assert ferr < 1e-4 and cerr < 1e-5 and perr < 1e-4
+
+
 def test_force_interp_and_drift(P):
     ng = 16
     rng = np.random.default_rng(4)
@@ -323,13 +373,67 @@ def test_block_cycle_matches_per_level_launches(P, ng, precision):
     assert float((psi1 - psi0).norm() / psi0.norm()) < 1e-9
 
 
+@pytest.mark.parametrize("ng,precision", [(64, "f64"), (128, "f64"), (128, "mixed"), (192, "mixed")])
+def test_tiled_smoother_matches_untiled(P, ng, precision):
+    """The 2.5D-tiled half-sweep computes the same cell updates; whole solves
+    differ only through the grouping of the lagged-mean partial sums."""
+    rho = torch.from_numpy(lognormal_density(ng, 500.0 * ng / 256, seed=23)).cuda()
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.6, alpha_m0=0.1, a=1.0)
+    opts = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision=precision)
+    out = {}
+    try:
+        for tiled in (0, 1):
+            for word in (4, 8):
+                P.pm_set_launch_shape(ng, word, 32, tiled)
+            chi = torch.zeros_like(rho)
+            rep = P.mg_scalar_solve(rho, prm, opts, chi)
+            assert rep["status"] == 0
+            out[tiled] = (chi, rep)
+    finally:
+        for word in (4, 8):
+            P.pm_set_launch_shape(ng, word, 32, 1)
+    err = float((out[1][0] - out[0][0]).norm() / out[0][0].norm())
+    assert err < 1e-9, err
+    assert abs(out[1][1]["vcycles"] - out[0][1]["vcycles"]) <= 1
+    assert out[1][1]["clamped_cells"] == out[0][1]["clamped_cells"]
+
+
 def test_autotune_picks_a_candidate(P):
     ng = 64
-    n = P.pm_autotune(ng, "mixed")
-    assert n in (0, 8, 16, 32)
+    n, tiled = P.pm_autotune(ng, "mixed")
+    assert n in (0, 8, 16, 32) and tiled in (0, 1)
     rho = torch.from_numpy(lognormal_density(ng, 125.0, seed=22)).cuda()
     chi = torch.zeros_like(rho)
     rep = P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.3, alpha_m0=0.0, a=1.0),
                             P.MgOpts(rel_tol=1e-9, precision="mixed"), chi)
     assert rep["status"] == 0
-    P.pm_set_launch_shape(ng, 4, 32)
+    P.pm_set_launch_shape(ng, 4, 32, 1)
+
+
+# ---------------------------------------------------------------- particle sort
+@pytest.mark.parametrize("ng,npart,dtype", [(32, 50000, torch.float64), (64, 262144, torch.float32),
+                                            (16, 1, torch.float64), (64, 300001, torch.float64)])
+def test_sort_particles_is_stable_argsort(P, ng, npart, dtype):
+    """The permutation equals NumPy's stable argsort of the CIC base-cell key
+    (bit-exact), pos/vel/ids move together, and the deposit is unchanged
+    (it is exact in fixed point)."""
+    rng = np.random.default_rng(ng + npart)
+    pos_np = rng.random((3, npart))
+    pos_np[:, : npart // 3] = np.round(pos_np[:, : npart // 3] * ng) / ng  # many ties and cell edges
+    pos = torch.from_numpy(pos_np).to("cuda", dtype)
+    vel = torch.from_numpy(rng.standard_normal((3, npart))).to("cuda", dtype)
+    ids = torch.arange(npart, dtype=torch.int64, device="cuda")
+    rho0 = torch.zeros((ng, ng, ng), dtype=dtype, device="cuda")
+    P.pm_deposit(pos, ng, rho0)
+    p64 = pos.cpu().numpy().astype(np.float64)
+    cell = np.mod(np.floor(p64 * ng - 0.5).astype(np.int64), ng)
+    key = (cell[0] * ng + cell[1]) * ng + cell[2]
+    order = np.argsort(key, kind="stable")
+    vel0 = vel.clone()
+    P.pm_sort_particles(pos, ng, vel=vel, ids=ids)
+    assert np.array_equal(ids.cpu().numpy(), order)
+    assert torch.equal(pos.cpu(), torch.from_numpy(p64[:, order]).to(dtype))
+    assert torch.equal(vel.cpu(), vel0.cpu()[:, torch.from_numpy(order)])
+    rho1 = torch.zeros_like(rho0)
+    P.pm_deposit(pos, ng, rho1)
+    assert torch.equal(rho0, rho1)

@@ -3,6 +3,7 @@ reference given the same BF16-rounded operands (FP32 accumulation only:
 relative error 1e-5), and of the whole network's forward pass and gradients
 (BF16 activations between layers: looser bounds)."""
 import ctypes
+import math
 
 import numpy as np
 import pytest
@@ -171,3 +172,46 @@ def test_learned_guess_rejects_bad_grid(P):
     with pytest.raises(P.PmError):
         P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=1.0),
                           P.MgOpts(guess="learned", learned=net), chi)
+
+
+def test_trained_network_gain_on_held_out_fields(P):
+    """What the trained network (committed weights) gains over the method
+    without it, on 128^3 lognormal fields of seeds outside the training range
+    and fresh parameter draws: its source error is far below the untrained
+    network's, the solve from its guess starts from a smaller residual than
+    the zero-guess full multigrid and never needs more V-cycles, and the
+    final field is the zero-guess one.  (Wall time is reported, not asserted:
+    the network's pass costs about as much as the cycle it saves.)"""
+    import os
+
+    from paper_2604_15434_amd.warmstart import DEFAULT_WEIGHTS, WarmStart
+    from workloads import lognormal_density, scan_params
+
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    net = WarmStart.load(DEFAULT_WEIGHTS)
+    untrained = WarmStart(seed=0)
+    n = 128
+    prms = scan_params(4, seed=5000)
+    for k, prm in enumerate(prms):
+        rho = torch.from_numpy(lognormal_density(n, 250.0, seed=5000 + k)).cuda()
+        ref = torch.zeros_like(rho)
+        P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=1e-10, max_vcycles=80), ref)
+        e_tr = math.sqrt(net.train_step(rho, ref, prm, 0.0)) / float(rho.std())
+        e_un = math.sqrt(untrained.train_step(rho, ref, prm, 0.0)) / float(rho.std())
+        out = {}
+        for g in ("zero", "learned"):
+            chi = torch.zeros_like(rho)
+            rep = P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=1e-7, max_vcycles=60, precision="mixed", guess=g,
+                                                       learned=net), chi)
+            assert rep["status"] == 0
+            out[g] = (chi, rep)
+        z, l = out["zero"][1], out["learned"][1]
+        print(f"seed {5000 + k}: source error {e_tr:.3f} (untrained {e_un:.3f}); first residual "
+              f"{l['residual_hist'][0]:.2e} vs {z['residual_hist'][0]:.2e}; V-cycles {l['vcycles']} vs "
+              f"{z['vcycles']}; ms {l['ms']:.2f} vs {z['ms']:.2f}")
+        assert e_tr < 0.2 and e_tr < 0.5 * e_un
+        assert l["residual_hist"][0] < 0.5 * z["residual_hist"][0]
+        assert l["vcycles"] <= z["vcycles"]
+        err = float((out["learned"][0] - ref).norm() / ref.norm())
+        assert err < 1e-5
