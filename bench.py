@@ -78,12 +78,55 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup, net=None):
     last = reps[-1]
     ok = all(r["status"] == 0 and r["scalar"]["rel_residual"] <= 1e-7 for r in reps)
     return dict(ms_per_step=wall, converged=ok, scalar_vcycles=last["scalar"]["vcycles"],
+                scalar_residual_hist=[float(f"{x:.3g}") for x in last["scalar"]["residual_hist"][:last["scalar"]["vcycles"] + 1]],
                 poisson_vcycles=last["poisson"]["vcycles"], scalar_rel_residual=last["scalar"]["rel_residual"],
                 ms_deposit=last["ms_deposit"], ms_poisson=last["poisson"]["ms"], ms_scalar=last["scalar"]["ms"],
                 ms_force=last["ms_force"], kernel_timing=kt, itemsize=8 if dt == torch.float64 else 4)
 
 
-def roofline(res, ng):
+SMOOTHER_SOURCES = [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f) for f in ("mg_stencil.h", "smooth_kernels.hip")]
+
+
+def smoother_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in SMOOTHER_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def smoother_kernel(itemsize, tiled, ng):
+    """Name of the finest-level scalar-field smoother the launch shape selects
+    (the tile configuration rule of smooth_kernels.hip)."""
+    r = "double" if itemsize == 8 else "float"
+    nh = ng // 2
+    if tiled and ng >= 64:
+        if tiled == 2 and nh % 64 == 0 and ng % 16 == 0 and (ng // 8) * (nh // 64) * (ng // 16) >= 512:
+            return f"k_smooth_tile<{r}, true, 64, 2, 16>"
+        if nh % 64 == 0 and ng % 8 == 0:
+            return f"k_smooth_tile<{r}, true, 64, 1, 8>"
+        if nh % 32 == 0 and ng % 8 == 0:
+            return f"k_smooth_tile<{r}, true, 32, 1, 8>"
+    return f"k_smooth<{r}, true>"
+
+
+def measured_traffic(kernel, ng):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current smoother source at this grid."""
+    path = os.path.join(ROOT, "profiles", f"pm_step_{ng}_smoother_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != smoother_source_hash():
+        return None
+    for k in rec.get("kernels", {}).values():
+        if k.get("kernel") == kernel:
+            return round(k["traffic_bytes"])
+    return None
+
+
+def roofline(res, ng, tiled):
     """Dominant kernel: the finest-level scalar-field smoother of the mode."""
     slot = "scalar_f64" if res["itemsize"] == 8 else "scalar_f32"
     ms, n = res["kernel_timing"][slot]
@@ -91,10 +134,11 @@ def roofline(res, ng):
         return None
     bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4)
     achieved = bytes_launch / (ms / n * 1e-3) / 1e9
+    kernel = smoother_kernel(res["itemsize"], tiled, ng)
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"k_smooth<{'double' if res['itemsize'] == 8 else 'float'},true> (finest level, one colour)",
-            "bytes_per_launch": bytes_launch, "avg_launch_us": round(ms / n * 1e3, 2), "launches": n}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, ng),
+            "kernel": f"{kernel} (finest level, one colour)", "bytes_per_launch": bytes_launch,
+            "avg_launch_us": round(ms / n * 1e3, 2), "launches": n}
 
 
 def cpu_baseline(pos_np, ng):
@@ -138,6 +182,47 @@ def cpu_baseline(pos_np, ng):
                        f"(oracle count to 1e-7 at 64^3, same statistics), gradient; OpenMP threads {threads}")}
 
 
+def run_scan(P, torch, per_size=16, sizes=(64, 128, 192, 256), tol=1e-7):
+    """The batched parameter scan: per_size lognormal densities at each grid
+    size (cell 500/256 Mpc/h, seeds 4000+), alpha_B0 ~ U[-1, 0], alpha_M0 ~
+    U[0, 0.2], a = 1 (seed 4), FP32 arrays with mixed-precision solves to tol;
+    one mg_scalar_solve_batched call against the same problems solved one
+    after another."""
+    from workloads import lognormal_density, scan_params
+
+    probs = []
+    prms = scan_params(per_size * len(sizes), seed=4, a=1.0)
+    for s_i, ng in enumerate(sizes):
+        for k in range(per_size):
+            idx = s_i * per_size + k
+            rho = torch.from_numpy(lognormal_density(ng, 500.0 * ng / 256, seed=4000 + idx)).to("cuda", torch.float32)
+            probs.append(dict(rho=rho, chi=torch.zeros_like(rho), params=prms[idx]))
+    opts = P.MgOpts(rel_tol=tol, max_vcycles=60, precision="mixed")
+    ws = torch.empty(P.mg_batched_workspace_bytes(probs, "mixed"), dtype=torch.uint8, device="cuda")
+    P.mg_scalar_solve_batched(probs, opts, ws=ws)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = P.mg_scalar_solve_batched(probs, opts, ws=ws)
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t0) * 1e3
+    pws = {}
+    t0 = time.perf_counter()
+    for pr in probs:
+        ng = pr["rho"].shape[0]
+        if ng not in pws:
+            pws[ng] = P.Workspace(ng, 0, 0, "mixed")
+        P.mg_scalar_solve(pr["rho"], pr["params"], opts, torch.zeros_like(pr["chi"]), ws=pws[ng])
+    torch.cuda.synchronize()
+    seq = (time.perf_counter() - t0) * 1e3
+    cells = sum(pr["rho"].numel() for pr in probs)
+    cyc = sum(r["vcycles"] * pr["rho"].numel() for r, pr in zip(reps, probs))
+    return {"problems": len(probs), "sizes": list(sizes), "per_size": per_size, "tol": tol,
+            "ms_batched": round(batched, 2), "ms_sequential": round(seq, 2),
+            "speedup": round(seq / batched, 3), "all_converged": all(r["status"] == 0 for r in reps),
+            "vcycles_min_max": [min(r["vcycles"] for r in reps), max(r["vcycles"] for r in reps)],
+            "cells": cells, "cells_vcycles_per_s": round(cyc / (batched * 1e-3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +232,13 @@ def main():
     ap.add_argument("--modes", default="plain,fp32,learned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tune-save", default=None, help="write the autotuned launch shapes to this file")
+    ap.add_argument("--tune-load", default=None, help="use the launch shapes of this file (implies --no-tune)")
+    ap.add_argument("--ics", default="lognormal", choices=("lognormal", "zeldovich"),
+                    help="lognormal: ng^3 particles from the log-sigma 1.5 lognormal density (seed 2, 500 ng/256 "
+                         "Mpc/h); zeldovich: Zel'dovich load of the sigma8 = 0.8 spectrum (seed 5, 1000 ng/512 Mpc/h)")
+    ap.add_argument("--scan", action="store_true",
+                    help="also time the batched parameter scan (16 problems each at 64^3..256^3)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2604_15434_amd", "weights", "unet_warmstart.f32"))
@@ -167,8 +259,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print(f"[bench] generating {ng}^3 lognormal particles", file=sys.stderr, flush=True)
-    pos_np, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=2)
+    print(f"[bench] generating {ng}^3 {args.ics} particles", file=sys.stderr, flush=True)
+    if args.ics == "lognormal":
+        box = 500.0 * ng / 256
+        pos_np, _ = lognormal_particles(ng, box, seed=2)
+    else:
+        from workloads import zeldovich_ics
+
+        box = 1000.0 * ng / 512
+        pos_np = zeldovich_ics(ng, box, seed=5)
     modes = args.modes.split(",")
     net = None
     if "learned" in modes:
@@ -181,10 +280,16 @@ def main():
                   flush=True)
             modes.remove("learned")
     shapes = {}
-    if not args.no_tune:
+    if args.tune_load:
+        P.pm_tune_load(args.tune_load)
+    elif not args.no_tune:
         for prec in ("f64", "mixed"):
-            shapes[prec] = P.pm_autotune(ng, prec)
-        print(f"[bench] autotuned block-cycle grids: {shapes}", file=sys.stderr, flush=True)
+            P.pm_autotune(ng, prec)
+    if args.tune_save:
+        P.pm_tune_save(args.tune_save)
+    for prec, word in (("f64", 8), ("mixed", 4)):
+        shapes[prec] = dict(zip(("block_cycle_grid", "tiled_smoother"), P.pm_get_launch_shape(ng, word)))
+    print(f"[bench] launch shapes: {shapes}", file=sys.stderr, flush=True)
     results = {}
     for mode in modes:
         print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
@@ -193,9 +298,12 @@ def main():
               f"V-cycles chi {results[mode]['scalar_vcycles']} psi {results[mode]['poisson_vcycles']}",
               file=sys.stderr, flush=True)
     head = next((m for m in ("learned", "fp32") if m in results and results[m]["converged"]), next(iter(results)))
+
+    def tiled_of(mode):
+        return shapes["f64" if mode == "plain" else "mixed"]["tiled_smoother"]
     r = results[head]
     line = {
-        "metric": "ms per 256^3 PM step (scalar MG to rel. residual 1e-7), plain vs learned+FP32",
+        "metric": f"ms per {ng}^3 PM step (scalar MG to rel. residual 1e-7), plain vs learned+FP32",
         "value": round(r["ms_per_step"], 3),
         "unit": "ms",
         "n_gpus": 1,
@@ -207,8 +315,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if head == "plain" else ("f32+f64+bf16" if head == "learned" else "f32+f64"),
         "data": "synthetic",
-        "config": {"workload": f"PM step, {ng}^3 grid, {ng}^3 lognormal particles (log-sigma 1.5, seed 2), "
-                               f"{500.0 * ng / 256:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7",
+        "config": {"workload": (f"PM step, {ng}^3 grid, {ng}^3 lognormal particles (log-sigma 1.5, seed 2), "
+                                f"{box:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7" if args.ics == "lognormal"
+                                else f"PM step, {ng}^3 grid, {ng}^3 Zel'dovich particles (sigma8 0.8, seed 5), "
+                                f"{box:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7"),
                    "mode": head, "launch_shapes": shapes},
         "plain_ms_per_step": round(results["plain"]["ms_per_step"], 3) if "plain" in results else None,
         "speedup_vs_plain": round(results["plain"]["ms_per_step"] / r["ms_per_step"], 3) if "plain" in results
@@ -217,9 +327,13 @@ def main():
                   for m, res in results.items()},
         "cells_vcycles_per_s": round(ng**3 * r["scalar_vcycles"] / (r["ms_scalar"] * 1e-3), 1)
         if r["ms_scalar"] > 0 else None,
-        "roofline": roofline(r, ng),
-        "roofline_modes": {m: roofline(res, ng) for m, res in results.items()},
+        "roofline": roofline(r, ng, tiled_of(head)),
+        "roofline_modes": {m: roofline(res, ng, tiled_of(m)) for m, res in results.items()},
     }
+    if args.scan:
+        print("[bench] batched parameter scan", file=sys.stderr, flush=True)
+        line["scan"] = run_scan(P, torch)
+        print(f"[bench] scan: {line['scan']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pos_np, ng)

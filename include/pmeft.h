@@ -55,7 +55,9 @@ typedef enum { PM_F32 = 0, PM_F64 = 1 } pm_dtype;
 /* Arithmetic of the multigrid solves.  PM_PREC_F64: every level in FP64.
  * PM_PREC_MIXED: smoothing, restriction, prolongation in FP32; the fine-grid
  * residual, the defect correction of the FP64 iterate, the convergence test
- * and the coarsest-grid solve in FP64. */
+ * and the coarsest-grid solve in FP64.  Each outer step (FP64 residual, test,
+ * correction) runs two FP32 V-cycles; the nonlinear scalar field finishes in
+ * FP64 once its residual nears the FP32 representation limit. */
 typedef enum { PM_PREC_F64 = 0, PM_PREC_MIXED = 1 } pm_prec;
 
 /* Initial guess of a solve: zero; the values passed in the output array
@@ -107,7 +109,9 @@ typedef struct {
     int status;                 /* PM_OK or PM_ENOCONV / PM_ENONFINITE */
     int vcycles;                /* V-cycles performed */
     double rel_residual;        /* of the returned iterate */
-    double residual_hist[64];   /* rel. residual before V-cycle i (i < 64) */
+    double residual_hist[64];   /* rel. residual before V-cycle i (i < 64); with PM_PREC_MIXED, before
+                                   each outer defect-correction step (two FP32 V-cycles each), then
+                                   before each V-cycle of an FP64 finish */
     double mean_shift;          /* mean of the quadratic-root Laplacian removed on the fine grid */
     long long clamped_cells;    /* void cells on the fine grid (Sec. 3.3) */
     float ms;                   /* wall time of the solve (HIP events) */
@@ -217,15 +221,18 @@ int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const
  *  - block_cycle_grid: the coarse end of every V-cycle (and of full
  *    multigrid) runs as one single-workgroup launch from the first level
  *    whose grid is at most this (0: every level launches its own kernels);
- *  - tiled_smoother (0/1): the large levels (grid >= 64, divisible by 8 and
- *    by 64 or 128) use the 2.5D-tiled red-black half-sweep, whose cell
- *    updates equal the untiled ones bit for bit.
+ *  - tiled_smoother (0 off, 1 small tiles, 2 large tiles): the large levels
+ *    (grid >= 64, divisible by 8 and by 64 or 128) use the 2.5D-tiled
+ *    red-black half-sweep, whose cell updates equal the untiled ones bit for
+ *    bit; large tiles (16 rows x 64 x 16 planes) replace small ones (4 or 8
+ *    rows x 64 or 32 x 8 planes) where they still give 512 tiles.
  * Defaults 8 and 1.  They change the cost of a cycle, and the grouping of
  * the partial sums behind the lagged means, not the converged answer.
  * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a
- * synthetic density for every candidate (block_cycle_grid in off, 8, 16, 32,
- * 64; tiled off, on) and keeps the fastest for (ng, precision); workspace:
- * pm_autotune_workspace_bytes.  pm_tune_save / pm_tune_load write and read
+ * synthetic density (uniform hash noise per cell in [0.2, 1.8], rough at every
+ * scale) for every candidate (block_cycle_grid in off, 8, 16, 32, 64;
+ * tiled_smoother 0, 1, 2) and keeps the fastest for (ng, precision);
+ * workspace: pm_autotune_workspace_bytes.  pm_tune_save / pm_tune_load write and read
  * the table as text lines "ng word_bytes block_cycle_grid tiled_smoother".
  * The table is process-wide. */
 size_t pm_autotune_workspace_bytes(int ng, int precision);

@@ -19,94 +19,11 @@
 // 12 edge neighbours of the scalar-field stencil have the cell's own colour,
 // so each half-sweep reads its own colour from one buffer and writes the new
 // values into another (no cell reads a value written in the same launch).
-#include "pmeft_internal.h"
+#include "mg_stencil.h"
 
 #include <math.h>
 
 namespace pmeft {
-
-// ---------------------------------------------------------------- helpers
-__device__ __forceinline__ int wrap_up(int i, int n) { return i >= n ? i - n : i; }
-__device__ __forceinline__ int wrap_dn(int i, int n) { return i < 0 ? i + n : i; }
-
-// Void-cell test and root of the local quadratic, computed in the type T.
-template <typename T>
-__device__ __forceinline__ T root_lap(T b, T Tsh, const SolveConsts &sc, bool nonlinear, int &is_void)
-{
-    const T nu = (T)sc.nu;
-    if (!nonlinear) {
-        is_void = 0;
-        return b / nu;
-    }
-    const T K = (T)sc.K;
-    const T dsph = nu * nu - (T)(8.0 / 3.0) * K * b;
-    if (dsph < (T)0) {
-        is_void = 1;
-        return (T)0.75 * nu / K;
-    }
-    is_void = 0;
-    const T G = K * Tsh - b;
-    const T disc = dsph + (T)(8.0 / 3.0) * K * K * Tsh;
-    return (T)-2 * G / (nu + sqrt(disc));
-}
-
-// Operator pieces from the 18 neighbour values of a cell: the six face
-// neighbours (other colour: x+, x-, y+, y-, z+, z-) and the twelve edge
-// neighbours (own colour: (i+-1, j+-1) at k; (i+-1) at k+-1; (j+-1) at
-// k+-1).  Returns S (face sum); sets Tsh (squared traceless Hessian times h^4)
-// when nonlinear.
-template <typename T>
-__device__ __forceinline__ T stencil_eval(T oxp, T oxm, T oyp, T oym, T ozp, T ozm, T epp, T epm, T emp, T emm,
-                                          T xpp, T xpm, T xmp, T xmm, T ypp, T ypm, T ymp, T ymm, bool nonlinear,
-                                          T &tsh_h4)
-{
-    const T ax = oxp + oxm;
-    const T ay = oyp + oym;
-    const T az = ozp + ozm;
-    tsh_h4 = (T)0;
-    if (nonlinear) {
-        const T dxy = epp - epm - emp + emm;
-        const T dxz = xpp - xpm - xmp + xmm;
-        const T dyz = ypp - ypm - ymp + ymm;
-        const T exy = ax - ay, eyz = ay - az, ezx = az - ax;
-        // (1/3) sum (D_ll - D_mm)^2 + 2 sum D_lm^2, all times h^4, with
-        // D_lm = d_lm / (4 h^2).
-        tsh_h4 = (exy * exy + eyz * eyz + ezx * ezx) * (T)(1.0 / 3.0) + (dxy * dxy + dxz * dxz + dyz * dyz) * (T)0.125;
-    }
-    return ax + ay + az;
-}
-
-// Operator pieces at cell (i, j, kh) of colour c.  `own` is the colour-c
-// block, `oth` the other block; values are loaded as Ts and computed as T.
-// In the packed layout the k-neighbours of (i, j, kh) sit at kh - 1 + p and
-// kh + p with p = (i + j + c) & 1.
-template <typename T, typename Ts>
-__device__ __forceinline__ T stencil_terms(const Ts *__restrict__ own, const Ts *__restrict__ oth, int n, int nh, int c,
-                                           int i, int j, int kh, bool nonlinear, T &tsh_h4)
-{
-    const int p = (i + j + c) & 1;
-    const int km = wrap_dn(kh - 1 + p, nh);
-    const int kp = wrap_up(kh + p, nh);
-    const int ip = wrap_up(i + 1, n), im = wrap_dn(i - 1, n);
-    const int jp = wrap_up(j + 1, n), jm = wrap_dn(j - 1, n);
-    const unsigned r00 = ((unsigned)i * n + j) * nh;
-    const unsigned rp0 = ((unsigned)ip * n + j) * nh;
-    const unsigned rm0 = ((unsigned)im * n + j) * nh;
-    const unsigned r0p = ((unsigned)i * n + jp) * nh;
-    const unsigned r0m = ((unsigned)i * n + jm) * nh;
-    if (!nonlinear)
-        return stencil_eval<T>((T)oth[rp0 + kh], (T)oth[rm0 + kh], (T)oth[r0p + kh], (T)oth[r0m + kh],
-                               (T)oth[r00 + kp], (T)oth[r00 + km], (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0, (T)0,
-                               (T)0, (T)0, (T)0, (T)0, false, tsh_h4);
-    const unsigned rpp = ((unsigned)ip * n + jp) * nh;
-    const unsigned rpm = ((unsigned)ip * n + jm) * nh;
-    const unsigned rmp = ((unsigned)im * n + jp) * nh;
-    const unsigned rmm = ((unsigned)im * n + jm) * nh;
-    return stencil_eval<T>((T)oth[rp0 + kh], (T)oth[rm0 + kh], (T)oth[r0p + kh], (T)oth[r0m + kh], (T)oth[r00 + kp],
-                           (T)oth[r00 + km], (T)own[rpp + kh], (T)own[rpm + kh], (T)own[rmp + kh], (T)own[rmm + kh],
-                           (T)own[rp0 + kp], (T)own[rp0 + km], (T)own[rm0 + kp], (T)own[rm0 + km], (T)own[r0p + kp],
-                           (T)own[r0p + km], (T)own[r0m + kp], (T)own[r0m + km], true, tsh_h4);
-}
 
 // One block: out[q] = sum over blocks b (in order) of partials[b * 8 + q].
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
@@ -136,259 +53,6 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, (const double *)rs.partials, (int)sp.nblocks, nv,
                        out);
-}
-
-// ---------------------------------------------------------------- smoothing
-// Block 0 of a half-sweep: csum_out = csum_in with the colour of the previous
-// half-sweep at this level (prev_colour; -1 none) replaced by the sum of its
-// per-block partials, in block order.
-__device__ __forceinline__ void fold_previous(const double *__restrict__ csum_in, double *__restrict__ csum_out,
-                                              const double *__restrict__ prev, int prev_nblocks, int prev_colour)
-{
-    __shared__ double fin[kBlock / 64];
-    double t = 0.0;
-    if (prev_colour >= 0)
-        for (int q = threadIdx.x; q < prev_nblocks; q += kBlock)
-            t += prev[(size_t)q * 8];
-    for (int off = 32; off > 0; off >>= 1)
-        t += __shfl_down(t, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        fin[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        double v = csum_in[threadIdx.x];
-        if ((int)threadIdx.x == prev_colour) {
-            v = 0.0;
-            for (int w = 0; w < kBlock / 64; w++)
-                v += fin[w];
-        }
-        csum_out[threadIdx.x] = v;
-    }
-}
-
-// Local update of one cell of colour `colour` (element e = (i, j, kh)):
-// x_new = (S - h^2 (Lq + tau - cmean)) / 6; returns Lq + tau.
-template <typename R, bool NL>
-__device__ __forceinline__ R smooth_cell(const R *__restrict__ xc_old, const R *__restrict__ xo, R *__restrict__ xc_new,
-                                         const R *__restrict__ dc, const R *__restrict__ tc, int n, int nh, int colour,
-                                         int i, int j, int kh, unsigned e, R cmean, R h2, R ih2, const SolveConsts &sc)
-{
-    R tsh;
-    const R S = stencil_terms<R, R>(xc_old, xo, n, nh, colour, i, j, kh, NL, tsh);
-    const R b = (R)sc.beta * dc[e];
-    int isv;
-    const R lq = root_lap<R>(b, tsh * ih2 * ih2, sc, NL, isv);
-    const R v = lq + (tc ? tc[e] : (R)0);
-    xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
-    return v;
-}
-
-// One half-sweep of colour `colour`.  The lagged mean c = <Lq + tau> comes
-// from csum_in (per-colour sums).  Block 0 also folds the partial sums of the
-// previous half-sweep at this level (prev, prev_nblocks, prev_colour; colour
-// -1 = none) into csum_out, which the next half-sweep reads: the mean thus
-// lags by about one sweep, needs no extra launch, and stays deterministic
-// (every launch reads only values completed by earlier launches).
-template <typename R, bool NL>
-__global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, const R *__restrict__ xc_old,
-                                                   const R *__restrict__ xo, R *__restrict__ xc_new,
-                                                   const double *__restrict__ csum_in, double *__restrict__ csum_out,
-                                                   const double *__restrict__ prev, int prev_nblocks, int prev_colour,
-                                                   ReduceSlot rs, SolveConsts sc, Span sp)
-{
-    const int n = L.n, nh = L.nh;
-    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
-    const R h2 = (R)(L.h * L.h);
-    const R ih2 = (R)(1.0 / (L.h * L.h));
-    const R *dc = colour ? L.db : L.dr;
-    const R *tc = colour ? L.tb : L.tr;
-    double acc[1] = {0.0};
-    const unsigned lb = span_block(sp);
-    const unsigned e0 = lb * sp.chunk + threadIdx.x;
-    const unsigned e1 = min(sp.total, (lb + 1) * sp.chunk);
-    int i, j, kh;
-    if (e0 < e1)
-        split(e0, nh, n, i, j, kh);
-    for (unsigned e = e0; e < e1;) {
-        acc[0] += (double)smooth_cell<R, NL>(xc_old, xo, xc_new, dc, tc, n, nh, colour, i, j, kh, e, cmean, h2, ih2, sc);
-        e += kBlock;
-        if (e < e1) {  // step (i, j, kh) by kBlock cells without dividing
-            kh += kBlock;
-            while (kh >= nh) {
-                kh -= nh;
-                if (++j == n) {
-                    j = 0;
-                    ++i;
-                }
-            }
-        }
-    }
-    block_partials<1>(acc, rs, sp);
-    if (blockIdx.x == 0)
-        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
-}
-
-// 2.5D-tiled half-sweep for the large levels: a tile is TJ = 256/TK rows in
-// j by TK elements in kh by kTilePlanes planes in i; its block keeps a
-// three-plane window of both colours (one halo row / element on each side) in
-// LDS and marches along i, issuing the next plane's loads into registers
-// before computing the current plane.  Each cell update is k_smooth's
-// arithmetic on the same operands (bitwise the same value); only the
-// grouping of the per-block partial sums of Lq + tau differs.  Blocks take
-// tiles lb, lb + nblocks, ... so that nblocks <= kMaxBlocks.
-constexpr int kTilePlanes = 8;
-
-template <typename R, bool NL, int TK>
-__global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colour, const R *__restrict__ xc_old,
-                                                        const R *__restrict__ xo, R *__restrict__ xc_new,
-                                                        const double *__restrict__ csum_in, double *__restrict__ csum_out,
-                                                        const double *__restrict__ prev, int prev_nblocks,
-                                                        int prev_colour, ReduceSlot rs, SolveConsts sc, Span sp,
-                                                        unsigned ntiles)
-{
-    constexpr int TJ = kBlock / TK;
-    constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
-    constexpr int PER = (2 * W + kBlock - 1) / kBlock;
-    __shared__ R win[2][3][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour
-    const int n = L.n, nh = L.nh;
-    const int nK = nh / TK, nI = n / kTilePlanes;
-    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
-    const R h2 = (R)(L.h * L.h);
-    const R ih2 = (R)(1.0 / (L.h * L.h));
-    const R *dc = colour ? L.db : L.dr;
-    const R *tc = colour ? L.tb : L.tr;
-    const int tj = threadIdx.x / TK, tk = threadIdx.x % TK;
-    double acc[1] = {0.0};
-    R pre[PER];
-    for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
-        const int ib = (int)(tile % nI), kb = (int)((tile / nI) % nK), jb = (int)(tile / ((unsigned)nI * nK));
-        const int i0 = ib * kTilePlanes, j0 = jb * TJ, k0 = kb * TK;
-        // window element q of a plane: colour q / W, row (q % W) / (TK + 2), column (q % W) % (TK + 2)
-        auto fetch = [&](int ii) {
-            ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
-#pragma unroll
-            for (int u = 0; u < PER; u++) {
-                const int q = threadIdx.x + u * kBlock;
-                if (q < 2 * W) {
-                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
-                    int jj = j0 - 1 + r, kk = k0 - 1 + c;
-                    jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
-                    kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
-                    pre[u] = (which ? xo : xc_old)[((unsigned)ii * n + jj) * nh + kk];
-                }
-            }
-        };
-        auto store = [&](int slot) {
-#pragma unroll
-            for (int u = 0; u < PER; u++) {
-                const int q = threadIdx.x + u * kBlock;
-                if (q < 2 * W) {
-                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
-                    win[which][slot][r][c] = pre[u];
-                }
-            }
-        };
-        fetch(i0 - 1);
-        store(0);
-        fetch(i0);
-        store(1);
-        fetch(i0 + 1);
-        store(2);
-        __syncthreads();
-        for (int t = 0; t < kTilePlanes; t++) {
-            const int i = i0 + t;
-            const int sm = t % 3, s0 = (t + 1) % 3, sp1 = (t + 2) % 3;  // planes i - 1, i, i + 1
-            if (t + 1 < kTilePlanes)
-                fetch(i + 2);  // into registers, stored after this plane
-            const int j = j0 + tj, kh = k0 + tk;
-            const int p = (i + j + colour) & 1;
-            const int a = tj + 1, b = tk + 1;        // window coordinates of the cell
-            const int bm = tk + p, bp = tk + 1 + p;  // its kh - 1 + p and kh + p neighbours
-            R tsh;
-            R S;
-            if (NL)
-                S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b], win[1][s0][a - 1][b],
-                                    win[1][s0][a][bp], win[1][s0][a][bm], win[0][sp1][a + 1][b], win[0][sp1][a - 1][b],
-                                    win[0][sm][a + 1][b], win[0][sm][a - 1][b], win[0][sp1][a][bp],
-                                    win[0][sp1][a][bm], win[0][sm][a][bp], win[0][sm][a][bm], win[0][s0][a + 1][bp],
-                                    win[0][s0][a + 1][bm], win[0][s0][a - 1][bp], win[0][s0][a - 1][bm], true, tsh);
-            else
-                S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b], win[1][s0][a - 1][b],
-                                    win[1][s0][a][bp], win[1][s0][a][bm], (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0,
-                                    (R)0, (R)0, (R)0, (R)0, (R)0, false, tsh);
-            const unsigned e = ((unsigned)i * n + j) * nh + kh;
-            const R bsrc = (R)sc.beta * dc[e];
-            int isv;
-            const R lq = root_lap<R>(bsrc, tsh * ih2 * ih2, sc, NL, isv);
-            const R v = lq + (tc ? tc[e] : (R)0);
-            xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
-            acc[0] += (double)v;
-            __syncthreads();
-            if (t + 1 < kTilePlanes)
-                store(sm);  // plane i + 2 replaces plane i - 1
-            __syncthreads();
-        }
-    }
-    block_partials<1>(acc, rs, sp);
-    if (blockIdx.x == 0)
-        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
-}
-
-// Whether the tiled half-sweep applies to a level (and with which TK).
-static inline int tile_width(int n)
-{
-    if (n < 64 || n % kTilePlanes)
-        return 0;
-    const int nh = n / 2;
-    if (nh % 64 == 0 && n % (kBlock / 64) == 0)
-        return 64;
-    if (nh % 32 == 0 && n % (kBlock / 32) == 0)
-        return 32;
-    return 0;
-}
-
-template <typename R>
-void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
-                   double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
-                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, bool tiled)
-{
-    const int tk = tiled ? tile_width(L.n) : 0;
-    if (tk) {
-        // Span only carries the block count (XCD mapping, partials)
-        const unsigned ntiles = (unsigned)((L.n / (kBlock / tk)) * (L.nh / tk) * (L.n / kTilePlanes));
-        Span sp;
-        unsigned nb = ntiles < (unsigned)kMaxBlocks ? ntiles : (unsigned)kMaxBlocks;
-        if (nb >= 8)
-            nb -= nb % 8;
-        sp.nblocks = nb;
-        sp.chunk = kBlock;
-        sp.total = nb * kBlock;
-        *nblocks_out = (int)nb;
-#define PM_TILE(NLV, TKV)                                                                                              \
-    hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV>), dim3(nb), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,      \
-                       csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
-        if (nonlinear) {
-            if (tk == 64)
-                PM_TILE(true, 64);
-            else
-                PM_TILE(true, 32);
-        } else {
-            if (tk == 64)
-                PM_TILE(false, 64);
-            else
-                PM_TILE(false, 32);
-        }
-#undef PM_TILE
-        return;
-    }
-    const Span sp = make_span(L.half);
-    *nblocks_out = (int)sp.nblocks;
-    if (nonlinear)
-        hipLaunchKernelGGL((k_smooth<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
-    else
-        hipLaunchKernelGGL((k_smooth<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
 }
 
 // ------------------------------------------------------- residual/restrict
@@ -432,9 +96,12 @@ __device__ __forceinline__ void restrict_cell(const LevelView<R> &F, const R *__
             const unsigned ef = ((unsigned)i * F.n + j) * F.nh + K;
 #pragma unroll
             for (int fc = 0; fc < 2; fc++) {
-                double lqt;
+                // in the level's own precision (the FP32 levels of the mixed
+                // solve need FP32 residuals only); sums in FP64
+                R lqt_r;
                 int isv;
-                const double r = cell_residual<double, R, NL>(F, xr, xb, fc, i, j, K, ef, cm, sc, lqt, isv);
+                const double r = (double)cell_residual<R, R, NL>(F, xr, xb, fc, i, j, K, ef, (R)cm, sc, lqt_r, isv);
+                const double lqt = (double)lqt_r;
                 sr += r;
                 sx += (double)(fc ? xb : xr)[ef];
                 acc[0] += r * r;
@@ -470,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, co
 template <typename R>
 void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
                               const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
-                              hipStream_t st)
+                              hipStream_t st, bool norms)
 {
     const Span sp = make_span(2 * C.half);
     if (nonlinear)
@@ -479,7 +146,8 @@ void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, c
     else
         hipLaunchKernelGGL((k_residual_restrict<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, C,
                            cxr, cxb, rs, sc, sp);
-    launch_finalize(rs, sp, 4, rs.out, st);
+    if (norms)
+        launch_finalize(rs, sp, 4, rs.out, st);
 }
 
 // ------------------------------------------------------------ FAS source
@@ -637,9 +305,11 @@ void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R>
 // ------------------------------------------------------------- coarsest
 // One workgroup, n <= 6: red-black Gauss-Seidel in FP64 in LDS with the exact
 // mean of Lq + tau recomputed before every half-sweep, until the largest
-// update falls below 1e-14 of the largest value or `sweeps` sweeps are done.
+// update falls below kCoarseTol of the largest value or `sweeps` sweeps are
+// done (the coarse correction needs far less than the V-cycle's per-cycle
+// reduction).
 constexpr int kCoarseMax = 216;
-constexpr double kCoarseTol = 1e-14;
+constexpr double kCoarseTol = 1e-10;
 
 // Device part, for any block size >= n^3 that is a multiple of 64 (all
 // threads of the block must call it).
@@ -738,10 +408,78 @@ __device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveC
     __syncthreads();
 }
 
+// The 4^3 coarsest grid in one wavefront: lane q holds cell q = (i n + j) n + k
+// and reads its neighbours with cross-lane shuffles, so a sweep needs no
+// barrier.  Same iteration as coarsest_solve (red-black Gauss-Seidel with the
+// exact mean of Lq + tau before every half-sweep, same stopping rule).
+// Called by the 64 lanes of one wave.
+template <typename R, bool NL>
+__device__ void coarsest_wave(const LevelView<R> &C, R *xr, R *xb, const SolveConsts &sc, int sweeps, double tol)
+{
+    constexpr int n = 4, nh = 2;
+    const int q = threadIdx.x & 63;
+    const int i = q >> 4, j = (q >> 2) & 3, k = q & 3;
+    const int col = (i + j + k) & 1;
+    const long long off = ((long long)i * n + j) * nh + (k >> 1);
+    double x = (double)(col ? xb : xr)[off];
+    const double d = (double)(col ? C.db : C.dr)[off];
+    const R *tc = col ? C.tb : C.tr;
+    const double t = tc ? (double)tc[off] : 0.0;
+    const double h2 = C.h * C.h, ih2 = 1.0 / h2;
+    auto lane = [&](int a, int b, int c) { return (((a + n) & 3) << 4) | (((b + n) & 3) << 2) | ((c + n) & 3); };
+    auto wsum = [](double v) {
+        for (int o = 32; o > 0; o >>= 1)
+            v += __shfl_xor(v, o, 64);
+        return v;
+    };
+    auto wmax = [](double v) {
+        for (int o = 32; o > 0; o >>= 1)
+            v = fmax(v, __shfl_xor(v, o, 64));
+        return v;
+    };
+    for (int sw = 0; sw < sweeps; sw++) {
+        double maxd = 0.0;
+        for (int colour = 0; colour < 2; colour++) {
+            const double ax = __shfl(x, lane(i + 1, j, k), 64) + __shfl(x, lane(i - 1, j, k), 64);
+            const double ay = __shfl(x, lane(i, j + 1, k), 64) + __shfl(x, lane(i, j - 1, k), 64);
+            const double az = __shfl(x, lane(i, j, k + 1), 64) + __shfl(x, lane(i, j, k - 1), 64);
+            const double S = ax + ay + az;
+            double tsh = 0.0;
+            if (NL) {
+                const double dxy = __shfl(x, lane(i + 1, j + 1, k), 64) - __shfl(x, lane(i + 1, j - 1, k), 64) -
+                                   __shfl(x, lane(i - 1, j + 1, k), 64) + __shfl(x, lane(i - 1, j - 1, k), 64);
+                const double dxz = __shfl(x, lane(i + 1, j, k + 1), 64) - __shfl(x, lane(i + 1, j, k - 1), 64) -
+                                   __shfl(x, lane(i - 1, j, k + 1), 64) + __shfl(x, lane(i - 1, j, k - 1), 64);
+                const double dyz = __shfl(x, lane(i, j + 1, k + 1), 64) - __shfl(x, lane(i, j + 1, k - 1), 64) -
+                                   __shfl(x, lane(i, j - 1, k + 1), 64) + __shfl(x, lane(i, j - 1, k - 1), 64);
+                tsh = ((ax - ay) * (ax - ay) + (ay - az) * (ay - az) + (az - ax) * (az - ax)) / 3.0 +
+                      0.125 * (dxy * dxy + dxz * dxz + dyz * dyz);
+            }
+            int isv;
+            const double val = root_lap<double>(sc.beta * d, tsh * ih2 * ih2, sc, NL, isv) + t;
+            const double cmean = wsum(val) / 64.0;
+            if (col == colour) {
+                const double nx = (S - h2 * (val - cmean)) / 6.0;
+                maxd = fmax(maxd, fabs(nx - x));
+                x = nx;
+            }
+        }
+        const double gx = wmax(fabs(x)), gd = wmax(maxd);
+        if (gd <= tol * gx)
+            break;
+    }
+    (col ? xb : xr)[off] = (R)x;
+}
+
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *xb, SolveConsts sc, int sweeps,
                                                      double tol)
 {
+    if (C.n == 4) {
+        if (threadIdx.x < 64)
+            coarsest_wave<R, NL>(C, xr, xb, sc, sweeps, tol);
+        return;
+    }
     coarsest_solve<R, NL>(C, xr, xb, sc, sweeps, tol);
 }
 
@@ -870,43 +608,108 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
 {
     const double cm = (csum64[0] + csum64[1]) / (2.0 * (double)F.half);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    const float ih2f = (float)(1.0 / (F.h * F.h));
+    const double ih2 = 1.0 / (F.h * F.h);
+    const float ih2f = (float)ih2;
     const unsigned half = (unsigned)F.half;
-    PM_SPAN_LOOP(e, sp)
-    {
-        const int c = e >= half;
-        const unsigned ef = e - (c ? half : 0u);
-        int i, j, kh;
-        split(ef, F.nh, F.n, i, j, kh);
-        double lqt;
+    const int n = F.n, nh = F.nh;
+    const unsigned lb = span_block(sp);
+    const unsigned e0 = lb * sp.chunk + threadIdx.x;
+    const unsigned e1 = min(sp.total, (lb + 1) * sp.chunk);
+    int c = e0 >= half;
+    unsigned ef = e0 - (c ? half : 0u);
+    int i = 0, j = 0, kh = 0;
+    if (e0 < e1)
+        split(ef, nh, n, i, j, kh);
+    for (unsigned e = e0; e < e1;) {
+        const double *own = c ? xb : xr;
+        const double *oth = c ? xr : xb;
+        // the 18 neighbours once, for both the FP64 residual and the FP32
+        // operator of x32 = fl(x64) (each neighbour rounded on load)
+        const int p = (i + j + c) & 1;
+        const int km = wrap_dn(kh - 1 + p, nh), kp = wrap_up(kh + p, nh);
+        const int ip = wrap_up(i + 1, n), im = wrap_dn(i - 1, n);
+        const int jp = wrap_up(j + 1, n), jm = wrap_dn(j - 1, n);
+        const unsigned r00 = ((unsigned)i * n + j) * nh, rp0 = ((unsigned)ip * n + j) * nh;
+        const unsigned rm0 = ((unsigned)im * n + j) * nh, r0p = ((unsigned)i * n + jp) * nh;
+        const unsigned r0m = ((unsigned)i * n + jm) * nh;
+        double v[18];
+        v[0] = oth[rp0 + kh];
+        v[1] = oth[rm0 + kh];
+        v[2] = oth[r0p + kh];
+        v[3] = oth[r0m + kh];
+        v[4] = oth[r00 + kp];
+        v[5] = oth[r00 + km];
+        if (NL) {
+            const unsigned rpp = ((unsigned)ip * n + jp) * nh, rpm = ((unsigned)ip * n + jm) * nh;
+            const unsigned rmp = ((unsigned)im * n + jp) * nh, rmm = ((unsigned)im * n + jm) * nh;
+            v[6] = own[rpp + kh];
+            v[7] = own[rpm + kh];
+            v[8] = own[rmp + kh];
+            v[9] = own[rmm + kh];
+            v[10] = own[rp0 + kp];
+            v[11] = own[rp0 + km];
+            v[12] = own[rm0 + kp];
+            v[13] = own[rm0 + km];
+            v[14] = own[r0p + kp];
+            v[15] = own[r0p + km];
+            v[16] = own[r0m + kp];
+            v[17] = own[r0m + km];
+        } else {
+            for (int q = 6; q < 18; q++)
+                v[q] = 0.0;
+        }
+        const double x64 = own[ef];
+        double tsh;
+        const double S = stencil_eval<double>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11],
+                                              v[12], v[13], v[14], v[15], v[16], v[17], NL, tsh);
+        const double b = sc.beta * (c ? F.db : F.dr)[ef];
         int isv;
-        const double r = cell_residual<double, double, NL>(F, xr, xb, c, i, j, kh, ef, cm, sc, lqt, isv);
+        const double lq = root_lap<double>(b, tsh * ih2 * ih2, sc, NL, isv);
+        const double r = lq - cm - (S - 6.0 * x64) * ih2;
         acc[0] += r * r;
         acc[1] += r;
-        acc[2] += lqt;
+        acc[2] += lq;
         acc[3] += (double)isv;
         if (!NL) {
             (c ? x32b : x32r)[ef] = 0.0f;
             (c ? G.x0b : G.x0r)[ef] = 0.0f;
             (c ? G.tb : G.tr)[ef] = (float)r;
             acc[4 + c] += (double)(float)r;
-            continue;
+        } else {
+            float tsh32;
+            const float S32 = stencil_eval<float>(
+                (float)v[0], (float)v[1], (float)v[2], (float)v[3], (float)v[4], (float)v[5], (float)v[6],
+                (float)v[7], (float)v[8], (float)v[9], (float)v[10], (float)v[11], (float)v[12], (float)v[13],
+                (float)v[14], (float)v[15], (float)v[16], (float)v[17], true, tsh32);
+            const float x32 = (float)x64;
+            const float b32 = (float)sc.beta * (c ? G.db : G.dr)[ef];
+            int isv32;
+            const float lq32 = root_lap<float>(b32, tsh32 * ih2f * ih2f, sc, true, isv32);
+            const float lap32 = (S32 - 6.0f * x32) * ih2f;
+            const float tau32 = (float)r + lap32 - lq32;
+            (c ? x32b : x32r)[ef] = x32;
+            (c ? G.x0b : G.x0r)[ef] = x32;
+            (c ? G.tb : G.tr)[ef] = tau32;
+            acc[4 + c] += (double)(lq32 + tau32);
         }
-        // FP32 operator of x32 = fl(x64), each neighbour rounded on load
-        const double *own = c ? xb : xr;
-        const double *oth = c ? xr : xb;
-        float tsh;
-        const float S = stencil_terms<float, double>(own, oth, F.n, F.nh, c, i, j, kh, NL, tsh);
-        const float x32 = (float)own[ef];
-        const float b = (float)sc.beta * (c ? G.db : G.dr)[ef];
-        int isv32;
-        const float lq32 = root_lap<float>(b, tsh * ih2f * ih2f, sc, NL, isv32);
-        const float lap32 = (S - 6.0f * x32) * ih2f;
-        const float tau32 = (float)r + lap32 - lq32;
-        (c ? x32b : x32r)[ef] = x32;
-        (c ? G.x0b : G.x0r)[ef] = x32;
-        (c ? G.tb : G.tr)[ef] = tau32;
-        acc[4 + c] += (double)(lq32 + tau32);
+        e += kBlock;
+        if (e < e1) {  // step by kBlock cells; re-split when crossing into colour 1
+            if (!c && e >= half) {
+                c = 1;
+                ef = e - half;
+                split(ef, nh, n, i, j, kh);
+            } else {
+                ef += kBlock;
+                kh += kBlock;
+                while (kh >= nh) {
+                    kh -= nh;
+                    if (++j == n) {
+                        j = 0;
+                        ++i;
+                    }
+                }
+            }
+        }
     }
     block_partials<6>(acc, rs, sp);
 }
@@ -1046,18 +849,12 @@ void launch_zero(void *p, size_t bytes, hipStream_t st)
 }
 
 // explicit instantiations
-template void launch_smooth<double>(const LevelView<double> &, int, const double *, const double *, double *,
-                                    const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
-                                    hipStream_t, int *, bool);
-template void launch_smooth<float>(const LevelView<float> &, int, const float *, const float *, float *,
-                                   const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
-                                   hipStream_t, int *, bool);
 template void launch_residual_restrict<double>(const LevelView<double> &, const double *, const double *,
                                                const double *, const LevelView<double> &, double *, double *,
-                                               ReduceSlot, SolveConsts, bool, hipStream_t);
+                                               ReduceSlot, SolveConsts, bool, hipStream_t, bool);
 template void launch_residual_restrict<float>(const LevelView<float> &, const float *, const float *, const double *,
                                               const LevelView<float> &, float *, float *, ReduceSlot, SolveConsts,
-                                              bool, hipStream_t);
+                                              bool, hipStream_t, bool);
 template void launch_fas_tau<double>(const LevelView<double> &, const double *, const double *, double *, ReduceSlot,
                                      SolveConsts, bool, bool, hipStream_t);
 template void launch_fas_tau<float>(const LevelView<float> &, const float *, const float *, double *, ReduceSlot,
@@ -1137,6 +934,15 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         }
     }
     __syncthreads();
+    auto coarsest = [&](const LevelView<R> &Cv, R *cr, R *cb) {
+        if (Cv.n == 4) {  // uniform branch: one wave solves, the block waits
+            if (tid < 64)
+                coarsest_wave<R, NL>(Cv, cr, cb, sc, coarse_sweeps, kCoarseTol);
+            __syncthreads();
+        } else {
+            coarsest_solve<R, NL>(Cv, cr, cb, sc, coarse_sweeps, kCoarseTol);
+        }
+    };
     auto xr = [&](int l) -> R * { return B.buf[l][cur[l][0]]; };
     auto xb = [&](int l) -> R * { return B.buf[l][cur[l][1]] + B.L[l].half; };
     auto half_sweep = [&](int m, int colour) {
@@ -1196,7 +1002,7 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
             __syncthreads();
             fas(m + 1, 0);
         }
-        coarsest_solve<R, NL>(B.L[L - 1], xr(L - 1), xb(L - 1), sc, coarse_sweeps, kCoarseTol);
+        coarsest(B.L[L - 1], xr(L - 1), xb(L - 1));
         for (int m = L - 2; m >= l; m--) {
             const unsigned tot = 2u * (unsigned)B.L[m + 1].half;
             R *x_r = xr(m), *x_b = xb(m), *c_r = xr(m + 1), *c_b = xb(m + 1);
@@ -1215,7 +1021,7 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         for (unsigned e = tid; e < totc; e += nt)
             xc[e] = (R)0;
         __syncthreads();
-        coarsest_solve<R, NL>(B.L[L - 1], xc, xc + B.L[L - 1].half, sc, coarse_sweeps, kCoarseTol);
+        coarsest(B.L[L - 1], xc, xc + B.L[L - 1].half);
         for (int l = L - 2; l >= l0; l--) {
             const unsigned tot = 2u * (unsigned)B.L[l + 1].half;
             R *x_r = B.buf[l][0], *x_b = B.buf[l][0] + B.L[l].half, *c_r = xr(l + 1), *c_b = xb(l + 1);

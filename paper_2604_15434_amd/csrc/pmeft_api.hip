@@ -211,7 +211,7 @@ struct Hier {
     int cs[kMaxLevels];      // current csum buffer per level
     int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
     int block_l0 = kMaxLevels;  // levels from here down run as one block cycle
-    bool tiled = true;          // 2.5D-tiled smoother on the levels it fits
+    int tiled = 1;              // 2.5D-tiled smoother: 0 off, 1 small tiles, 2 large tiles
     BlockHier<R> block() const
     {
         BlockHier<R> B;
@@ -295,7 +295,7 @@ template <typename R>
 static void set_block_level(Hier<R> &H, int ng)
 {
     const Shape sh = launch_shape(ng, (int)sizeof(R));
-    H.tiled = sh.tiled != 0;
+    H.tiled = sh.tiled;
     H.block_l0 = kMaxLevels;
     for (int l = 0; l < H.nlev - 1; l++)
         if (H.L[l].n <= sh.block_n) {
@@ -413,7 +413,7 @@ static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveCon
     }
     H.cur[l + 1][0] = H.cur[l + 1][1] = 0;
     launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
-                                sc, nl, C.st);
+                                sc, nl, C.st, false);
     launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum_cur(l + 1), C.rs, sc, nl, false, C.st);
     H.fresh(l + 1);
     vcycle_from(C, H, l + 1, o, sc, nl);
@@ -545,8 +545,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
 }
 
 // Mixed precision.  Every outer step evaluates the FP64 residual of the FP64
-// iterate (convergence test included) and hands the defect to an FP32
-// V-cycle whose result corrects the FP64 iterate.
+// iterate (convergence test included) and hands the defect to kMixedInner
+// FP32 V-cycles whose result corrects the FP64 iterate.
 //  - Linear problems (Poisson, linearised option): the FP32 V-cycle solves
 //    the correction equation lap e = r from e = 0, so the iteration has no
 //    FP32 floor.
@@ -557,6 +557,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
 //    cycle stops paying (reduction worse than 0.6), the remaining V-cycles
 //    run in FP64.
 constexpr double kMixedSwitchNL = 3e-5;
+constexpr int kMixedInner = 2;        // FP32 V-cycles per outer step
+constexpr double kMixedStall = 0.36;  // an outer step must reduce the residual at least this much (0.6 per V-cycle)
 
 static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
                        SolveOut &so, bool zero_start)
@@ -574,7 +576,7 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     const SolveConsts sc32 = nl ? sc : SolveConsts{sc.nu, 0.0, 0.0};
     const double switch_tol = fmax(kMixedSwitchNL, 30.0 * o.rel_tol);
     double out[8];
-    int it = 0;
+    int it = 0, cyc = 0;  // outer steps, FP32 V-cycles
     double prev = 0.0;
     bool to_f64 = false;
     for (;; it++) {
@@ -602,35 +604,39 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
             so.status = PM_OK;
             break;
         }
-        if (it >= o.max_vcycles) {
+        if (cyc >= o.max_vcycles) {
             so.status = PM_ENOCONV;
             break;
         }
-        if (nl && (rel <= switch_tol || (it > 0 && rel > 0.6 * prev))) {
+        if (nl && (rel <= switch_tol || (it > 0 && rel > kMixedStall * prev))) {
             to_f64 = true;
             break;
         }
         prev = rel;
-        if (it == 0 && zero_start)
-            fmg_start<float>(C, H, o, sc32, nl);
-        else
-            vcycle_from<float>(C, H, 0, o, sc32, nl);
+        // kMixedInner FP32 V-cycles per FP64 defect correction: the FP64
+        // residual and correction are paid once for all of them
+        for (int v = 0; v < kMixedInner && cyc < o.max_vcycles; v++, cyc++) {
+            if (it == 0 && v == 0 && zero_start)
+                fmg_start<float>(C, H, o, sc32, nl);
+            else
+                vcycle_from<float>(C, H, 0, o, sc32, nl);
+        }
         launch_mixed_correct(master, H.xr(0), H.xb(0), H.L[0].x0r, H.L[0].x0b, half, C.st);
     }
-    so.vcycles = it;
+    so.vcycles = cyc;
     int e = launched();
     if (e || !to_f64)
         return e;
     // finish in FP64 from the current iterate
     pm_mg_opts o64 = o;
-    o64.max_vcycles = o.max_vcycles - it;
+    o64.max_vcycles = o.max_vcycles - cyc;
     SolveOut s64;
     e = solve_f64(C, master, sc, nl, o64, src_norm, s64, false);
     if (e)
         return e;
     for (int i = 0; i <= s64.vcycles && it + i < 64; i++)
         so.hist[it + i] = s64.hist[i];
-    so.vcycles = it + s64.vcycles;
+    so.vcycles = cyc + s64.vcycles;
     so.rel = s64.rel;
     so.status = s64.status;
     so.mean_shift = s64.mean_shift;
@@ -1036,17 +1042,26 @@ int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts
 }
 
 // ---- autotuner ------------------------------------------------------------
-// Synthetic density for timing: rho = 1 + 0.9 sin(2 pi x) sin(2 pi y) sin(2 pi z)
-// on cell centres (natural order).
+// Synthetic density for timing: rho = 0.2 + 1.6 u per cell with u uniform in
+// [0, 1) from an integer hash of the cell index (mean 1, rough at every
+// scale), so that full multigrid + 3 V-cycles converge like a real field and
+// the mixed solve stays in its FP32 cycles while it is timed.
+__device__ __forceinline__ unsigned hash32(unsigned x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
 __global__ void k_synth_rho(double *rho, int n)
 {
     const unsigned long long n3 = (unsigned long long)n * n * n;
     for (unsigned long long e = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; e < n3;
-         e += (unsigned long long)gridDim.x * blockDim.x) {
-        const int k = (int)(e % n), j = (int)((e / n) % n), i = (int)(e / ((unsigned long long)n * n));
-        const double tp = 6.283185307179586 / n;
-        rho[e] = 1.0 + 0.9 * sin(tp * (i + 0.5)) * sin(tp * (j + 0.5)) * sin(tp * (k + 0.5));
-    }
+         e += (unsigned long long)gridDim.x * blockDim.x)
+        rho[e] = 0.2 + 1.6 * ((double)hash32((unsigned)e * 2654435761u + 12345u) * (1.0 / 4294967296.0));
 }
 
 size_t pm_autotune_workspace_bytes(int ng, int precision)
@@ -1071,8 +1086,8 @@ int pm_get_launch_shape(int ng, int word_bytes, int *block_cycle_grid, int *tile
 
 int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid, int tiled_smoother)
 {
-    if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8 ||
-        (tiled_smoother != 0 && tiled_smoother != 1))
+    if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8 || tiled_smoother < 0 ||
+        tiled_smoother > 2)
         return PM_EINVAL;
     set_shape(Shape{ng, word_bytes, block_cycle_grid, tiled_smoother});
     return PM_OK;
@@ -1104,7 +1119,7 @@ int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t st
     const int cands[5] = {0, 8, 16, 32, 64};
     Shape best = launch_shape(ng, word);
     float best_ms = 1e30f;
-    for (int tiled = 0; tiled < 2; tiled++)
+    for (int tiled = 0; tiled < 3; tiled++)
         for (int c = 0; c < 5; c++) {
             const int n = cands[c];
             if (n >= ng)
@@ -1112,7 +1127,7 @@ int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t st
             const Shape sh{ng, word, n, tiled};
             set_shape(sh);
             float ms = 1e30f;
-            for (int rep = 0; rep < 3; rep++) {  // first run warms up
+            for (int rep = 0; rep < 4; rep++) {  // first run warms up
                 pm_mg_report r;
                 const int e = grid_solve(rho, ng, PM_F64, &p, &o, chi, &r, ws, solver, stream, true);
                 if (e != PM_OK && e != PM_ENOCONV) {
@@ -1160,7 +1175,7 @@ int pm_tune_load(const char *path)
             continue;
         int ng, word, n, tiled;
         if (sscanf(line, "%d %d %d %d", &ng, &word, &n, &tiled) != 4 || (word != 4 && word != 8) || n < 0 ||
-            ng < 8 || (tiled != 0 && tiled != 1)) {
+            ng < 8 || tiled < 0 || tiled > 2) {
             rc = PM_EINVAL;
             break;
         }

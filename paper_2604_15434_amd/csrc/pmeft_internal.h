@@ -161,7 +161,7 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 template <typename R>
 void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
                    double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
-                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, bool tiled);
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, int tiled);
 
 // Fine-level residual r = Lq + tau - c - lap x fused with the 8-child
 // restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
@@ -170,7 +170,7 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
 template <typename R>
 void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
                               const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
-                              hipStream_t st);
+                              hipStream_t st, bool norms = true);
 
 // Coarse FAS source: tau += lap x - Lq(x) (unless accumulate_only or the
 // level has no tau); writes sum(Lq + tau) per colour into csum[0..1].

@@ -1,0 +1,239 @@
+// Red-black half-sweeps of the multigrid levels (gfx950): the grid-wide
+// kernel for every level and the 2.5D-tiled kernel for the large levels.
+// The operator and the cell update are those of mg_stencil.h.
+#include "mg_stencil.h"
+
+#include <math.h>
+
+namespace pmeft {
+
+// One half-sweep of colour `colour`.  The lagged mean c = <Lq + tau> comes
+// from csum_in (per-colour sums).  Block 0 also folds the partial sums of the
+// previous half-sweep at this level (prev, prev_nblocks, prev_colour; colour
+// -1 = none) into csum_out, which the next half-sweep reads: the mean thus
+// lags by about one sweep, needs no extra launch, and stays deterministic
+// (every launch reads only values completed by earlier launches).
+template <typename R, bool NL>
+__global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, const R *__restrict__ xc_old,
+                                                   const R *__restrict__ xo, R *__restrict__ xc_new,
+                                                   const double *__restrict__ csum_in, double *__restrict__ csum_out,
+                                                   const double *__restrict__ prev, int prev_nblocks, int prev_colour,
+                                                   ReduceSlot rs, SolveConsts sc, Span sp)
+{
+    const int n = L.n, nh = L.nh;
+    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
+    const R h2 = (R)(L.h * L.h);
+    const R ih2 = (R)(1.0 / (L.h * L.h));
+    const R *dc = colour ? L.db : L.dr;
+    const R *tc = colour ? L.tb : L.tr;
+    double acc[1] = {0.0};
+    const unsigned lb = span_block(sp);
+    const unsigned e0 = lb * sp.chunk + threadIdx.x;
+    const unsigned e1 = min(sp.total, (lb + 1) * sp.chunk);
+    int i, j, kh;
+    if (e0 < e1)
+        split(e0, nh, n, i, j, kh);
+    for (unsigned e = e0; e < e1;) {
+        acc[0] += (double)smooth_cell<R, NL>(xc_old, xo, xc_new, dc, tc, n, nh, colour, i, j, kh, e, cmean, h2, ih2, sc);
+        e += kBlock;
+        if (e < e1) {  // step (i, j, kh) by kBlock cells without dividing
+            kh += kBlock;
+            while (kh >= nh) {
+                kh -= nh;
+                if (++j == n) {
+                    j = 0;
+                    ++i;
+                }
+            }
+        }
+    }
+    block_partials<1>(acc, rs, sp);
+    if (blockIdx.x == 0)
+        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
+}
+
+// 2.5D-tiled half-sweep for the large levels: a tile is TJ = CJ * 256 / TK
+// rows in j by TK elements in kh by PL planes in i; each thread computes CJ
+// cells of a plane (rows tj, tj + 256/TK, ...).  The block keeps a
+// three-plane window of both colours (one halo row / element on each side) in
+// LDS and marches along i, issuing the next plane's loads into registers
+// before computing the current plane.  Each cell update is k_smooth's
+// arithmetic on the same operands (bitwise the same value); only the
+// grouping of the per-block partial sums of Lq + tau differs.  Blocks take
+// tiles lb, lb + nblocks, ... so that nblocks <= kMaxBlocks.
+template <typename R, bool NL, int TK, int CJ, int PL>
+__global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colour, const R *__restrict__ xc_old,
+                                                        const R *__restrict__ xo, R *__restrict__ xc_new,
+                                                        const double *__restrict__ csum_in, double *__restrict__ csum_out,
+                                                        const double *__restrict__ prev, int prev_nblocks,
+                                                        int prev_colour, ReduceSlot rs, SolveConsts sc, Span sp,
+                                                        unsigned ntiles)
+{
+    constexpr int RS = kBlock / TK;  // rows per pass of the block
+    constexpr int TJ = CJ * RS;
+    constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
+    constexpr int PER = (2 * W + kBlock - 1) / kBlock;
+    __shared__ R win[2][3][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour
+    const int n = L.n, nh = L.nh;
+    const int nK = nh / TK, nI = n / PL;
+    const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
+    const R h2 = (R)(L.h * L.h);
+    const R ih2 = (R)(1.0 / (L.h * L.h));
+    const R *dc = colour ? L.db : L.dr;
+    const R *tc = colour ? L.tb : L.tr;
+    const int tj = threadIdx.x / TK, tk = threadIdx.x % TK;
+    double acc[1] = {0.0};
+    R pre[PER];
+    for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
+        const int ib = (int)(tile % nI), kb = (int)((tile / nI) % nK), jb = (int)(tile / ((unsigned)nI * nK));
+        const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
+        // window element q of a plane: colour q / W, row (q % W) / (TK + 2), column (q % W) % (TK + 2)
+        auto fetch = [&](int ii) {
+            ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int q = threadIdx.x + u * kBlock;
+                if (q < 2 * W) {
+                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
+                    int jj = j0 - 1 + r, kk = k0 - 1 + c;
+                    jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
+                    kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
+                    pre[u] = (which ? xo : xc_old)[((unsigned)ii * n + jj) * nh + kk];
+                }
+            }
+        };
+        auto store = [&](int slot) {
+#pragma unroll
+            for (int u = 0; u < PER; u++) {
+                const int q = threadIdx.x + u * kBlock;
+                if (q < 2 * W) {
+                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
+                    win[which][slot][r][c] = pre[u];
+                }
+            }
+        };
+        fetch(i0 - 1);
+        store(0);
+        fetch(i0);
+        store(1);
+        fetch(i0 + 1);
+        store(2);
+        __syncthreads();
+        for (int t = 0; t < PL; t++) {
+            const int i = i0 + t;
+            const int sm = t % 3, s0 = (t + 1) % 3, sp1 = (t + 2) % 3;  // planes i - 1, i, i + 1
+            if (t + 1 < PL)
+                fetch(i + 2);  // into registers, stored after this plane
+#pragma unroll
+            for (int cj = 0; cj < CJ; cj++) {
+                const int j = j0 + tj + cj * RS, kh = k0 + tk;
+                const int p = (i + j + colour) & 1;
+                const int a = tj + cj * RS + 1, b = tk + 1;  // window coordinates of the cell
+                const int bm = tk + p, bp = tk + 1 + p;      // its kh - 1 + p and kh + p neighbours
+                R tsh;
+                R S;
+                if (NL)
+                    S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b],
+                                        win[1][s0][a - 1][b], win[1][s0][a][bp], win[1][s0][a][bm],
+                                        win[0][sp1][a + 1][b], win[0][sp1][a - 1][b], win[0][sm][a + 1][b],
+                                        win[0][sm][a - 1][b], win[0][sp1][a][bp], win[0][sp1][a][bm],
+                                        win[0][sm][a][bp], win[0][sm][a][bm], win[0][s0][a + 1][bp],
+                                        win[0][s0][a + 1][bm], win[0][s0][a - 1][bp], win[0][s0][a - 1][bm], true, tsh);
+                else
+                    S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b],
+                                        win[1][s0][a - 1][b], win[1][s0][a][bp], win[1][s0][a][bm], (R)0, (R)0, (R)0,
+                                        (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, false, tsh);
+                const unsigned e = ((unsigned)i * n + j) * nh + kh;
+                const R bsrc = (R)sc.beta * dc[e];
+                int isv;
+                const R lq = root_lap<R>(bsrc, tsh * ih2 * ih2, sc, NL, isv);
+                const R v = lq + (tc ? tc[e] : (R)0);
+                xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
+                acc[0] += (double)v;
+            }
+            __syncthreads();
+            if (t + 1 < PL)
+                store(sm);  // plane i + 2 replaces plane i - 1
+            __syncthreads();
+        }
+    }
+    block_partials<1>(acc, rs, sp);
+    if (blockIdx.x == 0)
+        fold_previous(csum_in, csum_out, prev, prev_nblocks, prev_colour);
+}
+
+// Tile configuration of a level for a tiling choice (1: small tiles, 2:
+// large tiles where they still give at least 512 tiles, else small):
+// 0 = untiled; 1 = (TK 64, CJ 2, 16 planes); 2 = (TK 64, CJ 1, 8 planes);
+// 3 = (TK 32, CJ 1, 8 planes).
+static inline int tile_config(int n, int choice)
+{
+    if (choice == 0 || n < 64)
+        return 0;
+    const int nh = n / 2;
+    if (choice == 2 && nh % 64 == 0 && n % 16 == 0 && (n / 8) * (nh / 64) * (n / 16) >= 512)
+        return 1;
+    if (nh % 64 == 0 && n % 8 == 0)
+        return 2;
+    if (nh % 32 == 0 && n % 8 == 0)
+        return 3;
+    return 0;
+}
+
+template <typename R>
+void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *xo, R *xc_new, const double *csum_in,
+                   double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
+                   SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, int tiled)
+{
+    const int cfg = tile_config(L.n, tiled);
+    if (cfg) {
+        const int TK = cfg == 3 ? 32 : 64, TJ = cfg == 1 ? 2 * kBlock / TK : kBlock / TK, PL = cfg == 1 ? 16 : 8;
+        const unsigned ntiles = (unsigned)((L.n / TJ) * (L.nh / TK) * (L.n / PL));
+        // Span only carries the block count (XCD mapping, partials)
+        Span sp;
+        unsigned nb = ntiles < (unsigned)kMaxBlocks ? ntiles : (unsigned)kMaxBlocks;
+        if (nb >= 8)
+            nb -= nb % 8;
+        sp.nblocks = nb;
+        sp.chunk = kBlock;
+        sp.total = nb * kBlock;
+        *nblocks_out = (int)nb;
+#define PM_TILE(NLV, TKV, CJV, PLV)                                                                                    \
+    hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV, CJV, PLV>), dim3(nb), dim3(kBlock), 0, st, L, colour, xc_old, xo,    \
+                       xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
+        if (nonlinear) {
+            if (cfg == 1)
+                PM_TILE(true, 64, 2, 16);
+            else if (cfg == 2)
+                PM_TILE(true, 64, 1, 8);
+            else
+                PM_TILE(true, 32, 1, 8);
+        } else {
+            if (cfg == 1)
+                PM_TILE(false, 64, 2, 16);
+            else if (cfg == 2)
+                PM_TILE(false, 64, 1, 8);
+            else
+                PM_TILE(false, 32, 1, 8);
+        }
+#undef PM_TILE
+        return;
+    }
+    const Span sp = make_span(L.half);
+    *nblocks_out = (int)sp.nblocks;
+    if (nonlinear)
+        hipLaunchKernelGGL((k_smooth<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
+                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
+    else
+        hipLaunchKernelGGL((k_smooth<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
+                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
+}
+
+template void launch_smooth<double>(const LevelView<double> &, int, const double *, const double *, double *,
+                                    const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
+                                    hipStream_t, int *, int);
+template void launch_smooth<float>(const LevelView<float> &, int, const float *, const float *, float *,
+                                   const double *, double *, const double *, int, int, ReduceSlot, SolveConsts, bool,
+                                   hipStream_t, int *, int);
+
+}  // namespace pmeft

@@ -136,6 +136,97 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, 
     }
 }
 
+// LDS-staged variant for grids with n % 64 == 0: a block computes a tile of
+// 4 rows (j) x 64 voxels (k) of one plane (i) for COT*16 output channels.
+// For every 16-channel input slice it stages the 3 x 6 x 66 voxel
+// neighbourhood of the tile in LDS (voxel stride 20 bf16 = 40 bytes, which
+// spreads a wave's 8-byte fragment reads over distinct banks), then each wave
+// (one row) runs the 27 taps x 4 voxel tiles x COT channel tiles from LDS.
+// The operands and their order per output are those of k_conv3 (bitwise the
+// same result).
+constexpr int kCvRows = 4, kCvK = 64, kCvStride = 20;
+constexpr int kCvVox = 3 * (kCvRows + 2) * (kCvK + 2);
+
+template <int COT>
+__global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ in, int in_stride, int in_off,
+                                                   int cin_pad, const uint16_t *__restrict__ wp, int cout_pad,
+                                                   const float *__restrict__ bias, int cout, void *__restrict__ out,
+                                                   int out_stride, int out_off, int out_f32, int n, int flip, int relu,
+                                                   unsigned ntiles)
+{
+    __shared__ __align__(16) uint16_t tile[kCvVox * kCvStride];
+    const unsigned t = xcd_block(0);
+    if (t >= ntiles)
+        return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int nkt = n / kCvK, njt = n / kCvRows;
+    const int kt = (int)(t % nkt), jt = (int)((t / nkt) % njt), i = (int)(t / ((unsigned)nkt * njt));
+    const int j0 = jt * kCvRows, k0 = kt * kCvK;
+    const int co_base = blockIdx.y * COT * 16;
+    const int sgn = flip ? -1 : 1;
+    f32x4 acc[4][COT];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int u = 0; u < COT; u++)
+            acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < cin_pad; c0 += 16) {
+        // stage the neighbourhood: voxel v = (plane * 6 + row) * 66 + col, 16 channels as 4 x 8 bytes
+        for (int u = threadIdx.x; u < kCvVox * 4; u += 256) {
+            const int v = u >> 2, part = u & 3;
+            const int pl = v / ((kCvRows + 2) * (kCvK + 2));
+            const int rem = v - pl * (kCvRows + 2) * (kCvK + 2);
+            const int row = rem / (kCvK + 2), col = rem - row * (kCvK + 2);
+            const int ii = wrapi(i + pl - 1, n), jj = wrapi(j0 + row - 1, n), kk = wrapi(k0 + col - 1, n);
+            const uint2 val =
+                *(const uint2 *)(in + (size_t)((ii * n + jj) * n + kk) * in_stride + in_off + c0 + 4 * part);
+            *(uint2 *)(tile + v * kCvStride + 4 * part) = val;
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 27; tap++) {
+            int di, dj, dk;
+            tap_offsets(tap, di, dj, dk);
+            const int pl = 1 + sgn * di, row = 1 + wave + sgn * dj, colb = 1 + r + sgn * dk;
+            const uint16_t *tb = tile + ((pl * (kCvRows + 2) + row) * (kCvK + 2) + colb) * kCvStride + 4 * q;
+            bf16x4 a[4], b[COT];
+#pragma unroll
+            for (int m = 0; m < 4; m++)
+                a[m] = *(const bf16x4 *)(tb + 16 * m * kCvStride);
+#pragma unroll
+            for (int u = 0; u < COT; u++)
+                b[u] = *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * cin_pad + c0 + 4 * q);
+#pragma unroll
+            for (int m = 0; m < 4; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], b[u], acc[m][u], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const size_t vbase = (size_t)((i * n + j0 + wave) * n + k0);
+#pragma unroll
+    for (int u = 0; u < COT; u++) {
+        const int o = co_base + u * 16 + r;
+        if (o >= cout)
+            continue;
+        const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                float v = acc[m][u][e] + bo;
+                if (relu)
+                    v = fmaxf(v, 0.f);
+                const size_t idx = (vbase + 16 * m + 4 * q + e) * out_stride + out_off + o;
+                if (out_f32)
+                    ((float *)out)[idx] = v;
+                else
+                    ((uint16_t *)out)[idx] = f2bf(v);
+            }
+    }
+}
+
 template <int MT>
 static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp,
                             int cout_pad, const float *bias, int cout, void *out, int out_stride, int out_off,
@@ -165,6 +256,25 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
                   const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
                   bool relu, hipStream_t st)
 {
+    if (n % kCvK == 0 && in_stride % 4 == 0 && in_off % 4 == 0) {
+        const unsigned ntiles = (unsigned)n * (n / kCvRows) * (n / kCvK);
+        const int tiles = cout_pad / 16;
+        const int cot = tiles % 4 == 0 ? 4 : (tiles % 3 == 0 ? 3 : (tiles % 2 == 0 ? 2 : 1));
+        dim3 grid(xcd_blocks(ntiles), cout_pad / (cot * 16));
+#define PM_CONVL(C)                                                                                                    \
+    hipLaunchKernelGGL((k_conv3_lds<C>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad, bias,   \
+                       cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles)
+        if (cot == 4)
+            PM_CONVL(4);
+        else if (cot == 3)
+            PM_CONVL(3);
+        else if (cot == 2)
+            PM_CONVL(2);
+        else
+            PM_CONVL(1);
+#undef PM_CONVL
+        return;
+    }
     if (n % 64 == 0)
         launch_conv3_mt<4>(in, in_stride, in_off, cin_pad, wp, cout_pad, bias, cout, out, out_stride, out_off,
                            out_f32, n, flip, relu, st);

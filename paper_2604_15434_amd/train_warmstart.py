@@ -1,9 +1,10 @@
 """Training driver of the learned warm start (runs on the GPU).
 
-Samples are lognormal density fields (log-sigma 1.5, power-law-break
-spectrum) on 64^3 and 128^3 grids whose cell matches the 256^3 / 500 Mpc/h
-workload (box = 500 ng / 256 Mpc/h), each with its own (alpha_B0 ~ U[-1, 0],
-alpha_M0 ~ U[0, 0.2], a ~ U[0.2, 1]).  Labels are the scalar fields solved by
+Samples are ng^3 particles drawn from lognormal density fields (log-sigma
+1.5, power-law-break spectrum) and deposited by the library's CIC kernel, as
+the PM step sees them (shot noise included), on 64^3 and 128^3 grids whose
+cell matches the 256^3 / 500 Mpc/h workload (box = 500 ng / 256 Mpc/h), each
+with its own (alpha_B0 ~ U[-1, 0], alpha_M0 ~ U[0, 0.2], a ~ U[0.2, 1]).  Labels are the scalar fields solved by
 this library in FP64 to relative residual 1e-8; the network learns the
 nonlinear part t of the normalised source (see include/pmeft.h).  Every
 forward, backward and Adam step runs in the library's kernels.
@@ -25,22 +26,24 @@ import numpy as np
 CELL_MPC = 500.0 / 256
 
 
-def _density(args):
-    from workloads import lognormal_density
+def _particles(args):
+    from workloads import lognormal_particles
 
     ng, seed = args
-    return lognormal_density(ng, CELL_MPC * ng, seed=seed)
+    pos, _ = lognormal_particles(ng, CELL_MPC * ng, seed=seed)
+    return pos
 
 
-def make_samples(n64, n128, seed0=1000, workers=8):
-    """(ng, seed, params) of each sample and its density (host arrays)."""
+def iter_samples(n64, n128, seed0=1000, workers=12):
+    """(ng, seed, params, pos) of each sample: ng^3 particles drawn from a
+    lognormal density, as the PM step deposits them (shot noise included)."""
     from workloads import scan_params
 
     specs = [(64, seed0 + i) for i in range(n64)] + [(128, seed0 + n64 + i) for i in range(n128)]
     params = scan_params(len(specs), seed=seed0)
     with ProcessPoolExecutor(max_workers=workers) as ex:
-        rhos = list(ex.map(_density, specs, chunksize=8))
-    return [(ng, sd, p, r) for (ng, sd), p, r in zip(specs, params, rhos)]
+        for (ng, sd), p, pos in zip(specs, params, ex.map(_particles, specs, chunksize=4)):
+            yield ng, sd, p, pos
 
 
 def label(P, torch, rho_d, prm, tol=1e-8):
@@ -84,15 +87,14 @@ def main(argv=None):
     from paper_2604_15434_amd.warmstart import WarmStart
 
     t0 = time.time()
-    samples = make_samples(args.n64, args.n128)
-    print(f"[train] {len(samples)} densities in {time.time() - t0:.1f} s", flush=True)
     data = []
-    t1 = time.time()
-    for idx, (ng, sd, prm, rho) in enumerate(samples):
+    n_all = args.n64 + args.n128
+    for idx, (ng, sd, prm, pos) in enumerate(iter_samples(args.n64, args.n128)):
         c = P.pm_eft_coefficients(prm)
         if not (c["nu"] > 0):
             continue
-        rho_d = torch.from_numpy(rho).cuda()
+        rho_d = torch.empty((ng, ng, ng), dtype=torch.float64, device="cuda")
+        P.pm_deposit(torch.from_numpy(pos).cuda(), ng, rho_d)
         chi_d, rep = label(P, torch, rho_d, prm)
         if rep["status"] != 0:
             print(f"[train] sample {idx} (ng {ng}, seed {sd}) label not converged: {rep['rel_residual']:.2e}",
@@ -100,14 +102,13 @@ def main(argv=None):
             continue
         data.append((ng, sd, prm, rho_d, chi_d))
         if idx % 200 == 0:
-            print(f"[train] labels {idx}/{len(samples)} ({time.time() - t1:.1f} s)", flush=True)
+            print(f"[train] samples {idx}/{n_all} ({time.time() - t0:.1f} s)", flush=True)
     rng = np.random.default_rng(args.seed)
     order = rng.permutation(len(data))
     n_hold = max(4, int(args.holdout * len(data)))
     hold = [data[i] for i in order[:n_hold]]
     train = [data[i] for i in order[n_hold:]]
-    print(f"[train] {len(train)} training / {len(hold)} held-out samples; labels {time.time() - t1:.1f} s",
-          flush=True)
+    print(f"[train] {len(train)} training / {len(hold)} held-out samples; data {time.time() - t0:.1f} s", flush=True)
 
     net = WarmStart.load(args.init) if args.init else WarmStart(seed=args.seed)
 
@@ -176,7 +177,8 @@ def main(argv=None):
               "  ".join(f"{g} {x['vcycles']} cyc {x['ms']:.2f} ms" for g, x in r.items()), flush=True)
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     meta = dict(samples=dict(n64=args.n64, n128=args.n128, seed0=1000, holdout=len(hold), train=len(train),
-                             cell_mpc=CELL_MPC, sigma_g=1.5, label_tol=1e-8),
+                             cell_mpc=CELL_MPC, sigma_g=1.5, label_tol=1e-8,
+                             density="CIC deposit of ng^3 lognormal particles"),
                 training=dict(steps=step, epochs=epoch, seconds=round(time.time() - t2, 1), lr=args.lr,
                               schedule="linear warmup over 1000 steps, cosine to 1e-5 over the time budget",
                               clipping="global norm, twice the median of the last 200 sampled norms", batch=1,

@@ -86,8 +86,10 @@ def test_launch_shape_table_roundtrip(tmp_path):
     assert P.pm_get_launch_shape(96, 8) == (16, 0) and P.pm_get_launch_shape(96, 4) == (0, 1)
     with pytest.raises(P.PmError):
         P.pm_set_launch_shape(96, 2, 16)
+    P.pm_set_launch_shape(96, 8, 16, 2)
+    assert P.pm_get_launch_shape(96, 8) == (16, 2)
     with pytest.raises(P.PmError):
-        P.pm_set_launch_shape(96, 8, 16, 2)
+        P.pm_set_launch_shape(96, 8, 16, 3)
     bad = tmp_path / "bad.txt"
     bad.write_text("96 3 16 1\n")
     with pytest.raises(P.PmError):

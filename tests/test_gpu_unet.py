@@ -176,8 +176,8 @@ def test_learned_guess_rejects_bad_grid(P):
 
 def test_trained_network_gain_on_held_out_fields(P):
     """What the trained network (committed weights) gains over the method
-    without it, on 128^3 lognormal fields of seeds outside the training range
-    and fresh parameter draws: its source error is far below the untrained
+    without it, on deposited 128^3 lognormal particle loads of seeds outside
+    the training range and fresh parameter draws: its source error is far below the untrained
     network's, the solve from its guess starts from a smaller residual than
     the zero-guess full multigrid and never needs more V-cycles, and the
     final field is the zero-guess one.  (Wall time is reported, not asserted:
@@ -185,7 +185,7 @@ def test_trained_network_gain_on_held_out_fields(P):
     import os
 
     from paper_2604_15434_amd.warmstart import DEFAULT_WEIGHTS, WarmStart
-    from workloads import lognormal_density, scan_params
+    from workloads import lognormal_particles, scan_params
 
     if not os.path.exists(DEFAULT_WEIGHTS):
         pytest.skip("no trained weights")
@@ -194,7 +194,9 @@ def test_trained_network_gain_on_held_out_fields(P):
     n = 128
     prms = scan_params(4, seed=5000)
     for k, prm in enumerate(prms):
-        rho = torch.from_numpy(lognormal_density(n, 250.0, seed=5000 + k)).cuda()
+        pos, _ = lognormal_particles(n, 250.0, seed=5000 + k)
+        rho = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        P.pm_deposit(torch.from_numpy(pos).cuda(), n, rho)
         ref = torch.zeros_like(rho)
         P.mg_scalar_solve(rho, prm, P.MgOpts(rel_tol=1e-10, max_vcycles=80), ref)
         e_tr = math.sqrt(net.train_step(rho, ref, prm, 0.0)) / float(rho.std())

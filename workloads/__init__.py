@@ -6,6 +6,7 @@ both the CPU oracle and the GPU path can take their inputs from it without
 sharing any of the method's code.
 """
 from .ics import (  # noqa: F401
+    expected_variance,
     gaussian_field,
     lattice_displacement_ics,
     zeldovich_ics,

@@ -143,12 +143,32 @@ def zeldovich_ics(ng, box, seed, pk=None, np_side=None):
     return np.mod(_lattice(nps) + psi, 1.0)
 
 
-def lognormal_density(ng, box, seed, sigma_g=1.5, pk=None):
-    """Lognormal density rho = e^g / <e^g> with Gaussian g of std ``sigma_g``."""
+def expected_variance(ng, box, pk):
+    """Expected per-cell variance of gaussian_field(ng, box, pk): the sum of
+    P(k) / L^3 over the modes it keeps (zero mode and Nyquist planes out)."""
+    kx, ky, kz = _kvec(ng, box)
+    k = np.sqrt(kx**2 + ky**2 + kz**2)
+    p = np.zeros_like(k)
+    nz = k > 0
+    p[nz] = pk(k[nz])
+    p = p * _nyquist_mask(ng)
+    w = np.full(p.shape, 2.0)
+    w[..., 0] = 1.0  # kz = 0 plane counted once; the Nyquist plane is masked
+    return float(np.sum(w * p) / box**3)
+
+
+def lognormal_density(ng, box, seed, sigma_g=1.5, pk=None, ref_grid=None):
+    """Lognormal density rho = e^g / <e^g>.  g has std ``sigma_g`` in the box
+    itself, or, with ref_grid = (ng_ref, box_ref), the amplitude that gives
+    std sigma_g on that reference grid (same P(k) per mode: a smaller box of
+    the same cell size then lacks only the long modes)."""
     if pk is None:
         pk = pk_powerlaw_break
     g = gaussian_field(ng, box, pk, seed=seed)
-    g *= sigma_g / g.std()
+    if ref_grid is None:
+        g *= sigma_g / g.std()
+    else:
+        g *= sigma_g / math.sqrt(expected_variance(ref_grid[0], ref_grid[1], pk))
     e = np.exp(g - g.max())
     return e / e.mean()
 
