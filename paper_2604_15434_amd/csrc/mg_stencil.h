@@ -23,6 +23,10 @@ __device__ __forceinline__ T root_lap(T b, T Tsh, const SolveConsts &sc, bool no
         is_void = 0;
         return b / nu;
     }
+    // Tsh is pinned here (an empty asm statement that reads it): otherwise the
+    // compiler sinks the loads of its operands into the non-void branch below,
+    // and every cell waits for two rounds of memory latency instead of one
+    asm volatile("" ::"v"(Tsh));
     const T K = (T)sc.K;
     const T dsph = nu * nu - (T)(8.0 / 3.0) * K * b;
     if (dsph < (T)0) {
@@ -32,7 +36,10 @@ __device__ __forceinline__ T root_lap(T b, T Tsh, const SolveConsts &sc, bool no
     is_void = 0;
     const T G = K * Tsh - b;
     const T disc = dsph + (T)(8.0 / 3.0) * K * K * Tsh;
-    return (T)-2 * G / (nu + sqrt(disc));
+    if constexpr (sizeof(T) == 4)  // FP32 smoothing: hardware sqrt and reciprocal (1 ulp each)
+        return (T)-2 * G * __builtin_amdgcn_rcpf(nu + __builtin_amdgcn_sqrtf(disc));
+    else
+        return (T)-2 * G / (nu + sqrt(disc));
 }
 
 // Operator pieces from the 18 neighbour values of a cell: the six face
@@ -129,11 +136,14 @@ __device__ __forceinline__ R smooth_cell(const R *__restrict__ xc_old, const R *
                                          int i, int j, int kh, unsigned e, R cmean, R h2, R ih2, const SolveConsts &sc)
 {
     R tsh;
+    const R tv = tc ? tc[e] : (R)0;
+    const R dv = dc[e];
     const R S = stencil_terms<R, R>(xc_old, xo, n, nh, colour, i, j, kh, NL, tsh);
-    const R b = (R)sc.beta * dc[e];
+    asm volatile("" ::"v"(tv), "v"(dv));  // loaded with the stencil operands, not after the root
+    const R b = (R)sc.beta * dv;
     int isv;
     const R lq = root_lap<R>(b, tsh * ih2 * ih2, sc, NL, isv);
-    const R v = lq + (tc ? tc[e] : (R)0);
+    const R v = lq + tv;
     xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
     return v;
 }

@@ -56,8 +56,9 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, c
 // rows in j by TK elements in kh by PL planes in i; each thread computes CJ
 // cells of a plane (rows tj, tj + 256/TK, ...).  The block keeps a
 // three-plane window of both colours (one halo row / element on each side) in
-// LDS and marches along i, issuing the next plane's loads into registers
-// before computing the current plane.  Each cell update is k_smooth's
+// a four-slot LDS ring and marches along i, issuing the next plane's loads
+// into registers before computing the current plane and storing them into the
+// free slot after it (one barrier per plane).  Each cell update is k_smooth's
 // arithmetic on the same operands (bitwise the same value); only the
 // grouping of the per-block partial sums of Lq + tau differs.  Blocks take
 // tiles lb, lb + nblocks, ... so that nblocks <= kMaxBlocks.
@@ -73,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
     constexpr int TJ = CJ * RS;
     constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
     constexpr int PER = (2 * W + kBlock - 1) / kBlock;
-    __shared__ R win[2][3][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour
+    __shared__ R win[2][4][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour; 4-plane ring
     const int n = L.n, nh = L.nh;
     const int nK = nh / TK, nI = n / PL;
     const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
@@ -87,30 +88,40 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
         const int ib = (int)(tile % nI), kb = (int)((tile / nI) % nK), jb = (int)(tile / ((unsigned)nI * nK));
         const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
-        // window element q of a plane: colour q / W, row (q % W) / (TK + 2), column (q % W) % (TK + 2)
+        // this thread's window elements, resolved once per tile: source
+        // array, offset within a plane (periodic wrap applied) and LDS slot
+        // offset; element q: colour q / W, row (q % W) / (TK + 2), column
+        // (q % W) % (TK + 2)
+        const R *src[PER];
+        unsigned poff[PER];
+        int loff[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int q = threadIdx.x + u * kBlock;
+            const int qq = q < 2 * W ? q : 0;
+            const int which = qq / W, r = (qq % W) / (TK + 2), c = (qq % W) % (TK + 2);
+            int jj = j0 - 1 + r, kk = k0 - 1 + c;
+            jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
+            kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
+            src[u] = which ? xo : xc_old;
+            poff[u] = (unsigned)jj * nh + kk;
+            loff[u] = (which * 4 * (TJ + 2) + r) * (TK + 2) + c;
+        }
+        const unsigned plane = (unsigned)n * nh;
+        R *wflat = &win[0][0][0][0];
         auto fetch = [&](int ii) {
             ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
+            const unsigned base = (unsigned)ii * plane;
 #pragma unroll
-            for (int u = 0; u < PER; u++) {
-                const int q = threadIdx.x + u * kBlock;
-                if (q < 2 * W) {
-                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
-                    int jj = j0 - 1 + r, kk = k0 - 1 + c;
-                    jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
-                    kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
-                    pre[u] = (which ? xo : xc_old)[((unsigned)ii * n + jj) * nh + kk];
-                }
-            }
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kBlock < 2 * W)
+                    pre[u] = src[u][base + poff[u]];
         };
         auto store = [&](int slot) {
 #pragma unroll
-            for (int u = 0; u < PER; u++) {
-                const int q = threadIdx.x + u * kBlock;
-                if (q < 2 * W) {
-                    const int which = q / W, r = (q % W) / (TK + 2), c = (q % W) % (TK + 2);
-                    win[which][slot][r][c] = pre[u];
-                }
-            }
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kBlock < 2 * W)
+                    wflat[loff[u] + slot * (TJ + 2) * (TK + 2)] = pre[u];
         };
         fetch(i0 - 1);
         store(0);
@@ -118,12 +129,27 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
         store(1);
         fetch(i0 + 1);
         store(2);
+        // density and tau of this thread's cells, one plane ahead as well
+        const unsigned e00 = ((unsigned)i0 * n + j0 + tj) * nh + k0 + tk;
+        R dcur[CJ], tcur[CJ], dnxt[CJ], tnxt[CJ];
+#pragma unroll
+        for (int cj = 0; cj < CJ; cj++) {
+            dcur[cj] = dc[e00 + cj * RS * nh];
+            tcur[cj] = tc ? tc[e00 + cj * RS * nh] : (R)0;
+        }
         __syncthreads();
         for (int t = 0; t < PL; t++) {
             const int i = i0 + t;
-            const int sm = t % 3, s0 = (t + 1) % 3, sp1 = (t + 2) % 3;  // planes i - 1, i, i + 1
-            if (t + 1 < PL)
+            const int sm = t & 3, s0 = (t + 1) & 3, sp1 = (t + 2) & 3;  // planes i - 1, i, i + 1
+            if (t + 1 < PL) {
                 fetch(i + 2);  // into registers, stored after this plane
+#pragma unroll
+                for (int cj = 0; cj < CJ; cj++) {
+                    const unsigned en = e00 + (unsigned)(t + 1) * plane + cj * RS * nh;
+                    dnxt[cj] = dc[en];
+                    tnxt[cj] = tc ? tc[en] : (R)0;
+                }
+            }
 #pragma unroll
             for (int cj = 0; cj < CJ; cj++) {
                 const int j = j0 + tj + cj * RS, kh = k0 + tk;
@@ -144,16 +170,24 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
                                         win[1][s0][a - 1][b], win[1][s0][a][bp], win[1][s0][a][bm], (R)0, (R)0, (R)0,
                                         (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, false, tsh);
                 const unsigned e = ((unsigned)i * n + j) * nh + kh;
-                const R bsrc = (R)sc.beta * dc[e];
+                const R tv = tcur[cj];
+                const R bsrc = (R)sc.beta * dcur[cj];
                 int isv;
                 const R lq = root_lap<R>(bsrc, tsh * ih2 * ih2, sc, NL, isv);
-                const R v = lq + (tc ? tc[e] : (R)0);
+                const R v = lq + tv;
                 xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
                 acc[0] += (double)v;
             }
-            __syncthreads();
-            if (t + 1 < PL)
-                store(sm);  // plane i + 2 replaces plane i - 1
+            // plane i + 2 goes to the fourth slot, which held plane i - 2
+            // and was last read before the previous barrier: one barrier a plane
+            if (t + 1 < PL) {
+                store((t + 3) & 3);
+#pragma unroll
+                for (int cj = 0; cj < CJ; cj++) {
+                    dcur[cj] = dnxt[cj];
+                    tcur[cj] = tnxt[cj];
+                }
+            }
             __syncthreads();
         }
     }
