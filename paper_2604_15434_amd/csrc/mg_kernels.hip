@@ -137,8 +137,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, co
 template <typename R>
 void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
                               const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
-                              hipStream_t st, bool norms)
+                              hipStream_t st, bool norms, int tiled)
 {
+    Span spt;
+    if (launch_residual_restrict_tiled<R>(F, xr, xb, csum, C, cxr, cxb, rs, sc, nonlinear, st, tiled, &spt)) {
+        if (norms)
+            launch_finalize(rs, spt, 4, rs.out, st);
+        return;
+    }
     const Span sp = make_span(2 * C.half);
     if (nonlinear)
         hipLaunchKernelGGL((k_residual_restrict<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, C,
@@ -196,10 +202,15 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau(LevelView<R> C, const R *__r
 
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, bool accumulate_only, hipStream_t st)
+                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled)
 {
-    const Span sp = make_span(2 * C.half);
     const int acc_only = (accumulate_only || C.tr == nullptr) ? 1 : 0;
+    Span spt;
+    if (launch_fas_tau_tiled<R>(C, xr, xb, rs, sc, nonlinear, acc_only, st, tiled, &spt)) {
+        launch_finalize(rs, spt, 2, csum, st);
+        return;
+    }
+    const Span sp = make_span(2 * C.half);
     if (nonlinear)
         hipLaunchKernelGGL((k_fas_tau<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
                            acc_only);
@@ -288,16 +299,20 @@ __device__ __forceinline__ void prolong_cell(const LevelView<R> &F, R *__restric
 
 template <typename R>
 void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
-                            hipStream_t st)
+                            hipStream_t st, int tiled)
 {
+    if (launch_prolong_tiled<R>(F, xr, xb, C, cxr, cxb, true, st, tiled))
+        return;
     const Span sp = make_span(2 * C.half);
     hipLaunchKernelGGL((k_prolong<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
 }
 
 template <typename R>
 void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
-                         hipStream_t st)
+                         hipStream_t st, int tiled)
 {
+    if (launch_prolong_tiled<R>(F, xr, xb, C, cxr, cxb, false, st, tiled))
+        return;
     const Span sp = make_span(2 * C.half);
     hipLaunchKernelGGL((k_prolong<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
 }
@@ -716,8 +731,13 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
 
 void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                                  const LevelView<float> &F32, float *x32r, float *x32b, double *, ReduceSlot rs,
-                                 SolveConsts sc, bool nonlinear, hipStream_t st)
+                                 SolveConsts sc, bool nonlinear, hipStream_t st, int tiled)
 {
+    Span spt;
+    if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt)) {
+        launch_finalize(rs, spt, 6, rs.out, st);
+        return;
+    }
     const Span sp = make_span(2 * F64.half);
     if (nonlinear)
         hipLaunchKernelGGL((k_mixed_outer<true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32, x32r,
@@ -851,22 +871,22 @@ void launch_zero(void *p, size_t bytes, hipStream_t st)
 // explicit instantiations
 template void launch_residual_restrict<double>(const LevelView<double> &, const double *, const double *,
                                                const double *, const LevelView<double> &, double *, double *,
-                                               ReduceSlot, SolveConsts, bool, hipStream_t, bool);
+                                               ReduceSlot, SolveConsts, bool, hipStream_t, bool, int);
 template void launch_residual_restrict<float>(const LevelView<float> &, const float *, const float *, const double *,
                                               const LevelView<float> &, float *, float *, ReduceSlot, SolveConsts,
-                                              bool, hipStream_t, bool);
+                                              bool, hipStream_t, bool, int);
 template void launch_fas_tau<double>(const LevelView<double> &, const double *, const double *, double *, ReduceSlot,
-                                     SolveConsts, bool, bool, hipStream_t);
+                                     SolveConsts, bool, bool, hipStream_t, int);
 template void launch_fas_tau<float>(const LevelView<float> &, const float *, const float *, double *, ReduceSlot,
-                                    SolveConsts, bool, bool, hipStream_t);
+                                    SolveConsts, bool, bool, hipStream_t, int);
 template void launch_prolong_correct<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
-                                             const double *, const double *, hipStream_t);
+                                             const double *, const double *, hipStream_t, int);
 template void launch_prolong_correct<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,
-                                            const float *, const float *, hipStream_t);
+                                            const float *, const float *, hipStream_t, int);
 template void launch_prolong_full<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
-                                          const double *, const double *, hipStream_t);
+                                          const double *, const double *, hipStream_t, int);
 template void launch_prolong_full<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,
-                                         const float *, const float *, hipStream_t);
+                                         const float *, const float *, hipStream_t, int);
 template void launch_coarsest<double>(const LevelView<double> &, double *, double *, SolveConsts, bool, int,
                                       hipStream_t);
 template void launch_coarsest<float>(const LevelView<float> &, float *, float *, SolveConsts, bool, int, hipStream_t);

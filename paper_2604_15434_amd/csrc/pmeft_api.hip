@@ -413,11 +413,11 @@ static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveCon
     }
     H.cur[l + 1][0] = H.cur[l + 1][1] = 0;
     launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
-                                sc, nl, C.st, false);
-    launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum_cur(l + 1), C.rs, sc, nl, false, C.st);
+                                sc, nl, C.st, false, H.tiled);
+    launch_fas_tau<R>(H.L[l + 1], H.xr(l + 1), H.xb(l + 1), H.csum_cur(l + 1), C.rs, sc, nl, false, C.st, H.tiled);
     H.fresh(l + 1);
     vcycle_from(C, H, l + 1, o, sc, nl);
-    launch_prolong_correct<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
+    launch_prolong_correct<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st, H.tiled);
     for (int s = 0; s < o.n_post; s++) {
         smooth(C, H, l, 0, sc, nl);
         smooth(C, H, l, 1, sc, nl);
@@ -447,7 +447,7 @@ static void fmg_start(Ctx &C, Hier<R> &H, const pm_mg_opts &o, SolveConsts sc, b
         top = H.block_l0 - 1;
         if (H.block_l0 == 0) {
             // the caller smooths level 0 next: set its per-colour sums exactly
-            launch_fas_tau<R>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st);
+            launch_fas_tau<R>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st, H.tiled);
             H.fresh(0);
         }
     } else {
@@ -457,8 +457,8 @@ static void fmg_start(Ctx &C, Hier<R> &H, const pm_mg_opts &o, SolveConsts sc, b
     }
     for (int l = top; l >= 0; l--) {
         H.cur[l][0] = H.cur[l][1] = 0;
-        launch_prolong_full<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st);
-        launch_fas_tau<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), C.rs, sc, nl, true, C.st);
+        launch_prolong_full<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st, H.tiled);
+        launch_fas_tau<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), C.rs, sc, nl, true, C.st, H.tiled);
         H.fresh(l);
         vcycle_from(C, H, l, o, sc, nl);
     }
@@ -491,7 +491,7 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
         fmg = 1;
     } else {
         // exact mean of Lq on the fine level for the first half-sweep
-        launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st);
+        launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st, H.tiled);
         H.fresh(0);
     }
     double out[8];
@@ -503,7 +503,7 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
         }
         H.cur[1][0] = H.cur[1][1] = 0;
         launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), H.L[1], H.xr(1), H.xb(1), C.rs, sc,
-                                         nl, C.st);
+                                         nl, C.st, true, H.tiled);
         int e = read_out(C, C.rs.out, out, 4);
         if (e)
             return e;
@@ -524,10 +524,10 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
             so.status = PM_ENOCONV;
             break;
         }
-        launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum_cur(1), C.rs, sc, nl, false, C.st);
+        launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum_cur(1), C.rs, sc, nl, false, C.st, H.tiled);
         H.fresh(1);
         vcycle_from(C, H, 1, o, sc, nl);
-        launch_prolong_correct<double>(H.L[0], H.xr(0), H.xb(0), H.L[1], H.xr(1), H.xb(1), C.st);
+        launch_prolong_correct<double>(H.L[0], H.xr(0), H.xb(0), H.L[1], H.xr(1), H.xb(1), C.st, H.tiled);
         for (int s = 0; s < o.n_post; s++) {
             smooth(C, H, 0, 0, sc, nl);
             smooth(C, H, 0, 1, sc, nl);
@@ -569,7 +569,7 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     LevelView<double> F64 = make_view<double>(C.P.n[0], 1.0 / C.P.n[0], C.at<double>(C.P.delta64[0]), nullptr, nullptr);
     const long long half = F64.half;
     // exact initial mean of Lq64
-    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, true, C.st);
+    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, true, C.st, H.tiled);
     ReduceSlot ro = C.rs;
     ro.out = C.outer_out;
     // the FP32 correction equation of a linear problem has no source term
@@ -582,7 +582,7 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     for (;; it++) {
         H.cur[0][0] = H.cur[0][1] = 0;
         launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), nullptr, ro, sc, nl,
-                                    C.st);
+                                    C.st, H.tiled);
         // lagged means for the next outer residual and the FP32 level 0
         PM_HIP(hipMemcpyAsync(C.csum64, C.outer_out + 2, sizeof(double), hipMemcpyDeviceToDevice, C.st));
         launch_zero(C.csum64 + 1, sizeof(double), C.st);

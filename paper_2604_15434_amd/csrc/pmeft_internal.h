@@ -167,26 +167,45 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
 // restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
 // into x0).  Accumulates sum r^2, sum r, sum Lq+tau into rs.out[0..2] and the
 // void-cell count into rs.out[3].
+// tiled != 0 selects the 2.5D-tiled kernel on levels with n >= 128.
 template <typename R>
 void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
                               const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc, bool nonlinear,
-                              hipStream_t st, bool norms = true);
+                              hipStream_t st, bool norms = true, int tiled = 0);
 
 // Coarse FAS source: tau += lap x - Lq(x) (unless accumulate_only or the
 // level has no tau); writes sum(Lq + tau) per colour into csum[0..1].
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, bool accumulate_only, hipStream_t st);
+                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled = 0);
+
+// The 2.5D-tiled variants (tile_kernels.hip): return false, launching
+// nothing, where the level is too small or its shape does not tile; else
+// launch and return the partial-sum span for the finalize.
+template <typename R>
+bool launch_residual_restrict_tiled(const LevelView<R> &F, const R *xr, const R *xb, const double *csum,
+                                    const LevelView<R> &C, R *cxr, R *cxb, ReduceSlot rs, SolveConsts sc,
+                                    bool nonlinear, hipStream_t st, int tiled, Span *sp_out);
+template <typename R>
+bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, ReduceSlot rs, SolveConsts sc,
+                          bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out);
+bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
+                              const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs, SolveConsts sc,
+                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out);
 
 // Fine x += P (x_H - x0_H), trilinear cell-centred prolongation.
 template <typename R>
 void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr,
-                            const R *cxb, hipStream_t st);
+                            const R *cxb, hipStream_t st, int tiled = 0);
 
 // Fine x = P x_H (full-approximation prolongation, to start full multigrid).
 template <typename R>
 void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
-                         hipStream_t st);
+                         hipStream_t st, int tiled = 0);
+// Tiled prolongation on coarse levels with n >= 64 (false: nothing launched).
+template <typename R>
+bool launch_prolong_tiled(const LevelView<R> &F, R *xr, R *xb, const LevelView<R> &C, const R *cxr, const R *cxb,
+                          bool corr, hipStream_t st, int tiled);
 
 // Coarsest level solved by one workgroup in FP64.
 template <typename R>
@@ -214,7 +233,8 @@ void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int 
 // Lq32 + tau32 into csum32.
 void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
                                  const double *csum64, const LevelView<float> &F32, float *x32r, float *x32b,
-                                 double *csum32, ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st);
+                                 double *csum32, ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st,
+                                 int tiled = 0);
 // x64 += x32 - x0_32
 void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, const float *x0r, const float *x0b,
                           long long half, hipStream_t st);

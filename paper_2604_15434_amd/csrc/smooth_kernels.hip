@@ -1,7 +1,7 @@
 // Red-black half-sweeps of the multigrid levels (gfx950): the grid-wide
 // kernel for every level and the 2.5D-tiled kernel for the large levels.
 // The operator and the cell update are those of mg_stencil.h.
-#include "mg_stencil.h"
+#include "tile_window.h"
 
 #include <math.h>
 
@@ -72,9 +72,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
 {
     constexpr int RS = kBlock / TK;  // rows per pass of the block
     constexpr int TJ = CJ * RS;
-    constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
-    constexpr int PER = (2 * W + kBlock - 1) / kBlock;
-    __shared__ R win[2][4][TJ + 2][TK + 2];  // [0]: own colour, [1]: other colour; 4-plane ring
+    __shared__ RingSlots<R, TK, TJ> win;  // [0]: own colour, [1]: other colour
     const int n = L.n, nh = L.nh;
     const int nK = nh / TK, nI = n / PL;
     const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
@@ -84,51 +82,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
     const R *tc = colour ? L.tb : L.tr;
     const int tj = threadIdx.x / TK, tk = threadIdx.x % TK;
     double acc[1] = {0.0};
-    R pre[PER];
+    PlaneRing<R, TK, TJ> ring;
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
-        const int ib = (int)(tile % nI), kb = (int)((tile / nI) % nK), jb = (int)(tile / ((unsigned)nI * nK));
+        int ib, kb, jb;
+        tile_coords(tile, nI, nK, ib, kb, jb);
         const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
-        // this thread's window elements, resolved once per tile: source
-        // array, offset within a plane (periodic wrap applied) and LDS slot
-        // offset; element q: colour q / W, row (q % W) / (TK + 2), column
-        // (q % W) % (TK + 2)
-        const R *src[PER];
-        unsigned poff[PER];
-        int loff[PER];
-#pragma unroll
-        for (int u = 0; u < PER; u++) {
-            const int q = threadIdx.x + u * kBlock;
-            const int qq = q < 2 * W ? q : 0;
-            const int which = qq / W, r = (qq % W) / (TK + 2), c = (qq % W) % (TK + 2);
-            int jj = j0 - 1 + r, kk = k0 - 1 + c;
-            jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
-            kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
-            src[u] = which ? xo : xc_old;
-            poff[u] = (unsigned)jj * nh + kk;
-            loff[u] = (which * 4 * (TJ + 2) + r) * (TK + 2) + c;
-        }
-        const unsigned plane = (unsigned)n * nh;
-        R *wflat = &win[0][0][0][0];
-        auto fetch = [&](int ii) {
-            ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
-            const unsigned base = (unsigned)ii * plane;
-#pragma unroll
-            for (int u = 0; u < PER; u++)
-                if (threadIdx.x + u * kBlock < 2 * W)
-                    pre[u] = src[u][base + poff[u]];
-        };
-        auto store = [&](int slot) {
-#pragma unroll
-            for (int u = 0; u < PER; u++)
-                if (threadIdx.x + u * kBlock < 2 * W)
-                    wflat[loff[u] + slot * (TJ + 2) * (TK + 2)] = pre[u];
-        };
-        fetch(i0 - 1);
-        store(0);
-        fetch(i0);
-        store(1);
-        fetch(i0 + 1);
-        store(2);
+        ring.setup(xc_old, xo, n, nh, j0, k0);
+        ring.prime(win, i0);
         // density and tau of this thread's cells, one plane ahead as well
         const unsigned e00 = ((unsigned)i0 * n + j0 + tj) * nh + k0 + tk;
         R dcur[CJ], tcur[CJ], dnxt[CJ], tnxt[CJ];
@@ -142,10 +102,10 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
             const int i = i0 + t;
             const int sm = t & 3, s0 = (t + 1) & 3, sp1 = (t + 2) & 3;  // planes i - 1, i, i + 1
             if (t + 1 < PL) {
-                fetch(i + 2);  // into registers, stored after this plane
+                ring.fetch(i + 2);  // into registers, stored after this plane
 #pragma unroll
                 for (int cj = 0; cj < CJ; cj++) {
-                    const unsigned en = e00 + (unsigned)(t + 1) * plane + cj * RS * nh;
+                    const unsigned en = e00 + (unsigned)(t + 1) * ring.plane + cj * RS * nh;
                     dnxt[cj] = dc[en];
                     tnxt[cj] = tc ? tc[en] : (R)0;
                 }
@@ -154,21 +114,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
             for (int cj = 0; cj < CJ; cj++) {
                 const int j = j0 + tj + cj * RS, kh = k0 + tk;
                 const int p = (i + j + colour) & 1;
-                const int a = tj + cj * RS + 1, b = tk + 1;  // window coordinates of the cell
-                const int bm = tk + p, bp = tk + 1 + p;      // its kh - 1 + p and kh + p neighbours
                 R tsh;
-                R S;
-                if (NL)
-                    S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b],
-                                        win[1][s0][a - 1][b], win[1][s0][a][bp], win[1][s0][a][bm],
-                                        win[0][sp1][a + 1][b], win[0][sp1][a - 1][b], win[0][sm][a + 1][b],
-                                        win[0][sm][a - 1][b], win[0][sp1][a][bp], win[0][sp1][a][bm],
-                                        win[0][sm][a][bp], win[0][sm][a][bm], win[0][s0][a + 1][bp],
-                                        win[0][s0][a + 1][bm], win[0][s0][a - 1][bp], win[0][s0][a - 1][bm], true, tsh);
-                else
-                    S = stencil_eval<R>(win[1][sp1][a][b], win[1][sm][a][b], win[1][s0][a + 1][b],
-                                        win[1][s0][a - 1][b], win[1][s0][a][bp], win[1][s0][a][bm], (R)0, (R)0, (R)0,
-                                        (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, (R)0, false, tsh);
+                const R S = ring_stencil<R, R, TK, TJ>(win, 0, sm, s0, sp1, tj + cj * RS + 1, tk, p, NL, tsh);
                 const unsigned e = ((unsigned)i * n + j) * nh + kh;
                 const R tv = tcur[cj];
                 const R bsrc = (R)sc.beta * dcur[cj];
@@ -178,10 +125,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
                 xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
                 acc[0] += (double)v;
             }
-            // plane i + 2 goes to the fourth slot, which held plane i - 2
-            // and was last read before the previous barrier: one barrier a plane
             if (t + 1 < PL) {
-                store((t + 3) & 3);
+                ring.store(win, (t + 3) & 3);
 #pragma unroll
                 for (int cj = 0; cj < CJ; cj++) {
                     dcur[cj] = dnxt[cj];
