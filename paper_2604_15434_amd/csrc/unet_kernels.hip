@@ -252,10 +252,246 @@ static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int c
 #undef PM_CONV
 }
 
+// Plane-marching variant for grids with n % 64 == 0 and at most 48 input
+// channels (8-aligned views): a block of 8 waves owns 4 rows (j) by 64 voxels
+// (k), two waves per row of 32 voxels, and walks PL planes along i, keeping
+// input planes i - 1, i, i + 1 (6 x 66 voxels, all input channels) in an LDS
+// ring of NS slots (one barrier per plane with 4 slots, two with 3), so every
+// input voxel is staged about 1.5 times instead of 4.6.  The K index of the
+// implicit GEMM runs over (tap, channel); it is consumed in chunks of 32 by
+// v_mfma_f32_16x16x32_bf16 (a chunk may span two taps: each lane's 8 values
+// lie in one tap, 8-aligned channels) and a final 16 by the 16x16x16 form
+// when 27 * cin_pad is not a multiple of 32.  The voxel stride in LDS is an
+// odd number of 16-byte units (the 16-byte fragment reads of 8 consecutive
+// lanes then fall in distinct banks).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMarchThreads = 512;
+
+template <int CS, int COT, int NS>
+__global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *__restrict__ in, int in_stride, int in_off,
+                                                     const uint16_t *__restrict__ wp, int cout_pad,
+                                                     const float *__restrict__ bias, int cout, void *__restrict__ out,
+                                                     int out_stride, int out_off, int out_f32, int n, int flip,
+                                                     int relu, unsigned ntiles, int PL)
+{
+    constexpr int CP = 16 * CS;                 // input channels (padded)
+    constexpr int SV = CP + 8;                  // LDS voxel stride (halfwords)
+    constexpr int WV = 6 * 66;                  // voxels per staged plane
+    constexpr int NCH = WV * (CP / 8);          // 16-byte chunks per plane
+    constexpr int PER = (NCH + kMarchThreads - 1) / kMarchThreads;
+    constexpr int KT = 27 * CP;                 // GEMM K
+    constexpr int NK32 = KT / 32, TAIL = KT % 32;
+    __shared__ __align__(16) uint16_t ring[NS * WV * SV];
+    const int wave = threadIdx.x >> 7, mh = ((threadIdx.x >> 6) & 1) * 2;  // row, first m-tile
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int nkt = n / 64, njt = n / 4, nit = n / PL;
+    const int co_base = blockIdx.y * COT * 16;
+    const int sgn = flip ? -1 : 1;
+    const size_t plane_elems = (size_t)n * n * in_stride;
+    const unsigned nb = gridDim.x;
+    const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    // with 16 input channels and one output tile the B fragments of all K
+    // chunks (13 x 4 + 2 VGPRs) stay in registers for the whole block
+    constexpr bool BREG = CS == 1 && COT == 1;
+    bf16x8 bw[BREG ? NK32 : 1];
+    bf16x4 btl = {0, 0, 0, 0};
+    if constexpr (BREG) {
+#pragma unroll
+        for (int kc = 0; kc < NK32; kc++) {
+            const int kk = kc * 32 + 8 * q, tap = kk / CP, ch = kk % CP;
+            bw[kc] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(wp + ((size_t)tap * cout_pad + co_base + r) * CP + ch));
+        }
+        if (TAIL) {
+            const int kk = NK32 * 32 + 4 * q, tap = kk / CP, ch = kk % CP;
+            btl = *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + r) * CP + ch);
+        }
+    }
+    for (unsigned t = lb; t < ntiles; t += nb) {
+        const int ib = (int)(t % nit), kt = (int)((t / nit) % nkt), jt = (int)(t / ((unsigned)nit * nkt));
+        const int i0 = ib * PL, j0 = jt * 4, k0 = kt * 64;
+        // this thread's staging chunks: within-plane source offset and LDS offset
+        unsigned soff[PER];
+        int loff[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int c = threadIdx.x + u * kMarchThreads;
+            const int cc = c < NCH ? c : 0;
+            const int v = cc / (CP / 8), part = cc % (CP / 8);
+            const int row = v / 66, col = v % 66;
+            const int jj = wrapi(j0 + row - 1, n), kk = wrapi(k0 + col - 1, n);
+            soff[u] = (unsigned)((jj * n + kk) * in_stride + in_off + 8 * part);
+            loff[u] = v * SV + 8 * part;
+        }
+        u32x4 pre[PER];
+#define PM_MARCH_FETCH(II)                                                                                             \
+    do {                                                                                                               \
+        const uint16_t *base_ = in + (size_t)wrapi((II), n) * plane_elems;                                             \
+        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH) pre[u] =           \
+            *(const u32x4 *)(base_ + soff[u]);                                                                         \
+    } while (0)
+#define PM_MARCH_STORE(SLOT)                                                                                           \
+    do {                                                                                                               \
+        uint16_t *dst_ = ring + (SLOT) * WV * SV;                                                                      \
+        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH)                    \
+            *(u32x4 *)(dst_ + loff[u]) = pre[u];                                                                       \
+    } while (0)
+        PM_MARCH_FETCH(i0 - 1);
+        PM_MARCH_STORE(0);
+        PM_MARCH_FETCH(i0);
+        PM_MARCH_STORE(1);
+        PM_MARCH_FETCH(i0 + 1);
+        PM_MARCH_STORE(2);
+        __syncthreads();
+        for (int p = 0; p < PL; p++) {
+            const int i = i0 + p;
+            // ring slot of plane i - 1 + d is (p + d) % NS
+            if (p + 1 < PL)
+                PM_MARCH_FETCH(i + 2);
+            f32x4 acc[2][COT];
+#pragma unroll
+            for (int m = 0; m < 2; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            // LDS halfword offset of this lane's A row (voxel 16 (mh + m) + r) for the
+            // tap (di, dj, dk), before the channel offset
+            auto a_base = [&](int tap) {
+                int di, dj, dk;
+                tap_offsets(tap, di, dj, dk);
+                const int slot = (p + 1 + sgn * di) % NS;
+                return ((slot * 6 + 1 + wave + sgn * dj) * 66 + 1 + 16 * mh + r + sgn * dk) * SV;
+            };
+            if constexpr (BREG) {
+                // A fragments two chunks ahead of the MFMAs that use them
+                constexpr int DEPTH = 3;
+                bf16x8 af[DEPTH][2];
+#pragma unroll
+                for (int kc = 0; kc < NK32 + DEPTH - 1; kc++) {
+                    if (kc < NK32) {
+                        const int kk = kc * 32 + 8 * q;  // this lane's first K index
+                        const int ab = a_base(kk / CP) + kk % CP;
+#pragma unroll
+                        for (int m = 0; m < 2; m++)
+                            af[kc % DEPTH][m] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(ring + ab + 16 * m * SV));
+                    }
+                    const int ku = kc - (DEPTH - 1);
+                    if (ku >= 0) {
+#pragma unroll
+                        for (int m = 0; m < 2; m++)
+                            acc[m][0] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ku % DEPTH][m], bw[ku], acc[m][0], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int kc = 0; kc < NK32; kc++) {
+                    const int kk = kc * 32 + 8 * q;  // this lane's first K index
+                    const int tap = kk / CP, ch = kk % CP;
+                    const int ab = a_base(tap) + ch;
+                    bf16x8 b[COT];
+#pragma unroll
+                    for (int u = 0; u < COT; u++)
+                        b[u] = __builtin_bit_cast(
+                            bf16x8, *(const u32x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch));
+#pragma unroll
+                    for (int m = 0; m < 2; m++) {
+                        const bf16x8 a = __builtin_bit_cast(bf16x8, *(const u32x4 *)(ring + ab + 16 * m * SV));
+#pragma unroll
+                        for (int u = 0; u < COT; u++)
+                            acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[u], acc[m][u], 0, 0, 0);
+                    }
+                }
+            }
+            if (TAIL) {
+                const int kk = NK32 * 32 + 4 * q;
+                const int tap = kk / CP, ch = kk % CP;
+                const int ab = a_base(tap) + ch;
+                bf16x4 b[COT];
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    b[u] = BREG ? btl : *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch);
+#pragma unroll
+                for (int m = 0; m < 2; m++) {
+                    const bf16x4 a = *(const bf16x4 *)(ring + ab + 16 * m * SV);
+#pragma unroll
+                    for (int u = 0; u < COT; u++)
+                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[u], acc[m][u], 0, 0, 0);
+                }
+            }
+            const size_t vbase = ((size_t)i * n + j0 + wave) * n + k0;
+#pragma unroll
+            for (int u = 0; u < COT; u++) {
+                const int o = co_base + u * 16 + r;
+                if (o >= cout)
+                    continue;
+                const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+                for (int m = 0; m < 2; m++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        float v = acc[m][u][e] + bo;
+                        if (relu)
+                            v = fmaxf(v, 0.f);
+                        const size_t idx = (vbase + 16 * (mh + m) + 4 * q + e) * out_stride + out_off + o;
+                        if (out_f32)
+                            ((float *)out)[idx] = v;
+                        else
+                            ((uint16_t *)out)[idx] = f2bf(v);
+                    }
+            }
+            if (NS == 4) {
+                // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
+                if (p + 1 < PL)
+                    PM_MARCH_STORE((p + 3) % NS);
+                __syncthreads();
+            } else {
+                __syncthreads();
+                if (p + 1 < PL)
+                    PM_MARCH_STORE(p % NS);  // plane i + 2 replaces plane i - 1
+                __syncthreads();
+            }
+        }
+#undef PM_MARCH_STORE
+#undef PM_MARCH_FETCH
+    }
+}
+
 void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
                   const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
                   bool relu, hipStream_t st)
 {
+    if (n % 64 == 0 && cin_pad <= 48 && in_stride % 8 == 0 && in_off % 8 == 0) {
+        const int cot = (cin_pad == 16 && (cout_pad / 16) % 2 == 0) ? 2 : 1;
+        const int PL = n >= 256 ? 16 : 8;
+        const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
+        unsigned nb = ntiles < 2048u ? ntiles : 2048u;
+        if (nb >= 8)
+            nb -= nb % 8;
+        dim3 grid(nb, cout_pad / (cot * 16));
+#define PM_CONVM(CSV, C, NSV)                                                                                          \
+    hipLaunchKernelGGL((k_conv3_march<CSV, C, NSV>), grid, dim3(kMarchThreads), 0, st, in, in_stride, in_off, wp, cout_pad,     \
+                       bias, cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles,   \
+                       PL)
+#define PM_CONVM_C(CSV, NSV)                                                                                           \
+    do {                                                                                                               \
+        if (cot == 2)                                                                                                  \
+            PM_CONVM(CSV, 2, NSV);                                                                                     \
+        else                                                                                                           \
+            PM_CONVM(CSV, 1, NSV);                                                                                     \
+    } while (0)
+        if (cin_pad == 16)
+            PM_CONVM_C(1, 4);
+        else if (cin_pad == 32)
+            PM_CONVM(2, 1, 4);
+        else
+            PM_CONVM(3, 1, 3);
+#undef PM_CONVM_C
+#undef PM_CONVM
+        return;
+    }
     if (n % kCvK == 0 && in_stride % 4 == 0 && in_off % 4 == 0) {
         const unsigned ntiles = (unsigned)n * (n / kCvRows) * (n / kCvK);
         const int tiles = cout_pad / 16;
@@ -506,10 +742,66 @@ __global__ __launch_bounds__(256) void k_up_bwd(const uint16_t *__restrict__ dou
     }
 }
 
+// The same two maps, 8 channels (16 bytes) per thread, for 8-aligned views;
+// thread e covers voxel e / (C / 8), channels 8 (e % (C / 8)) .. + 7.
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_pool8(const uint16_t *__restrict__ in, int istride, int ioff,
+                                               uint16_t *__restrict__ out, int ostride, int ooff, int C, int nc)
+{
+    const int G = C / 8;
+    const unsigned total = (unsigned)nc * nc * nc * G;
+    const int nf = 2 * nc;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / G;
+        const int c = 8 * (int)(e - v * G);
+        const int K = (int)(v % nc), J = (int)((v / nc) % nc), I = (int)(v / ((unsigned)nc * nc));
+        float sum[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                for (int d = 0; d < 2; d++) {
+                    const u16x8 x = *(const u16x8 *)(in + ((size_t)((2 * I + a) * nf + 2 * J + b) * nf + 2 * K + d) *
+                                                              istride +
+                                                      ioff + c);
+#pragma unroll
+                    for (int h = 0; h < 8; h++)
+                        sum[h] += bf2f(x[h]);
+                }
+        u16x8 y;
+#pragma unroll
+        for (int h = 0; h < 8; h++)
+            y[h] = f2bf(0.125f * sum[h]);
+        *(u16x8 *)(out + (size_t)v * ostride + ooff + c) = y;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_up8(const uint16_t *__restrict__ in, int istride, int ioff,
+                                             uint16_t *__restrict__ out, int ostride, int ooff, int C, int nf)
+{
+    const int G = C / 8;
+    const unsigned total = (unsigned)nf * nf * nf * G;
+    const int nc = nf / 2;
+    for (unsigned e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+        const unsigned v = e / G;
+        const int c = 8 * (int)(e - v * G);
+        const int k = (int)(v % nf), j = (int)((v / nf) % nf), i = (int)(v / ((unsigned)nf * nf));
+        const size_t p = (size_t)((i / 2) * nc + j / 2) * nc + k / 2;
+        *(u16x8 *)(out + (size_t)v * ostride + ooff + c) = *(const u16x8 *)(in + p * istride + ioff + c);
+    }
+}
+
+static inline bool aligned8(int C, int s1, int o1, int s2, int o2)
+{
+    return C % 8 == 0 && s1 % 8 == 0 && o1 % 8 == 0 && s2 % 8 == 0 && o2 % 8 == 0;
+}
+
 void launch_pool(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nc,
                  hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nc);
+    if (aligned8(C, istride, ioff, ostride, ooff))
+        hipLaunchKernelGGL(k_pool8, dim3(4096), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nc);
+    else
+        hipLaunchKernelGGL(k_pool, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nc);
 }
 void launch_pool_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nf,
                      hipStream_t st)
@@ -519,7 +811,10 @@ void launch_pool_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din,
 void launch_up(const uint16_t *in, int istride, int ioff, uint16_t *out, int ostride, int ooff, int C, int nf,
                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_up, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nf);
+    if (aligned8(C, istride, ioff, ostride, ooff))
+        hipLaunchKernelGGL(k_up8, dim3(4096), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nf);
+    else
+        hipLaunchKernelGGL(k_up, dim3(2048), dim3(256), 0, st, in, istride, ioff, out, ostride, ooff, C, nf);
 }
 void launch_up_bwd(const uint16_t *dout, int ostride, int ooff, uint16_t *din, int istride, int ioff, int C, int nc,
                    hipStream_t st)
