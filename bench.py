@@ -103,7 +103,7 @@ def smoother_kernel(itemsize, tiled, ng):
     nh = ng // 2
     if tiled and ng >= 64:
         if tiled == 2 and nh % 64 == 0 and ng % 16 == 0 and (ng // 8) * (nh // 64) * (ng // 16) >= 512:
-            return f"k_smooth_tile<{r}, true, 64, 2, 16>"
+            return f"k_smooth_tile<{r}, true, 64, 2, {8 if itemsize == 8 else 16}>"
         if nh % 64 == 0 and ng % 8 == 0:
             return f"k_smooth_tile<{r}, true, 64, 1, 8>"
         if nh % 32 == 0 and ng % 8 == 0:

@@ -325,6 +325,10 @@ void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R>
 // reduction).
 constexpr int kCoarseMax = 216;
 constexpr double kCoarseTol = 1e-10;
+// ... or below kCoarseRel of the largest accumulated change of the solve (the
+// coarse-grid correction is then resolved to about 0.1%, far below the
+// V-cycle's per-cycle reduction)
+constexpr double kCoarseRel = 1e-3;
 
 // Device part, for any block size >= n^3 that is a multiple of 64 (all
 // threads of the block must call it).
@@ -332,7 +336,7 @@ template <typename R, bool NL>
 __device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveConsts &sc, int sweeps, double tol)
 {
     __shared__ double x[kCoarseMax], d[kCoarseMax], t[kCoarseMax];
-    __shared__ double red[16][2];
+    __shared__ double red[16][2], cred[16];
     const int n = C.n, nh = C.nh, N = n * n * n;
     const int q = threadIdx.x, nw = blockDim.x >> 6;
     int i = 0, j = 0, k = 0, col = 0;
@@ -349,6 +353,7 @@ __device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveC
         t[q] = tc ? (double)tc[off] : 0.0;
     }
     __syncthreads();
+    const double xstart = q < N ? x[q] : 0.0;
     const double h2 = C.h * C.h, ih2 = 1.0 / h2;
     auto at = [&](int a, int b, int c) -> double {
         a = a < 0 ? a + n : (a >= n ? a - n : a);
@@ -397,25 +402,30 @@ __device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveC
                 x[q] = nx;
             __syncthreads();
         }
-        double mx = 0.0, md = maxd;
-        if (q < N)
+        double mx = 0.0, md = maxd, mc = 0.0;
+        if (q < N) {
             mx = fabs(x[q]);
+            mc = fabs(x[q] - xstart);
+        }
         for (int o = 32; o > 0; o >>= 1) {
             mx = fmax(mx, __shfl_down(mx, o, 64));
             md = fmax(md, __shfl_down(md, o, 64));
+            mc = fmax(mc, __shfl_down(mc, o, 64));
         }
         if (lane == 0) {
             red[wid][0] = mx;
             red[wid][1] = md;
+            cred[wid] = mc;
         }
         __syncthreads();
-        double gx = 0.0, gd = 0.0;
+        double gx = 0.0, gd = 0.0, gc = 0.0;
         for (int w = 0; w < nw; w++) {
             gx = fmax(gx, red[w][0]);
             gd = fmax(gd, red[w][1]);
+            gc = fmax(gc, cred[w]);
         }
         __syncthreads();
-        if (gd <= tol * gx)
+        if (gd <= tol * gx || gd <= kCoarseRel * gc)
             break;
     }
     if (q < N)
@@ -426,7 +436,7 @@ __device__ void coarsest_solve(const LevelView<R> &C, R *xr, R *xb, const SolveC
 // The 4^3 coarsest grid in one wavefront: lane q holds cell q = (i n + j) n + k
 // and reads its neighbours with cross-lane shuffles, so a sweep needs no
 // barrier.  Same iteration as coarsest_solve (red-black Gauss-Seidel with the
-// exact mean of Lq + tau before every half-sweep, same stopping rule).
+// exact mean of Lq + tau before every half-sweep, same stopping rules).
 // Called by the 64 lanes of one wave.
 template <typename R, bool NL>
 __device__ void coarsest_wave(const LevelView<R> &C, R *xr, R *xb, const SolveConsts &sc, int sweeps, double tol)
@@ -437,6 +447,7 @@ __device__ void coarsest_wave(const LevelView<R> &C, R *xr, R *xb, const SolveCo
     const int col = (i + j + k) & 1;
     const long long off = ((long long)i * n + j) * nh + (k >> 1);
     double x = (double)(col ? xb : xr)[off];
+    const double xstart = x;
     const double d = (double)(col ? C.db : C.dr)[off];
     const R *tc = col ? C.tb : C.tr;
     const double t = tc ? (double)tc[off] : 0.0;
@@ -479,8 +490,8 @@ __device__ void coarsest_wave(const LevelView<R> &C, R *xr, R *xb, const SolveCo
                 x = nx;
             }
         }
-        const double gx = wmax(fabs(x)), gd = wmax(maxd);
-        if (gd <= tol * gx)
+        const double gx = wmax(fabs(x)), gd = wmax(maxd), gc = wmax(fabs(x - xstart));
+        if (gd <= tol * gx || gd <= kCoarseRel * gc)
             break;
     }
     (col ? xb : xr)[off] = (R)x;

@@ -218,8 +218,112 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double *__restrict__ 
     }
 }
 
+// The same gradient, 2.5D-tiled for n % 64 == 0: a block owns 4 rows (j) by
+// 64 cells (k) and walks PL planes along i, keeping Psi_tot of planes
+// i - 2 .. i + 2 (with a two-cell halo in j and k, in natural order) in a
+// six-slot LDS ring: the next plane is fetched into registers before the
+// current one is computed and stored into the free slot after it (one
+// barrier per plane).  Same operands and expression as k_gradient.
+constexpr int kGradRows = 4, kGradK = 64, kGradPL = 16;
+
+template <typename Tg>
+__global__ __launch_bounds__(kBlock) void k_gradient_tile(const double *__restrict__ psi,
+                                                          const double *__restrict__ chi, double xi, int n,
+                                                          Tg *__restrict__ g4, unsigned ntiles)
+{
+    constexpr int WR = kGradRows + 4, WC = kGradK + 4, W = WR * WC;
+    constexpr int PER = (W + kBlock - 1) / kBlock;
+    __shared__ double win[6][WR][WC];
+    const int nh = n / 2;
+    const unsigned half = (unsigned)n * n * nh;
+    const double s = -(double)n / 12.0;
+    const int nI = n / kGradPL, nK = n / kGradK;
+    const int tj = threadIdx.x / kGradK, tk = threadIdx.x % kGradK;
+    const unsigned nb = gridDim.x;
+    const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    double *wflat = &win[0][0][0];
+    for (unsigned t = lb; t < ntiles; t += nb) {
+        const int ib = (int)(t % nI), kb = (int)((t / nI) % nK), jb = (int)(t / ((unsigned)nI * nK));
+        const int i0 = ib * kGradPL, j0 = jb * kGradRows, k0 = kb * kGradK;
+        // window element q: row q / WC (j = j0 - 2 + row), column q % WC
+        // (k = k0 - 2 + column); packed offset within a plane and j + k parity
+        unsigned poff[PER];
+        int par[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int q = threadIdx.x + u * kBlock;
+            const int qq = q < W ? q : 0;
+            int j = j0 - 2 + qq / WC, k = k0 - 2 + qq % WC;
+            j = j < 0 ? j + n : (j >= n ? j - n : j);
+            k = k < 0 ? k + n : (k >= n ? k - n : k);
+            poff[u] = (unsigned)j * nh + (k >> 1);
+            par[u] = (j + k) & 1;
+        }
+        double pre[PER];
+#define PM_GRAD_FETCH(II)                                                                                              \
+    do {                                                                                                               \
+        const int ii_ = (II) < 0 ? (II) + n : ((II) >= n ? (II) - n : (II));                                           \
+        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kBlock < W)                              \
+        {                                                                                                              \
+            const unsigned o_ = (((ii_ + par[u]) & 1) ? half : 0u) + (unsigned)ii_ * n * nh + poff[u];                 \
+            double v_ = psi[o_];                                                                                       \
+            if (chi)                                                                                                   \
+                v_ += xi * chi[o_];                                                                                    \
+            pre[u] = v_;                                                                                               \
+        }                                                                                                              \
+    } while (0)
+#define PM_GRAD_STORE(SLOT)                                                                                            \
+    do {                                                                                                               \
+        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kBlock < W) wflat[(SLOT) * W +          \
+                                                                                                  threadIdx.x +        \
+                                                                                                  u * kBlock] = pre[u]; \
+    } while (0)
+#pragma unroll 1
+        for (int d = 0; d < 5; d++) {
+            PM_GRAD_FETCH(i0 - 2 + d);
+            PM_GRAD_STORE(d);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int p = 0; p < kGradPL; p++) {
+            const int i = i0 + p;
+            if (p + 1 < kGradPL)
+                PM_GRAD_FETCH(i + 3);
+            const int r = tj + 2, c = tk + 2;
+            const double *m2 = &win[p % 6][r][c], *m1 = &win[(p + 1) % 6][r][c], *c0 = &win[(p + 2) % 6][r][c];
+            const double *p1 = &win[(p + 3) % 6][r][c], *p2 = &win[(p + 4) % 6][r][c];
+            const double gx = s * (m2[0] - 8.0 * m1[0] + 8.0 * p1[0] - p2[0]);
+            const double gy = s * (c0[-2 * WC] - 8.0 * c0[-WC] + 8.0 * c0[WC] - c0[2 * WC]);
+            const double gz = s * (c0[-2] - 8.0 * c0[-1] + 8.0 * c0[1] - c0[2]);
+            Tg *o = g4 + 4 * ((size_t)((unsigned)i * n + j0 + tj) * n + k0 + tk);
+            o[0] = (Tg)gx;
+            o[1] = (Tg)gy;
+            o[2] = (Tg)gz;
+            o[3] = (Tg)0;
+            if (p + 1 < kGradPL)
+                PM_GRAD_STORE((p + 5) % 6);  // plane i + 3 replaces plane i - 3
+            __syncthreads();
+        }
+#undef PM_GRAD_STORE
+#undef PM_GRAD_FETCH
+    }
+}
+
 void launch_gradient(const double *psi, const double *chi, double xi, int ng, void *g4, pm_dtype dt, hipStream_t st)
 {
+    if (ng % kGradK == 0 && ng % kGradPL == 0) {
+        const unsigned ntiles = (unsigned)(ng / kGradRows) * (ng / kGradK) * (ng / kGradPL);
+        unsigned nb = ntiles < 2048u ? ntiles : 2048u;
+        if (nb >= 8)
+            nb -= nb % 8;
+        if (dt == PM_F64)
+            hipLaunchKernelGGL((k_gradient_tile<double>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng,
+                               (double *)g4, ntiles);
+        else
+            hipLaunchKernelGGL((k_gradient_tile<float>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng, (float *)g4,
+                               ntiles);
+        return;
+    }
     const Span sp = make_span((unsigned long long)ng * ng * ng);
     if (dt == PM_F64)
         hipLaunchKernelGGL((k_gradient<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, psi, chi, xi, ng,
@@ -253,9 +357,11 @@ __global__ __launch_bounds__(kBlock) void k_interp_kick(const T *__restrict__ g4
                     for (int c = 0; c < 2; c++) {
                         const double w = wx[a] * wy[b] * wz[c];
                         const T *gv = g4 + 4 * (((unsigned)ix[a] * ng + iy[b]) * ng + iz[c]);
-                        ax += w * (double)gv[0];
-                        ay += w * (double)gv[1];
-                        az += w * (double)gv[2];
+                        typedef T T4 __attribute__((ext_vector_type(4)));
+                        const T4 g = *(const T4 *)gv;  // one 16- or 32-byte load per corner
+                        ax += w * (double)g[0];
+                        ay += w * (double)g[1];
+                        az += w * (double)g[2];
                     }
         }
         const double vx = (double)vel[p] + ax * dt_kick;

@@ -166,7 +166,10 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
 {
     const int cfg = tile_config(L.n, tiled);
     if (cfg) {
-        const int TK = cfg == 3 ? 32 : 64, TJ = cfg == 1 ? 2 * kBlock / TK : kBlock / TK, PL = cfg == 1 ? 16 : 8;
+        // FP64 large tiles march 8 planes: three such blocks fit a CU (LDS), and
+        // 16-plane tiles would leave a third of the last round of blocks idle
+        constexpr int PL1 = sizeof(R) == 8 ? 8 : 16;
+        const int TK = cfg == 3 ? 32 : 64, TJ = cfg == 1 ? 2 * kBlock / TK : kBlock / TK, PL = cfg == 1 ? PL1 : 8;
         const unsigned ntiles = (unsigned)((L.n / TJ) * (L.nh / TK) * (L.n / PL));
         // Span only carries the block count (XCD mapping, partials)
         Span sp;
@@ -182,14 +185,14 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
                        xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
         if (nonlinear) {
             if (cfg == 1)
-                PM_TILE(true, 64, 2, 16);
+                PM_TILE(true, 64, 2, PL1);
             else if (cfg == 2)
                 PM_TILE(true, 64, 1, 8);
             else
                 PM_TILE(true, 32, 1, 8);
         } else {
             if (cfg == 1)
-                PM_TILE(false, 64, 2, 16);
+                PM_TILE(false, 64, 2, PL1);
             else if (cfg == 2)
                 PM_TILE(false, 64, 1, 8);
             else
