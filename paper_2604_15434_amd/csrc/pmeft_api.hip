@@ -556,7 +556,7 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
 //    Once the FP64 residual is within `kMixedSwitch` of that floor, or a
 //    cycle stops paying (reduction worse than 0.6), the remaining V-cycles
 //    run in FP64.
-constexpr double kMixedSwitchNL = 3e-5;
+constexpr double kMixedSwitchNL = 3e-6;
 constexpr int kMixedInner = 2;        // FP32 V-cycles per outer step
 constexpr double kMixedStall = 0.36;  // an outer step must reduce the residual at least this much (0.6 per V-cycle)
 
@@ -730,19 +730,34 @@ static int poisson_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, So
     return run_solve(C, m, sc, false, o, src, so, o.guess != PM_GUESS_GIVEN);
 }
 
-// Learned warm start: one linear full-multigrid pass on
-// nu lap chi0 = xi s (delta + t - <t>), t from the network; delta is restored
-// afterwards.
-static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, double src)
+static int learned_ok(int ng, const pm_mg_opts &o)
 {
-    const int ng = C.P.ng;
     if (ng % 64 || ng < 64)
         return PM_EINVAL;
     if (o.learned_ws_bytes < ws_unet_workspace_bytes(ng, 0))
         return PM_ENOMEM;
+    return PM_OK;
+}
+
+// Learned warm start: one linear full-multigrid pass on
+// nu lap chi0 = xi s (delta + t - <t>), t from the network; delta is restored
+// afterwards.  forward_done: the network's forward pass was already issued
+// (and waited for) by the caller.
+static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, double src,
+                         bool forward_done)
+{
+    const int ng = C.P.ng;
+    int e = learned_ok(ng, o);
+    if (e)
+        return e;
     double *d0 = C.at<double>(C.P.delta64[0]);
     double *save = unet_save_area(o.learned_ws, ng);
-    int e = unet_learned_source(o.learned_params, d0, save, ng, p, o.learned_ws, o.learned_ws_bytes, C.st);
+    if (!forward_done) {
+        e = unet_learned_forward(o.learned_params, d0, save, ng, p, o.learned_ws, o.learned_ws_bytes, C.st);
+        if (e)
+            return e;
+    }
+    e = unet_add_learned_source(o.learned_ws, ng, d0, C.st);
     if (e)
         return e;
     delta_levels(C);
@@ -760,7 +775,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
 
 // Scalar field: nu lap chi - xi s delta - K N(chi) = 0 (beta = xi s).
 static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so,
-                       double dsq)
+                       double dsq, bool forward_done = false)
 {
     double *m = C.at<double>(C.P.chi64);
     so = SolveOut();
@@ -778,7 +793,7 @@ static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, 
     if (o.guess != PM_GUESS_GIVEN)
         launch_zero(m, sizeof(double) * C.P.N, C.st);
     if (o.guess == PM_GUESS_LEARNED && nl) {
-        int e = learned_guess(C, p, cf, o, src);
+        int e = learned_guess(C, p, cf, o, src, forward_done);
         if (e)
             return e;
         return run_solve(C, m, sc, nl, o, src, so, false);
@@ -1209,6 +1224,38 @@ int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, co
     return launched();
 }
 
+// The library's second stream (one per device, created on first use, default
+// priority, non-blocking): pm_step runs the warm start's network on it while
+// the Poisson solve runs on the caller's stream.  Overlapping pm_step calls on
+// one device share it (and its two events), which stays correct but may
+// serialise their network passes.
+namespace {
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr;
+};
+std::mutex g_side_mu;
+SideStream g_side[64];
+
+int side_stream(SideStream **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return PM_EHIP;
+    std::lock_guard<std::mutex> g(g_side_mu);
+    SideStream &S = g_side[dev];
+    if (!S.s) {
+        if (hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
+            return PM_EHIP;
+        if (hipEventCreateWithFlags(&S.ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess)
+            return PM_EHIP;
+    }
+    *out = &S;
+    return PM_OK;
+}
+}  // namespace
+
 int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p,
             const pm_mg_opts *poisson_opts, const pm_mg_opts *scalar_opts, double dt_kick, double dt_drift, void *psi,
             void *chi, pm_step_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
@@ -1241,14 +1288,35 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
     if (scalar_opts->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
+    // the warm start's network depends on delta only: issue it on the side
+    // stream so that it overlaps the Poisson solve
+    const bool side = scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0 && dsq > 0.0;
+    SideStream *S = nullptr;
+    if (side) {
+        e = learned_ok(ng, *scalar_opts);
+        if (!e)
+            e = side_stream(&S);
+        if (e)
+            return e;
+        PM_HIP(hipEventRecord(S->ready, C.st));
+        PM_HIP(hipStreamWaitEvent(S->s, S->ready, 0));
+        e = unet_learned_forward(scalar_opts->learned_params, C.at<double>(C.P.delta64[0]),
+                                 unet_save_area(scalar_opts->learned_ws, ng), ng, *p, scalar_opts->learned_ws,
+                                 scalar_opts->learned_ws_bytes, S->s);
+        if (e)
+            return e;
+        PM_HIP(hipEventRecord(S->done, S->s));
+    }
     SolveOut sp, sx;
     Timer tp(C.st);
     e = poisson_core(C, cf, *poisson_opts, sp, dsq);
     if (e)
         return e;
     const float ms_p = tp.stop();
+    if (side)
+        PM_HIP(hipStreamWaitEvent(C.st, S->done, 0));
     Timer tx(C.st);
-    e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq);
+    e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq, side);
     if (e)
         return e;
     const float ms_x = tx.stop();

@@ -274,10 +274,14 @@ void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int 
                         const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st);
 
 // ---- learned warm start (unet_api.hip) -----------------------------------
-// delta (packed, mean-free) -> delta + t - <t> with t the network's source
-// prediction; the original delta is copied to `save` first.
-int unet_learned_source(const float *params, double *delta_packed, double *save, int ng, const pm_eft_params &p,
-                        void *ws, size_t ws_bytes, hipStream_t st);
+// Forward pass: copy delta (packed, mean-free) to `save` and run the network
+// on that copy, leaving its source prediction t in the workspace; delta
+// itself is only read (by the copy), so this may run on a second stream
+// while other work reads delta.
+int unet_learned_forward(const float *params, const double *delta_packed, double *save, int ng,
+                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st);
+// delta -> delta + t - <t> with the t of the preceding forward pass.
+int unet_add_learned_source(void *ws, int ng, double *delta_packed, hipStream_t st);
 double *unet_save_area(void *ws, int ng);
 
 // ---- particle kernels (pm_kernels.hip) -----------------------------------

@@ -287,10 +287,11 @@ double *prepare_input(Net &N, const double *rho)
 
 namespace pmeft {
 
-// The learned source for the solver: save the packed delta into `save`
-// (ng^3 doubles) and replace delta by delta + t - <t> (t from the network).
-int unet_learned_source(const float *params, double *delta_packed, double *save, int ng, const pm_eft_params &p,
-                        void *ws, size_t ws_bytes, hipStream_t st)
+// The learned source for the solver, in two parts: the forward pass (the
+// packed delta saved into `save`, ng^3 doubles, and the network run on that
+// copy), then delta <- delta + t - <t>.
+int unet_learned_forward(const float *params, const double *delta_packed, double *save, int ng,
+                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st)
 {
     Net N;
     int e = setup(N, ng, false, ws, ws_bytes, st);
@@ -300,8 +301,20 @@ int unet_learned_source(const float *params, double *delta_packed, double *save,
     if (hipMemcpyAsync(save, delta_packed, sizeof(double) * n3, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return PM_EHIP;
     pack_all(N, params);
-    forward(N, params, delta_packed, p);
-    launch_add_source((const float *)(N.ws + N.P.yhat), ng, delta_packed, N.rs, st);
+    forward(N, params, save, p);
+    return launched();
+}
+
+int unet_add_learned_source(void *ws, int ng, double *delta_packed, hipStream_t st)
+{
+    NetPlan P;
+    if (!net_plan(P, ng, false))
+        return PM_EINVAL;
+    ReduceSlot rs;
+    rs.partials = (double *)((char *)ws + P.red_partials);
+    rs.counter = nullptr;
+    rs.out = (double *)((char *)ws + P.red_out);
+    launch_add_source((const float *)((char *)ws + P.yhat), ng, delta_packed, rs, st);
     return launched();
 }
 

@@ -217,3 +217,36 @@ def test_trained_network_gain_on_held_out_fields(P):
         assert l["vcycles"] <= z["vcycles"]
         err = float((out["learned"][0] - ref).norm() / ref.norm())
         assert err < 1e-5
+
+
+def test_step_overlaps_network_and_keeps_the_field(P):
+    """pm_step runs the warm start's network on a second stream, overlapping
+    the Poisson solve.  The step must give the fields of the zero-guess step
+    (to the solve tolerance) and be deterministic from run to run."""
+    from paper_2604_15434_amd.warmstart import DEFAULT_WEIGHTS, WarmStart
+    from workloads import lognormal_particles
+
+    ng = 64
+    pos_np, _ = lognormal_particles(ng, 125.0, seed=31)
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.5, alpha_m0=0.05, a=0.8)
+    net = WarmStart.load(DEFAULT_WEIGHTS)
+    out = {}
+    for tag, guess in (("zero", "zero"), ("learned", "learned"), ("learned2", "learned")):
+        pos = torch.from_numpy(pos_np).cuda()
+        vel = torch.zeros_like(pos)
+        psi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+        chi = torch.zeros_like(psi)
+        po = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision="mixed")
+        so = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision="mixed", guess=guess,
+                      learned=net if guess == "learned" else None)
+        rep = P.pm_step(pos, vel, ng, prm, po, so, 1e-2, 0.0, psi, chi)
+        assert rep["status"] == 0, rep
+        torch.cuda.synchronize()
+        out[tag] = (psi.clone(), chi.clone(), vel.clone())
+    for i in range(3):
+        a, b = out["learned"][i], out["learned2"][i]
+        assert torch.equal(a, b), i
+    err_chi = float((out["learned"][1] - out["zero"][1]).norm() / out["zero"][1].norm())
+    err_v = float((out["learned"][2] - out["zero"][2]).norm() / out["zero"][2].norm())
+    assert err_chi < 1e-8 and err_v < 1e-8, (err_chi, err_v)
+    assert torch.equal(out["learned"][0], out["zero"][0])
