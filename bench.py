@@ -84,7 +84,8 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup, net=None):
                 ms_force=last["ms_force"], kernel_timing=kt, itemsize=8 if dt == torch.float64 else 4)
 
 
-SMOOTHER_SOURCES = [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f) for f in ("mg_stencil.h", "smooth_kernels.hip")]
+SMOOTHER_SOURCES = [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f)
+                    for f in ("mg_stencil.h", "tile_window.h", "smooth_kernels.hip")]
 
 
 def smoother_source_hash():

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
     const R *tc = colour ? L.tb : L.tr;
     const int tj = threadIdx.x / TK, tk = threadIdx.x % TK;
     double acc[1] = {0.0};
-    PlaneRing<R, TK, TJ> ring;
+    PlaneRing<R, TK, TJ, NL ? 2 : 1> ring;
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
         int ib, kb, jb;
         tile_coords(tile, nI, nK, ib, kb, jb);

@@ -15,10 +15,12 @@ namespace pmeft {
 template <typename R, int TK, int TJ>
 using RingSlots = R[2][4][TJ + 2][TK + 2];
 
-template <typename R, int TK, int TJ>
+// NCOL = 1 loads colour 1 (a1) only: the linear smoother reads no neighbour
+// of its own colour.
+template <typename R, int TK, int TJ, int NCOL = 2>
 struct PlaneRing {
     static constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
-    static constexpr int PER = (2 * W + kBlock - 1) / kBlock;
+    static constexpr int PER = (NCOL * W + kBlock - 1) / kBlock;
     const R *src[PER];  // this thread's window elements: source array,
     unsigned poff[PER]; // offset within a plane (periodic wrap applied),
     int loff[PER];      // and LDS offset within slot 0
@@ -35,8 +37,8 @@ struct PlaneRing {
 #pragma unroll
         for (int u = 0; u < PER; u++) {
             const int q = threadIdx.x + u * kBlock;
-            const int qq = q < 2 * W ? q : 0;
-            const int which = qq / W, r = (qq % W) / (TK + 2), c = (qq % W) % (TK + 2);
+            const int qq = q < NCOL * W ? q : 0;
+            const int which = NCOL == 2 ? qq / W : 1, r = (qq % W) / (TK + 2), c = (qq % W) % (TK + 2);
             int jj = j0 - 1 + r, kk = k0 - 1 + c;
             jj = jj < 0 ? jj + n_ : (jj >= n_ ? jj - n_ : jj);
             kk = kk < 0 ? kk + nh : (kk >= nh ? kk - nh : kk);
@@ -52,7 +54,7 @@ struct PlaneRing {
         const unsigned base = (unsigned)ii * plane;
 #pragma unroll
         for (int u = 0; u < PER; u++)
-            if (threadIdx.x + u * kBlock < 2 * W)
+            if (threadIdx.x + u * kBlock < NCOL * W)
                 pre[u] = src[u][base + poff[u]];
     }
     // the fetched plane into ring slot `slot`
@@ -61,7 +63,7 @@ struct PlaneRing {
         R *w = &win[0][0][0][0];
 #pragma unroll
         for (int u = 0; u < PER; u++)
-            if (threadIdx.x + u * kBlock < 2 * W)
+            if (threadIdx.x + u * kBlock < NCOL * W)
                 w[loff[u] + slot * (TJ + 2) * (TK + 2)] = pre[u];
     }
     // planes i0 - 1, i0, i0 + 1 into slots 0, 1, 2 (the caller then syncs)
