@@ -300,7 +300,11 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
  * output (for testing the kernels): mode 0 forward out[n^3][cout] =
  * b + conv(x); mode 1 input gradient out[n^3][cin] from dy[n^3][cout]; mode
  * 2 weight gradient out[27][cin][cout] from x and dy (summed in a fixed
- * order: deterministic).  w: FP32 W[27][cin][cout] (device); n a multiple of
+ * order: deterministic); mode 3 the forward of a layer whose first 2cin/3
+ * input channels are the nearest-neighbour upsampling of x (a coarse
+ * (n/2)^3 x 2cin/3 tensor) and whose last cin/3 channels are dy (n^3 x
+ * cin/3), evaluated in the polyphase form the network uses at inference
+ * ((cin, cout) = (48, 16) or (96, 32), n a multiple of 128).  w: FP32 W[27][cin][cout] (device); n a multiple of
  * 16; ws: 256-byte aligned, at least 2 * W + 4 * 240 * (27 cin cout + cout)
  * bytes with W = 54 * pad16(cin) * pad16(cout) rounded up to 256. */
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,

@@ -21,6 +21,7 @@ template <typename R, int TK, int TJ, int NCOL = 2>
 struct PlaneRing {
     static constexpr int W = (TJ + 2) * (TK + 2);  // window elements per plane and colour
     static constexpr int PER = (NCOL * W + kBlock - 1) / kBlock;
+    static constexpr int FULL = NCOL * W / kBlock;  // elements u < FULL exist for every thread
     const R *src[PER];  // this thread's window elements: source array,
     unsigned poff[PER]; // offset within a plane (periodic wrap applied),
     int loff[PER];      // and LDS offset within slot 0
@@ -54,7 +55,7 @@ struct PlaneRing {
         const unsigned base = (unsigned)ii * plane;
 #pragma unroll
         for (int u = 0; u < PER; u++)
-            if (threadIdx.x + u * kBlock < NCOL * W)
+            if (u < FULL || threadIdx.x + u * kBlock < NCOL * W)
                 pre[u] = src[u][base + poff[u]];
     }
     // the fetched plane into ring slot `slot`
@@ -63,7 +64,7 @@ struct PlaneRing {
         R *w = &win[0][0][0][0];
 #pragma unroll
         for (int u = 0; u < PER; u++)
-            if (threadIdx.x + u * kBlock < NCOL * W)
+            if (u < FULL || threadIdx.x + u * kBlock < NCOL * W)
                 w[loff[u] + slot * (TJ + 2) * (TK + 2)] = pre[u];
     }
     // planes i0 - 1, i0, i0 + 1 into slots 0, 1, 2 (the caller then syncs)

@@ -40,6 +40,12 @@ void launch_adam(float *w, const float *g, float *m, float *v, long long n, floa
                  float c1, float c2, const double *gsq, float clip, hipStream_t st);
 void launch_sumsq(const float *g, long long n, ReduceSlot rs, hipStream_t st);
 void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st);
+void launch_pack_poly(const float *w, int cin, int cout, int cup, int cout_pad, uint16_t *wp, hipStream_t st);
+void launch_pack_conv_sub(const float *w, int cin, int cout, int c0, int csub, int csub_pad, int cout_pad,
+                          uint16_t *wf, hipStream_t st);
+bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp, int cout_pad, const float *bias,
+                        const float *add, int cout, void *out, int out_stride, int out_off, bool out_f32, bool relu,
+                        hipStream_t st);
 namespace {
 
 struct ConvSpec {
@@ -78,12 +84,20 @@ enum { X0, A1, C1, P1, A2, C2, P2, A3, B3, A4, B4, A5, B5, NT };
 constexpr int kTLevel[NT] = {0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 0, 0};
 constexpr int kTChan[NT] = {16, 16, 48, 16, 32, 96, 32, 64, 64, 32, 32, 16, 16};
 
+// The decoder layers whose input is [upsampled | skip] (l4a: 64 | 32 channels,
+// l5a: 32 | 16): at inference they run as a convolution of the skip channels
+// (FP32 result) plus the polyphase convolution of the coarse tensor, with no
+// upsampled tensor in memory.
+constexpr int kFused[2] = {6, 8};
+constexpr int kFusedUp[2] = {64, 32};
+
 struct NetPlan {
     int n = 0;
     bool training = false;
     size_t total = 0;
     size_t red_partials = 0, red_out = 0;
     size_t wf[10] = {}, wd[10] = {};
+    size_t wpoly[2] = {}, wsub[2] = {};  // inference: polyphase and skip-channel weights of kFused
     size_t act[NT] = {}, grad[NT] = {};
     size_t delta = 0, yhat = 0, target = 0, pgrad = 0, loss = 0, wg_part = 0;
 };
@@ -111,6 +125,12 @@ bool net_plan(NetPlan &P, int n, bool training)
         if (training && l > 0)
             P.wd[l] = take(c, sz);
     }
+    if (!training)
+        for (int f = 0; f < 2; f++) {
+            const int l = kFused[f], cout_pad = pad16(kConv[l].cout);
+            P.wpoly[f] = take(c, sizeof(uint16_t) * 64 * cout_pad * kFusedUp[f]);
+            P.wsub[f] = take(c, sizeof(uint16_t) * 27 * cout_pad * pad16(kConv[l].cin - kFusedUp[f]));
+        }
     for (int t = 0; t < NT; t++) {
         const size_t m = (size_t)(n >> kTLevel[t]);
         const size_t sz = sizeof(uint16_t) * m * m * m * kTChan[t];
@@ -155,6 +175,30 @@ void pack_all(Net &N, const float *params)
     for (int l = 0; l < 10; l++)
         launch_pack_conv(params + L.w[l], kConv[l].cin, kConv[l].cout, pad16(kConv[l].cin), pad16(kConv[l].cout),
                          (uint16_t *)(N.ws + N.P.wf[l]), N.P.wd[l] ? (uint16_t *)(N.ws + N.P.wd[l]) : nullptr, N.st);
+    if (!N.P.training)
+        for (int f = 0; f < 2; f++) {
+            const int l = kFused[f], cin = kConv[l].cin, cout = kConv[l].cout, up = kFusedUp[f];
+            launch_pack_poly(params + L.w[l], cin, cout, up, pad16(cout), (uint16_t *)(N.ws + N.P.wpoly[f]), N.st);
+            launch_pack_conv_sub(params + L.w[l], cin, cout, up, cin - up, pad16(cin - up), pad16(cout),
+                                 (uint16_t *)(N.ws + N.P.wsub[f]), N.st);
+        }
+}
+
+// Inference form of decoder layer kFused[f] (input tensor ti = [upsampled |
+// skip], coarse tensor tc, output to): the skip channels' convolution into an
+// FP32 scratch (the input and first activation tensors, dead by then), then
+// the polyphase convolution of tc adds it, the bias and the ReLU.
+bool fused_up_conv(Net &N, const float *params, int f, int ti, int tc, int to)
+{
+    const ParamLayout L = param_layout();
+    const int l = kFused[f], cin = kConv[l].cin, cout = kConv[l].cout, up = kFusedUp[f];
+    if (N.dim(tc) % 64)  // no polyphase instance for this grid
+        return false;
+    float *scratch = (float *)N.act(X0);
+    launch_conv3(N.act(ti), kTChan[ti], up, pad16(cin - up), (const uint16_t *)(N.ws + N.P.wsub[f]), pad16(cout),
+                 nullptr, cout, scratch, cout, 0, true, N.dim(to), false, false, N.st);
+    return launch_upconv_poly(N.act(tc), up, N.dim(tc), (const uint16_t *)(N.ws + N.P.wpoly[f]), pad16(cout),
+                              params + L.b[l], scratch, cout, N.act(to), kTChan[to], 0, false, true, N.st);
 }
 
 // conv layer l: input tensor (ti, channel offset), output (to, offset)
@@ -181,11 +225,18 @@ void forward(Net &N, const float *params, const double *delta, const pm_eft_para
     launch_pool(N.act(C2), 96, 64, N.act(P2), 32, 0, 32, n / 4, N.st);
     conv_fwd(N, params, 4, P2, 0, A3, 0);
     conv_fwd(N, params, 5, A3, 0, B3, 0);
-    launch_up(N.act(B3), 64, 0, N.act(C2), 96, 0, 64, n / 2, N.st);
-    conv_fwd(N, params, 6, C2, 0, A4, 0);
+    // inference skips the upsampled tensors (polyphase form); training keeps
+    // them, the backward pass reads them
+    const bool fused = !N.P.training;
+    if (!fused || !fused_up_conv(N, params, 0, C2, B3, A4)) {
+        launch_up(N.act(B3), 64, 0, N.act(C2), 96, 0, 64, n / 2, N.st);
+        conv_fwd(N, params, 6, C2, 0, A4, 0);
+    }
     conv_fwd(N, params, 7, A4, 0, B4, 0);
-    launch_up(N.act(B4), 32, 0, N.act(C1), 48, 0, 32, n, N.st);
-    conv_fwd(N, params, 8, C1, 0, A5, 0);
+    if (!fused || !fused_up_conv(N, params, 1, C1, B4, A5)) {
+        launch_up(N.act(B4), 32, 0, N.act(C1), 48, 0, 32, n, N.st);
+        conv_fwd(N, params, 8, C1, 0, A5, 0);
+    }
     conv_fwd(N, params, 9, A5, 0, B5, 0);
     const ParamLayout L = param_layout();
     launch_head(N.act(B5), params + L.hw, params + L.hb, nv, (float *)(N.ws + N.P.yhat), N.st);
@@ -406,7 +457,7 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
              const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream)
 {
-    if (mode < 0 || mode > 2 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws ||
+    if (mode < 0 || mode > 3 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws ||
         ((uintptr_t)ws & 255))
         return PM_EINVAL;
     const size_t wbytes = ((sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout)) + 255) & ~(size_t)255;
@@ -417,6 +468,25 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
     uint16_t *wf = (uint16_t *)ws;
     uint16_t *wd = (uint16_t *)((char *)ws + wbytes);
     float *part = (float *)((char *)ws + 2 * wbytes);
+    if (mode == 3) {
+        // decoder layer of the upsampled form: x = coarse (n/2)^3 x (2 cin / 3)
+        // channels (upsampled part), dy = n^3 x (cin / 3) skip channels
+        const int up = 2 * cin / 3, sub = cin - up;
+        if (!x_bf16 || !dy_bf16 || cin % 3 || up % 32 || sub % 16 || n % 128)
+            return PM_EINVAL;
+        const size_t pbytes = ((sizeof(uint16_t) * 64 * pad16(cout) * up) + 255) & ~(size_t)255;
+        if (pbytes + sizeof(uint16_t) * 27 * pad16(cout) * sub > 2 * wbytes)
+            return PM_ENOMEM;
+        uint16_t *wpoly = (uint16_t *)ws, *wsub = (uint16_t *)((char *)ws + pbytes);
+        launch_pack_poly(w, cin, cout, up, pad16(cout), wpoly, st);
+        launch_pack_conv_sub(w, cin, cout, up, sub, sub, pad16(cout), wsub, st);
+        launch_conv3((const uint16_t *)dy_bf16, sub, 0, sub, wsub, pad16(cout), nullptr, cout, out, cout, 0, true, n,
+                     false, false, st);
+        if (!launch_upconv_poly((const uint16_t *)x_bf16, up, n / 2, wpoly, pad16(cout), b, out, cout, out, cout, 0,
+                                true, false, st))
+            return PM_EINVAL;
+        return launched();
+    }
     launch_pack_conv(w, cin, cout, pad16(cin), pad16(cout), wf, wd, st);
     if (mode == 0) {
         if (!x_bf16 || cin % 16)

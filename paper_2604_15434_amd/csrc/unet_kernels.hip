@@ -459,6 +459,192 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
     }
 }
 
+// Convolution of a nearest-neighbour upsampled tensor, evaluated on the
+// coarse grid (inference).  A fine voxel v = 2P + pi (parity pi per axis) sees
+// the coarse parent of v + d for its 27 taps d; along an axis the three taps
+// fall on two coarse offsets, pi - 1 and pi, so the layer restricted to the
+// upsampled channels is, per parity, a 2 x 2 x 2 convolution of the coarse
+// tensor with weights summed over the taps that share a coarse offset (the
+// polyphase form; 8 x 8 instead of 27 taps per output).  Wp[p][e][o][c]: parity
+// p = 4 pi_i + 2 pi_j + pi_k, coarse tap e = 4 e_i + 2 e_j + e_k, offset
+// e - 1 + pi per axis.  The block stages the 3 x 6 x (KT + 2) coarse
+// neighbourhood of 4 coarse rows x KT coarse voxels (all CIN channels) in LDS
+// (KT small enough for three blocks per CU);
+// each wave takes one row and runs, per parity, the 8 taps x CIN/32 K-chunks on
+// v_mfma_f32_16x16x32_bf16.  Epilogue: out[v][ooff + o] =
+// act(bias[o] + add[v][o] + sum), with add the rest of the layer (the other
+// input channels, FP32, cout per voxel) computed beforehand; out may be add
+// itself when FP32.
+template <int CIN, int COT, int KT>
+__global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict__ in, int nc,
+                                                     const uint16_t *__restrict__ wp, int cout_pad,
+                                                     const float *__restrict__ bias, const float *add, int cout,
+                                                     void *out, int out_stride, int out_off, int out_f32, int relu,
+                                                     unsigned ntiles)
+{
+    constexpr int SV = CIN + 8;  // odd number of 16-byte units
+    constexpr int WK = KT + 2, WV = 3 * 6 * WK;
+    constexpr int NCH = WV * (CIN / 8);
+    constexpr int MT = KT / 16;
+    __shared__ __align__(16) uint16_t tile[WV * SV];
+    const unsigned t = xcd_block(0);
+    if (t >= ntiles)
+        return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const int nkt = nc / KT, njt = nc / 4;
+    const int kt = (int)(t % nkt), jt = (int)((t / nkt) % njt), I = (int)(t / ((unsigned)nkt * njt));
+    const int J0 = jt * 4, K0 = kt * KT;
+    const int co_base = blockIdx.y * COT * 16;
+    for (int c = threadIdx.x; c < NCH; c += 256) {
+        const int v = c / (CIN / 8), part = c % (CIN / 8);
+        const int pl = v / (6 * WK), rem = v - pl * 6 * WK, row = rem / WK, col = rem - row * WK;
+        const int ii = wrapi(I + pl - 1, nc), jj = wrapi(J0 + row - 1, nc), kk = wrapi(K0 + col - 1, nc);
+        *(u32x4 *)(tile + v * SV + 8 * part) =
+            *(const u32x4 *)(in + ((size_t)((ii * nc + jj) * nc + kk)) * CIN + 8 * part);
+    }
+    __syncthreads();
+    const int J = J0 + wave;
+    const int nf = 2 * nc;
+    for (int p = 0; p < 8; p++) {
+        const int pi = p >> 2, pj = (p >> 1) & 1, pk = p & 1;
+        f32x4 acc[MT][COT];
+        float addv[MT][COT][4];  // the addend of this parity's outputs, loaded ahead of the MFMAs
+#pragma unroll
+        for (int m = 0; m < MT; m++)
+#pragma unroll
+            for (int u = 0; u < COT; u++) {
+                acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                const int o = co_base + u * 16 + r;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int K = K0 + 16 * m + 4 * q + e;
+                    const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
+                    addv[m][u][e] = o < cout ? add[fv * cout + o] : 0.f;
+                }
+            }
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int oi = (e >> 2) - 1 + pi, oj = ((e >> 1) & 1) - 1 + pj, ok = (e & 1) - 1 + pk;
+            const int ab = ((1 + oi) * 6 + 1 + wave + oj) * WK + 1 + r + ok;  // window voxel of m = 0
+#pragma unroll
+            for (int ch = 0; ch < CIN; ch += 32) {
+                bf16x8 b[COT];
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    b[u] = __builtin_bit_cast(
+                        bf16x8, *(const u32x4 *)(wp + ((size_t)(p * 8 + e) * cout_pad + co_base + u * 16 + r) * CIN +
+                                                 ch + 8 * q));
+#pragma unroll
+                for (int m = 0; m < MT; m++) {
+                    const bf16x8 a =
+                        __builtin_bit_cast(bf16x8, *(const u32x4 *)(tile + (ab + 16 * m) * SV + ch + 8 * q));
+#pragma unroll
+                    for (int u = 0; u < COT; u++)
+                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[u], acc[m][u], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < COT; u++) {
+            const int o = co_base + u * 16 + r;
+            if (o >= cout)
+                continue;
+            const float bo = bias ? bias[o] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; m++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int K = K0 + 16 * m + 4 * q + e;
+                    const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
+                    float v = acc[m][u][e] + bo + addv[m][u][e];
+                    if (relu)
+                        v = fmaxf(v, 0.f);
+                    const size_t oi_ = fv * out_stride + out_off + o;
+                    if (out_f32)
+                        ((float *)out)[oi_] = v;  // may alias add: same element, same thread
+                    else
+                        ((uint16_t *)out)[oi_] = f2bf(v);
+                }
+        }
+    }
+}
+
+// Polyphase weights of k_upconv_poly from layer weights w[27][cin][cout]
+// (FP32) restricted to input channels [0, cup): Wp[p][e][o][c] = sum of
+// w[t][c][o] over the taps t whose coarse offset for parity p is e, in tap
+// order, rounded once to BF16.
+__global__ __launch_bounds__(256) void k_pack_poly(const float *__restrict__ w, int cin, int cout, int cup,
+                                                   int cout_pad, uint16_t *__restrict__ wp)
+{
+    const int total = 64 * cout_pad * cup;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < total; x += gridDim.x * 256) {
+        const int c = x % cup, o = (x / cup) % cout_pad, pe = x / (cup * cout_pad);
+        const int p = pe >> 3, e = pe & 7;
+        float s = 0.f;
+        if (o < cout)
+            for (int t = 0; t < 27; t++) {
+                int di, dj, dk;
+                tap_offsets(t, di, dj, dk);
+                // coarse offset of tap d for parity pi: floor((pi + d) / 2), as e = that + 1 - pi
+                const int ei = ((((p >> 2) + di + 2) >> 1) - 1) + 1 - (p >> 2);
+                const int ej = (((((p >> 1) & 1) + dj + 2) >> 1) - 1) + 1 - ((p >> 1) & 1);
+                const int ek = ((((p & 1) + dk + 2) >> 1) - 1) + 1 - (p & 1);
+                if (ei == (e >> 2) && ej == ((e >> 1) & 1) && ek == (e & 1))
+                    s += w[((size_t)t * cin + c) * cout + o];
+            }
+        wp[x] = f2bf(s);
+    }
+}
+
+// Conv weights of input channels [c0, c0 + csub) of a layer, packed like
+// k_pack_conv's forward layout ([27][cout_pad][csub_pad]).
+__global__ __launch_bounds__(256) void k_pack_conv_sub(const float *__restrict__ w, int cin, int cout, int c0,
+                                                       int csub, int csub_pad, int cout_pad, uint16_t *__restrict__ wf)
+{
+    const int total = 27 * cout_pad * csub_pad;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < total; x += gridDim.x * 256) {
+        const int c = x % csub_pad, o = (x / csub_pad) % cout_pad, t = x / (csub_pad * cout_pad);
+        const float v = (c < csub && o < cout) ? w[((size_t)t * cin + c0 + c) * cout + o] : 0.f;
+        wf[x] = f2bf(v);
+    }
+}
+
+void launch_pack_poly(const float *w, int cin, int cout, int cup, int cout_pad, uint16_t *wp, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_poly, dim3(128), dim3(256), 0, st, w, cin, cout, cup, cout_pad, wp);
+}
+
+void launch_pack_conv_sub(const float *w, int cin, int cout, int c0, int csub, int csub_pad, int cout_pad,
+                          uint16_t *wf, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_conv_sub, dim3(128), dim3(256), 0, st, w, cin, cout, c0, csub, csub_pad, cout_pad, wf);
+}
+
+// Returns false (nothing launched) for channel counts without an instance.
+bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp, int cout_pad, const float *bias,
+                        const float *add, int cout, void *out, int out_stride, int out_off, bool out_f32, bool relu,
+                        hipStream_t st)
+{
+    if (nc % 64)
+        return false;
+    if (cup == 32 && cout_pad == 16) {
+        const unsigned ntiles = (unsigned)nc * (nc / 4) * (nc / 32);
+        hipLaunchKernelGGL((k_upconv_poly<32, 1, 32>), dim3(xcd_blocks(ntiles), 1), dim3(256), 0, st, in, nc, wp,
+                           cout_pad, bias, add, cout, out, out_stride, out_off, out_f32 ? 1 : 0, relu ? 1 : 0,
+                           ntiles);
+        return true;
+    }
+    if (cup == 64 && cout_pad == 32) {
+        const unsigned ntiles = (unsigned)nc * (nc / 4) * (nc / 16);
+        hipLaunchKernelGGL((k_upconv_poly<64, 2, 16>), dim3(xcd_blocks(ntiles), 1), dim3(256), 0, st, in, nc, wp,
+                           cout_pad, bias, add, cout, out, out_stride, out_off, out_f32 ? 1 : 0, relu ? 1 : 0,
+                           ntiles);
+        return true;
+    }
+    return false;
+}
+
 void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
                   const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
                   bool relu, hipStream_t st)

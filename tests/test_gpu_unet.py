@@ -250,3 +250,46 @@ def test_step_overlaps_network_and_keeps_the_field(P):
     err_v = float((out["learned"][2] - out["zero"][2]).norm() / out["zero"][2].norm())
     assert err_chi < 1e-8 and err_v < 1e-8, (err_chi, err_v)
     assert torch.equal(out["learned"][0], out["zero"][0])
+
+
+@pytest.mark.parametrize("cin,cout", [(48, 16), (96, 32)])
+def test_upsampled_layer_polyphase_matches_reference(P, cin, cout):
+    """Inference form of a decoder layer whose input is [upsampled coarse
+    tensor | skip tensor]: the polyphase convolution of the coarse tensor plus
+    the convolution of the skip channels equals the convolution of the
+    concatenation (oracle, FP64, BF16-rounded operands).  The polyphase
+    weights are sums of up to 8 taps rounded once to BF16, so the bound is
+    that of BF16 weights (1e-2 relative), not the FP32-accumulation one."""
+    n = 128
+    up, sub = 2 * cin // 3, cin // 3
+    rng = np.random.default_rng(cin)
+    xc = rng.standard_normal((n // 2, n // 2, n // 2, up))
+    xs = rng.standard_normal((n, n, n, sub))
+    w = rng.standard_normal((27, cin, cout)) * 0.05
+    b = rng.standard_normal(cout)
+    L = P._lib
+    out = torch.zeros(n**3 * cout, dtype=torch.float32, device="cuda")
+    wb = (54 * cin * ((cout + 15) // 16 * 16) + 255) // 256 * 256
+    wsz = 2 * wb + 4 * 240 * (27 * cin * cout + cout)
+    ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+    wd = torch.from_numpy(w.astype(np.float32)).cuda()
+    bd = torch.from_numpy(b.astype(np.float32)).cuda()
+    xcd, xsd = dev_bits(bf16_bits(xc)), dev_bits(bf16_bits(xs))
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    rc = L.lib().ws_conv3(3, n, cin, cout, ptr(xcd), ptr(xsd), ptr(wd), ptr(bd), ptr(out), ptr(ws), wsz,
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    got = out.cpu().numpy().astype(np.float64).reshape(n, n, n, cout)
+    # reference at 4096 sampled voxels: the 27 taps of the concatenated input,
+    # the upsampled channels read from the coarse parent of each neighbour
+    v = rng.integers(0, n, size=(4096, 3))
+    xcr, xsr, wr = bf16_round(xc), bf16_round(xs), bf16_round(w)
+    ref = np.tile(b.astype(np.float32).astype(np.float64), (len(v), 1))
+    for t, d in enumerate(U.TAPS):
+        q = (v + np.asarray(d)) % n
+        xin = np.concatenate([xcr[q[:, 0] // 2, q[:, 1] // 2, q[:, 2] // 2], xsr[q[:, 0], q[:, 1], q[:, 2]]], axis=1)
+        ref += xin @ wr[t]
+    g = got[v[:, 0], v[:, 1], v[:, 2]]
+    err = rel(g, ref)
+    print(f"polyphase layer cin {cin} cout {cout}: rel err {err:.2e}")
+    assert err < 1e-2, err
