@@ -130,3 +130,34 @@ class WarmStart:
 
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.f32")
+
+
+def _time_forward(argv=None):
+    """python -m paper_2604_15434_amd.warmstart --ng 256 [--reps 4]: wall time
+    of the trained network's forward pass on a seeded lognormal density."""
+    import argparse
+    import time
+
+    import torch
+
+    from workloads import lognormal_density
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--ng", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=4)
+    args = ap.parse_args(argv)
+    net = WarmStart.load(DEFAULT_WEIGHTS)
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
+    rho = torch.from_numpy(lognormal_density(args.ng, 500.0 * args.ng / 256, seed=2)).cuda()
+    y = torch.zeros(args.ng**3, dtype=torch.float32, device="cuda")
+    for i in range(args.reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.predict(rho, prm, y)
+        torch.cuda.synchronize()
+        print(f"{args.ng}^3 forward {(time.perf_counter() - t0) * 1e3:.3f} ms" + (" (first call)" if i == 0 else ""),
+              flush=True)
+
+
+if __name__ == "__main__":
+    _time_forward()
