@@ -98,3 +98,20 @@ def test_launch_shape_table_roundtrip(tmp_path):
         P.pm_tune_load(tmp_path / "missing.txt")
     P.pm_set_launch_shape(96, 8, 32, 1)
     P.pm_set_launch_shape(96, 4, 32, 1)
+
+
+def test_conv_test_entry_rejects_bad_arguments(lib):
+    """ws_conv3 validates its arguments before touching the device: an
+    unknown mode, and for the upsampled-layer mode (3) channel counts without
+    a polyphase instance or a grid that is not a multiple of 128."""
+    f = lib.ws_conv3
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 6 + \
+        [ctypes.c_size_t, ctypes.c_void_p]
+    fake = 1 << 20  # never dereferenced: every call below fails validation first
+    big = 1 << 40
+    einval = -1
+    assert f(4, 128, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval
+    assert f(3, 128, 40, 16, fake, fake, fake, fake, fake, fake, big, None) == einval   # cin % 3
+    assert f(3, 64, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval    # n % 128
+    assert f(3, 128, 48, 16, None, fake, fake, fake, fake, fake, big, None) == einval   # no coarse tensor
