@@ -612,10 +612,19 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
             to_f64 = true;
             break;
         }
-        prev = rel;
         // kMixedInner FP32 V-cycles per FP64 defect correction: the FP64
-        // residual and correction are paid once for all of them
-        for (int v = 0; v < kMixedInner && cyc < o.max_vcycles; v++, cyc++) {
+        // residual and correction are paid once for all of them.  A linear
+        // problem converges at a steady rate per V-cycle; when one cycle at
+        // the last outer step's rate (with a 2x margin) reaches the tolerance,
+        // the final outer step runs one cycle only.
+        int inner = kMixedInner;
+        if (!nl && it >= 2 && prev > 0.0) {  // (the first step includes the FMG start)
+            const double per_cycle = pow(rel / prev, 1.0 / kMixedInner);
+            if (per_cycle < 1.0 && 2.0 * rel * per_cycle <= o.rel_tol)
+                inner = 1;
+        }
+        prev = rel;
+        for (int v = 0; v < inner && cyc < o.max_vcycles; v++, cyc++) {
             if (it == 0 && v == 0 && zero_start)
                 fmg_start<float>(C, H, o, sc32, nl);
             else
@@ -1310,11 +1319,16 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     SolveOut sp, sx;
     Timer tp(C.st);
     e = poisson_core(C, cf, *poisson_opts, sp, dsq);
+    const float ms_p = e ? 0.0f : tp.stop();
+    if (side) {
+        // also on the error path: the caller's stream must not run ahead of
+        // the network's use of the warm-start workspace
+        const hipError_t we = hipStreamWaitEvent(C.st, S->done, 0);
+        if (!e && we != hipSuccess)
+            e = PM_EHIP;
+    }
     if (e)
         return e;
-    const float ms_p = tp.stop();
-    if (side)
-        PM_HIP(hipStreamWaitEvent(C.st, S->done, 0));
     Timer tx(C.st);
     e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq, side);
     if (e)
