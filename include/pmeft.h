@@ -277,7 +277,11 @@ long long ws_unet_param_count(void);
 size_t ws_unet_workspace_bytes(int ng, int training);
 
 /* Forward pass.  rho: ng^3 FP64 density (natural order); yhat_out: ng^3 FP32,
- * the predicted t (natural order). */
+ * the predicted t (natural order).  Inference evaluates the two decoder
+ * layers that read nearest-neighbour upsampled tensors in the polyphase form
+ * (per output parity, a 2x2x2 convolution of the coarse tensor with summed
+ * taps) where the coarse grid is a multiple of 64; it differs from the
+ * training forward pass only by the BF16 rounding of those summed weights. */
 int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
                     float *yhat_out, void *ws, size_t ws_bytes, pm_stream_t stream);
 
