@@ -227,17 +227,19 @@ int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const
  *  - block_cycle_grid: the coarse end of every V-cycle (and of full
  *    multigrid) runs as one single-workgroup launch from the first level
  *    whose grid is at most this (0: every level launches its own kernels);
- *  - tiled_smoother (0 off, 1 small tiles, 2 large tiles): the large levels
- *    (grid >= 64, divisible by 8 and by 64 or 128) use the 2.5D-tiled
- *    red-black half-sweep, whose cell updates equal the untiled ones bit for
- *    bit; large tiles (16 rows x 64 x 16 planes) replace small ones (4 or 8
- *    rows x 64 or 32 x 8 planes) where they still give 512 tiles.
+ *  - tiled_smoother (0 off, 1 small tiles, 2 large tiles, 3 largest
+ *    tiles): the large levels (grid >= 64, divisible by 8 and by 64 or 128)
+ *    use the 2.5D-tiled red-black half-sweep, whose cell updates equal the
+ *    untiled ones bit for bit; large tiles (8 rows x 64 packed cells x 16
+ *    planes, 8 in FP64) replace small ones (4 rows x 64 or 8 rows x 32, 8
+ *    planes) where they still give 512 tiles, and the largest (16 rows x 64 x
+ *    16 planes) replace large ones under the same rule.
  * Defaults 8 and 1.  They change the cost of a cycle, and the grouping of
  * the partial sums behind the lagged means, not the converged answer.
  * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a
  * synthetic density (uniform hash noise per cell in [0.2, 1.8], rough at every
  * scale) for every candidate (block_cycle_grid in off, 8, 16, 32, 64;
- * tiled_smoother 0, 1, 2) and keeps the fastest for (ng, precision);
+ * tiled_smoother 0, 1, 2, 3) and keeps the fastest for (ng, precision);
  * workspace: pm_autotune_workspace_bytes.  pm_tune_save / pm_tune_load write and read
  * the table as text lines "ng word_bytes block_cycle_grid tiled_smoother".
  * The table is process-wide. */
@@ -308,11 +310,24 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
  * input channels are the nearest-neighbour upsampling of x (a coarse
  * (n/2)^3 x 2cin/3 tensor) and whose last cin/3 channels are dy (n^3 x
  * cin/3), evaluated in the polyphase form the network uses at inference
- * ((cin, cout) = (48, 16) or (96, 32), n a multiple of 128).  w: FP32 W[27][cin][cout] (device); n a multiple of
- * 16; ws: 256-byte aligned, at least 2 * W + 4 * 240 * (27 cin cout + cout)
- * bytes with W = 54 * pad16(cin) * pad16(cout) rounded up to 256. */
+ * ((cin, cout) = (48, 16) or (96, 32), n a multiple of 128); mode 4 the
+ * network's last layer with its output head as inference runs them, out[n^3]
+ * = hb + sum_o hw[o] relu(b[o] + conv(x)[o]) (cin = cout = 16, n a multiple
+ * of 64; b holds the 16 biases, then hw[16], then hb).  w: FP32
+ * W[27][cin][cout] (device); n a multiple of 16; ws: 256-byte aligned, at
+ * least 2 * W + 4 * 240 * (27 cin cout + cout) bytes with W = 54 *
+ * pad16(cin) * pad16(cout) rounded up to 256. */
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
              const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* The network's first layer as inference runs it (for testing the kernel):
+ * the 4-channel input [f, x1, x2, x3] with x1..x3 the same at every voxel
+ * (the broadcast parameters), out[n^3][16] = b + conv(input) (FP32, no
+ * ReLU), computed as a single-channel convolution of f (n^3 BF16, natural
+ * order) plus the broadcast channels' constant.  w: FP32 W[27][4][16], b[16]
+ * (device); xc: HOST [3]; n a multiple of 64. */
+int ws_conv3_first(int n, const void *f_bf16, const float *w, const float *b, const float *xc /* HOST [3] */,
+                   float *out, pm_stream_t stream);
 
 /* Measurement hooks.  While enabled, each launch of the finest-level
  * red-black smoother (one colour per launch) is bracketed by HIP events on

@@ -82,9 +82,16 @@ def init_params(seed=0):
     return p
 
 
-def forward(p, x0):
-    """Returns (yhat (n,n,n), cache) for the input x0 (n,n,n,4)."""
-    c = {"x0": x0}
+class _NoCache(dict):
+    def __setitem__(self, key, value):
+        pass
+
+
+def forward(p, x0, keep=True):
+    """Returns (yhat (n,n,n), cache) for the input x0 (n,n,n,4).  With
+    keep=False the activations are not kept (cache is empty), which bounds
+    the memory of large grids."""
+    c = {"x0": x0} if keep else _NoCache()
     a = relu(conv3(x0, p["l1a.w"], p["l1a.b"]))
     c["a1"] = a
     s1 = relu(conv3(a, p["l1b.w"], p["l1b.b"]))

@@ -56,7 +56,7 @@ EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_de
            "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
            "pm_strerror", "pm_sort_workspace_bytes", "pm_sort_particles", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
            "pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
-           "ws_conv3")
+           "ws_conv3", "ws_conv3_first")
 
 
 def _load():
@@ -100,7 +100,8 @@ def _load():
     lib.ws_unet_forward.argtypes = [vp, vp, i, P(EftParams), vp, vp, sz, vp]
     lib.ws_unet_train_step.argtypes = [vp, vp, vp, ll, d, d, vp, vp, i, P(EftParams), vp, P(d), P(d), vp, sz, vp]
     lib.ws_conv3.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp, sz, vp]
-    for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3"):
+    lib.ws_conv3_first.argtypes = [i, vp, vp, vp, P(ctypes.c_float), vp, vp]
+    for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3", "ws_conv3_first"):
         getattr(lib, name).restype = i
     lib.pm_strerror.argtypes = [i]
     lib.pm_strerror.restype = ctypes.c_char_p

@@ -46,6 +46,11 @@ void launch_pack_conv_sub(const float *w, int cin, int cout, int c0, int csub, i
 bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp, int cout_pad, const float *bias,
                         const float *add, int cout, void *out, int out_stride, int out_off, bool out_f32, bool relu,
                         hipStream_t st);
+void launch_unet_feature(const double *delta_packed, int n, const double *stats, uint16_t *f, hipStream_t st);
+bool launch_conv3_in1(const uint16_t *f, const float *w, const float *b, float x1, float x2, float x3, void *out,
+                      int out_stride, int out_off, bool out_f32, int n, hipStream_t st);
+bool launch_conv3_head(const uint16_t *in, int in_stride, int in_off, const uint16_t *wp, const float *bias,
+                       const float *hw, const float *hb, float *yhat, int n, hipStream_t st);
 namespace {
 
 struct ConvSpec {
@@ -184,62 +189,91 @@ void pack_all(Net &N, const float *params)
         }
 }
 
-// Inference form of decoder layer kFused[f] (input tensor ti = [upsampled |
-// skip], coarse tensor tc, output to): the skip channels' convolution into an
-// FP32 scratch (the input and first activation tensors, dead by then), then
-// the polyphase convolution of tc adds it, the bias and the ReLU.
-bool fused_up_conv(Net &N, const float *params, int f, int ti, int tc, int to)
+// A slice of an activation tensor: tensor t, voxel stride, channel offset.
+struct View {
+    int t, stride, off;
+};
+View whole(int t) { return View{t, kTChan[t], 0}; }
+
+// Inference form of decoder layer kFused[f] (skip channels in view `skip`,
+// coarse tensor tc, output to): the skip channels' convolution into an FP32
+// scratch (the input and first activation tensors, dead by then), then the
+// polyphase convolution of tc adds it, the bias and the ReLU.
+// Needs N.dim(tc) % 64 == 0 (the polyphase instances).
+void fused_up_conv(Net &N, const float *params, int f, View skip, int tc, int to)
 {
     const ParamLayout L = param_layout();
     const int l = kFused[f], cin = kConv[l].cin, cout = kConv[l].cout, up = kFusedUp[f];
-    if (N.dim(tc) % 64)  // no polyphase instance for this grid
-        return false;
     float *scratch = (float *)N.act(X0);
-    launch_conv3(N.act(ti), kTChan[ti], up, pad16(cin - up), (const uint16_t *)(N.ws + N.P.wsub[f]), pad16(cout),
-                 nullptr, cout, scratch, cout, 0, true, N.dim(to), false, false, N.st);
-    return launch_upconv_poly(N.act(tc), up, N.dim(tc), (const uint16_t *)(N.ws + N.P.wpoly[f]), pad16(cout),
-                              params + L.b[l], scratch, cout, N.act(to), kTChan[to], 0, false, true, N.st);
+    launch_conv3(N.act(skip.t), skip.stride, skip.off, pad16(cin - up), (const uint16_t *)(N.ws + N.P.wsub[f]),
+                 pad16(cout), nullptr, cout, scratch, cout, 0, true, N.dim(to), false, false, N.st);
+    launch_upconv_poly(N.act(tc), up, N.dim(tc), (const uint16_t *)(N.ws + N.P.wpoly[f]), pad16(cout),
+                       params + L.b[l], scratch, cout, N.act(to), kTChan[to], 0, false, true, N.st);
 }
 
-// conv layer l: input tensor (ti, channel offset), output (to, offset)
-void conv_fwd(Net &N, const float *params, int l, int ti, int ioff, int to, int ooff)
+// conv layer l (ReLU) from view vi into view vo
+void conv_fwd(Net &N, const float *params, int l, View vi, View vo)
 {
     const ParamLayout L = param_layout();
-    launch_conv3(N.act(ti), kTChan[ti], ioff, pad16(kConv[l].cin), (const uint16_t *)(N.ws + N.P.wf[l]),
-                 pad16(kConv[l].cout), params + L.b[l], kConv[l].cout, N.act(to), kTChan[to], ooff, false, N.dim(to),
-                 false, true, N.st);
+    launch_conv3(N.act(vi.t), vi.stride, vi.off, pad16(kConv[l].cin), (const uint16_t *)(N.ws + N.P.wf[l]),
+                 pad16(kConv[l].cout), params + L.b[l], kConv[l].cout, N.act(vo.t), vo.stride, vo.off, false,
+                 N.dim(vo.t), false, true, N.st);
 }
 
-// delta: packed, mean-free density contrast
+// delta: packed, mean-free density contrast.  Training keeps every
+// activation the backward pass reads, in the concatenation layout.
+// Inference (all exact rewrites of the same network): the first layer runs
+// on the density channel alone with the broadcast channels folded into its
+// bias; the two decoder layers that read upsampled tensors run in the
+// polyphase form (no upsampled tensor; their skip tensors then live in
+// compact views, not in the concatenation buffers); the last layer applies
+// the output head in its epilogue.
 void forward(Net &N, const float *params, const double *delta, const pm_eft_params &p)
 {
     const int n = N.P.n;
     const unsigned nv = (unsigned)n * n * n;
-    launch_feature_stats(delta, nv, N.rs, N.st);
-    launch_unet_input(delta, n, N.rs.out, (float)p.alpha_b0, (float)p.alpha_m0, (float)p.a, N.act(X0), N.st);
-    conv_fwd(N, params, 0, X0, 0, A1, 0);
-    conv_fwd(N, params, 1, A1, 0, C1, 32);  // skip 1 -> C1[32:48]
-    launch_pool(N.act(C1), 48, 32, N.act(P1), 16, 0, 16, n / 2, N.st);
-    conv_fwd(N, params, 2, P1, 0, A2, 0);
-    conv_fwd(N, params, 3, A2, 0, C2, 64);  // skip 2 -> C2[64:96]
-    launch_pool(N.act(C2), 96, 64, N.act(P2), 32, 0, 32, n / 4, N.st);
-    conv_fwd(N, params, 4, P2, 0, A3, 0);
-    conv_fwd(N, params, 5, A3, 0, B3, 0);
-    // inference skips the upsampled tensors (polyphase form); training keeps
-    // them, the backward pass reads them
-    const bool fused = !N.P.training;
-    if (!fused || !fused_up_conv(N, params, 0, C2, B3, A4)) {
-        launch_up(N.act(B3), 64, 0, N.act(C2), 96, 0, 64, n / 2, N.st);
-        conv_fwd(N, params, 6, C2, 0, A4, 0);
-    }
-    conv_fwd(N, params, 7, A4, 0, B4, 0);
-    if (!fused || !fused_up_conv(N, params, 1, C1, B4, A5)) {
-        launch_up(N.act(B4), 32, 0, N.act(C1), 48, 0, 32, n, N.st);
-        conv_fwd(N, params, 8, C1, 0, A5, 0);
-    }
-    conv_fwd(N, params, 9, A5, 0, B5, 0);
     const ParamLayout L = param_layout();
-    launch_head(N.act(B5), params + L.hw, params + L.hb, nv, (float *)(N.ws + N.P.yhat), N.st);
+    const bool infer = !N.P.training;
+    const bool poly0 = infer && N.dim(B3) % 64 == 0, poly1 = infer && N.dim(B4) % 64 == 0;
+    const View s1 = poly1 ? View{C1, 16, 0} : View{C1, 48, 32};  // skip 1
+    const View s2 = poly0 ? View{C2, 32, 0} : View{C2, 96, 64};  // skip 2
+    launch_feature_stats(delta, nv, N.rs, N.st);
+    bool first = false;
+    if (infer) {
+        launch_unet_feature(delta, n, N.rs.out, N.act(X0), N.st);
+        first = launch_conv3_in1(N.act(X0), params + L.w[0], params + L.b[0], (float)p.alpha_b0, (float)p.alpha_m0,
+                                 (float)p.a, N.act(A1), kTChan[A1], 0, false, n, N.st);
+    }
+    if (!first) {
+        launch_unet_input(delta, n, N.rs.out, (float)p.alpha_b0, (float)p.alpha_m0, (float)p.a, N.act(X0), N.st);
+        conv_fwd(N, params, 0, whole(X0), whole(A1));
+    }
+    conv_fwd(N, params, 1, whole(A1), s1);
+    launch_pool(N.act(C1), s1.stride, s1.off, N.act(P1), 16, 0, 16, n / 2, N.st);
+    conv_fwd(N, params, 2, whole(P1), whole(A2));
+    conv_fwd(N, params, 3, whole(A2), s2);
+    launch_pool(N.act(C2), s2.stride, s2.off, N.act(P2), 32, 0, 32, n / 4, N.st);
+    conv_fwd(N, params, 4, whole(P2), whole(A3));
+    conv_fwd(N, params, 5, whole(A3), whole(B3));
+    if (poly0) {
+        fused_up_conv(N, params, 0, s2, B3, A4);
+    } else {
+        launch_up(N.act(B3), 64, 0, N.act(C2), 96, 0, 64, n / 2, N.st);
+        conv_fwd(N, params, 6, whole(C2), whole(A4));
+    }
+    conv_fwd(N, params, 7, whole(A4), whole(B4));
+    if (poly1) {
+        fused_up_conv(N, params, 1, s1, B4, A5);
+    } else {
+        launch_up(N.act(B4), 32, 0, N.act(C1), 48, 0, 32, n, N.st);
+        conv_fwd(N, params, 8, whole(C1), whole(A5));
+    }
+    float *yhat = (float *)(N.ws + N.P.yhat);
+    if (infer && launch_conv3_head(N.act(A5), kTChan[A5], 0, (const uint16_t *)(N.ws + N.P.wf[9]), params + L.b[9],
+                                   params + L.hw, params + L.hb, yhat, n, N.st))
+        return;
+    conv_fwd(N, params, 9, whole(A5), whole(B5));
+    launch_head(N.act(B5), params + L.hw, params + L.hb, nv, yhat, N.st);
 }
 
 // backward of conv layer l given the (already ReLU-masked) output gradient
@@ -457,8 +491,11 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
 int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void *dy_bf16, const float *w,
              const float *b, float *out, void *ws, size_t ws_bytes, pm_stream_t stream)
 {
-    if (mode < 0 || mode > 3 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws ||
+    if (mode < 0 || mode > 4 || n < 16 || n % 16 || cin < 1 || cout < 1 || cin > 96 || cout > 96 || !w || !out || !ws ||
         ((uintptr_t)ws & 255))
+        return PM_EINVAL;
+    // mode 4, b: [cout biases | head weights (16) | head bias]
+    if (mode == 4 && (!x_bf16 || !b || cin != 16 || cout != 16 || n % 64))
         return PM_EINVAL;
     const size_t wbytes = ((sizeof(uint16_t) * 27 * pad16(cin) * pad16(cout)) + 255) & ~(size_t)255;
     const size_t need = 2 * wbytes + sizeof(float) * wgrad_partial_floats(cin, cout);
@@ -488,6 +525,11 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
         return launched();
     }
     launch_pack_conv(w, cin, cout, pad16(cin), pad16(cout), wf, wd, st);
+    if (mode == 4) {
+        if (!launch_conv3_head((const uint16_t *)x_bf16, 16, 0, wf, b, b + 16, b + 32, out, n, st))
+            return PM_EINVAL;
+        return launched();
+    }
     if (mode == 0) {
         if (!x_bf16 || cin % 16)
             return PM_EINVAL;
@@ -504,6 +546,17 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
         launch_conv3_wgrad((const uint16_t *)x_bf16, cin, 0, cin, (const uint16_t *)dy_bf16, cout, 0, cout, out,
                            nullptr, part, n, st);
     }
+    return launched();
+}
+
+int ws_conv3_first(int n, const void *f_bf16, const float *w, const float *b, const float *xc, float *out,
+                   pm_stream_t stream)
+{
+    if (n < 64 || n % 64 || !f_bf16 || !w || !b || !xc || !out)
+        return PM_EINVAL;
+    if (!launch_conv3_in1((const uint16_t *)f_bf16, w, b, xc[0], xc[1], xc[2], out, 16, 0, true, n,
+                          (hipStream_t)stream))
+        return PM_EINVAL;
     return launched();
 }
 

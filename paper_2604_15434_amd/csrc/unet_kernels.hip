@@ -265,17 +265,31 @@ static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int c
 // odd number of 16-byte units (the 16-byte fragment reads of 8 consecutive
 // lanes then fall in distinct banks).
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMarchThreads = 512;
 
-template <int CS, int COT, int NS>
+//
+// HD (one 16-channel output tile, ReLU): the network's 1x1x1 output head is
+// applied in the epilogue, out[v] = hb + sum_o hw[o] relu(conv[v][o]) as
+// FP32 in natural voxel order, and the 16-channel activation is never stored
+// (nor rounded to BF16, as the unfused form rounds it).  The channel sum runs over the 16 lanes of a row of the MFMA result
+// (row rotations 8, 4, 2, 1).
+template <int CS, int COT, int NS, bool HD = false>
 __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *__restrict__ in, int in_stride, int in_off,
                                                      const uint16_t *__restrict__ wp, int cout_pad,
                                                      const float *__restrict__ bias, int cout, void *__restrict__ out,
                                                      int out_stride, int out_off, int out_f32, int n, int flip,
-                                                     int relu, unsigned ntiles, int PL)
+                                                     int relu, unsigned ntiles, int PL, const float *__restrict__ hw,
+                                                     const float *__restrict__ hb)
 {
+    static_assert(!HD || COT == 1, "the head reads one output tile");
+    // TR: weights as the A operand, so the result is D[channel][voxel] and a
+    // lane holds four consecutive channels of one voxel (vector stores when
+    // the output view is 4-aligned); the head keeps D[voxel][channel]
+    constexpr bool TR = !HD;
+    const bool vec = out_stride % 4 == 0 && out_off % 4 == 0;
     constexpr int CP = 16 * CS;                 // input channels (padded)
     constexpr int SV = CP + 8;                  // LDS voxel stride (halfwords)
     constexpr int WV = 6 * 66;                  // voxels per staged plane
@@ -287,7 +301,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
     const int wave = threadIdx.x >> 7, mh = ((threadIdx.x >> 6) & 1) * 2;  // row, first m-tile
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
-    const int nkt = n / 64, njt = n / 4, nit = n / PL;
+    const int nkt = n / 64, nit = n / PL;
     const int co_base = blockIdx.y * COT * 16;
     const int sgn = flip ? -1 : 1;
     const size_t plane_elems = (size_t)n * n * in_stride;
@@ -381,8 +395,10 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                     if (ku >= 0) {
 #pragma unroll
                         for (int m = 0; m < 2; m++)
-                            acc[m][0] =
-                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ku % DEPTH][m], bw[ku], acc[m][0], 0, 0, 0);
+                            acc[m][0] = TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[ku], af[ku % DEPTH][m],
+                                                                                     acc[m][0], 0, 0, 0)
+                                           : __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ku % DEPTH][m], bw[ku],
+                                                                                     acc[m][0], 0, 0, 0);
                     }
                 }
             } else {
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                         const bf16x8 a = __builtin_bit_cast(bf16x8, *(const u32x4 *)(ring + ab + 16 * m * SV));
 #pragma unroll
                         for (int u = 0; u < COT; u++)
-                            acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[u], acc[m][u], 0, 0, 0);
+                            acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a, acc[m][u], 0, 0, 0);
                     }
                 }
             }
@@ -418,29 +434,71 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                     const bf16x4 a = *(const bf16x4 *)(ring + ab + 16 * m * SV);
 #pragma unroll
                     for (int u = 0; u < COT; u++)
-                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[u], acc[m][u], 0, 0, 0);
+                        acc[m][u] = TR ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[u], a, acc[m][u], 0, 0, 0)
+                                       : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[u], acc[m][u], 0, 0, 0);
                 }
             }
             const size_t vbase = ((size_t)i * n + j0 + wave) * n + k0;
-#pragma unroll
-            for (int u = 0; u < COT; u++) {
-                const int o = co_base + u * 16 + r;
-                if (o >= cout)
-                    continue;
-                const float bo = bias ? bias[o] : 0.f;
+            if constexpr (HD) {
+                // lane (r, q) holds channel r of voxels 16 (mh + m) + 4 q + e
+                const float bo = bias[r], ho = hw[r];
+                float s[2][4];
 #pragma unroll
                 for (int m = 0; m < 2; m++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        float v = acc[m][u][e] + bo;
-                        if (relu)
-                            v = fmaxf(v, 0.f);
-                        const size_t idx = (vbase + 16 * (mh + m) + 4 * q + e) * out_stride + out_off + o;
-                        if (out_f32)
-                            ((float *)out)[idx] = v;
-                        else
-                            ((uint16_t *)out)[idx] = f2bf(v);
+                        float v = ho * fmaxf(acc[m][0][e] + bo, 0.f);
+                        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+                        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
+                        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));
+                        v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));
+                        s[m][e] = v;
                     }
+                // every lane of a row now holds the row's eight sums; lane r < 8
+                // writes voxel 16 (mh + r / 4) + 4 q + r % 4
+                const int mm = (r >> 2) & 1, ee = r & 3;
+                float y = s[0][0];
+#pragma unroll
+                for (int m = 0; m < 2; m++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        y = (mm == m && ee == e) ? s[m][e] : y;
+                if (r < 8)
+                    ((float *)out)[vbase + 16 * (mh + mm) + 4 * q + ee] = hb[0] + y;
+            } else {
+                // lane (r, q) holds channels 4q .. 4q + 3 (+ 16 u) of voxel 16 (mh + m) + r
+#pragma unroll
+                for (int u = 0; u < COT; u++) {
+                    const int o0 = co_base + u * 16 + 4 * q;
+                    float bo[4];
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        bo[e] = (bias && o0 + e < cout) ? bias[o0 + e] : 0.f;
+#pragma unroll
+                    for (int m = 0; m < 2; m++) {
+                        float v[4];
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            v[e] = relu ? fmaxf(acc[m][u][e] + bo[e], 0.f) : acc[m][u][e] + bo[e];
+                        const size_t idx = (vbase + 16 * (mh + m) + r) * out_stride + out_off + o0;
+                        if (vec && o0 + 3 < cout) {
+                            if (out_f32)
+                                *(f32x4 *)((float *)out + idx) = (f32x4){v[0], v[1], v[2], v[3]};
+                            else
+                                *(u16x4 *)((uint16_t *)out + idx) =
+                                    (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                if (o0 + e < cout) {
+                                    if (out_f32)
+                                        ((float *)out)[idx + e] = v[e];
+                                    else
+                                        ((uint16_t *)out)[idx + e] = f2bf(v[e]);
+                                }
+                        }
+                    }
+                }
             }
             if (NS == 4) {
                 // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
@@ -506,6 +564,10 @@ __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict_
     __syncthreads();
     const int J = J0 + wave;
     const int nf = 2 * nc;
+    // weights as the A operand: lane (r, q) receives channels 4q .. 4q + 3
+    // (+ 16 u) of coarse voxel K0 + 16 m + r, so the addend loads and the
+    // output stores are 4-channel vectors when the views allow
+    const bool vec = cout % 4 == 0 && out_stride % 4 == 0 && out_off % 4 == 0;
     for (int p = 0; p < 8; p++) {
         const int pi = p >> 2, pj = (p >> 1) & 1, pk = p & 1;
         f32x4 acc[MT][COT];
@@ -515,12 +577,18 @@ __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict_
 #pragma unroll
             for (int u = 0; u < COT; u++) {
                 acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                const int o = co_base + u * 16 + r;
+                const int o0 = co_base + u * 16 + 4 * q;
+                const int K = K0 + 16 * m + r;
+                const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
+                if (vec && o0 + 3 < cout) {
+                    const f32x4 x = *(const f32x4 *)(add + fv * cout + o0);
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int K = K0 + 16 * m + 4 * q + e;
-                    const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
-                    addv[m][u][e] = o < cout ? add[fv * cout + o] : 0.f;
+                    for (int e = 0; e < 4; e++)
+                        addv[m][u][e] = x[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        addv[m][u][e] = o0 + e < cout ? add[fv * cout + o0 + e] : 0.f;
                 }
             }
 #pragma unroll
@@ -541,31 +609,46 @@ __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict_
                         __builtin_bit_cast(bf16x8, *(const u32x4 *)(tile + (ab + 16 * m) * SV + ch + 8 * q));
 #pragma unroll
                     for (int u = 0; u < COT; u++)
-                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[u], acc[m][u], 0, 0, 0);
+                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a, acc[m][u], 0, 0, 0);
                 }
             }
         }
 #pragma unroll
         for (int u = 0; u < COT; u++) {
-            const int o = co_base + u * 16 + r;
-            if (o >= cout)
-                continue;
-            const float bo = bias ? bias[o] : 0.f;
+            const int o0 = co_base + u * 16 + 4 * q;
+            float bo[4];
 #pragma unroll
-            for (int m = 0; m < MT; m++)
+            for (int e = 0; e < 4; e++)
+                bo[e] = (bias && o0 + e < cout) ? bias[o0 + e] : 0.f;
+#pragma unroll
+            for (int m = 0; m < MT; m++) {
+                const int K = K0 + 16 * m + r;
+                const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
+                float v[4];
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const int K = K0 + 16 * m + 4 * q + e;
-                    const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
-                    float v = acc[m][u][e] + bo + addv[m][u][e];
+                    v[e] = acc[m][u][e] + bo[e] + addv[m][u][e];
                     if (relu)
-                        v = fmaxf(v, 0.f);
-                    const size_t oi_ = fv * out_stride + out_off + o;
-                    if (out_f32)
-                        ((float *)out)[oi_] = v;  // may alias add: same element, same thread
-                    else
-                        ((uint16_t *)out)[oi_] = f2bf(v);
+                        v[e] = fmaxf(v[e], 0.f);
                 }
+                // out may alias add: same elements, same thread
+                const size_t oi_ = fv * out_stride + out_off + o0;
+                if (vec && o0 + 3 < cout) {
+                    if (out_f32)
+                        *(f32x4 *)((float *)out + oi_) = (f32x4){v[0], v[1], v[2], v[3]};
+                    else
+                        *(u16x4 *)((uint16_t *)out + oi_) = (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if (o0 + e < cout) {
+                            if (out_f32)
+                                ((float *)out)[oi_ + e] = v[e];
+                            else
+                                ((uint16_t *)out)[oi_ + e] = f2bf(v[e]);
+                        }
+                }
+            }
         }
     }
 }
@@ -645,6 +728,23 @@ bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp,
     return false;
 }
 
+// 16 -> 16 convolution with ReLU followed by the 1x1x1 head (yhat, FP32,
+// natural order); false when the grid has no plane-marching instance.
+bool launch_conv3_head(const uint16_t *in, int in_stride, int in_off, const uint16_t *wp, const float *bias,
+                       const float *hw, const float *hb, float *yhat, int n, hipStream_t st)
+{
+    if (n % 64 || in_stride % 8 || in_off % 8)
+        return false;
+    const int PL = n >= 256 ? 16 : 8;
+    const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
+    unsigned nb = ntiles < 2048u ? ntiles : 2048u;
+    if (nb >= 8)
+        nb -= nb % 8;
+    hipLaunchKernelGGL((k_conv3_march<1, 1, 4, true>), dim3(nb, 1), dim3(kMarchThreads), 0, st, in, in_stride, in_off,
+                       wp, 16, bias, 16, (void *)yhat, 1, 0, 1, n, 0, 1, ntiles, PL, hw, hb);
+    return true;
+}
+
 void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, const uint16_t *wp, int cout_pad,
                   const float *bias, int cout, void *out, int out_stride, int out_off, bool out_f32, int n, bool flip,
                   bool relu, hipStream_t st)
@@ -660,7 +760,7 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
 #define PM_CONVM(CSV, C, NSV)                                                                                          \
     hipLaunchKernelGGL((k_conv3_march<CSV, C, NSV>), grid, dim3(kMarchThreads), 0, st, in, in_stride, in_off, wp, cout_pad,     \
                        bias, cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles,   \
-                       PL)
+                       PL, nullptr, nullptr)
 #define PM_CONVM_C(CSV, NSV)                                                                                           \
     do {                                                                                                               \
         if (cot == 2)                                                                                                  \
@@ -1067,6 +1167,168 @@ void launch_unet_input(const double *delta_packed, int n, const double *stats, f
                        uint16_t *x0, hipStream_t st)
 {
     hipLaunchKernelGGL(k_unet_input, dim3(2048), dim3(256), 0, st, delta_packed, n, stats, ab0, am0, a, x0);
+}
+
+// Inference input: the density channel alone, f[v] = bf16(standardised
+// feature), natural order; the three broadcast channels enter the first
+// layer as a constant (k_conv3_in1).
+__global__ __launch_bounds__(256) void k_unet_feature(const double *__restrict__ delta, int n,
+                                                      const double *__restrict__ stats, uint16_t *__restrict__ f)
+{
+    const unsigned nvox = (unsigned)n * n * n;
+    const double mean = stats[0] / nvox;
+    const double var = fmax(stats[1] / nvox - mean * mean, 1e-30);
+    const double inv = 1.0 / sqrt(var);
+    for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256)
+        f[v] = f2bf((float)((feature_of(delta[packed_index(v, n)]) - mean) * inv));
+}
+
+void launch_unet_feature(const double *delta_packed, int n, const double *stats, uint16_t *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unet_feature, dim3(2048), dim3(256), 0, st, delta_packed, n, stats, f);
+}
+
+// First layer at inference (4 -> 16 channels, ReLU).  Channels 1..3 of its
+// input are the same value at every voxel and the padding is periodic, so
+// their taps add a per-channel constant: out[v][o] = relu(b'[o] + sum_t
+// f[v + d_t] W[t][0][o]) with b'[o] = b[o] + sum_{t, c >= 1} bf16(x_c)
+// bf16(W[t][c][o]) (the operands the general convolution would multiply).
+// The remaining single-channel convolution is one 16x16x32 MFMA per 16
+// voxels: A[m = o][k = tap] the weights (taps 27..31 zero), B[k = tap][n =
+// voxel] gathered from LDS, so the result D[o][v] gives each lane four
+// consecutive channels of one voxel (one 8-byte store; 16 bytes with F32
+// output, no ReLU: the test form).  Block: 4 waves, one row j each, 64
+// voxels along k, marching PL planes along i with planes i - 1 .. i + 2 of
+// the 6 x 66 window in a ring of four slots (the next plane's loads are
+// issued before the current plane is computed).  w: FP32 weights
+// w[t][c][o] of the 4-channel layer.
+template <bool F32>
+__global__ __launch_bounds__(256) void k_conv3_in1(const uint16_t *__restrict__ f, const float *__restrict__ w,
+                                                   const float *__restrict__ b, float x1, float x2, float x3,
+                                                   void *__restrict__ out, int out_stride, int out_off, int n, int PL)
+{
+    constexpr int RW = 66, PW = 6 * RW;  // window plane: 6 rows x 66 voxels
+    __shared__ uint16_t ring[4 * PW];
+    __shared__ float part[27 * 16];
+    __shared__ float beff[16];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane & 15, q = lane >> 4;
+    const unsigned nkt = (unsigned)(n / 64), nit = (unsigned)(n / PL);
+    const unsigned tile = xcd_block(0);
+    const int ib = (int)(tile % nit), kt = (int)((tile / nit) % nkt), jt = (int)(tile / (nit * nkt));
+    const int i0 = ib * PL, j0 = jt * 4, k0 = kt * 64;
+    // the broadcast channels' constant: 27 x 16 partial sums, then per channel
+    {
+        const float xb1 = bf2f(f2bf(x1)), xb2 = bf2f(f2bf(x2)), xb3 = bf2f(f2bf(x3));
+        for (int x = threadIdx.x; x < 27 * 16; x += 256) {
+            const float *wt = w + (size_t)(x >> 4) * 64 + (x & 15);
+            part[x] = xb1 * bf2f(f2bf(wt[16])) + xb2 * bf2f(f2bf(wt[32])) + xb3 * bf2f(f2bf(wt[48]));
+        }
+    }
+    // this thread's window elements (two at most: 396 per plane)
+    unsigned soff[2];
+    int loff[2];
+    bool has[2];
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int e = threadIdx.x + 256 * u;
+        has[u] = e < PW;
+        const int ee = has[u] ? e : 0, row = ee / RW, col = ee - row * RW;
+        soff[u] = (unsigned)(wrapi(j0 + row - 1, n) * n + wrapi(k0 + col - 1, n));
+        loff[u] = ee;
+    }
+    uint16_t pre[2];
+    const size_t plane = (size_t)n * n;
+#define PM_IN1_FETCH(II)                                                                                               \
+    do {                                                                                                               \
+        const uint16_t *src_ = f + (size_t)wrapi((II), n) * plane;                                                     \
+        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) pre[u] = src_[soff[u]];                             \
+    } while (0)
+#define PM_IN1_STORE(SLOT)                                                                                             \
+    do {                                                                                                               \
+        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) ring[(SLOT) * PW + loff[u]] = pre[u];              \
+    } while (0)
+    PM_IN1_FETCH(i0 - 1);
+    PM_IN1_STORE(0);
+    PM_IN1_FETCH(i0);
+    PM_IN1_STORE(1);
+    PM_IN1_FETCH(i0 + 1);
+    PM_IN1_STORE(2);
+    // A: lane (r, q) holds W[t][0][r] for the taps t = 8q .. 8q + 7; the B
+    // gather of voxel r reads window row 1 + wave + dj, column 1 + dk + r
+    bf16x8 a;
+    int roff[8], dio[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int t = 8 * q + u;
+        int di, dj, dk;
+        tap_offsets(t < 27 ? t : 13, di, dj, dk);
+        a[u] = t < 27 ? __builtin_bit_cast(__bf16, f2bf(w[(size_t)t * 64 + r])) : __builtin_bit_cast(__bf16, (uint16_t)0);
+        roff[u] = t < 27 ? (1 + wave + dj) * RW + 1 + dk : -1;
+        dio[u] = di;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        float sb = b[threadIdx.x];
+        for (int t = 0; t < 27; t++)
+            sb += part[t * 16 + threadIdx.x];
+        beff[threadIdx.x] = sb;
+    }
+    __syncthreads();
+    const float bq[4] = {beff[4 * q], beff[4 * q + 1], beff[4 * q + 2], beff[4 * q + 3]};
+    for (int p = 0; p < PL; p++) {
+        const int i = i0 + p;
+        if (p + 1 < PL)
+            PM_IN1_FETCH(i + 2);
+        int toff[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            toff[u] = roff[u] >= 0 ? ((p + 1 + dio[u]) & 3) * PW + roff[u] : -1;
+        const size_t vrow = ((size_t)i * n + j0 + wave) * n + k0;
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            bf16x8 bv;
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                bv[u] = toff[u] >= 0 ? __builtin_bit_cast(__bf16, ring[toff[u] + 16 * m + r])
+                                     : __builtin_bit_cast(__bf16, (uint16_t)0);
+            const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, (f32x4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            // lane (r, q): channels 4q .. 4q + 3 of voxel 16 m + r
+            const size_t idx = (vrow + 16 * m + r) * out_stride + out_off + 4 * q;
+            if constexpr (F32) {
+                *(f32x4 *)((float *)out + idx) = (f32x4){d[0] + bq[0], d[1] + bq[1], d[2] + bq[2], d[3] + bq[3]};
+            } else {
+                u16x4 y;
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    y[e] = f2bf(fmaxf(d[e] + bq[e], 0.f));
+                *(u16x4 *)((uint16_t *)out + idx) = y;
+            }
+        }
+        // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
+        if (p + 1 < PL)
+            PM_IN1_STORE((p + 3) & 3);
+        __syncthreads();
+    }
+#undef PM_IN1_STORE
+#undef PM_IN1_FETCH
+}
+
+// false unless n % 64 == 0 and the output view is 4-aligned
+bool launch_conv3_in1(const uint16_t *f, const float *w, const float *b, float x1, float x2, float x3, void *out,
+                      int out_stride, int out_off, bool out_f32, int n, hipStream_t st)
+{
+    if (n % 64 || out_stride % 4 || out_off % 4)
+        return false;
+    const int PL = n >= 256 ? 16 : 8;
+    const unsigned ntiles = (unsigned)(n / PL) * (n / 4) * (n / 64);
+    if (out_f32)
+        hipLaunchKernelGGL(k_conv3_in1<true>, dim3(ntiles), dim3(256), 0, st, f, w, b, x1, x2, x3, out, out_stride,
+                           out_off, n, PL);
+    else
+        hipLaunchKernelGGL(k_conv3_in1<false>, dim3(ntiles), dim3(256), 0, st, f, w, b, x1, x2, x3, out, out_stride,
+                           out_off, n, PL);
+    return true;
 }
 
 // Training target t = lap7(chi) / (h^2 s mu_chi) - delta (natural order out);

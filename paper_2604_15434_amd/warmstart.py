@@ -133,8 +133,10 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weig
 
 
 def _time_forward(argv=None):
-    """python -m paper_2604_15434_amd.warmstart --ng 256 [--reps 4]: wall time
-    of the trained network's forward pass on a seeded lognormal density."""
+    """python -m paper_2604_15434_amd.warmstart --ng 256 [--reps 4] [--train]:
+    wall time of the trained network's forward pass (or, with --train, of one
+    training step: forward, backward, Adam; lr 0) on a seeded lognormal
+    density."""
     import argparse
     import time
 
@@ -145,17 +147,23 @@ def _time_forward(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--ng", type=int, default=256)
     ap.add_argument("--reps", type=int, default=4)
+    ap.add_argument("--train", action="store_true")
     args = ap.parse_args(argv)
     net = WarmStart.load(DEFAULT_WEIGHTS)
     prm = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
     rho = torch.from_numpy(lognormal_density(args.ng, 500.0 * args.ng / 256, seed=2)).cuda()
     y = torch.zeros(args.ng**3, dtype=torch.float32, device="cuda")
+    chi = torch.zeros_like(rho)  # any target: the step's cost does not depend on it
+    what = "training step" if args.train else "forward"
     for i in range(args.reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        net.predict(rho, prm, y)
+        if args.train:
+            net.train_step(rho, chi, prm, 0.0)
+        else:
+            net.predict(rho, prm, y)
         torch.cuda.synchronize()
-        print(f"{args.ng}^3 forward {(time.perf_counter() - t0) * 1e3:.3f} ms" + (" (first call)" if i == 0 else ""),
+        print(f"{args.ng}^3 {what} {(time.perf_counter() - t0) * 1e3:.3f} ms" + (" (first call)" if i == 0 else ""),
               flush=True)
 
 

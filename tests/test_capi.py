@@ -86,10 +86,10 @@ def test_launch_shape_table_roundtrip(tmp_path):
     assert P.pm_get_launch_shape(96, 8) == (16, 0) and P.pm_get_launch_shape(96, 4) == (0, 1)
     with pytest.raises(P.PmError):
         P.pm_set_launch_shape(96, 2, 16)
-    P.pm_set_launch_shape(96, 8, 16, 2)
-    assert P.pm_get_launch_shape(96, 8) == (16, 2)
+    P.pm_set_launch_shape(96, 8, 16, 3)
+    assert P.pm_get_launch_shape(96, 8) == (16, 3)
     with pytest.raises(P.PmError):
-        P.pm_set_launch_shape(96, 8, 16, 3)
+        P.pm_set_launch_shape(96, 8, 16, 4)
     bad = tmp_path / "bad.txt"
     bad.write_text("96 3 16 1\n")
     with pytest.raises(P.PmError):
@@ -102,8 +102,10 @@ def test_launch_shape_table_roundtrip(tmp_path):
 
 def test_conv_test_entry_rejects_bad_arguments(lib):
     """ws_conv3 validates its arguments before touching the device: an
-    unknown mode, and for the upsampled-layer mode (3) channel counts without
-    a polyphase instance or a grid that is not a multiple of 128."""
+    unknown mode, for the upsampled-layer mode (3) channel counts without a
+    polyphase instance or a grid that is not a multiple of 128, and for the
+    last-layer-with-head mode (4) anything but 16 -> 16 channels on a grid
+    that is a multiple of 64."""
     f = lib.ws_conv3
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 6 + \
@@ -111,7 +113,28 @@ def test_conv_test_entry_rejects_bad_arguments(lib):
     fake = 1 << 20  # never dereferenced: every call below fails validation first
     big = 1 << 40
     einval = -1
-    assert f(4, 128, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval
+    assert f(5, 128, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval
+    assert f(4, 128, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval   # cin != 16
+    assert f(4, 96, 16, 16, fake, fake, fake, fake, fake, fake, big, None) == einval    # n % 64
+    assert f(4, 128, 16, 16, fake, fake, fake, None, fake, fake, big, None) == einval   # no biases
     assert f(3, 128, 40, 16, fake, fake, fake, fake, fake, fake, big, None) == einval   # cin % 3
     assert f(3, 64, 48, 16, fake, fake, fake, fake, fake, fake, big, None) == einval    # n % 128
     assert f(3, 128, 48, 16, None, fake, fake, fake, fake, fake, big, None) == einval   # no coarse tensor
+
+
+def test_first_layer_test_entry_rejects_bad_arguments(lib):
+    """ws_conv3_first (the first layer's inference form) rejects a grid that
+    is not a multiple of 64 and missing operands before touching the
+    device."""
+    f = lib.ws_conv3_first
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 6
+    fake = 1 << 20  # never dereferenced
+    xc = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    xp = ctypes.cast(xc, ctypes.c_void_p)
+    einval = -1
+    assert f(96, fake, fake, fake, xp, fake, None) == einval    # n % 64
+    assert f(32, fake, fake, fake, xp, fake, None) == einval    # n < 64
+    assert f(64, None, fake, fake, xp, fake, None) == einval    # no feature
+    assert f(64, fake, fake, fake, None, fake, None) == einval  # no broadcast values
+    assert f(64, fake, fake, fake, xp, None, None) == einval    # no output

@@ -41,7 +41,7 @@ def P():
 
 def _conv(P, mode, n, cin, cout, x=None, dy=None, w=None, b=None):
     L = P._lib
-    out_n = {0: n**3 * cout, 1: n**3 * cin, 2: 27 * cin * cout}[mode]
+    out_n = {0: n**3 * cout, 1: n**3 * cin, 2: 27 * cin * cout, 4: n**3}[mode]
     out = torch.zeros(out_n, dtype=torch.float32, device="cuda")
     wb = (54 * ((cin + 15) // 16 * 16) * ((cout + 15) // 16 * 16) + 255) // 256 * 256
     wsz = 2 * wb + 4 * 240 * (27 * cin * cout + cout)
@@ -293,3 +293,77 @@ def test_upsampled_layer_polyphase_matches_reference(P, cin, cout):
     err = rel(g, ref)
     print(f"polyphase layer cin {cin} cout {cout}: rel err {err:.2e}")
     assert err < 1e-2, err
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_first_layer_inference_form_matches_reference(P, n):
+    """Inference form of the first layer: the single-channel convolution of
+    the density feature plus the broadcast channels folded into the bias
+    equals the 4-channel convolution of [f, x1, x2, x3] (oracle, FP64,
+    BF16-rounded operands; FP32 accumulation only: 1e-5)."""
+    rng = np.random.default_rng(n + 1)
+    f = rng.standard_normal((n, n, n))
+    w = rng.standard_normal((27, 4, 16)) * 0.1
+    b = rng.standard_normal(16)
+    xc = np.array([-0.55, 0.13, 0.71], dtype=np.float32)
+    fd = dev_bits(bf16_bits(f))
+    wd = torch.from_numpy(w.astype(np.float32)).cuda()
+    bd = torch.from_numpy(b.astype(np.float32)).cuda()
+    out = torch.zeros(n**3 * 16, dtype=torch.float32, device="cuda")
+    xcc = (ctypes.c_float * 3)(*xc.tolist())
+    rc = P._lib.lib().ws_conv3_first(n, ctypes.c_void_p(fd.data_ptr()), ctypes.c_void_p(wd.data_ptr()),
+                                     ctypes.c_void_p(bd.data_ptr()), xcc, ctypes.c_void_p(out.data_ptr()),
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == 0
+    got = out.cpu().numpy().astype(np.float64).reshape(n, n, n, 16)
+    x4 = np.empty((n, n, n, 4))
+    x4[..., 0] = bf16_round(f)
+    x4[..., 1:] = bf16_round(xc)
+    ref = U.conv3(x4, bf16_round(w), b.astype(np.float32).astype(np.float64))
+    assert rel(got, ref) < 1e-5
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_last_layer_with_head_matches_reference(P, n):
+    """Inference form of the last layer: the 16 -> 16 convolution with ReLU
+    and the 1x1x1 head applied in its epilogue, yhat = hb + sum_o hw[o]
+    relu(conv(x)[o]), against the oracle on the same BF16-rounded operands
+    (FP32 accumulation only: 1e-5)."""
+    rng = np.random.default_rng(3 * n)
+    x = rng.standard_normal((n, n, n, 16))
+    w = rng.standard_normal((27, 16, 16)) * 0.1
+    b = rng.standard_normal(16) * 0.1
+    hw = rng.standard_normal(16) * 0.25
+    hb = np.array([0.03])
+    got = _conv(P, 4, n, 16, 16, x=x, w=w, b=np.concatenate([b, hw, hb])).reshape(n, n, n)
+    h = U.relu(U.conv3(bf16_round(x), bf16_round(w), b.astype(np.float32).astype(np.float64)))
+    ref = h @ hw.astype(np.float32).astype(np.float64) + float(np.float32(hb[0]))
+    assert rel(got, ref) < 1e-5
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_inference_forward_matches_oracle_samples(P, n):
+    """The whole network as inference runs it (first layer on the density
+    channel, polyphase decoder layers with compact skip tensors -- the first
+    decoder layer only from 256^3 -- and the head in the last layer's
+    epilogue) against the FP64 oracle network at sampled voxels stored by
+    tests/golden/make_unet_forward.py (BF16 activations between layers:
+    3e-2, as for the whole-network test)."""
+    import importlib.util
+    import os
+
+    from paper_2604_15434_amd.warmstart import WarmStart
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_unet_forward", os.path.join(here, "make_unet_forward.py"))
+    G = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    rows = np.loadtxt(os.path.join(here, f"unet_forward_{n}.txt"), comments="#")
+    idx, ref = rows[:, 0].astype(np.int64), rows[:, 1]
+    assert np.array_equal(idx, G.sample_index(n))
+    net = WarmStart(params=G.flat_params())
+    rho = torch.from_numpy(G.density(n)).cuda()
+    yhat = torch.zeros(n**3, dtype=torch.float32, device="cuda")
+    net.predict(rho, dict(omega_m0=0.3071, **G.PARAMS), yhat)
+    got = yhat.cpu().numpy().astype(np.float64)[idx]
+    assert rel(got, ref) < 3e-2, rel(got, ref)
