@@ -106,7 +106,9 @@ def smoother_kernel(itemsize, tiled, ng):
     r = "double" if itemsize == 8 else "float"
     nh = ng // 2
     if tiled and ng >= 64:
-        if tiled == 2 and nh % 64 == 0 and ng % 16 == 0 and (ng // 8) * (nh // 64) * (ng // 16) >= 512:
+        if tiled == 3 and nh % 64 == 0 and ng % 16 == 0 and (ng // 16) * (nh // 64) * (ng // 16) >= 512:
+            return f"k_smooth_tile<{r}, true, 64, 4, 16>"
+        if tiled >= 2 and nh % 64 == 0 and ng % 16 == 0 and (ng // 8) * (nh // 64) * (ng // 16) >= 512:
             return f"k_smooth_tile<{r}, true, 64, 2, {8 if itemsize == 8 else 16}>"
         if nh % 64 == 0 and ng % 8 == 0:
             return f"k_smooth_tile<{r}, true, 64, 1, 8>"

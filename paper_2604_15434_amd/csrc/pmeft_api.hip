@@ -211,7 +211,7 @@ struct Hier {
     int cs[kMaxLevels];      // current csum buffer per level
     int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
     int block_l0 = kMaxLevels;  // levels from here down run as one block cycle
-    int tiled = 1;              // 2.5D-tiled smoother: 0 off, 1 small tiles, 2 large tiles
+    int tiled = 1;              // 2.5D-tiled smoother: 0 off, 1 small, 2 large, 3 largest tiles
     BlockHier<R> block() const
     {
         BlockHier<R> B;
@@ -1111,7 +1111,7 @@ int pm_get_launch_shape(int ng, int word_bytes, int *block_cycle_grid, int *tile
 int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid, int tiled_smoother)
 {
     if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8 || tiled_smoother < 0 ||
-        tiled_smoother > 2)
+        tiled_smoother > 3)
         return PM_EINVAL;
     set_shape(Shape{ng, word_bytes, block_cycle_grid, tiled_smoother});
     return PM_OK;
@@ -1143,7 +1143,7 @@ int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t st
     const int cands[5] = {0, 8, 16, 32, 64};
     Shape best = launch_shape(ng, word);
     float best_ms = 1e30f;
-    for (int tiled = 0; tiled < 3; tiled++)
+    for (int tiled = 0; tiled < 4; tiled++)
         for (int c = 0; c < 5; c++) {
             const int n = cands[c];
             if (n >= ng)
@@ -1199,7 +1199,7 @@ int pm_tune_load(const char *path)
             continue;
         int ng, word, n, tiled;
         if (sscanf(line, "%d %d %d %d", &ng, &word, &n, &tiled) != 4 || (word != 4 && word != 8) || n < 0 ||
-            ng < 8 || tiled < 0 || tiled > 2) {
+            ng < 8 || tiled < 0 || tiled > 3) {
             rc = PM_EINVAL;
             break;
         }

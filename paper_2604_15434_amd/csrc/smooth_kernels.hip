@@ -142,15 +142,21 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
 }
 
 // Tile configuration of a level for a tiling choice (1: small tiles, 2:
-// large tiles where they still give at least 512 tiles, else small):
-// 0 = untiled; 1 = (TK 64, CJ 2, 16 planes); 2 = (TK 64, CJ 1, 8 planes);
-// 3 = (TK 32, CJ 1, 8 planes).
+// large tiles where they still give at least 512 tiles, else small; 3: the
+// largest tiles where they still give 512, else as 2): 0 = untiled; 1 = (TK
+// 64, CJ 2, 16 planes, 8 in FP64); 2 = (TK 64, CJ 1, 8 planes); 3 = (TK 32,
+// CJ 1, 8 planes); 4 = (TK 64, CJ 4, 16 planes).  Larger tiles re-read less
+// halo (j and i halos of 2 rows and 2 planes per tile), which counts where
+// the level's working set does not stay in the last-level cache (FP64 at
+// 256^3), at the price of LDS (two FP64 blocks per CU with CJ 4).
 static inline int tile_config(int n, int choice)
 {
     if (choice == 0 || n < 64)
         return 0;
     const int nh = n / 2;
-    if (choice == 2 && nh % 64 == 0 && n % 16 == 0 && (n / 8) * (nh / 64) * (n / 16) >= 512)
+    if (choice == 3 && nh % 64 == 0 && n % 16 == 0 && (n / 16) * (nh / 64) * (n / 16) >= 512)
+        return 4;
+    if (choice >= 2 && nh % 64 == 0 && n % 16 == 0 && (n / 8) * (nh / 64) * (n / 16) >= 512)
         return 1;
     if (nh % 64 == 0 && n % 8 == 0)
         return 2;
@@ -169,7 +175,9 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
         // FP64 large tiles march 8 planes: three such blocks fit a CU (LDS), and
         // 16-plane tiles would leave a third of the last round of blocks idle
         constexpr int PL1 = sizeof(R) == 8 ? 8 : 16;
-        const int TK = cfg == 3 ? 32 : 64, TJ = cfg == 1 ? 2 * kBlock / TK : kBlock / TK, PL = cfg == 1 ? PL1 : 8;
+        const int TK = cfg == 3 ? 32 : 64;
+        const int TJ = (cfg == 4 ? 4 : (cfg == 1 ? 2 : 1)) * kBlock / TK;
+        const int PL = cfg == 4 ? 16 : (cfg == 1 ? PL1 : 8);
         const unsigned ntiles = (unsigned)((L.n / TJ) * (L.nh / TK) * (L.n / PL));
         // Span only carries the block count (XCD mapping, partials)
         Span sp;
@@ -184,14 +192,18 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
     hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV, CJV, PLV>), dim3(nb), dim3(kBlock), 0, st, L, colour, xc_old, xo,    \
                        xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
         if (nonlinear) {
-            if (cfg == 1)
+            if (cfg == 4)
+                PM_TILE(true, 64, 4, 16);
+            else if (cfg == 1)
                 PM_TILE(true, 64, 2, PL1);
             else if (cfg == 2)
                 PM_TILE(true, 64, 1, 8);
             else
                 PM_TILE(true, 32, 1, 8);
         } else {
-            if (cfg == 1)
+            if (cfg == 4)
+                PM_TILE(false, 64, 4, 16);
+            else if (cfg == 1)
                 PM_TILE(false, 64, 2, PL1);
             else if (cfg == 2)
                 PM_TILE(false, 64, 1, 8);
