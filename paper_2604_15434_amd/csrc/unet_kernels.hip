@@ -276,7 +276,12 @@ constexpr int kMarchThreads = 512;
 // FP32 in natural voxel order, and the 16-channel activation is never stored
 // (nor rounded to BF16, as the unfused form rounds it).  The channel sum runs over the 16 lanes of a row of the MFMA result
 // (row rotations 8, 4, 2, 1).
-template <int CS, int COT, int NS, bool HD = false>
+//
+// AH: the loads of plane i + 3 are issued before plane i is computed (two
+// planes in flight instead of one; the ring is unchanged, the registers of
+// plane i + 2 are stored after plane i).  Only where the registers allow it
+// (16 input channels).
+template <int CS, int COT, int NS, bool HD = false, bool AH = false>
 __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *__restrict__ in, int in_stride, int in_off,
                                                      const uint16_t *__restrict__ wp, int cout_pad,
                                                      const float *__restrict__ bias, int cout, void *__restrict__ out,
@@ -285,6 +290,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                                                      const float *__restrict__ hb)
 {
     static_assert(!HD || COT == 1, "the head reads one output tile");
+    static_assert(!AH || NS == 4, "two planes ahead needs the four-slot ring");
     // TR: weights as the A operand, so the result is D[channel][voxel] and a
     // lane holds four consecutive channels of one voxel (vector stores when
     // the output view is 4-aligned); the head keeps D[voxel][channel]
@@ -339,13 +345,14 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
             soff[u] = (unsigned)((jj * n + kk) * in_stride + in_off + 8 * part);
             loff[u] = v * SV + 8 * part;
         }
-        u32x4 pre[PER];
-#define PM_MARCH_FETCH(II)                                                                                             \
+        u32x4 pre[PER], pre2[AH ? PER : 1];
+#define PM_MARCH_FETCH_TO(DST, II)                                                                                     \
     do {                                                                                                               \
         const uint16_t *base_ = in + (size_t)wrapi((II), n) * plane_elems;                                             \
-        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH) pre[u] =           \
+        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH) DST[u] =           \
             *(const u32x4 *)(base_ + soff[u]);                                                                         \
     } while (0)
+#define PM_MARCH_FETCH(II) PM_MARCH_FETCH_TO(pre, II)
 #define PM_MARCH_STORE(SLOT)                                                                                           \
     do {                                                                                                               \
         uint16_t *dst_ = ring + (SLOT) * WV * SV;                                                                      \
@@ -358,12 +365,18 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
         PM_MARCH_STORE(1);
         PM_MARCH_FETCH(i0 + 1);
         PM_MARCH_STORE(2);
+        if (AH)
+            PM_MARCH_FETCH(i0 + 2);
         __syncthreads();
         for (int p = 0; p < PL; p++) {
             const int i = i0 + p;
             // ring slot of plane i - 1 + d is (p + d) % NS
-            if (p + 1 < PL)
+            if (AH) {
+                if (p + 2 < PL)
+                    PM_MARCH_FETCH_TO(pre2, i + 3);
+            } else if (p + 1 < PL) {
                 PM_MARCH_FETCH(i + 2);
+            }
             f32x4 acc[2][COT];
 #pragma unroll
             for (int m = 0; m < 2; m++)
@@ -502,8 +515,14 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
             }
             if (NS == 4) {
                 // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
-                if (p + 1 < PL)
+                if (p + 1 < PL) {
                     PM_MARCH_STORE((p + 3) % NS);
+                    if (AH) {
+#pragma unroll
+                        for (int u = 0; u < PER; u++)
+                            pre[u] = pre2[u];
+                    }
+                }
                 __syncthreads();
             } else {
                 __syncthreads();
@@ -514,6 +533,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
         }
 #undef PM_MARCH_STORE
 #undef PM_MARCH_FETCH
+#undef PM_MARCH_FETCH_TO
     }
 }
 
@@ -728,6 +748,15 @@ bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp,
     return false;
 }
 
+// Planes per tile of the plane-marching convolution: long tiles where two
+// planes are in flight (fewer ring fills per voxel), else 16 / 8.
+static inline int march_planes(int n, bool ahead)
+{
+    if (ahead)
+        return n >= 256 ? 64 : (n >= 128 ? 16 : 8);
+    return n >= 256 ? 16 : 8;
+}
+
 // 16 -> 16 convolution with ReLU followed by the 1x1x1 head (yhat, FP32,
 // natural order); false when the grid has no plane-marching instance.
 bool launch_conv3_head(const uint16_t *in, int in_stride, int in_off, const uint16_t *wp, const float *bias,
@@ -735,13 +764,13 @@ bool launch_conv3_head(const uint16_t *in, int in_stride, int in_off, const uint
 {
     if (n % 64 || in_stride % 8 || in_off % 8)
         return false;
-    const int PL = n >= 256 ? 16 : 8;
+    const int PL = march_planes(n, true);
     const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
     unsigned nb = ntiles < 2048u ? ntiles : 2048u;
     if (nb >= 8)
         nb -= nb % 8;
-    hipLaunchKernelGGL((k_conv3_march<1, 1, 4, true>), dim3(nb, 1), dim3(kMarchThreads), 0, st, in, in_stride, in_off,
-                       wp, 16, bias, 16, (void *)yhat, 1, 0, 1, n, 0, 1, ntiles, PL, hw, hb);
+    hipLaunchKernelGGL((k_conv3_march<1, 1, 4, true, true>), dim3(nb, 1), dim3(kMarchThreads), 0, st, in, in_stride,
+                       in_off, wp, 16, bias, 16, (void *)yhat, 1, 0, 1, n, 0, 1, ntiles, PL, hw, hb);
     return true;
 }
 
@@ -751,14 +780,15 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
 {
     if (n % 64 == 0 && cin_pad <= 48 && in_stride % 8 == 0 && in_off % 8 == 0) {
         const int cot = (cin_pad == 16 && (cout_pad / 16) % 2 == 0) ? 2 : 1;
-        const int PL = n >= 256 ? 16 : 8;
+        const int PL = march_planes(n, cin_pad == 16);
         const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
         unsigned nb = ntiles < 2048u ? ntiles : 2048u;
         if (nb >= 8)
             nb -= nb % 8;
         dim3 grid(nb, cout_pad / (cot * 16));
 #define PM_CONVM(CSV, C, NSV)                                                                                          \
-    hipLaunchKernelGGL((k_conv3_march<CSV, C, NSV>), grid, dim3(kMarchThreads), 0, st, in, in_stride, in_off, wp, cout_pad,     \
+    hipLaunchKernelGGL((k_conv3_march<CSV, C, NSV, false, CSV == 1>), grid, dim3(kMarchThreads), 0, st, in, in_stride, \
+                       in_off, wp, cout_pad,                                                                           \
                        bias, cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles,   \
                        PL, nullptr, nullptr)
 #define PM_CONVM_C(CSV, NSV)                                                                                           \
@@ -1199,9 +1229,10 @@ void launch_unet_feature(const double *delta_packed, int n, const double *stats,
 // consecutive channels of one voxel (one 8-byte store; 16 bytes with F32
 // output, no ReLU: the test form).  Block: 4 waves, one row j each, 64
 // voxels along k, marching PL planes along i with planes i - 1 .. i + 2 of
-// the 6 x 66 window in a ring of four slots (the next plane's loads are
-// issued before the current plane is computed).  w: FP32 weights
-// w[t][c][o] of the 4-channel layer.
+// the 6 x 66 window in a ring of four slots; the loads run four planes ahead
+// through a register queue (a plane costs only four MFMAs per wave, far less
+// than a load's latency).  w: FP32 weights w[t][c][o] of the 4-channel
+// layer.
 template <bool F32>
 __global__ __launch_bounds__(256) void k_conv3_in1(const uint16_t *__restrict__ f, const float *__restrict__ w,
                                                    const float *__restrict__ b, float x1, float x2, float x3,
@@ -1237,23 +1268,27 @@ __global__ __launch_bounds__(256) void k_conv3_in1(const uint16_t *__restrict__ 
         soff[u] = (unsigned)(wrapi(j0 + row - 1, n) * n + wrapi(k0 + col - 1, n));
         loff[u] = ee;
     }
-    uint16_t pre[2];
+    // pre[d]: plane i + 2 + d of the current plane i (a queue of four)
+    uint16_t pre[4][2];
     const size_t plane = (size_t)n * n;
-#define PM_IN1_FETCH(II)                                                                                               \
+#define PM_IN1_FETCH(D, II)                                                                                            \
     do {                                                                                                               \
         const uint16_t *src_ = f + (size_t)wrapi((II), n) * plane;                                                     \
-        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) pre[u] = src_[soff[u]];                             \
+        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) pre[D][u] = src_[soff[u]];                          \
     } while (0)
-#define PM_IN1_STORE(SLOT)                                                                                             \
+#define PM_IN1_STORE(D, SLOT)                                                                                          \
     do {                                                                                                               \
-        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) ring[(SLOT) * PW + loff[u]] = pre[u];              \
+        _Pragma("unroll") for (int u = 0; u < 2; u++) if (has[u]) ring[(SLOT) * PW + loff[u]] = pre[D][u];           \
     } while (0)
-    PM_IN1_FETCH(i0 - 1);
-    PM_IN1_STORE(0);
-    PM_IN1_FETCH(i0);
-    PM_IN1_STORE(1);
-    PM_IN1_FETCH(i0 + 1);
-    PM_IN1_STORE(2);
+    PM_IN1_FETCH(0, i0 - 1);
+    PM_IN1_STORE(0, 0);
+    PM_IN1_FETCH(0, i0);
+    PM_IN1_STORE(0, 1);
+    PM_IN1_FETCH(0, i0 + 1);
+    PM_IN1_STORE(0, 2);
+    PM_IN1_FETCH(0, i0 + 2);
+    PM_IN1_FETCH(1, i0 + 3);
+    PM_IN1_FETCH(2, i0 + 4);
     // A: lane (r, q) holds W[t][0][r] for the taps t = 8q .. 8q + 7; the B
     // gather of voxel r reads window row 1 + wave + dj, column 1 + dk + r
     bf16x8 a;
@@ -1278,8 +1313,8 @@ __global__ __launch_bounds__(256) void k_conv3_in1(const uint16_t *__restrict__ 
     const float bq[4] = {beff[4 * q], beff[4 * q + 1], beff[4 * q + 2], beff[4 * q + 3]};
     for (int p = 0; p < PL; p++) {
         const int i = i0 + p;
-        if (p + 1 < PL)
-            PM_IN1_FETCH(i + 2);
+        if (p + 4 < PL)
+            PM_IN1_FETCH(3, i + 5);
         int toff[8];
 #pragma unroll
         for (int u = 0; u < 8; u++)
@@ -1306,8 +1341,14 @@ __global__ __launch_bounds__(256) void k_conv3_in1(const uint16_t *__restrict__ 
             }
         }
         // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
-        if (p + 1 < PL)
-            PM_IN1_STORE((p + 3) & 3);
+        if (p + 1 < PL) {
+            PM_IN1_STORE(0, (p + 3) & 3);
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+#pragma unroll
+                for (int u = 0; u < 2; u++)
+                    pre[d][u] = pre[d + 1][u];
+        }
         __syncthreads();
     }
 #undef PM_IN1_STORE
