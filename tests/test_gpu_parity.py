@@ -374,7 +374,8 @@ def test_block_cycle_matches_per_level_launches(P, ng, precision):
     assert float((psi1 - psi0).norm() / psi0.norm()) < 1e-9
 
 
-@pytest.mark.parametrize("ng,precision", [(64, "f64"), (128, "f64"), (128, "mixed"), (192, "mixed"), (256, "mixed")])
+@pytest.mark.parametrize("ng,precision", [(64, "f64"), (128, "f64"), (128, "mixed"), (192, "mixed"), (256, "mixed"),
+                                          (256, "f64")])
 def test_tiled_smoother_matches_untiled(P, ng, precision):
     """The 2.5D-tiled half-sweep computes the same cell updates; whole solves
     differ only through the grouping of the lagged-mean partial sums."""
