@@ -840,104 +840,191 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
 
 // Weight and bias gradients:
 //   dW[t][c][o] = sum_v x[v + d_t][x_off + c] dy[v][dy_off + o],  db[o] = sum_v dy[v][dy_off + o].
-// GEMMs with the voxels as the reduction index, on the MFMA unit with
-// A[m = c][k = voxel] and B[k = voxel][n = o].  The voxels are walked in
-// groups of 16 consecutive voxels along k; for each group the dy fragment is
-// loaded once for all 27 taps, and the six x values a lane needs along k
-// (offsets -1 .. 4 of its four voxels) once per (di, dj) row for the three
-// dk taps.  grid: x = voxel chunks (kWgBlocks at most), y = (c tile, o tile).
-// Every block writes its partial sums; k_wgrad_reduce adds them in block
-// order, so the gradients do not depend on scheduling.
+// GEMMs with the voxels as the reduction index on v_mfma_f32_16x16x16_bf16:
+// A[m = c][k = voxel] from x, B[k = voxel][n = o] from dy, D[c][o].  A block
+// owns one (16-channel c tile, 16-channel o tile) pair and a contiguous range
+// of units; a unit is a row segment (SEG = min(64, n) voxels along k of row
+// j) marched over PLW planes i.  The block keeps rows j - 1 .. j + 1 of
+// planes i - 1 .. i + 2 of x (SEG + 2 voxels: the k halo) in a four-slot LDS
+// ring and the dy segment of plane i in a two-slot one, voxel-major with a
+// padded voxel stride; per plane it stages only the new plane's three rows,
+// whose loads were issued before the previous plane was computed.  Wave w
+// (nine per block) owns the neighbour row (di, dj) = (w / 3 - 1, w % 3 - 1)
+// and its three taps 3w .. 3w + 2: a lane reads six consecutive voxels of
+// one channel once and forms the A operands of the three k offsets from
+// them.  Every block writes its partial sums; k_wgrad_reduce adds them in
+// block order, so the gradients do not depend on scheduling.  vec: the views
+// allow 16-byte loads of 16-channel tiles (strides and offsets multiples of
+// 8, padded channel counts within the strides), else 2-byte loads.
 constexpr int kWgBlocks = 240;
+constexpr int kWgThreads = 576;  // nine waves
+constexpr int kWgSeg = 64;       // voxels per row segment (n if smaller)
+constexpr int kWgPlanes = 16;    // planes per unit (n if smaller)
+constexpr int kWgVS = 24;        // LDS voxel stride in halfwords (16 channels + pad)
+constexpr int kWgXW = kWgSeg + 2;
+constexpr int kWgSlotX = 3 * kWgXW * kWgVS;  // one plane: three rows
+constexpr int kWgSlotD = kWgSeg * kWgVS;
+
+__host__ __device__ __forceinline__ int wgrad_seg(int n) { return n < kWgSeg ? n : kWgSeg; }
+__host__ __device__ __forceinline__ int wgrad_planes(int n) { return n < kWgPlanes ? n : kWgPlanes; }
 
 static inline unsigned wgrad_blocks(int n)
 {
-    const unsigned groups = (unsigned)n * n * (n / 16);
-    const unsigned nb = (groups + 15) / 16;  // at least 4 groups per wave
-    return nb < (unsigned)kWgBlocks ? (nb ? nb : 1) : (unsigned)kWgBlocks;
+    const unsigned units = (unsigned)(n / wgrad_planes(n)) * n * (unsigned)(n / wgrad_seg(n));
+    return units < (unsigned)kWgBlocks ? (units ? units : 1) : (unsigned)kWgBlocks;
 }
 
 size_t wgrad_partial_floats(int cin, int cout) { return (size_t)kWgBlocks * (27 * (size_t)cin * cout + cout); }
 
-__global__ __launch_bounds__(256) void k_conv3_wgrad(const uint16_t *__restrict__ x, int x_stride, int x_off, int cin,
-                                                     const uint16_t *__restrict__ dy, int dy_stride, int dy_off,
-                                                     int cout, float *__restrict__ part, int n)
+__global__ __launch_bounds__(kWgThreads) void k_conv3_wgrad(const uint16_t *__restrict__ x, int x_stride, int x_off,
+                                                            int cin, const uint16_t *__restrict__ dy, int dy_stride,
+                                                            int dy_off, int cout, float *__restrict__ part, int n,
+                                                            int vec)
 {
-    __shared__ float red[4][9][64][4];
-    __shared__ float bred[4][16];
+    __shared__ __align__(16) uint16_t lds[4 * kWgSlotX + 2 * kWgSlotD];
+    uint16_t *const xr = lds, *const dr = lds + 4 * kWgSlotX;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
     const int otiles = (cout + 15) / 16;
     const int ct = blockIdx.y / otiles, ot = blockIdx.y - (blockIdx.y / otiles) * otiles;
-    const int c = ct * 16 + r, o = ot * 16 + r;
-    const bool cok = c < cin, ook = o < cout;
-    const unsigned ngk = (unsigned)(n / 16);
-    const unsigned G = (unsigned)n * n * ngk;
-    const unsigned g0 = (unsigned)(((unsigned long long)blockIdx.x * G) / gridDim.x);
-    const unsigned g1 = (unsigned)(((unsigned long long)(blockIdx.x + 1) * G) / gridDim.x);
-    f32x4 acc[27];
+    const int c0 = ct * 16, o0 = ot * 16;
+    const int seg = wgrad_seg(n), pl = wgrad_planes(n), nsr = n / seg, nkc = seg / 16;
+    const int nxc = 3 * (seg + 2) * 2, nch = nxc + seg * 2;  // 16-byte chunks per plane step
+    const unsigned units = (unsigned)(n / pl) * n * (unsigned)nsr;
+    const unsigned u0 = (unsigned)(((unsigned long long)blockIdx.x * units) / gridDim.x);
+    const unsigned u1 = (unsigned)(((unsigned long long)(blockIdx.x + 1) * units) / gridDim.x);
+    // this thread's chunk of a plane step (one at most: nch <= 3 * 66 * 2 + 128 < 576):
+    // an x row (dj) and voxel, or a dy voxel; first channel; LDS offset in its slot
+    const int e = threadIdx.x;
+    const bool isx = e < nxc, has = e < nch;
+    int c_dj = 0, c_vx = 0, c_ch = 0, c_off = 0;
+    if (isx) {
+        const int rw = e / ((seg + 2) * 2), rem = e - rw * (seg + 2) * 2;
+        c_dj = rw - 1;
+        c_vx = (rem >> 1) - 1;
+        c_ch = c0 + 8 * (rem & 1);
+        c_off = (rw * kWgXW + (rem >> 1)) * kWgVS + 8 * (rem & 1);
+    } else if (has) {
+        const int rem = e - nxc;
+        c_vx = rem >> 1;
+        c_ch = o0 + 8 * (rem & 1);
+        c_off = (rem >> 1) * kWgVS + 8 * (rem & 1);
+    }
+    const int lim = isx ? cin : cout;
+    const bool ok = has && c_ch < lim, full = c_ch + 8 <= lim;
+    // chunk of plane II (x rows j - 1 .. j + 1) or of dy row (II, j), segment k0
+    auto fetch = [&](int II, int j, int k0, bool want_x, bool want_d) -> u32x4 {
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (!ok || (isx ? !want_x : !want_d))
+            return v;
+        const uint16_t *src;
+        if (isx) {
+            const int ii = wrapi(II, n), jj = wrapi(j + c_dj, n), kk = wrapi(k0 + c_vx, n);
+            src = x + ((size_t)((ii * n + jj) * n + kk)) * x_stride + x_off + c_ch;
+        } else {
+            src = dy + ((size_t)((II * n + j) * n + k0 + c_vx)) * dy_stride + dy_off + c_ch;
+        }
+        if (vec) {
+            v = *(const u32x4 *)src;
+            if (!full)
 #pragma unroll
-    for (int t = 0; t < 27; t++)
-        acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                for (int h = 0; h < 4; h++) {
+                    const unsigned lo = c_ch + 2 * h < lim ? 0xffffu : 0u;
+                    const unsigned hi = c_ch + 2 * h + 1 < lim ? 0xffff0000u : 0u;
+                    v[h] &= lo | hi;
+                }
+        } else {
+#pragma unroll
+            for (int h = 0; h < 4; h++) {
+                const unsigned lo = c_ch + 2 * h < lim ? src[2 * h] : 0u;
+                const unsigned hi = c_ch + 2 * h + 1 < lim ? src[2 * h + 1] : 0u;
+                v[h] = lo | (hi << 16);
+            }
+        }
+        return v;
+    };
+    const int di = wave / 3 - 1, dj = wave % 3 - 1;
+    f32x4 acc[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++)
+        acc[d] = (f32x4){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (unsigned g = g0 + wave; g < g1; g += 4) {
-        const unsigned row = g / ngk;
-        const int k0 = (int)(g - row * ngk) * 16;
-        const int i = (int)(row / n), j = (int)(row - (row / n) * n);
-        bf16x4 b;
-        const uint16_t *dyp = dy + ((size_t)row * n + k0 + 4 * q) * dy_stride + dy_off + o;
+    for (unsigned un = u0; un < u1; un++) {
+        const unsigned col = un / (unsigned)(n / pl);  // (j, segment): planes fastest
+        const int i0 = (int)(un - col * (unsigned)(n / pl)) * pl;
+        const int j = (int)(col / (unsigned)nsr), k0 = (int)(col - (col / (unsigned)nsr) * (unsigned)nsr) * seg;
+        // prime: x planes i0 - 1, i0, i0 + 1 into slots 0, 1, 2; dy of plane i0 into slot 0
+        __syncthreads();  // the previous unit's operands have been read
+        if (isx) {
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            const uint16_t v = ook ? dyp[(size_t)e * dy_stride] : (uint16_t)0;
-            b[e] = (short)v;
-            bsum += bf2f(v);
+            for (int d = 0; d < 3; d++) {
+                const u32x4 v = fetch(i0 - 1 + d, j, k0, true, false);
+                if (has)
+                    *(u32x4 *)(xr + d * kWgSlotX + c_off) = v;
+            }
+        } else if (has) {
+            *(u32x4 *)(dr + c_off) = fetch(i0, j, k0, false, true);
         }
+        // next loads: x plane i0 + 2, dy of plane i0 + 1 (rows within the unit's planes)
+        u32x4 pre = isx ? fetch(i0 + 2, j, k0, true, false)
+                        : (pl > 1 ? fetch(i0 + 1, j, k0, false, true) : (u32x4){0u, 0u, 0u, 0u});
+        __syncthreads();
+        for (int p = 0; p < pl; p++) {
+            const int i = i0 + p;
+            // operands of this plane: dy segment (B, all taps), then the wave's x row
+            const uint16_t *dseg = dr + (p & 1) * kWgSlotD;
+            const uint16_t *xrow = xr + ((p + 1 + di) & 3) * kWgSlotX + (dj + 1) * kWgXW * kWgVS;
 #pragma unroll
-        for (int dij = 0; dij < 9; dij++) {
-            const int ii = wrapi(i + dij / 3 - 1, n), jj = wrapi(j + dij % 3 - 1, n);
-            const uint16_t *xr = x + (size_t)((ii * n + jj) * n) * x_stride + x_off + c;
-            short xv[6];
+            for (int kc = 0; kc < kWgSeg / 16; kc++)
+                if (kc < nkc) {
+                    bf16x4 b;
 #pragma unroll
-            for (int t = 0; t < 6; t++) {
-                const int kk = wrapi(k0 + 4 * q + t - 1, n);
-                xv[t] = cok ? (short)xr[(size_t)kk * x_stride] : (short)0;
+                    for (int u = 0; u < 4; u++)
+                        b[u] = (short)dseg[(16 * kc + 4 * q + u) * kWgVS + r];
+                    if (wave == 0)
+#pragma unroll
+                        for (int u = 0; u < 4; u++)
+                            bsum += bf2f((uint16_t)b[u]);
+                    short xv[6];  // window voxels 16 kc + 4q .. + 5 (offsets -1 .. 4), channel r
+#pragma unroll
+                    for (int u = 0; u < 6; u++)
+                        xv[u] = (short)xrow[(16 * kc + 4 * q + u) * kWgVS + r];
+#pragma unroll
+                    for (int d = 0; d < 3; d++) {
+                        const bf16x4 a = (bf16x4){xv[d], xv[d + 1], xv[d + 2], xv[d + 3]};
+                        acc[d] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[d], 0, 0, 0);
+                    }
+                }
+            if (p + 1 < pl) {
+                // plane i + 2 into the x slot of plane i - 2, dy of plane i + 1 into the other dy slot
+                // (both last read before the previous barrier)
+                if (has)
+                    *(u32x4 *)((isx ? xr + ((p + 3) & 3) * kWgSlotX : dr + ((p + 1) & 1) * kWgSlotD) + c_off) = pre;
+                if (p + 2 < pl)
+                    pre = isx ? fetch(i + 3, j, k0, true, false) : fetch(i + 2, j, k0, false, true);
             }
-#pragma unroll
-            for (int dk = 0; dk < 3; dk++) {
-                const bf16x4 a = (bf16x4){xv[dk], xv[dk + 1], xv[dk + 2], xv[dk + 3]};
-                acc[dij * 3 + dk] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[dij * 3 + dk], 0, 0, 0);
-            }
+            __syncthreads();
         }
     }
-    // block reduction in three rounds of nine taps; lane (r, q) holds
-    // dW[t][ct*16 + 4q + e][ot*16 + r]
+    // lane (r, q) holds dW[3 wave + d][c0 + 4q + e][o0 + r]
     float *pb = part + (size_t)blockIdx.x * (27 * (size_t)cin * cout + cout);
+    const int o = o0 + r;
+    if (o < cout)
 #pragma unroll
-    for (int round = 0; round < 3; round++) {
+        for (int d = 0; d < 3; d++)
 #pragma unroll
-        for (int tt = 0; tt < 9; tt++)
-#pragma unroll
-            for (int e = 0; e < 4; e++)
-                red[wave][tt][lane][e] = acc[round * 9 + tt][e];
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 9 * 64 * 4; idx += 256) {
-            const int e = idx & 3, ln = (idx >> 2) & 63, tt = idx >> 8;
-            const float v = red[0][tt][ln][e] + red[1][tt][ln][e] + red[2][tt][ln][e] + red[3][tt][ln][e];
-            const int cc = ct * 16 + 4 * (ln >> 4) + e, oo = ot * 16 + (ln & 15);
-            if (cc < cin && oo < cout)
-                pb[((size_t)(round * 9 + tt) * cin + cc) * cout + oo] = v;
-        }
-        __syncthreads();
+            for (int e4 = 0; e4 < 4; e4++) {
+                const int c = c0 + 4 * q + e4;
+                if (c < cin)
+                    pb[((size_t)(3 * wave + d) * cin + c) * cout + o] = acc[d][e4];
+            }
+    // bias: wave 0, lanes r, r + 16, r + 32, r + 48 hold partial sums of o0 + r
+    if (ct == 0 && wave == 0) {
+        bsum += __shfl_down(bsum, 32, 64);
+        bsum += __shfl_down(bsum, 16, 64);
+        if (lane < 16 && o < cout)
+            pb[27 * (size_t)cin * cout + o] = bsum;
     }
-    // bias: lanes r, r+16, r+32, r+48 hold partial sums of column o
-    bsum += __shfl_down(bsum, 32, 64);
-    bsum += __shfl_down(bsum, 16, 64);
-    if (lane < 16)
-        bred[wave][lane] = bsum;
-    __syncthreads();
-    if (ct == 0 && threadIdx.x < 16 && ot * 16 + (int)threadIdx.x < cout)
-        pb[27 * (size_t)cin * cout + ot * 16 + threadIdx.x] =
-            bred[0][threadIdx.x] + bred[1][threadIdx.x] + bred[2][threadIdx.x] + bred[3][threadIdx.x];
 }
 
 // dw[e] = sum_b part[b][e] (e over 27 cin cout), db[o] = sum_b part[b][27 cin cout + o]
@@ -947,6 +1034,7 @@ __global__ __launch_bounds__(256) void k_wgrad_reduce(const float *__restrict__ 
     const size_t nw = 27 * (size_t)cin * cout, stride = nw + cout;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < stride; e += (size_t)gridDim.x * 256) {
         float s = 0.f;
+#pragma unroll 16
         for (unsigned b = 0; b < nb; b++)
             s += part[(size_t)b * stride + e];
         if (e < nw)
@@ -961,8 +1049,10 @@ void launch_conv3_wgrad(const uint16_t *x, int x_stride, int x_off, int cin, con
 {
     const unsigned nb = wgrad_blocks(n);
     dim3 grid(nb, ((cin + 15) / 16) * ((cout + 15) / 16));
-    hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(256), 0, st, x, x_stride, x_off, cin, dy, dy_stride, dy_off, cout,
-                       part, n);
+    const int vec = x_stride % 8 == 0 && x_off % 8 == 0 && x_off + (cin + 15) / 16 * 16 <= x_stride &&
+                    dy_stride % 8 == 0 && dy_off % 8 == 0 && dy_off + (cout + 15) / 16 * 16 <= dy_stride;
+    hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(kWgThreads), 0, st, x, x_stride, x_off, cin, dy, dy_stride, dy_off,
+                       cout, part, n, vec);
     const size_t total = 27 * (size_t)cin * cout + cout;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nb, cin, cout,
                        dw, db);
