@@ -43,14 +43,19 @@ __device__ __forceinline__ bool cic_axis(double x, int ng, int &i0, int &i1, dou
 // integer, which makes the sum independent of particle order (bitwise
 // reproducible) and loses at most 2^-41 per weight.
 //
-// A block takes a chunk of kDepChunk consecutive particles.  Particles of a
-// PM code are stored in (roughly) spatial order, so a chunk's CIC footprint
-// is a small box: the block accumulates it in LDS with 64-bit LDS atomics and
-// then adds each touched cell to the grid with one global atomic, instead of
-// 8 contended global atomics per particle.  A chunk whose box does not fit
-// the LDS tile (scattered order, or a chunk that straddles the periodic
-// boundary) falls back to direct global atomics.
+// A chunk is kDepChunk consecutive particles.  Particles of a PM code are
+// stored in (roughly) spatial order, so a chunk's CIC footprint is a small
+// box: the block accumulates it in LDS with 64-bit LDS atomics and then adds
+// each touched cell to the grid with one global atomic, instead of 8
+// contended global atomics per particle.  A chunk whose box does not fit the
+// LDS tile (scattered order, or a chunk that straddles the periodic boundary)
+// falls back to direct global atomics.  Each block walks chunks lb, lb + nb,
+// ... (consecutive chunks on one XCD share boundary cells in its L2); a
+// thread keeps the cells and fractions of its kDepPer particles between the
+// box reduction (wave shuffles, then one LDS slot per wave) and the deposit,
+// and the positions of the block's next chunk are already loading.
 constexpr int kDepChunk = 1024;
+constexpr int kDepPer = kDepChunk / kBlock;
 constexpr int kDepTile = 8192;  // 64 KB of 64-bit counters
 
 template <typename Tp>
@@ -58,85 +63,130 @@ __global__ __launch_bounds__(kBlock) void k_deposit_tiled(const Tp *__restrict__
                                                           unsigned long long *__restrict__ acc, unsigned nchunks)
 {
     __shared__ unsigned long long tile[kDepTile];
-    __shared__ int bmin[3], bmax[3];
-    const unsigned b = blockIdx.x;
-    const unsigned chunk = (gridDim.x % 8) ? b : (b % 8) * (gridDim.x / 8) + b / 8;
-    if (chunk >= nchunks)
-        return;
-    const unsigned p0 = chunk * kDepChunk;
-    const unsigned p1 = min(np, p0 + kDepChunk);
-    if (threadIdx.x < 3) {
-        bmin[threadIdx.x] = 0x7fffffff;
-        bmax[threadIdx.x] = -1;
-    }
-    __syncthreads();
-    int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    __shared__ int wbox[kBlock / 64][6];  // per wave: min x, y, z, max x, y, z of the base cells
+    const unsigned nb = gridDim.x;
+    const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Tp cur[3][kDepPer], nxt[3][kDepPer];
+    auto load = [&](unsigned chunk, Tp(&dst)[3][kDepPer]) {
+#pragma unroll
+        for (int u = 0; u < kDepPer; u++) {
+            const unsigned p = chunk * kDepChunk + threadIdx.x + u * kBlock;
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+                dst[d][u] = p < np ? pos[(size_t)d * np + p] : (Tp)0;
+        }
+    };
+    if (lb < nchunks)
+        load(lb, cur);
+    for (unsigned chunk = lb; chunk < nchunks; chunk += nb) {
+        if (chunk + nb < nchunks)
+            load(chunk + nb, nxt);
+        // base cells and fractions of this thread's particles
+        int c0[3][kDepPer], c1[3][kDepPer];
+        double fr[3][kDepPer];
+        bool ok[kDepPer];
+        int mn[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, mx[3] = {-1, -1, -1};
+#pragma unroll
+        for (int u = 0; u < kDepPer; u++) {
+            const unsigned p = chunk * kDepChunk + threadIdx.x + u * kBlock;
+            ok[u] = p < np;
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+                ok[u] = ok[u] && cic_axis((double)cur[d][u], ng, c0[d][u], c1[d][u], fr[d][u]);
+            if (ok[u])
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    mn[d] = min(mn[d], c0[d][u]);
+                    mx[d] = max(mx[d], c0[d][u]);
+                }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                mn[d] = min(mn[d], __shfl_xor(mn[d], off, 64));
+                mx[d] = max(mx[d], __shfl_xor(mx[d], off, 64));
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                wbox[wave][d] = mn[d];
+                wbox[wave][3 + d] = mx[d];
+            }
+        __syncthreads();  // also: the previous chunk's flush has read the tile
+        int bmin[3], bmax[3];
+#pragma unroll
         for (int d = 0; d < 3; d++) {
-            int i0, i1;
-            double f;
-            if (cic_axis((double)pos[(size_t)d * np + p], ng, i0, i1, f)) {
-                mn[d] = min(mn[d], i0);
-                mx[d] = max(mx[d], i0);
+            bmin[d] = wbox[0][d];
+            bmax[d] = wbox[0][3 + d];
+#pragma unroll
+            for (int w = 1; w < kBlock / 64; w++) {
+                bmin[d] = min(bmin[d], wbox[w][d]);
+                bmax[d] = max(bmax[d], wbox[w][3 + d]);
             }
         }
-    }
-    for (int d = 0; d < 3; d++) {
-        atomicMin(&bmin[d], mn[d]);
-        atomicMax(&bmax[d], mx[d]);
-    }
-    __syncthreads();
-    // box of base cells [bmin, bmax] plus one for the upper corners
-    const int ex = bmax[0] - bmin[0] + 2, ey = bmax[1] - bmin[1] + 2, ez = bmax[2] - bmin[2] + 2;
-    const bool use_tile = bmax[0] >= 0 && (long long)ex * ey * ez <= kDepTile;
-    const int vol = use_tile ? ex * ey * ez : 0;
-    for (int t = threadIdx.x; t < vol; t += kBlock)
-        tile[t] = 0ull;
-    __syncthreads();
-    for (unsigned p = p0 + threadIdx.x; p < p1; p += kBlock) {
-        int x0, x1, y0, y1, z0, z1;
-        double fx, fy, fz;
-        if (!cic_axis((double)pos[p], ng, x0, x1, fx) || !cic_axis((double)pos[(size_t)np + p], ng, y0, y1, fy) ||
-            !cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz))
-            continue;
-        const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        // box of base cells [bmin, bmax] plus one for the upper corners
+        const int ex = bmax[0] - bmin[0] + 2, ey = bmax[1] - bmin[1] + 2, ez = bmax[2] - bmin[2] + 2;
+        const bool use_tile = bmax[0] >= 0 && (long long)ex * ey * ez <= kDepTile;
+        const int vol = use_tile ? ex * ey * ez : 0;
+        for (int t = threadIdx.x; t < vol; t += kBlock)
+            tile[t] = 0ull;
+        __syncthreads();  // wbox read and the tile cleared
 #pragma unroll
-        for (int a = 0; a < 2; a++)
+        for (int u = 0; u < kDepPer; u++) {
+            if (!ok[u])
+                continue;
+            const double wx[2] = {1.0 - fr[0][u], fr[0][u]}, wy[2] = {1.0 - fr[1][u], fr[1][u]},
+                         wz[2] = {1.0 - fr[2][u], fr[2][u]};
 #pragma unroll
-            for (int bb = 0; bb < 2; bb++)
+            for (int a = 0; a < 2; a++)
 #pragma unroll
-                for (int c = 0; c < 2; c++) {
-                    const double w = wx[a] * wy[bb] * wz[c];
-                    const unsigned long long q = (unsigned long long)(w * kFixScale + 0.5);
-                    if (!q)
-                        continue;
-                    if (use_tile) {
-                        const int li = ((x0 - bmin[0] + a) * ey + (y0 - bmin[1] + bb)) * ez + (z0 - bmin[2] + c);
-                        atomicAdd(&tile[li], q);
-                    } else {
-                        const int gi = a ? x1 : x0, gj = bb ? y1 : y0, gk = c ? z1 : z0;
-                        atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], q);
+                for (int bb = 0; bb < 2; bb++)
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const double w = wx[a] * wy[bb] * wz[c];
+                        const unsigned long long q = (unsigned long long)(w * kFixScale + 0.5);
+                        if (!q)
+                            continue;
+                        if (use_tile) {
+                            const int li = ((c0[0][u] - bmin[0] + a) * ey + (c0[1][u] - bmin[1] + bb)) * ez +
+                                           (c0[2][u] - bmin[2] + c);
+                            atomicAdd(&tile[li], q);
+                        } else {
+                            const int gi = a ? c1[0][u] : c0[0][u], gj = bb ? c1[1][u] : c0[1][u],
+                                      gk = c ? c1[2][u] : c0[2][u];
+                            atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], q);
+                        }
                     }
-                }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < vol; t += kBlock) {
-        const unsigned long long v = tile[t];
-        if (!v)
-            continue;
-        const int kk = t % ez, r = t / ez, jj = r % ey, ii = r / ey;
-        int gi = bmin[0] + ii, gj = bmin[1] + jj, gk = bmin[2] + kk;
-        gi = gi >= ng ? gi - ng : gi;
-        gj = gj >= ng ? gj - ng : gj;
-        gk = gk >= ng ? gk - ng : gk;
-        atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], v);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < vol; t += kBlock) {
+            const unsigned long long v = tile[t];
+            if (!v)
+                continue;
+            const int kk = t % ez, r = t / ez, jj = r % ey, ii = r / ey;
+            int gi = bmin[0] + ii, gj = bmin[1] + jj, gk = bmin[2] + kk;
+            gi = gi >= ng ? gi - ng : gi;
+            gj = gj >= ng ? gj - ng : gj;
+            gk = gk >= ng ? gk - ng : gk;
+            atomicAdd(&acc[((unsigned)gi * ng + gj) * ng + gk], v);
+        }
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int u = 0; u < kDepPer; u++)
+                cur[d][u] = nxt[d][u];
     }
 }
 
 void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc, hipStream_t st)
 {
     const unsigned nchunks = (unsigned)((np + kDepChunk - 1) / kDepChunk);
-    unsigned nb = nchunks >= 8 ? (nchunks + 7) / 8 * 8 : nchunks;
+    // two 64 KB-tile blocks fit a CU: 512 blocks walk the chunks
+    unsigned nb = nchunks < 512u ? nchunks : 512u;
+    if (nb >= 8)
+        nb -= nb % 8;
     if (dt == PM_F64)
         hipLaunchKernelGGL((k_deposit_tiled<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)pos,
                            (unsigned)np, ng, acc, nchunks);
