@@ -161,11 +161,16 @@ __global__ __launch_bounds__(kBlock) void k_deposit_tiled(const Tp *__restrict__
                     }
         }
         __syncthreads();
+        // cell t -> (ii, jj, kk) by float reciprocals: exact for t < 2^13 (the
+        // quotient's error is below 2^-20 of it, its distance to an integer
+        // at least 1/(2 ez))
+        const float rez = 1.0f / (float)ez, rey = 1.0f / (float)ey;
         for (int t = threadIdx.x; t < vol; t += kBlock) {
             const unsigned long long v = tile[t];
             if (!v)
                 continue;
-            const int kk = t % ez, r = t / ez, jj = r % ey, ii = r / ey;
+            const int r = __float2int_rz(((float)t + 0.5f) * rez), kk = t - r * ez;
+            const int ii = __float2int_rz(((float)r + 0.5f) * rey), jj = r - ii * ey;
             int gi = bmin[0] + ii, gj = bmin[1] + jj, gk = bmin[2] + kk;
             gi = gi >= ng ? gi - ng : gi;
             gj = gj >= ng ? gj - ng : gj;
