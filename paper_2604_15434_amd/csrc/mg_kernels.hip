@@ -326,9 +326,9 @@ void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R>
 constexpr int kCoarseMax = 216;
 constexpr double kCoarseTol = 1e-10;
 // ... or below kCoarseRel of the largest accumulated change of the solve (the
-// coarse-grid correction is then resolved to about 0.1%, far below the
-// V-cycle's per-cycle reduction)
-constexpr double kCoarseRel = 1e-3;
+// coarse-grid correction is then resolved to about 1%, well below the
+// V-cycle's per-cycle reduction of about a tenth)
+constexpr double kCoarseRel = 1e-2;
 
 // Device part, for any block size >= n^3 that is a multiple of 64 (all
 // threads of the block must call it).
