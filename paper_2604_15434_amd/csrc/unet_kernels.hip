@@ -3,12 +3,23 @@
 // Activations are channels-last bf16 tensors (voxel-major, channels
 // contiguous); a tensor view is (pointer, row stride in elements, channel
 // offset), so a convolution can read or write one slice of a concatenation
-// buffer.  Convolutions are implicit GEMMs on the MFMA unit
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation): a wave computes 16
-// consecutive voxels along k times 16 output channels per tile and runs the
-// K loop over the 27 taps (periodic neighbours) and 16-channel input slices.
-// MFMA operand layout (16x16x16): lane l supplies A[l%16][4(l/16)+i] and
-// B[4(l/16)+i][l%16], i = 0..3, and receives D[4(l/16)+i][l%16].
+// buffer.  Convolutions are implicit GEMMs on the MFMA unit (BF16 operands,
+// FP32 accumulation) with the 27 taps (periodic neighbours) and the input
+// channels as the K index:
+//   k_conv3          one-plane kernel: a wave computes 16 consecutive voxels
+//                    along k times 16 output channels per tile
+//                    (v_mfma_f32_16x16x16_bf16);
+//   k_conv3_lds      the same with the plane staged in LDS;
+//   k_conv3_march    grids that are multiples of 64, up to 48 input channels:
+//                    blocks march along i with three input planes in an LDS
+//                    ring (v_mfma_f32_16x16x32_bf16);
+//   k_conv3_in1      the first layer at inference (one density channel);
+//   k_upconv_poly    decoder layers on upsampled tensors at inference
+//                    (polyphase form on the coarse grid);
+//   k_conv3_wgrad    weight and bias gradients (voxels as the K index).
+// MFMA operand layout (16x16xK, K = 16 or 32, L = K / 4 values per lane):
+// lane l supplies A[l%16][L(l/16)+i] and B[L(l/16)+i][l%16], i < L, and
+// receives D[4(l/16)+i][l%16], i = 0..3.
 #include "pmeft_internal.h"
 
 #include <math.h>
