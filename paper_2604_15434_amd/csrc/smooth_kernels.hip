@@ -149,6 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
 // halo (j and i halos of 2 rows and 2 planes per tile), which counts where
 // the level's working set does not stay in the last-level cache (FP64 at
 // 256^3), at the price of LDS (two FP64 blocks per CU with CJ 4).
+constexpr int kMinTiles = 256;
+
 static inline int tile_config(int n, int choice)
 {
     if (choice == 0 || n < 64)
@@ -158,9 +160,11 @@ static inline int tile_config(int n, int choice)
         return 4;
     if (choice >= 2 && nh % 64 == 0 && n % 16 == 0 && (n / 8) * (nh / 64) * (n / 16) >= 512)
         return 1;
-    if (nh % 64 == 0 && n % 8 == 0)
+    // small tiles only where they still occupy the chip: a level with fewer
+    // than kMinTiles of them runs the grid-wide kernel (more blocks)
+    if (nh % 64 == 0 && n % 8 == 0 && (n / 4) * (nh / 64) * (n / 8) >= kMinTiles)
         return 2;
-    if (nh % 32 == 0 && n % 8 == 0)
+    if (nh % 32 == 0 && n % 8 == 0 && (n / 8) * (nh / 32) * (n / 8) >= kMinTiles)
         return 3;
     return 0;
 }
