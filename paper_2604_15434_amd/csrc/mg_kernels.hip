@@ -55,6 +55,40 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
                        out);
 }
 
+// k_finalize for the six sums of the mixed-precision outer residual, which
+// also writes the next lagged means (lag64[0] = sum 2, lag64[1] = 0,
+// lag32[0..1] = sums 4, 5), saving the copies a separate launch would need.
+__global__ __launch_bounds__(kBlock) void k_finalize_outer(const double *__restrict__ partials, int nblocks,
+                                                           double *__restrict__ out, double *__restrict__ lag64,
+                                                           double *__restrict__ lag32)
+{
+    constexpr int nv = 6;
+    __shared__ double sm[nv][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = 0; q < nv; q++) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock)
+            acc += partials[(size_t)b * 8 + q];
+        for (int off = 32; off > 0; off >>= 1)
+            acc += __shfl_down(acc, off, 64);
+        if (lane == 0)
+            sm[q][wid] = acc;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / 64; w++)
+            t += sm[threadIdx.x][w];
+        out[threadIdx.x] = t;
+        if (threadIdx.x == 2)
+            lag64[0] = t;
+        else if (threadIdx.x == 4 || threadIdx.x == 5)
+            lag32[threadIdx.x - 4] = t;
+    } else if (threadIdx.x == nv) {
+        lag64[1] = 0.0;
+    }
+}
+
 // ------------------------------------------------------- residual/restrict
 template <typename T, typename R, bool NL>
 __device__ __forceinline__ T cell_residual(const LevelView<R> &F, const R *xr, const R *xb, int c, int i, int j, int kh,
@@ -741,12 +775,20 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
 }
 
 void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
-                                 const LevelView<float> &F32, float *x32r, float *x32b, double *, ReduceSlot rs,
-                                 SolveConsts sc, bool nonlinear, hipStream_t st, int tiled)
+                                 const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs,
+                                 SolveConsts sc, bool nonlinear, hipStream_t st, int tiled, double *lag64,
+                                 double *lag32)
 {
+    auto finish = [&](const Span &s) {
+        if (lag64 && lag32)
+            hipLaunchKernelGGL(k_finalize_outer, dim3(1), dim3(kBlock), 0, st, (const double *)rs.partials,
+                               (int)s.nblocks, rs.out, lag64, lag32);
+        else
+            launch_finalize(rs, s, 6, rs.out, st);
+    };
     Span spt;
     if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt)) {
-        launch_finalize(rs, spt, 6, rs.out, st);
+        finish(spt);
         return;
     }
     const Span sp = make_span(2 * F64.half);
@@ -756,7 +798,7 @@ void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
     else
         hipLaunchKernelGGL((k_mixed_outer<false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32,
                            x32r, x32b, rs, sc, sp);
-    launch_finalize(rs, sp, 6, rs.out, st);
+    finish(sp);
 }
 
 __global__ __launch_bounds__(kBlock) void k_mixed_correct(double *__restrict__ x64, const float *__restrict__ x32r,

@@ -581,12 +581,10 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     bool to_f64 = false;
     for (;; it++) {
         H.cur[0][0] = H.cur[0][1] = 0;
-        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), nullptr, ro, sc, nl,
-                                    C.st, H.tiled);
-        // lagged means for the next outer residual and the FP32 level 0
-        PM_HIP(hipMemcpyAsync(C.csum64, C.outer_out + 2, sizeof(double), hipMemcpyDeviceToDevice, C.st));
-        launch_zero(C.csum64 + 1, sizeof(double), C.st);
-        PM_HIP(hipMemcpyAsync(H.csum_cur(0), C.outer_out + 4, 2 * sizeof(double), hipMemcpyDeviceToDevice, C.st));
+        // (its final stage also sets the lagged means for the next outer
+        // residual and the FP32 level 0)
+        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), ro, sc, nl, C.st,
+                                    H.tiled, C.csum64, H.csum_cur(0));
         H.fresh(0);
         int e = read_out(C, C.outer_out, out, 4);
         if (e)

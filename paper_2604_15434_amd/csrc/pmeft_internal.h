@@ -231,10 +231,14 @@ void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int 
 // partials, cast x32 = fl(x64) (into level-0 x and x0) and the FP32 FAS
 // target tau32 = fl(r64) + lap32 x32 - Lq32(x32); per-colour sums of
 // Lq32 + tau32 into csum32.
+// The six sums go to rs.out; with lag64 / lag32 set, the same final stage
+// also writes the next lagged means: lag64[0] = out[2], lag64[1] = 0,
+// lag32[0..1] = out[4..5] (lag64 may be csum64: the residual kernel has
+// read it by then).
 void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
                                  const double *csum64, const LevelView<float> &F32, float *x32r, float *x32b,
-                                 double *csum32, ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st,
-                                 int tiled = 0);
+                                 ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st, int tiled = 0,
+                                 double *lag64 = nullptr, double *lag32 = nullptr);
 // x64 += x32 - x0_32
 void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, const float *x0r, const float *x0b,
                           long long half, hipStream_t st);
