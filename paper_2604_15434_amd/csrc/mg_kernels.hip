@@ -984,7 +984,9 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
                                                                     int coarse_sweeps)
 {
     // the level table lives in LDS: indexed by level at run time, a kernel
-    // argument would be copied to private memory
+    // argument would be copied to private memory.  The helpers below capture
+    // by value: a by-reference capture of the arguments (sc, the sweep
+    // counts, tid) would keep them in private memory too, read in every loop.
     __shared__ BlockHier<R> B;
     if (threadIdx.x == 0)
         B = Barg;
@@ -1007,7 +1009,7 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         }
     }
     __syncthreads();
-    auto coarsest = [&](const LevelView<R> &Cv, R *cr, R *cb) {
+    auto coarsest = [=](const LevelView<R> &Cv, R *cr, R *cb) {
         if (Cv.n == 4) {  // uniform branch: one wave solves, the block waits
             if (tid < 64)
                 coarsest_wave<R, NL>(Cv, cr, cb, sc, coarse_sweeps, kCoarseTol);
@@ -1016,9 +1018,9 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
             coarsest_solve<R, NL>(Cv, cr, cb, sc, coarse_sweeps, kCoarseTol);
         }
     };
-    auto xr = [&](int l) -> R * { return B.buf[l][cur[l][0]]; };
-    auto xb = [&](int l) -> R * { return B.buf[l][cur[l][1]] + B.L[l].half; };
-    auto half_sweep = [&](int m, int colour) {
+    auto xr = [=](int l) -> R * { return B.buf[l][cur[l][0]]; };
+    auto xb = [=](int l) -> R * { return B.buf[l][cur[l][1]] + B.L[l].half; };
+    auto half_sweep = [=](int m, int colour) {
         const LevelView<R> &Lv = B.L[m];
         const int own = cur[m][colour];
         const unsigned half = (unsigned)Lv.half;
@@ -1043,7 +1045,7 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         }
         __syncthreads();
     };
-    auto fas = [&](int m, int acc_only) {
+    auto fas = [=](int m, int acc_only) {
         double acc[2] = {0.0, 0.0};
         const unsigned tot = 2u * (unsigned)B.L[m].half;
         R *x_r = xr(m), *x_b = xb(m);
@@ -1056,7 +1058,7 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         }
         __syncthreads();
     };
-    auto vcycle = [&](int l) {
+    auto vcycle = [=](int l) {
         for (int m = l; m < L - 1; m++) {
             for (int s = 0; s < n_pre; s++) {
                 half_sweep(m, 0);
