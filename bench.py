@@ -110,9 +110,10 @@ def smoother_kernel(itemsize, tiled, ng):
             return f"k_smooth_tile<{r}, true, 64, 4, 16>"
         if tiled >= 2 and nh % 64 == 0 and ng % 16 == 0 and (ng // 8) * (nh // 64) * (ng // 16) >= 512:
             return f"k_smooth_tile<{r}, true, 64, 2, {8 if itemsize == 8 else 16}>"
-        if nh % 64 == 0 and ng % 8 == 0:
+        # small tiles only where they still give 256 tiles
+        if nh % 64 == 0 and ng % 8 == 0 and (ng // 4) * (nh // 64) * (ng // 8) >= 256:
             return f"k_smooth_tile<{r}, true, 64, 1, 8>"
-        if nh % 32 == 0 and ng % 8 == 0:
+        if nh % 32 == 0 and ng % 8 == 0 and (ng // 8) * (nh // 32) * (ng // 8) >= 256:
             return f"k_smooth_tile<{r}, true, 32, 1, 8>"
     return f"k_smooth<{r}, true>"
 
