@@ -977,11 +977,21 @@ __device__ __forceinline__ void block_sum2(double a, double b, double *out2, dou
     __syncthreads();
 }
 
+// Levels lr..L-1 of a block cycle live in LDS for the whole launch: every
+// operation on them is bound by memory latency, not bandwidth.  A resident
+// level holds its delta, its tau (if it has one), x0 (below l0 only) and the
+// two colour buffers, each 2 half elements; at most kBlockLdsBytes in all.
+constexpr size_t kBlockLdsBytes = 48 * 1024;
+__host__ __device__ constexpr unsigned block_level_elems(long long half, bool has_tau, bool has_x0)
+{
+    return (unsigned)(2 * half) * (3u + (has_tau ? 1u : 0u) + (has_x0 ? 1u : 0u));
+}
+
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R> Barg, int l0, int fmg, int n_pre,
                                                                     int n_post, SolveConsts sc,
                                                                     const double *__restrict__ csum_l0, int cur_bits,
-                                                                    int coarse_sweeps)
+                                                                    int coarse_sweeps, int lr)
 {
     // the level table lives in LDS: indexed by level at run time, a kernel
     // argument would be copied to private memory.  The helpers below capture
@@ -1009,6 +1019,57 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
         }
     }
     __syncthreads();
+    // Move the resident levels into LDS.  Delta and tau are inputs (tau of
+    // every level below l0 is still read by full multigrid), level l0's two
+    // colour buffers are inputs and outputs; the rest is written in the cycle
+    // before it is read.  The views in B are repointed level by level, once
+    // all threads have copied through the old pointers.
+    extern __shared__ __align__(16) unsigned char bc_dyn[];
+    __shared__ R *gx0[2];
+    if (lr < L) {
+        R *lds = reinterpret_cast<R *>(bc_dyn);
+        unsigned o = 0;
+        for (int m = lr; m < L; m++) {
+            const unsigned half = (unsigned)B.L[m].half, tot = 2u * half;
+            const bool has_t = B.L[m].tr != nullptr, has_x0 = m > l0 && B.L[m].x0r != nullptr;
+            R *d = lds + o;
+            R *t = d + tot;
+            R *x0 = t + (has_t ? tot : 0u);
+            R *b0 = x0 + (has_x0 ? tot : 0u);
+            R *b1 = b0 + tot;
+            o += block_level_elems(half, has_t, has_x0);
+            for (unsigned e = tid; e < tot; e += nt) {
+                const bool red_half = e < half;
+                d[e] = red_half ? B.L[m].dr[e] : B.L[m].db[e - half];
+                if (has_t)
+                    t[e] = red_half ? B.L[m].tr[e] : B.L[m].tb[e - half];
+                if (m == l0) {
+                    b0[e] = B.buf[m][0][e];
+                    b1[e] = B.buf[m][1][e];
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                if (m == l0) {
+                    gx0[0] = B.buf[m][0];
+                    gx0[1] = B.buf[m][1];
+                }
+                B.L[m].dr = d;
+                B.L[m].db = d + half;
+                if (has_t) {
+                    B.L[m].tr = t;
+                    B.L[m].tb = t + half;
+                }
+                if (has_x0) {
+                    B.L[m].x0r = x0;
+                    B.L[m].x0b = x0 + half;
+                }
+                B.buf[m][0] = b0;
+                B.buf[m][1] = b1;
+            }
+            __syncthreads();
+        }
+    }
     auto coarsest = [=](const LevelView<R> &Cv, R *cr, R *cb) {
         if (Cv.n == 4) {  // uniform branch: one wave solves, the block waits
             if (tid < 64)
@@ -1112,18 +1173,37 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
     } else {
         vcycle(l0);
     }
+    if (lr <= l0) {  // level l0 resident: its colour buffers go back
+        __syncthreads();
+        const unsigned tot = 2u * (unsigned)B.L[l0].half;
+        for (unsigned e = tid; e < tot; e += nt) {
+            gx0[0][e] = B.buf[l0][0][e];
+            gx0[1][e] = B.buf[l0][1][e];
+        }
+    }
 }
 
 template <typename R>
 void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
                         const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st)
 {
+    // the coarsest levels that fit in kBlockLdsBytes become resident
+    int lr = B.nlev;
+    size_t bytes = 0;
+    for (int m = B.nlev - 1; m >= l0; m--) {
+        const size_t b = sizeof(R) * block_level_elems(B.L[m].half, B.L[m].tr != nullptr,
+                                                       m > l0 && B.L[m].x0r != nullptr);
+        if (bytes + b > kBlockLdsBytes)
+            break;
+        bytes += b;
+        lr = m;
+    }
     if (nonlinear)
-        hipLaunchKernelGGL((k_block_cycle<R, true>), dim3(1), dim3(kBlockCycleThreads), 0, st, B, l0, fmg ? 1 : 0,
-                           n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps);
+        hipLaunchKernelGGL((k_block_cycle<R, true>), dim3(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
+                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr);
     else
-        hipLaunchKernelGGL((k_block_cycle<R, false>), dim3(1), dim3(kBlockCycleThreads), 0, st, B, l0, fmg ? 1 : 0,
-                           n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps);
+        hipLaunchKernelGGL((k_block_cycle<R, false>), dim3(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
+                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr);
 }
 
 template void launch_block_cycle<float>(const BlockHier<float> &, int, bool, int, int, SolveConsts, bool,
