@@ -172,13 +172,17 @@ int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, co
 
 /* One PM gravity step: deposit, Poisson, scalar field, force, kick and, if
  * dt_drift != 0, drift pos += vel * dt_drift (mod 1).  psi and chi (ng^3) are
- * outputs and, with guess GIVEN, carry the previous step's fields in.  With
- * scalar_opts->guess == PM_GUESS_LEARNED the network's forward pass runs on a
- * second stream owned by the library (one per device, created on the first
- * such call, default priority), ordered after the deposit and before the
- * scalar solve by events, so that it overlaps the Poisson solve; all other
- * work stays on `stream`.  Overlapping calls on one device share that stream:
- * correct, but their network passes serialise. */
+ * outputs and, with guess GIVEN, carry the previous step's fields in.  The
+ * two solves depend on the deposit's delta only and run side by side: the
+ * scalar-field solve (with PM_GUESS_LEARNED, after the network's forward pass
+ * and the warm-start pass) is issued by a library worker thread on a second
+ * stream owned by the library (one per device, created on first use, default
+ * priority), ordered after the deposit and before the force by events; the
+ * Poisson solve and all other work stay on `stream`, and the call returns
+ * once both solves have finished their host-side convergence tests.  The
+ * results are those of running the solves one after the other.  Overlapping
+ * calls on one device share the second stream: correct, but their scalar
+ * solves serialise. */
 int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p /* HOST */,
             const pm_mg_opts *poisson_opts /* HOST */, const pm_mg_opts *scalar_opts /* HOST */,
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,

@@ -78,7 +78,12 @@ struct Plan {
     size_t d32[kMaxLevels] = {}, p32[kMaxLevels] = {}, q32[kMaxLevels] = {}, t32[kMaxLevels] = {},
            x032[kMaxLevels] = {};
     size_t fixacc = 0, g4 = 0;
+    size_t dalt64[kMaxLevels] = {}, dalt32[kMaxLevels] = {};  // step plans: the warm start's delta hierarchy
     int precs = 0;
+    // Everything one solve writes (reductions, lagged means, the hierarchy
+    // buffers) sits in [solve_lo, solve_lo + solve_bytes); a step plan holds a
+    // second such region at solve2 so that its two solves can run side by side.
+    size_t solve_lo = 0, solve_bytes = 0, solve2 = 0;
 };
 
 static size_t take(size_t &cur, size_t bytes)
@@ -101,6 +106,26 @@ static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
     for (int l = 0, m = ng; l < P.nlev; l++, m /= 2)
         P.n[l] = m;
     size_t c = 0;
+    // shared by both solves (read-only while they run)
+    for (int l = 0; l < P.nlev; l++)
+        P.delta64[l] = take(c, sizeof(double) * (size_t)P.n[l] * P.n[l] * P.n[l]);
+    P.psi64 = take(c, sizeof(double) * P.N);
+    P.chi64 = take(c, sizeof(double) * P.N);
+    if (precs & kPrecMixed)
+        for (int l = 0; l < P.nlev; l++)
+            P.d32[l] = take(c, sizeof(float) * (size_t)P.n[l] * P.n[l] * P.n[l]);
+    if (np > 0) {
+        P.fixacc = take(c, sizeof(unsigned long long) * P.N);
+        P.g4 = take(c, (dt == PM_F64 ? sizeof(double) : sizeof(float)) * 4 * P.N);
+        for (int l = 0; l < P.nlev; l++) {
+            const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
+            P.dalt64[l] = take(c, sizeof(double) * m3);
+            if (precs & kPrecMixed)
+                P.dalt32[l] = take(c, sizeof(float) * m3);
+        }
+    }
+    // one solve's own region
+    P.solve_lo = c;
     P.red_partials = take(c, sizeof(double) * 8 * kMaxBlocks);
     P.red_counter = take(c, 256);
     P.red_out = take(c, sizeof(double) * 8);
@@ -108,10 +133,6 @@ static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
     P.csum64 = take(c, sizeof(double) * 2 * 2 * kMaxLevels);
     P.csum32 = take(c, sizeof(double) * 2 * 2 * kMaxLevels);
     P.sm_partials = take(c, sizeof(double) * 8 * kMaxBlocks * 2 * kMaxLevels);
-    for (int l = 0; l < P.nlev; l++)
-        P.delta64[l] = take(c, sizeof(double) * (size_t)P.n[l] * P.n[l] * P.n[l]);
-    P.psi64 = take(c, sizeof(double) * P.N);
-    P.chi64 = take(c, sizeof(double) * P.N);
     if (precs & kPrecF64) {
         for (int l = 0; l < P.nlev; l++) {
             const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
@@ -127,19 +148,45 @@ static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
     if (precs & kPrecMixed) {
         for (int l = 0; l < P.nlev; l++) {
             const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
-            P.d32[l] = take(c, sizeof(float) * m3);
             P.p32[l] = take(c, sizeof(float) * m3);
             P.q32[l] = take(c, sizeof(float) * m3);
             P.t32[l] = take(c, sizeof(float) * m3);
             P.x032[l] = take(c, sizeof(float) * m3);
         }
     }
+    P.solve_bytes = c - P.solve_lo;
     if (np > 0) {
-        P.fixacc = take(c, sizeof(unsigned long long) * P.N);
-        P.g4 = take(c, (dt == PM_F64 ? sizeof(double) : sizeof(float)) * 4 * P.N);
+        P.solve2 = c;
+        c += P.solve_bytes;
     }
     P.total = c + 256;
     return true;
+}
+
+// Moves every offset of the per-solve region to start at `to` (the layout
+// inside the region is unchanged).
+static void rebase_solve(Plan &P, size_t to)
+{
+    const size_t d = to - P.solve_lo;
+    for (size_t *f : {&P.red_partials, &P.red_counter, &P.red_out, &P.outer_out, &P.csum64, &P.csum32, &P.sm_partials})
+        *f += d;
+    for (int l = 0; l < P.nlev; l++) {
+        if (P.precs & kPrecF64) {
+            if (l > 0) {
+                P.p64[l] += d;
+                P.t64[l] += d;
+                P.x064[l] += d;
+            }
+            P.q64[l] += d;
+        }
+        if (P.precs & kPrecMixed) {
+            P.p32[l] += d;
+            P.q32[l] += d;
+            P.t32[l] += d;
+            P.x032[l] += d;
+        }
+    }
+    P.solve_lo = to;
 }
 
 // ---------------------------------------------------------------- context
@@ -164,6 +211,20 @@ static int launched()
     return hipGetLastError() == hipSuccess ? PM_OK : PM_EHIP;
 }
 
+// Pointers of the context's per-solve region (from its plan); the reduction
+// counter is cleared on the context's stream.
+static void bind_solve(Ctx &C)
+{
+    C.rs.partials = C.at<double>(C.P.red_partials);
+    C.rs.counter = C.at<unsigned>(C.P.red_counter);
+    C.rs.out = C.at<double>(C.P.red_out);
+    C.csum64 = C.at<double>(C.P.csum64);
+    C.csum32 = C.at<double>(C.P.csum32);
+    C.outer_out = C.at<double>(C.P.outer_out);
+    C.sm_partials = C.at<double>(C.P.sm_partials);
+    launch_zero(C.ws + C.P.red_counter, 256, C.st);
+}
+
 static int setup_ctx(Ctx &C, void *ws, size_t ws_bytes, int ng, long long np, pm_dtype dt, int precs,
                      pm_stream_t stream)
 {
@@ -178,14 +239,7 @@ static int setup_ctx(Ctx &C, void *ws, size_t ws_bytes, int ng, long long np, pm
         return PM_EINVAL;
     C.ws = (char *)ws;
     C.st = (hipStream_t)stream;
-    C.rs.partials = C.at<double>(C.P.red_partials);
-    C.rs.counter = C.at<unsigned>(C.P.red_counter);
-    C.rs.out = C.at<double>(C.P.red_out);
-    C.csum64 = C.at<double>(C.P.csum64);
-    C.csum32 = C.at<double>(C.P.csum32);
-    C.outer_out = C.at<double>(C.P.outer_out);
-    C.sm_partials = C.at<double>(C.P.sm_partials);
-    launch_zero(C.ws + C.P.red_counter, 256, C.st);
+    bind_solve(C);
     return launched();
 }
 
@@ -747,11 +801,13 @@ static int learned_ok(int ng, const pm_mg_opts &o)
 }
 
 // Learned warm start: one linear full-multigrid pass on
-// nu lap chi0 = xi s (delta + t - <t>), t from the network; delta is restored
-// afterwards.  forward_done: the network's forward pass was already issued
-// (and waited for) by the caller.
+// nu lap chi0 = xi s (delta + t - <t>), t from the network.  forward_done: the
+// network's forward pass was already issued (and waited for) by the caller.
+// separate: the pass's delta is built in the plan's second delta hierarchy
+// (step plans), so the shared one is never modified and a concurrent solve
+// may read it; otherwise delta is modified in place and restored afterwards.
 static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, double src,
-                         bool forward_done)
+                         bool forward_done, bool separate)
 {
     const int ng = C.P.ng;
     int e = learned_ok(ng, o);
@@ -764,17 +820,30 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
         if (e)
             return e;
     }
-    e = unet_add_learned_source(o.learned_ws, ng, d0, C.st);
+    Ctx G = C;  // the guess pass: C's solve region, its own delta when separate
+    if (separate) {
+        if (!C.P.dalt64[0])
+            return PM_EINVAL;
+        for (int l = 0; l < C.P.nlev; l++) {
+            G.P.delta64[l] = C.P.dalt64[l];
+            G.P.d32[l] = C.P.dalt32[l];
+        }
+        PM_HIP(hipMemcpyAsync(G.at<double>(G.P.delta64[0]), save, sizeof(double) * C.P.N, hipMemcpyDeviceToDevice,
+                              C.st));
+    }
+    e = unet_add_learned_source(o.learned_ws, ng, G.at<double>(G.P.delta64[0]), C.st);
     if (e)
         return e;
-    delta_levels(C);
+    delta_levels(G);
     pm_mg_opts lo = o;
     lo.rel_tol = 1e-30;  // the pass itself, no convergence test
     lo.max_vcycles = 1;
     SolveOut tmp;
-    e = run_solve(C, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true);
+    e = run_solve(G, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true);
     if (e)
         return e;
+    if (separate)
+        return launched();
     PM_HIP(hipMemcpyAsync(d0, save, sizeof(double) * C.P.N, hipMemcpyDeviceToDevice, C.st));
     delta_levels(C);
     return launched();
@@ -782,7 +851,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
 
 // Scalar field: nu lap chi - xi s delta - K N(chi) = 0 (beta = xi s).
 static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so,
-                       double dsq, bool forward_done = false)
+                       double dsq, bool forward_done = false, bool separate_delta = false)
 {
     double *m = C.at<double>(C.P.chi64);
     so = SolveOut();
@@ -800,7 +869,7 @@ static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, 
     if (o.guess != PM_GUESS_GIVEN)
         launch_zero(m, sizeof(double) * C.P.N, C.st);
     if (o.guess == PM_GUESS_LEARNED && nl) {
-        int e = learned_guess(C, p, cf, o, src, forward_done);
+        int e = learned_guess(C, p, cf, o, src, forward_done, separate_delta);
         if (e)
             return e;
         return run_solve(C, m, sc, nl, o, src, so, false);
@@ -1232,14 +1301,13 @@ int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, co
 }
 
 // The library's second stream (one per device, created on first use, default
-// priority, non-blocking): pm_step runs the warm start's network on it while
-// the Poisson solve runs on the caller's stream.  Overlapping pm_step calls on
-// one device share it (and its two events), which stays correct but may
-// serialise their network passes.
+// priority, non-blocking): pm_step runs its scalar-field solve on it while the
+// Poisson solve runs on the caller's stream.  Overlapping pm_step calls on one
+// device share it, which stays correct (each call orders its work with events
+// of its own) but serialises their scalar solves.
 namespace {
 struct SideStream {
     hipStream_t s = nullptr;
-    hipEvent_t ready = nullptr, done = nullptr;
 };
 std::mutex g_side_mu;
 SideStream g_side[64];
@@ -1251,17 +1319,85 @@ int side_stream(SideStream **out)
         return PM_EHIP;
     std::lock_guard<std::mutex> g(g_side_mu);
     SideStream &S = g_side[dev];
-    if (!S.s) {
-        if (hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
-            return PM_EHIP;
-        if (hipEventCreateWithFlags(&S.ready, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess)
-            return PM_EHIP;
-    }
+    if (!S.s && hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
+        return PM_EHIP;
     *out = &S;
     return PM_OK;
 }
 }  // namespace
+
+// The Poisson and scalar-field solves of a step depend on delta only, so they
+// run side by side: the scalar field (after the warm start's network and
+// pass, built on the plan's second delta hierarchy) on the side stream,
+// driven by a worker thread through the plan's second per-solve region, the
+// Poisson solve on the caller's stream in this thread.  Each solve's launches
+// and convergence reads stay those of running it alone, so the results do not
+// change; the latency-bound coarse levels of one overlap the other's large
+// levels.
+static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &po,
+                      const pm_mg_opts &so, double dsq, SolveOut &sp, SolveOut &sx, float &ms_p, float &ms_x)
+{
+    SideStream *S = nullptr;
+    int e = side_stream(&S);
+    if (e)
+        return e;
+    int dev = 0;
+    PM_HIP(hipGetDevice(&dev));
+    hipEvent_t ready = nullptr, done = nullptr;
+    PM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        return PM_EHIP;
+    }
+    Ctx C1 = C;
+    rebase_solve(C1.P, C.P.solve2);
+    C1.st = S->s;
+    e = hipEventRecord(ready, C.st) == hipSuccess && hipStreamWaitEvent(C1.st, ready, 0) == hipSuccess ? PM_OK
+                                                                                                      : PM_EHIP;
+    if (e) {
+        (void)hipEventDestroy(ready);
+        (void)hipEventDestroy(done);
+        return e;
+    }
+    bind_solve(C1);
+    int ex = PM_OK;
+    auto scalar_job = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) {
+            ex = PM_EHIP;
+            return;
+        }
+        Timer tx(C1.st);
+        ex = scalar_core(C1, p, cf, so, sx, dsq, false, true);
+        if (!ex)
+            ms_x = tx.stop();
+    };
+    std::thread worker;
+    bool threaded = true;
+    try {
+        worker = std::thread(scalar_job);
+    } catch (...) {  // no thread: the same work, issued from this thread first
+        threaded = false;
+    }
+    if (!threaded)
+        scalar_job();
+    {
+        Timer tp(C.st);
+        e = poisson_core(C, cf, po, sp, dsq);
+        if (!e)
+            ms_p = tp.stop();
+    }
+    if (threaded)
+        worker.join();
+    // on every path: the caller's stream waits for the scalar solve's work
+    const bool waited = hipEventRecord(done, C1.st) == hipSuccess && hipStreamWaitEvent(C.st, done, 0) == hipSuccess;
+    (void)hipEventDestroy(ready);
+    (void)hipEventDestroy(done);
+    if (!e)
+        e = ex;
+    if (!e && !waited)
+        e = PM_EHIP;
+    return e;
+}
 
 int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p,
             const pm_mg_opts *poisson_opts, const pm_mg_opts *scalar_opts, double dt_kick, double dt_drift, void *psi,
@@ -1295,43 +1431,19 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
     if (scalar_opts->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
-    // the warm start's network depends on delta only: issue it on the side
-    // stream so that it overlaps the Poisson solve
-    const bool side = scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0 && dsq > 0.0;
-    SideStream *S = nullptr;
-    if (side) {
+    // the learned warm start's workspace is checked before either solve
+    // starts (its network runs at the start of the scalar solve, on that
+    // solve's stream)
+    if (scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0 && dsq > 0.0) {
         e = learned_ok(ng, *scalar_opts);
-        if (!e)
-            e = side_stream(&S);
         if (e)
             return e;
-        PM_HIP(hipEventRecord(S->ready, C.st));
-        PM_HIP(hipStreamWaitEvent(S->s, S->ready, 0));
-        e = unet_learned_forward(scalar_opts->learned_params, C.at<double>(C.P.delta64[0]),
-                                 unet_save_area(scalar_opts->learned_ws, ng), ng, *p, scalar_opts->learned_ws,
-                                 scalar_opts->learned_ws_bytes, S->s);
-        if (e)
-            return e;
-        PM_HIP(hipEventRecord(S->done, S->s));
     }
     SolveOut sp, sx;
-    Timer tp(C.st);
-    e = poisson_core(C, cf, *poisson_opts, sp, dsq);
-    const float ms_p = e ? 0.0f : tp.stop();
-    if (side) {
-        // also on the error path: the caller's stream must not run ahead of
-        // the network's use of the warm-start workspace
-        const hipError_t we = hipStreamWaitEvent(C.st, S->done, 0);
-        if (!e && we != hipSuccess)
-            e = PM_EHIP;
-    }
+    float ms_p = 0.0f, ms_x = 0.0f;
+    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, sp, sx, ms_p, ms_x);
     if (e)
         return e;
-    Timer tx(C.st);
-    e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq, side);
-    if (e)
-        return e;
-    const float ms_x = tx.stop();
     Timer tf(C.st);
     void *g4 = C.ws + C.P.g4;
     launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
