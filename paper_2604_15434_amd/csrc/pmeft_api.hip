@@ -614,8 +614,11 @@ constexpr double kMixedSwitchNL = 3e-6;
 constexpr int kMixedInner = 2;        // FP32 V-cycles per outer step
 constexpr double kMixedStall = 0.36;  // an outer step must reduce the residual at least this much (0.6 per V-cycle)
 
+// final_residual = false: once the cycle budget is spent, the last outer
+// residual (which changes nothing but the report) and its readback are
+// skipped; for callers that read no residual.
 static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                       SolveOut &so, bool zero_start)
+                       SolveOut &so, bool zero_start, bool final_residual = true)
 {
     Hier<float> H;
     build_hier32(C, H);
@@ -634,6 +637,10 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     double prev = 0.0;
     bool to_f64 = false;
     for (;; it++) {
+        if (!final_residual && it > 0 && cyc >= o.max_vcycles) {
+            so.status = PM_ENOCONV;
+            break;
+        }
         H.cur[0][0] = H.cur[0][1] = 0;
         // (its final stage also sets the lagged means for the next outer
         // residual and the FP32 level 0)
@@ -768,10 +775,11 @@ static bool opts_ok(const pm_mg_opts *o)
 // its last V-cycles in FP64.
 static int prec_bits(const pm_mg_opts *o) { return o->precision == PM_PREC_MIXED ? (kPrecMixed | kPrecF64) : kPrecF64; }
 
+// final_residual: see solve_mixed (the FP64 path always tests).
 static int run_solve(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                     SolveOut &so, bool zero_start)
+                     SolveOut &so, bool zero_start, bool final_residual = true)
 {
-    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so, zero_start)
+    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so, zero_start, final_residual)
                                         : solve_f64(C, master, sc, nl, o, src_norm, so, zero_start);
 }
 
@@ -839,7 +847,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
     lo.rel_tol = 1e-30;  // the pass itself, no convergence test
     lo.max_vcycles = 1;
     SolveOut tmp;
-    e = run_solve(G, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true);
+    e = run_solve(G, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true, false);
     if (e)
         return e;
     if (separate)
@@ -1334,8 +1342,11 @@ int side_stream(SideStream **out)
 // and convergence reads stay those of running it alone, so the results do not
 // change; the latency-bound coarse levels of one overlap the other's large
 // levels.
+// Also writes psi_out (natural order, mean removed) right after the Poisson
+// solve, while the scalar solve still runs.
 static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &po,
-                      const pm_mg_opts &so, double dsq, SolveOut &sp, SolveOut &sx, float &ms_p, float &ms_x)
+                      const pm_mg_opts &so, double dsq, void *psi_out, pm_dtype dtype, SolveOut &sp, SolveOut &sx,
+                      float &ms_p, float &ms_x)
 {
     SideStream *S = nullptr;
     int e = side_stream(&S);
@@ -1383,8 +1394,13 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
     {
         Timer tp(C.st);
         e = poisson_core(C, cf, po, sp, dsq);
-        if (!e)
+        if (!e) {
             ms_p = tp.stop();
+            double *ps = C.at<double>(C.P.psi64);
+            launch_field_sum(ps, C.P.N, C.rs, C.st);
+            launch_packed_to_natural(ps, psi_out, dtype, C.P.ng, 0.0, C.rs.out, C.st);
+            e = launched();
+        }
     }
     if (threaded)
         worker.join();
@@ -1441,7 +1457,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     }
     SolveOut sp, sx;
     float ms_p = 0.0f, ms_x = 0.0f;
-    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, sp, sx, ms_p, ms_x);
+    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x);
     if (e)
         return e;
     Timer tf(C.st);
@@ -1449,8 +1465,6 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
     launch_interp_kick(g4, ng, dtype, pos, np, vel, dt_kick, dt_drift, nullptr, C.st);
     const float ms_f = tf.stop();
-    launch_field_sum(ps, C.P.N, C.rs, C.st);
-    launch_packed_to_natural(ps, psi, dtype, ng, 0.0, C.rs.out, C.st);
     launch_field_sum(ch, C.P.N, C.rs, C.st);
     launch_packed_to_natural(ch, chi, dtype, ng, 0.0, C.rs.out, C.st);
     e = launched();
