@@ -176,6 +176,40 @@ def test_pm_step_cfg0_matches_oracle(P, dtype, prec, ftol):
     assert np.array_equal(gp.cpu().numpy(), pos.astype(gp.cpu().numpy().dtype))  # no drift requested
 
 
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_pm_step_solves_match_standalone_solves(P, prec):
+    """pm_step runs its two solves side by side: the scalar field on a second
+    stream from a worker thread, in a workspace region of its own.  Its fields
+    must be those of the standalone solves on the step's own deposit, and
+    repeated steps must agree bit for bit."""
+    from workloads import lognormal_particles
+
+    ng = 64
+    pos_np, _ = lognormal_particles(ng, 125.0, seed=41)
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.05, a=0.9)
+    opts = P.MgOpts(rel_tol=1e-10, max_vcycles=80, precision=prec)
+    pos = torch.from_numpy(pos_np).cuda()
+    rho = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    P.pm_deposit(pos, ng, rho)
+    psi_ref, chi_ref = torch.zeros_like(rho), torch.zeros_like(rho)
+    assert P.mg_poisson_solve(rho, prm, opts, psi_ref)["status"] == 0
+    assert P.mg_scalar_solve(rho, prm, opts, chi_ref)["status"] == 0
+    outs = []
+    for _ in range(2):
+        vel = torch.zeros_like(pos)
+        psi, chi = torch.zeros_like(rho), torch.zeros_like(rho)
+        rep = P.pm_step(pos, vel, ng, prm, opts, opts, 1e-2, 0.0, psi, chi)
+        assert rep["status"] == 0, rep
+        torch.cuda.synchronize()
+        outs.append((psi.clone(), chi.clone(), vel.clone()))
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    psi, chi, _ = outs[0]
+    assert float(chi_ref.norm()) > 0.0 and float(psi_ref.norm()) > 0.0
+    assert float((psi - psi_ref).norm() / psi_ref.norm()) < 1e-8
+    assert float((chi - chi_ref).norm() / chi_ref.norm()) < 1e-8
+
+
 _CFG1_CACHE = {}
 
 
