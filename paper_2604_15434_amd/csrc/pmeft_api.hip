@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -730,12 +731,20 @@ static void delta_levels(Ctx &C)
 }
 
 // delta hierarchy from the packed fine delta (mean removed here) + FP32 copy
-static int prepare_delta(Ctx &C, double *delta_sq_sum)
+// after_mean (optional) is called once the fine delta is mean-free on C.st,
+// before the coarse levels and the norm: work that needs only the fine delta
+// can start there.
+static int prepare_delta(Ctx &C, double *delta_sq_sum, const std::function<int()> &after_mean = nullptr)
 {
     const Plan &P = C.P;
     double *d0 = C.at<double>(P.delta64[0]);
     launch_field_sum(d0, P.N, C.rs, C.st);
     launch_subtract_mean(d0, P.N, C.rs.out, C.st);
+    if (after_mean) {
+        const int e = after_mean();
+        if (e)
+            return e;
+    }
     delta_levels(C);
     launch_field_sum(d0, P.N, C.rs, C.st);
     double out[2];
@@ -1344,9 +1353,10 @@ int side_stream(SideStream **out)
 // levels.
 // Also writes psi_out (natural order, mean removed) right after the Poisson
 // solve, while the scalar solve still runs.
+// forward_done: the warm start's forward pass is already on the side stream.
 static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &po,
                       const pm_mg_opts &so, double dsq, void *psi_out, pm_dtype dtype, SolveOut &sp, SolveOut &sx,
-                      float &ms_p, float &ms_x)
+                      float &ms_p, float &ms_x, bool forward_done)
 {
     SideStream *S = nullptr;
     int e = side_stream(&S);
@@ -1378,7 +1388,7 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
             return;
         }
         Timer tx(C1.st);
-        ex = scalar_core(C1, p, cf, so, sx, dsq, false, true);
+        ex = scalar_core(C1, p, cf, so, sx, dsq, forward_done, true);
         if (!ex)
             ms_x = tx.stop();
     };
@@ -1437,27 +1447,55 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
     launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
     launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, C.at<double>(C.P.delta64[0]), C.rs, C.st);
+    // with the learned warm start, the network needs the mean-free fine
+    // delta only: its forward pass starts on the scalar solve's stream as soon
+    // as that exists, beside the rest of the delta preparation
+    const bool learned = scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0;
+    SideStream *S = nullptr;
+    if (learned) {
+        e = learned_ok(ng, *scalar_opts);
+        if (!e)
+            e = side_stream(&S);
+        if (e)
+            return e;
+    }
+    bool fwd = false;
+    auto start_network = [&]() -> int {
+        if (!learned)
+            return PM_OK;
+        hipEvent_t ev = nullptr;
+        PM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        const bool ok = hipEventRecord(ev, C.st) == hipSuccess && hipStreamWaitEvent(S->s, ev, 0) == hipSuccess;
+        (void)hipEventDestroy(ev);
+        if (!ok)
+            return PM_EHIP;
+        fwd = true;  // (set before the call: on failure part of it may be queued)
+        return unet_learned_forward(scalar_opts->learned_params, C.at<double>(C.P.delta64[0]),
+                                    unet_save_area(scalar_opts->learned_ws, ng), ng, *p, scalar_opts->learned_ws,
+                                    scalar_opts->learned_ws_bytes, S->s);
+    };
     double dsq = 0.0;
-    e = prepare_delta(C, &dsq);
-    if (e)
+    e = prepare_delta(C, &dsq, start_network);
+    if (e) {
+        if (fwd) {  // the caller's stream must not run ahead of the network's use of its buffers
+            hipEvent_t ev = nullptr;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+                (void)hipEventRecord(ev, S->s);
+                (void)hipStreamWaitEvent(C.st, ev, 0);
+                (void)hipEventDestroy(ev);
+            }
+        }
         return e;
+    }
     const float ms_dep = tdep.stop();
     double *ps = C.at<double>(C.P.psi64), *ch = C.at<double>(C.P.chi64);
     if (poisson_opts->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
     if (scalar_opts->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
-    // the learned warm start's workspace is checked before either solve
-    // starts (its network runs at the start of the scalar solve, on that
-    // solve's stream)
-    if (scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0 && dsq > 0.0) {
-        e = learned_ok(ng, *scalar_opts);
-        if (e)
-            return e;
-    }
     SolveOut sp, sx;
     float ms_p = 0.0f, ms_x = 0.0f;
-    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x);
+    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
     if (e)
         return e;
     Timer tf(C.st);
