@@ -132,7 +132,9 @@ int pm_eft_coefficients(const pm_eft_params *p /* HOST */, pm_eft_coeffs *out /*
 int pm_grid_levels(int ng);
 
 /* Workspace bytes for any entry point at this size (np may be 0 for the
- * grid-only calls). */
+ * grid-only calls).  With np > 0 (pm_step) it also holds a second per-solve
+ * region and a second delta hierarchy, so that the step's two solves (and the
+ * warm start's modified delta) run side by side. */
 size_t pm_workspace_bytes(int ng, long long np, pm_dtype dtype, pm_prec prec);
 
 /* CIC deposit (Sec. 3.6.2): rho_c = (ng^3/np) sum_p W(x_p - x_c), the tent
