@@ -220,9 +220,10 @@ def test_trained_network_gain_on_held_out_fields(P):
 
 
 def test_step_overlaps_network_and_keeps_the_field(P):
-    """pm_step runs the warm start's network on a second stream, overlapping
-    the Poisson solve.  The step must give the fields of the zero-guess step
-    (to the solve tolerance) and be deterministic from run to run."""
+    """pm_step runs the warm start's network, the warm-start pass and the
+    scalar solve on a second stream, beside the Poisson solve.  The step must
+    give the fields of the zero-guess step (to the solve tolerance), the same
+    psi, and be deterministic from run to run."""
     from paper_2604_15434_amd.warmstart import DEFAULT_WEIGHTS, WarmStart
     from workloads import lognormal_particles
 
