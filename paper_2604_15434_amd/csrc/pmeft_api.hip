@@ -1474,17 +1474,20 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
                                     unet_save_area(scalar_opts->learned_ws, ng), ng, *p, scalar_opts->learned_ws,
                                     scalar_opts->learned_ws_bytes, S->s);
     };
+    // on an error return after the network was issued: the caller's stream
+    // must not run ahead of the network's use of its buffers
+    auto wait_network = [&]() {
+        hipEvent_t ev = nullptr;
+        if (fwd && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+            (void)hipEventRecord(ev, S->s);
+            (void)hipStreamWaitEvent(C.st, ev, 0);
+            (void)hipEventDestroy(ev);
+        }
+    };
     double dsq = 0.0;
     e = prepare_delta(C, &dsq, start_network);
     if (e) {
-        if (fwd) {  // the caller's stream must not run ahead of the network's use of its buffers
-            hipEvent_t ev = nullptr;
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-                (void)hipEventRecord(ev, S->s);
-                (void)hipStreamWaitEvent(C.st, ev, 0);
-                (void)hipEventDestroy(ev);
-            }
-        }
+        wait_network();
         return e;
     }
     const float ms_dep = tdep.stop();
@@ -1496,8 +1499,10 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     SolveOut sp, sx;
     float ms_p = 0.0f, ms_x = 0.0f;
     e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
-    if (e)
+    if (e) {
+        wait_network();  // (solve_both waits itself once its worker has started)
         return e;
+    }
     Timer tf(C.st);
     void *g4 = C.ws + C.P.g4;
     launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
