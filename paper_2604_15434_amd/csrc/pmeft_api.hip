@@ -1440,16 +1440,10 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     e = setup_ctx(C, ws, ws_bytes, ng, np, dtype, prec_bits(poisson_opts) | prec_bits(scalar_opts), stream);
     if (e)
         return e;
-    Timer tall(C.st);
-    // deposit -> packed delta
-    Timer tdep(C.st);
-    unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
-    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
-    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
-    launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, C.at<double>(C.P.delta64[0]), C.rs, C.st);
-    // with the learned warm start, the network needs the mean-free fine
-    // delta only: its forward pass starts on the scalar solve's stream as soon
-    // as that exists, beside the rest of the delta preparation
+    // With the learned warm start the network runs on the scalar solve's
+    // stream: its weights are packed there first, beside the deposit (they
+    // depend on the parameters only), and its forward pass starts as soon as
+    // the fine delta is mean-free, beside the rest of the delta preparation.
     const bool learned = scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0;
     SideStream *S = nullptr;
     if (learned) {
@@ -1459,23 +1453,27 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         if (e)
             return e;
     }
-    bool fwd = false;
-    auto start_network = [&]() -> int {
-        if (!learned)
-            return PM_OK;
+    bool fwd = false;  // work that uses the caller's buffers is queued on S
+    auto after_caller = [&]() -> int {  // S waits for the caller's stream as it is now
         hipEvent_t ev = nullptr;
         PM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         const bool ok = hipEventRecord(ev, C.st) == hipSuccess && hipStreamWaitEvent(S->s, ev, 0) == hipSuccess;
         (void)hipEventDestroy(ev);
-        if (!ok)
-            return PM_EHIP;
+        return ok ? PM_OK : PM_EHIP;
+    };
+    auto start_network = [&]() -> int {
+        if (!learned)
+            return PM_OK;
+        const int r = after_caller();
+        if (r)
+            return r;
         fwd = true;  // (set before the call: on failure part of it may be queued)
         return unet_learned_forward(scalar_opts->learned_params, C.at<double>(C.P.delta64[0]),
                                     unet_save_area(scalar_opts->learned_ws, ng), ng, *p, scalar_opts->learned_ws,
-                                    scalar_opts->learned_ws_bytes, S->s);
+                                    scalar_opts->learned_ws_bytes, S->s, true);
     };
-    // on an error return after the network was issued: the caller's stream
-    // must not run ahead of the network's use of its buffers
+    // on an error return after work was queued on S: the caller's stream
+    // must not run ahead of that work's use of its buffers
     auto wait_network = [&]() {
         hipEvent_t ev = nullptr;
         if (fwd && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
@@ -1484,6 +1482,25 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             (void)hipEventDestroy(ev);
         }
     };
+    if (learned) {
+        e = after_caller();
+        if (!e) {
+            fwd = true;
+            e = unet_learned_pack(scalar_opts->learned_params, ng, scalar_opts->learned_ws,
+                                  scalar_opts->learned_ws_bytes, S->s);
+        }
+        if (e) {
+            wait_network();
+            return e;
+        }
+    }
+    Timer tall(C.st);
+    // deposit -> packed delta
+    Timer tdep(C.st);
+    unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
+    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
+    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
+    launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, C.at<double>(C.P.delta64[0]), C.rs, C.st);
     double dsq = 0.0;
     e = prepare_delta(C, &dsq, start_network);
     if (e) {

@@ -282,8 +282,13 @@ void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int 
 // on that copy, leaving its source prediction t in the workspace; delta
 // itself is only read (by the copy), so this may run on a second stream
 // while other work reads delta.
+// packed: the weights were already packed into ws by unet_learned_pack (for
+// these params), so the pass skips that.
 int unet_learned_forward(const float *params, const double *delta_packed, double *save, int ng,
-                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st);
+                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st, bool packed = false);
+// The weights' MFMA layouts into ws (inference form), ahead of
+// unet_learned_forward(..., packed = true): they depend on params only.
+int unet_learned_pack(const float *params, int ng, void *ws, size_t ws_bytes, hipStream_t st);
 // delta -> delta + t - <t> with the t of the preceding forward pass.
 int unet_add_learned_source(void *ws, int ng, double *delta_packed, hipStream_t st);
 double *unet_save_area(void *ws, int ng);

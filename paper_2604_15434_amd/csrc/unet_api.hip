@@ -376,7 +376,7 @@ namespace pmeft {
 // packed delta saved into `save`, ng^3 doubles, and the network run on that
 // copy), then delta <- delta + t - <t>.
 int unet_learned_forward(const float *params, const double *delta_packed, double *save, int ng,
-                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st)
+                         const pm_eft_params &p, void *ws, size_t ws_bytes, hipStream_t st, bool packed)
 {
     Net N;
     int e = setup(N, ng, false, ws, ws_bytes, st);
@@ -385,8 +385,19 @@ int unet_learned_forward(const float *params, const double *delta_packed, double
     const size_t n3 = (size_t)ng * ng * ng;
     if (hipMemcpyAsync(save, delta_packed, sizeof(double) * n3, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return PM_EHIP;
-    pack_all(N, params);
+    if (!packed)
+        pack_all(N, params);
     forward(N, params, save, p);
+    return launched();
+}
+
+int unet_learned_pack(const float *params, int ng, void *ws, size_t ws_bytes, hipStream_t st)
+{
+    Net N;
+    int e = setup(N, ng, false, ws, ws_bytes, st);
+    if (e)
+        return e;
+    pack_all(N, params);
     return launched();
 }
 
