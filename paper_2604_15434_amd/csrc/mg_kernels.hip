@@ -25,20 +25,51 @@
 
 namespace pmeft {
 
+// Per-thread stage of the finalize kernels: thread t adds, in order, the
+// rows b = t, t + kBlock, ... (< nblocks) of the partials, each value q into
+// acc[q].  All of a thread's rows are loaded (64 bytes each) before any is
+// added, so the stage waits for memory once; rows past nblocks add +0, which
+// leaves every sum bitwise what the row-by-row loop gives.
+constexpr int kFinRows = kMaxBlocks / kBlock;
+__device__ __forceinline__ void finalize_rows(const double *__restrict__ partials, int nblocks, double acc[8])
+{
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 v[kFinRows][4];
+#pragma unroll
+    for (int u = 0; u < kFinRows; u++) {
+        const int b = threadIdx.x + u * kBlock;
+        const d2 *row = reinterpret_cast<const d2 *>(partials + (size_t)b * 8);
+#pragma unroll
+        for (int h = 0; h < 4; h++)
+            v[u][h] = b < nblocks ? row[h] : d2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        acc[q] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kFinRows; u++)
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            acc[q] += v[u][q >> 1][q & 1];
+}
+
 // One block: out[q] = sum over blocks b (in order) of partials[b * 8 + q].
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
                                                      double *__restrict__ out)
 {
     __shared__ double sm[8][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = 0; q < nv; q++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock)
-            acc += partials[(size_t)b * 8 + q];
+    double acc[8];
+    finalize_rows(partials, nblocks, acc);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        if (q >= nv)
+            break;
+        double a = acc[q];
         for (int off = 32; off > 0; off >>= 1)
-            acc += __shfl_down(acc, off, 64);
+            a += __shfl_down(a, off, 64);
         if (lane == 0)
-            sm[q][wid] = acc;
+            sm[q][wid] = a;
     }
     __syncthreads();
     if ((int)threadIdx.x < nv) {
@@ -65,14 +96,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize_outer(const double *__restr
     constexpr int nv = 6;
     __shared__ double sm[nv][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double acc[8];
+    finalize_rows(partials, nblocks, acc);
+#pragma unroll
     for (int q = 0; q < nv; q++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kBlock)
-            acc += partials[(size_t)b * 8 + q];
+        double a = acc[q];
         for (int off = 32; off > 0; off >>= 1)
-            acc += __shfl_down(acc, off, 64);
+            a += __shfl_down(a, off, 64);
         if (lane == 0)
-            sm[q][wid] = acc;
+            sm[q][wid] = a;
     }
     __syncthreads();
     if ((int)threadIdx.x < nv) {
