@@ -72,6 +72,30 @@ def test_grid_levels_and_workspace():
     assert P.pm_strerror(-6) == "workspace too small"
 
 
+def test_step_workspace_holds_two_solves():
+    """A step's two solves run side by side, so a step workspace holds, on top
+    of a grid-solve workspace, the deposit's fixed-point grid, the force grid,
+    a second delta hierarchy (the warm start's) and a second per-solve region
+    (reductions, lagged means, hierarchy buffers) of exactly the grid
+    workspace's size minus the shared arrays (FP64 plan: delta levels, psi,
+    chi; 256-byte granules, plus 256 bytes of slack)."""
+    import paper_2604_15434_amd as P
+
+    def r(b):
+        return (b + 255) // 256 * 256
+
+    ng = 64
+    n3 = ng**3
+    levels = [ng >> l for l in range(P.pm_grid_levels(ng))]
+    delta = sum(r(8 * m**3) for m in levels)
+    shared = delta + 2 * r(8 * n3)
+    grid = P.pm_workspace_bytes(ng, 0, 1, "f64")
+    step = P.pm_workspace_bytes(ng, n3, 1, "f64")
+    region = grid - 256 - shared
+    assert region > 8 * n3  # at least the finest level's second colour buffer
+    assert step == grid + r(8 * n3) + r(32 * n3) + delta + region
+
+
 def test_launch_shape_table_roundtrip(tmp_path):
     import paper_2604_15434_amd as P
 
