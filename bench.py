@@ -39,10 +39,19 @@ HBM_PEAK_GBS = 8000.0
 PARAMS = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
 
 
-def smoother_bytes_per_launch(ng, itemsize, with_tau):
+def smoother_bytes_per_launch(ng, itemsize):
     """Algorithmic bytes of one finest-level half-sweep (one colour, ng^3/2
-    cells): read own colour (edges), other colour (faces), delta (and the FAS
-    source tau on the FP32 level), write own colour."""
+    cells updated), counted as a smoother sweep is counted for the roofline:
+    a full sweep (both colours) reads the iterate and the right-hand side and
+    writes the iterate, 3 words per cell, so one colour's launch is 1.5 words
+    per cell of the grid."""
+    return 3 * itemsize * ng**3 // 2
+
+
+def smoother_operand_bytes_per_launch(ng, itemsize, with_tau):
+    """Bytes one half-sweep must move with its operands as they are stored:
+    read own colour (edges), other colour (faces), delta (and the FAS source
+    tau on the FP32 level), write own colour, per cell of that colour."""
     per_cell = itemsize * (4 + (1 if with_tau else 0))
     return per_cell * ng**3 // 2
 
@@ -166,12 +175,16 @@ def roofline(res, ng, tiled):
     ms, n = res["kernel_timing"][slot]
     if n == 0:
         return None
-    bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4)
+    bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"])
+    operand_bytes = smoother_operand_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4)
     achieved = bytes_launch / (ms / n * 1e-3) / 1e9
     kernel = smoother_kernel(res["itemsize"], tiled, ng)
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, ng),
            "kernel": f"{kernel} (finest level, one colour)", "bytes_per_launch": bytes_launch,
+           "bytes_rule": "3 words per cell per full sweep (iterate + right-hand side read, iterate written)",
+           "operand_bytes_per_launch": operand_bytes,
+           "operand_GBps": round(operand_bytes / (ms / n * 1e-3) / 1e9, 1),
            "avg_launch_us": round(ms / n * 1e3, 2), "launches": n,
            "note": "launch times from the last timed step, where the Poisson solve runs concurrently on a second stream"}
     ms_a, n_a = res.get("kernel_timing_alone", {}).get(slot, (0.0, 0))

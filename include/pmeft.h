@@ -190,6 +190,51 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,
             void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* Bardeen potentials (eqs. phipsi_mod) from the Newtonian part Psi_N (lap
+ * Psi_N = s delta, the psi of mg_poisson_solve / pm_step) and the scalar
+ * field chi at the parameters' a: Psi = Psi_N + (alpha_B - alpha_M) chi, the
+ * potential the particles feel; Phi = Psi_N + alpha_B chi; and Psi + Phi, the
+ * combination that lensing sees (Sec. 1).  With screening off, chi =
+ * mu_chi Psi_N and these reduce to mu_Psi Psi_N and mu_Phi Psi_N (eq.
+ * linearised).  All arrays ng^3 natural order of dtype; each output nullable
+ * (not all three).  Only enqueues; no workspace. */
+int pm_potentials(const void *psi_n, const void *chi, int ng, pm_dtype dtype, const pm_eft_params *p /* HOST */,
+                  void *psi_out, void *phi_out, void *lens_out, pm_stream_t stream);
+
+/* Multi-step evolution: kick-drift-kick leapfrog of the particles in the
+ * code time of Sec. 3.1, dt~ = da / (a^3 E(a)) (dx/dt~ = v, dv/dt~ = -grad Psi),
+ * from a_start to a_end in nsteps steps uniform in a (log_spacing 0) or in
+ * ln a (1).  pos, vel: 3 x np SoA at a_start (velocities in code units,
+ * synchronous with the positions); on return both are at a_end.  The force
+ * is evaluated nsteps + 1 times, at every a_k (one pm_step each, the model's
+ * coefficients taken at a_k): the kick of evaluation k spans
+ * [a_{k-1/2}, a_{k+1/2}] (clipped to [a_start, a_end]; half steps at the
+ * midpoint of the spacing variable) and its drift [a_k, a_{k+1}].  The first
+ * evaluation uses the guesses of the options; every later one starts both
+ * solves from the previous step's fields (Sec. 3.5.1).  psi, chi: ng^3
+ * (dtype) out, the fields of the last evaluation (in: guesses if GIVEN).
+ * The parameters' a is ignored.  The report (HOST, nullable) sums the
+ * V-cycles.  Returns PM_OK, PM_ENOCONV if some solve stopped at max_vcycles
+ * (the run continues), or the first hard error; PM_EUNSTABLE if nu <= 0 at
+ * some a_k while xi != 0 (checked before anything runs).  Workspace as for
+ * pm_step. */
+typedef struct {
+    int status, steps, force_evaluations, max_scalar_vcycles;
+    long long poisson_vcycles, scalar_vcycles, clamped_cells_last;
+    double max_rel_residual, a_end;
+    float ms_total;
+} pm_evolve_report;
+
+int pm_evolve(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p /* HOST */,
+              double a_start, double a_end, int nsteps, int log_spacing, const pm_mg_opts *poisson_opts /* HOST */,
+              const pm_mg_opts *scalar_opts /* HOST */, void *psi, void *chi, pm_evolve_report *rep /* HOST */,
+              void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* The code-time interval int_{a0}^{a1} da / (a^3 E(a)) of the flat LCDM
+ * background (Sec. 3.1), as pm_evolve uses it for its kicks and drifts; NAN
+ * for invalid arguments.  HOST only. */
+double pm_code_time(double a0, double a1, double omega_m0);
+
 /* Particle sort: reorders the particles (pos, and vel and ids when given)
  * by the cell of their CIC base corner, key (i0 ng + j0) ng + k0 with
  * i0 = floor(x ng - 1/2) mod ng per axis (Sec. 3.6.2's CIC), so that
@@ -293,20 +338,68 @@ size_t ws_unet_workspace_bytes(int ng, int training);
 int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
                     float *yhat_out, void *ws, size_t ws_bytes, pm_stream_t stream);
 
-/* One training step on one sample: forward, MSE loss mean (yhat - t)^2
- * against the target t = lap_h chi / (s mu_chi) - delta of the solved field
- * chi_target (ng^3 FP64, natural order; 7-point Laplacian), backward, and
- * (if lr > 0) an Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias
- * correction with `step` >= 1) on the FP32 params with moment arrays adam_m,
- * adam_v, the gradient scaled by min(1, grad_clip / ||g||_2) when
- * grad_clip > 0 (global-norm clipping).  grad_out (param_count FP32,
- * nullable) receives the unclipped gradients; *loss and *grad_norm (HOST,
- * nullable) the sample's loss and ||g||_2 (either makes the call synchronise
- * the stream).  Gradients are summed in a fixed order (deterministic). */
+/* Forward pass in the training form (spec grown form (4): the network
+ * is trained by the library's own forward and backward kernels): the same
+ * network as ws_unet_forward, but the two decoder layers read explicit
+ * nearest-neighbour upsampled tensors (no polyphase rewrite), the first layer
+ * reads the padded 4-channel input, and every activation the backward pass
+ * reads stays in ws, a training workspace (ws_unet_workspace_bytes(ng, 1)
+ * bytes).  yhat_out: ng^3 FP32, natural order (nullable).  Errors as above. */
+int ws_unet_forward_train(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
+                          float *yhat_out, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* Backward pass (reverse-mode differentiation of the training forward pass):
+ * the gradient of a scalar loss L with respect to every parameter, given
+ * dloss_dyhat = dL/dyhat (ng^3 FP32, natural order).  ws must hold the
+ * activations of the preceding ws_unet_forward_train call with the same
+ * params and ng (nothing in between may have used ws).  grad_out
+ * (ws_unet_param_count FP32, parameter layout above) is overwritten.
+ * Activation gradients are BF16 between layers (rounded after each
+ * convolution's input gradient, each upsampling's and pooling's adjoint);
+ * weight and bias gradients accumulate in FP32 per block and are summed in
+ * block order, so a rerun gives the same bits. */
+int ws_unet_backward(const float *params, const float *dloss_dyhat, int ng, float *grad_out, void *ws,
+                     size_t ws_bytes, pm_stream_t stream);
+
+/* Adam (Kingma & Ba, with bias correction) on FP32 parameters, after optional
+ * global-norm clipping: g <- g min(1, grad_clip / ||g||_2) when grad_clip > 0;
+ * m <- beta1 m + (1 - beta1) g; v <- beta2 v + (1 - beta2) g^2;
+ * params <- params - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step))
+ * + eps).  params, grads, m, v: n FP32 (device; grads is only read); step >= 1
+ * counts the updates so far including this one.  grad_norm (HOST, nullable)
+ * receives ||g||_2 before clipping (the call then synchronises the stream).
+ * ws: ws_adam_workspace_bytes(n) bytes, 256-byte aligned (the norm's partial
+ * sums).  Errors: PM_EINVAL (null pointer, n <= 0 or >= 2^31, step < 1,
+ * lr < 0, beta outside [0, 1), eps <= 0, grad_clip < 0, misaligned ws),
+ * PM_ENOMEM, PM_EHIP. */
+size_t ws_adam_workspace_bytes(long long n);
+int ws_adam_step(float *params, const float *grads, float *m, float *v, long long n, long long step, double lr,
+                 double beta1, double beta2, double eps, double grad_clip, double *grad_norm /* HOST */, void *ws,
+                 size_t ws_bytes, pm_stream_t stream);
+
+/* One training step on one sample, the composition of the three calls above:
+ * ws_unet_forward_train, the MSE loss mean (yhat - t)^2 against the target
+ * t = lap_h chi / (s mu_chi) - delta of the solved field chi_target (ng^3
+ * FP64, natural order; 7-point Laplacian) and its gradient dL/dyhat =
+ * 2 (yhat - t) / ng^3, ws_unet_backward and (if lr > 0) ws_adam_step with
+ * beta1 0.9, beta2 0.999, eps 1e-8 on params with moment arrays adam_m,
+ * adam_v.  grad_out (param_count FP32, nullable) receives the unclipped
+ * gradients; *loss and *grad_norm (HOST, nullable) the sample's loss and
+ * ||g||_2 (either makes the call synchronise the stream). */
 int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, double grad_clip,
                        const double *rho, const double *chi_target, int ng, const pm_eft_params *p /* HOST */,
                        float *grad_out, double *loss /* HOST */, double *grad_norm /* HOST */, void *ws,
                        size_t ws_bytes, pm_stream_t stream);
+
+/* Read-back of an activation tensor that ws_unet_forward_train left in the
+ * training workspace ws (for testing the backward pass on the network's own
+ * BF16 activations): tensor index 0..12 = input (16 channels, the first 4
+ * used), l1a out (16), [upsampled l4b out (32) | l1b out (16)] (48), pool 1
+ * (16), l2a out (32), [upsampled l3b out (64) | l2b out (32)] (96), pool 2
+ * (32), l3a out (64), l3b out (64), l4a out (32), l4b out (32), l5a out (16),
+ * l5b out (16); grid ng, ng/2 or ng/4 per tensor as the network runs it.  out:
+ * (grid^3 x channels) FP32, channels-last natural order. */
+int ws_unet_activation(const void *ws, int ng, int tensor, float *out, pm_stream_t stream);
 
 /* One 3x3x3 periodic convolution on BF16 channels-last tensors with FP32
  * output (for testing the kernels): mode 0 forward out[n^3][cout] =

@@ -80,16 +80,22 @@ def eft_coefficients(omega_m0, alpha_b0, alpha_m0, a, screening=True, alpha_b_do
 
 
 # ---------------------------------------------------------------- growth
-def growth_factor(a_end, omega_m0, alpha_b0=0.0, alpha_m0=0.0, a_start=1e-3, n_steps=20000):
+def growth_factor(a_end, omega_m0, alpha_b0=0.0, alpha_m0=0.0, a_start=1e-3, n_steps=20000, mu_of_a=None,
+                  with_rate=False, screening=True):
     """Growing mode D+(a_end) of eq. delta_mod_a, normalised to D = a at a_start.
 
-    delta'' + (3/a + dlnH/da) delta' - 3/(2a^2) Omega_m(a) (Geff/G) mu_Psi delta = 0,
-    integrated in ln a with classical 4th-order Runge-Kutta on a uniform grid.
+    delta'' + (3/a + dlnH/da) delta' - 3/(2a^2) Omega_m(a) mu(a) delta = 0 with
+    mu = (Geff/G) mu_Psi (Sec. 2.6), integrated in ln a with classical
+    4th-order Runge-Kutta on a uniform grid.  ``mu_of_a`` replaces mu(a) by
+    a given function (used to pin the integrator on closed forms).  With
+    ``with_rate`` the result is (D, dD/dln a).
     """
     def mu_eff(a):
+        if mu_of_a is not None:
+            return mu_of_a(a)
         if alpha_b0 == 0.0 and alpha_m0 == 0.0:
             return 1.0
-        c = eft_coefficients(omega_m0, alpha_b0, alpha_m0, a)
+        c = eft_coefficients(omega_m0, alpha_b0, alpha_m0, a, screening=screening)
         return c["geff"] * c["mu_psi"]
 
     # variables y = (D, dD/dlna); with x = ln a:
@@ -114,6 +120,8 @@ def growth_factor(a_end, omega_m0, alpha_b0=0.0, alpha_m0=0.0, a_start=1e-3, n_s
         k4 = rhs(x + hstep, y + hstep * k3)
         y = y + hstep / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
         x += hstep
+    if with_rate:
+        return float(y[0]), float(y[1])
     return float(y[0])
 
 

@@ -124,35 +124,65 @@ def forward(p, x0, keep=True):
     return y, c
 
 
-def backward(p, c, dy):
-    """Gradients of all parameters for the output gradient dy (n,n,n)."""
+def backward(p, c, dy, rnd=None):
+    """Gradients of all parameters for the output gradient dy (n,n,n).
+
+    ``rnd`` (default: none) is applied to every activation gradient a layer
+    hands to the layer below -- the head's, each convolution's input
+    gradient, each upsampling adjoint and each pooling adjoint plus its skip
+    gradient -- so that a caller can reproduce a narrower storage format of
+    those tensors; the parameter gradients are never rounded."""
+    if rnd is None:
+        rnd = _identity
     g = {}
     g["head.w"] = np.tensordot(c["b5"], dy, axes=([0, 1, 2], [0, 1, 2]))
     g["head.b"] = np.array([dy.sum()])
-    d = dy[..., None] * p["head.w"][None, None, None, :]
+    d = rnd(dy[..., None] * p["head.w"][None, None, None, :])
 
     def back(name, x, out, d):
         d = d * (out > 0)
         dx, g[name + ".w"], g[name + ".b"] = conv3_backward(x, p[name + ".w"], d)
-        return dx
+        return rnd(dx)
 
     d = back("l5b", c["a5"], c["b5"], d)
     d = back("l5a", c["c1"], c["a5"], d)
     d_up1, d_s1 = d[..., :32], d[..., 32:]
-    d = up_backward(d_up1)
+    d = rnd(up_backward(d_up1))
     d = back("l4b", c["a4"], c["b4"], d)
     d = back("l4a", c["c2"], c["a4"], d)
     d_up2, d_s2 = d[..., :64], d[..., 64:]
-    d = up_backward(d_up2)
+    d = rnd(up_backward(d_up2))
     d = back("l3b", c["a3"], c["b3"], d)
     d = back("l3a", c["p2"], c["a3"], d)
-    d = pool_backward(d) + d_s2
+    d = rnd(pool_backward(d) + d_s2)
     d = back("l2b", c["a2"], c["s2"], d)
     d = back("l2a", c["p1"], c["a2"], d)
-    d = pool_backward(d) + d_s1
+    d = rnd(pool_backward(d) + d_s1)
     d = back("l1b", c["a1"], c["s1"], d)
     back("l1a", c["x0"], c["a1"], d)
     return g
+
+
+def _identity(x):
+    return x
+
+
+def adam_step(w, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_clip=0.0):
+    """One step of Adam (Kingma and Ba, "Adam: a method for stochastic
+    optimization", 2015, Algorithm 1), preceded by global-norm clipping of
+    the gradient when grad_clip > 0: g <- g min(1, grad_clip / ||g||_2).
+    ``step`` is t >= 1, the number of the update.  Returns (w, m, v, ||g||_2
+    before clipping) as new arrays."""
+    g = np.asarray(g, dtype=np.float64)
+    gnorm = float(np.sqrt(np.sum(g * g)))
+    if grad_clip > 0.0 and gnorm > grad_clip:
+        g = g * (grad_clip / gnorm)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1**step)
+    v_hat = v / (1.0 - beta2**step)
+    w = np.asarray(w, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return w, m, v, gnorm
 
 
 def input_features(rho, alpha_b0, alpha_m0, a):

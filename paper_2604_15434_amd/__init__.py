@@ -19,7 +19,7 @@ __all__ = [
     "mg_scalar_solve_batched", "pm_autotune", "pm_deposit", "pm_eft_coefficients", "pm_get_launch_shape",
     "pm_set_launch_shape", "pm_sort_particles", "pm_tune_load", "pm_tune_save",
     "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
-    "pm_strerror", "pm_workspace_bytes",
+    "pm_strerror", "pm_workspace_bytes", "pm_potentials", "pm_evolve", "pm_code_time",
 ]
 
 
@@ -330,3 +330,46 @@ def pm_step(pos, vel, ng, params, poisson_opts, scalar_opts, dt_kick, dt_drift, 
         raise PmError(rc, "pm_step")
     return dict(poisson=_report(rep.poisson), scalar=_report(rep.scalar), ms_deposit=rep.ms_deposit,
                 ms_force=rep.ms_force, ms_total=rep.ms_total, status=rc)
+
+
+def pm_potentials(psi_n, chi, params, psi_out=None, phi_out=None, lens_out=None, stream=None):
+    """Psi = Psi_N + xi chi, Phi = Psi_N + alpha_B chi and Psi + Phi (each
+    output optional) from Psi_N and chi."""
+    dt = _dtype_code(psi_n)
+    ng = psi_n.shape[0]
+    _check(psi_n, (ng, ng, ng), dt, "psi_n")
+    _check(chi, (ng, ng, ng), dt, "chi")
+    for t, nm in ((psi_out, "psi_out"), (phi_out, "phi_out"), (lens_out, "lens_out")):
+        if t is not None:
+            _check(t, (ng, ng, ng), dt, nm)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else 0)  # noqa: E731
+    rc = L.lib().pm_potentials(ptr(psi_n), ptr(chi), int(ng), dt, ctypes.byref(_params(params)), ptr(psi_out),
+                               ptr(phi_out), ptr(lens_out), _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_potentials")
+
+
+def pm_code_time(a0, a1, omega_m0):
+    """int_{a0}^{a1} da / (a^3 E(a)) (the code time of a kick or drift)."""
+    return float(L.lib().pm_code_time(float(a0), float(a1), float(omega_m0)))
+
+
+def pm_evolve(pos, vel, ng, params, a_start, a_end, nsteps, poisson_opts, scalar_opts, psi, chi, log_spacing=False,
+              ws=None, stream=None):
+    """Kick-drift-kick evolution from a_start to a_end (see pmeft.h)."""
+    dt = _dtype_code(pos)
+    npart = pos.shape[1]
+    _check(pos, (3, npart), dt, "pos")
+    _check(vel, (3, npart), dt, "vel")
+    _check(psi, (ng, ng, ng), dt, "psi")
+    _check(chi, (ng, ng, ng), dt, "chi")
+    ws = _ws(ws, ng, npart, dt)
+    rep = L.EvolveReport()
+    rc = L.lib().pm_evolve(ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()), npart, int(ng), dt,
+                           ctypes.byref(_params(params)), float(a_start), float(a_end), int(nsteps),
+                           int(bool(log_spacing)), ctypes.byref(poisson_opts.c(ng)), ctypes.byref(scalar_opts.c(ng)),
+                           ctypes.c_void_p(psi.data_ptr()), ctypes.c_void_p(chi.data_ptr()), ctypes.byref(rep),
+                           ws.ptr, ws.nbytes, _stream(stream))
+    if rc not in (L.PM_OK, L.PM_ENOCONV):
+        raise PmError(rc, "pm_evolve")
+    return {n: getattr(rep, n) for n, _ in L.EvolveReport._fields_}

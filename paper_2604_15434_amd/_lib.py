@@ -52,11 +52,19 @@ class StepReport(ctypes.Structure):
                 ("ms_force", ctypes.c_float), ("ms_total", ctypes.c_float)]
 
 
+class EvolveReport(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("steps", ctypes.c_int), ("force_evaluations", ctypes.c_int),
+                ("max_scalar_vcycles", ctypes.c_int), ("poisson_vcycles", ctypes.c_longlong),
+                ("scalar_vcycles", ctypes.c_longlong), ("clamped_cells_last", ctypes.c_longlong),
+                ("max_rel_residual", ctypes.c_double), ("a_end", ctypes.c_double), ("ms_total", ctypes.c_float)]
+
+
 EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_deposit", "mg_poisson_solve",
            "mg_scalar_solve", "pm_force_interp", "pm_step", "pm_kernel_timing_enable", "pm_kernel_timing_read",
            "pm_strerror", "pm_sort_workspace_bytes", "pm_sort_particles", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
            "pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
-           "ws_conv3", "ws_conv3_first")
+           "ws_unet_forward_train", "ws_unet_backward", "ws_adam_workspace_bytes", "ws_adam_step",
+           "ws_unet_activation", "ws_conv3", "ws_conv3_first", "pm_potentials", "pm_evolve", "pm_code_time")
 
 
 def _load():
@@ -99,10 +107,24 @@ def _load():
     lib.ws_unet_workspace_bytes.restype = sz
     lib.ws_unet_forward.argtypes = [vp, vp, i, P(EftParams), vp, vp, sz, vp]
     lib.ws_unet_train_step.argtypes = [vp, vp, vp, ll, d, d, vp, vp, i, P(EftParams), vp, P(d), P(d), vp, sz, vp]
+    lib.ws_unet_forward_train.argtypes = [vp, vp, i, P(EftParams), vp, vp, sz, vp]
+    lib.ws_unet_backward.argtypes = [vp, vp, i, vp, vp, sz, vp]
+    lib.ws_adam_workspace_bytes.argtypes = [ll]
+    lib.ws_adam_workspace_bytes.restype = sz
+    lib.ws_adam_step.argtypes = [vp, vp, vp, vp, ll, ll, d, d, d, d, d, P(d), vp, sz, vp]
+    lib.ws_unet_activation.argtypes = [vp, i, i, vp, vp]
     lib.ws_conv3.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.ws_conv3_first.argtypes = [i, vp, vp, vp, P(ctypes.c_float), vp, vp]
-    for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3", "ws_conv3_first"):
+    for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3", "ws_conv3_first", "ws_unet_forward_train",
+                 "ws_unet_backward", "ws_adam_step", "ws_unet_activation"):
         getattr(lib, name).restype = i
+    lib.pm_potentials.argtypes = [vp, vp, i, i, P(EftParams), vp, vp, vp, vp]
+    lib.pm_potentials.restype = i
+    lib.pm_evolve.argtypes = [vp, vp, ll, i, i, P(EftParams), d, d, i, i, P(MgOpts), P(MgOpts), vp, vp,
+                              P(EvolveReport), vp, sz, vp]
+    lib.pm_evolve.restype = i
+    lib.pm_code_time.argtypes = [d, d, d]
+    lib.pm_code_time.restype = d
     lib.pm_strerror.argtypes = [i]
     lib.pm_strerror.restype = ctypes.c_char_p
     for name in ("pm_eft_coefficients", "pm_grid_levels", "pm_deposit", "mg_poisson_solve", "mg_scalar_solve",

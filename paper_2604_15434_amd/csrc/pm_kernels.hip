@@ -456,6 +456,39 @@ void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long lon
                            (float *)pos, (unsigned)np, (float *)vel, dt_kick, dt_drift, (float *)acc_out, sp);
 }
 
+// Bardeen potentials from Psi_N and chi (natural order, same dtype):
+// Psi = Psi_N + c_psi chi, Phi = Psi_N + c_phi chi, Psi + Phi; each output
+// nullable.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_potentials(const T *__restrict__ psi_n, const T *__restrict__ chi,
+                                                       double c_psi, double c_phi, T *__restrict__ psi,
+                                                       T *__restrict__ phi, T *__restrict__ lens, Span sp)
+{
+    PM_SPAN_LOOP(e, sp)
+    {
+        const double pn = (double)psi_n[e], x = (double)chi[e];
+        const double a = pn + c_psi * x, b = pn + c_phi * x;
+        if (psi)
+            psi[e] = (T)a;
+        if (phi)
+            phi[e] = (T)b;
+        if (lens)
+            lens[e] = (T)(a + b);
+    }
+}
+
+void launch_potentials(const void *psi_n, const void *chi, pm_dtype dt, long long n3, double c_psi, double c_phi,
+                       void *psi, void *phi, void *lens, hipStream_t st)
+{
+    const Span sp = make_span(n3);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_potentials<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)psi_n,
+                           (const double *)chi, c_psi, c_phi, (double *)psi, (double *)phi, (double *)lens, sp);
+    else
+        hipLaunchKernelGGL((k_potentials<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)psi_n,
+                           (const float *)chi, c_psi, c_phi, (float *)psi, (float *)phi, (float *)lens, sp);
+}
+
 // ------------------------------------------------------------ particle sort
 // Stable LSD radix sort of the particles by the cell of their CIC base
 // corner, key = (i0 ng + j0) ng + k0 (particles with unusable coordinates

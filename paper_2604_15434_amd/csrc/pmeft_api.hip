@@ -1515,7 +1515,29 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
     SolveOut sp, sx;
     float ms_p = 0.0f, ms_x = 0.0f;
-    e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
+    if (cf.K == 0.0) {
+        // Linearised option (screening off) or no scalar field: chi obeys
+        // nu lap chi = xi s delta with the same 7-point Laplacian as Psi_N,
+        // so chi = mu_chi Psi_N exactly and the step costs one Poisson solve
+        // (eq. linearised; Psi_N + xi chi = mu_Psi Psi_N).  The scalar report
+        // takes the Poisson solve's residual, which the scaling leaves
+        // unchanged, with no V-cycles of its own.
+        Timer tp(C.st);
+        e = poisson_core(C, cf, *poisson_opts, sp, dsq);
+        if (e)
+            return e;
+        ms_p = tp.stop();
+        launch_scale(ps, ch, cf.mu_chi, C.P.N, C.st);
+        launch_field_sum(ps, C.P.N, C.rs, C.st);
+        launch_packed_to_natural(ps, psi, dtype, ng, 0.0, C.rs.out, C.st);
+        sx = sp;
+        sx.vcycles = 0;
+        for (int i = 0; i < 64; i++)
+            sx.hist[i] = i == 0 ? sp.rel : 0.0;
+        e = launched();
+    } else {
+        e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
+    }
     if (e) {
         wait_network();  // (solve_both waits itself once its worker has started)
         return e;
@@ -1542,6 +1564,148 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     if (sp.status)
         return sp.status;
     return sx.status;
+}
+
+int pm_potentials(const void *psi_n, const void *chi, int ng, pm_dtype dtype, const pm_eft_params *p, void *psi_out,
+                  void *phi_out, void *lens_out, pm_stream_t stream)
+{
+    if (!psi_n || !chi || !p || ng < 1 || ng > 1024 || (dtype != PM_F32 && dtype != PM_F64) ||
+        (!psi_out && !phi_out && !lens_out))
+        return PM_EINVAL;
+    pm_eft_coeffs cf;
+    const int e = coefficients(*p, cf);
+    if (e == PM_EINVAL)
+        return e;
+    launch_potentials(psi_n, chi, dtype, (long long)ng * ng * ng, cf.xi, cf.alpha_b, psi_out, phi_out, lens_out,
+                      (hipStream_t)stream);
+    return launched();
+}
+
+// Time variable of the equations of motion in code units (Sec. 3.1):
+// dt~ = H0 dt / a^2 = da / (a^3 E(a)), E^2 = Omega_m0 a^-3 + 1 - Omega_m0.
+// Integral over [a0, a1] by composite 8-point Gauss-Legendre quadrature on
+// 32 panels; the nodes come from Newton's method on the Legendre polynomial
+// P_8 (three-term recurrence), started from the asymptotic estimate
+// cos(pi (i - 1/4) / (n + 1/2)).
+static void gauss_legendre8(double x[8], double w[8])
+{
+    const int n = 8;
+    for (int i = 1; i <= n; i++) {
+        double z = cos(M_PI * (i - 0.25) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16)
+                break;
+        }
+        x[i - 1] = z;
+        w[i - 1] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+static double code_time(double a0, double a1, double om0)
+{
+    double x[8], w[8];
+    gauss_legendre8(x, w);
+    const int panels = 32;
+    const double hpan = (a1 - a0) / panels;
+    double sum = 0.0;
+    for (int q = 0; q < panels; q++) {
+        const double lo = a0 + q * hpan, mid = lo + 0.5 * hpan;
+        for (int i = 0; i < 8; i++) {
+            const double a = mid + 0.5 * hpan * x[i];
+            const double E = sqrt(om0 / (a * a * a) + 1.0 - om0);
+            sum += 0.5 * hpan * w[i] / (a * a * a * E);
+        }
+    }
+    return sum;
+}
+
+int pm_evolve(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p, double a_start,
+              double a_end, int nsteps, int log_spacing, const pm_mg_opts *poisson_opts, const pm_mg_opts *scalar_opts,
+              void *psi, void *chi, pm_evolve_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!p || !poisson_opts || !scalar_opts || nsteps < 1 || nsteps > 100000 || !(a_start > 0.0) ||
+        !(a_end > a_start) || !opts_ok(poisson_opts) || !opts_ok(scalar_opts))
+        return PM_EINVAL;
+    pm_eft_params q = *p;
+    // the whole interval must be a valid model (nu > 0 where xi != 0)
+    for (int k = 0; k <= nsteps; k++) {
+        pm_eft_coeffs cf;
+        q.a = log_spacing ? a_start * pow(a_end / a_start, (double)k / nsteps)
+                          : a_start + (a_end - a_start) * k / nsteps;
+        const int e = coefficients(q, cf);
+        if (e)
+            return e;
+    }
+    auto a_at = [&](double k) {  // k may be half-integer
+        return log_spacing ? a_start * pow(a_end / a_start, k / nsteps) : a_start + (a_end - a_start) * k / nsteps;
+    };
+    if (rep)
+        memset(rep, 0, sizeof(*rep));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    PM_HIP(hipEventCreate(&t0));
+    PM_HIP(hipEventCreate(&t1));
+    (void)hipEventRecord(t0, (hipStream_t)stream);
+    int status = PM_OK;
+    pm_mg_opts po = *poisson_opts, so = *scalar_opts;
+    for (int k = 0; k <= nsteps; k++) {
+        // kick from a_{k-1/2} (a_0 at the start) to a_{k+1/2} (a_N at the end),
+        // then drift from a_k to a_{k+1} (none after the last force)
+        const double ak = a_at(k);
+        const double kick_lo = k == 0 ? ak : a_at(k - 0.5), kick_hi = k == nsteps ? ak : a_at(k + 0.5);
+        const double dk = code_time(kick_lo, kick_hi, p->omega_m0);
+        const double dd = k == nsteps ? 0.0 : code_time(ak, a_at(k + 1), p->omega_m0);
+        q.a = ak;
+        pm_step_report sr;
+        const int e = pm_step(pos, vel, np, ng, dtype, &q, &po, &so, dk, dd, psi, chi, &sr, ws, ws_bytes, stream);
+        if (e && e != PM_ENOCONV) {
+            (void)hipEventDestroy(t0);
+            (void)hipEventDestroy(t1);
+            return e;
+        }
+        if (e)
+            status = e;
+        if (rep) {
+            rep->force_evaluations++;
+            rep->poisson_vcycles += sr.poisson.vcycles;
+            rep->scalar_vcycles += sr.scalar.vcycles;
+            rep->max_scalar_vcycles = std::max(rep->max_scalar_vcycles, sr.scalar.vcycles);
+            rep->max_rel_residual = std::max(rep->max_rel_residual, std::max(sr.poisson.rel_residual,
+                                                                             sr.scalar.rel_residual));
+            rep->clamped_cells_last = sr.scalar.clamped_cells;
+        }
+        // the next step starts from this step's fields (Sec. 3.5.1)
+        po.guess = PM_GUESS_GIVEN;
+        so.guess = PM_GUESS_GIVEN;
+    }
+    float ms = 0.f;
+    (void)hipEventRecord(t1, (hipStream_t)stream);
+    (void)hipEventSynchronize(t1);
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rep) {
+        rep->steps = nsteps;
+        rep->a_end = a_at(nsteps);
+        rep->ms_total = ms;
+        rep->status = status;
+    }
+    return status;
+}
+
+double pm_code_time(double a0, double a1, double omega_m0)
+{
+    if (!(a0 > 0.0) || !(a1 > 0.0) || !(omega_m0 > 0.0 && omega_m0 <= 1.0))
+        return NAN;
+    return code_time(a0, a1, omega_m0);
 }
 
 int pm_kernel_timing_enable(int on)

@@ -304,5 +304,9 @@ void launch_gradient(const double *psi, const double *chi, double xi, int ng, vo
                      hipStream_t st);
 void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long long np, void *vel,
                         double dt_kick, double dt_drift, void *acc_out, hipStream_t st);
+// Psi = Psi_N + c_psi chi, Phi = Psi_N + c_phi chi, Psi + Phi (natural order;
+// outputs nullable)
+void launch_potentials(const void *psi_n, const void *chi, pm_dtype dt, long long n3, double c_psi, double c_phi,
+                       void *psi, void *phi, void *lens, hipStream_t st);
 
 }  // namespace pmeft

@@ -33,7 +33,9 @@ void launch_source_target(const double *chi, const double *delta_packed, int n, 
 void launch_add_source(const float *yhat, int n, double *delta_packed, ReduceSlot rs, hipStream_t st);
 void launch_head(const uint16_t *b5, const float *hw, const float *hb, unsigned nvox, float *yhat, hipStream_t st);
 void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5, const float *hw, unsigned nvox,
-                          uint16_t *db5, float *ghw, float *ghb, float *loss, hipStream_t st);
+                          uint16_t *db5, float *ghw, float *ghb, float *loss, float *part, hipStream_t st);
+size_t head_partial_floats();
+void launch_bf16_slice_to_f32(const uint16_t *s, int stride, int off, int C, float *d, size_t nvox, hipStream_t st);
 void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
                       hipStream_t st);
 void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
@@ -150,7 +152,7 @@ bool net_plan(NetPlan &P, int n, bool training)
         P.target = take(c, sizeof(float) * n3);
         P.pgrad = take(c, sizeof(float) * param_layout().total);
         P.loss = take(c, 256);
-        size_t wmax = 0;
+        size_t wmax = head_partial_floats();
         for (int l = 0; l < 10; l++) {
             const size_t f = wgrad_partial_floats(kConv[l].cin, kConv[l].cout);
             wmax = wmax > f ? wmax : f;
@@ -296,16 +298,23 @@ void mask(Net &N, int tg, int goff, int ta, int aoff, int C)
     launch_relu_bwd(N.grad(tg), kTChan[tg], goff, N.act(ta), kTChan[ta], aoff, C, N.nvox(ta), N.st);
 }
 
-void backward(Net &N, const float *params)
+// Gradients of every parameter into the workspace's pgrad.  dy: dL/dyhat
+// (ng^3 FP32, natural order); null: the MSE loss against the workspace's
+// target t, whose mean goes to the workspace's loss slot.  Every gradient is
+// written, not accumulated, in a fixed order.
+void backward(Net &N, const float *params, const float *dy)
 {
     const int n = N.P.n;
     const unsigned nv = (unsigned)n * n * n;
     const ParamLayout L = param_layout();
     float *pg = (float *)(N.ws + N.P.pgrad);
-    launch_zero(pg, sizeof(float) * L.total, N.st);
-    launch_zero(N.ws + N.P.loss, 256, N.st);
-    launch_head_loss_bwd((const float *)(N.ws + N.P.yhat), (const float *)(N.ws + N.P.target), N.act(B5),
-                         params + L.hw, nv, N.grad(B5), pg + L.hw, pg + L.hb, (float *)(N.ws + N.P.loss), N.st);
+    if (dy)
+        launch_head_loss_bwd(dy, nullptr, N.act(B5), params + L.hw, nv, N.grad(B5), pg + L.hw, pg + L.hb, nullptr,
+                             (float *)(N.ws + N.P.wg_part), N.st);
+    else
+        launch_head_loss_bwd((const float *)(N.ws + N.P.yhat), (const float *)(N.ws + N.P.target), N.act(B5),
+                             params + L.hw, nv, N.grad(B5), pg + L.hw, pg + L.hb, (float *)(N.ws + N.P.loss),
+                             (float *)(N.ws + N.P.wg_part), N.st);
     conv_bwd(N, 9, A5, 0, B5, 0, A5, 0);
     mask(N, A5, 0, A5, 0, 16);
     conv_bwd(N, 8, C1, 0, A5, 0, C1, 0);
@@ -455,6 +464,87 @@ int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft
     return launched();
 }
 
+int ws_unet_forward_train(const float *params, const double *rho, int ng, const pm_eft_params *p, float *yhat_out,
+                          void *ws, size_t ws_bytes, pm_stream_t stream)
+{
+    if (!params || !rho || !p)
+        return PM_EINVAL;
+    Net N;
+    int e = setup(N, ng, true, ws, ws_bytes, stream);
+    if (e)
+        return e;
+    const double *d = prepare_input(N, rho);
+    pack_all(N, params);
+    forward(N, params, d, *p);
+    const unsigned nv = (unsigned)ng * ng * ng;
+    if (yhat_out &&
+        hipMemcpyAsync(yhat_out, N.ws + N.P.yhat, sizeof(float) * nv, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
+        return PM_EHIP;
+    return launched();
+}
+
+int ws_unet_backward(const float *params, const float *dloss_dyhat, int ng, float *grad_out, void *ws,
+                     size_t ws_bytes, pm_stream_t stream)
+{
+    if (!params || !dloss_dyhat || !grad_out)
+        return PM_EINVAL;
+    Net N;
+    int e = setup(N, ng, true, ws, ws_bytes, stream);
+    if (e)
+        return e;
+    backward(N, params, dloss_dyhat);
+    const long long np = param_layout().total;
+    if (hipMemcpyAsync(grad_out, N.ws + N.P.pgrad, sizeof(float) * np, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
+        return PM_EHIP;
+    return launched();
+}
+
+size_t ws_adam_workspace_bytes(long long n)
+{
+    (void)n;
+    return sizeof(double) * 8 * kMaxBlocks + 256 + 256;
+}
+
+namespace {
+int adam_impl(float *params, const float *grads, float *m, float *v, long long n, long long step, double lr,
+              double b1, double b2, double eps, double grad_clip, ReduceSlot rs, hipStream_t st)
+{
+    launch_sumsq(grads, n, rs, st);
+    const float c1 = (float)(1.0 - pow(b1, (double)step)), c2 = (float)(1.0 - pow(b2, (double)step));
+    launch_adam(params, grads, m, v, n, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, rs.out, (float)grad_clip,
+                st);
+    return launched();
+}
+}  // namespace
+
+int ws_adam_step(float *params, const float *grads, float *m, float *v, long long n, long long step, double lr,
+                 double beta1, double beta2, double eps, double grad_clip, double *grad_norm, void *ws,
+                 size_t ws_bytes, pm_stream_t stream)
+{
+    if (!params || !grads || !m || !v || n <= 0 || n > (1LL << 31) - 1 || step < 1 || !(lr >= 0.0) ||
+        !(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0) || !(grad_clip >= 0.0) ||
+        !ws || ((uintptr_t)ws & 255))
+        return PM_EINVAL;
+    if (ws_bytes < ws_adam_workspace_bytes(n))
+        return PM_ENOMEM;
+    ReduceSlot rs;
+    rs.partials = (double *)ws;
+    rs.counter = nullptr;
+    rs.out = (double *)((char *)ws + sizeof(double) * 8 * kMaxBlocks);
+    hipStream_t st = (hipStream_t)stream;
+    int e = adam_impl(params, grads, m, v, n, step, lr, beta1, beta2, eps, grad_clip, rs, st);
+    if (e)
+        return e;
+    if (grad_norm) {
+        double g2 = 0.0;
+        if (hipMemcpyAsync(&g2, rs.out, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return PM_EHIP;
+        *grad_norm = sqrt(g2);
+    }
+    return PM_OK;
+}
+
 int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long step, double lr, double grad_clip,
                        const double *rho, const double *chi_target, int ng, const pm_eft_params *p, float *grad_out,
                        double *loss, double *grad_norm, void *ws, size_t ws_bytes, pm_stream_t stream)
@@ -472,17 +562,17 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
     launch_source_target(chi_target, d, ng, 1.0 / sc, (float *)(N.ws + N.P.target), N.st);
     pack_all(N, params);
     forward(N, params, d, *p);
-    backward(N, params);
+    backward(N, params, nullptr);
     const long long np = param_layout().total;
     const float *pg = (const float *)(N.ws + N.P.pgrad);
     if (grad_out && hipMemcpyAsync(grad_out, pg, sizeof(float) * np, hipMemcpyDeviceToDevice, N.st) != hipSuccess)
         return PM_EHIP;
-    launch_sumsq(pg, np, N.rs, N.st);
     if (lr > 0.0) {
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-        launch_adam(params, pg, adam_m, adam_v, np, (float)lr, b1, b2, 1e-8f, c1, c2, N.rs.out, (float)grad_clip,
-                    N.st);
+        e = adam_impl(params, pg, adam_m, adam_v, np, step, lr, 0.9, 0.999, 1e-8, grad_clip, N.rs, N.st);
+        if (e)
+            return e;
+    } else {
+        launch_sumsq(pg, np, N.rs, N.st);
     }
     if (loss || grad_norm) {
         float l = 0.f;
@@ -496,6 +586,17 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
         if (grad_norm)
             *grad_norm = sqrt(g2);
     }
+    return launched();
+}
+
+int ws_unet_activation(const void *ws, int ng, int tensor, float *out, pm_stream_t stream)
+{
+    NetPlan P;
+    if (!ws || !out || tensor < 0 || tensor >= NT || !net_plan(P, ng, true))
+        return PM_EINVAL;
+    const size_t m = (size_t)(ng >> kTLevel[tensor]);
+    launch_bf16_slice_to_f32((const uint16_t *)((const char *)ws + P.act[tensor]), kTChan[tensor], 0, kTChan[tensor],
+                             out, m * m * m, (hipStream_t)stream);
     return launched();
 }
 

@@ -1516,13 +1516,16 @@ void launch_head(const uint16_t *b5, const float *hw, const float *hb, unsigned 
     hipLaunchKernelGGL(k_head, dim3(2048), dim3(256), 0, st, b5, hw, hb, nvox, yhat);
 }
 
-// MSE loss L = mean (yhat - y)^2: dyhat = 2 (yhat - y) / N; db5 = dyhat hw
-// (masked by b5 > 0); grads of hw, hb and the loss accumulated with atomics.
+// Backward of the output head yhat = hb + sum_c hw[c] b5[c].  With y given:
+// MSE loss L = mean (yhat - y)^2 and dyhat = 2 (yhat - y) / N; with y null,
+// `yhat` already holds dL/dyhat.  db5 = dyhat hw (masked by b5 > 0, the ReLU
+// of the layer below), rounded to BF16.  Each block writes its partial sums
+// of the head's 17 gradients and of the loss to part[block * 18 + q]; the
+// one-block k_head_finalize adds them in block order (deterministic).
 __global__ __launch_bounds__(256) void k_head_loss_bwd(const float *__restrict__ yhat, const float *__restrict__ y,
                                                        const uint16_t *__restrict__ b5, const float *__restrict__ hw,
                                                        unsigned nvox, uint16_t *__restrict__ db5,
-                                                       float *__restrict__ ghw, float *__restrict__ ghb,
-                                                       float *__restrict__ loss)
+                                                       float *__restrict__ part)
 {
     __shared__ float sm[18][4];
     float gw[16], gb = 0.f, ls = 0.f;
@@ -1530,9 +1533,14 @@ __global__ __launch_bounds__(256) void k_head_loss_bwd(const float *__restrict__
         gw[c] = 0.f;
     const float sc = 2.0f / (float)nvox;
     for (unsigned v = blockIdx.x * 256 + threadIdx.x; v < nvox; v += gridDim.x * 256) {
-        const float d = yhat[v] - y[v];
-        ls += d * d;
-        const float g = sc * d;
+        float g;
+        if (y) {
+            const float d = yhat[v] - y[v];
+            ls += d * d;
+            g = sc * d;
+        } else {
+            g = yhat[v];
+        }
         gb += g;
         const uint16_t *h = b5 + (size_t)v * 16;
         uint16_t *dh = db5 + (size_t)v * 16;
@@ -1551,24 +1559,41 @@ __global__ __launch_bounds__(256) void k_head_loss_bwd(const float *__restrict__
             sm[q][wid] = x;
     }
     __syncthreads();
-    if (threadIdx.x < 18) {
-        const float t = sm[threadIdx.x][0] + sm[threadIdx.x][1] + sm[threadIdx.x][2] + sm[threadIdx.x][3];
-        if (threadIdx.x < 16)
-            atomicAdd(&ghw[threadIdx.x], t);
-        else if (threadIdx.x == 16)
-            atomicAdd(ghb, t);
-        else
-            atomicAdd(loss, t / (float)nvox);
-    }
+    if (threadIdx.x < 18)
+        part[(size_t)blockIdx.x * 18 + threadIdx.x] =
+            sm[threadIdx.x][0] + sm[threadIdx.x][1] + sm[threadIdx.x][2] + sm[threadIdx.x][3];
 }
 
+// ghw[16], ghb[1] (overwritten) and, when loss is not null, the mean loss.
+__global__ __launch_bounds__(64) void k_head_finalize(const float *__restrict__ part, unsigned nb,
+                                                      float *__restrict__ ghw, float *__restrict__ ghb,
+                                                      float *__restrict__ loss, unsigned nvox)
+{
+    const int q = threadIdx.x;
+    if (q >= 18)
+        return;
+    float t = 0.f;
+    for (unsigned b = 0; b < nb; b++)
+        t += part[(size_t)b * 18 + q];
+    if (q < 16)
+        ghw[q] = t;
+    else if (q == 16)
+        ghb[0] = t;
+    else if (loss)
+        loss[0] = t / (float)nvox;
+}
+
+size_t head_partial_floats() { return 1024 * 18; }
+
 void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5, const float *hw, unsigned nvox,
-                          uint16_t *db5, float *ghw, float *ghb, float *loss, hipStream_t st)
+                          uint16_t *db5, float *ghw, float *ghb, float *loss, float *part, hipStream_t st)
 {
     unsigned nb = (nvox + 255) / 256;
     if (nb > 1024)
         nb = 1024;
-    hipLaunchKernelGGL(k_head_loss_bwd, dim3(nb), dim3(256), 0, st, yhat, y, b5, hw, nvox, db5, ghw, ghb, loss);
+    hipLaunchKernelGGL(k_head_loss_bwd, dim3(nb), dim3(256), 0, st, yhat, y, b5, hw, nvox, db5, part);
+    hipLaunchKernelGGL(k_head_finalize, dim3(1), dim3(64), 0, st, (const float *)part, nb, ghw, ghb, y ? loss : nullptr,
+                       nvox);
 }
 
 // ---------------------------------------------------------------- parameters
@@ -1637,6 +1662,21 @@ void launch_adam(float *w, const float *g, float *m, float *v, long long n, floa
 }
 
 // bf16 <-> f32 helpers for tests and the output path
+__global__ __launch_bounds__(256) void k_bf16_slice_to_f32(const uint16_t *__restrict__ s, int stride, int off, int C,
+                                                           float *__restrict__ d, size_t nvox)
+{
+    const size_t total = nvox * (size_t)C;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+        const size_t v = e / C;
+        d[e] = bf2f(s[v * stride + off + (e - v * C)]);
+    }
+}
+
+void launch_bf16_slice_to_f32(const uint16_t *s, int stride, int off, int C, float *d, size_t nvox, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bf16_slice_to_f32, dim3(1024), dim3(256), 0, st, s, stride, off, C, d, nvox);
+}
+
 __global__ __launch_bounds__(256) void k_f32_to_bf16(const float *__restrict__ s, uint16_t *__restrict__ d, size_t n)
 {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)

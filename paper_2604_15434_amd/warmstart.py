@@ -111,6 +111,40 @@ class WarmStart:
             return loss.value, gn.value
         return loss.value if want_loss else None
 
+    def forward_train(self, rho, params, yhat_out=None, stream=None):
+        """Training-form forward pass; keeps the activations in the training
+        workspace for backward()."""
+        ng = rho.shape[0]
+        ws = self._workspace(ng, True)
+        rc = L.lib().ws_unet_forward_train(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(rho.data_ptr()),
+                                           int(ng), ctypes.byref(_params(params)),
+                                           ctypes.c_void_p(yhat_out.data_ptr() if yhat_out is not None else 0),
+                                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_forward_train")
+        return yhat_out
+
+    def backward(self, dloss_dyhat, ng, grad_out, stream=None):
+        """Parameter gradients for dL/dyhat, from the activations of the last
+        forward_train at this grid."""
+        ws = self._workspace(ng, True)
+        rc = L.lib().ws_unet_backward(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(dloss_dyhat.data_ptr()),
+                                      int(ng), ctypes.c_void_p(grad_out.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      ws.numel(), _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_backward")
+        return grad_out
+
+    def activation(self, ng, tensor, out, stream=None):
+        """FP32 copy of activation tensor `tensor` (0..12) of the last
+        forward_train at this grid."""
+        ws = self._workspace(ng, True)
+        rc = L.lib().ws_unet_activation(ctypes.c_void_p(ws.data_ptr()), int(ng), int(tensor),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_activation")
+        return out
+
     def save(self, path, meta=None):
         flat = self.params.detach().cpu().numpy().astype("<f4")
         with open(path, "wb") as f:
@@ -127,6 +161,27 @@ class WarmStart:
         ws = cls(params=flat, device=device)
         ws.step = int(meta.get("step", 0))
         return ws
+
+
+def adam_step(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_clip=0.0, want_norm=False,
+              stream=None):
+    """ws_adam_step on FP32 device tensors (updated in place).  Returns the
+    gradient norm with want_norm (the call then synchronises), else None."""
+    import torch
+
+    n = params.numel()
+    for t in (grads, m, v):
+        assert t.dtype == torch.float32 and t.numel() == n and t.is_contiguous()
+    ws = torch.empty(int(L.lib().ws_adam_workspace_bytes(n)), dtype=torch.uint8, device=params.device)
+    gn = ctypes.c_double(0.0)
+    rc = L.lib().ws_adam_step(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grads.data_ptr()),
+                              ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(n), int(step),
+                              float(lr), float(beta1), float(beta2), float(eps), float(grad_clip),
+                              ctypes.byref(gn) if want_norm else None, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream(stream))
+    if rc:
+        raise PmError(rc, "ws_adam_step")
+    return gn.value if want_norm else None
 
 
 DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet_warmstart.f32")

@@ -1,12 +1,14 @@
 """The C ABI library: every function declared in include/pmeft.h is exported,
 and the host-only entry points behave (no GPU needed)."""
 import ctypes
+import math
 import os
 import re
 
 import pytest
 
 import oracle
+from paper_2604_15434_amd import _lib
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pmeft.h")
@@ -162,3 +164,40 @@ def test_first_layer_test_entry_rejects_bad_arguments(lib):
     assert f(64, None, fake, fake, xp, fake, None) == einval    # no feature
     assert f(64, fake, fake, fake, None, fake, None) == einval  # no broadcast values
     assert f(64, fake, fake, fake, xp, None, None) == einval    # no output
+
+
+def test_code_time_matches_oracle_quadrature(lib):
+    """The library's kick/drift time integral (host Gauss-Legendre) against
+    the oracle's adaptive quadrature of da / (a^3 E(a))."""
+    from oracle.evolve import code_time
+
+    lib_ = _lib.lib()
+    for a0, a1, om in ((0.2, 1.0, 0.3071), (0.33, 0.3467, 0.3071), (0.05, 0.5, 0.257), (0.5, 1.0, 1.0)):
+        assert lib_.pm_code_time(a0, a1, om) == pytest.approx(code_time(a0, a1, om), rel=1e-12)
+    assert math.isnan(lib_.pm_code_time(-1.0, 1.0, 0.3))
+
+
+def test_evolve_and_adam_reject_bad_arguments_before_any_gpu_work(lib):
+    """Host-side argument checks (no device pointer is touched)."""
+    lib_ = _lib.lib()
+    prm = _lib.EftParams(0.3071, -0.4, 0.0, 1.0, 1, 1)
+    o = _lib.MgOpts(1e-7, 10, 1, 2, 0, 0)
+    vp = ctypes.c_void_p
+    args = lambda a0, a1, n, p=prm: (vp(16), vp(16), 8, 16, 1, ctypes.byref(p), a0, a1, n, 0, ctypes.byref(o),  # noqa: E731
+                                     ctypes.byref(o), vp(16), vp(16), None, vp(256), 1 << 20, None)
+    assert lib_.pm_evolve(*args(0.5, 1.0, 0)) == _lib.PM_EINVAL
+    assert lib_.pm_evolve(*args(1.0, 0.5, 4)) == _lib.PM_EINVAL
+    assert lib_.pm_evolve(*args(0.0, 1.0, 4)) == _lib.PM_EINVAL
+    unstable = _lib.EftParams(0.3071, 0.5, 0.0, 1.0, 1, 1)  # nu < 0 with xi != 0
+    assert lib_.pm_evolve(*args(0.5, 1.0, 4, unstable)) == _lib.PM_EUNSTABLE
+    d = ctypes.c_double
+    ws_n = lib_.ws_adam_workspace_bytes(10)
+    assert ws_n >= 8 * 8 * 2048
+    for bad in ((10, 0, 1e-3, 0.9, 0.999, 1e-8, 0.0), (10, 1, -1.0, 0.9, 0.999, 1e-8, 0.0),
+                (10, 1, 1e-3, 1.0, 0.999, 1e-8, 0.0), (10, 1, 1e-3, 0.9, 0.999, 0.0, 0.0),
+                (0, 1, 1e-3, 0.9, 0.999, 1e-8, 0.0), (10, 1, 1e-3, 0.9, 0.999, 1e-8, -1.0)):
+        n, step, lr, b1, b2, eps, clip = bad
+        assert lib_.ws_adam_step(vp(256), vp(256), vp(256), vp(256), n, step, d(lr), d(b1), d(b2), d(eps), d(clip),
+                                 None, vp(256), ws_n, None) == _lib.PM_EINVAL
+    assert lib_.ws_adam_step(vp(256), vp(256), vp(256), vp(256), 10, 1, d(1e-3), d(0.9), d(0.999), d(1e-8),
+                             d(0.0), None, vp(256), 16, None) == _lib.PM_ENOMEM

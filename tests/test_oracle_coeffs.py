@@ -127,3 +127,24 @@ def test_point_mass_force_ratio_screened_near_and_enhanced_far():
     y, _ = C.spherical_yz(A, x, c["alpha_b"], c["alpha_m"])
     assert y[0] / A[0] == pytest.approx(1.0, abs=2e-4)
     assert y[1] / A[1] == pytest.approx(c["mu_psi"], rel=1e-6)
+
+
+@pytest.mark.parametrize("mu", [1.0, 1.3, 0.7])
+def test_growth_integrator_matches_eds_closed_form_with_constant_mu(mu):
+    """Einstein-de Sitter background (Omega_m = 1, dlnH/dlna = -3/2) with a
+    constant coupling mu: eq. delta_mod_a becomes D'' + D'/2 - (3/2) mu D = 0
+    in ln a, solved by a^p with p = (-1 +- sqrt(1 + 24 mu))/4.  The start
+    D = D' = a_start (slope 1) mixes both modes; the exact solution is that
+    mix.  A dropped mu, a wrong friction term or a wrong Omega_m factor moves
+    the result by percents."""
+    a0, a1 = 1e-2, 1.0
+    pp = (-1.0 + math.sqrt(1.0 + 24.0 * mu)) / 4.0
+    pm = (-1.0 - math.sqrt(1.0 + 24.0 * mu)) / 4.0
+    A = a0 * (1.0 - pm) / (pp - pm)
+    B = a0 * (pp - 1.0) / (pp - pm)
+    x = math.log(a1 / a0)
+    exact = A * math.exp(pp * x) + B * math.exp(pm * x)
+    rate = pp * A * math.exp(pp * x) + pm * B * math.exp(pm * x)
+    d, dd = C.growth_factor(a1, 1.0, a_start=a0, n_steps=4000, mu_of_a=lambda a: mu, with_rate=True)
+    assert d == pytest.approx(exact, rel=1e-10)
+    assert dd == pytest.approx(rate, rel=1e-10)

@@ -116,3 +116,105 @@ def test_static_sphere_matches_printed_accuracy(ng):
         rmid = (edges[np.minimum(np.nonzero(good)[0], len(edges) - 1)] - 0.5 * h)
         assert rel.max() < g["psi_rel_tol"]
         assert rel[rmid >= 0.2].max() < g["psi_rel_tol_beyond_4_cells"]
+
+
+def _tophat_closed_form(c, delta_in, radius):
+    """u(r) = chi'(r)/r of eq. analytical in code units for an isolated top-hat
+    of contrast delta_in and radius `radius`: 2K u^2 - nu u + xi s m(r)/r^3
+    = 0 with m(r) = delta_in min(r, radius)^3 / 3, on the root that is
+    continuous to the linear solution; chi(r) = -int_r^inf s u(s) ds."""
+    nu, K, xs = c["nu"], c["K"], c["xi"] * c["s"]
+
+    def u(r):
+        m = delta_in * min(r, radius) ** 3 / 3.0
+        return 2.0 * xs * m / r**3 / (nu + math.sqrt(nu * nu - 8.0 * K * xs * m / r**3))
+
+    def chi(r):
+        lo = integrate.quad(lambda s: s * u(s), r, max(r, radius), epsabs=0, epsrel=1e-12)[0] if r < radius else 0.0
+        hi = integrate.quad(lambda s: s * u(s), max(r, radius), np.inf, epsabs=0, epsrel=1e-12, limit=400)[0]
+        return -(lo + hi)
+
+    return u, chi
+
+
+def test_tophat_interior_is_exact_for_the_discrete_operator():
+    """Inside a top-hat the closed form is chi = u0 r^2 / 2 + const, for which
+    the second differences are exact and the cross differences vanish
+    (T = 0): the discrete operator's residual vanishes to rounding at every
+    cell whose stencil lies inside (Sec. 2.7 against Sec. 3.2)."""
+    from workloads import tophat_density
+
+    ng, R, d_in = 32, 10.0, 8.0
+    c = C.eft_coefficients(0.3071, -0.6, 0.0, 1.0)
+    h = 1.0 / ng
+    delta = np.where(tophat_density(ng, R, d_in) > 1.0, d_in, 0.0)
+    u, _ = _tophat_closed_form(c, d_in, R * h)
+    u0 = u(0.5 * R * h)
+    x = (np.arange(ng) + 0.5 - ng / 2) * h
+    r2 = x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2
+    chi = 0.5 * u0 * r2
+    xg = (np.arange(-1, ng + 1) + 0.5 - ng / 2) * h
+    ghosts = 0.5 * u0 * (xg[:, None, None] ** 2 + xg[None, :, None] ** 2 + xg[None, None, :] ** 2)
+    op = oracle.chi_operator(chi, c["xi"] * c["s"] * delta, h, c["nu"], c["K"], ghosts=ghosts)
+    inner = np.sqrt(r2) < (R - 2.0) * h
+    assert inner.sum() > 500
+    assert np.abs(op["T"][inner]).max() < 1e-9 * u0**2
+    assert np.abs(op["r"][inner]).max() < 1e-11 * abs(3.0 * u0)
+    assert op["lq"][inner] == pytest.approx(3.0 * u0, rel=1e-12)
+
+
+@pytest.mark.slow
+def test_tophat_full_solve_matches_closed_form_gradient():
+    """Full nonlinear solve of a strongly screened top-hat (delta 10, radius 8
+    cells of a 64^3 grid, alpha_B0 = -0.6, a = 1; (8/3)|lambda| delta = 16.6),
+    faces held at the closed form (whose mass is that of the cells the
+    top-hat covers): the radial gradient chi'(r) matches the closed form
+    within 1 % more than 2 cells inside the edge, where the closed form is
+    a quadratic the discrete operator treats exactly.  Outside, the
+    screening term's discretisation at the staircase edge costs a first-order
+    error (measured -2.0 % at radius 8 cells and -1.2 % at 12 cells on a 96^3
+    grid, while the linearised field is within 1e-4): bound 3 %.  The same
+    solve with screening off matches its closed form within 1 % everywhere."""
+    from workloads import tophat_density
+
+    ng, R, d_in = 64, 8.0, 10.0
+    h = 1.0 / ng
+    inside = tophat_density(ng, R, d_in) > 1.0
+    delta = np.where(inside, d_in, 0.0)
+    r_eff = (3.0 * inside.sum() / (4.0 * math.pi)) ** (1.0 / 3.0) * h
+    xg = (np.arange(-1, ng + 1) + 0.5 - ng / 2) * h
+    rg = np.sqrt(xg[:, None, None] ** 2 + xg[None, :, None] ** 2 + xg[None, None, :] ** 2)
+    face = np.zeros(rg.shape, bool)
+    face[[0, -1]] = True
+    face[:, [0, -1]] = True
+    face[:, :, [0, -1]] = True
+    x = xg[1:-1]
+    X = np.meshgrid(x, x, x, indexing="ij")
+    r = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    for screening, ext_tol in ((True, 3e-2), (False, 1e-2)):
+        c = C.eft_coefficients(0.3071, -0.6, 0.0, 1.0, screening=screening)
+        if screening:
+            u, chi_of_r = _tophat_closed_form(c, d_in, r_eff)
+        else:  # K = 0: u = mu_chi s m / r^3
+            def u(rv):
+                return c["mu_chi"] * c["s"] * d_in * min(rv, r_eff) ** 3 / 3.0 / rv**3
+
+            def chi_of_r(rv):
+                lo = integrate.quad(lambda q: q * u(q), rv, max(rv, r_eff))[0] if rv < r_eff else 0.0
+                return -(lo + integrate.quad(lambda q: q * u(q), max(rv, r_eff), np.inf, limit=400)[0])
+        rr = np.unique(np.round(rg[face], 12))
+        lut = {k: chi_of_r(k) for k in rr}
+        ghosts = np.zeros(rg.shape)
+        ghosts[face] = [lut[k] for k in np.round(rg[face], 12)]
+        chi, rep = oracle.fas_solve(c["xi"] * c["s"] * delta, h, c["nu"], c["K"], tol=1e-11, max_cycles=200,
+                                    ghosts=ghosts)
+        assert rep["status"] == 0
+        full = ghosts.copy()
+        full[1:-1, 1:-1, 1:-1] = chi
+        g = [(np.roll(full, -1, ax) - np.roll(full, 1, ax))[1:-1, 1:-1, 1:-1] / (2 * h) for ax in range(3)]
+        radial = (g[0] * X[0] + g[1] * X[1] + g[2] * X[2]) / r
+        for lo, hi, tol in ((1.0, R - 2.0, 1e-2), (R + 2.0, 2.5 * R, ext_tol)):
+            sel = (r > lo * h) & (r < hi * h)
+            exact = np.array([rv * u(rv) for rv in r[sel]])
+            worst = np.abs(radial[sel] / exact - 1.0).max()
+            assert worst < tol, (screening, lo, hi, worst)

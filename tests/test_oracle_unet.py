@@ -106,3 +106,69 @@ def test_input_features_standardised():
     # lognormal densities have mean 1, so the feature is ln(rho + 1e-3) standardised
     lr = np.log(rho + 1e-3)
     np.testing.assert_allclose(x[..., 0], (lr - lr.mean()) / lr.std(), atol=1e-9)
+
+
+def test_adam_first_step_moves_each_weight_by_lr_against_its_gradient_sign():
+    """From m = v = 0 the bias-corrected moments of the first step are g and
+    g^2 exactly, so the update is lr g / (|g| + eps): lr sign(g) for
+    |g| >> eps, and nothing where g = 0."""
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-3, 3, 50)
+    g[7] = 0.0
+    lr, eps = 1e-2, 1e-8
+    w1, m1, v1, gn = U.adam_step(w, g, np.zeros(50), np.zeros(50), 1, lr, eps=eps)
+    np.testing.assert_allclose(w1, w - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-15)
+    assert w1[7] == w[7]
+    big = np.abs(g) > 1e-2
+    np.testing.assert_allclose((w - w1)[big], lr * np.sign(g[big]), rtol=0, atol=lr * 1e-6)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v1, 0.001 * g * g, rtol=1e-13)
+    assert gn == pytest.approx(np.sqrt(np.sum(g * g)), rel=1e-14)
+
+
+def test_adam_constant_gradient_sequence_is_exactly_bias_corrected():
+    """A constant gradient g for T steps gives m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so after bias correction every step moves
+    lr g / (|g| + eps): a missing or off-by-one correction fails."""
+    g = np.array([3.0, -0.25, 1e-4, -7.0])
+    w0 = np.array([0.5, -1.0, 2.0, 0.0])
+    w, m, v = w0.copy(), np.zeros(4), np.zeros(4)
+    lr, b1, b2, eps = 3e-3, 0.8, 0.99, 1e-8
+    T = 25
+    for t in range(1, T + 1):
+        w, m, v, _ = U.adam_step(w, g, m, v, t, lr, beta1=b1, beta2=b2, eps=eps)
+        np.testing.assert_allclose(m, (1 - b1**t) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - b2**t) * g * g, rtol=1e-13)
+    np.testing.assert_allclose(w, w0 - T * lr * g / (np.abs(g) + eps), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_global_norm_clipping():
+    """With grad_clip below ||g||, the moments see g grad_clip / ||g|| (a
+    vector of norm grad_clip); above it, g unchanged."""
+    g = np.array([3.0, 4.0])  # norm 5
+    _, m, v, gn = U.adam_step(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 1e-3, grad_clip=1.0)
+    assert gn == 5.0
+    np.testing.assert_allclose(m, 0.1 * np.array([0.6, 0.8]), rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * np.array([0.36, 0.64]), rtol=1e-13)
+    _, m2, _, _ = U.adam_step(np.zeros(2), g, np.zeros(2), np.zeros(2), 1, 1e-3, grad_clip=10.0)
+    np.testing.assert_allclose(m2, 0.1 * g, rtol=1e-15)
+
+
+def test_backward_rounding_hook_is_applied_to_activation_gradients_only():
+    """With a rounding hook that is the identity the gradients are unchanged;
+    with a hook that zeroes every activation gradient only the head's own
+    parameters keep a gradient."""
+    rng = np.random.default_rng(4)
+    p = U.init_params(1)
+    x0 = rng.standard_normal((8, 8, 8, 4))
+    y, cache = U.forward(p, x0)
+    dy = rng.standard_normal((8, 8, 8))
+    g0 = U.backward(p, cache, dy)
+    g1 = U.backward(p, cache, dy, rnd=lambda a: a.copy())
+    for k in g0:
+        np.testing.assert_array_equal(g0[k], g1[k])
+    gz = U.backward(p, cache, dy, rnd=np.zeros_like)
+    assert np.any(gz["head.w"] != 0)
+    for name, _, _ in U.LAYERS:
+        assert not np.any(gz[name + ".w"])

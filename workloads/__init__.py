@@ -10,6 +10,7 @@ from .ics import (  # noqa: F401
     gaussian_field,
     lattice_displacement_ics,
     zeldovich_ics,
+    zeldovich_displacement,
     lognormal_density,
     lognormal_particles,
     tophat_density,

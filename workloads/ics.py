@@ -120,27 +120,35 @@ def lattice_displacement_ics(ng, box=100.0, seed=0, rms_cells=0.3, slope=-2.0):
     return np.mod(_lattice(ng) + psi, 1.0)
 
 
+def zeldovich_displacement(ng, box, seed, pk=None):
+    """Lattice q (cell centres) and the Zel'dovich displacement field psi
+    (psi_hat = i k delta_hat / k^2 of a Gaussian delta with spectrum ``pk``,
+    default the sigma8 = 0.8 power-law-break one), both (3, ng^3) in box
+    units; x = q + D psi moves the particles to growth factor D (D = 1 for
+    the spectrum's normalisation)."""
+    if pk is None:
+        amp = pk_sigma8_norm()
+        pk = lambda k: amp * pk_powerlaw_break(k)  # noqa: E731
+    delta = gaussian_field(ng, box, pk, seed=seed)
+    dh = np.fft.rfftn(delta)
+    kx, ky, kz = _kvec(ng, box)
+    k2 = kx**2 + ky**2 + kz**2
+    k2[0, 0, 0] = 1.0
+    psi = []
+    for kc in (kx, ky, kz):
+        ph = 1j * kc * dh / k2
+        psi.append(np.fft.irfftn(ph, s=(ng, ng, ng), axes=(0, 1, 2)).ravel() / box)
+    return _lattice(ng), np.stack(psi)
+
+
 def zeldovich_ics(ng, box, seed, pk=None, np_side=None):
     """Zel'dovich particle load x = q + psi with psi_hat = i k delta_hat / k^2.
 
     ``pk`` defaults to the sigma8=0.8 normalised power-law-break spectrum.
     Positions of all (np_side^3) particles in box units, shape (3, np).
     """
-    if pk is None:
-        amp = pk_sigma8_norm()
-        pk = lambda k: amp * pk_powerlaw_break(k)  # noqa: E731
-    nps = ng if np_side is None else np_side
-    delta = gaussian_field(nps, box, pk, seed=seed)
-    dh = np.fft.rfftn(delta)
-    kx, ky, kz = _kvec(nps, box)
-    k2 = kx**2 + ky**2 + kz**2
-    k2[0, 0, 0] = 1.0
-    psi = []
-    for kc in (kx, ky, kz):
-        ph = 1j * kc * dh / k2
-        psi.append(np.fft.irfftn(ph, s=(nps, nps, nps), axes=(0, 1, 2)).ravel() / box)
-    psi = np.stack(psi)
-    return np.mod(_lattice(nps) + psi, 1.0)
+    q, psi = zeldovich_displacement(ng if np_side is None else np_side, box, seed, pk)
+    return np.mod(q + psi, 1.0)
 
 
 def expected_variance(ng, box, pk):
