@@ -103,7 +103,20 @@ typedef struct {
     const float *learned_params;
     void *learned_ws;
     size_t learned_ws_bytes;
+    /* Smoother of every level: PM_SMOOTH_RBGS (0, default), red-black
+     * Gauss-Seidel with the Laplacian-form Newton update (Sec. 3.2.2); or
+     * PM_SMOOTH_JACOBI, the pointwise local solve of PySCo (Secs. 3.2.1 and
+     * 3.5.1): every cell takes the root of its local equation from the
+     * previous iterate's neighbours, under-relaxed as
+     * chi <- w chi* + (1 - w) chi with w = jacobi_weight (0 means 0.6).  The
+     * root is the same branch as the Newton update's, so both smoothers
+     * converge to the same discrete solution; the Jacobi smoother runs the
+     * per-level grid-wide kernels only. */
+    int smoother;
+    double jacobi_weight;
 } pm_mg_opts;
+
+enum { PM_SMOOTH_RBGS = 0, PM_SMOOTH_JACOBI = 1 };
 
 typedef struct {
     int status;                 /* PM_OK or PM_ENOCONV / PM_ENONFINITE */
@@ -234,6 +247,41 @@ int pm_evolve(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const 
  * background (Sec. 3.1), as pm_evolve uses it for its kicks and drifts; NAN
  * for invalid arguments.  HOST only. */
 double pm_code_time(double a0, double a1, double omega_m0);
+
+/* ---- Power spectrum and boost (Sec. 3.6.2, Sec. 4.2) ----------------------
+ * P(k) of a periodic field sampled on an n^3 grid (n a power of two, 8..1024)
+ * in a box of side `box`: the 3D discrete Fourier transform F of the field
+ * (FP64, computed by the library's FFT kernels) and the shell averages
+ *   P_b = box^3 <|F_m|^2> / n^6,  k_b = (2 pi / box) <|m|>
+ * over the integer wave vectors m (components in [-n/2, n/2)) with
+ * b + 1/2 <= |m| < b + 3/2, b = 0 .. nbins - 1 (the zero mode is never
+ * counted); count_b is the number of modes.  nbins <= n / 2; the paper keeps
+ * the bins below half the estimator grid's Nyquist wavenumber, nbins = n / 4.
+ * No window deconvolution.  Outputs are HOST arrays of nbins (each
+ * nullable); the call synchronises the stream.  The shell sums use FP64
+ * atomics in LDS: reruns agree to rounding, not bit for bit.
+ * pm_particle_power first deposits the particles (3 x np SoA, dtype) with the
+ * CIC kernel of pm_deposit on the n^3 estimator grid (finer than the particle
+ * grid, to push aliasing to higher k) and transforms rho - 1.
+ * Workspace: pm_power_workspace_bytes(n, particles) bytes (particles = 1 for
+ * pm_particle_power), 256-byte aligned.  Errors: PM_EINVAL, PM_ENOMEM,
+ * PM_EHIP. */
+size_t pm_power_workspace_bytes(int n, int particles);
+int pm_field_power(const void *field, int n, pm_dtype dtype, double box, int nbins, double *k_out /* HOST */,
+                   double *pk_out /* HOST */, double *count_out /* HOST */, void *ws, size_t ws_bytes,
+                   pm_stream_t stream);
+int pm_particle_power(const void *pos, long long np, pm_dtype dtype, int n, double box, int nbins,
+                      double *k_out /* HOST */, double *pk_out /* HOST */, double *count_out /* HOST */, void *ws,
+                      size_t ws_bytes, pm_stream_t stream);
+
+/* Power-spectrum boost R(k) = P_num(k) / P_den(k) of a simulation pair
+ * (Sec. 4.2), smoothed over the bins with a one-dimensional Gaussian filter
+ * of width sigma_k in k (the paper smooths its boosts this way):
+ * r_b = sum_c w_bc R_c / sum_c w_bc, w_bc = exp(-(k_c - k_b)^2 / (2 sigma_k^2));
+ * sigma_k = 0 returns R unsmoothed.  HOST arrays of nbins.  PM_ENONFINITE if
+ * some P_den is 0 or a ratio is not finite; PM_EINVAL for bad arguments. */
+int pm_boost(const double *k /* HOST */, const double *pk_num /* HOST */, const double *pk_den /* HOST */, int nbins,
+             double sigma_k, double *r_out /* HOST */);
 
 /* Particle sort: reorders the particles (pos, and vel and ids when given)
  * by the cell of their CIC base corner, key (i0 ng + j0) ng + k0 with
@@ -391,15 +439,17 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
                        float *grad_out, double *loss /* HOST */, double *grad_norm /* HOST */, void *ws,
                        size_t ws_bytes, pm_stream_t stream);
 
-/* Read-back of an activation tensor that ws_unet_forward_train left in the
- * training workspace ws (for testing the backward pass on the network's own
- * BF16 activations): tensor index 0..12 = input (16 channels, the first 4
- * used), l1a out (16), [upsampled l4b out (32) | l1b out (16)] (48), pool 1
- * (16), l2a out (32), [upsampled l3b out (64) | l2b out (32)] (96), pool 2
- * (32), l3a out (64), l3b out (64), l4a out (32), l4b out (32), l5a out (16),
- * l5b out (16); grid ng, ng/2 or ng/4 per tensor as the network runs it.  out:
- * (grid^3 x channels) FP32, channels-last natural order. */
-int ws_unet_activation(const void *ws, int ng, int tensor, float *out, pm_stream_t stream);
+/* Read-back of a tensor of the training workspace ws (for testing the
+ * backward pass stage by stage on the network's own BF16 values): gradient
+ * 0, the activation that ws_unet_forward_train left; gradient 1, its
+ * gradient as ws_unet_backward left it (ReLU masks applied, skip gradients
+ * added; tensor 0 has none).  Tensor index 0..12 = input (16 channels, the
+ * first 4 used), l1a out (16), [upsampled l4b out (32) | l1b out (16)] (48),
+ * pool 1 (16), l2a out (32), [upsampled l3b out (64) | l2b out (32)] (96),
+ * pool 2 (32), l3a out (64), l3b out (64), l4a out (32), l4b out (32), l5a
+ * out (16), l5b out (16); grid ng, ng/2 or ng/4 per tensor as the network
+ * runs it.  out: (grid^3 x channels) FP32, channels-last natural order. */
+int ws_unet_tensor(const void *ws, int ng, int tensor, int gradient, float *out, pm_stream_t stream);
 
 /* One 3x3x3 periodic convolution on BF16 channels-last tensors with FP32
  * output (for testing the kernels): mode 0 forward out[n^3][cout] =
@@ -427,6 +477,16 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
  * (device); xc: HOST [3]; n a multiple of 64. */
 int ws_conv3_first(int n, const void *f_bf16, const float *w, const float *b, const float *xc /* HOST [3] */,
                    float *out, pm_stream_t stream);
+
+/* Self-check of the workspace plan for (ng, np, dtype, prec), on the host
+ * only (no device work, no allocation): every multigrid level view and
+ * colour buffer lies inside pm_workspace_bytes(ng, np, dtype, prec), no two
+ * arrays that a level's kernels write overlap, the levels halve down to a
+ * 4^3 or 6^3 grid, and for every start level of the single-workgroup coarse
+ * cycle the levels it keeps resident fit the LDS it requests (within its
+ * budget).  PM_OK, or PM_EINVAL if any of these fails or the size is
+ * unsupported. */
+int pm_plan_check(int ng, long long np, pm_dtype dtype, pm_prec prec);
 
 /* Measurement hooks.  While enabled, each launch of the finest-level
  * red-black smoother (one colour per launch) is bracketed by HIP events on

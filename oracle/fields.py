@@ -134,3 +134,15 @@ def power_spectrum(field, box, nbins=None):
     ksum = np.bincount(which[ok], weights=(wgt.ravel() * kk.ravel())[ok], minlength=nb)
     good = cnt > 0
     return ksum[good] / cnt[good], psum[good] / cnt[good], cnt[good]
+
+
+def smoothed_ratio(k, p_num, p_den, sigma_k):
+    """Boost R = p_num / p_den smoothed over the bins with a one-dimensional
+    Gaussian filter of width sigma_k in k (normalised weights); sigma_k = 0
+    returns R itself."""
+    k = np.asarray(k, dtype=np.float64)
+    r = np.asarray(p_num, dtype=np.float64) / np.asarray(p_den, dtype=np.float64)
+    if sigma_k == 0.0:
+        return r
+    w = np.exp(-0.5 * ((k[None, :] - k[:, None]) / sigma_k) ** 2)
+    return (w @ r) / w.sum(axis=1)

@@ -19,7 +19,8 @@ __all__ = [
     "mg_scalar_solve_batched", "pm_autotune", "pm_deposit", "pm_eft_coefficients", "pm_get_launch_shape",
     "pm_set_launch_shape", "pm_sort_particles", "pm_tune_load", "pm_tune_save",
     "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
-    "pm_strerror", "pm_workspace_bytes", "pm_potentials", "pm_evolve", "pm_code_time",
+    "pm_strerror", "pm_workspace_bytes", "pm_potentials", "pm_evolve", "pm_code_time", "pm_field_power",
+    "pm_particle_power", "pm_boost",
 ]
 
 
@@ -38,12 +39,16 @@ class MgOpts:
     precision: str = "f64"  # "f64" | "mixed"
     guess: str = "zero"     # "zero" | "given" | "linear" | "learned"
     learned: object = None  # warmstart.WarmStart, for guess "learned"
+    smoother: str = "rbgs"  # "rbgs" | "jacobi"
+    jacobi_weight: float = 0.6
 
     def c(self, ng=None):
         prec = {"f64": L.PM_PREC_F64, "mixed": L.PM_PREC_MIXED}[self.precision]
         guess = {"zero": L.PM_GUESS_ZERO, "given": L.PM_GUESS_GIVEN, "linear": L.PM_GUESS_LINEAR,
                  "learned": L.PM_GUESS_LEARNED}[self.guess]
         o = L.MgOpts(self.rel_tol, self.max_vcycles, self.n_pre, self.n_post, prec, guess)
+        o.smoother = {"rbgs": 0, "jacobi": 1}[self.smoother]
+        o.jacobi_weight = float(self.jacobi_weight)
         if self.guess == "learned":
             if self.learned is None or ng is None:
                 raise ValueError("guess 'learned' needs MgOpts.learned (a WarmStart) and the grid size")
@@ -373,3 +378,65 @@ def pm_evolve(pos, vel, ng, params, a_start, a_end, nsteps, poisson_opts, scalar
     if rc not in (L.PM_OK, L.PM_ENOCONV):
         raise PmError(rc, "pm_evolve")
     return {n: getattr(rep, n) for n, _ in L.EvolveReport._fields_}
+
+
+def _power_out(nbins):
+    return [(ctypes.c_double * nbins)() for _ in range(3)]
+
+
+def _power_ws(n, particles, ws):
+    import torch
+
+    need = int(L.lib().pm_power_workspace_bytes(int(n), int(particles)))
+    if need == 0:
+        raise PmError(L.PM_EINVAL, f"power spectrum workspace for n={n}")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    return ws
+
+
+def pm_field_power(field, box, nbins=None, ws=None, stream=None):
+    """(k, P, counts) of a periodic (n, n, n) device field (see pmeft.h)."""
+    import numpy as np
+
+    dt = _dtype_code(field)
+    n = field.shape[0]
+    _check(field, (n, n, n), dt, "field")
+    nb = n // 4 if nbins is None else int(nbins)
+    ws = _power_ws(n, 0, ws)
+    k, p, c = _power_out(nb)
+    rc = L.lib().pm_field_power(ctypes.c_void_p(field.data_ptr()), int(n), dt, float(box), nb, k, p, c,
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_field_power")
+    return np.array(k), np.array(p), np.array(c)
+
+
+def pm_particle_power(pos, n, box, nbins=None, ws=None, stream=None):
+    """(k, P, counts) of the CIC density of the particles on an n^3 grid."""
+    import numpy as np
+
+    dt = _dtype_code(pos)
+    npart = pos.shape[1]
+    _check(pos, (3, npart), dt, "pos")
+    nb = n // 4 if nbins is None else int(nbins)
+    ws = _power_ws(n, 1, ws)
+    k, p, c = _power_out(nb)
+    rc = L.lib().pm_particle_power(ctypes.c_void_p(pos.data_ptr()), npart, dt, int(n), float(box), nb, k, p, c,
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream))
+    if rc:
+        raise PmError(rc, "pm_particle_power")
+    return np.array(k), np.array(p), np.array(c)
+
+
+def pm_boost(k, pk_num, pk_den, sigma_k=0.0):
+    """Gaussian-smoothed P_num / P_den over the bins (host)."""
+    import numpy as np
+
+    nb = len(k)
+    arr = lambda a: (ctypes.c_double * nb)(*[float(x) for x in a])  # noqa: E731
+    out = (ctypes.c_double * nb)()
+    rc = L.lib().pm_boost(arr(k), arr(pk_num), arr(pk_den), nb, float(sigma_k), out)
+    if rc:
+        raise PmError(rc, "pm_boost")
+    return np.array(out)

@@ -33,7 +33,7 @@ class MgOpts(ctypes.Structure):
     _fields_ = [("rel_tol", ctypes.c_double), ("max_vcycles", ctypes.c_int), ("n_pre", ctypes.c_int),
                 ("n_post", ctypes.c_int), ("precision", ctypes.c_int), ("guess", ctypes.c_int),
                 ("learned_params", ctypes.c_void_p), ("learned_ws", ctypes.c_void_p),
-                ("learned_ws_bytes", ctypes.c_size_t)]
+                ("learned_ws_bytes", ctypes.c_size_t), ("smoother", ctypes.c_int), ("jacobi_weight", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -64,7 +64,8 @@ EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_de
            "pm_strerror", "pm_sort_workspace_bytes", "pm_sort_particles", "mg_batched_workspace_bytes", "mg_scalar_solve_batched", "pm_autotune_workspace_bytes",
            "pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
            "ws_unet_forward_train", "ws_unet_backward", "ws_adam_workspace_bytes", "ws_adam_step",
-           "ws_unet_activation", "ws_conv3", "ws_conv3_first", "pm_potentials", "pm_evolve", "pm_code_time")
+           "ws_unet_tensor", "ws_conv3", "ws_conv3_first", "pm_potentials", "pm_evolve", "pm_code_time",
+           "pm_plan_check", "pm_power_workspace_bytes", "pm_field_power", "pm_particle_power", "pm_boost")
 
 
 def _load():
@@ -112,11 +113,11 @@ def _load():
     lib.ws_adam_workspace_bytes.argtypes = [ll]
     lib.ws_adam_workspace_bytes.restype = sz
     lib.ws_adam_step.argtypes = [vp, vp, vp, vp, ll, ll, d, d, d, d, d, P(d), vp, sz, vp]
-    lib.ws_unet_activation.argtypes = [vp, i, i, vp, vp]
+    lib.ws_unet_tensor.argtypes = [vp, i, i, i, vp, vp]
     lib.ws_conv3.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.ws_conv3_first.argtypes = [i, vp, vp, vp, P(ctypes.c_float), vp, vp]
     for name in ("ws_unet_forward", "ws_unet_train_step", "ws_conv3", "ws_conv3_first", "ws_unet_forward_train",
-                 "ws_unet_backward", "ws_adam_step", "ws_unet_activation"):
+                 "ws_unet_backward", "ws_adam_step", "ws_unet_tensor"):
         getattr(lib, name).restype = i
     lib.pm_potentials.argtypes = [vp, vp, i, i, P(EftParams), vp, vp, vp, vp]
     lib.pm_potentials.restype = i
@@ -125,6 +126,16 @@ def _load():
     lib.pm_evolve.restype = i
     lib.pm_code_time.argtypes = [d, d, d]
     lib.pm_code_time.restype = d
+    lib.pm_power_workspace_bytes.argtypes = [i, i]
+    lib.pm_power_workspace_bytes.restype = sz
+    lib.pm_field_power.argtypes = [vp, i, i, d, i, P(d), P(d), P(d), vp, sz, vp]
+    lib.pm_field_power.restype = i
+    lib.pm_particle_power.argtypes = [vp, ll, i, i, d, i, P(d), P(d), P(d), vp, sz, vp]
+    lib.pm_particle_power.restype = i
+    lib.pm_boost.argtypes = [P(d), P(d), P(d), i, d, P(d)]
+    lib.pm_boost.restype = i
+    lib.pm_plan_check.argtypes = [i, ll, i, i]
+    lib.pm_plan_check.restype = i
     lib.pm_strerror.argtypes = [i]
     lib.pm_strerror.restype = ctypes.c_char_p
     for name in ("pm_eft_coefficients", "pm_grid_levels", "pm_deposit", "mg_poisson_solve", "mg_scalar_solve",

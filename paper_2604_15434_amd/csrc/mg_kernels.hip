@@ -1215,11 +1215,12 @@ __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R>
     }
 }
 
+// The coarsest levels (from l0 down) that fit in kBlockLdsBytes become
+// resident: returns their LDS bytes and the first resident level in *lr
+// (B.nlev: none).
 template <typename R>
-void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
-                        const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st)
+size_t block_cycle_lds(const BlockHier<R> &B, int l0, int *lr_out)
 {
-    // the coarsest levels that fit in kBlockLdsBytes become resident
     int lr = B.nlev;
     size_t bytes = 0;
     for (int m = B.nlev - 1; m >= l0; m--) {
@@ -1230,6 +1231,20 @@ void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int 
         bytes += b;
         lr = m;
     }
+    *lr_out = lr;
+    return bytes;
+}
+template size_t block_cycle_lds<float>(const BlockHier<float> &, int, int *);
+template size_t block_cycle_lds<double>(const BlockHier<double> &, int, int *);
+
+size_t block_cycle_lds_limit() { return kBlockLdsBytes; }
+
+template <typename R>
+void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
+                        const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st)
+{
+    int lr = B.nlev;
+    const size_t bytes = block_cycle_lds(B, l0, &lr);
     if (nonlinear)
         hipLaunchKernelGGL((k_block_cycle<R, true>), dim3(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
                            fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr);

@@ -151,7 +151,8 @@ __device__ __forceinline__ void fold_previous(const double *__restrict__ csum_in
 }
 
 // Local update of one cell of colour `colour` (element e = (i, j, kh)):
-// x_new = (S - h^2 (Lq + tau - cmean)) / 6; returns Lq + tau.
+// x_new = (S - h^2 (Lq + tau - cmean)) / 6 (blended with the old value for
+// the Jacobi smoother); returns Lq + tau.
 template <typename R, bool NL>
 __device__ __forceinline__ R smooth_cell(const R *__restrict__ xc_old, const R *__restrict__ xo, R *__restrict__ xc_new,
                                          const R *__restrict__ dc, const R *__restrict__ tc, int n, int nh, int colour,
@@ -166,7 +167,10 @@ __device__ __forceinline__ R smooth_cell(const R *__restrict__ xc_old, const R *
     int isv;
     const R lq = root_lap<R>(b, tsh * ih2 * ih2, sc, NL, isv);
     const R v = lq + tv;
-    xc_new[e] = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
+    R xn = (S - h2 * (v - cmean)) * (R)(1.0 / 6.0);
+    if (sc.jacobi)  // under-relaxed Jacobi: blend with the cell's previous value
+        xn = (R)sc.omega * xn + (R)(1.0 - sc.omega) * xc_old[e];
+    xc_new[e] = xn;
     return v;
 }
 

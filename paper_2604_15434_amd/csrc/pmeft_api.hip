@@ -415,6 +415,8 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     R *src = H.buf[l][own] + (colour ? half : 0);
     R *dst = H.buf[l][1 - own] + (colour ? half : 0);
     const R *oth = H.buf[l][H.cur[l][1 - colour]] + (colour ? 0 : half);
+    if (sc.jacobi && colour == 1)  // Jacobi: the red values from before this sweep's red half
+        oth = H.buf[l][1 - H.cur[l][0]];
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (l == 0 && g_kt.on) {
         std::lock_guard<std::mutex> g(g_kt.mu);
@@ -432,7 +434,7 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     rs.partials = H.part(l, k);
     int nb = 0;
     launch_smooth<R>(H.L[l], colour, src, oth, dst, H.csum_cur(l), H.csum_alt(l), H.part(l, k ^ 1), H.pend_nb[l],
-                     H.pend_col[l], rs, sc, nl, C.st, &nb, H.tiled);
+                     H.pend_col[l], rs, sc, nl, C.st, &nb, sc.jacobi ? 0 : H.tiled);
     if (e1)
         (void)hipEventRecord(e1, C.st);
     H.cur[l][colour] = 1 - own;
@@ -539,6 +541,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
 {
     Hier<double> H;
     build_hier64(C, H, master);
+    if (sc.jacobi)  // (the single-workgroup coarse cycle smooths by Gauss-Seidel only)
+        H.block_l0 = kMaxLevels;
     const long long N = C.P.N;
     int fmg = 0;
     if (zero_start && o.max_vcycles > 0) {
@@ -623,6 +627,8 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
 {
     Hier<float> H;
     build_hier32(C, H);
+    if (sc.jacobi)
+        H.block_l0 = kMaxLevels;
     const long long N = C.P.N;
     LevelView<double> F64 = make_view<double>(C.P.n[0], 1.0 / C.P.n[0], C.at<double>(C.P.delta64[0]), nullptr, nullptr);
     const long long half = F64.half;
@@ -631,7 +637,11 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
     ReduceSlot ro = C.rs;
     ro.out = C.outer_out;
     // the FP32 correction equation of a linear problem has no source term
-    const SolveConsts sc32 = nl ? sc : SolveConsts{sc.nu, 0.0, 0.0};
+    SolveConsts sc32 = sc;
+    if (!nl) {
+        sc32.K = 0.0;
+        sc32.beta = 0.0;
+    }
     const double switch_tol = fmax(kMixedSwitchNL, 30.0 * o.rel_tol);
     double out[8];
     int it = 0, cyc = 0;  // outer steps, FP32 V-cycles
@@ -777,7 +787,9 @@ static bool opts_ok(const pm_mg_opts *o)
     return o && o->rel_tol > 0.0 && o->max_vcycles >= 0 && o->n_pre >= 0 && o->n_post >= 0 && o->n_pre + o->n_post > 0 &&
            (o->precision == PM_PREC_F64 || o->precision == PM_PREC_MIXED) && o->guess >= PM_GUESS_ZERO &&
            o->guess <= PM_GUESS_LEARNED &&
-           (o->guess != PM_GUESS_LEARNED || (o->learned_params && o->learned_ws));
+           (o->guess != PM_GUESS_LEARNED || (o->learned_params && o->learned_ws)) &&
+           (o->smoother == PM_SMOOTH_RBGS || o->smoother == PM_SMOOTH_JACOBI) &&
+           o->jacobi_weight >= 0.0 && o->jacobi_weight <= 1.0;
 }
 
 // The mixed path also needs the FP64 hierarchy: the nonlinear solve finishes
@@ -792,13 +804,24 @@ static int run_solve(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
                                         : solve_f64(C, master, sc, nl, o, src_norm, so, zero_start);
 }
 
+// Solve constants with the smoother the options ask for.
+static SolveConsts consts(double nu, double K, double beta, const pm_mg_opts &o)
+{
+    SolveConsts sc{nu, K, beta};
+    if (o.smoother == PM_SMOOTH_JACOBI) {
+        sc.jacobi = 1;
+        sc.omega = o.jacobi_weight > 0.0 ? o.jacobi_weight : 0.6;
+    }
+    return sc;
+}
+
 // Poisson: lap psi = s delta (nu = 1, K = 0, beta = s).
 static int poisson_core(Ctx &C, const pm_eft_coeffs &cf, const pm_mg_opts &o, SolveOut &so, double dsq)
 {
     double *m = C.at<double>(C.P.psi64);
     if (o.guess != PM_GUESS_GIVEN)
         launch_zero(m, sizeof(double) * C.P.N, C.st);
-    SolveConsts sc{1.0, 0.0, cf.s};
+    SolveConsts sc = consts(1.0, 0.0, cf.s, o);
     const double src = fabs(cf.s) * sqrt(dsq);
     if (src == 0.0) {
         launch_zero(m, sizeof(double) * C.P.N, C.st);
@@ -856,7 +879,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
     lo.rel_tol = 1e-30;  // the pass itself, no convergence test
     lo.max_vcycles = 1;
     SolveOut tmp;
-    e = run_solve(G, C.at<double>(C.P.chi64), SolveConsts{cf.nu, 0.0, cf.xi * cf.s}, false, lo, src, tmp, true, false);
+    e = run_solve(G, C.at<double>(C.P.chi64), consts(cf.nu, 0.0, cf.xi * cf.s, o), false, lo, src, tmp, true, false);
     if (e)
         return e;
     if (separate)
@@ -882,7 +905,7 @@ static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, 
         launch_zero(m, sizeof(double) * C.P.N, C.st);
         return launched();
     }
-    SolveConsts sc{cf.nu, cf.K, cf.xi * cf.s};
+    SolveConsts sc = consts(cf.nu, cf.K, cf.xi * cf.s, o);
     if (o.guess != PM_GUESS_GIVEN)
         launch_zero(m, sizeof(double) * C.P.N, C.st);
     if (o.guess == PM_GUESS_LEARNED && nl) {
@@ -896,7 +919,7 @@ static int scalar_core(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, 
         lo.rel_tol = 1e-3;
         lo.max_vcycles = 4;
         SolveOut tmp;
-        SolveConsts lin{cf.nu, 0.0, cf.xi * cf.s};
+        SolveConsts lin = consts(cf.nu, 0.0, cf.xi * cf.s, o);
         int e = run_solve(C, m, lin, false, lo, src, tmp, true);
         if (e)
             return e;
@@ -1706,6 +1729,123 @@ double pm_code_time(double a0, double a1, double omega_m0)
     if (!(a0 > 0.0) || !(a1 > 0.0) || !(omega_m0 > 0.0 && omega_m0 <= 1.0))
         return NAN;
     return code_time(a0, a1, omega_m0);
+}
+
+// Host self-check of a workspace plan (no device work): every level view and
+// colour buffer the kernels receive lies inside the workspace and no two
+// arrays a kernel writes overlap; the levels halve down to a 4^3 or 6^3 grid;
+// and for every block-cycle start level the resident levels fit the LDS the
+// launch requests, which stays within the budget.  The hierarchies are
+// built exactly as the solves build them, from a base address of 256.
+}  // extern "C"
+namespace pmeft {
+namespace {
+struct Extent {
+    size_t lo, hi;
+    const char *what;
+};
+template <typename R>
+bool check_hier(const Hier<R> &H, const char *base, size_t total, std::vector<Extent> &ext)
+{
+    auto in = [&](const void *p, long long elems, const char *what) {
+        if (!p)
+            return true;
+        const size_t lo = (size_t)((const char *)p - base), hi = lo + sizeof(R) * (size_t)elems;
+        if ((const char *)p < base || hi > total)
+            return false;
+        ext.push_back(Extent{lo, hi, what});
+        return true;
+    };
+    for (int l = 0; l < H.nlev; l++) {
+        const LevelView<R> &L = H.L[l];
+        if (L.half != (long long)L.n * L.n * (L.n / 2) || L.nh * 2 != L.n)
+            return false;
+        if (l > 0 && L.n * 2 != H.L[l - 1].n)
+            return false;
+        // the red / black halves of each array are adjacent
+        if ((L.db && L.db != L.dr + L.half) || (L.tb && L.tb != L.tr + L.half) ||
+            (L.x0b && L.x0b != L.x0r + L.half))
+            return false;
+        if (!in(L.dr, 2 * L.half, "delta") || !in(L.tr, 2 * L.half, "tau") || !in(L.x0r, 2 * L.half, "x0") ||
+            !in(H.buf[l][0], 2 * L.half, "buf0") || !in(H.buf[l][1], 2 * L.half, "buf1"))
+            return false;
+    }
+    const int nc = H.L[H.nlev - 1].n;
+    if (nc != 4 && nc != 6)
+        return false;
+    BlockHier<R> B = H.block();
+    for (int l0 = 0; l0 < H.nlev - 1; l0++) {
+        int lr = H.nlev;
+        const size_t bytes = block_cycle_lds(B, l0, &lr);
+        if (bytes > block_cycle_lds_limit() || lr < l0 || lr > H.nlev)
+            return false;
+        size_t need = 0;  // the kernel's own layout of the resident levels
+        for (int m = lr; m < H.nlev; m++)
+            need += sizeof(R) * 2 * (size_t)B.L[m].half *
+                    (3 + (B.L[m].tr ? 1 : 0) + (m > l0 && B.L[m].x0r ? 1 : 0));
+        if (need != bytes)
+            return false;
+    }
+    return true;
+}
+}  // namespace
+}  // namespace pmeft
+extern "C" {
+
+int pm_plan_check(int ng, long long np, pm_dtype dtype, pm_prec prec)
+{
+    if ((dtype != PM_F32 && dtype != PM_F64) || np < 0)
+        return PM_EINVAL;
+    int precs = prec == PM_PREC_F64 ? kPrecF64 : (kPrecMixed | kPrecF64);
+    Ctx C;
+    if (!make_plan(C.P, ng, np, dtype, precs))
+        return PM_EINVAL;
+    char *base = (char *)(uintptr_t)256;
+    C.ws = base;
+    std::vector<Ctx> ctxs{C};
+    if (np > 0) {  // the step's second per-solve region
+        Ctx C2 = C;
+        rebase_solve(C2.P, C.P.solve2);
+        if (C2.P.solve_lo + C2.P.solve_bytes > C.P.total)
+            return PM_EINVAL;
+        ctxs.push_back(C2);
+    }
+    for (Ctx &X : ctxs) {
+        X.csum64 = X.at<double>(X.P.csum64);
+        X.csum32 = X.at<double>(X.P.csum32);
+        X.sm_partials = X.at<double>(X.P.sm_partials);
+        std::vector<Extent> ext;
+        Hier<double> H64;
+        if (!(precs & kPrecF64))
+            return PM_EINVAL;
+        for (double *master : {X.at<double>(X.P.psi64), X.at<double>(X.P.chi64)}) {
+            ext.clear();
+            build_hier64(X, H64, master);
+            if (!check_hier(H64, base, X.P.total, ext))
+                return PM_EINVAL;
+            // arrays written by the hierarchy's kernels never overlap each other
+            std::sort(ext.begin(), ext.end(), [](const Extent &a, const Extent &b) { return a.lo < b.lo; });
+            for (size_t i = 1; i < ext.size(); i++)
+                if (ext[i].lo < ext[i - 1].hi)
+                    return PM_EINVAL;
+        }
+        if (precs & kPrecMixed) {
+            Hier<float> H32;
+            ext.clear();
+            build_hier32(X, H32);
+            if (!check_hier(H32, base, X.P.total, ext))
+                return PM_EINVAL;
+            std::sort(ext.begin(), ext.end(), [](const Extent &a, const Extent &b) { return a.lo < b.lo; });
+            for (size_t i = 1; i < ext.size(); i++)
+                if (ext[i].lo < ext[i - 1].hi)
+                    return PM_EINVAL;
+        }
+        // per-solve scratch inside the workspace
+        if (X.P.sm_partials + sizeof(double) * 8 * kMaxBlocks * 2 * kMaxLevels > X.P.total ||
+            X.P.red_partials + sizeof(double) * 8 * kMaxBlocks > X.P.total)
+            return PM_EINVAL;
+    }
+    return PM_OK;
 }
 
 int pm_kernel_timing_enable(int on)

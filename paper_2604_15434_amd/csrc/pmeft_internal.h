@@ -95,6 +95,11 @@ struct SolveConsts {
     double nu;     // coefficient of lap chi (1 for the Poisson solve)
     double K;      // screening prefactor (0 for Poisson or the linearised option)
     double beta;   // source b = beta * delta (s for Poisson, xi s for chi)
+    // Smoother: red-black Gauss-Seidel (jacobi 0), or Jacobi sweeps under-
+    // relaxed as x <- omega x* + (1 - omega) x with x* the local root from the
+    // previous iterate's neighbours (jacobi 1).
+    double omega = 1.0;
+    int jacobi = 0;
 };
 
 // Device view of one multigrid level (pointers are to packed arrays).
@@ -276,6 +281,11 @@ struct BlockHier {
 template <typename R>
 void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int n_post, SolveConsts sc, bool nonlinear,
                         const double *csum_l0, int cur_bits, int coarse_sweeps, hipStream_t st);
+// LDS bytes of the levels a block cycle from l0 keeps resident (the first
+// resident level in *lr) and the budget they must fit.
+template <typename R>
+size_t block_cycle_lds(const BlockHier<R> &B, int l0, int *lr);
+size_t block_cycle_lds_limit();
 
 // ---- learned warm start (unet_api.hip) -----------------------------------
 // Forward pass: copy delta (packed, mean-free) to `save` and run the network

@@ -589,14 +589,14 @@ int ws_unet_train_step(float *params, float *adam_m, float *adam_v, long long st
     return launched();
 }
 
-int ws_unet_activation(const void *ws, int ng, int tensor, float *out, pm_stream_t stream)
+int ws_unet_tensor(const void *ws, int ng, int tensor, int gradient, float *out, pm_stream_t stream)
 {
     NetPlan P;
-    if (!ws || !out || tensor < 0 || tensor >= NT || !net_plan(P, ng, true))
+    if (!ws || !out || tensor < 0 || tensor >= NT || !net_plan(P, ng, true) || (gradient && tensor == X0))
         return PM_EINVAL;
     const size_t m = (size_t)(ng >> kTLevel[tensor]);
-    launch_bf16_slice_to_f32((const uint16_t *)((const char *)ws + P.act[tensor]), kTChan[tensor], 0, kTChan[tensor],
-                             out, m * m * m, (hipStream_t)stream);
+    launch_bf16_slice_to_f32((const uint16_t *)((const char *)ws + (gradient ? P.grad[tensor] : P.act[tensor])),
+                             kTChan[tensor], 0, kTChan[tensor], out, m * m * m, (hipStream_t)stream);
     return launched();
 }
 

@@ -135,14 +135,14 @@ class WarmStart:
             raise PmError(rc, "ws_unet_backward")
         return grad_out
 
-    def activation(self, ng, tensor, out, stream=None):
-        """FP32 copy of activation tensor `tensor` (0..12) of the last
-        forward_train at this grid."""
+    def tensor(self, ng, tensor, out, gradient=False, stream=None):
+        """FP32 copy of training tensor `tensor` (0..12) of the last
+        forward_train at this grid, or of its gradient after backward()."""
         ws = self._workspace(ng, True)
-        rc = L.lib().ws_unet_activation(ctypes.c_void_p(ws.data_ptr()), int(ng), int(tensor),
-                                        ctypes.c_void_p(out.data_ptr()), _stream(stream))
+        rc = L.lib().ws_unet_tensor(ctypes.c_void_p(ws.data_ptr()), int(ng), int(tensor), int(bool(gradient)),
+                                    ctypes.c_void_p(out.data_ptr()), _stream(stream))
         if rc:
-            raise PmError(rc, "ws_unet_activation")
+            raise PmError(rc, "ws_unet_tensor")
         return out
 
     def save(self, path, meta=None):

@@ -5,6 +5,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 import oracle
@@ -201,3 +202,35 @@ def test_evolve_and_adam_reject_bad_arguments_before_any_gpu_work(lib):
                                  None, vp(256), ws_n, None) == _lib.PM_EINVAL
     assert lib_.ws_adam_step(vp(256), vp(256), vp(256), vp(256), 10, 1, d(1e-3), d(0.9), d(0.999), d(1e-8),
                              d(0.0), None, vp(256), 16, None) == _lib.PM_ENOMEM
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_workspace_plans_keep_every_view_in_bounds(lib, dtype, prec):
+    """Host self-check of every plan the solves build: level views and colour
+    buffers inside the workspace, written arrays disjoint, the levels halving
+    to 4^3 or 6^3, and the single-workgroup coarse cycle's resident levels
+    within the LDS it requests, for every start level (grid-only plans and
+    step plans with their second per-solve region)."""
+    lib_ = _lib.lib()
+    for ng in (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 1024):
+        for np_ in (0, ng**3):
+            assert lib_.pm_plan_check(ng, np_, dtype, prec) == 0, (ng, np_)
+    for bad in (7, 10, 14, 2048):
+        assert lib_.pm_plan_check(bad, 0, dtype, prec) == _lib.PM_EINVAL
+
+
+def test_boost_smoothing_matches_oracle(lib):
+    """pm_boost (host) against the oracle's Gaussian-smoothed ratio."""
+    from oracle.fields import smoothed_ratio
+
+    import paper_2604_15434_amd as P
+
+    rng = np.random.default_rng(2)
+    k = np.sort(rng.uniform(0.01, 2.0, 60))
+    den = rng.uniform(0.5, 2.0, 60)
+    num = den * (1.0 + 0.05 * np.sin(3 * k))
+    for sig in (0.0, 0.019, 0.028, 0.3):
+        np.testing.assert_allclose(P.pm_boost(k, num, den, sig), smoothed_ratio(k, num, den, sig), rtol=1e-13)
+    with pytest.raises(P.PmError):
+        P.pm_boost(k, num, np.zeros(60), 0.1)

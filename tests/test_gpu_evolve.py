@@ -132,8 +132,9 @@ def test_evolve_large_scale_growth_matches_growth_equation(P, screening):
     P_EFT / P_LCDM equals (D_EFT / D_LCDM)^2 of the growth equation started
     from the same D = dD/dln a at a = 0.33 (Sec. 4.2: within 0.4 % at
     k < 0.05 h/Mpc).  Bound 1 % with screening (the Vainshtein term acts on
-    small scales only), 0.3 % linearised.  The previous step's fields seed
-    every solve after the first."""
+    small scales only, but at alpha_B0 = -0.6 part of the mass is screened),
+    0.2 % linearised, on the fundamental shell.  The previous step's fields
+    seed every solve after the first."""
     ng, box, om0, a0 = 128, 250.0, 0.3071, 0.33
     if "ics" not in _GROWTH:
         _GROWTH["ics"] = _zeldovich_start(ng, box, 1, a0, om0)
@@ -160,4 +161,7 @@ def test_evolve_large_scale_growth_matches_growth_equation(P, screening):
     expect = (d_eft / d_lcdm) ** 2
     err = np.abs(ratio / expect - 1.0)
     print(f"growth screening={screening}: R(k) lowest bins {ratio} vs linear {expect:.5f} (rel. err {err})")
-    assert err.max() < (1e-2 if screening else 3e-3)
+    # the fundamental shell (k = 0.025 h/Mpc); the next one (0.05 h/Mpc)
+    # already carries mode coupling from the nonlinear scales (measured
+    # +0.6 % linearised, -0.5 % screened) and is reported only
+    assert err[0] < (1e-2 if screening else 2e-3)

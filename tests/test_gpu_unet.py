@@ -140,67 +140,100 @@ def _smooth_chi(n):
     return np.real(np.fft.ifftn(np.fft.fftn(rng.standard_normal((n, n, n))) * np.exp(-k2 * 200.0))) * 1e-3
 
 
-# tensor index of ws_unet_activation -> (oracle cache key, channel slice)
-_ACTS = [("x0", slice(0, 4)), ("a1", None), ("c1", None), ("p1", None), ("a2", None), ("c2", None), ("p2", None),
-         ("a3", None), ("b3", None), ("a4", None), ("b4", None), ("a5", None), ("b5", None)]
-_ACT_CH = [16, 16, 48, 16, 32, 96, 32, 64, 64, 32, 32, 16, 16]
-_ACT_LEVEL = [0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 0, 0]
+# tensors of the training workspace: index -> (name, channels, grid level)
+_T = ["x0", "a1", "c1", "p1", "a2", "c2", "p2", "a3", "b3", "a4", "b4", "a5", "b5"]
+_T_CH = [16, 16, 48, 16, 32, 96, 32, 64, 64, 32, 32, 16, 16]
+_T_LEVEL = [0, 0, 0, 1, 1, 1, 2, 2, 2, 1, 1, 0, 0]
 
 
-def _gpu_cache(net, n):
-    cache = {}
-    for t, (key, sl) in enumerate(_ACTS):
-        m = n >> _ACT_LEVEL[t]
-        out = torch.empty(m**3 * _ACT_CH[t], dtype=torch.float32, device="cuda")
-        net.activation(n, t, out)
-        a = out.cpu().numpy().astype(np.float64).reshape(m, m, m, _ACT_CH[t])
-        cache[key] = a[..., sl] if sl is not None else a
-    cache["s1"] = cache["c1"][..., 32:]
-    cache["s2"] = cache["c2"][..., 64:]
-    return cache
+def _read(net, n, t, gradient=False):
+    m = n >> _T_LEVEL[t]
+    out = torch.empty(m**3 * _T_CH[t], dtype=torch.float32, device="cuda")
+    net.tensor(n, t, out, gradient=gradient)
+    return out.cpu().numpy().astype(np.float64).reshape(m, m, m, _T_CH[t])
 
 
-def _per_tensor_errors(g, g_ref):
-    errs, o = {}, 0
-    for (name, ci, co) in U.LAYERS:
-        for part, sz in ((".w", 27 * ci * co), (".b", co)):
-            errs[name + part] = rel(g[o:o + sz], g_ref[name + part].reshape(-1))
-            o += sz
-    errs["head.w"] = rel(g[o:o + 16], g_ref["head.w"])
-    errs["head.b"] = rel(g[o + 16:o + 17], g_ref["head.b"])
-    return errs
-
-
-def test_network_backward_matches_reference_per_tensor(P):
-    """ws_unet_backward on a 64^3 lognormal density against the FP64
-    backward pass run on the network's own BF16 activations (read back from
-    the training workspace) with the same BF16 weights, given the same
-    dL/dyhat, the reference rounding every activation gradient to BF16 where
-    the kernels store one: every parameter tensor's gradient within 1e-3
-    relative L2 (what remains is FP32 accumulation and the BF16 roundings it
-    occasionally flips)."""
+def test_network_backward_stages_match_reference(P):
+    """ws_unet_backward on a 64^3 lognormal density, checked stage by stage:
+    each layer's parameter gradients and output gradient are recomputed by the
+    FP64 reference from that layer's own input -- the BF16 activations and
+    the BF16 gradient the network stored (read back from the training
+    workspace) -- with the same BF16 weights, and the reference rounds the
+    gradient it hands on to BF16 as the kernels store it.  Weight and bias
+    gradients within 1e-5 relative (FP32 accumulation only), handed-on
+    activation gradients within 1e-4 relative L2 (BF16 roundings that FP32
+    accumulation flips).  Chaining the stages instead lets those flips grow
+    to a BF16 ulp (4e-3) over the ten layers, so the stages are compared
+    separately."""
     from paper_2604_15434_amd.warmstart import WarmStart
 
     n = 64
     rho, prm = _net_case(n)
     net = WarmStart(seed=3)
-    flat = net.params.cpu().numpy().astype(np.float64)
-    p = _ref_params(flat)
+    p = _ref_params(net.params.cpu().numpy().astype(np.float64))
     pb = {k: (bf16_round(v) if k.endswith(".w") and not k.startswith("head") else v) for k, v in p.items()}
     rho_d = torch.from_numpy(rho).cuda()
-    yhat = torch.zeros(n**3, dtype=torch.float32, device="cuda")
-    net.forward_train(rho_d, prm, yhat)
-    cache = _gpu_cache(net, n)
+    net.forward_train(rho_d, prm)
+    act = {name: _read(net, n, t) for t, name in enumerate(_T)}
+    act["x0"] = act["x0"][..., :4]
     rng = np.random.default_rng(21)
     dy = (rng.standard_normal(n**3) * 2.0 / n**3).astype(np.float32)
     grads = torch.zeros(net.params.numel(), dtype=torch.float32, device="cuda")
     net.backward(torch.from_numpy(dy).cuda(), n, grads)
+    grad = {name: _read(net, n, t, gradient=True) for t, name in enumerate(_T) if t > 0}
     g = grads.cpu().numpy().astype(np.float64)
-    g_ref = U.backward(pb, cache, dy.astype(np.float64).reshape(n, n, n), rnd=bf16_round)
-    errs = _per_tensor_errors(g, g_ref)
-    worst = max(errs, key=errs.get)
-    print(f"backward per-tensor rel. L2: max {errs[worst]:.2e} ({worst}), median {np.median(list(errs.values())):.2e}")
-    assert errs[worst] < 1e-3, errs
+    gsl, o = {}, 0
+    for (name, ci, co) in U.LAYERS:
+        gsl[name + ".w"] = g[o:o + 27 * ci * co].reshape(27, ci, co)
+        o += 27 * ci * co
+        gsl[name + ".b"] = g[o:o + co]
+        o += co
+    gsl["head.w"], gsl["head.b"] = g[o:o + 16], g[o + 16:o + 17]
+    errs = {}
+
+    def cmp(key, got, ref):
+        errs[key] = rel(got, ref)
+
+    # head: d b5 = bf16(dy hw), masked by the ReLU of l5b
+    dyn = dy.astype(np.float64).reshape(n, n, n)
+    cmp("head.w", gsl["head.w"], np.tensordot(act["b5"], dyn, axes=([0, 1, 2], [0, 1, 2])))
+    cmp("head.b", gsl["head.b"], np.array([dyn.sum()]))
+    cmp("d b5", grad["b5"], bf16_round(dyn[..., None] * p["head.w"]) * (act["b5"] > 0))
+
+    def layer(name, x, dout, mask=None):
+        """parameter gradients of layer `name` from its stored input x and
+        stored (masked) output gradient; returns its BF16 input gradient,
+        masked by `mask` > 0 when given."""
+        dx, dw, db = U.conv3_backward(x, pb[name + ".w"], dout)
+        cmp(name + ".w", gsl[name + ".w"], dw)
+        cmp(name + ".b", gsl[name + ".b"], db)
+        dx = bf16_round(dx)
+        return dx * (mask > 0) if mask is not None else dx
+
+    cmp("d a5", grad["a5"], layer("l5b", act["a5"], grad["b5"], act["a5"]))
+    dc1 = layer("l5a", act["c1"], grad["a5"])
+    cmp("d c1[up]", grad["c1"][..., :32], dc1[..., :32])
+    cmp("d b4", grad["b4"], bf16_round(U.up_backward(grad["c1"][..., :32])) * (act["b4"] > 0))
+    cmp("d a4", grad["a4"], layer("l4b", act["a4"], grad["b4"], act["a4"]))
+    dc2 = layer("l4a", act["c2"], grad["a4"])
+    cmp("d c2[up]", grad["c2"][..., :64], dc2[..., :64])
+    cmp("d b3", grad["b3"], bf16_round(U.up_backward(grad["c2"][..., :64])) * (act["b3"] > 0))
+    cmp("d a3", grad["a3"], layer("l3b", act["a3"], grad["b3"], act["a3"]))
+    cmp("d p2", grad["p2"], layer("l3a", act["p2"], grad["a3"]))
+    s2 = act["c2"][..., 64:]
+    cmp("d s2", grad["c2"][..., 64:], bf16_round(dc2[..., 64:] + U.pool_backward(grad["p2"])) * (s2 > 0))
+    cmp("d a2", grad["a2"], layer("l2b", act["a2"], grad["c2"][..., 64:], act["a2"]))
+    cmp("d p1", grad["p1"], layer("l2a", act["p1"], grad["a2"]))
+    s1 = act["c1"][..., 32:]
+    cmp("d s1", grad["c1"][..., 32:], bf16_round(dc1[..., 32:] + U.pool_backward(grad["p1"])) * (s1 > 0))
+    cmp("d a1", grad["a1"], layer("l1b", act["a1"], grad["c1"][..., 32:], act["a1"]))
+    layer("l1a", act["x0"], grad["a1"])
+    wkeys = [k for k in errs if not k.startswith("d ")]
+    dkeys = [k for k in errs if k.startswith("d ")]
+    print("backward stages: max parameter-gradient error %.2e (%s), max activation-gradient error %.2e (%s)" % (
+        max(errs[k] for k in wkeys), max(wkeys, key=errs.get), max(errs[k] for k in dkeys), max(dkeys, key=errs.get)))
+    assert all(errs[k] < 1e-5 for k in wkeys), {k: errs[k] for k in wkeys}
+    assert all(errs[k] < 1e-4 for k in dkeys), {k: errs[k] for k in dkeys}
     # deterministic: a second backward gives the same bits
     grads2 = torch.zeros_like(grads)
     net.backward(torch.from_numpy(dy).cuda(), n, grads2)
@@ -256,9 +289,19 @@ def test_adam_step_matches_oracle(P):
         assert gn == pytest.approx(gn_ref, rel=1e-12)
         if step == 2:
             assert gn_ref > clip  # clipping is active in this step
-        for got, ref in ((wd, w_ref), (md, m_ref), (vd, v_ref)):
+        gc = g.astype(np.float64) * (min(1.0, clip / gn_ref) if clip > 0 else 1.0)
+        # FP32 arithmetic: each result within 1e-6 of the magnitudes it is formed from
+        scales = ((wd, w_ref, np.abs(w_in) + np.abs(w_ref - w_in)),
+                  (md, m_ref, b1 * np.abs(m_in) + (1 - b1) * np.abs(gc)),
+                  (vd, v_ref, b2 * np.abs(v_in) + (1 - b2) * gc * gc))
+        for got, ref, scale in scales:
             gg = got.cpu().numpy().astype(np.float64)
-            np.testing.assert_allclose(gg, ref, rtol=1e-6, atol=1e-30)
+            bad = np.abs(gg - ref) > 1e-6 * scale + 1e-30
+            assert not bad.any(), (step, int(bad.sum()), float(np.max(np.abs(gg - ref) / (scale + 1e-300))))
+        # the update itself, where it is not lost in w's own rounding
+        upd, upd_ref = w_in - wd.cpu().numpy().astype(np.float64), w_in - w_ref
+        big = np.abs(upd_ref) > 1e-3 * np.abs(w_in)
+        np.testing.assert_allclose(upd[big], upd_ref[big], rtol=2e-4)
 
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])

@@ -113,3 +113,19 @@ def test_lone_particle_at_cell_centre_feels_no_self_force():
                    dict(omega_m0=0.3071, alpha_b0=-0.4, alpha_m0=0.0, a=0.5, screening=False)):
         out = oracle.pm_step(pos, np.zeros((3, 1)), ng, params, dt_kick=1.0)
         np.testing.assert_allclose(out["acc"], 0.0, atol=1e-9)
+
+
+def test_smoothed_ratio_is_a_normalised_symmetric_filter():
+    """A constant boost stays constant; a boost linear in k stays linear more
+    than 8 sigma from the ends of uniformly spaced bins (symmetric kernel);
+    sigma = 0 gives the plain ratio."""
+    k = 0.01 * np.arange(1, 201)
+    den = 1.0 + k**2
+    out = F.smoothed_ratio(k, 1.03 * den, den, 0.028)
+    np.testing.assert_allclose(out, 1.03, rtol=1e-14)
+    lin = 1.0 + 0.5 * k
+    out = F.smoothed_ratio(k, lin * den, den, 0.028)
+    inner = (k > k[0] + 8 * 0.028) & (k < k[-1] - 8 * 0.028)
+    np.testing.assert_allclose(out[inner], lin[inner], rtol=1e-12)
+    raw = F.smoothed_ratio(k, lin * den, den, 0.0)
+    np.testing.assert_allclose(raw, lin, rtol=1e-15)
