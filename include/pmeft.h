@@ -203,6 +203,14 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
             double dt_kick, double dt_drift, void *psi, void *chi, pm_step_report *rep /* HOST, nullable */,
             void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* Arrangement of pm_step's two solves, process-wide: side_by_side 1 (the
+ * default) as described above; 0: both solves (and the learned warm start's
+ * network) are issued from the calling thread on `stream` alone, Poisson
+ * first, so that all of the step's work is ordered on the caller's stream
+ * and no library thread or stream is used (same results; slower, since the
+ * solves no longer overlap).  Returns the previous setting. */
+int pm_set_step_concurrency(int side_by_side);
+
 /* Bardeen potentials (eqs. phipsi_mod) from the Newtonian part Psi_N (lap
  * Psi_N = s delta, the psi of mg_poisson_solve / pm_step) and the scalar
  * field chi at the parameters' a: Psi = Psi_N + (alpha_B - alpha_M) chi, the
@@ -385,6 +393,18 @@ size_t ws_unet_workspace_bytes(int ng, int training);
  * training forward pass only by the BF16 rounding of those summed weights. */
 int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft_params *p /* HOST */,
                     float *yhat_out, void *ws, size_t ws_bytes, pm_stream_t stream);
+
+/* The learned warm start's initial scalar field chi_0 itself (north-star
+ * grown form (4)): the network's source prediction t for the density rho
+ * (ng^3 natural order, dtype), then one linear full-multigrid pass on
+ * lap chi_0 = s mu_chi (delta + t - <t>) -- exactly the guess that
+ * PM_GUESS_LEARNED starts the scalar-field solve from.  chi0_out: ng^3
+ * (dtype), mean-free.  learned_ws: ws_unet_workspace_bytes(ng, 0) bytes; ws:
+ * a solver workspace (pm_workspace_bytes(ng, 0, dtype, PM_PREC_F64)).  ng a
+ * multiple of 64.  Errors as mg_scalar_solve. */
+int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, const pm_eft_params *p /* HOST */,
+                  void *chi0_out, void *learned_ws, size_t learned_ws_bytes, void *ws, size_t ws_bytes,
+                  pm_stream_t stream);
 
 /* Forward pass in the training form (spec grown form (4): the network
  * is trained by the library's own forward and backward kernels): the same

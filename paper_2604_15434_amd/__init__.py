@@ -20,7 +20,7 @@ __all__ = [
     "pm_set_launch_shape", "pm_sort_particles", "pm_tune_load", "pm_tune_save",
     "pm_force_interp", "pm_grid_levels", "pm_kernel_timing_enable", "pm_kernel_timing_read", "pm_step",
     "pm_strerror", "pm_workspace_bytes", "pm_potentials", "pm_evolve", "pm_code_time", "pm_field_power",
-    "pm_particle_power", "pm_boost",
+    "pm_particle_power", "pm_boost", "pm_set_step_concurrency",
 ]
 
 
@@ -440,3 +440,9 @@ def pm_boost(k, pk_num, pk_den, sigma_k=0.0):
     if rc:
         raise PmError(rc, "pm_boost")
     return np.array(out)
+
+
+def pm_set_step_concurrency(side_by_side=True):
+    """pm_step's solves side by side (True, default) or both on the caller's
+    stream from the calling thread (False); returns the previous setting."""
+    return bool(L.lib().pm_set_step_concurrency(int(bool(side_by_side))))

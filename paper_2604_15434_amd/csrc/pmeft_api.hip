@@ -1063,6 +1063,26 @@ int mg_scalar_solve(const void *rho, int ng, pm_dtype dtype, const pm_eft_params
     return grid_solve(rho, ng, dtype, p, opts, chi, rep, ws, ws_bytes, stream, true);
 }
 
+int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, const pm_eft_params *p,
+                  void *chi0_out, void *learned_ws, size_t learned_ws_bytes, void *ws, size_t ws_bytes,
+                  pm_stream_t stream)
+{
+    if (!params || !learned_ws)
+        return PM_EINVAL;
+    pm_mg_opts o{};
+    o.rel_tol = 1e-300;  // never met: the solve stops before its first V-cycle
+    o.max_vcycles = 0;
+    o.n_pre = 1;
+    o.n_post = 2;
+    o.precision = PM_PREC_F64;
+    o.guess = PM_GUESS_LEARNED;
+    o.learned_params = params;
+    o.learned_ws = learned_ws;
+    o.learned_ws_bytes = learned_ws_bytes;
+    const int e = grid_solve(rho, ng, dtype, p, &o, chi0_out, nullptr, ws, ws_bytes, stream, true);
+    return e == PM_ENOCONV ? PM_OK : e;
+}
+
 // ---- batched solve ---------------------------------------------------------
 // Host workers, each with its own stream and workspace slice, take the
 // problems largest grid first from a shared counter and run the single-problem
@@ -1448,6 +1468,14 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
     return e;
 }
 
+// Process-wide choice of pm_step's solve arrangement (pm_set_step_concurrency).
+static std::atomic<int> g_step_side{1};
+
+int pm_set_step_concurrency(int side_by_side)
+{
+    return g_step_side.exchange(side_by_side ? 1 : 0);
+}
+
 int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm_eft_params *p,
             const pm_mg_opts *poisson_opts, const pm_mg_opts *scalar_opts, double dt_kick, double dt_drift, void *psi,
             void *chi, pm_step_report *rep, void *ws, size_t ws_bytes, pm_stream_t stream)
@@ -1467,7 +1495,8 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     // stream: its weights are packed there first, beside the deposit (they
     // depend on the parameters only), and its forward pass starts as soon as
     // the fine delta is mean-free, beside the rest of the delta preparation.
-    const bool learned = scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0;
+    const bool side = g_step_side.load() != 0;
+    const bool learned = side && scalar_opts->guess == PM_GUESS_LEARNED && cf.K != 0.0 && cf.xi != 0.0;
     SideStream *S = nullptr;
     if (learned) {
         e = learned_ok(ng, *scalar_opts);
@@ -1558,6 +1587,21 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         for (int i = 0; i < 64; i++)
             sx.hist[i] = i == 0 ? sp.rel : 0.0;
         e = launched();
+    } else if (!side) {
+        // both solves on the caller's stream, issued from this thread
+        {
+            Timer tp(C.st);
+            e = poisson_core(C, cf, *poisson_opts, sp, dsq);
+            if (e)
+                return e;
+            ms_p = tp.stop();
+        }
+        launch_field_sum(ps, C.P.N, C.rs, C.st);
+        launch_packed_to_natural(ps, psi, dtype, ng, 0.0, C.rs.out, C.st);
+        Timer tx(C.st);
+        e = scalar_core(C, *p, cf, *scalar_opts, sx, dsq);
+        if (!e)
+            ms_x = tx.stop();
     } else {
         e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
     }

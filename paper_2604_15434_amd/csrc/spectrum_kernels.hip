@@ -36,11 +36,11 @@ inline int ilog2(int n)
     return l;
 }
 
-// lines per block: the largest power of two C <= 16 with C * N complex
+// lines per block: the largest power of two C <= min(16, N) with C * N complex
 // doubles within kFftLdsBytes (C divides N)
 inline int fft_lines(int n)
 {
-    int c = 16;
+    int c = n < 16 ? n : 16;
     while (c > 1 && (size_t)c * n * 16 > (size_t)kFftLdsBytes)
         c /= 2;
     return c;

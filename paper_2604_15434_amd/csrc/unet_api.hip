@@ -38,8 +38,8 @@ size_t head_partial_floats();
 void launch_bf16_slice_to_f32(const uint16_t *s, int stride, int off, int C, float *d, size_t nvox, hipStream_t st);
 void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
                       hipStream_t st);
-void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
-                 float c1, float c2, const double *gsq, float clip, hipStream_t st);
+void launch_adam(float *w, const float *g, float *m, float *v, long long n, double lr, double b1, double b2,
+                 double eps, long long step, const double *gsq, double clip, hipStream_t st);
 void launch_sumsq(const float *g, long long n, ReduceSlot rs, hipStream_t st);
 void launch_f32_to_bf16(const float *s, uint16_t *d, size_t n, hipStream_t st);
 void launch_pack_poly(const float *w, int cin, int cout, int cup, int cout_pad, uint16_t *wp, hipStream_t st);
@@ -510,9 +510,7 @@ int adam_impl(float *params, const float *grads, float *m, float *v, long long n
               double b1, double b2, double eps, double grad_clip, ReduceSlot rs, hipStream_t st)
 {
     launch_sumsq(grads, n, rs, st);
-    const float c1 = (float)(1.0 - pow(b1, (double)step)), c2 = (float)(1.0 - pow(b2, (double)step));
-    launch_adam(params, grads, m, v, n, (float)lr, (float)b1, (float)b2, (float)eps, c1, c2, rs.out, (float)grad_clip,
-                st);
+    launch_adam(params, grads, m, v, n, lr, b1, b2, eps, step, rs.out, grad_clip, st);
     return launched();
 }
 }  // namespace

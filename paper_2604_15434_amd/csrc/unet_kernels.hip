@@ -1639,26 +1639,31 @@ void launch_sumsq(const float *g, long long n, ReduceSlot rs, hipStream_t st)
 
 // Adam (Kingma & Ba) with bias correction on FP32 master weights; the
 // gradient is scaled by min(1, clip / ||g||) when clip > 0 (||g||^2 in gsq).
+// omb1 = 1 - b1 and omb2 = 1 - b2 come from the host, formed in FP64: in
+// FP32, 1 - b2 from a rounded b2 = 0.999 would be off by 1e-5 relative.
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
-                                              float *__restrict__ v, long long n, float lr, float b1, float b2,
-                                              float eps, float c1, float c2, const double *__restrict__ gsq, float clip)
+                                              float *__restrict__ v, long long n, float lr, float b1, float omb1,
+                                              float b2, float omb2, float eps, float c1, float c2,
+                                              const double *__restrict__ gsq, float clip)
 {
     const double gn = sqrt(gsq[0]);
     const float scale = (clip > 0.f && gn > (double)clip) ? (float)((double)clip / gn) : 1.f;
     for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long long)gridDim.x * 256) {
         const float gg = scale * g[e];
-        const float mm = b1 * m[e] + (1.f - b1) * gg;
-        const float vv = b2 * v[e] + (1.f - b2) * gg * gg;
+        const float mm = b1 * m[e] + omb1 * gg;
+        const float vv = b2 * v[e] + omb2 * gg * gg;
         m[e] = mm;
         v[e] = vv;
         w[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
     }
 }
 
-void launch_adam(float *w, const float *g, float *m, float *v, long long n, float lr, float b1, float b2, float eps,
-                 float c1, float c2, const double *gsq, float clip, hipStream_t st)
+void launch_adam(float *w, const float *g, float *m, float *v, long long n, double lr, double b1, double b2,
+                 double eps, long long step, const double *gsq, double clip, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2, gsq, clip);
+    const float c1 = (float)(1.0 - pow(b1, (double)step)), c2 = (float)(1.0 - pow(b2, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3(512), dim3(256), 0, st, w, g, m, v, n, (float)lr, (float)b1, (float)(1.0 - b1),
+                       (float)b2, (float)(1.0 - b2), (float)eps, c1, c2, gsq, (float)clip);
 }
 
 // bf16 <-> f32 helpers for tests and the output path

@@ -111,6 +111,22 @@ class WarmStart:
             return loss.value, gn.value
         return loss.value if want_loss else None
 
+    def guess(self, rho, params, chi0_out, ws=None, stream=None):
+        """The learned initial field chi_0 (network + linear multigrid pass)
+        that a solve with guess "learned" starts from."""
+        from . import Workspace, _dtype_code
+
+        ng = rho.shape[0]
+        dt = _dtype_code(rho)
+        lws = self._workspace(ng, False)
+        ws = ws if ws is not None else Workspace(ng, 0, dt, "f64")
+        rc = L.lib().ws_unet_guess(ctypes.c_void_p(self.params.data_ptr()), ctypes.c_void_p(rho.data_ptr()), int(ng),
+                                   dt, ctypes.byref(_params(params)), ctypes.c_void_p(chi0_out.data_ptr()),
+                                   ctypes.c_void_p(lws.data_ptr()), lws.numel(), ws.ptr, ws.nbytes, _stream(stream))
+        if rc:
+            raise PmError(rc, "ws_unet_guess")
+        return chi0_out
+
     def forward_train(self, rho, params, yhat_out=None, stream=None):
         """Training-form forward pass; keeps the activations in the training
         workspace for backward()."""

@@ -643,3 +643,30 @@ def test_sort_particles_is_stable_argsort(P, ng, npart, dtype):
     rho1 = torch.zeros_like(rho0)
     P.pm_deposit(pos, ng, rho1)
     assert torch.equal(rho0, rho1)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_step_on_the_callers_stream_alone_gives_the_same_bits(P, prec):
+    """pm_set_step_concurrency(False): both solves issued from the calling
+    thread on the caller's stream (no library thread or stream) give the
+    side-by-side step's fields and velocities bit for bit."""
+    ng = 64
+    pos_np, _ = lognormal_particles(ng, 125.0, seed=43)
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.45, alpha_m0=0.05, a=0.95)
+    opts = P.MgOpts(rel_tol=1e-9, max_vcycles=80, precision=prec)
+    outs = []
+    try:
+        for side in (True, False):
+            P.pm_set_step_concurrency(side)
+            pos = torch.from_numpy(pos_np).cuda()
+            vel = torch.zeros_like(pos)
+            psi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+            chi = torch.zeros_like(psi)
+            rep = P.pm_step(pos, vel, ng, prm, opts, opts, 1e-2, 1e-3, psi, chi)
+            assert rep["status"] == 0
+            torch.cuda.synchronize()
+            outs.append((psi, chi, vel, pos))
+    finally:
+        P.pm_set_step_concurrency(True)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)

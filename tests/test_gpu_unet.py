@@ -533,3 +533,33 @@ def test_inference_forward_matches_oracle_samples(P, n):
     net.predict(rho, dict(omega_m0=0.3071, **G.PARAMS), yhat)
     got = yhat.cpu().numpy().astype(np.float64)[idx]
     assert rel(got, ref) < 3e-2, rel(got, ref)
+
+
+def test_learned_guess_entry_is_the_solves_starting_field(P):
+    """ws_unet_guess returns chi_0, the field a solve with guess "learned"
+    starts from: a solve from it (guess "given") takes the same number of
+    V-cycles as the learned solve and reaches the same field; chi_0 is
+    mean-free and far closer to the solution than zero."""
+    from paper_2604_15434_amd.warmstart import DEFAULT_WEIGHTS, WarmStart
+    from workloads import lognormal_density
+
+    import os
+
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights")
+    net = WarmStart.load(DEFAULT_WEIGHTS)
+    n = 64
+    rho = torch.from_numpy(lognormal_density(n, 125.0, seed=31)).cuda()
+    prm = dict(omega_m0=0.3071, alpha_b0=-0.5, alpha_m0=0.1, a=0.9)
+    chi0 = torch.zeros_like(rho)
+    net.guess(rho, prm, chi0)
+    assert abs(float(chi0.mean())) < 1e-12 * float(chi0.abs().max())
+    opts = dict(rel_tol=1e-10, max_vcycles=60)
+    chi_l = torch.zeros_like(rho)
+    rl = P.mg_scalar_solve(rho, prm, P.MgOpts(guess="learned", learned=net, **opts), chi_l)
+    chi_g = chi0.clone()
+    rg = P.mg_scalar_solve(rho, prm, P.MgOpts(guess="given", **opts), chi_g)
+    assert rl["status"] == rg["status"] == 0
+    assert abs(rl["vcycles"] - rg["vcycles"]) <= 1
+    assert float((chi_g - chi_l).norm() / chi_l.norm()) < 1e-8
+    assert float((chi0 - chi_l).norm() / chi_l.norm()) < 0.5
