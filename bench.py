@@ -7,7 +7,10 @@ alpha_B0 = -0.2, alpha_M0 = 0, a = 1 (Omega_m0 = 0.3071).  One step is the
 whole hot path: CIC deposit, Poisson multigrid, screened scalar-field
 multigrid to relative residual 1e-7 (both from a zero guess, every step
 solving the same input from scratch), 5-point gradient, CIC interpolation
-and kick.  Inputs are resident in device memory before the timed region.
+and kick.  Inputs are resident in device memory before the timed region;
+the particles are put in CIC base-cell order once before timing (the order
+a PM code keeps them in, re-sorting every few steps), which lets the
+deposit gather instead of scatter.
 
 Modes
   plain   : FP64 everywhere (particles, fields, V-cycles), zero guess.
@@ -39,19 +42,23 @@ HBM_PEAK_GBS = 8000.0
 PARAMS = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
 
 
-def smoother_bytes_per_launch(ng, itemsize):
-    """Algorithmic bytes of one finest-level half-sweep (one colour, ng^3/2
-    cells updated), counted as a smoother sweep is counted for the roofline:
-    a full sweep (both colours) reads the iterate and the right-hand side and
-    writes the iterate, 3 words per cell, so one colour's launch is 1.5 words
-    per cell of the grid."""
-    return 3 * itemsize * ng**3 // 2
+def smoother_bytes_per_launch(ng, itemsize, fused=False):
+    """Algorithmic bytes of one finest-level smoother launch, counted as a
+    smoother sweep is counted for the roofline: a full sweep (both colours)
+    reads the iterate and the right-hand side and writes the iterate, 3 words
+    per cell.  A half-sweep launch (one colour) is half of that; a fused
+    launch is a full sweep."""
+    return 3 * itemsize * ng**3 // (1 if fused else 2)
 
 
-def smoother_operand_bytes_per_launch(ng, itemsize, with_tau):
-    """Bytes one half-sweep must move with its operands as they are stored:
-    read own colour (edges), other colour (faces), delta (and the FAS source
-    tau on the FP32 level), write own colour, per cell of that colour."""
+def smoother_operand_bytes_per_launch(ng, itemsize, with_tau, fused=False):
+    """Bytes one launch must move with its operands as they are stored.
+    Half-sweep, per cell of its colour: read own colour (edges), other colour
+    (faces), delta (and the FAS source tau on the FP32 level), write own
+    colour.  Fused sweep, per cell: read the old iterate, delta (and tau),
+    write the new iterate."""
+    if fused:
+        return itemsize * (3 + (1 if with_tau else 0)) * ng**3
     per_cell = itemsize * (4 + (1 if with_tau else 0))
     return per_cell * ng**3 // 2
 
@@ -121,7 +128,7 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup, net=None, presort=False)
 
 
 SMOOTHER_SOURCES = [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f)
-                    for f in ("mg_stencil.h", "tile_window.h", "smooth_kernels.hip")]
+                    for f in ("mg_stencil.h", "tile_window.h", "smooth_kernels.hip", "sweep2_kernels.hip")]
 
 
 def smoother_source_hash():
@@ -138,6 +145,10 @@ def smoother_kernel(itemsize, tiled, ng):
     (the tile configuration rule of smooth_kernels.hip)."""
     r = "double" if itemsize == 8 else "float"
     nh = ng // 2
+    tj, tk = (16, 32) if itemsize == 8 else (8, 64)
+    if tiled == 4 and ng >= 64 and nh % tk == 0 and ng % tj == 0 and ng % 16 == 0:
+        pl = 32 if ng % 32 == 0 and (ng // 32) * (ng // tj) * (nh // tk) >= 512 else 16
+        return f"k_sweep2_tile<{r}, true, {tk}, {tj}, {pl}, true>"
     if tiled and ng >= 64:
         if tiled == 3 and nh % 64 == 0 and ng % 16 == 0 and (ng // 16) * (nh // 64) * (ng // 16) >= 512:
             return f"k_smooth_tile<{r}, true, 64, 4, 16>"
@@ -172,16 +183,20 @@ def roofline(res, ng, tiled):
     launches share the GPU with the other solve's kernels; the figure is what
     the kernel achieves inside the step, not alone."""
     slot = "scalar_f64" if res["itemsize"] == 8 else "scalar_f32"
+    fused = res["kernel_timing"].get(slot + "_fused", (0.0, 0))[1] > 0
+    if fused:
+        slot += "_fused"
     ms, n = res["kernel_timing"][slot]
     if n == 0:
         return None
-    bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"])
-    operand_bytes = smoother_operand_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4)
+    bytes_launch = smoother_bytes_per_launch(ng, res["itemsize"], fused)
+    operand_bytes = smoother_operand_bytes_per_launch(ng, res["itemsize"], with_tau=res["itemsize"] == 4, fused=fused)
     achieved = bytes_launch / (ms / n * 1e-3) / 1e9
     kernel = smoother_kernel(res["itemsize"], tiled, ng)
     out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, ng),
-           "kernel": f"{kernel} (finest level, one colour)", "bytes_per_launch": bytes_launch,
+           "kernel": f"{kernel} (finest level, {'both colours' if fused else 'one colour'})",
+           "bytes_per_launch": bytes_launch,
            "bytes_rule": "3 words per cell per full sweep (iterate + right-hand side read, iterate written)",
            "operand_bytes_per_launch": operand_bytes,
            "operand_GBps": round(operand_bytes / (ms / n * 1e-3) / 1e9, 1),
@@ -349,8 +364,7 @@ def main():
     results = {}
     for mode in modes:
         print(f"[bench] mode {mode}: {args.warmup} warmup + {args.steps} timed steps", file=sys.stderr, flush=True)
-        results[mode] = run_mode(P, torch, mode, pos_np, ng, args.steps, args.warmup, net,
-                                 presort=args.ics == "zeldovich")
+        results[mode] = run_mode(P, torch, mode, pos_np, ng, args.steps, args.warmup, net, presort=True)
         print(f"[bench] mode {mode}: {results[mode]['ms_per_step']:.3f} ms/step, "
               f"V-cycles chi {results[mode]['scalar_vcycles']} psi {results[mode]['poisson_vcycles']}",
               file=sys.stderr, flush=True)
@@ -373,7 +387,7 @@ def main():
         "dtype": "f64" if head == "plain" else ("f32+f64+bf16" if head == "learned" else "f32+f64"),
         "data": "synthetic",
         "config": {"workload": (f"PM step, {ng}^3 grid, {ng}^3 lognormal particles (log-sigma 1.5, seed 2), "
-                                f"{box:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7" if args.ics == "lognormal"
+                                f"{box:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7; particles in CIC base-cell order" if args.ics == "lognormal"
                                 else f"PM step, {ng}^3 grid, {ng}^3 Zel'dovich particles (sigma8 0.8, seed 5; "
                                 f"sorted by CIC cell once before timing), "
                                 f"{box:g} Mpc/h, alpha_B0=-0.2 alpha_M0=0 a=1, tol 1e-7"),

@@ -340,13 +340,18 @@ int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const
  *    untiled ones bit for bit; large tiles (8 rows x 64 packed cells x 16
  *    planes, 8 in FP64) replace small ones (4 rows x 64 or 8 rows x 32, 8
  *    planes) where they still give 512 tiles, and the largest (16 rows x 64 x
- *    16 planes) replace large ones under the same rule.
+ *    16 planes) replace large ones under the same rule; 4: the largest tiles
+ *    for the transfers, and every red-black sweep of a level with grid >= 64
+ *    (grid / 2 divisible by 64) runs both colours in one launch: each tile
+ *    updates its red cells plus a one-cell halo, then its black cells from
+ *    those new red values, so the sweep reads the old values once (the black
+ *    half then takes the lagged mean the red half takes).
  * Defaults 8 and 1.  They change the cost of a cycle, and the grouping of
  * the partial sums behind the lagged means, not the converged answer.
  * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a
  * synthetic density (uniform hash noise per cell in [0.2, 1.8], rough at every
  * scale) for every candidate (block_cycle_grid in off, 8, 16, 32, 64;
- * tiled_smoother 0, 1, 2, 3) and keeps the fastest for (ng, precision);
+ * tiled_smoother 0, 1, 2, 3, 4) and keeps the fastest for (ng, precision);
  * workspace: pm_autotune_workspace_bytes.  pm_tune_save / pm_tune_load write and read
  * the table as text lines "ng word_bytes block_cycle_grid tiled_smoother".
  * The table is process-wide. */
@@ -399,9 +404,10 @@ int ws_unet_forward(const float *params, const double *rho, int ng, const pm_eft
  * (ng^3 natural order, dtype), then one linear full-multigrid pass on
  * lap chi_0 = s mu_chi (delta + t - <t>) -- exactly the guess that
  * PM_GUESS_LEARNED starts the scalar-field solve from.  chi0_out: ng^3
- * (dtype), mean-free.  learned_ws: ws_unet_workspace_bytes(ng, 0) bytes; ws:
- * a solver workspace (pm_workspace_bytes(ng, 0, dtype, PM_PREC_F64)).  ng a
- * multiple of 64.  Errors as mg_scalar_solve. */
+ * (dtype), mean-free (zero where the scalar equation is linear or xi = 0:
+ * no learned guess is taken there).  learned_ws: ws_unet_workspace_bytes(ng,
+ * 0) bytes; ws: a solver workspace (pm_workspace_bytes(ng, 0, dtype,
+ * PM_PREC_F64)).  ng a multiple of 64.  Errors as mg_scalar_solve. */
 int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, const pm_eft_params *p /* HOST */,
                   void *chi0_out, void *learned_ws, size_t learned_ws_bytes, void *ws, size_t ws_bytes,
                   pm_stream_t stream);
@@ -509,14 +515,15 @@ int ws_conv3_first(int n, const void *f_bf16, const float *w, const float *b, co
 int pm_plan_check(int ng, long long np, pm_dtype dtype, pm_prec prec);
 
 /* Measurement hooks.  While enabled, each launch of the finest-level
- * red-black smoother (one colour per launch) is bracketed by HIP events on
- * the stream it runs on (a fixed pool of 16384 launches; later launches go
- * untimed).  pm_kernel_timing_read synchronises on the recorded events,
- * returns per-slot totals and launch counts (slots: 0 scalar field FP64,
- * 1 scalar field FP32, 2 Poisson FP64, 3 Poisson FP32) and clears them.
- * Not for concurrent use from several threads while timing is on. */
+ * red-black smoother (a half-sweep, or a fused two-colour sweep) is
+ * bracketed by HIP events on the stream it runs on (a fixed pool of 16384
+ * launches; later launches go untimed).  pm_kernel_timing_read synchronises
+ * on the recorded events, returns per-slot totals and launch counts (slots:
+ * 0 scalar field FP64, 1 scalar field FP32, 2 Poisson FP64, 3 Poisson FP32
+ * for half-sweeps; 4..7 the same for fused sweeps) and clears them.  Not for
+ * concurrent use from several threads while timing is on. */
 int pm_kernel_timing_enable(int on);
-int pm_kernel_timing_read(double *total_ms /* HOST [4] */, long long *launches /* HOST [4] */);
+int pm_kernel_timing_read(double *total_ms /* HOST [8] */, long long *launches /* HOST [8] */);
 
 const char *pm_strerror(int code);
 

@@ -101,13 +101,14 @@ def pm_kernel_timing_enable(on=True):
 def pm_kernel_timing_read():
     """{slot: (total_ms, launches)} for the finest-level smoother launches
     timed since the last read (slots: scalar_f64, scalar_f32, poisson_f64,
-    poisson_f32)."""
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_longlong * 4)()
+    poisson_f32 for half-sweeps, the same with _fused for fused sweeps)."""
+    ms = (ctypes.c_double * 8)()
+    n = (ctypes.c_longlong * 8)()
     rc = L.lib().pm_kernel_timing_read(ms, n)
     if rc:
         raise PmError(rc, "pm_kernel_timing_read")
-    names = ("scalar_f64", "scalar_f32", "poisson_f64", "poisson_f32")
+    names = ("scalar_f64", "scalar_f32", "poisson_f64", "poisson_f32", "scalar_f64_fused", "scalar_f32_fused",
+             "poisson_f64_fused", "poisson_f32_fused")
     return {k: (ms[q], n[q]) for q, k in enumerate(names)}
 
 

@@ -124,27 +124,34 @@ __device__ __forceinline__ T stencil_terms(const Ts *__restrict__ own, const Ts 
 
 // ---------------------------------------------------------------- smoothing
 // Block 0 of a half-sweep: csum_out = csum_in with the colour of the previous
-// half-sweep at this level (prev_colour; -1 none) replaced by the sum of its
-// per-block partials, in block order.
+// launch at this level (prev_colour; -1 none, 2 both: a fused two-colour
+// sweep, whose partials hold red in slot 0 and black in slot 1) replaced by
+// the sum of its per-block partials, in block order.
 __device__ __forceinline__ void fold_previous(const double *__restrict__ csum_in, double *__restrict__ csum_out,
                                               const double *__restrict__ prev, int prev_nblocks, int prev_colour)
 {
-    __shared__ double fin[kBlock / 64];
-    double t = 0.0;
+    __shared__ double fin[2][kBlock / 64];
+    double t[2] = {0.0, 0.0};
     if (prev_colour >= 0)
-        for (int q = threadIdx.x; q < prev_nblocks; q += kBlock)
-            t += prev[(size_t)q * 8];
-    for (int off = 32; off > 0; off >>= 1)
-        t += __shfl_down(t, off, 64);
-    if ((threadIdx.x & 63) == 0)
-        fin[threadIdx.x >> 6] = t;
+        for (int q = threadIdx.x; q < prev_nblocks; q += kBlock) {
+            t[0] += prev[(size_t)q * 8];
+            if (prev_colour == 2)
+                t[1] += prev[(size_t)q * 8 + 1];
+        }
+    for (int c = 0; c < 2; c++) {
+        for (int off = 32; off > 0; off >>= 1)
+            t[c] += __shfl_down(t[c], off, 64);
+        if ((threadIdx.x & 63) == 0)
+            fin[c][threadIdx.x >> 6] = t[c];
+    }
     __syncthreads();
     if (threadIdx.x < 2) {
         double v = csum_in[threadIdx.x];
-        if ((int)threadIdx.x == prev_colour) {
+        const int slot = prev_colour == 2 ? (int)threadIdx.x : 0;
+        if ((int)threadIdx.x == prev_colour || prev_colour == 2) {
             v = 0.0;
             for (int w = 0; w < kBlock / 64; w++)
-                v += fin[w];
+                v += fin[slot][w];
         }
         csum_out[threadIdx.x] = v;
     }

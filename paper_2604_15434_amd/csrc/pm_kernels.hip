@@ -60,8 +60,11 @@ constexpr int kDepTile = 8192;  // 64 KB of 64-bit counters
 
 template <typename Tp>
 __global__ __launch_bounds__(kBlock) void k_deposit_tiled(const Tp *__restrict__ pos, unsigned np, int ng,
-                                                          unsigned long long *__restrict__ acc, unsigned nchunks)
+                                                          unsigned long long *__restrict__ acc, unsigned nchunks,
+                                                          const unsigned *__restrict__ sorted_flag)
 {
+    if (sorted_flag && sorted_flag[0] == 0u)  // the input is row-sorted: the gather deposits it
+        return;
     __shared__ unsigned long long tile[kDepTile];
     __shared__ int wbox[kBlock / 64][6];  // per wave: min x, y, z, max x, y, z of the base cells
     const unsigned nb = gridDim.x;
@@ -194,10 +197,156 @@ void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, un
         nb -= nb % 8;
     if (dt == PM_F64)
         hipLaunchKernelGGL((k_deposit_tiled<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)pos,
-                           (unsigned)np, ng, acc, nchunks);
+                           (unsigned)np, ng, acc, nchunks, (const unsigned *)nullptr);
     else
         hipLaunchKernelGGL((k_deposit_tiled<float>), dim3(nb), dim3(kBlock), 0, st, (const float *)pos, (unsigned)np,
-                           ng, acc, nchunks);
+                           ng, acc, nchunks, (const unsigned *)nullptr);
+}
+
+// ------------------------------------------------------- gather deposit
+// Particles stored in the order of their CIC base row (i0, j0) (as
+// pm_sort_particles leaves them) let each cell collect its own sum: a
+// target row (I, J) receives from the particles of the four base rows
+// (I - a, J - b), a, b in {0, 1}, which are contiguous ranges of the
+// particle arrays.  A block sums a target row's ng cells in LDS (64-bit
+// integer atomics, the same 2^-40 rounding of every weight as the scatter,
+// so the grid is bitwise the scatter's) and writes each cell once: no global
+// atomics and no clearing of the grid.  k_row_index finds the rows' first
+// particles and flags input that is not in base-row order (or has unusable
+// coordinates); then the scatter deposits instead.  The choice is made on
+// the device, so the deposit still only enqueues.
+template <typename Tp>
+__device__ __forceinline__ int base_row(const Tp *__restrict__ pos, unsigned np, unsigned p, int ng)
+{
+    int x0, x1, y0, y1;
+    double fx, fy;
+    if (!cic_axis((double)pos[p], ng, x0, x1, fx) || !cic_axis((double)pos[np + p], ng, y0, y1, fy))
+        return -1;
+    return x0 * ng + y0;
+}
+
+// flag[0]: 1 if the input is not row-sorted (cleared before the launch);
+// rowstart[r] = first particle of base row r, rowstart[ng^2] = np.
+template <typename Tp>
+__global__ __launch_bounds__(kBlock) void k_row_index(const Tp *__restrict__ pos, unsigned np, int ng,
+                                                      unsigned *__restrict__ rowstart, unsigned *__restrict__ flag)
+{
+    const int nrows = ng * ng;
+    for (unsigned p = blockIdx.x * kBlock + threadIdx.x; p < np; p += gridDim.x * kBlock) {
+        const int r = base_row(pos, np, p, ng);
+        const int prev = p > 0 ? base_row(pos, np, p - 1, ng) : -1;
+        if (r < 0 || (p > 0 && prev < 0) || prev > r) {
+            flag[0] = 1u;
+            continue;
+        }
+        for (int q = prev + 1; q <= r; q++)
+            rowstart[q] = p;
+        if (p == np - 1)
+            for (int q = r + 1; q <= nrows; q++)
+                rowstart[q] = np;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_if_unsorted(unsigned long long *__restrict__ acc, unsigned long long n,
+                                                             const unsigned *__restrict__ flag)
+{
+    if (flag[0] == 0u)
+        return;
+    for (unsigned long long e = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; e < n;
+         e += (unsigned long long)gridDim.x * kBlock)
+        acc[e] = 0ull;
+}
+
+template <typename Tp>
+__global__ __launch_bounds__(kBlock) void k_deposit_gather(const Tp *__restrict__ pos, unsigned np, int ng,
+                                                           const unsigned *__restrict__ rowstart,
+                                                           const unsigned *__restrict__ flag,
+                                                           unsigned long long *__restrict__ acc, unsigned rows_per_block)
+{
+    if (flag[0] != 0u)
+        return;
+    __shared__ unsigned long long row[1024];
+    const unsigned nb = gridDim.x;
+    // XCD-aware: the blocks of one XCD take one contiguous range of rows, so
+    // the four source rows of neighbouring target rows stay in its L2
+    const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const unsigned nrows = (unsigned)ng * ng;
+    const unsigned r0 = lb * rows_per_block, r1 = min(nrows, r0 + rows_per_block);
+    for (unsigned R = r0; R < r1; R++) {
+        const int I = (int)(R / (unsigned)ng), J = (int)(R - (unsigned)I * ng);
+        for (int k = threadIdx.x; k < ng; k += kBlock)
+            row[k] = 0ull;
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                const int i0 = I - a < 0 ? I - a + ng : I - a, j0 = J - b < 0 ? J - b + ng : J - b;
+                const unsigned src = (unsigned)i0 * ng + j0;
+                const unsigned s = rowstart[src], e = rowstart[src + 1];
+                for (unsigned p = s + threadIdx.x; p < e; p += kBlock) {
+                    int x0, x1, y0, y1, z0, z1;
+                    double fx, fy, fz;
+                    cic_axis((double)pos[p], ng, x0, x1, fx);
+                    cic_axis((double)pos[np + p], ng, y0, y1, fy);
+                    cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz);
+                    // the scatter's weight products, in its order
+                    const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const double w = wx[a] * wy[b] * wz[c];
+                        const unsigned long long q = (unsigned long long)(w * kFixScale + 0.5);
+                        if (q)
+                            atomicAdd(&row[c ? z1 : z0], q);
+                    }
+                }
+            }
+        __syncthreads();
+        for (int k = threadIdx.x; k < ng; k += kBlock)
+            acc[(size_t)R * ng + k] = row[k];
+        __syncthreads();
+    }
+}
+
+size_t deposit_index_bytes(int ng) { return sizeof(unsigned) * ((size_t)ng * ng + 1 + 64); }
+
+// Deposit into acc (ng^3 fixed point): the gather where the particles are in
+// base-row order, else the scatter (acc cleared first in that case only).
+// idx: deposit_index_bytes(ng) bytes of scratch.
+void launch_deposit_auto(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc, void *idx,
+                         hipStream_t st)
+{
+    unsigned *flag = (unsigned *)idx, *rowstart = flag + 64;
+    launch_zero(flag, 256, st);
+    const unsigned nbi = (unsigned)std::min<long long>((np + kBlock - 1) / kBlock, 4096);
+    if (dt == PM_F64)
+        hipLaunchKernelGGL((k_row_index<double>), dim3(nbi), dim3(kBlock), 0, st, (const double *)pos, (unsigned)np,
+                           ng, rowstart, flag);
+    else
+        hipLaunchKernelGGL((k_row_index<float>), dim3(nbi), dim3(kBlock), 0, st, (const float *)pos, (unsigned)np, ng,
+                           rowstart, flag);
+    const unsigned long long n3 = (unsigned long long)ng * ng * ng;
+    hipLaunchKernelGGL(k_zero_if_unsorted, dim3(2048), dim3(kBlock), 0, st, acc, n3, (const unsigned *)flag);
+    const unsigned nchunks = (unsigned)((np + kDepChunk - 1) / kDepChunk);
+    unsigned nb = nchunks < 512u ? nchunks : 512u;
+    if (nb >= 8)
+        nb -= nb % 8;
+    const unsigned nrows = (unsigned)ng * ng;
+    unsigned gb = nrows < 4096u ? nrows : 4096u;
+    if (gb >= 8)
+        gb -= gb % 8;
+    const unsigned rpb = (nrows + gb - 1) / gb;
+    if (dt == PM_F64) {
+        hipLaunchKernelGGL((k_deposit_tiled<double>), dim3(nb), dim3(kBlock), 0, st, (const double *)pos,
+                           (unsigned)np, ng, acc, nchunks, (const unsigned *)flag);
+        hipLaunchKernelGGL((k_deposit_gather<double>), dim3(gb), dim3(kBlock), 0, st, (const double *)pos,
+                           (unsigned)np, ng, (const unsigned *)rowstart, (const unsigned *)flag, acc, rpb);
+    } else {
+        hipLaunchKernelGGL((k_deposit_tiled<float>), dim3(nb), dim3(kBlock), 0, st, (const float *)pos, (unsigned)np,
+                           ng, acc, nchunks, (const unsigned *)flag);
+        hipLaunchKernelGGL((k_deposit_gather<float>), dim3(gb), dim3(kBlock), 0, st, (const float *)pos, (unsigned)np,
+                           ng, (const unsigned *)rowstart, (const unsigned *)flag, acc, rpb);
+    }
 }
 
 // fixed point (natural layout) -> packed delta_raw = rho - 1, with its sum.

@@ -78,7 +78,7 @@ struct Plan {
     size_t p64[kMaxLevels] = {}, q64[kMaxLevels] = {}, t64[kMaxLevels] = {}, x064[kMaxLevels] = {};
     size_t d32[kMaxLevels] = {}, p32[kMaxLevels] = {}, q32[kMaxLevels] = {}, t32[kMaxLevels] = {},
            x032[kMaxLevels] = {};
-    size_t fixacc = 0, g4 = 0;
+    size_t fixacc = 0, g4 = 0, depidx = 0;
     size_t dalt64[kMaxLevels] = {}, dalt32[kMaxLevels] = {};  // step plans: the warm start's delta hierarchy
     int precs = 0;
     // Everything one solve writes (reductions, lagged means, the hierarchy
@@ -117,6 +117,7 @@ static bool make_plan(Plan &P, int ng, long long np, pm_dtype dt, int precs)
             P.d32[l] = take(c, sizeof(float) * (size_t)P.n[l] * P.n[l] * P.n[l]);
     if (np > 0) {
         P.fixacc = take(c, sizeof(unsigned long long) * P.N);
+        P.depidx = take(c, deposit_index_bytes(ng));
         P.g4 = take(c, (dt == PM_F64 ? sizeof(double) : sizeof(float)) * 4 * P.N);
         for (int l = 0; l < P.nlev; l++) {
             const size_t m3 = (size_t)P.n[l] * P.n[l] * P.n[l];
@@ -267,6 +268,7 @@ struct Hier {
     int pend_col[kMaxLevels], pend_nb[kMaxLevels], next_part[kMaxLevels];
     int block_l0 = kMaxLevels;  // levels from here down run as one block cycle
     int tiled = 1;              // 2.5D-tiled smoother: 0 off, 1 small, 2 large, 3 largest tiles
+    bool fused = false;         // large levels sweep both colours in one launch
     BlockHier<R> block() const
     {
         BlockHier<R> B;
@@ -350,7 +352,8 @@ template <typename R>
 static void set_block_level(Hier<R> &H, int ng)
 {
     const Shape sh = launch_shape(ng, (int)sizeof(R));
-    H.tiled = sh.tiled;
+    H.tiled = sh.tiled > 3 ? 3 : sh.tiled;  // 4: the largest tiles for the transfers, fused sweeps
+    H.fused = sh.tiled == 4;
     H.block_l0 = kMaxLevels;
     for (int l = 0; l < H.nlev - 1; l++)
         if (H.L[l].n <= sh.block_n) {
@@ -406,6 +409,7 @@ struct KernelTiming {
 };
 static KernelTiming g_kt;
 constexpr size_t kTimingPairs = 16384;
+constexpr int kTimingSlots = 8;  // 0..3 half-sweeps, 4..7 fused sweeps (same order)
 
 template <typename R>
 static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool nl)
@@ -444,6 +448,49 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     H.next_part[l] = k ^ 1;
 }
 
+// One full sweep of level l: both colours in one launch where the level
+// takes the fused sweep, else two half-sweeps.
+template <typename R>
+static void sweep(Ctx &C, Hier<R> &H, int l, SolveConsts sc, bool nl)
+{
+    if (H.fused && !sc.jacobi && sweep2_fits(H.L[l].n, (int)sizeof(R))) {
+        const long long half = H.L[l].half;
+        const int orr = H.cur[l][0], ob = H.cur[l][1];
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (l == 0 && g_kt.on) {
+            std::lock_guard<std::mutex> g(g_kt.mu);
+            if (g_kt.used + 2 <= g_kt.pool.size()) {
+                e0 = g_kt.pool[g_kt.used];
+                e1 = g_kt.pool[g_kt.used + 1];
+                g_kt.used += 2;
+                g_kt.slot_of_pair.push_back(4 + (sizeof(R) == 4 ? 1 : 0) + (nl ? 0 : 2));
+            }
+        }
+        if (e0)
+            (void)hipEventRecord(e0, C.st);
+        ReduceSlot rs = C.rs;
+        const int k = H.next_part[l];
+        rs.partials = H.part(l, k);
+        int nb = 0;
+        const bool done = launch_sweep2<R>(H.L[l], H.buf[l][orr], H.buf[l][ob] + half, H.buf[l][1 - orr],
+                                           H.buf[l][1 - ob] + half, H.csum_cur(l), H.csum_alt(l), H.part(l, k ^ 1),
+                                           H.pend_nb[l], H.pend_col[l], rs, sc, nl, C.st, &nb);
+        if (e1)
+            (void)hipEventRecord(e1, C.st);
+        if (done) {
+            H.cur[l][0] = 1 - orr;
+            H.cur[l][1] = 1 - ob;
+            H.cs[l] ^= 1;
+            H.pend_col[l] = 2;
+            H.pend_nb[l] = nb;
+            H.next_part[l] = k ^ 1;
+            return;
+        }
+    }
+    smooth(C, H, l, 0, sc, nl);
+    smooth(C, H, l, 1, sc, nl);
+}
+
 constexpr int kCoarseSweeps = 100;
 
 // V-cycle below level l (level l's tau and csum are set).  Levels below get
@@ -464,10 +511,8 @@ static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveCon
         launch_coarsest<R>(H.L[l], H.xr(l), H.xb(l), sc, nl, kCoarseSweeps, C.st);
         return;
     }
-    for (int s = 0; s < o.n_pre; s++) {
-        smooth(C, H, l, 0, sc, nl);
-        smooth(C, H, l, 1, sc, nl);
-    }
+    for (int s = 0; s < o.n_pre; s++)
+        sweep(C, H, l, sc, nl);
     H.cur[l + 1][0] = H.cur[l + 1][1] = 0;
     launch_residual_restrict<R>(H.L[l], H.xr(l), H.xb(l), H.csum_cur(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.rs,
                                 sc, nl, C.st, false, H.tiled);
@@ -475,10 +520,8 @@ static void vcycle_from(Ctx &C, Hier<R> &H, int l, const pm_mg_opts &o, SolveCon
     H.fresh(l + 1);
     vcycle_from(C, H, l + 1, o, sc, nl);
     launch_prolong_correct<R>(H.L[l], H.xr(l), H.xb(l), H.L[l + 1], H.xr(l + 1), H.xb(l + 1), C.st, H.tiled);
-    for (int s = 0; s < o.n_post; s++) {
-        smooth(C, H, l, 0, sc, nl);
-        smooth(C, H, l, 1, sc, nl);
-    }
+    for (int s = 0; s < o.n_post; s++)
+        sweep(C, H, l, sc, nl);
 }
 
 // Full multigrid start from a zero iterate: each level's problem takes the
@@ -556,10 +599,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
     double out[8];
     int it = fmg;
     for (;; it++) {
-        for (int s = 0; s < o.n_pre; s++) {
-            smooth(C, H, 0, 0, sc, nl);
-            smooth(C, H, 0, 1, sc, nl);
-        }
+        for (int s = 0; s < o.n_pre; s++)
+            sweep(C, H, 0, sc, nl);
         H.cur[1][0] = H.cur[1][1] = 0;
         launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), H.L[1], H.xr(1), H.xb(1), C.rs, sc,
                                          nl, C.st, true, H.tiled);
@@ -587,10 +628,8 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
         H.fresh(1);
         vcycle_from(C, H, 1, o, sc, nl);
         launch_prolong_correct<double>(H.L[0], H.xr(0), H.xb(0), H.L[1], H.xr(1), H.xb(1), C.st, H.tiled);
-        for (int s = 0; s < o.n_post; s++) {
-            smooth(C, H, 0, 0, sc, nl);
-            smooth(C, H, 0, 1, sc, nl);
-        }
+        for (int s = 0; s < o.n_post; s++)
+            sweep(C, H, 0, sc, nl);
     }
     so.vcycles = it;
     // bring both colours back into the master buffer
@@ -1039,8 +1078,7 @@ int pm_deposit(const void *pos, long long np, pm_dtype dtype, int ng, void *rho,
     if (e)
         return e;
     unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
-    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
-    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
+    launch_deposit_auto(pos, np, dtype, ng, acc, C.ws + C.P.depidx, C.st);
     double *d0 = C.at<double>(C.P.delta64[0]);
     launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, d0, C.rs, C.st);
     // rho = delta_raw + 1 in natural order
@@ -1067,20 +1105,42 @@ int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, 
                   void *chi0_out, void *learned_ws, size_t learned_ws_bytes, void *ws, size_t ws_bytes,
                   pm_stream_t stream)
 {
-    if (!params || !learned_ws)
+    if (!params || !learned_ws || !rho || !p || !chi0_out || (dtype != PM_F32 && dtype != PM_F64))
         return PM_EINVAL;
-    pm_mg_opts o{};
-    o.rel_tol = 1e-300;  // never met: the solve stops before its first V-cycle
-    o.max_vcycles = 0;
-    o.n_pre = 1;
-    o.n_post = 2;
-    o.precision = PM_PREC_F64;
-    o.guess = PM_GUESS_LEARNED;
-    o.learned_params = params;
-    o.learned_ws = learned_ws;
-    o.learned_ws_bytes = learned_ws_bytes;
-    const int e = grid_solve(rho, ng, dtype, p, &o, chi0_out, nullptr, ws, ws_bytes, stream, true);
-    return e == PM_ENOCONV ? PM_OK : e;
+    pm_eft_coeffs cf;
+    int e = coefficients(*p, cf);
+    if (e)
+        return e;
+    Ctx C;
+    e = setup_ctx(C, ws, ws_bytes, ng, 0, dtype, kPrecF64, stream);
+    if (e)
+        return e;
+    launch_natural_to_packed(rho, dtype, C.at<double>(C.P.delta64[0]), ng, 1.0, -1.0, C.st);
+    double dsq = 0.0;
+    e = prepare_delta(C, &dsq);
+    if (e)
+        return e;
+    double *m = C.at<double>(C.P.chi64);
+    launch_zero(m, sizeof(double) * C.P.N, C.st);
+    const double src = cf.nu != 0.0 ? fabs(cf.xi * cf.s / cf.nu) * sqrt(dsq) : 0.0;
+    if (cf.xi != 0.0 && cf.K != 0.0 && src > 0.0) {  // (otherwise no learned guess: chi_0 = 0)
+        pm_mg_opts o{};
+        o.rel_tol = 1e-30;
+        o.max_vcycles = 1;
+        o.n_pre = 1;
+        o.n_post = 2;
+        o.precision = PM_PREC_F64;
+        o.guess = PM_GUESS_LEARNED;
+        o.learned_params = params;
+        o.learned_ws = learned_ws;
+        o.learned_ws_bytes = learned_ws_bytes;
+        e = learned_guess(C, *p, cf, o, src, false, false);
+        if (e)
+            return e;
+    }
+    launch_field_sum(m, C.P.N, C.rs, C.st);
+    launch_packed_to_natural(m, chi0_out, dtype, ng, 0.0, C.rs.out, C.st);
+    return launched();
 }
 
 // ---- batched solve ---------------------------------------------------------
@@ -1238,7 +1298,7 @@ int pm_get_launch_shape(int ng, int word_bytes, int *block_cycle_grid, int *tile
 int pm_set_launch_shape(int ng, int word_bytes, int block_cycle_grid, int tiled_smoother)
 {
     if ((word_bytes != 4 && word_bytes != 8) || block_cycle_grid < 0 || ng < 8 || tiled_smoother < 0 ||
-        tiled_smoother > 3)
+        tiled_smoother > 4)
         return PM_EINVAL;
     set_shape(Shape{ng, word_bytes, block_cycle_grid, tiled_smoother});
     return PM_OK;
@@ -1270,7 +1330,7 @@ int pm_autotune(int ng, int precision, void *ws, size_t ws_bytes, pm_stream_t st
     const int cands[5] = {0, 8, 16, 32, 64};
     Shape best = launch_shape(ng, word);
     float best_ms = 1e30f;
-    for (int tiled = 0; tiled < 4; tiled++)
+    for (int tiled = 0; tiled < 5; tiled++)
         for (int c = 0; c < 5; c++) {
             const int n = cands[c];
             if (n >= ng)
@@ -1326,7 +1386,7 @@ int pm_tune_load(const char *path)
             continue;
         int ng, word, n, tiled;
         if (sscanf(line, "%d %d %d %d", &ng, &word, &n, &tiled) != 4 || (word != 4 && word != 8) || n < 0 ||
-            ng < 8 || tiled < 0 || tiled > 3) {
+            ng < 8 || tiled < 0 || tiled > 4) {
             rc = PM_EINVAL;
             break;
         }
@@ -1550,8 +1610,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     // deposit -> packed delta
     Timer tdep(C.st);
     unsigned long long *acc = C.at<unsigned long long>(C.P.fixacc);
-    launch_zero(acc, sizeof(unsigned long long) * C.P.N, C.st);
-    launch_deposit_fixed(pos, np, dtype, ng, acc, C.st);
+    launch_deposit_auto(pos, np, dtype, ng, acc, C.ws + C.P.depidx, C.st);
     launch_fixed_to_delta(acc, ng, (double)C.P.N / (double)np, C.at<double>(C.P.delta64[0]), C.rs, C.st);
     double dsq = 0.0;
     e = prepare_delta(C, &dsq, start_network);
@@ -1905,12 +1964,12 @@ int pm_kernel_timing_enable(int on)
     return PM_OK;
 }
 
-int pm_kernel_timing_read(double *total_ms /* HOST [4] */, long long *launches /* HOST [4] */)
+int pm_kernel_timing_read(double *total_ms /* HOST [8] */, long long *launches /* HOST [8] */)
 {
     if (!total_ms || !launches)
         return PM_EINVAL;
     std::lock_guard<std::mutex> g(g_kt.mu);
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < kTimingSlots; q++) {
         total_ms[q] = 0.0;
         launches[q] = 0;
     }

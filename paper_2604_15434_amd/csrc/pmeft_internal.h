@@ -168,6 +168,17 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
                    double *csum_out, const double *prev, int prev_nblocks, int prev_colour, ReduceSlot rs,
                    SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out, int tiled);
 
+// Both colours of one red-black sweep in one launch (the 2.5D-tiled fused
+// sweep of sweep2_kernels.hip): red from (xr_old, xb_old) into xr_new, then
+// black from (xb_old, new red) into xb_new.  Returns false, launching
+// nothing, where the level does not tile that way or the smoother is Jacobi.
+template <typename R>
+bool launch_sweep2(const LevelView<R> &L, const R *xr_old, const R *xb_old, R *xr_new, R *xb_new,
+                   const double *csum_in, double *csum_out, const double *prev, int prev_nblocks, int prev_colour,
+                   ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st, int *nblocks_out);
+// whether a level of n cells per side takes the fused sweep
+bool sweep2_fits(int n, int word_bytes);
+
 // Fine-level residual r = Lq + tau - c - lap x fused with the 8-child
 // restriction into the coarse level: coarse tau <- R r, coarse x <- R x (also
 // into x0).  Accumulates sum r^2, sum r, sum Lq+tau into rs.out[0..2] and the
@@ -306,6 +317,12 @@ double *unet_save_area(void *ws, int ng);
 // ---- particle kernels (pm_kernels.hip) -----------------------------------
 void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc,
                           hipStream_t st);
+// The deposit pm_deposit and pm_step use: the gather over particles in CIC
+// base-row order, else the scatter (decided on the device; acc need not be
+// cleared).  idx: deposit_index_bytes(ng) bytes of workspace.
+size_t deposit_index_bytes(int ng);
+void launch_deposit_auto(const void *pos, long long np, pm_dtype dt, int ng, unsigned long long *acc, void *idx,
+                         hipStream_t st);
 // acc (fixed point) -> packed delta = rho - 1 (FP64); sum into rs.out[0]
 void launch_fixed_to_delta(const unsigned long long *acc, int ng, double rho_scale, double *delta_packed,
                            ReduceSlot rs, hipStream_t st);

@@ -77,11 +77,12 @@ def test_grid_levels_and_workspace():
 
 def test_step_workspace_holds_two_solves():
     """A step's two solves run side by side, so a step workspace holds, on top
-    of a grid-solve workspace, the deposit's fixed-point grid, the force grid,
-    a second delta hierarchy (the warm start's) and a second per-solve region
-    (reductions, lagged means, hierarchy buffers) of exactly the grid
-    workspace's size minus the shared arrays (FP64 plan: delta levels, psi,
-    chi; 256-byte granules, plus 256 bytes of slack)."""
+    of a grid-solve workspace, the deposit's fixed-point grid and its row
+    index (ng^2 + 65 words: a flag block and the first particle of every base
+    row), the force grid, a second delta hierarchy (the warm start's) and a
+    second per-solve region (reductions, lagged means, hierarchy buffers) of
+    exactly the grid workspace's size minus the shared arrays (FP64 plan:
+    delta levels, psi, chi; 256-byte granules, plus 256 bytes of slack)."""
     import paper_2604_15434_amd as P
 
     def r(b):
@@ -96,7 +97,7 @@ def test_step_workspace_holds_two_solves():
     step = P.pm_workspace_bytes(ng, n3, 1, "f64")
     region = grid - 256 - shared
     assert region > 8 * n3  # at least the finest level's second colour buffer
-    assert step == grid + r(8 * n3) + r(32 * n3) + delta + region
+    assert step == grid + r(8 * n3) + r(4 * (ng * ng + 65)) + r(32 * n3) + delta + region
 
 
 def test_launch_shape_table_roundtrip(tmp_path):
@@ -115,8 +116,10 @@ def test_launch_shape_table_roundtrip(tmp_path):
         P.pm_set_launch_shape(96, 2, 16)
     P.pm_set_launch_shape(96, 8, 16, 3)
     assert P.pm_get_launch_shape(96, 8) == (16, 3)
+    P.pm_set_launch_shape(96, 8, 16, 4)  # fused two-colour sweeps
+    assert P.pm_get_launch_shape(96, 8) == (16, 4)
     with pytest.raises(P.PmError):
-        P.pm_set_launch_shape(96, 8, 16, 4)
+        P.pm_set_launch_shape(96, 8, 16, 5)
     bad = tmp_path / "bad.txt"
     bad.write_text("96 3 16 1\n")
     with pytest.raises(P.PmError):

@@ -60,6 +60,32 @@ def test_deposit_matches_oracle(P, ng, kind):
     assert np.abs(rho32.cpu().numpy() - ref).max() < 2e-5 * max(1.0, ref.max())
 
 
+@pytest.mark.parametrize("ng,dtype", [(32, torch.float64), (64, torch.float32), (128, torch.float64),
+                                      (128, torch.float32)])
+def test_sorted_deposit_gathers_the_same_grid(P, ng, dtype):
+    """Particles in CIC base-row order (pm_sort_particles) take the gather
+    deposit (every cell summed once, no global atomics); the grid is bitwise
+    the scatter's (the same 2^-40 integer sums) and matches the oracle.  One
+    pair of particles swapped out of order sends the deposit back to the
+    scatter, again bitwise the same."""
+    pos_np, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=12)
+    pos = torch.from_numpy(pos_np).to("cuda", dtype)
+    rho_scatter = torch.empty((ng, ng, ng), dtype=dtype, device="cuda")
+    P.pm_deposit(pos, ng, rho_scatter)  # lognormal loads are in cell order, not base-row order: scatter
+    P.pm_sort_particles(pos, ng)
+    rho_gather = torch.empty_like(rho_scatter)
+    P.pm_deposit(pos, ng, rho_gather)
+    assert torch.equal(rho_gather, rho_scatter)
+    ref = oracle.cic_deposit(pos.cpu().numpy().astype(np.float64), ng)
+    tol = 1e-10 if dtype == torch.float64 else 2e-5 * max(1.0, ref.max())
+    assert np.abs(rho_gather.cpu().numpy() - ref).max() < tol
+    swapped = pos.clone()
+    swapped[:, [10, pos.shape[1] - 10]] = swapped[:, [pos.shape[1] - 10, 10]]
+    rho_swapped = torch.empty_like(rho_scatter)
+    P.pm_deposit(swapped, ng, rho_swapped)
+    assert torch.equal(rho_swapped, rho_scatter)
+
+
 # ------------------------------------------------------------------ Poisson
 @pytest.mark.parametrize("ng", [32, 48])
 def test_poisson_matches_fft_solution(P, ng):
@@ -383,13 +409,15 @@ def _cfg2_ref(k, f32_positions=False):
 
 
 @pytest.mark.timeout(1200)
+@pytest.mark.parametrize("shape", [3, 4])
 @pytest.mark.parametrize("mode", ["f64", "mixed", "learned"])
 @pytest.mark.parametrize("k", [0, 1])
-def test_pm_step_256_matches_oracle(P, k, mode):
+def test_pm_step_256_matches_oracle(P, k, mode, shape):
     """The 256^3 step of the benchmark workload against the oracle, on the
-    launch shape the benchmark's tuning keeps at this size (largest tiles:
-    16 rows x 64 packed cells x 16 planes for the finest smoother, block
-    cycle from 8^3): FP64 fields and particles at 1e-12 (chi within 1e-10),
+    launch shapes the benchmark's tuning chooses from at this size (block
+    cycle from 8^3; shape 3: largest tiles, 16 rows x 64 packed cells x 16
+    planes, for the half-sweeps; shape 4: fused two-colour sweeps): FP64
+    fields and particles at 1e-12 (chi within 1e-10),
     FP32 particles with mixed-precision solves at 1e-7 (chi within 1e-5),
     and the same with the learned warm start; force RMS error within 1e-4
     (FP64: 1e-9), the void-cell count equal, and the maximum P_chi(k) error
@@ -405,7 +433,7 @@ def test_pm_step_256_matches_oracle(P, k, mode):
     saved = {w: P.pm_get_launch_shape(ng, w) for w in (4, 8)}
     try:
         for w in (4, 8):
-            P.pm_set_launch_shape(ng, w, 8, 3)
+            P.pm_set_launch_shape(ng, w, 8, shape)
         gp = dev(pos, dtype)
         gv = torch.zeros_like(gp)
         psi = torch.zeros((ng, ng, ng), dtype=dtype, device="cuda")
@@ -430,7 +458,7 @@ def test_pm_step_256_matches_oracle(P, k, mode):
     cerr = rel(chi_g, ref["chi"])
     _, pk_g, _ = oracle.power_spectrum(chi_g, 500.0)
     perr = float(np.max(np.abs(pk_g / ref["pk"] - 1.0)))
-    print(f"256^3 alpha_B0={prm['alpha_b0']} {mode}: force {ferr:.2e} chi {cerr:.2e} P_chi(k) max {perr:.2e} "
+    print(f"256^3 alpha_B0={prm['alpha_b0']} {mode} shape {shape}: force {ferr:.2e} chi {cerr:.2e} P_chi(k) max {perr:.2e} "
           f"V-cycles chi {rep['scalar']['vcycles']} psi {rep['poisson']['vcycles']} "
           f"clamped {rep['scalar']['clamped_cells']} (oracle {ref['clamped']})")
     assert rep["scalar"]["clamped_cells"] == ref["clamped"]
@@ -581,23 +609,33 @@ def test_block_cycle_matches_per_level_launches(P, ng, precision):
                                           (256, "f64")])
 def test_tiled_smoother_matches_untiled(P, ng, precision):
     """The 2.5D-tiled half-sweep computes the same cell updates; whole solves
-    differ only through the grouping of the lagged-mean partial sums."""
+    differ only through the grouping of the lagged-mean partial sums.  Shape
+    4 (the fused two-colour sweep on levels whose half-row is a multiple of
+    64) reaches the same field: its black half takes the lagged mean of its
+    red half."""
     rho = torch.from_numpy(lognormal_density(ng, 500.0 * ng / 256, seed=23)).cuda()
     prm = dict(omega_m0=0.3071, alpha_b0=-0.6, alpha_m0=0.1, a=1.0)
     opts = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision=precision)
     out = {}
     try:
-        for tiled in (0, 1, 2, 3):
+        for tiled in (0, 1, 2, 3, 4):
             for word in (4, 8):
                 P.pm_set_launch_shape(ng, word, 8, tiled)
             chi = torch.zeros_like(rho)
             rep = P.mg_scalar_solve(rho, prm, opts, chi)
             assert rep["status"] == 0
             out[tiled] = (chi, rep)
+            if tiled == 4:  # the Poisson solve through the fused linear sweep as well
+                psi4, psi0 = torch.zeros_like(rho), torch.zeros_like(rho)
+                assert P.mg_poisson_solve(rho, prm, opts, psi4)["status"] == 0
+                for word in (4, 8):
+                    P.pm_set_launch_shape(ng, word, 8, 0)
+                assert P.mg_poisson_solve(rho, prm, opts, psi0)["status"] == 0
+                assert float((psi4 - psi0).norm() / psi0.norm()) < 1e-9
     finally:
         for word in (4, 8):
             P.pm_set_launch_shape(ng, word, 8, 1)
-    for tiled in (1, 2, 3):
+    for tiled in (1, 2, 3, 4):
         err = float((out[tiled][0] - out[0][0]).norm() / out[0][0].norm())
         assert err < 1e-9, (tiled, err)
         assert abs(out[tiled][1]["vcycles"] - out[0][1]["vcycles"]) <= 1
@@ -607,7 +645,7 @@ def test_tiled_smoother_matches_untiled(P, ng, precision):
 def test_autotune_picks_a_candidate(P):
     ng = 64
     n, tiled = P.pm_autotune(ng, "mixed")
-    assert n in (0, 8, 16, 32) and tiled in (0, 1, 2, 3)
+    assert n in (0, 8, 16, 32) and tiled in (0, 1, 2, 3, 4)
     rho = torch.from_numpy(lognormal_density(ng, 125.0, seed=22)).cuda()
     chi = torch.zeros_like(rho)
     rep = P.mg_scalar_solve(rho, dict(omega_m0=0.3071, alpha_b0=-0.3, alpha_m0=0.0, a=1.0),
