@@ -157,6 +157,21 @@ size_t pm_workspace_bytes(int ng, long long np, pm_dtype dtype, pm_prec prec);
 int pm_deposit(const void *pos, long long np, pm_dtype dtype, int ng, void *rho,
                void *ws, size_t ws_bytes, pm_stream_t stream);
 
+/* The CIC deposit of pm_deposit without a caller workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the call allocates
+ * nothing; its scratch (the fixed-point accumulator, the packed density and
+ * the reduction partials, 16 bytes per cell plus 128 KiB) lives in a device
+ * array of pm_deposit_noalloc_max_bytes() = 33 MiB inside the library, one
+ * per GPU, held until the process ends.  Same arguments and result as
+ * pm_deposit (bit for bit); ng up to 128 (PM_ENOMEM beyond: the scratch
+ * array is too small), PM_EINVAL as pm_deposit.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's contents (the
+ * accumulator is cleared by each call): calls that overlap on one GPU, on
+ * any streams, race. */
+size_t pm_deposit_noalloc_max_bytes(void);
+int pm_deposit_noalloc(const void *pos, long long np, pm_dtype dtype, int ng, void *rho, pm_stream_t stream);
+
 /* Newtonian potential (eq. phipsi_mod with Geff/G inside s): solve
  * lap_7 Psi_N = s (rho - 1 - <rho - 1>), <Psi_N> = 0, by red-black
  * Gauss-Seidel V-cycles.  rho: ng^3 in; psi: ng^3 in (guess if GIVEN) / out. */

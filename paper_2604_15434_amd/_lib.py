@@ -65,7 +65,7 @@ EXPORTS = ("pm_eft_coefficients", "pm_grid_levels", "pm_workspace_bytes", "pm_de
            "pm_autotune", "pm_get_launch_shape", "pm_set_launch_shape", "pm_tune_save", "pm_tune_load", "ws_unet_param_count", "ws_unet_workspace_bytes", "ws_unet_forward", "ws_unet_train_step",
            "ws_unet_forward_train", "ws_unet_backward", "ws_adam_workspace_bytes", "ws_adam_step",
            "ws_unet_tensor", "ws_conv3", "ws_conv3_first", "pm_potentials", "pm_evolve", "pm_code_time",
-           "pm_plan_check", "pm_set_step_concurrency", "ws_unet_guess", "pm_power_workspace_bytes", "pm_field_power", "pm_particle_power", "pm_boost")
+           "pm_plan_check", "pm_set_step_concurrency", "pm_deposit_noalloc", "pm_deposit_noalloc_max_bytes", "ws_unet_guess", "pm_power_workspace_bytes", "pm_field_power", "pm_particle_power", "pm_boost")
 
 
 def _load():
@@ -134,6 +134,9 @@ def _load():
     lib.pm_particle_power.restype = i
     lib.pm_boost.argtypes = [P(d), P(d), P(d), i, d, P(d)]
     lib.pm_boost.restype = i
+    lib.pm_deposit_noalloc.argtypes = [vp, ll, i, i, vp, vp]
+    lib.pm_deposit_noalloc.restype = i
+    lib.pm_deposit_noalloc_max_bytes.restype = sz
     lib.pm_set_step_concurrency.argtypes = [i]
     lib.pm_set_step_concurrency.restype = i
     lib.ws_unet_guess.argtypes = [vp, vp, i, i, P(EftParams), vp, vp, sz, vp, sz, vp]

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmeft.so")
 SOURCES = ["mg_kernels.hip", "smooth_kernels.hip", "tile_kernels.hip", "pm_kernels.hip", "pmeft_api.hip", "unet_kernels.hip",
-           "unet_api.hip", "spectrum_kernels.hip", "sweep2_kernels.hip"]
+           "unet_api.hip", "spectrum_kernels.hip", "sweep2_kernels.hip", "noalloc_api.hip"]
 ARCH = os.environ.get("PMEFT_ARCH", "gfx950")
 
 
