@@ -127,15 +127,18 @@ def run_mode(P, torch, mode, pos_np, ng, steps, warmup, net=None, presort=False)
                 itemsize=8 if dt == torch.float64 else 4)
 
 
-SMOOTHER_SOURCES = [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f)
-                    for f in ("mg_stencil.h", "tile_window.h", "smooth_kernels.hip", "sweep2_kernels.hip")]
+def smoother_sources(kernel):
+    """Source files that define a smoother kernel: the half-sweep kernels, or
+    the fused two-colour sweep."""
+    last = "sweep2_kernels.hip" if kernel.startswith("k_sweep2_tile") else "smooth_kernels.hip"
+    return [os.path.join(ROOT, "paper_2604_15434_amd", "csrc", f) for f in ("mg_stencil.h", "tile_window.h", last)]
 
 
-def smoother_source_hash():
+def smoother_source_hash(kernel):
     import hashlib
 
     h = hashlib.sha256()
-    for f in SMOOTHER_SOURCES:
+    for f in smoother_sources(kernel):
         h.update(open(f, "rb").read())
     return h.hexdigest()
 
@@ -145,10 +148,11 @@ def smoother_kernel(itemsize, tiled, ng):
     (the tile configuration rule of smooth_kernels.hip)."""
     r = "double" if itemsize == 8 else "float"
     nh = ng // 2
-    tj, tk = (16, 32) if itemsize == 8 else (8, 64)
-    if tiled == 4 and ng >= 64 and nh % tk == 0 and ng % tj == 0 and ng % 16 == 0:
-        pl = 32 if ng % 32 == 0 and (ng // 32) * (ng // tj) * (nh // tk) >= 512 else 16
-        return f"k_sweep2_tile<{r}, true, {tk}, {tj}, {pl}, true>"
+    tj, tk = 8, (32 if itemsize == 8 else 64)
+    # the fused sweep: tiles of tj rows by tk packed elements, chunks of at
+    # least 8 planes, at least 256 tiles (sweep2_kernels.hip)
+    if tiled == 4 and ng >= 64 and nh % tk == 0 and ng % tj == 0 and (ng // tj) * (nh // tk) * (ng // 8) >= 256:
+        return f"k_sweep2_tile<{r}, true, {tk}, {tj}>"
     if tiled and ng >= 64:
         if tiled == 3 and nh % 64 == 0 and ng % 16 == 0 and (ng // 16) * (nh // 64) * (ng // 16) >= 512:
             return f"k_smooth_tile<{r}, true, 64, 4, 16>"
@@ -169,10 +173,8 @@ def measured_traffic(kernel, ng):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != smoother_source_hash():
-        return None
     for k in rec.get("kernels", {}).values():
-        if k.get("kernel") == kernel:
+        if k.get("kernel") == kernel and k.get("source_sha256") == smoother_source_hash(kernel):
             return round(k["traffic_bytes"])
     return None
 
@@ -250,7 +252,32 @@ def cpu_baseline(pos_np, ng):
     return {"value": round(ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
             "sample": (f"oracle on the {ng}^3 workload: deposit+interpolation on 1/8 of the particles (x8), "
                        f"FFT Poisson, 1 FAS V-cycle at {ng}^3 ({t_cyc:.2f} s) x {rep64['vcycles']} V-cycles "
-                       f"(oracle count to 1e-7 at 64^3, same statistics), gradient; OpenMP threads {threads}")}
+                       f"(oracle count to 1e-7 at 64^3, same statistics), gradient; OpenMP threads {threads}"),
+            "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def one_thread_baseline(ng, ics):
+    """The same bounded sample with one OpenMP thread, in a child process (the
+    oracle's thread count is fixed when its library loads).  The child runs
+    only the oracle: it imports no GPU code."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--ng", str(ng),
+                          "--ics", ics], env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode != 0:
+        return None
+    return json.loads(out.stdout.strip().splitlines()[-1])
 
 
 def run_scan(P, torch, per_size=16, sizes=(64, 128, 192, 256), tol=1e-7):
@@ -294,6 +321,19 @@ def run_scan(P, torch, per_size=16, sizes=(64, 128, 192, 256), tol=1e-7):
             "cells": cells, "cells_vcycles_per_s": round(cyc / (batched * 1e-3), 1)}
 
 
+def make_particles(ng, ics):
+    """Particle positions of the workload (host, [3, ng^3]) and the box size."""
+    if ics == "lognormal":
+        from workloads import lognormal_particles
+
+        box = 500.0 * ng / 256
+        return lognormal_particles(ng, box, seed=2)[0], box
+    from workloads import zeldovich_ics
+
+    box = 1000.0 * ng / 512
+    return zeldovich_ics(ng, box, seed=5), box
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,7 +353,12 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2604_15434_amd", "weights", "unet_warmstart.f32"))
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="print only the oracle's bounded-sample figure for the workload (no GPU)")
     args = ap.parse_args()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(make_particles(args.ng, args.ics)[0], args.ng)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -321,7 +366,6 @@ def main():
     import torch
 
     import paper_2604_15434_amd as P
-    from workloads import lognormal_particles
 
     ng = args.ng
     if args.calib_copy:
@@ -331,14 +375,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     print(f"[bench] generating {ng}^3 {args.ics} particles", file=sys.stderr, flush=True)
-    if args.ics == "lognormal":
-        box = 500.0 * ng / 256
-        pos_np, _ = lognormal_particles(ng, box, seed=2)
-    else:
-        from workloads import zeldovich_ics
-
-        box = 1000.0 * ng / 512
-        pos_np = zeldovich_ics(ng, box, seed=5)
+    pos_np, box = make_particles(ng, args.ics)
     modes = args.modes.split(",")
     net = None
     if "learned" in modes:
@@ -409,6 +446,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(pos_np, ng)
+        one = one_thread_baseline(ng, args.ics)
+        if one:
+            line["cpu_baseline"]["one_thread"] = {"value": one["value"], "unit": "ms", "cores": 1}
     print(json.dumps(line), flush=True)
 
 

@@ -36,6 +36,31 @@ __device__ __forceinline__ double rcp_nr(double x)
     return r;
 }
 
+// Root of the local quadratic without a branch: both cases are evaluated
+// with the operations of root_lap below and the void value is selected, so
+// that a kernel updating several cells per thread can interleave them.
+template <typename T>
+__device__ __forceinline__ T root_lap_select(T b, T Tsh, const SolveConsts &sc, bool nonlinear)
+{
+    const T nu = (T)sc.nu;
+    if (!nonlinear)
+        return b / nu;
+    const T K = (T)sc.K;
+    const T dsph = nu * nu - (T)(8.0 / 3.0) * K * b;
+    const T G = K * Tsh - b;
+    const T disc = dsph + (T)(8.0 / 3.0) * K * K * Tsh;
+    T r;
+    if constexpr (sizeof(T) == 4)
+        r = (T)-2 * G * __builtin_amdgcn_rcpf(nu + __builtin_amdgcn_sqrtf(disc));
+    else
+        r = (T)-2 * G * rcp_nr(nu + sqrt_nr(disc));
+    // r is pinned (an empty asm statement that reads it): otherwise the
+    // compiler turns the select back into a branch around r and its operand
+    // loads
+    asm volatile("" ::"v"(r));
+    return dsph < (T)0 ? (T)0.75 * nu / K : r;
+}
+
 // Void-cell test and root of the local quadratic, computed in the type T.
 template <typename T>
 __device__ __forceinline__ T root_lap(T b, T Tsh, const SolveConsts &sc, bool nonlinear, int &is_void)

@@ -610,9 +610,9 @@ def test_block_cycle_matches_per_level_launches(P, ng, precision):
 def test_tiled_smoother_matches_untiled(P, ng, precision):
     """The 2.5D-tiled half-sweep computes the same cell updates; whole solves
     differ only through the grouping of the lagged-mean partial sums.  Shape
-    4 (the fused two-colour sweep on levels whose half-row is a multiple of
-    64) reaches the same field: its black half takes the lagged mean of its
-    red half."""
+    4 (the fused two-colour sweep on the levels of 128^3 and up whose tiles
+    divide them: FP32 at 128 and 256, FP64 at 128, 192 and 256) reaches the
+    same field: its black half takes the lagged mean of its red half."""
     rho = torch.from_numpy(lognormal_density(ng, 500.0 * ng / 256, seed=23)).cuda()
     prm = dict(omega_m0=0.3071, alpha_b0=-0.6, alpha_m0=0.1, a=1.0)
     opts = P.MgOpts(rel_tol=1e-11, max_vcycles=60, precision=precision)
