@@ -348,8 +348,9 @@ def main():
     ap.add_argument("--ics", default="lognormal", choices=("lognormal", "zeldovich"),
                     help="lognormal: ng^3 particles from the log-sigma 1.5 lognormal density (seed 2, 500 ng/256 "
                          "Mpc/h); zeldovich: Zel'dovich load of the sigma8 = 0.8 spectrum (seed 5, 1000 ng/512 Mpc/h)")
-    ap.add_argument("--scan", action="store_true",
-                    help="also time the batched parameter scan (16 problems each at 64^3..256^3)")
+    ap.add_argument("--no-scan", action="store_true",
+                    help="skip the batched parameter scan (16 problems each at 64^3..256^3), timed by default "
+                         "after the steps at 256^3")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (reference for HBM byte counters)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2604_15434_amd", "weights", "unet_warmstart.f32"))
@@ -439,7 +440,7 @@ def main():
         "roofline": roofline(r, ng, tiled_of(head)),
         "roofline_modes": {m: roofline(res, ng, tiled_of(m)) for m, res in results.items()},
     }
-    if args.scan:
+    if not args.no_scan and ng == 256:
         print("[bench] batched parameter scan", file=sys.stderr, flush=True)
         line["scan"] = run_scan(P, torch)
         print(f"[bench] scan: {line['scan']}", file=sys.stderr, flush=True)
