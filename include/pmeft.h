@@ -321,16 +321,24 @@ int pm_sort_particles(void *pos, void *vel, long long *ids, long long np, int ng
                       size_t ws_bytes, pm_stream_t stream);
 
 /* ---- Batched solves ------------------------------------------------------
- * Many independent scalar-field problems (a parameter scan, several boxes)
- * in one call.  Each problem has its own grid size, precision of its arrays,
- * parameters and hierarchy; its result and report equal those of
- * mg_scalar_solve on the same problem bit for bit.  The problems run
- * concurrently on internal streams (host worker threads, largest grid first);
- * the call waits for work already queued on `stream`, and returns when every
- * problem is solved (all output arrays are complete).  opts apply to every
- * problem (PM_GUESS_LEARNED is not accepted here).  Returns PM_OK, PM_ENOCONV
- * if some problem stopped at max_vcycles, or the first hard error; reps
- * (HOST, nprob entries, nullable) receive the per-problem reports. */
+ * Many independent scalar-field problems (a parameter scan, several boxes;
+ * the batched scan of Sec. 4's parameter studies) in one call.  Each problem
+ * has its own grid size, precision of its arrays, parameters and hierarchy;
+ * its result and report equal those of mg_scalar_solve on the same problem
+ * bit for bit.  Problems of one grid size and dtype form a group, solved in
+ * lockstep: every kernel of the solve is one launch for all members still
+ * iterating (grid rows select the member), so small grids fill the GPU
+ * together; a member leaves at its own convergence test, and the mixed-
+ * precision members that finish in FP64 do so together.  Members with
+ * screening off (linear) are solved one after another.  Groups run largest
+ * grid first, all on `stream` (no host threads); the call returns when every
+ * problem is solved (all output arrays complete).  opts apply to every
+ * problem (PM_GUESS_LEARNED is not accepted here).  Workspace
+ * (mg_batched_workspace_bytes, 256-byte aligned): the largest group's
+ * members' solver workspaces side by side, plus a small control area.
+ * Returns PM_OK, PM_ENOCONV if some problem stopped at max_vcycles, or the
+ * first hard error; reps (HOST, nprob entries, nullable) receive the
+ * per-problem reports (ms: the time of the problem's group). */
 typedef struct {
     const void *rho;     /* ng^3 density (device), natural order */
     void *chi;           /* ng^3 out (guess in if GIVEN) */
@@ -356,11 +364,12 @@ int mg_scalar_solve_batched(const pm_problem *probs /* HOST */, int nprob, const
  *    planes, 8 in FP64) replace small ones (4 rows x 64 or 8 rows x 32, 8
  *    planes) where they still give 512 tiles, and the largest (16 rows x 64 x
  *    16 planes) replace large ones under the same rule; 4: the largest tiles
- *    for the transfers, and every red-black sweep of a level with grid >= 64
- *    (grid / 2 divisible by 64) runs both colours in one launch: each tile
- *    updates its red cells plus a one-cell halo, then its black cells from
- *    those new red values, so the sweep reads the old values once (the black
- *    half then takes the lagged mean the red half takes).
+ *    for the transfers, and every red-black sweep of a level whose tiles (8
+ *    rows by 32 packed cells in FP64, 64 in FP32) divide it into at least
+ *    256 tiles runs both colours in one launch: each tile updates its red
+ *    cells plus a one-cell halo one plane ahead of its black cells, which
+ *    take those new red values, so the sweep reads the old values once (the
+ *    black half then takes the lagged mean the red half takes).
  * Defaults 8 and 1.  They change the cost of a cycle, and the grouping of
  * the partial sums behind the lagged means, not the converged answer.
  * pm_autotune times full multigrid + 3 V-cycles of the scalar field on a

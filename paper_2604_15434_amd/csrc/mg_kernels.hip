@@ -25,6 +25,14 @@
 
 namespace pmeft {
 
+namespace {
+thread_local Group t_group;
+}
+const Group &cur_group() { return t_group; }
+void set_cur_group(const Group &g) { t_group = g; }
+GroupScope::GroupScope(const Group &g) : prev(t_group) { t_group = g; }
+GroupScope::~GroupScope() { t_group = prev; }
+
 // Per-thread stage of the finalize kernels: thread t adds, in order, the
 // rows b = t, t + kBlock, ... (< nblocks) of the partials, each value q into
 // acc[q].  All of a thread's rows are loaded (64 bytes each) before any is
@@ -55,8 +63,11 @@ __device__ __forceinline__ void finalize_rows(const double *__restrict__ partial
 
 // One block: out[q] = sum over blocks b (in order) of partials[b * 8 + q].
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partials, int nblocks, int nv,
-                                                     double *__restrict__ out)
+                                                     double *__restrict__ out, Group grp)
 {
+    const long long go = group_offset(grp);
+    partials = gshift(partials, go);
+    out = gshift(out, go);
     __shared__ double sm[8][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double acc[8];
@@ -82,8 +93,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
 
 void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, (const double *)rs.partials, (int)sp.nblocks, nv,
-                       out);
+    hipLaunchKernelGGL(k_finalize, group_grid(1), dim3(kBlock), 0, st, (const double *)rs.partials, (int)sp.nblocks, nv,
+                       out, cur_group());
 }
 
 // k_finalize for the six sums of the mixed-precision outer residual, which
@@ -91,8 +102,13 @@ void launch_finalize(const ReduceSlot &rs, const Span &sp, int nv, double *out, 
 // lag32[0..1] = sums 4, 5), saving the copies a separate launch would need.
 __global__ __launch_bounds__(kBlock) void k_finalize_outer(const double *__restrict__ partials, int nblocks,
                                                            double *__restrict__ out, double *__restrict__ lag64,
-                                                           double *__restrict__ lag32)
+                                                           double *__restrict__ lag32, Group grp)
 {
+    const long long go = group_offset(grp);
+    partials = gshift(partials, go);
+    out = gshift(out, go);
+    lag64 = gshift(lag64, go);
+    lag32 = gshift(lag32, go);
     constexpr int nv = 6;
     __shared__ double sm[nv][kBlock / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -191,8 +207,18 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict(LevelView<R> F, co
                                                               const R *__restrict__ xb, const double *__restrict__ csum,
                                                               LevelView<R> C, R *__restrict__ cxr,
                                                               R *__restrict__ cxb, ReduceSlot rs, SolveConsts sc,
-                                                              Span sp)
+                                                              Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    csum = gshift(csum, go);
+    cxr = gshift(cxr, go);
+    cxb = gshift(cxb, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     const double cm = (csum[0] + csum[1]) / (2.0 * (double)F.half);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
@@ -213,11 +239,11 @@ void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, c
     }
     const Span sp = make_span(2 * C.half);
     if (nonlinear)
-        hipLaunchKernelGGL((k_residual_restrict<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, C,
-                           cxr, cxb, rs, sc, sp);
+        hipLaunchKernelGGL((k_residual_restrict<R, true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb,
+                           csum, C, cxr, cxb, rs, sc, sp, cur_group());
     else
-        hipLaunchKernelGGL((k_residual_restrict<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, C,
-                           cxr, cxb, rs, sc, sp);
+        hipLaunchKernelGGL((k_residual_restrict<R, false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb,
+                           csum, C, cxr, cxb, rs, sc, sp, cur_group());
     if (norms)
         launch_finalize(rs, sp, 4, rs.out, st);
 }
@@ -258,8 +284,14 @@ __device__ __forceinline__ void fas_cell(const LevelView<R> &C, const R *__restr
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlock) void k_fas_tau(LevelView<R> C, const R *__restrict__ xr,
                                                     const R *__restrict__ xb, ReduceSlot rs, SolveConsts sc, Span sp,
-                                                    int accumulate_only)
+                                                    int accumulate_only, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     double acc[2] = {0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
     fas_cell<R, NL>(C, xr, xb, sc, e, accumulate_only, acc);
@@ -278,11 +310,11 @@ void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csu
     }
     const Span sp = make_span(2 * C.half);
     if (nonlinear)
-        hipLaunchKernelGGL((k_fas_tau<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
-                           acc_only);
+        hipLaunchKernelGGL((k_fas_tau<R, true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
+                           acc_only, cur_group());
     else
-        hipLaunchKernelGGL((k_fas_tau<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
-                           acc_only);
+        hipLaunchKernelGGL((k_fas_tau<R, false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, C, xr, xb, rs, sc, sp,
+                           acc_only, cur_group());
     launch_finalize(rs, sp, 2, csum, st);
 }
 
@@ -307,8 +339,15 @@ __device__ __forceinline__ void prolong_cell(const LevelView<R> &F, R *__restric
 template <typename R, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_prolong(LevelView<R> F, R *__restrict__ xr, R *__restrict__ xb,
                                                     LevelView<R> C, const R *__restrict__ cxr,
-                                                    const R *__restrict__ cxb, Span sp)
+                                                    const R *__restrict__ cxb, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    cxr = gshift(cxr, go);
+    cxb = gshift(cxb, go);
     PM_SPAN_LOOP(e, sp)
     prolong_cell<R, CORR>(F, xr, xb, C, cxr, cxb, e);
 }
@@ -370,7 +409,8 @@ void launch_prolong_correct(const LevelView<R> &F, R *xr, R *xb, const LevelView
     if (launch_prolong_tiled<R>(F, xr, xb, C, cxr, cxb, true, st, tiled))
         return;
     const Span sp = make_span(2 * C.half);
-    hipLaunchKernelGGL((k_prolong<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
+    hipLaunchKernelGGL((k_prolong<R, true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp,
+                       cur_group());
 }
 
 template <typename R>
@@ -380,7 +420,8 @@ void launch_prolong_full(const LevelView<R> &F, R *xr, R *xb, const LevelView<R>
     if (launch_prolong_tiled<R>(F, xr, xb, C, cxr, cxb, false, st, tiled))
         return;
     const Span sp = make_span(2 * C.half);
-    hipLaunchKernelGGL((k_prolong<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp);
+    hipLaunchKernelGGL((k_prolong<R, false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp,
+                       cur_group());
 }
 
 // ------------------------------------------------------------- coarsest
@@ -565,8 +606,13 @@ __device__ void coarsest_wave(const LevelView<R> &C, R *xr, R *xb, const SolveCo
 
 template <typename R, bool NL>
 __global__ __launch_bounds__(kBlock) void k_coarsest(LevelView<R> C, R *xr, R *xb, SolveConsts sc, int sweeps,
-                                                     double tol)
+                                                     double tol, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    gconsts(sc, grp);
     if (C.n == 4) {
         if (threadIdx.x < 64)
             coarsest_wave<R, NL>(C, xr, xb, sc, sweeps, tol);
@@ -579,16 +625,23 @@ template <typename R>
 void launch_coarsest(const LevelView<R> &C, R *xr, R *xb, SolveConsts sc, bool nonlinear, int sweeps, hipStream_t st)
 {
     if (nonlinear)
-        hipLaunchKernelGGL((k_coarsest<R, true>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol);
+        hipLaunchKernelGGL((k_coarsest<R, true>), group_grid(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol,
+                           cur_group());
     else
-        hipLaunchKernelGGL((k_coarsest<R, false>), dim3(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol);
+        hipLaunchKernelGGL((k_coarsest<R, false>), group_grid(1), dim3(kBlock), 0, st, C, xr, xb, sc, sweeps, kCoarseTol,
+                           cur_group());
 }
 
 // ------------------------------------------------------------- transfers
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_restrict_field(int nc, const R *__restrict__ fr, const R *__restrict__ fb,
-                                                           R *__restrict__ cr, R *__restrict__ cb, Span sp)
+                                                           R *__restrict__ cr, R *__restrict__ cb, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    fr = gshift(fr, go);
+    fb = gshift(fb, go);
+    cr = gshift(cr, go);
+    cb = gshift(cb, go);
     const int nch = nc / 2, nf = 2 * nc, nfh = nc;
     PM_SPAN_LOOP(e, sp)
     {
@@ -609,11 +662,16 @@ template <typename R>
 void launch_restrict_field(int nc, const R *fr, const R *fb, R *cr, R *cb, hipStream_t st)
 {
     const Span sp = make_span((unsigned long long)nc * nc * nc);
-    hipLaunchKernelGGL((k_restrict_field<R>), dim3(sp.nblocks), dim3(kBlock), 0, st, nc, fr, fb, cr, cb, sp);
+    hipLaunchKernelGGL((k_restrict_field<R>), group_grid(sp.nblocks), dim3(kBlock), 0, st, nc, fr, fb, cr, cb, sp,
+                       cur_group());
 }
 
-__global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double *__restrict__ s, float *__restrict__ d, Span sp)
+__global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double *__restrict__ s, float *__restrict__ d, Span sp,
+                                                         Group grp)
 {
+    const long long go = group_offset(grp);
+    s = gshift(s, go);
+    d = gshift(d, go);
     PM_SPAN_LOOP(e, sp)
     d[e] = (float)s[e];
 }
@@ -621,14 +679,17 @@ __global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double *__restric
 void launch_cast_f64_f32(const double *src, float *dst, long long n, hipStream_t st)
 {
     const Span sp = make_span(n);
-    hipLaunchKernelGGL(k_cast_f64_f32, dim3(sp.nblocks), dim3(kBlock), 0, st, src, dst, sp);
+    hipLaunchKernelGGL(k_cast_f64_f32, group_grid(sp.nblocks), dim3(kBlock), 0, st, src, dst, sp, cur_group());
 }
 
 // natural [i][j][k] (float or double) -> packed double, y = scale * x + shift
 template <typename Tn>
 __global__ __launch_bounds__(kBlock) void k_nat_to_packed(const Tn *__restrict__ nat, double *__restrict__ packed, int n,
-                                                          double scale, double shift, Span sp)
+                                                          double scale, double shift, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    nat = gshift(nat, go);
+    packed = gshift(packed, go);
     const int nh = n / 2;
     const unsigned half = (unsigned)n * n * nh;
     PM_SPAN_LOOP(e, sp)
@@ -647,19 +708,23 @@ void launch_natural_to_packed(const void *nat, pm_dtype dt, double *packed, int 
 {
     const Span sp = make_span((unsigned long long)n * n * n);
     if (dt == PM_F64)
-        hipLaunchKernelGGL((k_nat_to_packed<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)nat,
-                           packed, n, scale, shift, sp);
+        hipLaunchKernelGGL((k_nat_to_packed<double>), group_grid(sp.nblocks), dim3(kBlock), 0, st,
+                           (const double *)nat, packed, n, scale, shift, sp, cur_group());
     else
-        hipLaunchKernelGGL((k_nat_to_packed<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)nat, packed,
-                           n, scale, shift, sp);
+        hipLaunchKernelGGL((k_nat_to_packed<float>), group_grid(sp.nblocks), dim3(kBlock), 0, st, (const float *)nat,
+                           packed, n, scale, shift, sp, cur_group());
 }
 
 // packed double -> natural, subtracting sum_ptr[0] / n^3 (the mean) if given
 // and adding `add`
 template <typename Tn>
 __global__ __launch_bounds__(kBlock) void k_packed_to_nat(const double *__restrict__ packed, Tn *__restrict__ nat, int n,
-                                                          const double *sum_ptr, double add, Span sp)
+                                                          const double *sum_ptr, double add, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    packed = gshift(packed, go);
+    nat = gshift(nat, go);
+    sum_ptr = gshift(sum_ptr, go);
     const int nh = n / 2;
     const unsigned half = (unsigned)n * n * nh;
     const double shift = sum_ptr ? sum_ptr[0] / (2.0 * (double)half) : 0.0;
@@ -679,11 +744,11 @@ void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int 
 {
     const Span sp = make_span((unsigned long long)n * n * n);
     if (dt == PM_F64)
-        hipLaunchKernelGGL((k_packed_to_nat<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, packed, (double *)nat, n,
-                           sum_ptr, add, sp);
+        hipLaunchKernelGGL((k_packed_to_nat<double>), group_grid(sp.nblocks), dim3(kBlock), 0, st, packed,
+                           (double *)nat, n, sum_ptr, add, sp, cur_group());
     else
-        hipLaunchKernelGGL((k_packed_to_nat<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, packed, (float *)nat, n,
-                           sum_ptr, add, sp);
+        hipLaunchKernelGGL((k_packed_to_nat<float>), group_grid(sp.nblocks), dim3(kBlock), 0, st, packed,
+                           (float *)nat, n, sum_ptr, add, sp, cur_group());
 }
 
 // ------------------------------------------------------------ mixed precision
@@ -696,8 +761,18 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
                                                         const double *__restrict__ xb, const double *__restrict__ csum64,
                                                         LevelView<float> G, float *__restrict__ x32r,
                                                         float *__restrict__ x32b, ReduceSlot rs, SolveConsts sc,
-                                                        Span sp)
+                                                        Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(G, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    csum64 = gshift(csum64, go);
+    x32r = gshift(x32r, go);
+    x32b = gshift(x32b, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     const double cm = (csum64[0] + csum64[1]) / (2.0 * (double)F.half);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const double ih2 = 1.0 / (F.h * F.h);
@@ -813,8 +888,8 @@ void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
 {
     auto finish = [&](const Span &s) {
         if (lag64 && lag32)
-            hipLaunchKernelGGL(k_finalize_outer, dim3(1), dim3(kBlock), 0, st, (const double *)rs.partials,
-                               (int)s.nblocks, rs.out, lag64, lag32);
+            hipLaunchKernelGGL(k_finalize_outer, group_grid(1), dim3(kBlock), 0, st, (const double *)rs.partials,
+                               (int)s.nblocks, rs.out, lag64, lag32, cur_group());
         else
             launch_finalize(rs, s, 6, rs.out, st);
     };
@@ -825,18 +900,25 @@ void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
     }
     const Span sp = make_span(2 * F64.half);
     if (nonlinear)
-        hipLaunchKernelGGL((k_mixed_outer<true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32, x32r,
-                           x32b, rs, sc, sp);
+        hipLaunchKernelGGL((k_mixed_outer<true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32,
+                           x32r, x32b, rs, sc, sp, cur_group());
     else
-        hipLaunchKernelGGL((k_mixed_outer<false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32,
-                           x32r, x32b, rs, sc, sp);
+        hipLaunchKernelGGL((k_mixed_outer<false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64,
+                           F32, x32r, x32b, rs, sc, sp, cur_group());
     finish(sp);
 }
 
 __global__ __launch_bounds__(kBlock) void k_mixed_correct(double *__restrict__ x64, const float *__restrict__ x32r,
                                                           const float *__restrict__ x32b, const float *__restrict__ x0r,
-                                                          const float *__restrict__ x0b, unsigned half, Span sp)
+                                                          const float *__restrict__ x0b, unsigned half, Span sp,
+                                                          Group grp)
 {
+    const long long go = group_offset(grp);
+    x64 = gshift(x64, go);
+    x32r = gshift(x32r, go);
+    x32b = gshift(x32b, go);
+    x0r = gshift(x0r, go);
+    x0b = gshift(x0b, go);
     PM_SPAN_LOOP(e, sp)
     {
         const int c = e >= half;
@@ -850,16 +932,23 @@ void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, con
                           long long half, hipStream_t st)
 {
     const Span sp = make_span(2 * half);
-    hipLaunchKernelGGL(k_mixed_correct, dim3(sp.nblocks), dim3(kBlock), 0, st, x64, x32r, x32b, x0r, x0b,
-                       (unsigned)half, sp);
+    hipLaunchKernelGGL(k_mixed_correct, group_grid(sp.nblocks), dim3(kBlock), 0, st, x64, x32r, x32b, x0r, x0b,
+                       (unsigned)half, sp, cur_group());
 }
 
 // ------------------------------------------------------------ residual norm
 template <bool NL>
 __global__ __launch_bounds__(kBlock) void k_residual_norm(LevelView<double> F, const double *__restrict__ xr,
                                                           const double *__restrict__ xb, const double *__restrict__ csum,
-                                                          ReduceSlot rs, SolveConsts sc, Span sp)
+                                                          ReduceSlot rs, SolveConsts sc, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    csum = gshift(csum, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     const double cm = (csum[0] + csum[1]) / (2.0 * (double)F.half);
     double acc[4] = {0, 0, 0, 0};
     const unsigned half = (unsigned)F.half;
@@ -885,15 +974,20 @@ void launch_residual_norm(const LevelView<double> &F, const double *xr, const do
 {
     const Span sp = make_span(2 * F.half);
     if (nonlinear)
-        hipLaunchKernelGGL((k_residual_norm<true>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, rs, sc, sp);
+        hipLaunchKernelGGL((k_residual_norm<true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, rs, sc,
+                           sp, cur_group());
     else
-        hipLaunchKernelGGL((k_residual_norm<false>), dim3(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, rs, sc, sp);
+        hipLaunchKernelGGL((k_residual_norm<false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F, xr, xb, csum, rs,
+                           sc, sp, cur_group());
     launch_finalize(rs, sp, 4, rs.out, st);
 }
 
 // ------------------------------------------------------------ small helpers
-__global__ __launch_bounds__(kBlock) void k_field_sum(const double *__restrict__ x, ReduceSlot rs, Span sp)
+__global__ __launch_bounds__(kBlock) void k_field_sum(const double *__restrict__ x, ReduceSlot rs, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    x = gshift(x, go);
+    gshift_slot(rs, go);
     double acc[2] = {0.0, 0.0};
     PM_SPAN_LOOP(e, sp)
     {
@@ -907,12 +1001,16 @@ __global__ __launch_bounds__(kBlock) void k_field_sum(const double *__restrict__
 void launch_field_sum(const double *x, long long n, ReduceSlot rs, hipStream_t st)
 {
     const Span sp = make_span(n);
-    hipLaunchKernelGGL(k_field_sum, dim3(sp.nblocks), dim3(kBlock), 0, st, x, rs, sp);
+    hipLaunchKernelGGL(k_field_sum, group_grid(sp.nblocks), dim3(kBlock), 0, st, x, rs, sp, cur_group());
     launch_finalize(rs, sp, 2, rs.out, st);
 }
 
-__global__ __launch_bounds__(kBlock) void k_subtract_mean(double *__restrict__ x, const double *sum_ptr, Span sp)
+__global__ __launch_bounds__(kBlock) void k_subtract_mean(double *__restrict__ x, const double *sum_ptr, Span sp,
+                                                          Group grp)
 {
+    const long long go = group_offset(grp);
+    x = gshift(x, go);
+    sum_ptr = gshift(sum_ptr, go);
     const double m = sum_ptr[0] / (double)sp.total;
     PM_SPAN_LOOP(e, sp)
     x[e] -= m;
@@ -921,11 +1019,15 @@ __global__ __launch_bounds__(kBlock) void k_subtract_mean(double *__restrict__ x
 void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStream_t st)
 {
     const Span sp = make_span(n);
-    hipLaunchKernelGGL(k_subtract_mean, dim3(sp.nblocks), dim3(kBlock), 0, st, x, sum_ptr, sp);
+    hipLaunchKernelGGL(k_subtract_mean, group_grid(sp.nblocks), dim3(kBlock), 0, st, x, sum_ptr, sp, cur_group());
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale(const double *__restrict__ x, double *__restrict__ y, double a, Span sp)
+__global__ __launch_bounds__(kBlock) void k_scale(const double *__restrict__ x, double *__restrict__ y, double a, Span sp,
+                                                  Group grp)
 {
+    const long long go = group_offset(grp);
+    x = gshift(x, go);
+    y = gshift(y, go);
     PM_SPAN_LOOP(e, sp)
     y[e] = a * x[e];
 }
@@ -933,13 +1035,34 @@ __global__ __launch_bounds__(kBlock) void k_scale(const double *__restrict__ x, 
 void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st)
 {
     const Span sp = make_span(n);
-    hipLaunchKernelGGL(k_scale, dim3(sp.nblocks), dim3(kBlock), 0, st, x, y, a, sp);
+    hipLaunchKernelGGL(k_scale, group_grid(sp.nblocks), dim3(kBlock), 0, st, x, y, a, sp, cur_group());
+}
+
+// dst[s * count + q] = src[q] of slot s (slot s at src + s * stride bytes),
+// for the m slots of a group: their norms in one contiguous readback.
+__global__ __launch_bounds__(kBlock) void k_gather_slots(const double *__restrict__ src, long long stride, int m,
+                                                         int count, double *__restrict__ dst)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t < m * count) {
+        const int s = t / count, q = t - s * count;
+        dst[t] = *reinterpret_cast<const double *>(reinterpret_cast<const char *>(src) + (long long)s * stride +
+                                                   (long long)q * sizeof(double));
+    }
+}
+
+void launch_gather_slots(const double *src, long long stride, int m, int count, double *dst, hipStream_t st)
+{
+    const int n = m * count;
+    hipLaunchKernelGGL(k_gather_slots, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, src, stride, m, count,
+                       dst);
 }
 
 // Zero fill as a kernel (not hipMemsetAsync), 64-bit indices: the
 // workspace can exceed 2^32 words.
-__global__ __launch_bounds__(kBlock) void k_zero(uint32_t *__restrict__ p, long long nw)
+__global__ __launch_bounds__(kBlock) void k_zero(uint32_t *__restrict__ p, long long nw, Group grp)
 {
+    p = gshift(p, group_offset(grp));
     for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < nw; e += (long long)gridDim.x * kBlock)
         p[e] = 0u;
 }
@@ -950,7 +1073,8 @@ void launch_zero(void *p, size_t bytes, hipStream_t st)
     long long b = (nw + kBlock - 1) / kBlock;
     if (b > kMaxBlocks)
         b = kMaxBlocks;
-    hipLaunchKernelGGL(k_zero, dim3((int)(b < 1 ? 1 : b)), dim3(kBlock), 0, st, (uint32_t *)p, nw);
+    hipLaunchKernelGGL(k_zero, group_grid((unsigned)(b < 1 ? 1 : b)), dim3(kBlock), 0, st, (uint32_t *)p, nw,
+                       cur_group());
 }
 
 // explicit instantiations
@@ -1023,15 +1147,24 @@ template <typename R, bool NL>
 __global__ __launch_bounds__(kBlockCycleThreads) void k_block_cycle(BlockHier<R> Barg, int l0, int fmg, int n_pre,
                                                                     int n_post, SolveConsts sc,
                                                                     const double *__restrict__ csum_l0, int cur_bits,
-                                                                    int coarse_sweeps, int lr)
+                                                                    int coarse_sweeps, int lr, Group grp)
 {
     // the level table lives in LDS: indexed by level at run time, a kernel
     // argument would be copied to private memory.  The helpers below capture
     // by value: a by-reference capture of the arguments (sc, the sweep
     // counts, tid) would keep them in private memory too, read in every loop.
     __shared__ BlockHier<R> B;
-    if (threadIdx.x == 0)
+    const long long go = group_offset(grp);
+    csum_l0 = gshift(csum_l0, go);
+    gconsts(sc, grp);
+    if (threadIdx.x == 0) {
         B = Barg;
+        for (int l = 0; l < kMaxLevels; l++) {
+            gshift_view(B.L[l], go);
+            B.buf[l][0] = gshift(B.buf[l][0], go);
+            B.buf[l][1] = gshift(B.buf[l][1], go);
+        }
+    }
     __shared__ int cur[kMaxLevels][2];
     __shared__ double cs[kMaxLevels][2];
     __shared__ double red[16][2];
@@ -1246,11 +1379,11 @@ void launch_block_cycle(const BlockHier<R> &B, int l0, bool fmg, int n_pre, int 
     int lr = B.nlev;
     const size_t bytes = block_cycle_lds(B, l0, &lr);
     if (nonlinear)
-        hipLaunchKernelGGL((k_block_cycle<R, true>), dim3(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
-                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr);
+        hipLaunchKernelGGL((k_block_cycle<R, true>), group_grid(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
+                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr, cur_group());
     else
-        hipLaunchKernelGGL((k_block_cycle<R, false>), dim3(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
-                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr);
+        hipLaunchKernelGGL((k_block_cycle<R, false>), group_grid(1), dim3(kBlockCycleThreads), bytes, st, B, l0,
+                           fmg ? 1 : 0, n_pre, n_post, sc, csum_l0, cur_bits, coarse_sweeps, lr, cur_group());
 }
 
 template void launch_block_cycle<float>(const BlockHier<float> &, int, bool, int, int, SolveConsts, bool,

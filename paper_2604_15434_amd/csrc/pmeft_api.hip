@@ -577,11 +577,77 @@ static void record(SolveOut &so, int i, double rel)
     so.rel = rel;
 }
 
-// FP64 solve of one field held packed in `master` (initial guess in, solution
-// out).  src_norm = ||beta delta / nu||_2.
-static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                     SolveOut &so, bool zero_start)
+// Problems of one shape solved in lockstep (mg_scalar_solve_batched): slot s
+// of the group has its workspace stride * s bytes after slot 0's, which the
+// context C addresses; every launch covers the active slots (the device map
+// lists them), and each slot's convergence test drops it from the map.  One
+// problem is the group {slot 0} with stride 0: no map and plain launches.
+struct GroupRun {
+    int m = 1;                     // slots
+    long long stride = 0;          // bytes between slots
+    int *dmap = nullptr;           // device map [m] (grouped runs)
+    const SolveConsts *dsc = nullptr;  // device per-slot constants (grouped runs)
+    double *dgather = nullptr;     // device [m * 8]: the slots' norms, gathered for one readback
+    std::vector<int> active{0};    // active slots, ascending
+    std::vector<int> uploaded;     // the list the device map holds
+    hipStream_t st = nullptr;      // the stream of the group's launches
+    bool grouped() const { return stride != 0; }
+};
+
+// Makes G's active list this thread's launch group.  A changed list is
+// copied into the device map in stream order and waited for: launches before
+// it read the old map, launches after it the new one, and the host list may
+// change again at once.
+static int group_bind(GroupRun &G)
 {
+    if (!G.grouped()) {
+        set_cur_group(Group());
+        return PM_OK;
+    }
+    if (G.active.empty())
+        return PM_OK;
+    if (G.uploaded != G.active) {
+        PM_HIP(hipMemcpyAsync(G.dmap, G.active.data(), sizeof(int) * G.active.size(), hipMemcpyHostToDevice, G.st));
+        PM_HIP(hipStreamSynchronize(G.st));
+        G.uploaded = G.active;
+    }
+    Group g;
+    g.stride = G.stride;
+    g.map = G.dmap;
+    g.sc = G.dsc;
+    g.rows = (int)G.active.size();
+    set_cur_group(g);
+    return PM_OK;
+}
+
+// count doubles at dev (slot 0's address) for every slot: host[s * count + q]
+static int read_group(Ctx &C, const GroupRun &G, const double *dev, double *host, int count)
+{
+    if (!G.grouped())
+        return read_out(C, dev, host, count);
+    launch_gather_slots(dev, G.stride, G.m, count, G.dgather, C.st);
+    PM_HIP(hipMemcpyAsync(host, G.dgather, sizeof(double) * count * G.m, hipMemcpyDeviceToHost, C.st));
+    PM_HIP(hipStreamSynchronize(C.st));
+    return PM_OK;
+}
+
+// Device-to-device copy of `bytes` from src to dst (slot 0 addresses) for slot s.
+static int slot_copy(Ctx &C, const GroupRun &G, int s, void *dst, const void *src, size_t bytes)
+{
+    const long long o = (long long)s * G.stride;
+    PM_HIP(hipMemcpyAsync((char *)dst + o, (const char *)src + o, bytes, hipMemcpyDeviceToDevice, C.st));
+    return PM_OK;
+}
+
+// FP64 solve of one field held packed in `master` (initial guess in, solution
+// out), for every active slot of G.  src_norm[s] = ||beta delta / nu||_2 of
+// slot s; limit[s]: its V-cycle budget (null: o.max_vcycles).
+static int solve_f64(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o,
+                     const double *src_norm, SolveOut *so, bool zero_start, const int *limit = nullptr)
+{
+    int e = group_bind(G);
+    if (e)
+        return e;
     Hier<double> H;
     build_hier64(C, H, master);
     if (sc.jacobi)  // (the single-workgroup coarse cycle smooths by Gauss-Seidel only)
@@ -596,34 +662,51 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
         launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st, H.tiled);
         H.fresh(0);
     }
-    double out[8];
-    int it = fmg;
-    for (;; it++) {
+    std::vector<double> out(4 * (size_t)G.m);
+    const long long half = H.L[0].half;
+    for (int it = fmg;; it++) {
         for (int s = 0; s < o.n_pre; s++)
             sweep(C, H, 0, sc, nl);
         H.cur[1][0] = H.cur[1][1] = 0;
         launch_residual_restrict<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), H.L[1], H.xr(1), H.xb(1), C.rs, sc,
                                          nl, C.st, true, H.tiled);
-        int e = read_out(C, C.rs.out, out, 4);
+        e = read_group(C, G, C.rs.out, out.data(), 4);
         if (e)
             return e;
-        const double r2 = fmax(out[0] - out[1] * out[1] / (double)N, 0.0);
-        const double rel = sqrt(r2) / src_norm;
-        record(so, it - fmg, rel);
-        so.mean_shift = out[2] / (double)N;
-        so.clamped = (long long)out[3];
-        if (!isfinite(rel)) {
-            so.status = PM_ENONFINITE;
-            break;
+        std::vector<int> next;
+        for (int s : G.active) {
+            const double *q = &out[(size_t)s * 4];
+            SolveOut &r = so[s];
+            const double r2 = fmax(q[0] - q[1] * q[1] / (double)N, 0.0);
+            const double rel = sqrt(r2) / src_norm[s];
+            record(r, it - fmg, rel);
+            r.mean_shift = q[2] / (double)N;
+            r.clamped = (long long)q[3];
+            bool done = true;
+            if (!isfinite(rel))
+                r.status = PM_ENONFINITE;
+            else if (rel <= o.rel_tol)
+                r.status = PM_OK;
+            else if (it >= (limit ? limit[s] : o.max_vcycles))
+                r.status = PM_ENOCONV;
+            else
+                done = false;
+            if (!done) {
+                next.push_back(s);
+                continue;
+            }
+            r.vcycles = it;
+            // bring both colours back into the master buffer
+            if (H.cur[0][0] && (e = slot_copy(C, G, s, master, H.buf[0][1], sizeof(double) * half)))
+                return e;
+            if (H.cur[0][1] && (e = slot_copy(C, G, s, master + half, H.buf[0][1] + half, sizeof(double) * half)))
+                return e;
         }
-        if (rel <= o.rel_tol) {
-            so.status = PM_OK;
+        G.active = next;
+        if (G.active.empty())
             break;
-        }
-        if (it >= o.max_vcycles) {
-            so.status = PM_ENOCONV;
-            break;
-        }
+        if ((e = group_bind(G)))
+            return e;
         launch_fas_tau<double>(H.L[1], H.xr(1), H.xb(1), H.csum_cur(1), C.rs, sc, nl, false, C.st, H.tiled);
         H.fresh(1);
         vcycle_from(C, H, 1, o, sc, nl);
@@ -631,14 +714,6 @@ static int solve_f64(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_m
         for (int s = 0; s < o.n_post; s++)
             sweep(C, H, 0, sc, nl);
     }
-    so.vcycles = it;
-    // bring both colours back into the master buffer
-    const long long half = H.L[0].half;
-    if (H.cur[0][0])
-        PM_HIP(hipMemcpyAsync(master, H.buf[0][1], sizeof(double) * half, hipMemcpyDeviceToDevice, C.st));
-    if (H.cur[0][1])
-        PM_HIP(hipMemcpyAsync(master + half, H.buf[0][1] + half, sizeof(double) * half, hipMemcpyDeviceToDevice, C.st));
-    (void)N;
     return launched();
 }
 
@@ -660,10 +735,15 @@ constexpr double kMixedStall = 0.36;  // an outer step must reduce the residual 
 
 // final_residual = false: once the cycle budget is spent, the last outer
 // residual (which changes nothing but the report) and its readback are
-// skipped; for callers that read no residual.
-static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
-                       SolveOut &so, bool zero_start, bool final_residual = true)
+// skipped; for callers that read no residual.  For every active slot of G
+// (see solve_f64); slots that finish in FP64 do so together, after the FP32
+// phase of the whole group.
+static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o,
+                       const double *src_norm, SolveOut *so, bool zero_start, bool final_residual = true)
 {
+    int e = group_bind(G);
+    if (e)
+        return e;
     Hier<float> H;
     build_hier32(C, H);
     if (sc.jacobi)
@@ -682,13 +762,16 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
         sc32.beta = 0.0;
     }
     const double switch_tol = fmax(kMixedSwitchNL, 30.0 * o.rel_tol);
-    double out[8];
-    int it = 0, cyc = 0;  // outer steps, FP32 V-cycles
-    double prev = 0.0;
-    bool to_f64 = false;
-    for (;; it++) {
+    std::vector<double> out(4 * (size_t)G.m), prev(G.m, 0.0);
+    std::vector<int> cyc_of(G.m, 0), it_of(G.m, 0), to_f64;
+    int cyc = 0;  // FP32 V-cycles (the same for every slot still in the FP32 phase)
+    for (int it = 0;; it++) {
         if (!final_residual && it > 0 && cyc >= o.max_vcycles) {
-            so.status = PM_ENOCONV;
+            for (int s : G.active) {
+                so[s].status = PM_ENOCONV;
+                so[s].vcycles = cyc;
+            }
+            G.active.clear();
             break;
         }
         H.cur[0][0] = H.cur[0][1] = 0;
@@ -697,42 +780,54 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
         launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), ro, sc, nl, C.st,
                                     H.tiled, C.csum64, H.csum_cur(0));
         H.fresh(0);
-        int e = read_out(C, C.outer_out, out, 4);
+        e = read_group(C, G, C.outer_out, out.data(), 4);
         if (e)
             return e;
-        const double r2 = fmax(out[0] - out[1] * out[1] / (double)N, 0.0);
-        const double rel = sqrt(r2) / src_norm;
-        record(so, it, rel);
-        so.mean_shift = out[2] / (double)N;
-        so.clamped = (long long)out[3];
-        if (!isfinite(rel)) {
-            so.status = PM_ENONFINITE;
-            break;
+        std::vector<int> next;
+        double rel_last = 0.0, prev_last = 0.0;
+        for (int s : G.active) {
+            const double *q = &out[(size_t)s * 4];
+            SolveOut &r = so[s];
+            const double r2 = fmax(q[0] - q[1] * q[1] / (double)N, 0.0);
+            const double rel = sqrt(r2) / src_norm[s];
+            record(r, it, rel);
+            r.mean_shift = q[2] / (double)N;
+            r.clamped = (long long)q[3];
+            r.vcycles = cyc;
+            if (!isfinite(rel)) {
+                r.status = PM_ENONFINITE;
+            } else if (rel <= o.rel_tol) {
+                r.status = PM_OK;
+            } else if (cyc >= o.max_vcycles) {
+                r.status = PM_ENOCONV;
+            } else if (nl && (rel <= switch_tol || (it > 0 && rel > kMixedStall * prev[s]))) {
+                cyc_of[s] = cyc;
+                it_of[s] = it;
+                to_f64.push_back(s);
+            } else {
+                prev_last = prev[s];
+                rel_last = rel;
+                prev[s] = rel;
+                next.push_back(s);
+            }
         }
-        if (rel <= o.rel_tol) {
-            so.status = PM_OK;
+        G.active = next;
+        if (G.active.empty())
             break;
-        }
-        if (cyc >= o.max_vcycles) {
-            so.status = PM_ENOCONV;
-            break;
-        }
-        if (nl && (rel <= switch_tol || (it > 0 && rel > kMixedStall * prev))) {
-            to_f64 = true;
-            break;
-        }
+        if ((e = group_bind(G)))
+            return e;
         // kMixedInner FP32 V-cycles per FP64 defect correction: the FP64
         // residual and correction are paid once for all of them.  A linear
         // problem converges at a steady rate per V-cycle; when one cycle at
         // the last outer step's rate (with a 2x margin) reaches the tolerance,
-        // the final outer step runs one cycle only.
+        // the final outer step runs one cycle only.  Only with one problem
+        // active: members of a lockstep group run the same cycles.
         int inner = kMixedInner;
-        if (!nl && it >= 2 && prev > 0.0) {  // (the first step includes the FMG start)
-            const double per_cycle = pow(rel / prev, 1.0 / kMixedInner);
-            if (per_cycle < 1.0 && 2.0 * rel * per_cycle <= o.rel_tol)
+        if (!nl && G.active.size() == 1 && it >= 2 && prev_last > 0.0) {  // (the first step includes the FMG start)
+            const double per_cycle = pow(rel_last / prev_last, 1.0 / kMixedInner);
+            if (per_cycle < 1.0 && 2.0 * rel_last * per_cycle <= o.rel_tol)
                 inner = 1;
         }
-        prev = rel;
         for (int v = 0; v < inner && cyc < o.max_vcycles; v++, cyc++) {
             if (it == 0 && v == 0 && zero_start)
                 fmg_start<float>(C, H, o, sc32, nl);
@@ -741,24 +836,31 @@ static int solve_mixed(Ctx &C, double *master, SolveConsts sc, bool nl, const pm
         }
         launch_mixed_correct(master, H.xr(0), H.xb(0), H.L[0].x0r, H.L[0].x0b, half, C.st);
     }
-    so.vcycles = cyc;
-    int e = launched();
-    if (e || !to_f64)
+    e = launched();
+    if (e || to_f64.empty())
         return e;
-    // finish in FP64 from the current iterate
-    pm_mg_opts o64 = o;
-    o64.max_vcycles = o.max_vcycles - cyc;
-    SolveOut s64;
-    e = solve_f64(C, master, sc, nl, o64, src_norm, s64, false);
+    // finish in FP64 from the current iterates
+    std::sort(to_f64.begin(), to_f64.end());
+    std::vector<SolveOut> s64(G.m);
+    std::vector<int> limit(G.m, 0);
+    for (int s : to_f64)
+        limit[s] = o.max_vcycles - cyc_of[s];
+    G.active = to_f64;
+    e = solve_f64(C, G, master, sc, nl, o, src_norm, s64.data(), false, limit.data());
     if (e)
         return e;
-    for (int i = 0; i <= s64.vcycles && it + i < 64; i++)
-        so.hist[it + i] = s64.hist[i];
-    so.vcycles = cyc + s64.vcycles;
-    so.rel = s64.rel;
-    so.status = s64.status;
-    so.mean_shift = s64.mean_shift;
-    so.clamped = s64.clamped;
+    for (int s : to_f64) {
+        SolveOut &r = so[s];
+        // the FP64 phase's residuals follow the FP32 phase's, from the
+        // switching outer step's own
+        for (int i = 0; i <= s64[s].vcycles && it_of[s] + i < 64; i++)
+            r.hist[it_of[s] + i] = s64[s].hist[i];
+        r.vcycles = cyc_of[s] + s64[s].vcycles;
+        r.rel = s64[s].rel;
+        r.status = s64[s].status;
+        r.mean_shift = s64[s].mean_shift;
+        r.clamped = s64[s].clamped;
+    }
     return PM_OK;
 }
 
@@ -836,11 +938,20 @@ static bool opts_ok(const pm_mg_opts *o)
 static int prec_bits(const pm_mg_opts *o) { return o->precision == PM_PREC_MIXED ? (kPrecMixed | kPrecF64) : kPrecF64; }
 
 // final_residual: see solve_mixed (the FP64 path always tests).
+static int run_solve_group(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o,
+                           const double *src_norm, SolveOut *so, bool zero_start, bool final_residual = true)
+{
+    return o.precision == PM_PREC_MIXED
+               ? solve_mixed(C, G, master, sc, nl, o, src_norm, so, zero_start, final_residual)
+               : solve_f64(C, G, master, sc, nl, o, src_norm, so, zero_start);
+}
+
+// One problem: the group {slot 0}.
 static int run_solve(Ctx &C, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o, double src_norm,
                      SolveOut &so, bool zero_start, bool final_residual = true)
 {
-    return o.precision == PM_PREC_MIXED ? solve_mixed(C, master, sc, nl, o, src_norm, so, zero_start, final_residual)
-                                        : solve_f64(C, master, sc, nl, o, src_norm, so, zero_start);
+    GroupRun G;
+    return run_solve_group(C, G, master, sc, nl, o, &src_norm, &so, zero_start, final_residual);
 }
 
 // Solve constants with the smoother the options ask for.
@@ -1148,33 +1259,238 @@ int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, 
 // problems largest grid first from a shared counter and run the single-problem
 // solve on them; the kernel sequence of a problem does not depend on the
 // worker, so each result equals the problem's own solve bit for bit.
-static constexpr int kBatchWorkers = 4;
-
-static size_t batch_slice_bytes(const pm_problem *probs, int nprob, int precision)
-{
+// ---- grouped batched solves ----------------------------------------------
+// The problems are grouped by (grid, dtype of their arrays), largest grid
+// first, and each group is solved in lockstep: one launch per kernel of the
+// solve covers every problem of the group still iterating (Group), each in
+// its own workspace slot.  The groups run one after another on the caller's
+// stream and share one region of the workspace.
+namespace {
+struct BatchGroup {
     int ng = 0;
     pm_dtype dt = PM_F32;
-    for (int i = 0; i < nprob; i++) {
-        ng = std::max(ng, probs[i].ng);
-        if (probs[i].dtype == PM_F64)
-            dt = PM_F64;
+    std::vector<int> idx;  // problem indices
+    size_t slice = 0;      // bytes per slot
+};
+
+// control area per slot: its map entry and two constants tables
+constexpr size_t kBatchCtlPerSlot = sizeof(int) + 2 * sizeof(SolveConsts) + 8 * sizeof(double);
+
+bool batch_groups(const pm_problem *probs, int nprob, int precision, std::vector<BatchGroup> &out)
+{
+    out.clear();
+    std::vector<int> order(nprob);
+    for (int i = 0; i < nprob; i++)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].ng > probs[b].ng; });
+    for (int i : order) {
+        BatchGroup *g = nullptr;
+        for (auto &x : out)
+            if (x.ng == probs[i].ng && x.dt == probs[i].dtype)
+                g = &x;
+        if (!g) {
+            out.emplace_back();
+            g = &out.back();
+            g->ng = probs[i].ng;
+            g->dt = probs[i].dtype;
+            const size_t b = pm_workspace_bytes(g->ng, 0, g->dt, (pm_prec)precision);
+            if (b == 0)
+                return false;
+            g->slice = (b + 255) & ~(size_t)255;
+        }
+        g->idx.push_back(i);
     }
-    const size_t b = pm_workspace_bytes(ng, 0, dt, (pm_prec)precision);
-    return (b + 255) & ~(size_t)255;
+    return true;
 }
 
-static int batch_workers(int nprob) { return std::min(kBatchWorkers, std::max(nprob, 1)); }
+size_t batch_region_bytes(const std::vector<BatchGroup> &gs)
+{
+    size_t r = 0;
+    for (const auto &g : gs)
+        r = std::max(r, g.slice * g.idx.size());
+    return r;
+}
+
+size_t batch_ctl_bytes(int nprob) { return ((size_t)nprob * kBatchCtlPerSlot + 4 * 256 + 255) & ~(size_t)255; }
+
+struct GroupReset {
+    ~GroupReset() { set_cur_group(Group()); }
+};
+
+// One group in lockstep: the steps of grid_solve and scalar_core for every
+// slot, each launch covering the slots that take it.
+int solve_group(const pm_problem *probs, const BatchGroup &bg, const pm_mg_opts &o, pm_mg_report *reps,
+                std::vector<int> &codes, char *region, char *ctl, hipStream_t st)
+{
+    const int m = (int)bg.idx.size();
+    const int ng = bg.ng;
+    Ctx C;
+    int e = setup_ctx(C, region, bg.slice, ng, 0, bg.dt, prec_bits(&o), st);
+    if (e)
+        return e;
+    GroupReset reset;
+    GroupRun G;
+    G.m = m;
+    G.stride = (long long)bg.slice;
+    G.st = C.st;
+    G.dmap = reinterpret_cast<int *>(ctl);
+    // control area: map [m] | constants [m] | linear-guess constants [m] | gathered norms [m * 8]
+    SolveConsts *dsc = reinterpret_cast<SolveConsts *>(ctl + (((size_t)m * sizeof(int) + 255) & ~(size_t)255));
+    SolveConsts *dlin = dsc + m;
+    G.dgather = reinterpret_cast<double *>(
+        reinterpret_cast<char *>(dsc) + ((2 * (size_t)m * sizeof(SolveConsts) + 255) & ~(size_t)255));
+    std::vector<pm_eft_coeffs> cf(m);
+    std::vector<SolveConsts> tsc(m), tlin(m);
+    std::vector<double> dsq(m, 0.0), src(m, 0.0);
+    std::vector<SolveOut> so(m);
+    std::vector<int> live;  // slots still in the run
+    for (int s = 0; s < m; s++) {
+        const int i = bg.idx[s];
+        const int ce = coefficients(probs[i].p, cf[s]);
+        if (ce == PM_EINVAL || ce == PM_EUNSTABLE) {
+            codes[i] = ce;
+            continue;
+        }
+        tsc[s] = consts(cf[s].nu, cf[s].K, cf[s].xi * cf[s].s, o);
+        tlin[s] = consts(cf[s].nu, 0.0, cf[s].xi * cf[s].s, o);
+        live.push_back(s);
+    }
+    if (live.empty())
+        return PM_OK;
+    PM_HIP(hipMemcpyAsync(dsc, tsc.data(), sizeof(SolveConsts) * m, hipMemcpyHostToDevice, C.st));
+    PM_HIP(hipMemcpyAsync(dlin, tlin.data(), sizeof(SolveConsts) * m, hipMemcpyHostToDevice, C.st));
+    PM_HIP(hipStreamSynchronize(C.st));
+    const long long N = C.P.N;
+    const size_t esz = bg.dt == PM_F64 ? sizeof(double) : sizeof(float);
+    double *stage = C.at<double>(C.P.psi64);  // natural-order staging of rho and chi (the scalar solve leaves psi free)
+    double *d0 = C.at<double>(C.P.delta64[0]);
+    double *m0 = C.at<double>(C.P.chi64);
+    auto bind = [&](const std::vector<int> &slots) {
+        G.active = slots;
+        return group_bind(G);
+    };
+    // a problem's array <-> its slot's staging area
+    auto stage_in = [&](int s, const void *user) {
+        return hipMemcpyAsync((char *)stage + (long long)s * G.stride, user, esz * N, hipMemcpyDeviceToDevice, C.st) ==
+                       hipSuccess
+                   ? PM_OK
+                   : PM_EHIP;
+    };
+    auto stage_out = [&](int s, void *user) {
+        return hipMemcpyAsync(user, (const char *)stage + (long long)s * G.stride, esz * N, hipMemcpyDeviceToDevice,
+                              C.st) == hipSuccess
+                   ? PM_OK
+                   : PM_EHIP;
+    };
+    Timer tm(C.st);
+    // rho -> packed delta = rho - 1, mean removed, coarse levels, norms
+    for (int s : live)
+        if ((e = stage_in(s, probs[bg.idx[s]].rho)))
+            return e;
+    if ((e = bind(live)))
+        return e;
+    launch_zero(C.ws + C.P.red_counter, 256, C.st);
+    launch_natural_to_packed(stage, bg.dt, d0, ng, 1.0, -1.0, C.st);
+    launch_field_sum(d0, N, C.rs, C.st);
+    launch_subtract_mean(d0, N, C.rs.out, C.st);
+    delta_levels(C);
+    launch_field_sum(d0, N, C.rs, C.st);
+    std::vector<double> out(2 * (size_t)m);
+    if ((e = read_group(C, G, C.rs.out, out.data(), 2)))
+        return e;
+    std::vector<int> ok, zero, nlset, linset;
+    for (int s : live) {
+        if (!isfinite(out[2 * s]) || !isfinite(out[2 * s + 1])) {
+            codes[bg.idx[s]] = PM_ENONFINITE;
+            continue;
+        }
+        dsq[s] = out[2 * s + 1];
+        ok.push_back(s);
+        src[s] = fabs(cf[s].xi * cf[s].s / cf[s].nu) * sqrt(dsq[s]);
+        if (cf[s].xi == 0.0 || src[s] == 0.0)
+            zero.push_back(s);
+        else
+            (cf[s].K != 0.0 ? nlset : linset).push_back(s);
+    }
+    if (ok.empty())
+        return launched();
+    if (o.guess == PM_GUESS_GIVEN) {
+        for (int s : ok)
+            if ((e = stage_in(s, probs[bg.idx[s]].chi)))
+                return e;
+        if ((e = bind(ok)))
+            return e;
+        launch_natural_to_packed(stage, bg.dt, m0, ng, 1.0, 0.0, C.st);
+    }
+    if (!zero.empty()) {  // no source: chi = 0
+        if ((e = bind(zero)))
+            return e;
+        launch_zero(m0, sizeof(double) * N, C.st);
+    }
+    G.dsc = dsc;
+    // the nonlinear members in lockstep, then the linear ones (screening off)
+    // one at a time: a linear mixed-precision solve may end with one FP32
+    // cycle instead of two, which members would decide differently
+    std::vector<std::vector<int>> runs;
+    if (!nlset.empty())
+        runs.push_back(nlset);
+    for (int s : linset)
+        runs.push_back({s});
+    for (const auto &set : runs) {
+        const bool nl = cf[set[0]].K != 0.0;
+        if (o.guess != PM_GUESS_GIVEN) {
+            if ((e = bind(set)))
+                return e;
+            launch_zero(m0, sizeof(double) * N, C.st);
+        }
+        if (o.guess == PM_GUESS_LINEAR && nl) {
+            pm_mg_opts lo = o;
+            lo.rel_tol = 1e-3;
+            lo.max_vcycles = 4;
+            std::vector<SolveOut> tmp(m);
+            G.dsc = dlin;
+            G.active = set;
+            e = run_solve_group(C, G, m0, tlin[set[0]], false, lo, src.data(), tmp.data(), true);
+            G.dsc = dsc;
+            if (e)
+                return e;
+        }
+        G.active = set;
+        e = run_solve_group(C, G, m0, tsc[set[0]], nl, o, src.data(), so.data(),
+                            o.guess == PM_GUESS_ZERO || o.guess == PM_GUESS_LEARNED);
+        if (e)
+            return e;
+    }
+    // packed chi -> natural (mean removed) -> the problems' arrays
+    G.dsc = nullptr;
+    if ((e = bind(ok)))
+        return e;
+    launch_field_sum(m0, N, C.rs, C.st);
+    launch_packed_to_natural(m0, stage, bg.dt, ng, 0.0, C.rs.out, C.st);
+    if ((e = launched()))
+        return e;
+    for (int s : ok)
+        if ((e = stage_out(s, probs[bg.idx[s]].chi)))
+            return e;
+    const float ms = tm.stop();
+    for (int s : ok) {
+        const int i = bg.idx[s];
+        codes[i] = so[s].status;
+        if (reps)
+            fill_report(&reps[i], so[s], ms);
+    }
+    return launched();
+}
+}  // namespace
 
 size_t mg_batched_workspace_bytes(const pm_problem *probs, int nprob, int precision)
 {
     if (!probs || nprob <= 0 || (precision != PM_PREC_F64 && precision != PM_PREC_MIXED))
         return 0;
-    for (int i = 0; i < nprob; i++) {
-        Plan P;
-        if (!make_plan(P, probs[i].ng, 0, probs[i].dtype, kPrecF64))
-            return 0;
-    }
-    return batch_slice_bytes(probs, nprob, precision) * batch_workers(nprob);
+    std::vector<BatchGroup> gs;
+    if (!batch_groups(probs, nprob, precision, gs))
+        return 0;
+    return batch_region_bytes(gs) + batch_ctl_bytes(nprob);
 }
 
 int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts *opts, pm_mg_report *reps, void *ws,
@@ -1190,60 +1506,22 @@ int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts
         return PM_EINVAL;
     if (ws_bytes < need)
         return PM_ENOMEM;
-    const size_t slice = batch_slice_bytes(probs, nprob, opts->precision);
-    std::vector<int> order(nprob);
-    for (int i = 0; i < nprob; i++)
-        order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].ng > probs[b].ng; });
-    int dev = 0;
-    PM_HIP(hipGetDevice(&dev));
-    hipEvent_t ready;
-    PM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
-        (void)hipEventDestroy(ready);
-        return PM_EHIP;
-    }
+    std::vector<BatchGroup> gs;
+    if (!batch_groups(probs, nprob, opts->precision, gs))
+        return PM_EINVAL;
+    char *region = (char *)ws;
+    char *ctl = region + batch_region_bytes(gs);
     std::vector<int> codes(nprob, PM_OK);
-    std::vector<pm_mg_report> local(nprob);
-    std::atomic<int> next{0};
-    std::atomic<int> setup_err{PM_OK};
-    auto work = [&](int w) {
-        if (hipSetDevice(dev) != hipSuccess) {
-            setup_err = PM_EHIP;
-            return;
-        }
-        hipStream_t st;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            setup_err = PM_EHIP;
-            return;
-        }
-        if (hipStreamWaitEvent(st, ready, 0) == hipSuccess) {
-            char *mine = (char *)ws + (size_t)w * slice;
-            for (int k = next.fetch_add(1); k < nprob; k = next.fetch_add(1)) {
-                const int i = order[k];
-                codes[i] = grid_solve(probs[i].rho, probs[i].ng, probs[i].dtype, &probs[i].p, opts, probs[i].chi,
-                                      &local[i], mine, slice, st, true);
-            }
-        } else {
-            setup_err = PM_EHIP;
-        }
-        if (hipStreamSynchronize(st) != hipSuccess)
-            setup_err = PM_EHIP;
-        (void)hipStreamDestroy(st);
-    };
-    const int nw = batch_workers(nprob);
-    std::vector<std::thread> pool;
-    for (int w = 0; w < nw; w++)
-        pool.emplace_back(work, w);
-    for (auto &t : pool)
-        t.join();
-    (void)hipEventDestroy(ready);
-    if (setup_err != PM_OK)
-        return setup_err;
+    if (reps)
+        for (int i = 0; i < nprob; i++)
+            memset(&reps[i], 0, sizeof(reps[i]));
+    for (const auto &g : gs) {
+        const int e = solve_group(probs, g, *opts, reps, codes, region, ctl, (hipStream_t)stream);
+        if (e)
+            return e;
+    }
     int rc = PM_OK;
     for (int i = 0; i < nprob; i++) {
-        if (reps)
-            reps[i] = local[i];
         if (codes[i] != PM_OK && codes[i] != PM_ENOCONV && (rc == PM_OK || rc == PM_ENOCONV))
             rc = codes[i];
         else if (codes[i] == PM_ENOCONV && rc == PM_OK)

@@ -124,6 +124,72 @@ struct ReduceSlot {
     double *out;        // finalised sums
 };
 
+// Grouped launches.  Problems of one shape solved together sit in workspace
+// slots `stride` bytes apart; every pointer a solver kernel receives is the
+// one of slot 0, and grid row blockIdx.y works on slot map[blockIdx.y] (the
+// row itself without a map), so one launch covers the same step of every
+// problem in the group.  Per-slot solve constants (nu, K, beta) replace the
+// argument's when `sc` is set (see gconsts).  stride 0 is a single problem: no pointer
+// moves and the kernels do exactly what they do without a group.
+struct Group {
+    long long stride = 0;              // bytes between slots
+    const int *map = nullptr;          // device: slot of grid row y (null: y)
+    const SolveConsts *sc = nullptr;   // device: per-slot constants (null: the argument's)
+    int rows = 1;                      // grid rows (host side: gridDim.y)
+};
+
+__device__ __forceinline__ int group_slot(const Group &g) { return g.map ? g.map[blockIdx.y] : (int)blockIdx.y; }
+__device__ __forceinline__ long long group_offset(const Group &g)
+{
+    return g.stride ? (long long)group_slot(g) * g.stride : 0;
+}
+template <typename T>
+__device__ __forceinline__ T *gshift(T *p, long long off)
+{
+    return p ? reinterpret_cast<T *>(reinterpret_cast<char *>(const_cast<void *>(static_cast<const void *>(p))) + off)
+             : p;
+}
+template <typename R>
+__device__ __forceinline__ void gshift_view(LevelView<R> &L, long long off)
+{
+    L.dr = gshift(L.dr, off);
+    L.db = gshift(L.db, off);
+    L.tr = gshift(L.tr, off);
+    L.tb = gshift(L.tb, off);
+    L.x0r = gshift(L.x0r, off);
+    L.x0b = gshift(L.x0b, off);
+}
+__device__ __forceinline__ void gshift_slot(ReduceSlot &rs, long long off)
+{
+    rs.partials = gshift(rs.partials, off);
+    rs.counter = gshift(rs.counter, off);
+    rs.out = gshift(rs.out, off);
+}
+// A zero K or beta in the argument stays zero: the host zeroes them for the
+// correction equation of a linear problem and for the linear guess.
+__device__ __forceinline__ void gconsts(SolveConsts &sc, const Group &g)
+{
+    if (g.sc) {
+        const SolveConsts &t = g.sc[group_slot(g)];
+        sc.nu = t.nu;
+        if (sc.K != 0.0)
+            sc.K = t.K;
+        if (sc.beta != 0.0)
+            sc.beta = t.beta;
+    }
+}
+
+// The group the launchers of this host thread use (a single problem unless a
+// GroupScope is open).
+const Group &cur_group();
+void set_cur_group(const Group &g);
+struct GroupScope {
+    Group prev;
+    explicit GroupScope(const Group &g);
+    ~GroupScope();
+};
+inline dim3 group_grid(unsigned nblocks) { return dim3(nblocks, (unsigned)cur_group().rows); }
+
 // Block reduction of NV doubles; thread 0 stores the block's sums at
 // partials[logical block * 8 + q].  The k_finalize launch that follows adds
 // the partials in block order, so results do not depend on scheduling.
@@ -270,6 +336,9 @@ void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStre
 // y = a * x
 void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
+// dst[s * count + q] = src[q] of slot s = 0 .. m-1 (slots `stride` bytes apart);
+// not a grouped launch (one grid covers every slot)
+void launch_gather_slots(const double *src, long long stride, int m, int count, double *dst, hipStream_t st);
 
 // ---- particle sort (pm_kernels.hip) --------------------------------------
 size_t sort_workspace_bytes(unsigned long long np, int word);

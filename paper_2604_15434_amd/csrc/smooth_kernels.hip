@@ -18,8 +18,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth(LevelView<R> L, int colour, c
                                                    const R *__restrict__ xo, R *__restrict__ xc_new,
                                                    const double *__restrict__ csum_in, double *__restrict__ csum_out,
                                                    const double *__restrict__ prev, int prev_nblocks, int prev_colour,
-                                                   ReduceSlot rs, SolveConsts sc, Span sp)
+                                                   ReduceSlot rs, SolveConsts sc, Span sp, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(L, go);
+    xc_old = gshift(xc_old, go);
+    xo = gshift(xo, go);
+    xc_new = gshift(xc_new, go);
+    csum_in = gshift(csum_in, go);
+    csum_out = gshift(csum_out, go);
+    prev = gshift(prev, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     const int n = L.n, nh = L.nh;
     const R cmean = (R)((csum_in[0] + csum_in[1]) / (2.0 * (double)L.half));
     const R h2 = (R)(L.h * L.h);
@@ -68,8 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_smooth_tile(LevelView<R> L, int colo
                                                         const double *__restrict__ csum_in, double *__restrict__ csum_out,
                                                         const double *__restrict__ prev, int prev_nblocks,
                                                         int prev_colour, ReduceSlot rs, SolveConsts sc, Span sp,
-                                                        unsigned ntiles)
+                                                        unsigned ntiles, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(L, go);
+    xc_old = gshift(xc_old, go);
+    xo = gshift(xo, go);
+    xc_new = gshift(xc_new, go);
+    csum_in = gshift(csum_in, go);
+    csum_out = gshift(csum_out, go);
+    prev = gshift(prev, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     constexpr int RS = kBlock / TK;  // rows per pass of the block
     constexpr int TJ = CJ * RS;
     __shared__ RingSlots<R, TK, TJ> win;  // [0]: own colour, [1]: other colour
@@ -193,8 +213,8 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
         sp.total = nb * kBlock;
         *nblocks_out = (int)nb;
 #define PM_TILE(NLV, TKV, CJV, PLV)                                                                                    \
-    hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV, CJV, PLV>), dim3(nb), dim3(kBlock), 0, st, L, colour, xc_old, xo,    \
-                       xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles)
+    hipLaunchKernelGGL((k_smooth_tile<R, NLV, TKV, CJV, PLV>), group_grid(nb), dim3(kBlock), 0, st, L, colour, xc_old, \
+                       xo, xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles, cur_group())
         if (nonlinear) {
             if (cfg == 4)
                 PM_TILE(true, 64, 4, 16);
@@ -220,11 +240,11 @@ void launch_smooth(const LevelView<R> &L, int colour, const R *xc_old, const R *
     const Span sp = make_span(L.half);
     *nblocks_out = (int)sp.nblocks;
     if (nonlinear)
-        hipLaunchKernelGGL((k_smooth<R, true>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
+        hipLaunchKernelGGL((k_smooth<R, true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo,
+                           xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, cur_group());
     else
-        hipLaunchKernelGGL((k_smooth<R, false>), dim3(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo, xc_new,
-                           csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp);
+        hipLaunchKernelGGL((k_smooth<R, false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, L, colour, xc_old, xo,
+                           xc_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, cur_group());
 }
 
 template void launch_smooth<double>(const LevelView<double> &, int, const double *, const double *, double *,

@@ -78,8 +78,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
                                                         double *__restrict__ csum_out,
                                                         const double *__restrict__ prev, int prev_nblocks,
                                                         int prev_colour, ReduceSlot rs, SolveConsts sc, Span sp,
-                                                        unsigned ntiles, int nI)
+                                                        unsigned ntiles, int nI, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(L, go);
+    xr_old = gshift(xr_old, go);
+    xb_old = gshift(xb_old, go);
+    xr_new = gshift(xr_new, go);
+    xb_new = gshift(xb_new, go);
+    csum_in = gshift(csum_in, go);
+    csum_out = gshift(csum_out, go);
+    prev = gshift(prev, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     using D = Sweep2Dims<TK, TJ, NL>;
     constexpr int W = D::W, WK = D::WK, RW = D::RW, RK = D::RK, NR = D::NR, NB = D::NB;
     constexpr int NC = NL ? 2 : 1;  // colours loaded (the linear update reads no old value of its own colour)
@@ -399,11 +410,13 @@ bool launch_sweep2(const LevelView<R> &L, const R *xr_old, const R *xb_old, R *x
     *nblocks_out = (int)nb;
     using S = Sweep2Shape<R>;
     if (nonlinear)
-        hipLaunchKernelGGL((k_sweep2_tile<R, true, S::TK, S::TJ>), dim3(nb), dim3(kBlock), 0, st, L, xr_old, xb_old,
-                           xr_new, xb_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles, nI);
+        hipLaunchKernelGGL((k_sweep2_tile<R, true, S::TK, S::TJ>), group_grid(nb), dim3(kBlock), 0, st, L, xr_old,
+                           xb_old, xr_new, xb_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles,
+                           nI, cur_group());
     else
-        hipLaunchKernelGGL((k_sweep2_tile<R, false, S::TK, S::TJ>), dim3(nb), dim3(kBlock), 0, st, L, xr_old, xb_old,
-                           xr_new, xb_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles, nI);
+        hipLaunchKernelGGL((k_sweep2_tile<R, false, S::TK, S::TJ>), group_grid(nb), dim3(kBlock), 0, st, L, xr_old,
+                           xb_old, xr_new, xb_new, csum_in, csum_out, prev, prev_nblocks, prev_colour, rs, sc, sp, ntiles,
+                           nI, cur_group());
     return true;
 }
 

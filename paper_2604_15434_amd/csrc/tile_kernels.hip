@@ -62,9 +62,19 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict_tile(LevelView<R> 
                                                                    const double *__restrict__ csum, LevelView<R> C,
                                                                    R *__restrict__ cxr, R *__restrict__ cxb,
                                                                    ReduceSlot rs, SolveConsts sc, Span sp,
-                                                                   unsigned ntiles)
+                                                                   unsigned ntiles, Group grp)
 {
     static_assert(PL % 2 == 0, "plane pairs");
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    csum = gshift(csum, go);
+    cxr = gshift(cxr, go);
+    cxb = gshift(cxb, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     constexpr int TJ = 2 * kBlock / TK;
     __shared__ RingSlots<R, TK, TJ> win;  // [0]: red, [1]: black
     const int n = F.n, nh = F.nh, nI = n / PL, nK = nh / TK;
@@ -165,8 +175,14 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict_tile(LevelView<R> 
 template <typename R, bool NL, int TK, int PL>
 __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R *__restrict__ xr,
                                                          const R *__restrict__ xb, ReduceSlot rs, SolveConsts sc,
-                                                         Span sp, unsigned ntiles, int accumulate_only)
+                                                         Span sp, unsigned ntiles, int accumulate_only, Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(L, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     constexpr int TJ = 2 * kBlock / TK;
     __shared__ RingSlots<R, TK, TJ> win;
     const int n = L.n, nh = L.nh, nI = n / PL, nK = nh / TK;
@@ -255,8 +271,19 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                                                              const double *__restrict__ xb,
                                                              const double *__restrict__ csum64, LevelView<float> G,
                                                              float *__restrict__ x32r, float *__restrict__ x32b,
-                                                             ReduceSlot rs, SolveConsts sc, Span sp, unsigned ntiles)
+                                                             ReduceSlot rs, SolveConsts sc, Span sp, unsigned ntiles,
+                                                             Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(G, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    csum64 = gshift(csum64, go);
+    x32r = gshift(x32r, go);
+    x32b = gshift(x32b, go);
+    gshift_slot(rs, go);
+    gconsts(sc, grp);
     constexpr int TJ = 2 * kBlock / TK;
     __shared__ RingSlots<double, TK, TJ> win;
     const int n = F.n, nh = F.nh, nI = n / PL, nK = nh / TK;
@@ -364,8 +391,16 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
 template <typename R, bool CORR, int TKc, int PLc>
 __global__ __launch_bounds__(kBlock) void k_prolong_tile(LevelView<R> F, R *__restrict__ xr, R *__restrict__ xb,
                                                          LevelView<R> C, const R *__restrict__ cxr,
-                                                         const R *__restrict__ cxb, Span sp, unsigned ntiles)
+                                                         const R *__restrict__ cxb, Span sp, unsigned ntiles,
+                                                         Group grp)
 {
+    const long long go = group_offset(grp);
+    gshift_view(F, go);
+    gshift_view(C, go);
+    xr = gshift(xr, go);
+    xb = gshift(xb, go);
+    cxr = gshift(cxr, go);
+    cxb = gshift(cxb, go);
     constexpr int RPc = kBlock / TKc;
     constexpr int WR = RPc + 2, WC = TKc + 2, W = WR * WC;
     constexpr int PER = (W + kBlock - 1) / kBlock;
@@ -493,11 +528,11 @@ bool launch_residual_restrict_tiled(const LevelView<R> &F, const R *xr, const R 
 #define PM_RR(TKV, PLV)                                                                                                \
     do {                                                                                                               \
         if (nonlinear)                                                                                                 \
-            hipLaunchKernelGGL((k_residual_restrict_tile<R, true, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0, st, \
-                               F, xr, xb, csum, C, cxr, cxb, rs, sc, g.sp, g.ntiles);                                  \
+            hipLaunchKernelGGL((k_residual_restrict_tile<R, true, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), \
+                               0, st, F, xr, xb, csum, C, cxr, cxb, rs, sc, g.sp, g.ntiles, cur_group());              \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_residual_restrict_tile<R, false, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0,    \
-                               st, F, xr, xb, csum, C, cxr, cxb, rs, sc, g.sp, g.ntiles);                              \
+            hipLaunchKernelGGL((k_residual_restrict_tile<R, false, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), \
+                               0, st, F, xr, xb, csum, C, cxr, cxb, rs, sc, g.sp, g.ntiles, cur_group());              \
     } while (0)
     PM_PAIR_DISPATCH(PM_RR)
 #undef PM_RR
@@ -515,11 +550,11 @@ bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, Reduc
 #define PM_FT(TKV, PLV)                                                                                                \
     do {                                                                                                               \
         if (nonlinear)                                                                                                 \
-            hipLaunchKernelGGL((k_fas_tau_tile<R, true, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0, st, L, xr,    \
-                               xb, rs, sc, g.sp, g.ntiles, accumulate_only);                                           \
+            hipLaunchKernelGGL((k_fas_tau_tile<R, true, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, L,  \
+                               xr, xb, rs, sc, g.sp, g.ntiles, accumulate_only, cur_group());                          \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_fas_tau_tile<R, false, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0, st, L, xr,   \
-                               xb, rs, sc, g.sp, g.ntiles, accumulate_only);                                           \
+            hipLaunchKernelGGL((k_fas_tau_tile<R, false, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, L, \
+                               xr, xb, rs, sc, g.sp, g.ntiles, accumulate_only, cur_group());                          \
     } while (0)
     PM_PAIR_DISPATCH(PM_FT)
 #undef PM_FT
@@ -537,11 +572,11 @@ bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, co
 #define PM_MO(TKV, PLV)                                                                                                \
     do {                                                                                                               \
         if (nonlinear)                                                                                                 \
-            hipLaunchKernelGGL((k_mixed_outer_tile<true, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0, st, F64, xr, \
-                               xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles);                                   \
+            hipLaunchKernelGGL((k_mixed_outer_tile<true, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st,    \
+                               F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cur_group());             \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_mixed_outer_tile<false, TKV, PLV>), dim3(g.sp.nblocks), dim3(kBlock), 0, st, F64,    \
-                               xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles);                               \
+            hipLaunchKernelGGL((k_mixed_outer_tile<false, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st,   \
+                               F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cur_group());             \
     } while (0)
     PM_PAIR_DISPATCH(PM_MO)
 #undef PM_MO
@@ -571,8 +606,8 @@ bool launch_prolong_tiled(const LevelView<R> &F, R *xr, R *xb, const LevelView<R
     sp.chunk = kBlock;
     sp.total = nb * kBlock;
 #define PM_PT(CV, TKV, PLV)                                                                                            \
-    hipLaunchKernelGGL((k_prolong_tile<R, CV, TKV, PLV>), dim3(nb), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, sp,   \
-                       ntiles)
+    hipLaunchKernelGGL((k_prolong_tile<R, CV, TKV, PLV>), group_grid(nb), dim3(kBlock), 0, st, F, xr, xb, C, cxr, cxb, \
+                       sp, ntiles, cur_group())
 #define PM_PT_C(TKV, PLV)                                                                                              \
     do {                                                                                                               \
         if (corr)                                                                                                      \

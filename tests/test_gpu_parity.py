@@ -547,6 +547,46 @@ def test_batched_equals_single_solves_bitwise(P):
         assert rel(got, ref) < 1e-5, n
 
 
+@pytest.mark.parametrize("precision,guess", [("mixed", "zero"), ("f64", "zero"), ("mixed", "linear"),
+                                             ("mixed", "given")])
+def test_grouped_batch_equals_single_solves_bitwise(P, precision, guess):
+    """Problems of one grid and dtype are solved in lockstep, one launch per
+    step for the whole group.  Members converge after different numbers of
+    V-cycles (and, mixed, switch to FP64 at different outer steps), one has
+    no scalar source (alpha_B0 = alpha_M0 = 0); each equals its own single
+    solve bit for bit, with the same report."""
+    from workloads import lognormal_density
+
+    # (alpha_B0, alpha_M0, screening): screening off is a linear solve, run
+    # as its own lockstep pass after the nonlinear members
+    groups = [(48, torch.float32, [(-0.1, 0.0, 1), (-0.6, 0.1, 1), (0.0, 0.0, 1), (-0.9, 0.2, 1), (-0.3, 0.05, 1),
+                                   (-0.4, 0.0, 0), (-0.8, 0.1, 0)]),
+              (32, torch.float64, [(-0.2, 0.0, 1), (-1.0, 0.15, 1), (-0.5, 0.0, 1), (-0.3, 0.0, 0)])]
+    probs = []
+    for n, dt, pars in groups:
+        for k, (ab, am, scr) in enumerate(pars):
+            rho = torch.from_numpy(lognormal_density(n, 500.0 * n / 256, seed=4100 + 10 * n + k)).to("cuda", dt)
+            guess0 = torch.zeros_like(rho)
+            if guess == "given":
+                guess0 = 1e-4 * torch.sin(torch.arange(rho.numel(), device="cuda", dtype=torch.float64)
+                                          ).reshape(rho.shape).to(dt)
+            probs.append(dict(rho=rho, chi=guess0.clone(), guess0=guess0,
+                              params=dict(omega_m0=0.3071, alpha_b0=ab, alpha_m0=am, a=1.0, screening=scr)))
+    opts = P.MgOpts(rel_tol=1e-9, max_vcycles=60, precision=precision, guess=guess)
+    reps = P.mg_scalar_solve_batched(probs, opts)
+    vcycles = set()
+    for k, pr in enumerate(probs):
+        single = pr["guess0"].clone()
+        rep = P.mg_scalar_solve(pr["rho"], pr["params"], opts, single)
+        assert torch.equal(single, pr["chi"]), k
+        for key in ("status", "vcycles", "rel_residual", "clamped_cells", "mean_shift"):
+            assert reps[k][key] == rep[key], (k, key)
+        assert reps[k]["residual_hist"] == rep["residual_hist"], k
+        vcycles.add(rep["vcycles"])
+    assert len(vcycles) >= 3  # the members left the lockstep at different cycles
+    assert float(probs[2]["chi"].abs().max()) == 0.0  # no scalar source
+
+
 def test_batched_rejects_learned_and_bad_sizes(P):
     rho = torch.ones((32, 32, 32), dtype=torch.float64, device="cuda")
     prm = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
