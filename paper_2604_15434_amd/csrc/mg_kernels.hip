@@ -1038,6 +1038,24 @@ void launch_scale(const double *x, double *y, double a, long long n, hipStream_t
     hipLaunchKernelGGL(k_scale, group_grid(sp.nblocks), dim3(kBlock), 0, st, x, y, a, sp, cur_group());
 }
 
+// src[0 .. count-1] into host memory, then the sequence number (one lane, a
+// system-scope release between them), for a host that polls the sequence
+// number instead of synchronising the stream.
+__global__ void k_publish(const double *__restrict__ src, int count, double *dst, unsigned *seqp, unsigned seq)
+{
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < count; q++)
+            dst[q] = src[q];
+        __threadfence_system();
+        *(volatile unsigned *)seqp = seq;
+    }
+}
+
+void launch_publish(const double *src, int count, double *dst, unsigned *seqp, unsigned seq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, src, count, dst, seqp, seq);
+}
+
 // dst[s * count + q] = src[q] of slot s (slot s at src + s * stride bytes),
 // for the m slots of a group: their norms in one contiguous readback.
 __global__ __launch_bounds__(kBlock) void k_gather_slots(const double *__restrict__ src, long long stride, int m,

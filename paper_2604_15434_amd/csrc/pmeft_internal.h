@@ -336,6 +336,9 @@ void launch_subtract_mean(double *x, long long n, const double *sum_ptr, hipStre
 // y = a * x
 void launch_scale(const double *x, double *y, double a, long long n, hipStream_t st);
 void launch_zero(void *p, size_t bytes, hipStream_t st);
+// dst[0 .. count-1] = src (dst in host memory the device can write), then
+// *seqp = seq after a system-scope fence
+void launch_publish(const double *src, int count, double *dst, unsigned *seqp, unsigned seq, hipStream_t st);
 // dst[s * count + q] = src[q] of slot s = 0 .. m-1 (slots `stride` bytes apart);
 // not a grouped launch (one grid covers every slot)
 void launch_gather_slots(const double *src, long long stride, int m, int count, double *dst, hipStream_t st);
