@@ -469,6 +469,87 @@ def test_pm_step_256_matches_oracle(P, k, mode, shape):
 
 
 # ------------------------------------------------------------------ edge cases
+# ---------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("ng", [8, 12])
+@pytest.mark.parametrize("prec", ["f64", "mixed"])
+def test_smallest_grids_match_oracle(P, ng, prec):
+    """The shallowest hierarchies: 8^3 (the 4^3 coarsest level right below the
+    finest) and 12^3 (the 6^3 coarsest solve by one workgroup); the scalar
+    field against the oracle, Poisson against the exact FFT solve."""
+    rho = lognormal_density(ng, 500.0 * ng / 256, seed=31)
+    p = dict(omega_m0=0.3071, alpha_b0=-0.6, alpha_m0=0.1, a=1.0)
+    c = oracle.eft_coefficients(**p)
+    delta = oracle.density_contrast(rho)
+    ref_chi, orep = oracle.solve_chi(delta, c, 1.0 / ng, tol=1e-12, max_cycles=400)
+    ref_psi = oracle.solve_poisson(delta, c, 1.0 / ng)
+    tol = 1e-12 if prec == "f64" else 1e-9
+    chi = torch.zeros((ng, ng, ng), dtype=torch.float64, device="cuda")
+    rep = P.mg_scalar_solve(dev(rho), p, P.MgOpts(rel_tol=tol, max_vcycles=100, precision=prec), chi)
+    assert rep["status"] == 0 and rep["clamped_cells"] == orep["clamped"], rep
+    assert rel(_mean_free(chi.cpu().numpy()), ref_chi) < (1e-10 if prec == "f64" else 1e-5)
+    psi = torch.zeros_like(chi)
+    rep = P.mg_poisson_solve(dev(rho), p, P.MgOpts(rel_tol=tol, max_vcycles=100, precision=prec), psi)
+    assert rep["status"] == 0, rep
+    assert rel(_mean_free(psi.cpu().numpy()), ref_psi) < (1e-10 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_particles_on_faces_and_box_edges(P, dtype):
+    """Particles at x = 0, on cell faces and centres and just below 1 (the
+    largest position below the box length in the array's precision): the
+    deposit equals the oracle's with the mass conserved, the same particles
+    in base-cell order take the gather and give the same grid bit for bit, a
+    single particle spreads over its 8 corners, and a step with them matches
+    the oracle's forces."""
+    import itertools
+
+    ng = 16
+    h = 1.0 / ng
+    below_one = float(np.nextafter(np.float32(1.0), np.float32(0.0))) if dtype == torch.float32 else \
+        float(np.nextafter(1.0, 0.0))
+    coords = [0.0, 0.5 * h, h, 3.25 * h, 0.5, 1.0 - 0.5 * h, below_one]
+    pos = np.array(list(itertools.product(coords, repeat=3)), dtype=np.float64).T.copy()
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    pos_t = pos.astype(npdt).astype(np.float64)  # the positions the GPU sees
+    ref = oracle.cic_deposit(pos_t, ng)
+    tol = 1e-10 if dtype == torch.float64 else 2e-5 * max(1.0, ref.max())
+    gp = dev(pos_t, dtype)
+    rho = torch.empty((ng, ng, ng), dtype=dtype, device="cuda")
+    P.pm_deposit(gp, ng, rho)
+    got = rho.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() < tol
+    # total mass: exact fixed-point sums, then the output dtype's rounding per cell
+    assert abs(got.sum() - ng ** 3) < (1e-9 if dtype == torch.float64 else 1e-5) * ng ** 3
+    sorted_pos = gp.clone()
+    P.pm_sort_particles(sorted_pos, ng)
+    rho_g = torch.empty_like(rho)
+    P.pm_deposit(sorted_pos, ng, rho_g)
+    assert torch.equal(rho_g, rho)
+    one = np.array([[0.3], [0.7], [below_one]])
+    one_t = one.astype(npdt).astype(np.float64)
+    rho1 = torch.empty_like(rho)
+    P.pm_deposit(dev(one_t, dtype), ng, rho1)
+    r1 = rho1.cpu().numpy().astype(np.float64)
+    ref1 = oracle.cic_deposit(one_t, ng)
+    # (weights rounded to 2^-40 and scaled by ng^3 / np = 4096: about 2e-9 per cell in FP64)
+    assert np.count_nonzero(ref1) == 8 and np.abs(r1 - ref1).max() < (1e-8 if dtype == torch.float64 else 1e-1)
+    assert abs(r1.sum() - ng ** 3) < 1e-6 * ng ** 3
+    # a step: forces against the oracle (positions are not drifted)
+    vel = np.zeros_like(pos_t)
+    refs = oracle.pm_step(pos_t, vel, ng, CFG0, dt_kick=1.0, tol=1e-12)
+    prec = "f64" if dtype == torch.float64 else "mixed"
+    stol = 1e-12 if prec == "f64" else 1e-7
+    gv = dev(vel, dtype)
+    psi = torch.zeros((ng, ng, ng), dtype=dtype, device="cuda")
+    chi = torch.zeros_like(psi)
+    rep = P.pm_step(gp, gv, ng, CFG0, P.MgOpts(rel_tol=stol, max_vcycles=80, precision=prec),
+                    P.MgOpts(rel_tol=stol, max_vcycles=80, precision=prec), 1.0, 0.0, psi, chi)
+    assert rep["status"] == 0, rep
+    acc = gv.cpu().numpy().astype(np.float64)
+    err = np.sqrt(np.mean(np.sum((acc - refs["acc"]) ** 2, 0)) / np.mean(np.sum(refs["acc"] ** 2, 0)))
+    assert err < (1e-9 if dtype == torch.float64 else 1e-4)
+
+
 def test_lcdm_gives_zero_scalar_field(P):
     ng = 16
     rho = lognormal_density(ng, 30.0, seed=1)
