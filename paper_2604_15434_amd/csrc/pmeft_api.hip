@@ -1329,11 +1329,6 @@ int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, 
     return launched();
 }
 
-// ---- batched solve ---------------------------------------------------------
-// Host workers, each with its own stream and workspace slice, take the
-// problems largest grid first from a shared counter and run the single-problem
-// solve on them; the kernel sequence of a problem does not depend on the
-// worker, so each result equals the problem's own solve bit for bit.
 // ---- grouped batched solves ----------------------------------------------
 // The problems are grouped by (grid, dtype of their arrays), largest grid
 // first, and each group is solved in lockstep: one launch per kernel of the
