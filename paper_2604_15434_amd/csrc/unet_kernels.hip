@@ -182,36 +182,77 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ 
 #pragma unroll
         for (int u = 0; u < COT; u++)
             acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 0; c0 < cin_pad; c0 += 16) {
-        // stage the neighbourhood: voxel v = (plane * 6 + row) * 66 + col, 16 channels as 4 x 8 bytes
-        for (int u = threadIdx.x; u < kCvVox * 4; u += 256) {
-            const int v = u >> 2, part = u & 3;
-            const int pl = v / ((kCvRows + 2) * (kCvK + 2));
-            const int rem = v - pl * (kCvRows + 2) * (kCvK + 2);
-            const int row = rem / (kCvK + 2), col = rem - row * (kCvK + 2);
-            const int ii = wrapi(i + pl - 1, n), jj = wrapi(j0 + row - 1, n), kk = wrapi(k0 + col - 1, n);
-            const uint2 val =
-                *(const uint2 *)(in + (size_t)((ii * n + jj) * n + kk) * in_stride + in_off + c0 + 4 * part);
-            *(uint2 *)(tile + v * kCvStride + 4 * part) = val;
-        }
-        __syncthreads();
-        for (int tap = 0; tap < 27; tap++) {
-            int di, dj, dk;
-            tap_offsets(tap, di, dj, dk);
-            const int pl = 1 + sgn * di, row = 1 + wave + sgn * dj, colb = 1 + r + sgn * dk;
-            const uint16_t *tb = tile + ((pl * (kCvRows + 2) + row) * (kCvK + 2) + colb) * kCvStride + 4 * q;
-            bf16x4 a[4], b[COT];
+    // weight fragments of tap `tap` and input slice c0 for this lane (a
+    // uniform base plus the lane's offset)
+    const unsigned wlane = (unsigned)((co_base + r) * cin_pad + 4 * q);
+    auto load_b = [&](int tap, int c0, bf16x4 *dst) {
 #pragma unroll
-            for (int m = 0; m < 4; m++)
-                a[m] = *(const bf16x4 *)(tb + 16 * m * kCvStride);
+        for (int u = 0; u < COT; u++) {
+            const uint16_t *wt = wp + ((size_t)tap * cout_pad + u * 16) * cin_pad + c0;
+            dst[u] = *(const bf16x4 *)(wt + wlane);
+        }
+    };
+    // staging of one 16-channel input slice: this thread's 8-byte chunks of
+    // the 3 x 6 x 66 neighbourhood in three batches, each with all its loads
+    // issued before any is stored (one batch's registers keep three blocks
+    // per CU)
+    constexpr int NST = (kCvVox * 4 + 255) / 256, NB = (NST + 2) / 3;
+    const int part = threadIdx.x & 3;
+    auto stage = [&](int c0, int st0) {
+        uint2 stg[NB];
+#pragma unroll
+        for (int u = 0; u < NB; u++) {
+            const int v = (threadIdx.x >> 2) + 64 * (st0 + u);
+            if (st0 + u < NST && v < kCvVox) {
+                const int pl = v / ((kCvRows + 2) * (kCvK + 2));
+                const int rem = v - pl * (kCvRows + 2) * (kCvK + 2);
+                const int row = rem / (kCvK + 2), col = rem - row * (kCvK + 2);
+                const int ii = wrapi(i + pl - 1, n), jj = wrapi(j0 + row - 1, n), kk = wrapi(k0 + col - 1, n);
+                stg[u] = *(const uint2 *)(in + (size_t)((ii * n + jj) * n + kk) * in_stride + in_off + c0 + 4 * part);
+            }
+        }
+        // voxel v = (plane * 6 + row) * 66 + col, 16 channels as 4 x 8 bytes
+#pragma unroll
+        for (int u = 0; u < NB; u++) {
+            const int v = (threadIdx.x >> 2) + 64 * (st0 + u);
+            if (st0 + u < NST && v < kCvVox)
+                *(uint2 *)(tile + v * kCvStride + 4 * part) = stg[u];
+        }
+    };
+    // one tap: the MFMAs of tap `tap` on weights bc while the weights of tap
+    // + 2 load into bl (the slot of the tap computed last; the last two taps
+    // reload tap 26, unconditionally, so the wait counts stay static)
+    auto tap_step = [&](int tap, int c0, const bf16x4 *bc, bf16x4 *bl) {
+        load_b(tap + 2 < 27 ? tap + 2 : 26, c0, bl);
+        int di, dj, dk;
+        tap_offsets(tap, di, dj, dk);
+        const int pl = 1 + sgn * di, row = 1 + wave + sgn * dj, colb = 1 + r + sgn * dk;
+        const uint16_t *tb = tile + ((pl * (kCvRows + 2) + row) * (kCvK + 2) + colb) * kCvStride + 4 * q;
+        bf16x4 a[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+            a[m] = *(const bf16x4 *)(tb + 16 * m * kCvStride);
+#pragma unroll
+        for (int m = 0; m < 4; m++)
 #pragma unroll
             for (int u = 0; u < COT; u++)
-                b[u] = *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * cin_pad + c0 + 4 * q);
-#pragma unroll
-            for (int m = 0; m < 4; m++)
-#pragma unroll
-                for (int u = 0; u < COT; u++)
-                    acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], b[u], acc[m][u], 0, 0, 0);
+                acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bc[u], acc[m][u], 0, 0, 0);
+    };
+    for (int c0 = 0; c0 < cin_pad; c0 += 16) {
+        // weights two taps ahead in a ring of three register slots; the first
+        // two taps' load with the slice
+        bf16x4 b0[COT], b1[COT], b2[COT];
+        load_b(0, c0, b0);
+        load_b(1, c0, b1);
+        stage(c0, 0);
+        stage(c0, NB);
+        stage(c0, 2 * NB);
+        __syncthreads();
+#pragma unroll 1
+        for (int t3 = 0; t3 < 27; t3 += 3) {
+            tap_step(t3, c0, b0, b2);
+            tap_step(t3 + 1, c0, b1, b0);
+            tap_step(t3 + 2, c0, b2, b1);
         }
         __syncthreads();
     }
@@ -265,35 +306,40 @@ static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int c
 
 // Plane-marching variant for grids with n % 64 == 0 and at most 48 input
 // channels (8-aligned views): a block of 8 waves owns 4 rows (j) by 64 voxels
-// (k), two waves per row of 32 voxels, and walks PL planes along i, keeping
-// input planes i - 1, i, i + 1 (6 x 66 voxels, all input channels) in an LDS
-// ring of NS slots (one barrier per plane with 4 slots, two with 3), so every
-// input voxel is staged about 1.5 times instead of 4.6.  The K index of the
-// implicit GEMM runs over (tap, channel); it is consumed in chunks of 32 by
-// v_mfma_f32_16x16x32_bf16 (a chunk may span two taps: each lane's 8 values
-// lie in one tap, 8-aligned channels) and a final 16 by the 16x16x16 form
-// when 27 * cin_pad is not a multiple of 32.  The voxel stride in LDS is an
-// odd number of 16-byte units (the 16-byte fragment reads of 8 consecutive
-// lanes then fall in distinct banks).
+// (k), two waves per row of 32 voxels, and walks the input planes s = i0 - 1
+// .. i0 + PL of its PL output planes i0 .. i0 + PL - 1.  Input plane s
+// (6 x 66 voxels, all input channels, in an LDS ring of three slots: plane
+// s + 2 loads while s is computed) feeds the output planes s - 1, s and s + 1
+// through the taps with di = +1, 0, -1 (forward; mirrored for the input
+// gradient), held in three rolling accumulators: every activation fragment
+// read from LDS feeds three MFMAs, and output plane s - 1 is complete after
+// plane s.  Per input plane the K index runs over the 9 (dj, dk) taps and the
+// channels, in chunks of 32 on v_mfma_f32_16x16x32_bf16 (a chunk may span two
+// taps: each lane's 8 values lie in one tap, 8-aligned channels) and a final
+// 16 on the 16x16x16 form when 9 * cin_pad is not a multiple of 32; each
+// output still sums its taps in order.  The voxel stride in LDS is an odd
+// number of 16-byte units (the 16-byte fragment reads of 8 consecutive lanes
+// then fall in distinct banks).  PL = 2 mod 3, so the steps between the two
+// boundary steps at each end come in whole rounds of the three slots.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMarchThreads = 512;
 
+template <int V>
+struct IConst {
+    static constexpr int value = V;
+};
+
 //
 // HD (one 16-channel output tile, ReLU): the network's 1x1x1 output head is
 // applied in the epilogue, out[v] = hb + sum_o hw[o] relu(conv[v][o]) as
 // FP32 in natural voxel order, and the 16-channel activation is never stored
-// (nor rounded to BF16, as the unfused form rounds it).  The channel sum runs over the 16 lanes of a row of the MFMA result
-// (row rotations 8, 4, 2, 1).
-//
-// AH: the loads of plane i + 3 are issued before plane i is computed (two
-// planes in flight instead of one; the ring is unchanged, the registers of
-// plane i + 2 are stored after plane i).  Only where the registers allow it
-// (16 input channels).
-template <int CS, int COT, int NS, bool HD = false, bool AH = false>
-__global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *__restrict__ in, int in_stride, int in_off,
+// (nor rounded to BF16, as the unfused form rounds it).  The channel sum runs
+// over the 16 lanes of a row of the MFMA result (row rotations 8, 4, 2, 1).
+template <int CS, int COT, bool HD = false>
+__global__ __launch_bounds__(kMarchThreads) __attribute__((amdgpu_waves_per_eu(CS == 1 && COT == 1 ? 4 : 1))) void k_conv3_march(const uint16_t *__restrict__ in, int in_stride, int in_off,
                                                      const uint16_t *__restrict__ wp, int cout_pad,
                                                      const float *__restrict__ bias, int cout, void *__restrict__ out,
                                                      int out_stride, int out_off, int out_f32, int n, int flip,
@@ -301,7 +347,6 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                                                      const float *__restrict__ hb)
 {
     static_assert(!HD || COT == 1, "the head reads one output tile");
-    static_assert(!AH || NS == 4, "two planes ahead needs the four-slot ring");
     // TR: weights as the A operand, so the result is D[channel][voxel] and a
     // lane holds four consecutive channels of one voxel (vector stores when
     // the output view is 4-aligned); the head keeps D[voxel][channel]
@@ -312,9 +357,9 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
     constexpr int WV = 6 * 66;                  // voxels per staged plane
     constexpr int NCH = WV * (CP / 8);          // 16-byte chunks per plane
     constexpr int PER = (NCH + kMarchThreads - 1) / kMarchThreads;
-    constexpr int KT = 27 * CP;                 // GEMM K
-    constexpr int NK32 = KT / 32, TAIL = KT % 32;
-    __shared__ __align__(16) uint16_t ring[NS * WV * SV];
+    constexpr int KP = 9 * CP;                  // GEMM K per input plane
+    constexpr int NK = KP / 32, TAIL = KP % 32;
+    __shared__ __align__(16) uint16_t ring[3 * WV * SV];
     const int wave = threadIdx.x >> 7, mh = ((threadIdx.x >> 6) & 1) * 2;  // row, first m-tile
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
@@ -324,21 +369,31 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
     const size_t plane_elems = (size_t)n * n * in_stride;
     const unsigned nb = gridDim.x;
     const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
-    // with 16 input channels and one output tile the B fragments of all K
-    // chunks (13 x 4 + 2 VGPRs) stay in registers for the whole block
-    constexpr bool BREG = CS == 1 && COT == 1;
-    bf16x8 bw[BREG ? NK32 : 1];
-    bf16x4 btl = {0, 0, 0, 0};
+    // B fragments of output offset e (output plane s - 1 + e takes input plane
+    // s through the tap with di = sgn (1 - e)) and K chunk c; in registers for
+    // the whole block where they fit
+    constexpr bool BREG = COT == 1 && CS <= 2;
+    auto wfrag8 = [&](const uint16_t *w, int e, int c, int u) {
+        const int kk = 32 * c + 8 * q, tap = (1 + sgn * (1 - e)) * 9 + kk / CP, ch = kk % CP;
+        return __builtin_bit_cast(bf16x8, *(const u32x4 *)(w + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch));
+    };
+    auto wfrag4 = [&](const uint16_t *w, int e, int u) {
+        const int kk = 32 * NK + 4 * q, tap = (1 + sgn * (1 - e)) * 9 + kk / CP, ch = kk % CP;
+        return *(const bf16x4 *)(w + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch);
+    };
+    bf16x8 bw[BREG ? 3 : 1][BREG ? NK : 1][COT];
+    bf16x4 bt[BREG && TAIL ? 3 : 1][COT];
     if constexpr (BREG) {
 #pragma unroll
-        for (int kc = 0; kc < NK32; kc++) {
-            const int kk = kc * 32 + 8 * q, tap = kk / CP, ch = kk % CP;
-            bw[kc] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(wp + ((size_t)tap * cout_pad + co_base + r) * CP + ch));
-        }
-        if (TAIL) {
-            const int kk = NK32 * 32 + 4 * q, tap = kk / CP, ch = kk % CP;
-            btl = *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + r) * CP + ch);
-        }
+        for (int e = 0; e < 3; e++)
+#pragma unroll
+            for (int u = 0; u < COT; u++) {
+#pragma unroll
+                for (int c = 0; c < NK; c++)
+                    bw[e][c][u] = wfrag8(wp, e, c, u);
+                if constexpr (TAIL != 0)
+                    bt[e][u] = wfrag4(wp, e, u);
+            }
     }
     for (unsigned t = lb; t < ntiles; t += nb) {
         const int ib = (int)(t % nit), kt = (int)((t / nit) % nkt), jt = (int)(t / ((unsigned)nit * nkt));
@@ -356,137 +411,61 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
             soff[u] = (unsigned)((jj * n + kk) * in_stride + in_off + 8 * part);
             loff[u] = v * SV + 8 * part;
         }
-        u32x4 pre[PER], pre2[AH ? PER : 1];
-#define PM_MARCH_FETCH_TO(DST, II)                                                                                     \
-    do {                                                                                                               \
-        const uint16_t *base_ = in + (size_t)wrapi((II), n) * plane_elems;                                             \
-        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH) DST[u] =           \
-            *(const u32x4 *)(base_ + soff[u]);                                                                         \
-    } while (0)
-#define PM_MARCH_FETCH(II) PM_MARCH_FETCH_TO(pre, II)
-#define PM_MARCH_STORE(SLOT)                                                                                           \
-    do {                                                                                                               \
-        uint16_t *dst_ = ring + (SLOT) * WV * SV;                                                                      \
-        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kMarchThreads < NCH)                    \
-            *(u32x4 *)(dst_ + loff[u]) = pre[u];                                                                       \
-    } while (0)
-        PM_MARCH_FETCH(i0 - 1);
-        PM_MARCH_STORE(0);
-        PM_MARCH_FETCH(i0);
-        PM_MARCH_STORE(1);
-        PM_MARCH_FETCH(i0 + 1);
-        PM_MARCH_STORE(2);
-        if (AH)
-            PM_MARCH_FETCH(i0 + 2);
+        u32x4 pre[PER];
+        auto fetch = [&](int ii) {
+            const uint16_t *base = in + (size_t)wrapi(ii, n) * plane_elems;
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kMarchThreads < NCH)
+                    pre[u] = *(const u32x4 *)(base + soff[u]);
+        };
+        auto put = [&](int slot) {
+            uint16_t *dst = ring + slot * WV * SV;
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kMarchThreads < NCH)
+                    *(u32x4 *)(dst + loff[u]) = pre[u];
+        };
+        fetch(i0 - 1);
+        put(0);
+        fetch(i0);
+        put(1);
         __syncthreads();
-        for (int p = 0; p < PL; p++) {
-            const int i = i0 + p;
-            // ring slot of plane i - 1 + d is (p + d) % NS
-            if (AH) {
-                if (p + 2 < PL)
-                    PM_MARCH_FETCH_TO(pre2, i + 3);
-            } else if (p + 1 < PL) {
-                PM_MARCH_FETCH(i + 2);
-            }
-            f32x4 acc[2][COT];
+        f32x4 acc[3][2][COT];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
 #pragma unroll
             for (int m = 0; m < 2; m++)
 #pragma unroll
                 for (int u = 0; u < COT; u++)
-                    acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            // LDS halfword offset of this lane's A row (voxel 16 (mh + m) + r) for the
-            // tap (di, dj, dk), before the channel offset
-            auto a_base = [&](int tap) {
-                int di, dj, dk;
-                tap_offsets(tap, di, dj, dk);
-                const int slot = (p + 1 + sgn * di) % NS;
-                return ((slot * 6 + 1 + wave + sgn * dj) * 66 + 1 + 16 * mh + r + sgn * dk) * SV;
-            };
-            if constexpr (BREG) {
-                // A fragments two chunks ahead of the MFMAs that use them
-                constexpr int DEPTH = 3;
-                bf16x8 af[DEPTH][2];
-#pragma unroll
-                for (int kc = 0; kc < NK32 + DEPTH - 1; kc++) {
-                    if (kc < NK32) {
-                        const int kk = kc * 32 + 8 * q;  // this lane's first K index
-                        const int ab = a_base(kk / CP) + kk % CP;
-#pragma unroll
-                        for (int m = 0; m < 2; m++)
-                            af[kc % DEPTH][m] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(ring + ab + 16 * m * SV));
-                    }
-                    const int ku = kc - (DEPTH - 1);
-                    if (ku >= 0) {
-#pragma unroll
-                        for (int m = 0; m < 2; m++)
-                            acc[m][0] = TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[ku], af[ku % DEPTH][m],
-                                                                                     acc[m][0], 0, 0, 0)
-                                           : __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ku % DEPTH][m], bw[ku],
-                                                                                     acc[m][0], 0, 0, 0);
-                    }
-                }
-            } else {
-#pragma unroll 2
-                for (int kc = 0; kc < NK32; kc++) {
-                    const int kk = kc * 32 + 8 * q;  // this lane's first K index
-                    const int tap = kk / CP, ch = kk % CP;
-                    const int ab = a_base(tap) + ch;
-                    bf16x8 b[COT];
-#pragma unroll
-                    for (int u = 0; u < COT; u++)
-                        b[u] = __builtin_bit_cast(
-                            bf16x8, *(const u32x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch));
-#pragma unroll
-                    for (int m = 0; m < 2; m++) {
-                        const bf16x8 a = __builtin_bit_cast(bf16x8, *(const u32x4 *)(ring + ab + 16 * m * SV));
-#pragma unroll
-                        for (int u = 0; u < COT; u++)
-                            acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a, acc[m][u], 0, 0, 0);
-                    }
-                }
-            }
-            if (TAIL) {
-                const int kk = NK32 * 32 + 4 * q;
-                const int tap = kk / CP, ch = kk % CP;
-                const int ab = a_base(tap) + ch;
-                bf16x4 b[COT];
-#pragma unroll
-                for (int u = 0; u < COT; u++)
-                    b[u] = BREG ? btl : *(const bf16x4 *)(wp + ((size_t)tap * cout_pad + co_base + u * 16 + r) * CP + ch);
-#pragma unroll
-                for (int m = 0; m < 2; m++) {
-                    const bf16x4 a = *(const bf16x4 *)(ring + ab + 16 * m * SV);
-#pragma unroll
-                    for (int u = 0; u < COT; u++)
-                        acc[m][u] = TR ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[u], a, acc[m][u], 0, 0, 0)
-                                       : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[u], acc[m][u], 0, 0, 0);
-                }
-            }
-            const size_t vbase = ((size_t)i * n + j0 + wave) * n + k0;
+                    acc[a][m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // output plane o from its accumulators
+        auto store_plane = [&](int o, const f32x4 (&ac)[2][COT]) {
+            const size_t vbase = ((size_t)o * n + j0 + wave) * n + k0;
             if constexpr (HD) {
                 // lane (r, q) holds channel r of voxels 16 (mh + m) + 4 q + e
                 const float bo = bias[r], ho = hw[r];
-                float s[2][4];
+                float sm[2][4];
 #pragma unroll
                 for (int m = 0; m < 2; m++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        float v = ho * fmaxf(acc[m][0][e] + bo, 0.f);
+                        float v = ho * fmaxf(ac[m][0][e] + bo, 0.f);
                         v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
                         v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false));
                         v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x122, 0xf, 0xf, false));
                         v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x121, 0xf, 0xf, false));
-                        s[m][e] = v;
+                        sm[m][e] = v;
                     }
                 // every lane of a row now holds the row's eight sums; lane r < 8
                 // writes voxel 16 (mh + r / 4) + 4 q + r % 4
                 const int mm = (r >> 2) & 1, ee = r & 3;
-                float y = s[0][0];
+                float y = sm[0][0];
 #pragma unroll
                 for (int m = 0; m < 2; m++)
 #pragma unroll
                     for (int e = 0; e < 4; e++)
-                        y = (mm == m && ee == e) ? s[m][e] : y;
+                        y = (mm == m && ee == e) ? sm[m][e] : y;
                 if (r < 8)
                     ((float *)out)[vbase + 16 * (mh + mm) + 4 * q + ee] = hb[0] + y;
             } else {
@@ -503,7 +482,7 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                         float v[4];
 #pragma unroll
                         for (int e = 0; e < 4; e++)
-                            v[e] = relu ? fmaxf(acc[m][u][e] + bo[e], 0.f) : acc[m][u][e] + bo[e];
+                            v[e] = relu ? fmaxf(ac[m][u][e] + bo[e], 0.f) : ac[m][u][e] + bo[e];
                         const size_t idx = (vbase + 16 * (mh + m) + r) * out_stride + out_off + o0;
                         if (vec && o0 + 3 < cout) {
                             if (out_f32)
@@ -524,27 +503,104 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
                     }
                 }
             }
-            if (NS == 4) {
-                // plane i + 2 into the slot of plane i - 2 (last read before the previous barrier)
-                if (p + 1 < PL) {
-                    PM_MARCH_STORE((p + 3) % NS);
-                    if (AH) {
+        };
+        // one input plane s whose ring slot (and the accumulator slot of output
+        // plane s - 1) is JM; LD: plane s + 2 is still to be staged; ST: output
+        // plane s - 1 lies in the tile
+        auto step = [&](int s, auto JM, auto LD, auto ST) {
+            constexpr int jm = decltype(JM)::value;
+            if constexpr (decltype(LD)::value)
+                fetch(s + 2);
+            const uint16_t *sl = ring + jm * WV * SV;
+            // without register-resident weights each step loads its own
+            // (the empty asm keeps them from being hoisted out of the loops)
+            const uint16_t *ws = wp;
+            if constexpr (!BREG)
+                asm volatile("" : "+s"(ws));
+            auto chunk = [&](int c) {
+                const int kk = 32 * c + 8 * q, tip = kk / CP, ch = kk % CP;
+                const int dj = tip / 3 - 1, dk = tip % 3 - 1;
+                const int ab = ((1 + wave + sgn * dj) * 66 + 1 + 16 * mh + r + sgn * dk) * SV + ch;
+                bf16x8 a[2];
 #pragma unroll
-                        for (int u = 0; u < PER; u++)
-                            pre[u] = pre2[u];
-                    }
+                for (int m = 0; m < 2; m++)
+                    a[m] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(sl + ab + 16 * m * SV));
+#pragma unroll
+                for (int e = 0; e < 3; e++) {
+                    bf16x8 b[COT];
+#pragma unroll
+                    for (int u = 0; u < COT; u++)
+                        b[u] = BREG ? bw[BREG ? e : 0][BREG ? c : 0][u] : wfrag8(ws, e, c, u);
+#pragma unroll
+                    for (int m = 0; m < 2; m++)
+#pragma unroll
+                        for (int u = 0; u < COT; u++)
+                            acc[(jm + e) % 3][m][u] =
+                                TR ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a[m], acc[(jm + e) % 3][m][u], 0, 0, 0)
+                                   : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[u], acc[(jm + e) % 3][m][u], 0, 0, 0);
                 }
-                __syncthreads();
+            };
+            if constexpr (BREG) {
+#pragma unroll
+                for (int c = 0; c < NK; c++)
+                    chunk(c);
             } else {
-                __syncthreads();
-                if (p + 1 < PL)
-                    PM_MARCH_STORE(p % NS);  // plane i + 2 replaces plane i - 1
-                __syncthreads();
+#pragma unroll 2
+                for (int c = 0; c < NK; c++)
+                    chunk(c);
             }
+            if constexpr (TAIL != 0) {
+                const int kk = 32 * NK + 4 * q, tip = kk / CP, ch = kk % CP;
+                const int dj = tip / 3 - 1, dk = tip % 3 - 1;
+                const int ab = ((1 + wave + sgn * dj) * 66 + 1 + 16 * mh + r + sgn * dk) * SV + ch;
+                bf16x4 a[2];
+#pragma unroll
+                for (int m = 0; m < 2; m++)
+                    a[m] = *(const bf16x4 *)(sl + ab + 16 * m * SV);
+#pragma unroll
+                for (int e = 0; e < 3; e++) {
+                    bf16x4 b[COT];
+#pragma unroll
+                    for (int u = 0; u < COT; u++)
+                        b[u] = BREG ? bt[BREG ? e : 0][u] : wfrag4(ws, e, u);
+#pragma unroll
+                    for (int m = 0; m < 2; m++)
+#pragma unroll
+                        for (int u = 0; u < COT; u++)
+                            acc[(jm + e) % 3][m][u] =
+                                TR ? __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[u], a[m], acc[(jm + e) % 3][m][u], 0, 0, 0)
+                                   : __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], b[u], acc[(jm + e) % 3][m][u], 0, 0, 0);
+                }
+            }
+            // the epilogue is kept apart from the MFMAs around it (scheduling
+            // barriers): with the compiler free to interleave the two, the
+            // head instance's results varied from run to run
+            if constexpr (decltype(ST)::value) {
+                __builtin_amdgcn_sched_barrier(0);
+                store_plane(s - 1, acc[jm]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // the slot of plane s - 1 (stored, or outside the tile) becomes plane s + 2's
+#pragma unroll
+            for (int m = 0; m < 2; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    acc[jm][m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if constexpr (decltype(LD)::value)
+                put((jm + 2) % 3);
+            __syncthreads();
+        };
+        // input planes i0 - 1 and i0 (no complete output plane yet), then whole
+        // rounds of three, then i0 + PL - 1 and i0 + PL (nothing left to stage)
+        step(i0 - 1, IConst<0>(), IConst<1>(), IConst<0>());
+        step(i0, IConst<1>(), IConst<1>(), IConst<0>());
+        for (int s = i0 + 1; s < i0 + PL - 1; s += 3) {
+            step(s, IConst<2>(), IConst<1>(), IConst<1>());
+            step(s + 1, IConst<0>(), IConst<1>(), IConst<1>());
+            step(s + 2, IConst<1>(), IConst<1>(), IConst<1>());
         }
-#undef PM_MARCH_STORE
-#undef PM_MARCH_FETCH
-#undef PM_MARCH_FETCH_TO
+        step(i0 + PL - 1, IConst<2>(), IConst<0>(), IConst<1>());
+        step(i0 + PL, IConst<0>(), IConst<0>(), IConst<1>());
     }
 }
 
@@ -558,18 +614,20 @@ __global__ __launch_bounds__(kMarchThreads) void k_conv3_march(const uint16_t *_
 // p = 4 pi_i + 2 pi_j + pi_k, coarse tap e = 4 e_i + 2 e_j + e_k, offset
 // e - 1 + pi per axis.  The block stages the 3 x 6 x (KT + 2) coarse
 // neighbourhood of 4 coarse rows x KT coarse voxels (all CIN channels) in LDS
-// (KT small enough for three blocks per CU);
-// each wave takes one row and runs, per parity, the 8 taps x CIN/32 K-chunks on
-// v_mfma_f32_16x16x32_bf16.  Epilogue: out[v][ooff + o] =
+// (KT small enough for three blocks per CU).  Wave w owns the two parities
+// (pi_i, pi_j) = (w / 2, w % 2), pi_k = 0, 1, for all four rows: per parity it
+// runs the 8 taps x CIN/32 K-chunks on v_mfma_f32_16x16x32_bf16, each weight
+// fragment feeding the four rows (every block reads the same weights, so
+// fewer fragment loads per output keep them off the L2's critical path).
+// Epilogue: out[v][ooff + o] =
 // act(bias[o] + add[v][o] + sum), with add the rest of the layer (the other
 // input channels, FP32, cout per voxel) computed beforehand; out may be add
 // itself when FP32.
-template <int CIN, int COT, int KT>
+template <int CIN, int COT, int KT, bool F32OUT, bool RELU>
 __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict__ in, int nc,
                                                      const uint16_t *__restrict__ wp, int cout_pad,
-                                                     const float *__restrict__ bias, const float *add, int cout,
-                                                     void *out, int out_stride, int out_off, int out_f32, int relu,
-                                                     unsigned ntiles)
+                                                     const float *__restrict__ bias, const float *add, void *out,
+                                                     int out_stride, int out_off, unsigned ntiles)
 {
     constexpr int SV = CIN + 8;  // odd number of 16-byte units
     constexpr int WK = KT + 2, WV = 3 * 6 * WK;
@@ -593,94 +651,100 @@ __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict_
             *(const u32x4 *)(in + ((size_t)((ii * nc + jj) * nc + kk)) * CIN + 8 * part);
     }
     __syncthreads();
-    const int J = J0 + wave;
     const int nf = 2 * nc;
-    // weights as the A operand: lane (r, q) receives channels 4q .. 4q + 3
-    // (+ 16 u) of coarse voxel K0 + 16 m + r, so the addend loads and the
-    // output stores are 4-channel vectors when the views allow
-    const bool vec = cout % 4 == 0 && out_stride % 4 == 0 && out_off % 4 == 0;
-    for (int p = 0; p < 8; p++) {
-        const int pi = p >> 2, pj = (p >> 1) & 1, pk = p & 1;
-        f32x4 acc[MT][COT];
-        float addv[MT][COT][4];  // the addend of this parity's outputs, loaded ahead of the MFMAs
+    const int pi = wave >> 1, pj = wave & 1;
+    // Every output channel group is whole and every view 4-aligned (the
+    // launcher checks), so loads and stores are 4-channel vectors with no
+    // branch to split the load pipeline: both parities' addends load before
+    // the first parity is computed.
+    constexpr int NCK = CIN / 32;
+    typedef f32x4 AddRegs[4][MT][COT];
+    const int cout = cout_pad;
+    f32x4 bo[COT];
 #pragma unroll
-        for (int m = 0; m < MT; m++)
+    for (int u = 0; u < COT; u++) {
+        const int o0 = co_base + u * 16 + 4 * q;
 #pragma unroll
-            for (int u = 0; u < COT; u++) {
-                acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                const int o0 = co_base + u * 16 + 4 * q;
-                const int K = K0 + 16 * m + r;
-                const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
-                if (vec && o0 + 3 < cout) {
-                    const f32x4 x = *(const f32x4 *)(add + fv * cout + o0);
+        for (int e = 0; e < 4; e++)
+            bo[u][e] = bias ? bias[o0 + e] : 0.f;
+    }
+    // fine voxel of parity (pi, pj, pk) above coarse voxel (I, J0 + row, K0 + 16 m + r)
+    auto fine_voxel = [&](int row, int pk, int m) {
+        const int J = J0 + row, K = K0 + 16 * m + r;
+        return ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
+    };
+    auto load_add = [&](int pk, AddRegs &addv) {
 #pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        addv[m][u][e] = x[e];
-                } else {
+        for (int row = 0; row < 4; row++)
 #pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        addv[m][u][e] = o0 + e < cout ? add[fv * cout + o0 + e] : 0.f;
-                }
-            }
+            for (int m = 0; m < MT; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    addv[row][m][u] = *(const f32x4 *)(add + fine_voxel(row, pk, m) * cout + co_base + u * 16 + 4 * q);
+    };
+    auto compute = [&](int pk, const AddRegs &addv) {
+        const int p = 4 * pi + 2 * pj + pk;
+        f32x4 acc[4][MT][COT];
+#pragma unroll
+        for (int row = 0; row < 4; row++)
+#pragma unroll
+            for (int m = 0; m < MT; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    acc[row][m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int e = 0; e < 8; e++) {
             const int oi = (e >> 2) - 1 + pi, oj = ((e >> 1) & 1) - 1 + pj, ok = (e & 1) - 1 + pk;
-            const int ab = ((1 + oi) * 6 + 1 + wave + oj) * WK + 1 + r + ok;  // window voxel of m = 0
 #pragma unroll
-            for (int ch = 0; ch < CIN; ch += 32) {
+            for (int c = 0; c < NCK; c++) {
                 bf16x8 b[COT];
 #pragma unroll
                 for (int u = 0; u < COT; u++)
-                    b[u] = __builtin_bit_cast(
-                        bf16x8, *(const u32x4 *)(wp + ((size_t)(p * 8 + e) * cout_pad + co_base + u * 16 + r) * CIN +
-                                                 ch + 8 * q));
+                    b[u] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(wp + ((size_t)(p * 8 + e) * cout_pad + co_base +
+                                                                             u * 16 + r) * CIN + 32 * c + 8 * q));
+#pragma unroll
+                for (int row = 0; row < 4; row++) {
+                    const int ab = ((1 + oi) * 6 + 1 + row + oj) * WK + 1 + r + ok;  // window voxel of m = 0
+#pragma unroll
+                    for (int m = 0; m < MT; m++) {
+                        const bf16x8 a =
+                            __builtin_bit_cast(bf16x8, *(const u32x4 *)(tile + (ab + 16 * m) * SV + 32 * c + 8 * q));
+#pragma unroll
+                        for (int u = 0; u < COT; u++)
+                            acc[row][m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a, acc[row][m][u], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int row = 0; row < 4; row++)
+#pragma unroll
+            for (int u = 0; u < COT; u++) {
+                const int o0 = co_base + u * 16 + 4 * q;
 #pragma unroll
                 for (int m = 0; m < MT; m++) {
-                    const bf16x8 a =
-                        __builtin_bit_cast(bf16x8, *(const u32x4 *)(tile + (ab + 16 * m) * SV + ch + 8 * q));
+                    float v[4];
 #pragma unroll
-                    for (int u = 0; u < COT; u++)
-                        acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[u], a, acc[m][u], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < COT; u++) {
-            const int o0 = co_base + u * 16 + 4 * q;
-            float bo[4];
-#pragma unroll
-            for (int e = 0; e < 4; e++)
-                bo[e] = (bias && o0 + e < cout) ? bias[o0 + e] : 0.f;
-#pragma unroll
-            for (int m = 0; m < MT; m++) {
-                const int K = K0 + 16 * m + r;
-                const size_t fv = ((size_t)(2 * I + pi) * nf + 2 * J + pj) * nf + 2 * K + pk;
-                float v[4];
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    v[e] = acc[m][u][e] + bo[e] + addv[m][u][e];
-                    if (relu)
-                        v[e] = fmaxf(v[e], 0.f);
-                }
-                // out may alias add: same elements, same thread
-                const size_t oi_ = fv * out_stride + out_off + o0;
-                if (vec && o0 + 3 < cout) {
-                    if (out_f32)
+                    for (int e = 0; e < 4; e++) {
+                        v[e] = acc[row][m][u][e] + bo[u][e] + addv[row][m][u][e];
+                        if (RELU)
+                            v[e] = fmaxf(v[e], 0.f);
+                    }
+                    // out may alias add: same elements, same thread
+                    const size_t oi_ = fine_voxel(row, pk, m) * out_stride + out_off + o0;
+                    if constexpr (F32OUT)
                         *(f32x4 *)((float *)out + oi_) = (f32x4){v[0], v[1], v[2], v[3]};
                     else
-                        *(u16x4 *)((uint16_t *)out + oi_) = (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; e++)
-                        if (o0 + e < cout) {
-                            if (out_f32)
-                                ((float *)out)[oi_ + e] = v[e];
-                            else
-                                ((uint16_t *)out)[oi_ + e] = f2bf(v[e]);
-                        }
+                        *(u16x4 *)((uint16_t *)out + oi_) =
+                            (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
                 }
             }
-        }
+    };
+#pragma unroll 1
+    for (int pk = 0; pk < 2; pk++) {
+        AddRegs addv;
+        load_add(pk, addv);
+        compute(pk, addv);
     }
 }
 
@@ -740,32 +804,40 @@ bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp,
                         const float *add, int cout, void *out, int out_stride, int out_off, bool out_f32, bool relu,
                         hipStream_t st)
 {
-    if (nc % 64)
+    // the two forms in use: BF16 activation with ReLU (inference) and FP32
+    // without (the layer on its own); whole channel groups, 4-aligned views
+    if (nc % 64 || cout != cout_pad || out_stride % 4 || out_off % 4 || out_f32 == relu)
         return false;
+#define PM_UPCONV(CI, C, KTV, F, RL, NT)                                                                                \
+    hipLaunchKernelGGL((k_upconv_poly<CI, C, KTV, F, RL>), dim3(xcd_blocks(NT), 1), dim3(256), 0, st, in, nc, wp,     \
+                       cout_pad, bias, add, out, out_stride, out_off, NT)
     if (cup == 32 && cout_pad == 16) {
         const unsigned ntiles = (unsigned)nc * (nc / 4) * (nc / 32);
-        hipLaunchKernelGGL((k_upconv_poly<32, 1, 32>), dim3(xcd_blocks(ntiles), 1), dim3(256), 0, st, in, nc, wp,
-                           cout_pad, bias, add, cout, out, out_stride, out_off, out_f32 ? 1 : 0, relu ? 1 : 0,
-                           ntiles);
+        if (out_f32)
+            PM_UPCONV(32, 1, 32, true, false, ntiles);
+        else
+            PM_UPCONV(32, 1, 32, false, true, ntiles);
         return true;
     }
     if (cup == 64 && cout_pad == 32) {
         const unsigned ntiles = (unsigned)nc * (nc / 4) * (nc / 16);
-        hipLaunchKernelGGL((k_upconv_poly<64, 2, 16>), dim3(xcd_blocks(ntiles), 1), dim3(256), 0, st, in, nc, wp,
-                           cout_pad, bias, add, cout, out, out_stride, out_off, out_f32 ? 1 : 0, relu ? 1 : 0,
-                           ntiles);
+        if (out_f32)
+            PM_UPCONV(64, 2, 16, true, false, ntiles);
+        else
+            PM_UPCONV(64, 2, 16, false, true, ntiles);
         return true;
     }
+#undef PM_UPCONV
     return false;
 }
 
-// Planes per tile of the plane-marching convolution: long tiles where two
-// planes are in flight (fewer ring fills per voxel), else 16 / 8.
-static inline int march_planes(int n, bool ahead)
+// Planes per tile of the plane-marching convolution (2 mod 3): long tiles
+// where the grid still has a tile per block slot, else 32 / 8.
+static inline int march_planes(int n)
 {
-    if (ahead)
-        return n >= 256 ? 64 : (n >= 128 ? 16 : 8);
-    return n >= 256 ? 16 : 8;
+    if (n >= 256 && n % 128 == 0)
+        return 128;
+    return n >= 128 ? 32 : 8;
 }
 
 // 16 -> 16 convolution with ReLU followed by the 1x1x1 head (yhat, FP32,
@@ -775,12 +847,12 @@ bool launch_conv3_head(const uint16_t *in, int in_stride, int in_off, const uint
 {
     if (n % 64 || in_stride % 8 || in_off % 8)
         return false;
-    const int PL = march_planes(n, true);
+    const int PL = march_planes(n);
     const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
     unsigned nb = ntiles < 2048u ? ntiles : 2048u;
     if (nb >= 8)
         nb -= nb % 8;
-    hipLaunchKernelGGL((k_conv3_march<1, 1, 4, true, true>), dim3(nb, 1), dim3(kMarchThreads), 0, st, in, in_stride,
+    hipLaunchKernelGGL((k_conv3_march<1, 1, true>), dim3(nb, 1), dim3(kMarchThreads), 0, st, in, in_stride,
                        in_off, wp, 16, bias, 16, (void *)yhat, 1, 0, 1, n, 0, 1, ntiles, PL, hw, hb);
     return true;
 }
@@ -790,32 +862,22 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
                   bool relu, hipStream_t st)
 {
     if (n % 64 == 0 && cin_pad <= 48 && in_stride % 8 == 0 && in_off % 8 == 0) {
-        const int cot = (cin_pad == 16 && (cout_pad / 16) % 2 == 0) ? 2 : 1;
-        const int PL = march_planes(n, cin_pad == 16);
+        const int PL = march_planes(n);
         const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
         unsigned nb = ntiles < 2048u ? ntiles : 2048u;
         if (nb >= 8)
             nb -= nb % 8;
-        dim3 grid(nb, cout_pad / (cot * 16));
-#define PM_CONVM(CSV, C, NSV)                                                                                          \
-    hipLaunchKernelGGL((k_conv3_march<CSV, C, NSV, false, CSV == 1>), grid, dim3(kMarchThreads), 0, st, in, in_stride, \
-                       in_off, wp, cout_pad,                                                                           \
+        dim3 grid(nb, cout_pad / 16);
+#define PM_CONVM(CSV, C)                                                                                              \
+    hipLaunchKernelGGL((k_conv3_march<CSV, C>), grid, dim3(kMarchThreads), 0, st, in, in_stride, in_off, wp, cout_pad, \
                        bias, cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles,   \
                        PL, nullptr, nullptr)
-#define PM_CONVM_C(CSV, NSV)                                                                                           \
-    do {                                                                                                               \
-        if (cot == 2)                                                                                                  \
-            PM_CONVM(CSV, 2, NSV);                                                                                     \
-        else                                                                                                           \
-            PM_CONVM(CSV, 1, NSV);                                                                                     \
-    } while (0)
         if (cin_pad == 16)
-            PM_CONVM_C(1, 4);
+            PM_CONVM(1, 1);
         else if (cin_pad == 32)
-            PM_CONVM(2, 1, 4);
+            PM_CONVM(2, 1);
         else
-            PM_CONVM(3, 1, 3);
-#undef PM_CONVM_C
+            PM_CONVM(3, 1);
 #undef PM_CONVM
         return;
     }

@@ -57,8 +57,12 @@ def _conv(P, mode, n, cin, cout, x=None, dy=None, w=None, b=None):
     return out.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (32, 96, 32), (16, 32, 64), (16, 16, 48), (16, 32, 96), (64, 16, 16), (64, 48, 16), (64, 32, 64)])
+@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (32, 96, 32), (16, 32, 64), (16, 16, 48), (16, 32, 96), (64, 16, 16), (64, 48, 16), (64, 32, 64), (64, 16, 32), (64, 64, 64), (64, 96, 32), (128, 16, 16)])
 def test_conv_forward_matches_reference(P, n, cin, cout):
+    """Every forward kernel form: the one-plane and LDS-staged ones (n not a
+    multiple of 64, or more than 48 input channels), and the plane march
+    with 16, 32 and 48 input channels, one and several output tiles, and
+    8- and 32-plane tiles (64^3, 128^3)."""
     rng = np.random.default_rng(cin + cout)
     x = rng.standard_normal((n, n, n, cin))
     w = rng.standard_normal((27, cin, cout)) * 0.1
@@ -68,7 +72,7 @@ def test_conv_forward_matches_reference(P, n, cin, cout):
     assert rel(got, ref) < 1e-5
 
 
-@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (16, 32, 64), (16, 4, 16), (32, 96, 32), (64, 16, 16)])
+@pytest.mark.parametrize("n,cin,cout", [(16, 16, 16), (16, 48, 16), (16, 32, 64), (16, 4, 16), (32, 96, 32), (64, 16, 16), (64, 32, 16), (64, 16, 32)])
 def test_conv_input_and_weight_gradients(P, n, cin, cout):
     rng = np.random.default_rng(7 * cin + cout)
     x = rng.standard_normal((n, n, n, cin))
