@@ -48,6 +48,9 @@ void launch_pack_conv_sub(const float *w, int cin, int cout, int c0, int csub, i
 bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp, int cout_pad, const float *bias,
                         const float *add, int cout, void *out, int out_stride, int out_off, bool out_f32, bool relu,
                         hipStream_t st);
+bool launch_updec16(const uint16_t *skip, int skip_stride, int skip_off, const uint16_t *coarse, const uint16_t *wsub,
+                    const uint16_t *wpoly, const float *bias, void *out, int out_stride, int out_off, bool out_f32,
+                    bool relu, int n, hipStream_t st);
 void launch_unet_feature(const double *delta_packed, int n, const double *stats, uint16_t *f, hipStream_t st);
 bool launch_conv3_in1(const uint16_t *f, const float *w, const float *b, float x1, float x2, float x3, void *out,
                       int out_stride, int out_off, bool out_f32, int n, hipStream_t st);
@@ -200,12 +203,18 @@ View whole(int t) { return View{t, kTChan[t], 0}; }
 // Inference form of decoder layer kFused[f] (skip channels in view `skip`,
 // coarse tensor tc, output to): the skip channels' convolution into an FP32
 // scratch (the input and first activation tensors, dead by then), then the
-// polyphase convolution of tc adds it, the bias and the ReLU.
+// polyphase convolution of tc adds it, the bias and the ReLU; the layer on
+// the 16-channel level runs both in one kernel (the same values).
 // Needs N.dim(tc) % 64 == 0 (the polyphase instances).
 void fused_up_conv(Net &N, const float *params, int f, View skip, int tc, int to)
 {
     const ParamLayout L = param_layout();
     const int l = kFused[f], cin = kConv[l].cin, cout = kConv[l].cout, up = kFusedUp[f];
+    if (cin - up == 16 && up == 32 && cout == 16 &&
+        launch_updec16(N.act(skip.t), skip.stride, skip.off, N.act(tc), (const uint16_t *)(N.ws + N.P.wsub[f]),
+                       (const uint16_t *)(N.ws + N.P.wpoly[f]), params + L.b[l], N.act(to), kTChan[to], 0, false,
+                       true, N.dim(to), N.st))
+        return;
     float *scratch = (float *)N.act(X0);
     launch_conv3(N.act(skip.t), skip.stride, skip.off, pad16(cin - up), (const uint16_t *)(N.ws + N.P.wsub[f]),
                  pad16(cout), nullptr, cout, scratch, cout, 0, true, N.dim(to), false, false, N.st);
@@ -627,6 +636,13 @@ int ws_conv3(int mode, int n, int cin, int cout, const void *x_bf16, const void 
         uint16_t *wpoly = (uint16_t *)ws, *wsub = (uint16_t *)((char *)ws + pbytes);
         launch_pack_poly(w, cin, cout, up, pad16(cout), wpoly, st);
         launch_pack_conv_sub(w, cin, cout, up, sub, sub, pad16(cout), wsub, st);
+        if (up == 32 && sub == 16 && cout == 16) {
+            // the 16-channel level's layer: one fused kernel
+            if (!launch_updec16((const uint16_t *)dy_bf16, sub, 0, (const uint16_t *)x_bf16, wsub, wpoly, b, out,
+                                cout, 0, true, false, n, st))
+                return PM_EINVAL;
+            return launched();
+        }
         launch_conv3((const uint16_t *)dy_bf16, sub, 0, sub, wsub, pad16(cout), nullptr, cout, out, cout, 0, true, n,
                      false, false, st);
         if (!launch_upconv_poly((const uint16_t *)x_bf16, up, n / 2, wpoly, pad16(cout), b, out, cout, out, cout, 0,

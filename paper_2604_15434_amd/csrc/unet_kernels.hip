@@ -327,6 +327,15 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMarchThreads = 512;
 
+// Planes per tile of the plane-marching convolution (2 mod 3): long tiles
+// where the grid still has a tile per block slot, else 32 / 8.
+static inline int march_planes(int n)
+{
+    if (n >= 256 && n % 128 == 0)
+        return 128;
+    return n >= 128 ? 32 : 8;
+}
+
 template <int V>
 struct IConst {
     static constexpr int value = V;
@@ -748,6 +757,273 @@ __global__ __launch_bounds__(256) void k_upconv_poly(const uint16_t *__restrict_
     }
 }
 
+// The decoder layer on the upsampled 16-channel level in one kernel
+// (inference): 16 skip channels at the fine grid n plus 32 coarse channels
+// at n/2 seen through nearest-neighbour upsampling, 16 outputs.  It marches
+// the fine input planes like k_conv3_march (three-slot ring, three rolling
+// accumulators of the skip channels' 27 taps), and when fine output plane o
+// is complete adds the polyphase sum of the coarse tensor (parity p = 4 pi_i
+// + 2 pi_j + pi_k, 8 coarse taps, k_upconv_poly's weights Wp[p][e][o][c]),
+// the bias and the ReLU.  Wave w owns fine row j0 + w / 2 (pi_j = w / 2 mod
+// 2) and the parity pi_k = w mod 2 of the block's 64 voxels (two tiles of 16
+// voxels at stride 2), so its polyphase weights (two parities, pi_i = 0, 1)
+// stay in registers beside the skip weights.  The fine planes sit in LDS
+// de-interleaved by k parity (even voxels, then odd), so the stride-2 tiles
+// read consecutive voxel slots; the coarse planes (4 rows x 34 voxels) sit
+// in a ring of three slots, one staged every second step.  Each output is
+// bias + skip sum + polyphase sum in the order of the two-kernel form
+// (k_conv3_march into an FP32 scratch, then k_upconv_poly), and the same
+// value.  PL even and 2 mod 3, so the main loop runs in rounds of six steps.
+template <bool F32OUT, bool RELU>
+__global__ __launch_bounds__(kMarchThreads) void k_updec_march(const uint16_t *__restrict__ skip, int skip_stride,
+                                                               int skip_off, const uint16_t *__restrict__ coarse,
+                                                               const uint16_t *__restrict__ wsub,
+                                                               const uint16_t *__restrict__ wpoly,
+                                                               const float *__restrict__ bias, void *__restrict__ out,
+                                                               int out_stride, int out_off, int n, unsigned ntiles,
+                                                               int PL)
+{
+    constexpr int SV = 24;                       // fine voxel stride (halfwords): 16 channels + pad
+    constexpr int WV = 6 * 66;                   // fine voxel slots per plane
+    constexpr int NCH = WV * 2, PER = (NCH + kMarchThreads - 1) / kMarchThreads;
+    constexpr int SVC = 40;                      // coarse voxel stride: 32 channels + pad
+    constexpr int WVC = 4 * 34;                  // coarse voxel slots per plane
+    constexpr int NCHC = WVC * 4, PERC = (NCHC + kMarchThreads - 1) / kMarchThreads;
+    __shared__ __align__(16) uint16_t ring[3 * WV * SV];
+    __shared__ __align__(16) uint16_t cring[3 * WVC * SVC];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = w >> 1, pk = w & 1, pj = row & 1;
+    const int r = lane & 15, q = lane >> 4;
+    const int nc = n / 2;
+    const int nkt = n / 64, nit = n / PL;
+    const size_t plane_elems = (size_t)n * n * skip_stride;
+    const size_t cplane_elems = (size_t)nc * nc * 32;
+    const unsigned nb = gridDim.x;
+    const unsigned lb = (nb % 8) ? blockIdx.x : (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    // skip weights [27][16][16]: chunk c of input plane offset e (tap di = 1 - e)
+    bf16x8 bw[3][4];
+    bf16x4 bt[3];
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const int kk = 32 * c + 8 * q, tap = (2 - e) * 9 + kk / 16, ch = kk % 16;
+            bw[e][c] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(wsub + (tap * 16 + r) * 16 + ch));
+        }
+        const int tap = (2 - e) * 9 + 8;
+        bt[e] = *(const bf16x4 *)(wsub + (tap * 16 + r) * 16 + 4 * q);
+    }
+    // polyphase weights of this wave's parities (pi_i = 0, 1)
+    bf16x8 pw[2][8];
+#pragma unroll
+    for (int pi = 0; pi < 2; pi++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            const int p = 4 * pi + 2 * pj + pk;
+            pw[pi][e] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(wpoly + ((p * 8 + e) * 16 + r) * 32 + 8 * q));
+        }
+    f32x4 bo;
+#pragma unroll
+    for (int e = 0; e < 4; e++)
+        bo[e] = bias ? bias[4 * q + e] : 0.f;
+    for (unsigned t = lb; t < ntiles; t += nb) {
+        const int ib = (int)(t % nit), kt = (int)((t / nit) % nkt), jt = (int)(t / ((unsigned)nit * nkt));
+        const int i0 = ib * PL, j0 = jt * 4, k0 = kt * 64;
+        unsigned soff[PER], csoff[PERC];
+        int loff[PER], cloff[PERC];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int c = threadIdx.x + u * kMarchThreads;
+            const int cc = c < NCH ? c : 0;
+            const int v = cc / 2, part = cc % 2;
+            const int rw = v / 66, col = v % 66;
+            const int jj = wrapi(j0 + rw - 1, n), kk = wrapi(k0 + col - 1, n);
+            soff[u] = (unsigned)((jj * n + kk) * skip_stride + skip_off + 8 * part);
+            loff[u] = (rw * 66 + (col & 1) * 33 + (col >> 1)) * SV + 8 * part;
+        }
+#pragma unroll
+        for (int u = 0; u < PERC; u++) {
+            const int c = threadIdx.x + u * kMarchThreads;
+            const int cc = c < NCHC ? c : 0;
+            const int v = cc / 4, part = cc % 4;
+            const int rw = v / 34, col = v % 34;
+            const int jj = wrapi(j0 / 2 + rw - 1, nc), kk = wrapi(k0 / 2 + col - 1, nc);
+            csoff[u] = (unsigned)((jj * nc + kk) * 32 + 8 * part);
+            cloff[u] = v * SVC + 8 * part;
+        }
+        u32x4 pre[PER], prec[PERC];
+        auto fetch = [&](int ii) {
+            const uint16_t *base = skip + (size_t)wrapi(ii, n) * plane_elems;
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kMarchThreads < NCH)
+                    pre[u] = *(const u32x4 *)(base + soff[u]);
+        };
+        auto put = [&](int slot) {
+            uint16_t *dst = ring + slot * WV * SV;
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kMarchThreads < NCH)
+                    *(u32x4 *)(dst + loff[u]) = pre[u];
+        };
+        // coarse plane cp lives in slot (cp - (i0 / 2 - 1)) mod 3
+        auto cslot = [&](int cp) { return (cp - i0 / 2 + 1) % 3; };
+        auto cfetch = [&](int cp) {
+            const uint16_t *base = coarse + (size_t)wrapi(cp, nc) * cplane_elems;
+#pragma unroll
+            for (int u = 0; u < PERC; u++)
+                if (threadIdx.x + u * kMarchThreads < NCHC)
+                    prec[u] = *(const u32x4 *)(base + csoff[u]);
+        };
+        auto cput = [&](int cp) {
+            uint16_t *dst = cring + cslot(cp) * WVC * SVC;
+#pragma unroll
+            for (int u = 0; u < PERC; u++)
+                if (threadIdx.x + u * kMarchThreads < NCHC)
+                    *(u32x4 *)(dst + cloff[u]) = prec[u];
+        };
+        fetch(i0 - 1);
+        put(0);
+        fetch(i0);
+        put(1);
+        cfetch(i0 / 2 - 1);
+        cput(i0 / 2 - 1);
+        cfetch(i0 / 2);
+        cput(i0 / 2);
+        __syncthreads();
+        f32x4 acc[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int m = 0; m < 2; m++)
+                acc[a][m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        // fine output plane o (parity PI along i): polyphase sum, bias, skip sum, ReLU, store
+        auto finish = [&](int o, auto PI, const f32x4 (&ac)[2]) {
+            constexpr int pi = decltype(PI)::value;
+            const int I = o >> 1;
+            f32x4 ap[2] = {(f32x4){0.f, 0.f, 0.f, 0.f}, (f32x4){0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int oi = (e >> 2) - 1 + pi, oj = ((e >> 1) & 1) - 1 + pj, ok = (e & 1) - 1 + pk;
+                const uint16_t *cs = cring + cslot(I + oi) * WVC * SVC;
+                const int cb = (((row >> 1) + oj + 1) * 34 + r + ok + 1) * SVC + 8 * q;
+#pragma unroll
+                for (int m = 0; m < 2; m++) {
+                    const bf16x8 b = __builtin_bit_cast(bf16x8, *(const u32x4 *)(cs + cb + 16 * m * SVC));
+                    ap[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(pw[pi][e], b, ap[m], 0, 0, 0);
+                }
+            }
+            const int j = j0 + row;
+#pragma unroll
+            for (int m = 0; m < 2; m++) {
+                const size_t vf = ((size_t)o * n + j) * n + k0 + 2 * (16 * m + r) + pk;
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    v[e] = ap[m][e] + bo[e] + ac[m][e];
+                    if (RELU)
+                        v[e] = fmaxf(v[e], 0.f);
+                }
+                const size_t oi_ = vf * out_stride + out_off + 4 * q;
+                if constexpr (F32OUT)
+                    *(f32x4 *)((float *)out + oi_) = (f32x4){v[0], v[1], v[2], v[3]};
+                else
+                    *(u16x4 *)((uint16_t *)out + oi_) = (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+            }
+        };
+        // input plane s in ring slot JM (also the accumulator slot of output
+        // plane s - 1); LD: fine plane s + 2 still to stage; ST: output plane
+        // s - 1 in the tile, of parity PI; CLD: coarse plane s / 2 + 1 to stage
+        auto step = [&](int s, auto JM, auto LD, auto ST, auto PI, auto CLD) {
+            constexpr int jm = decltype(JM)::value;
+            if constexpr (decltype(LD)::value)
+                fetch(s + 2);
+            if constexpr (decltype(CLD)::value)
+                cfetch(s / 2 + 1);
+            const uint16_t *sl = ring + jm * WV * SV;
+#pragma unroll
+            for (int c = 0; c < 5; c++) {
+                // K chunk c (c = 4: the last tap alone, 16 wide)
+                const int kk = c < 4 ? 32 * c + 8 * q : 128 + 4 * q, tip = kk / 16, ch = kk % 16;
+                const int dj = tip / 3 - 1, dk = tip % 3 - 1;
+                const int kl = pk + 1 + dk;  // fine k offset (window slot) of lane r's voxel, less 2 (16 m + r)
+                const int ab = ((1 + row + dj) * 66 + (kl & 1) * 33 + r + (kl >> 1)) * SV + ch;
+#pragma unroll
+                for (int m = 0; m < 2; m++) {
+                    if (c < 4) {
+                        const bf16x8 a = __builtin_bit_cast(bf16x8, *(const u32x4 *)(sl + ab + 16 * m * SV));
+#pragma unroll
+                        for (int e = 0; e < 3; e++)
+                            acc[(jm + e) % 3][m] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(bw[e][c < 4 ? c : 0], a, acc[(jm + e) % 3][m], 0, 0, 0);
+                    } else {
+                        const bf16x4 a = *(const bf16x4 *)(sl + ab + 16 * m * SV);
+#pragma unroll
+                        for (int e = 0; e < 3; e++)
+                            acc[(jm + e) % 3][m] =
+                                __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bt[e], a, acc[(jm + e) % 3][m], 0, 0, 0);
+                    }
+                }
+            }
+            if constexpr (decltype(ST)::value) {
+                // kept apart from the MFMAs around it, as in k_conv3_march
+                __builtin_amdgcn_sched_barrier(0);
+                finish(s - 1, PI, acc[jm]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int m = 0; m < 2; m++)
+                acc[jm][m] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if constexpr (decltype(LD)::value)
+                put((jm + 2) % 3);
+            if constexpr (decltype(CLD)::value)
+                cput(s / 2 + 1);
+            __syncthreads();
+        };
+        using I0 = IConst<0>;
+        using I1 = IConst<1>;
+        using I2 = IConst<2>;
+        step(i0 - 1, I0(), I1(), I0(), I0(), I0());
+        step(i0, I1(), I1(), I0(), I0(), I1());
+        for (int s = i0 + 1; s < i0 + PL - 1; s += 6) {
+            step(s, I2(), I1(), I1(), I0(), I0());
+            step(s + 1, I0(), I1(), I1(), I1(), I1());
+            step(s + 2, I1(), I1(), I1(), I0(), I0());
+            step(s + 3, I2(), I1(), I1(), I1(), I1());
+            step(s + 4, I0(), I1(), I1(), I0(), I0());
+            step(s + 5, I1(), I1(), I1(), I1(), I1());
+        }
+        step(i0 + PL - 1, I2(), I0(), I1(), I0(), I0());
+        step(i0 + PL, I0(), I0(), I1(), I1(), I0());
+    }
+}
+
+// The fused decoder layer above: skip (n^3 x 16, view), coarse ((n/2)^3 x 32,
+// compact), wsub [27][16][16] and wpoly [64][16][32] as packed by
+// k_pack_conv_sub and k_pack_poly.  Returns false (nothing launched) for
+// grids or views it does not handle.
+bool launch_updec16(const uint16_t *skip, int skip_stride, int skip_off, const uint16_t *coarse, const uint16_t *wsub,
+                    const uint16_t *wpoly, const float *bias, void *out, int out_stride, int out_off, bool out_f32,
+                    bool relu, int n, hipStream_t st)
+{
+    if (n % 64 || skip_stride % 8 || skip_off % 8 || out_stride % 4 || out_off % 4 || out_f32 == relu)
+        return false;
+    const int PL = march_planes(n);
+    const unsigned ntiles = (unsigned)(n / 4) * (n / 64) * (n / PL);
+    unsigned nb = ntiles < 2048u ? ntiles : 2048u;
+    if (nb >= 8)
+        nb -= nb % 8;
+#define PM_UPDEC(F, RL)                                                                                               \
+    hipLaunchKernelGGL((k_updec_march<F, RL>), dim3(nb), dim3(kMarchThreads), 0, st, skip, skip_stride, skip_off,    \
+                       coarse, wsub, wpoly, bias, out, out_stride, out_off, n, ntiles, PL)
+    if (out_f32)
+        PM_UPDEC(true, false);
+    else
+        PM_UPDEC(false, true);
+#undef PM_UPDEC
+    return true;
+}
+
 // Polyphase weights of k_upconv_poly from layer weights w[27][cin][cout]
 // (FP32) restricted to input channels [0, cup): Wp[p][e][o][c] = sum of
 // w[t][c][o] over the taps t whose coarse offset for parity p is e, in tap
@@ -831,14 +1107,6 @@ bool launch_upconv_poly(const uint16_t *in, int cup, int nc, const uint16_t *wp,
     return false;
 }
 
-// Planes per tile of the plane-marching convolution (2 mod 3): long tiles
-// where the grid still has a tile per block slot, else 32 / 8.
-static inline int march_planes(int n)
-{
-    if (n >= 256 && n % 128 == 0)
-        return 128;
-    return n >= 128 ? 32 : 8;
-}
 
 // 16 -> 16 convolution with ReLU followed by the 1x1x1 head (yhat, FP32,
 // natural order); false when the grid has no plane-marching instance.
