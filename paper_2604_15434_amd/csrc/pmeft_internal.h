@@ -118,6 +118,24 @@ struct LevelView {
 // writes its partial sums (8 slots per block); a one-block finalize kernel
 // launched right after adds them in block order (deterministic, and no
 // device-scope fence inside the reducing kernel).
+// Weight packing jobs of the learned warm start's network, run in one launch:
+// kind 0 convolution (a = cin_pad, b = cout_pad, d0 forward and d1 input-
+// gradient layout or null), 1 polyphase (a = coarse channels, b = cout_pad),
+// 2 a channel range (a = first channel, b = count, c = padded count, d =
+// cout_pad).
+struct PackJob {
+    int kind;
+    const float *w;
+    int cin, cout, a, b, c, d;
+    uint16_t *d0, *d1;
+};
+constexpr int kMaxPackJobs = 16;
+struct PackJobs {
+    PackJob job[kMaxPackJobs];
+    int n;
+};
+void launch_pack_jobs(const PackJobs &jobs, hipStream_t st);
+
 struct ReduceSlot {
     double *partials;   // kMaxBlocks * 8
     unsigned *counter;  // unused (kept zero)

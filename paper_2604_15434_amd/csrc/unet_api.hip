@@ -179,19 +179,24 @@ struct Net {
 
 int launched() { return hipGetLastError() == hipSuccess ? PM_OK : PM_EHIP; }
 
+// every weight layout the network's kernels read, in one launch
 void pack_all(Net &N, const float *params)
 {
     const ParamLayout L = param_layout();
+    PackJobs J{};
     for (int l = 0; l < 10; l++)
-        launch_pack_conv(params + L.w[l], kConv[l].cin, kConv[l].cout, pad16(kConv[l].cin), pad16(kConv[l].cout),
-                         (uint16_t *)(N.ws + N.P.wf[l]), N.P.wd[l] ? (uint16_t *)(N.ws + N.P.wd[l]) : nullptr, N.st);
+        J.job[J.n++] = PackJob{0, params + L.w[l], kConv[l].cin, kConv[l].cout, pad16(kConv[l].cin),
+                               pad16(kConv[l].cout), 0, 0, (uint16_t *)(N.ws + N.P.wf[l]),
+                               N.P.wd[l] ? (uint16_t *)(N.ws + N.P.wd[l]) : nullptr};
     if (!N.P.training)
         for (int f = 0; f < 2; f++) {
             const int l = kFused[f], cin = kConv[l].cin, cout = kConv[l].cout, up = kFusedUp[f];
-            launch_pack_poly(params + L.w[l], cin, cout, up, pad16(cout), (uint16_t *)(N.ws + N.P.wpoly[f]), N.st);
-            launch_pack_conv_sub(params + L.w[l], cin, cout, up, cin - up, pad16(cin - up), pad16(cout),
-                                 (uint16_t *)(N.ws + N.P.wsub[f]), N.st);
+            J.job[J.n++] = PackJob{1, params + L.w[l], cin, cout, up, pad16(cout), 0, 0,
+                                   (uint16_t *)(N.ws + N.P.wpoly[f]), nullptr};
+            J.job[J.n++] = PackJob{2, params + L.w[l], cin, cout, up, cin - up, pad16(cin - up), pad16(cout),
+                                   (uint16_t *)(N.ws + N.P.wsub[f]), nullptr};
         }
+    launch_pack_jobs(J, N.st);
 }
 
 // A slice of an activation tensor: tensor t, voxel stride, channel offset.

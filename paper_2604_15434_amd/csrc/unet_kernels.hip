@@ -1028,11 +1028,11 @@ bool launch_updec16(const uint16_t *skip, int skip_stride, int skip_off, const u
 // (FP32) restricted to input channels [0, cup): Wp[p][e][o][c] = sum of
 // w[t][c][o] over the taps t whose coarse offset for parity p is e, in tap
 // order, rounded once to BF16.
-__global__ __launch_bounds__(256) void k_pack_poly(const float *__restrict__ w, int cin, int cout, int cup,
-                                                   int cout_pad, uint16_t *__restrict__ wp)
+__device__ __forceinline__ void pack_poly(const float *__restrict__ w, int cin, int cout, int cup, int cout_pad,
+                                          uint16_t *__restrict__ wp, int x0, int dx)
 {
     const int total = 64 * cout_pad * cup;
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < total; x += gridDim.x * 256) {
+    for (int x = x0; x < total; x += dx) {
         const int c = x % cup, o = (x / cup) % cout_pad, pe = x / (cup * cout_pad);
         const int p = pe >> 3, e = pe & 7;
         float s = 0.f;
@@ -1050,18 +1050,28 @@ __global__ __launch_bounds__(256) void k_pack_poly(const float *__restrict__ w, 
         wp[x] = f2bf(s);
     }
 }
+__global__ __launch_bounds__(256) void k_pack_poly(const float *__restrict__ w, int cin, int cout, int cup,
+                                                   int cout_pad, uint16_t *__restrict__ wp)
+{
+    pack_poly(w, cin, cout, cup, cout_pad, wp, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
+}
 
 // Conv weights of input channels [c0, c0 + csub) of a layer, packed like
 // k_pack_conv's forward layout ([27][cout_pad][csub_pad]).
-__global__ __launch_bounds__(256) void k_pack_conv_sub(const float *__restrict__ w, int cin, int cout, int c0,
-                                                       int csub, int csub_pad, int cout_pad, uint16_t *__restrict__ wf)
+__device__ __forceinline__ void pack_conv_sub(const float *__restrict__ w, int cin, int cout, int c0, int csub,
+                                              int csub_pad, int cout_pad, uint16_t *__restrict__ wf, int x0, int dx)
 {
     const int total = 27 * cout_pad * csub_pad;
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < total; x += gridDim.x * 256) {
+    for (int x = x0; x < total; x += dx) {
         const int c = x % csub_pad, o = (x / csub_pad) % cout_pad, t = x / (csub_pad * cout_pad);
         const float v = (c < csub && o < cout) ? w[((size_t)t * cin + c0 + c) * cout + o] : 0.f;
         wf[x] = f2bf(v);
     }
+}
+__global__ __launch_bounds__(256) void k_pack_conv_sub(const float *__restrict__ w, int cin, int cout, int c0,
+                                                       int csub, int csub_pad, int cout_pad, uint16_t *__restrict__ wf)
+{
+    pack_conv_sub(w, cin, cout, c0, csub, csub_pad, cout_pad, wf, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
 }
 
 void launch_pack_poly(const float *w, int cin, int cout, int cup, int cout_pad, uint16_t *wp, hipStream_t st)
@@ -1929,11 +1939,11 @@ void launch_head_loss_bwd(const float *yhat, const float *y, const uint16_t *b5,
 // ---------------------------------------------------------------- parameters
 // Pack fp32 W[27][cin][cout] into bf16 Wf[27][cout_pad][cin_pad] (forward)
 // and Wd[27][cin_pad][cout_pad] (input gradient: output channels = cin).
-__global__ __launch_bounds__(256) void k_pack_conv(const float *__restrict__ w, int cin, int cout, int cin_pad,
-                                                   int cout_pad, uint16_t *__restrict__ wf, uint16_t *__restrict__ wd)
+__device__ __forceinline__ void pack_conv(const float *__restrict__ w, int cin, int cout, int cin_pad, int cout_pad,
+                                          uint16_t *__restrict__ wf, uint16_t *__restrict__ wd, size_t x0, size_t dx)
 {
     const size_t total = (size_t)27 * cin_pad * cout_pad;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
+    for (size_t e = x0; e < total; e += dx) {
         const int t = (int)(e / ((size_t)cin_pad * cout_pad));
         const int rem = (int)(e - (size_t)t * cin_pad * cout_pad);
         const int c = rem / cout_pad, o = rem % cout_pad;
@@ -1943,6 +1953,31 @@ __global__ __launch_bounds__(256) void k_pack_conv(const float *__restrict__ w, 
         if (wd)
             wd[((size_t)t * cin_pad + c) * cout_pad + o] = b;
     }
+}
+__global__ __launch_bounds__(256) void k_pack_conv(const float *__restrict__ w, int cin, int cout, int cin_pad,
+                                                   int cout_pad, uint16_t *__restrict__ wf, uint16_t *__restrict__ wd)
+{
+    pack_conv(w, cin, cout, cin_pad, cout_pad, wf, wd, (size_t)blockIdx.x * 256 + threadIdx.x, (size_t)gridDim.x * 256);
+}
+
+// All of a network's weight packings in one launch: grid row y runs job y
+// (the element loops of the packing kernels).
+__global__ __launch_bounds__(256) void k_pack_jobs(PackJobs jobs)
+{
+    const PackJob &J = jobs.job[blockIdx.y];
+    const int x0 = blockIdx.x * 256 + threadIdx.x, dx = gridDim.x * 256;
+    if (J.kind == 0)
+        pack_conv(J.w, J.cin, J.cout, J.a, J.b, J.d0, J.d1, (size_t)x0, (size_t)dx);
+    else if (J.kind == 1)
+        pack_poly(J.w, J.cin, J.cout, J.a, J.b, J.d0, x0, dx);
+    else
+        pack_conv_sub(J.w, J.cin, J.cout, J.a, J.b, J.c, J.d, J.d0, x0, dx);
+}
+
+void launch_pack_jobs(const PackJobs &jobs, hipStream_t st)
+{
+    if (jobs.n > 0)
+        hipLaunchKernelGGL(k_pack_jobs, dim3(64, jobs.n), dim3(256), 0, st, jobs);
 }
 
 void launch_pack_conv(const float *w, int cin, int cout, int cin_pad, int cout_pad, uint16_t *wf, uint16_t *wd,
