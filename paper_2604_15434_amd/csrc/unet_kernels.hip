@@ -28,6 +28,9 @@ namespace pmeft {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -148,40 +151,45 @@ __global__ __launch_bounds__(256) void k_conv3(const uint16_t *__restrict__ in, 
 }
 
 // LDS-staged variant for grids with n % 64 == 0: a block computes a tile of
-// 4 rows (j) x 64 voxels (k) of one plane (i) for COT*16 output channels.
-// For every 16-channel input slice it stages the 3 x 6 x 66 voxel
+// 4 RW rows (j) x 64 voxels (k) of one plane (i) for COT*16 output channels.
+// For every 16-channel input slice it stages the 3 x (4 RW + 2) x 66 voxel
 // neighbourhood of the tile in LDS (voxel stride 20 bf16 = 40 bytes, which
 // spreads a wave's 8-byte fragment reads over distinct banks), then each wave
-// (one row) runs the 27 taps x 4 voxel tiles x COT channel tiles from LDS.
-// The operands and their order per output are those of k_conv3 (bitwise the
-// same result).
-constexpr int kCvRows = 4, kCvK = 64, kCvStride = 20;
-constexpr int kCvVox = 3 * (kCvRows + 2) * (kCvK + 2);
+// (RW rows) runs the 27 taps x 4 RW voxel tiles x COT channel tiles from LDS.
+// Every block reads the same weights, so each fragment feeding RW rows' MFMAs
+// halves their L2 traffic at RW = 2.  The weights are the MFMA's A operand:
+// a lane holds four consecutive output channels of one voxel (vector stores
+// when the view is 4-aligned).
+constexpr int kCvK = 64, kCvStride = 20;
 
-template <int COT>
-__global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ in, int in_stride, int in_off,
+template <int COT, int RW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_lds(const uint16_t *__restrict__ in, int in_stride, int in_off,
                                                    int cin_pad, const uint16_t *__restrict__ wp, int cout_pad,
                                                    const float *__restrict__ bias, int cout, void *__restrict__ out,
                                                    int out_stride, int out_off, int out_f32, int n, int flip, int relu,
                                                    unsigned ntiles)
 {
-    __shared__ __align__(16) uint16_t tile[kCvVox * kCvStride];
+    constexpr int ROWS = 4 * RW, WR = ROWS + 2, WVOX = 3 * WR * (kCvK + 2);
+    __shared__ __align__(16) uint16_t tile[WVOX * kCvStride];
     const unsigned t = xcd_block(0);
     if (t >= ntiles)
         return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int r = lane & 15, q = lane >> 4;
-    const int nkt = n / kCvK, njt = n / kCvRows;
+    const int nkt = n / kCvK, njt = n / ROWS;
     const int kt = (int)(t % nkt), jt = (int)((t / nkt) % njt), i = (int)(t / ((unsigned)nkt * njt));
-    const int j0 = jt * kCvRows, k0 = kt * kCvK;
+    const int j0 = jt * ROWS, k0 = kt * kCvK;
     const int co_base = blockIdx.y * COT * 16;
     const int sgn = flip ? -1 : 1;
-    f32x4 acc[4][COT];
+    const bool vec = out_stride % 4 == 0 && out_off % 4 == 0;
+    f32x4 acc[RW][4][COT];
 #pragma unroll
-    for (int m = 0; m < 4; m++)
+    for (int w = 0; w < RW; w++)
 #pragma unroll
-        for (int u = 0; u < COT; u++)
-            acc[m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < 4; m++)
+#pragma unroll
+            for (int u = 0; u < COT; u++)
+                acc[w][m][u] = (f32x4){0.f, 0.f, 0.f, 0.f};
     // weight fragments of tap `tap` and input slice c0 for this lane (a
     // uniform base plus the lane's offset)
     const unsigned wlane = (unsigned)((co_base + r) * cin_pad + 4 * q);
@@ -193,29 +201,28 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ 
         }
     };
     // staging of one 16-channel input slice: this thread's 8-byte chunks of
-    // the 3 x 6 x 66 neighbourhood in three batches, each with all its loads
-    // issued before any is stored (one batch's registers keep three blocks
-    // per CU)
-    constexpr int NST = (kCvVox * 4 + 255) / 256, NB = (NST + 2) / 3;
+    // the neighbourhood in three batches, each with all its loads issued
+    // before any is stored
+    constexpr int NST = (WVOX * 4 + 255) / 256, NB = (NST + 2) / 3;
     const int part = threadIdx.x & 3;
     auto stage = [&](int c0, int st0) {
         uint2 stg[NB];
 #pragma unroll
         for (int u = 0; u < NB; u++) {
             const int v = (threadIdx.x >> 2) + 64 * (st0 + u);
-            if (st0 + u < NST && v < kCvVox) {
-                const int pl = v / ((kCvRows + 2) * (kCvK + 2));
-                const int rem = v - pl * (kCvRows + 2) * (kCvK + 2);
+            if (st0 + u < NST && v < WVOX) {
+                const int pl = v / (WR * (kCvK + 2));
+                const int rem = v - pl * WR * (kCvK + 2);
                 const int row = rem / (kCvK + 2), col = rem - row * (kCvK + 2);
                 const int ii = wrapi(i + pl - 1, n), jj = wrapi(j0 + row - 1, n), kk = wrapi(k0 + col - 1, n);
                 stg[u] = *(const uint2 *)(in + (size_t)((ii * n + jj) * n + kk) * in_stride + in_off + c0 + 4 * part);
             }
         }
-        // voxel v = (plane * 6 + row) * 66 + col, 16 channels as 4 x 8 bytes
+        // voxel v = (plane * WR + row) * 66 + col, 16 channels as 4 x 8 bytes
 #pragma unroll
         for (int u = 0; u < NB; u++) {
             const int v = (threadIdx.x >> 2) + 64 * (st0 + u);
-            if (st0 + u < NST && v < kCvVox)
+            if (st0 + u < NST && v < WVOX)
                 *(uint2 *)(tile + v * kCvStride + 4 * part) = stg[u];
         }
     };
@@ -226,17 +233,21 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ 
         load_b(tap + 2 < 27 ? tap + 2 : 26, c0, bl);
         int di, dj, dk;
         tap_offsets(tap, di, dj, dk);
-        const int pl = 1 + sgn * di, row = 1 + wave + sgn * dj, colb = 1 + r + sgn * dk;
-        const uint16_t *tb = tile + ((pl * (kCvRows + 2) + row) * (kCvK + 2) + colb) * kCvStride + 4 * q;
-        bf16x4 a[4];
+        const int pl = 1 + sgn * di, colb = 1 + r + sgn * dk;
 #pragma unroll
-        for (int m = 0; m < 4; m++)
-            a[m] = *(const bf16x4 *)(tb + 16 * m * kCvStride);
+        for (int w = 0; w < RW; w++) {
+            const int row = 1 + RW * wave + w + sgn * dj;
+            const uint16_t *tb = tile + ((pl * WR + row) * (kCvK + 2) + colb) * kCvStride + 4 * q;
+            bf16x4 a[4];
 #pragma unroll
-        for (int m = 0; m < 4; m++)
+            for (int m = 0; m < 4; m++)
+                a[m] = *(const bf16x4 *)(tb + 16 * m * kCvStride);
 #pragma unroll
-            for (int u = 0; u < COT; u++)
-                acc[m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[m], bc[u], acc[m][u], 0, 0, 0);
+            for (int m = 0; m < 4; m++)
+#pragma unroll
+                for (int u = 0; u < COT; u++)
+                    acc[w][m][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bc[u], a[m], acc[w][m][u], 0, 0, 0);
+        }
     };
     for (int c0 = 0; c0 < cin_pad; c0 += 16) {
         // weights two taps ahead in a ring of three register slots; the first
@@ -256,26 +267,41 @@ __global__ __launch_bounds__(256) void k_conv3_lds(const uint16_t *__restrict__ 
         }
         __syncthreads();
     }
-    const size_t vbase = (size_t)((i * n + j0 + wave) * n + k0);
+    // lane (r, q) holds channels 4q .. 4q + 3 (+ 16 u) of voxel 16 m + r
 #pragma unroll
-    for (int u = 0; u < COT; u++) {
-        const int o = co_base + u * 16 + r;
-        if (o >= cout)
-            continue;
-        const float bo = bias ? bias[o] : 0.f;
+    for (int w = 0; w < RW; w++) {
+        const size_t vbase = (size_t)((i * n + j0 + RW * wave + w) * n + k0);
 #pragma unroll
-        for (int m = 0; m < 4; m++)
+        for (int u = 0; u < COT; u++) {
+            const int o0 = co_base + u * 16 + 4 * q;
+            float bo[4];
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                float v = acc[m][u][e] + bo;
-                if (relu)
-                    v = fmaxf(v, 0.f);
-                const size_t idx = (vbase + 16 * m + 4 * q + e) * out_stride + out_off + o;
-                if (out_f32)
-                    ((float *)out)[idx] = v;
-                else
-                    ((uint16_t *)out)[idx] = f2bf(v);
+            for (int e = 0; e < 4; e++)
+                bo[e] = (bias && o0 + e < cout) ? bias[o0 + e] : 0.f;
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    v[e] = relu ? fmaxf(acc[w][m][u][e] + bo[e], 0.f) : acc[w][m][u][e] + bo[e];
+                const size_t idx = (vbase + 16 * m + r) * out_stride + out_off + o0;
+                if (vec && o0 + 3 < cout) {
+                    if (out_f32)
+                        *(f32x4 *)((float *)out + idx) = (f32x4){v[0], v[1], v[2], v[3]};
+                    else
+                        *(u16x4 *)((uint16_t *)out + idx) = (u16x4){f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if (o0 + e < cout) {
+                            if (out_f32)
+                                ((float *)out)[idx + e] = v[e];
+                            else
+                                ((uint16_t *)out)[idx + e] = f2bf(v[e]);
+                        }
+                }
             }
+        }
     }
 }
 
@@ -321,9 +347,6 @@ static void launch_conv3_mt(const uint16_t *in, int in_stride, int in_off, int c
 // number of 16-byte units (the 16-byte fragment reads of 8 consecutive lanes
 // then fall in distinct banks).  PL = 2 mod 3, so the steps between the two
 // boundary steps at each end come in whole rounds of the three slots.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMarchThreads = 512;
 
@@ -1160,13 +1183,14 @@ void launch_conv3(const uint16_t *in, int in_stride, int in_off, int cin_pad, co
         return;
     }
     if (n % kCvK == 0 && in_stride % 4 == 0 && in_off % 4 == 0) {
-        const unsigned ntiles = (unsigned)n * (n / kCvRows) * (n / kCvK);
+        // two rows per wave (8-row tiles)
+        const unsigned ntiles = (unsigned)n * (n / 8) * (n / kCvK);
         const int tiles = cout_pad / 16;
         const int cot = tiles % 4 == 0 ? 4 : (tiles % 3 == 0 ? 3 : (tiles % 2 == 0 ? 2 : 1));
         dim3 grid(xcd_blocks(ntiles), cout_pad / (cot * 16));
 #define PM_CONVL(C)                                                                                                    \
-    hipLaunchKernelGGL((k_conv3_lds<C>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad, bias,   \
-                       cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles)
+    hipLaunchKernelGGL((k_conv3_lds<C, 2>), grid, dim3(256), 0, st, in, in_stride, in_off, cin_pad, wp, cout_pad,      \
+                       bias, cout, out, out_stride, out_off, out_f32 ? 1 : 0, n, flip ? 1 : 0, relu ? 1 : 0, ntiles)
         if (cot == 4)
             PM_CONVL(4);
         else if (cot == 3)
