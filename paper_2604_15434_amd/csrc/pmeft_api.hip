@@ -479,7 +479,7 @@ static void build_hier32(Ctx &C, Hier<float> &H)
 // 3 Poisson FP32.
 struct KernelTiming {
     std::mutex mu;
-    bool on = false;
+    std::atomic<bool> on{false};  // read by the step's worker thread too
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<int> slot_of_pair;
@@ -499,7 +499,7 @@ static void smooth(Ctx &C, Hier<R> &H, int l, int colour, SolveConsts sc, bool n
     if (sc.jacobi && colour == 1)  // Jacobi: the red values from before this sweep's red half
         oth = H.buf[l][1 - H.cur[l][0]];
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (l == 0 && g_kt.on) {
+    if (l == 0 && g_kt.on.load(std::memory_order_relaxed)) {
         std::lock_guard<std::mutex> g(g_kt.mu);
         if (g_kt.used + 2 <= g_kt.pool.size()) {
             e0 = g_kt.pool[g_kt.used];
@@ -534,7 +534,7 @@ static void sweep(Ctx &C, Hier<R> &H, int l, SolveConsts sc, bool nl)
         const long long half = H.L[l].half;
         const int orr = H.cur[l][0], ob = H.cur[l][1];
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (l == 0 && g_kt.on) {
+        if (l == 0 && g_kt.on.load(std::memory_order_relaxed)) {
             std::lock_guard<std::mutex> g(g_kt.mu);
             if (g_kt.used + 2 <= g_kt.pool.size()) {
                 e0 = g_kt.pool[g_kt.used];
@@ -1163,11 +1163,17 @@ struct Timer {
     }
     float stop()
     {
-        float ms = 0.f;
-        (void)hipEventRecord(b, st);
+        mark();
+        return ms();
+    }
+    // end of the timed span, read later with ms() (no host wait here)
+    void mark() { (void)hipEventRecord(b, st); }
+    float ms()
+    {
+        float v = 0.f;
         (void)hipEventSynchronize(b);
-        (void)hipEventElapsedTime(&ms, a, b);
-        return ms;
+        (void)hipEventElapsedTime(&v, a, b);
+        return v;
     }
     ~Timer()
     {
@@ -1966,7 +1972,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         wait_network();
         return e;
     }
-    const float ms_dep = tdep.stop();
+    tdep.mark();
     double *ps = C.at<double>(C.P.psi64), *ch = C.at<double>(C.P.chi64);
     if (poisson_opts->guess == PM_GUESS_GIVEN)
         launch_natural_to_packed(psi, dtype, ps, ng, 1.0, 0.0, C.st);
@@ -2020,7 +2026,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     void *g4 = C.ws + C.P.g4;
     launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
     launch_interp_kick(g4, ng, dtype, pos, np, vel, dt_kick, dt_drift, nullptr, C.st);
-    const float ms_f = tf.stop();
+    tf.mark();
     launch_field_sum(ch, C.P.N, C.rs, C.st);
     launch_packed_to_natural(ch, chi, dtype, ng, 0.0, C.rs.out, C.st);
     e = launched();
@@ -2031,8 +2037,8 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         memset(rep, 0, sizeof(*rep));
         fill_report(&rep->poisson, sp, ms_p);
         fill_report(&rep->scalar, sx, ms_x);
-        rep->ms_deposit = ms_dep;
-        rep->ms_force = ms_f;
+        rep->ms_deposit = tdep.ms();
+        rep->ms_force = tf.ms();
         rep->ms_total = ms_all;
     }
     if (sp.status)
@@ -2308,7 +2314,7 @@ int pm_kernel_timing_enable(int on)
             if (hipEventCreate(&e) != hipSuccess)
                 return PM_EHIP;
     }
-    g_kt.on = on != 0;
+    g_kt.on.store(on != 0);
     return PM_OK;
 }
 

@@ -9,14 +9,19 @@
 //   k_conv3          one-plane kernel: a wave computes 16 consecutive voxels
 //                    along k times 16 output channels per tile
 //                    (v_mfma_f32_16x16x16_bf16);
-//   k_conv3_lds      the same with the plane staged in LDS;
+//   k_conv3_lds      the plane's neighbourhood staged in LDS (grids that are
+//                    multiples of 64, more than 48 input channels);
 //   k_conv3_march    grids that are multiples of 64, up to 48 input channels:
-//                    blocks march along i with three input planes in an LDS
-//                    ring (v_mfma_f32_16x16x32_bf16);
+//                    blocks march along i over input planes (three-slot LDS
+//                    ring), each feeding three output planes' accumulators
+//                    (v_mfma_f32_16x16x32_bf16);
 //   k_conv3_in1      the first layer at inference (one density channel);
 //   k_upconv_poly    decoder layers on upsampled tensors at inference
 //                    (polyphase form on the coarse grid);
-//   k_conv3_wgrad    weight and bias gradients (voxels as the K index).
+//   k_updec_march    the decoder layer on the 16-channel level at inference,
+//                    skip channels and polyphase sum in one march;
+//   k_conv3_wgrad    weight and bias gradients (voxels as the K index);
+//   k_pack_jobs      every weight layout the kernels read, in one launch.
 // MFMA operand layout (16x16xK, K = 16 or 32, L = K / 4 values per lane):
 // lane l supplies A[l%16][L(l/16)+i] and B[L(l/16)+i][l%16], i < L, and
 // receives D[4(l/16)+i][l%16], i = 0..3.
