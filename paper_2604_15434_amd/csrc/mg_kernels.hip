@@ -829,7 +829,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
         double tsh;
         const double S = stencil_eval<double>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8], v[9], v[10], v[11],
                                               v[12], v[13], v[14], v[15], v[16], v[17], NL, tsh);
-        const double b = sc.beta * (c ? F.db : F.dr)[ef];
+        const double dv = (c ? F.db : F.dr)[ef];
+        const double b = sc.beta * dv;
         int isv;
         const double lq = root_lap<double>(b, tsh * ih2 * ih2, sc, NL, isv);
         const double r = lq - cm - (S - 6.0 * x64) * ih2;
@@ -839,7 +840,6 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
         acc[3] += (double)isv;
         if (!NL) {
             (c ? x32b : x32r)[ef] = 0.0f;
-            (c ? G.x0b : G.x0r)[ef] = 0.0f;
             (c ? G.tb : G.tr)[ef] = (float)r;
             acc[4 + c] += (double)(float)r;
         } else {
@@ -849,13 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
                 (float)v[7], (float)v[8], (float)v[9], (float)v[10], (float)v[11], (float)v[12], (float)v[13],
                 (float)v[14], (float)v[15], (float)v[16], (float)v[17], true, tsh32);
             const float x32 = (float)x64;
-            const float b32 = (float)sc.beta * (c ? G.db : G.dr)[ef];
+            const float b32 = (float)sc.beta * (float)dv;  // the FP32 level's delta is fl32 of the FP64 one
             int isv32;
             const float lq32 = root_lap<float>(b32, tsh32 * ih2f * ih2f, sc, true, isv32);
             const float lap32 = (S32 - 6.0f * x32) * ih2f;
             const float tau32 = (float)r + lap32 - lq32;
             (c ? x32b : x32r)[ef] = x32;
-            (c ? G.x0b : G.x0r)[ef] = x32;
             (c ? G.tb : G.tr)[ef] = tau32;
             acc[4 + c] += (double)(lq32 + tau32);
         }
@@ -881,10 +880,10 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
     block_partials<6>(acc, rs, sp);
 }
 
-void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
+bool launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                                  const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs,
                                  SolveConsts sc, bool nonlinear, hipStream_t st, int tiled, double *lag64,
-                                 double *lag32)
+                                 double *lag32, const MixedCorr *corr)
 {
     auto finish = [&](const Span &s) {
         if (lag64 && lag32)
@@ -894,10 +893,12 @@ void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
             launch_finalize(rs, s, 6, rs.out, st);
     };
     Span spt;
-    if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt)) {
+    if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt, corr)) {
         finish(spt);
-        return;
+        return true;
     }
+    if (corr)
+        return false;
     const Span sp = make_span(2 * F64.half);
     if (nonlinear)
         hipLaunchKernelGGL((k_mixed_outer<true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64, F32,
@@ -906,34 +907,41 @@ void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
         hipLaunchKernelGGL((k_mixed_outer<false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, F64, xr, xb, csum64,
                            F32, x32r, x32b, rs, sc, sp, cur_group());
     finish(sp);
+    return true;
 }
 
+// x64 += fl32(x32 - fl32(x64)) (NL: the FP32 level started from fl32(x64))
+// or x64 += x32 (the linear correction form, started from 0).
+template <bool NL>
 __global__ __launch_bounds__(kBlock) void k_mixed_correct(double *__restrict__ x64, const float *__restrict__ x32r,
-                                                          const float *__restrict__ x32b, const float *__restrict__ x0r,
-                                                          const float *__restrict__ x0b, unsigned half, Span sp,
+                                                          const float *__restrict__ x32b, unsigned half, Span sp,
                                                           Group grp)
 {
     const long long go = group_offset(grp);
     x64 = gshift(x64, go);
     x32r = gshift(x32r, go);
     x32b = gshift(x32b, go);
-    x0r = gshift(x0r, go);
-    x0b = gshift(x0b, go);
     PM_SPAN_LOOP(e, sp)
     {
         const int c = e >= half;
         const unsigned ec = e - (c ? half : 0u);
-        const float d = c ? x32b[ec] - x0b[ec] : x32r[ec] - x0r[ec];
-        x64[e] += (double)d;
+        const double x = x64[e];
+        const float v = c ? x32b[ec] : x32r[ec];
+        const float d = NL ? v - (float)x : v;
+        x64[e] = x + (double)d;
     }
 }
 
-void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, const float *x0r, const float *x0b,
-                          long long half, hipStream_t st)
+void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, long long half, bool nonlinear,
+                          hipStream_t st)
 {
     const Span sp = make_span(2 * half);
-    hipLaunchKernelGGL(k_mixed_correct, group_grid(sp.nblocks), dim3(kBlock), 0, st, x64, x32r, x32b, x0r, x0b,
-                       (unsigned)half, sp, cur_group());
+    if (nonlinear)
+        hipLaunchKernelGGL((k_mixed_correct<true>), group_grid(sp.nblocks), dim3(kBlock), 0, st, x64, x32r, x32b,
+                           (unsigned)half, sp, cur_group());
+    else
+        hipLaunchKernelGGL((k_mixed_correct<false>), group_grid(sp.nblocks), dim3(kBlock), 0, st, x64, x32r, x32b,
+                           (unsigned)half, sp, cur_group());
 }
 
 // ------------------------------------------------------------ residual norm

@@ -422,20 +422,22 @@ __global__ __launch_bounds__(kBlock) void k_gradient(const double *__restrict__ 
     }
 }
 
-// The same gradient, 2.5D-tiled for n % 64 == 0: a block owns 4 rows (j) by
-// 64 cells (k) and walks PL planes along i, keeping Psi_tot of planes
+// The same gradient, 2.5D-tiled for n % 64 == 0: a block owns 4 CJ rows (j)
+// by 64 cells (k) and walks PL planes along i, keeping Psi_tot of planes
 // i - 2 .. i + 2 (with a two-cell halo in j and k, in natural order) in a
 // six-slot LDS ring: the next plane is fetched into registers before the
 // current one is computed and stored into the free slot after it (one
-// barrier per plane).  Same operands and expression as k_gradient.
-constexpr int kGradRows = 4, kGradK = 64, kGradPL = 16;
+// barrier per plane).  Thread (tj, tk) computes rows tj, tj + 4, ... of the
+// tile.  Same operands and expression as k_gradient.
+constexpr int kGradK = 64, kGradPL = 16, kGradCJ = 2;
 
-template <typename Tg>
+template <typename Tg, int CJ>
 __global__ __launch_bounds__(kBlock) void k_gradient_tile(const double *__restrict__ psi,
                                                           const double *__restrict__ chi, double xi, int n,
                                                           Tg *__restrict__ g4, unsigned ntiles)
 {
-    constexpr int WR = kGradRows + 4, WC = kGradK + 4, W = WR * WC;
+    constexpr int RS = kBlock / kGradK, ROWS = RS * CJ;
+    constexpr int WR = ROWS + 4, WC = kGradK + 4, W = WR * WC;
     constexpr int PER = (W + kBlock - 1) / kBlock;
     __shared__ double win[6][WR][WC];
     const int nh = n / 2;
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void k_gradient_tile(const double *__restri
     double *wflat = &win[0][0][0];
     for (unsigned t = lb; t < ntiles; t += nb) {
         const int ib = (int)(t % nI), kb = (int)((t / nI) % nK), jb = (int)(t / ((unsigned)nI * nK));
-        const int i0 = ib * kGradPL, j0 = jb * kGradRows, k0 = kb * kGradK;
+        const int i0 = ib * kGradPL, j0 = jb * ROWS, k0 = kb * kGradK;
         // window element q: row q / WC (j = j0 - 2 + row), column q % WC
         // (k = k0 - 2 + column); packed offset within a plane and j + k parity
         unsigned poff[PER];
@@ -464,68 +466,72 @@ __global__ __launch_bounds__(kBlock) void k_gradient_tile(const double *__restri
             par[u] = (j + k) & 1;
         }
         double pre[PER];
-#define PM_GRAD_FETCH(II)                                                                                              \
-    do {                                                                                                               \
-        const int ii_ = (II) < 0 ? (II) + n : ((II) >= n ? (II) - n : (II));                                           \
-        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kBlock < W)                              \
-        {                                                                                                              \
-            const unsigned o_ = (((ii_ + par[u]) & 1) ? half : 0u) + (unsigned)ii_ * n * nh + poff[u];                 \
-            double v_ = psi[o_];                                                                                       \
-            if (chi)                                                                                                   \
-                v_ += xi * chi[o_];                                                                                    \
-            pre[u] = v_;                                                                                               \
-        }                                                                                                              \
-    } while (0)
-#define PM_GRAD_STORE(SLOT)                                                                                            \
-    do {                                                                                                               \
-        _Pragma("unroll") for (int u = 0; u < PER; u++) if (threadIdx.x + u * kBlock < W) wflat[(SLOT) * W +          \
-                                                                                                  threadIdx.x +        \
-                                                                                                  u * kBlock] = pre[u]; \
-    } while (0)
+        auto fetch = [&](int ii) {
+            ii = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kBlock < W) {
+                    const unsigned o = (((ii + par[u]) & 1) ? half : 0u) + (unsigned)ii * n * nh + poff[u];
+                    double v = psi[o];
+                    if (chi)
+                        v += xi * chi[o];
+                    pre[u] = v;
+                }
+        };
+        auto store = [&](int slot) {
+#pragma unroll
+            for (int u = 0; u < PER; u++)
+                if (threadIdx.x + u * kBlock < W)
+                    wflat[slot * W + threadIdx.x + u * kBlock] = pre[u];
+        };
 #pragma unroll 1
         for (int d = 0; d < 5; d++) {
-            PM_GRAD_FETCH(i0 - 2 + d);
-            PM_GRAD_STORE(d);
+            fetch(i0 - 2 + d);
+            store(d);
         }
         __syncthreads();
 #pragma unroll 1
         for (int p = 0; p < kGradPL; p++) {
             const int i = i0 + p;
             if (p + 1 < kGradPL)
-                PM_GRAD_FETCH(i + 3);
-            const int r = tj + 2, c = tk + 2;
-            const double *m2 = &win[p % 6][r][c], *m1 = &win[(p + 1) % 6][r][c], *c0 = &win[(p + 2) % 6][r][c];
-            const double *p1 = &win[(p + 3) % 6][r][c], *p2 = &win[(p + 4) % 6][r][c];
-            const double gx = s * (m2[0] - 8.0 * m1[0] + 8.0 * p1[0] - p2[0]);
-            const double gy = s * (c0[-2 * WC] - 8.0 * c0[-WC] + 8.0 * c0[WC] - c0[2 * WC]);
-            const double gz = s * (c0[-2] - 8.0 * c0[-1] + 8.0 * c0[1] - c0[2]);
-            Tg *o = g4 + 4 * ((size_t)((unsigned)i * n + j0 + tj) * n + k0 + tk);
-            o[0] = (Tg)gx;
-            o[1] = (Tg)gy;
-            o[2] = (Tg)gz;
-            o[3] = (Tg)0;
+                fetch(i + 3);
+#pragma unroll
+            for (int cj = 0; cj < CJ; cj++) {
+                const int r = tj + cj * RS + 2, c = tk + 2;
+                const double *m2 = &win[p % 6][r][c], *m1 = &win[(p + 1) % 6][r][c], *c0 = &win[(p + 2) % 6][r][c];
+                const double *p1 = &win[(p + 3) % 6][r][c], *p2 = &win[(p + 4) % 6][r][c];
+                const double gx = s * (m2[0] - 8.0 * m1[0] + 8.0 * p1[0] - p2[0]);
+                const double gy = s * (c0[-2 * WC] - 8.0 * c0[-WC] + 8.0 * c0[WC] - c0[2 * WC]);
+                const double gz = s * (c0[-2] - 8.0 * c0[-1] + 8.0 * c0[1] - c0[2]);
+                typedef Tg Tg4 __attribute__((ext_vector_type(4)));
+                Tg4 o;
+                o[0] = (Tg)gx;
+                o[1] = (Tg)gy;
+                o[2] = (Tg)gz;
+                o[3] = (Tg)0;
+                *(Tg4 *)(g4 + 4 * ((size_t)((unsigned)i * n + j0 + tj + cj * RS) * n + k0 + tk)) = o;
+            }
             if (p + 1 < kGradPL)
-                PM_GRAD_STORE((p + 5) % 6);  // plane i + 3 replaces plane i - 3
+                store((p + 5) % 6);  // plane i + 3 replaces plane i - 3
             __syncthreads();
         }
-#undef PM_GRAD_STORE
-#undef PM_GRAD_FETCH
     }
 }
 
 void launch_gradient(const double *psi, const double *chi, double xi, int ng, void *g4, pm_dtype dt, hipStream_t st)
 {
-    if (ng % kGradK == 0 && ng % kGradPL == 0) {
-        const unsigned ntiles = (unsigned)(ng / kGradRows) * (ng / kGradK) * (ng / kGradPL);
+    constexpr int rows = kBlock / kGradK * kGradCJ;
+    if (ng % kGradK == 0 && ng % kGradPL == 0 && ng % rows == 0) {
+        const unsigned ntiles = (unsigned)(ng / rows) * (ng / kGradK) * (ng / kGradPL);
         unsigned nb = ntiles < 2048u ? ntiles : 2048u;
         if (nb >= 8)
             nb -= nb % 8;
         if (dt == PM_F64)
-            hipLaunchKernelGGL((k_gradient_tile<double>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng,
+            hipLaunchKernelGGL((k_gradient_tile<double, kGradCJ>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng,
                                (double *)g4, ntiles);
         else
-            hipLaunchKernelGGL((k_gradient_tile<float>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng, (float *)g4,
-                               ntiles);
+            hipLaunchKernelGGL((k_gradient_tile<float, kGradCJ>), dim3(nb), dim3(kBlock), 0, st, psi, chi, xi, ng,
+                               (float *)g4, ntiles);
         return;
     }
     const Span sp = make_span((unsigned long long)ng * ng * ng);
@@ -538,21 +544,63 @@ void launch_gradient(const double *psi, const double *chi, double xi, int ng, vo
 }
 
 // ---------------------------------------------------------- interpolation
-template <typename T>
+// CIC interpolation of g at each particle, kick, optional drift.  A thread
+// takes UNR particles (kBlock apart) per pass and issues all their position
+// and corner loads before the arithmetic on any of them; a particle with a
+// non-finite coordinate reads cell 0 and gets zero acceleration.
+constexpr int kInterpUnr = 2;
+
+template <typename T, int UNR>
 __global__ __launch_bounds__(kBlock) void k_interp_kick(const T *__restrict__ g4, int ng, T *__restrict__ pos,
                                                         unsigned np, T *__restrict__ vel, double dt_kick,
                                                         double dt_drift, T *__restrict__ acc_out, Span sp)
 {
-    PM_SPAN_LOOP(p, sp)
-    {
-        int x0, x1, y0, y1, z0, z1;
-        double fx, fy, fz;
-        const bool ok = cic_axis((double)pos[p], ng, x0, x1, fx) && cic_axis((double)pos[np + p], ng, y0, y1, fy) &&
-                        cic_axis((double)pos[2 * np + p], ng, z0, z1, fz);
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        if (ok) {
-            const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-            const int ix[2] = {x0, x1}, iy[2] = {y0, y1}, iz[2] = {z0, z1};
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    const unsigned b0 = span_block(sp) * sp.chunk;
+    const unsigned end = min(sp.total, b0 + sp.chunk);
+    for (unsigned p0 = b0 + threadIdx.x; p0 < end; p0 += UNR * kBlock) {
+        unsigned pp[UNR];
+        bool live[UNR], ok[UNR];
+        double x[UNR][3], fr[UNR][3];
+        int c0[UNR][3], c1[UNR][3];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const unsigned p = p0 + u * kBlock;
+            live[u] = p < end;
+            pp[u] = live[u] ? p : p0;
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+                x[u][d] = (double)pos[(size_t)d * np + pp[u]];
+        }
+        T4 g[UNR][8];
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            ok[u] = true;
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+                ok[u] = ok[u] && cic_axis(x[u][d], ng, c0[u][d], c1[u][d], fr[u][d]);
+            if (!ok[u])
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    c0[u][d] = c1[u][d] = 0;
+                    fr[u][d] = 0.0;
+                }
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int b = 0; b < 2; b++)
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        const unsigned cell = ((unsigned)(a ? c1[u][0] : c0[u][0]) * ng + (b ? c1[u][1] : c0[u][1])) * ng +
+                                              (c ? c1[u][2] : c0[u][2]);
+                        g[u][4 * a + 2 * b + c] = *(const T4 *)(g4 + 4 * (size_t)cell);  // one 16- or 32-byte load
+                    }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            const double wx[2] = {1.0 - fr[u][0], fr[u][0]}, wy[2] = {1.0 - fr[u][1], fr[u][1]},
+                         wz[2] = {1.0 - fr[u][2], fr[u][2]};
 #pragma unroll
             for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -560,35 +608,38 @@ __global__ __launch_bounds__(kBlock) void k_interp_kick(const T *__restrict__ g4
 #pragma unroll
                     for (int c = 0; c < 2; c++) {
                         const double w = wx[a] * wy[b] * wz[c];
-                        const T *gv = g4 + 4 * (((unsigned)ix[a] * ng + iy[b]) * ng + iz[c]);
-                        typedef T T4 __attribute__((ext_vector_type(4)));
-                        const T4 g = *(const T4 *)gv;  // one 16- or 32-byte load per corner
-                        ax += w * (double)g[0];
-                        ay += w * (double)g[1];
-                        az += w * (double)g[2];
+                        const T4 gv = g[u][4 * a + 2 * b + c];
+                        ax += w * (double)gv[0];
+                        ay += w * (double)gv[1];
+                        az += w * (double)gv[2];
                     }
-        }
-        const double vx = (double)vel[p] + ax * dt_kick;
-        const double vy = (double)vel[np + p] + ay * dt_kick;
-        const double vz = (double)vel[2 * np + p] + az * dt_kick;
-        vel[p] = (T)vx;
-        vel[np + p] = (T)vy;
-        vel[2 * np + p] = (T)vz;
-        if (acc_out) {
-            acc_out[p] = (T)ax;
-            acc_out[np + p] = (T)ay;
-            acc_out[2 * np + p] = (T)az;
-        }
-        if (dt_drift != 0.0 && ok) {
-            double x = (double)pos[p] + vx * dt_drift;
-            double y = (double)pos[np + p] + vy * dt_drift;
-            double z = (double)pos[2 * np + p] + vz * dt_drift;
-            x -= floor(x);
-            y -= floor(y);
-            z -= floor(z);
-            pos[p] = (T)(x >= 1.0 ? 0.0 : x);
-            pos[np + p] = (T)(y >= 1.0 ? 0.0 : y);
-            pos[2 * np + p] = (T)(z >= 1.0 ? 0.0 : z);
+            if (!ok[u])
+                ax = ay = az = 0.0;
+            if (!live[u])
+                continue;
+            const unsigned p = pp[u];
+            const double vx = (double)vel[p] + ax * dt_kick;
+            const double vy = (double)vel[np + p] + ay * dt_kick;
+            const double vz = (double)vel[2 * np + p] + az * dt_kick;
+            vel[p] = (T)vx;
+            vel[np + p] = (T)vy;
+            vel[2 * np + p] = (T)vz;
+            if (acc_out) {
+                acc_out[p] = (T)ax;
+                acc_out[np + p] = (T)ay;
+                acc_out[2 * np + p] = (T)az;
+            }
+            if (dt_drift != 0.0 && ok[u]) {
+                double xn = x[u][0] + vx * dt_drift;
+                double yn = x[u][1] + vy * dt_drift;
+                double zn = x[u][2] + vz * dt_drift;
+                xn -= floor(xn);
+                yn -= floor(yn);
+                zn -= floor(zn);
+                pos[p] = (T)(xn >= 1.0 ? 0.0 : xn);
+                pos[np + p] = (T)(yn >= 1.0 ? 0.0 : yn);
+                pos[2 * np + p] = (T)(zn >= 1.0 ? 0.0 : zn);
+            }
         }
     }
 }
@@ -598,11 +649,13 @@ void launch_interp_kick(const void *g4, int ng, pm_dtype dt, void *pos, long lon
 {
     const Span sp = make_span(np);
     if (dt == PM_F64)
-        hipLaunchKernelGGL((k_interp_kick<double>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const double *)g4, ng,
-                           (double *)pos, (unsigned)np, (double *)vel, dt_kick, dt_drift, (double *)acc_out, sp);
+        hipLaunchKernelGGL((k_interp_kick<double, kInterpUnr>), dim3(sp.nblocks), dim3(kBlock), 0, st,
+                           (const double *)g4, ng, (double *)pos, (unsigned)np, (double *)vel, dt_kick, dt_drift,
+                           (double *)acc_out, sp);
     else
-        hipLaunchKernelGGL((k_interp_kick<float>), dim3(sp.nblocks), dim3(kBlock), 0, st, (const float *)g4, ng,
-                           (float *)pos, (unsigned)np, (float *)vel, dt_kick, dt_drift, (float *)acc_out, sp);
+        hipLaunchKernelGGL((k_interp_kick<float, kInterpUnr>), dim3(sp.nblocks), dim3(kBlock), 0, st,
+                           (const float *)g4, ng, (float *)pos, (unsigned)np, (float *)vel, dt_kick, dt_drift,
+                           (float *)acc_out, sp);
 }
 
 // Bardeen potentials from Psi_N and chi (natural order, same dtype):

@@ -840,20 +840,53 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
     std::vector<double> out(4 * (size_t)G.m), prev(G.m, 0.0);
     std::vector<int> cyc_of(G.m, 0), it_of(G.m, 0), to_f64;
     int cyc = 0;  // FP32 V-cycles (the same for every slot still in the FP32 phase)
+    // The FP64 iterate lives in `cur`: the master buffer, or the level's
+    // second FP64 buffer after an odd number of corrections applied out of
+    // place by the tiled outer step.  `pending`: the FP32 V-cycles since the
+    // last outer step have not corrected it yet (the next outer step does).
+    // Applied out of place from 256^3 up: on smaller levels the separate
+    // correction launch costs less than the fused loads add to the outer
+    // step's latency.
+    double *cur = master, *alt = C.at<double>(C.P.q64[0]);
+    const bool fuse = C.P.n[0] >= 256 && mixed_outer_tiles(C.P.n[0], H.tiled);
+    bool pending = false;
+    auto to_master = [&](int s) { return cur == master ? PM_OK : slot_copy(C, G, s, master, cur, sizeof(double) * 2 * half); };
     for (int it = 0;; it++) {
         if (!final_residual && it > 0 && cyc >= o.max_vcycles) {
+            if (pending)
+                launch_mixed_correct(cur, H.xr(0), H.xb(0), half, nl, C.st);
             for (int s : G.active) {
+                if ((e = to_master(s)))
+                    return e;
                 so[s].status = PM_ENOCONV;
                 so[s].vcycles = cyc;
             }
             G.active.clear();
             break;
         }
-        H.cur[0][0] = H.cur[0][1] = 0;
+        MixedCorr mc;
+        const bool fused = pending && fuse;
+        if (fused) {
+            mc.vr = H.xr(0);
+            mc.vb = H.xb(0);
+            mc.yr = alt;
+            mc.yb = alt + half;
+            // x32 goes to the other buffer of each colour (v is read there)
+            H.cur[0][0] ^= 1;
+            H.cur[0][1] ^= 1;
+        } else {
+            if (pending)
+                launch_mixed_correct(cur, H.xr(0), H.xb(0), half, nl, C.st);
+            H.cur[0][0] = H.cur[0][1] = 0;
+        }
         // (its final stage also sets the lagged means for the next outer
         // residual and the FP32 level 0)
-        launch_mixed_outer_residual(F64, master, master + half, C.csum64, H.L[0], H.xr(0), H.xb(0), ro, sc, nl, C.st,
-                                    H.tiled, C.csum64, H.csum_cur(0));
+        if (!launch_mixed_outer_residual(F64, cur, cur + half, C.csum64, H.L[0], H.xr(0), H.xb(0), ro, sc, nl, C.st,
+                                         H.tiled, C.csum64, H.csum_cur(0), fused ? &mc : nullptr))
+            return PM_EINVAL;
+        if (fused)
+            std::swap(cur, alt);
+        pending = false;
         H.fresh(0);
         e = read_group(C, G, C.outer_out, out.data(), 4);
         if (e)
@@ -869,6 +902,7 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
             r.mean_shift = q[2] / (double)N;
             r.clamped = (long long)q[3];
             r.vcycles = cyc;
+            bool leaves = true;  // the slot's FP32 phase ends here
             if (!isfinite(rel)) {
                 r.status = PM_ENONFINITE;
             } else if (rel <= o.rel_tol) {
@@ -884,7 +918,10 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
                 rel_last = rel;
                 prev[s] = rel;
                 next.push_back(s);
+                leaves = false;
             }
+            if (leaves && (e = to_master(s)))
+                return e;
         }
         G.active = next;
         if (G.active.empty())
@@ -909,7 +946,7 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
             else
                 vcycle_from<float>(C, H, 0, o, sc32, nl);
         }
-        launch_mixed_correct(master, H.xr(0), H.xb(0), H.L[0].x0r, H.L[0].x0b, half, C.st);
+        pending = true;
     }
     e = launched();
     if (e || to_f64.empty())

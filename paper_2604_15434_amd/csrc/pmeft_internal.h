@@ -114,10 +114,6 @@ struct LevelView {
     R *x0r, *x0b;       // restricted fine iterate (coarse levels)
 };
 
-// Reduction scratch inside the workspace: every block of a reducing kernel
-// writes its partial sums (8 slots per block); a one-block finalize kernel
-// launched right after adds them in block order (deterministic, and no
-// device-scope fence inside the reducing kernel).
 // Weight packing jobs of the learned warm start's network, run in one launch:
 // kind 0 convolution (a = cin_pad, b = cout_pad, d0 forward and d1 input-
 // gradient layout or null), 1 polyphase (a = coarse channels, b = cout_pad),
@@ -136,10 +132,25 @@ struct PackJobs {
 };
 void launch_pack_jobs(const PackJobs &jobs, hipStream_t st);
 
+// Reduction scratch inside the workspace: every block of a reducing kernel
+// writes its partial sums (8 slots per block); a one-block finalize kernel
+// launched right after adds them in block order (deterministic, and no
+// device-scope fence inside the reducing kernel).
 struct ReduceSlot {
     double *partials;   // kMaxBlocks * 8
     unsigned *counter;  // unused (kept zero)
     double *out;        // finalised sums
+};
+
+// A pending mixed-precision correction of the FP64 iterate x64 by the FP32
+// level-0 iterate v of the last V-cycles: x64 += fl32(v - fl32(x64)) for the
+// nonlinear (full-approximation) form, x64 += v for the linear correction
+// form.  The tiled outer residual applies it to every value it loads and
+// writes the corrected iterate of its own cells to yr / yb (not the arrays
+// it reads: neighbouring tiles still read the old values).
+struct MixedCorr {
+    const float *vr = nullptr, *vb = nullptr;
+    double *yr = nullptr, *yb = nullptr;
 };
 
 // Grouped launches.  Problems of one shape solved together sit in workspace
@@ -291,7 +302,10 @@ bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, Reduc
                           bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out);
 bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                               const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs, SolveConsts sc,
-                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out);
+                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr);
+// Whether the mixed outer residual of a level of n cells per side runs tiled
+// (and can therefore take a pending correction).
+bool mixed_outer_tiles(int n, int tiled);
 
 // Fine x += P (x_H - x0_H), trilinear cell-centred prolongation.
 template <typename R>
@@ -328,20 +342,24 @@ void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int 
                               hipStream_t st);
 
 // Mixed precision outer step: FP64 residual of (x64, delta64) with norm
-// partials, cast x32 = fl(x64) (into level-0 x and x0) and the FP32 FAS
-// target tau32 = fl(r64) + lap32 x32 - Lq32(x32); per-colour sums of
-// Lq32 + tau32 into csum32.
+// partials, cast x32 = fl(x64) into the level-0 x (0 for the linear
+// correction form) and the FP32 FAS target tau32 = fl(r64) + lap32 x32 -
+// Lq32(x32); per-colour sums of Lq32 + tau32 into csum32.
 // The six sums go to rs.out; with lag64 / lag32 set, the same final stage
 // also writes the next lagged means: lag64[0] = out[2], lag64[1] = 0,
 // lag32[0..1] = out[4..5] (lag64 may be csum64: the residual kernel has
-// read it by then).
-void launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
+// read it by then).  With corr set (tiled levels only, see
+// mixed_outer_tiles) the residual is that of the corrected iterate, which
+// goes to corr->yr / yb; returns false, launching nothing, where corr is set
+// and the level does not tile.
+bool launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
                                  const double *csum64, const LevelView<float> &F32, float *x32r, float *x32b,
                                  ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st, int tiled = 0,
-                                 double *lag64 = nullptr, double *lag32 = nullptr);
-// x64 += x32 - x0_32
-void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, const float *x0r, const float *x0b,
-                          long long half, hipStream_t st);
+                                 double *lag64 = nullptr, double *lag32 = nullptr, const MixedCorr *corr = nullptr);
+// The correction of MixedCorr applied on its own: x64 += fl32(x32 - fl32(x64))
+// (nonlinear) or x64 += x32 (linear).
+void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, long long half, bool nonlinear,
+                          hipStream_t st);
 
 // Plain FP64 residual norm (no restriction) of the finest level.
 void launch_residual_norm(const LevelView<double> &F, const double *xr, const double *xb, const double *csum,

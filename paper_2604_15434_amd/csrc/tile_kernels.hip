@@ -263,16 +263,19 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
 
 // ---------------------------------------------------- mixed-precision outer
 // As k_mixed_outer: FP64 residual of the FP64 iterate (norm partials in
-// acc[0..3]), x32 = fl(x64) into the FP32 level's x and x0, and the FP32
-// target tau32 = fl(r) + lap32 x32 - Lq32(x32) (nonlinear) or tau32 = fl(r)
-// with x32 = x0 = 0 (linear); acc[4 + colour] += Lq32 + tau32.
-template <bool NL, int TK, int PL>
+// acc[0..3]), x32 = fl(x64) into the FP32 level's x, and the FP32 target
+// tau32 = fl(r) + lap32 x32 - Lq32(x32) (nonlinear) or tau32 = fl(r) with
+// x32 = 0 (linear); acc[4 + colour] += Lq32 + tau32.  CORR: the iterate is
+// first corrected by the FP32 result of the previous V-cycles (MixedCorr),
+// value by value as the window loads it, with k_mixed_correct's arithmetic;
+// the corrected values of the tile's own cells go to cr.yr / cr.yb.
+template <bool NL, int TK, int PL, bool CORR>
 __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F, const double *__restrict__ xr,
                                                              const double *__restrict__ xb,
                                                              const double *__restrict__ csum64, LevelView<float> G,
                                                              float *__restrict__ x32r, float *__restrict__ x32b,
                                                              ReduceSlot rs, SolveConsts sc, Span sp, unsigned ntiles,
-                                                             Group grp)
+                                                             MixedCorr cr, Group grp)
 {
     const long long go = group_offset(grp);
     gshift_view(F, go);
@@ -282,6 +285,10 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
     csum64 = gshift(csum64, go);
     x32r = gshift(x32r, go);
     x32b = gshift(x32b, go);
+    cr.vr = gshift(cr.vr, go);
+    cr.vb = gshift(cr.vb, go);
+    cr.yr = gshift(cr.yr, go);
+    cr.yb = gshift(cr.yb, go);
     gshift_slot(rs, go);
     gconsts(sc, grp);
     constexpr int TJ = 2 * kBlock / TK;
@@ -292,39 +299,74 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
     const float ih2f = (float)ih2;
     const int tp = threadIdx.x / TK, tk = threadIdx.x % TK;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    PlaneRing<double, TK, TJ> ring;
+    using Ring = PlaneRing<double, TK, TJ>;
+    Ring ring;
+    // CORR: the FP32 values of this thread's window elements (same offsets as
+    // the ring's), loaded with them and folded in just before the LDS store
+    const float *vsrc[Ring::PER];
+    float vpre[Ring::PER];
+    auto fetch = [&](int ii) {
+        ring.fetch(ii);
+        if constexpr (CORR) {
+            const int iw = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
+            const unsigned base = (unsigned)iw * ring.plane;
+#pragma unroll
+            for (int u = 0; u < Ring::PER; u++)
+                if (u < Ring::FULL || threadIdx.x + u * kBlock < 2 * Ring::W)
+                    vpre[u] = vsrc[u][base + ring.poff[u]];
+        }
+    };
+    auto store = [&](int slot) {
+        if constexpr (CORR) {
+#pragma unroll
+            for (int u = 0; u < Ring::PER; u++)
+                if (u < Ring::FULL || threadIdx.x + u * kBlock < 2 * Ring::W) {
+                    const double x = ring.pre[u];
+                    const float d = NL ? vpre[u] - (float)x : vpre[u];
+                    ring.pre[u] = x + (double)d;
+                }
+        }
+        ring.store(win, slot);
+    };
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
         int ib, kb, jb;
         tile_coords(tile, nI, nK, ib, kb, jb);
         const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
         ring.setup(xr, xb, n, nh, j0, k0);
-        ring.prime(win, i0);
+        if constexpr (CORR) {
+#pragma unroll
+            for (int u = 0; u < Ring::PER; u++) {
+                const int q = threadIdx.x + u * kBlock;
+                vsrc[u] = (q < 2 * Ring::W ? q : 0) < Ring::W ? cr.vr : cr.vb;
+            }
+        }
+        fetch(i0 - 1);
+        store(0);
+        fetch(i0);
+        store(1);
+        fetch(i0 + 1);
+        store(2);
         const unsigned e00 = ((unsigned)i0 * n + j0 + 2 * tp) * nh + k0 + tk;
+        // (the FP32 level's delta is fl32 of the FP64 one: rounded here
+        // instead of loaded)
         double dcur[2][2], dnxt[2][2];
-        float fcur[2][2], fnxt[2][2];
 #pragma unroll
         for (int b = 0; b < 2; b++)
 #pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const unsigned e = e00 + b * nh;
-                dcur[b][c] = (c ? F.db : F.dr)[e];
-                fcur[b][c] = NL ? (c ? G.db : G.dr)[e] : 0.0f;
-            }
+            for (int c = 0; c < 2; c++)
+                dcur[b][c] = (c ? F.db : F.dr)[e00 + b * nh];
         __syncthreads();
 #pragma unroll 1
         for (int t = 0; t < PL; t++) {
             const int i = i0 + t;
             const int sm = t & 3, s0 = (t + 1) & 3, sp1 = (t + 2) & 3;
             if (t + 1 < PL) {
-                ring.fetch(i + 2);
+                fetch(i + 2);
 #pragma unroll
                 for (int b = 0; b < 2; b++)
 #pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        const unsigned e = e00 + (unsigned)(t + 1) * ring.plane + b * nh;
-                        dnxt[b][c] = (c ? F.db : F.dr)[e];
-                        fnxt[b][c] = NL ? (c ? G.db : G.dr)[e] : 0.0f;
-                    }
+                    for (int c = 0; c < 2; c++)
+                        dnxt[b][c] = (c ? F.db : F.dr)[e00 + (unsigned)(t + 1) * ring.plane + b * nh];
             }
 #pragma unroll
             for (int b = 0; b < 2; b++) {
@@ -336,6 +378,8 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                     double tsh;
                     const double S = ring_stencil<double, double, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, NL, tsh);
                     const double x64 = win[c][s0][a][tk + 1];
+                    if constexpr (CORR)
+                        (c ? cr.yb : cr.yr)[e] = x64;
                     int isv;
                     const double lq = root_lap<double>(sc.beta * dcur[b][c], tsh * ih2 * ih2, sc, NL, isv);
                     const double r = lq - cm - (S - 6.0 * x64) * ih2;
@@ -345,7 +389,6 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                     acc[3] += (double)isv;
                     if (!NL) {
                         (c ? x32b : x32r)[e] = 0.0f;
-                        (c ? G.x0b : G.x0r)[e] = 0.0f;
                         (c ? G.tb : G.tr)[e] = (float)r;
                         acc[4 + c] += (double)(float)r;
                     } else {
@@ -355,25 +398,22 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                         const float x32 = (float)x64;
                         int isv32;
                         const float lq32 =
-                            root_lap<float>((float)sc.beta * fcur[b][c], tsh32 * ih2f * ih2f, sc, true, isv32);
+                            root_lap<float>((float)sc.beta * (float)dcur[b][c], tsh32 * ih2f * ih2f, sc, true, isv32);
                         const float lap32 = (S32 - 6.0f * x32) * ih2f;
                         const float tau32 = (float)r + lap32 - lq32;
                         (c ? x32b : x32r)[e] = x32;
-                        (c ? G.x0b : G.x0r)[e] = x32;
                         (c ? G.tb : G.tr)[e] = tau32;
                         acc[4 + c] += (double)(lq32 + tau32);
                     }
                 }
             }
             if (t + 1 < PL) {
-                ring.store(win, (t + 3) & 3);
+                store((t + 3) & 3);
 #pragma unroll
                 for (int b = 0; b < 2; b++)
 #pragma unroll
-                    for (int c = 0; c < 2; c++) {
+                    for (int c = 0; c < 2; c++)
                         dcur[b][c] = dnxt[b][c];
-                        fcur[b][c] = fnxt[b][c];
-                    }
             }
             __syncthreads();
         }
@@ -562,24 +602,37 @@ bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, Reduc
     return true;
 }
 
+bool mixed_outer_tiles(int n, int tiled)
+{
+    PairTiles g;
+    return pair_tiles(n, tiled, g);
+}
+
 bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                               const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs, SolveConsts sc,
-                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out)
+                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr)
 {
     PairTiles g;
     if (!pair_tiles(F64.n, tiled, g))
         return false;
+    const MixedCorr cr = corr ? *corr : MixedCorr{};
+#define PM_MO1(NLV, TKV, PLV, CV)                                                                                      \
+    hipLaunchKernelGGL((k_mixed_outer_tile<NLV, TKV, PLV, CV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, F64,   \
+                       xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cr, cur_group())
 #define PM_MO(TKV, PLV)                                                                                                \
     do {                                                                                                               \
-        if (nonlinear)                                                                                                 \
-            hipLaunchKernelGGL((k_mixed_outer_tile<true, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st,    \
-                               F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cur_group());             \
+        if (nonlinear && corr)                                                                                         \
+            PM_MO1(true, TKV, PLV, true);                                                                              \
+        else if (nonlinear)                                                                                            \
+            PM_MO1(true, TKV, PLV, false);                                                                             \
+        else if (corr)                                                                                                 \
+            PM_MO1(false, TKV, PLV, true);                                                                             \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_mixed_outer_tile<false, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st,   \
-                               F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cur_group());             \
+            PM_MO1(false, TKV, PLV, false);                                                                            \
     } while (0)
     PM_PAIR_DISPATCH(PM_MO)
 #undef PM_MO
+#undef PM_MO1
     *sp_out = g.sp;
     return true;
 }
