@@ -716,9 +716,12 @@ static int slot_copy(Ctx &C, const GroupRun &G, int s, void *dst, const void *sr
 
 // FP64 solve of one field held packed in `master` (initial guess in, solution
 // out), for every active slot of G.  src_norm[s] = ||beta delta / nu||_2 of
-// slot s; limit[s]: its V-cycle budget (null: o.max_vcycles).
+// slot s; limit[s]: its V-cycle budget (null: o.max_vcycles).  mean_set: the
+// fine level's lagged mean already holds the exact mean of Lq of the guess
+// (the mixed solve's last outer step wrote it), so it is not evaluated again.
 static int solve_f64(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o,
-                     const double *src_norm, SolveOut *so, bool zero_start, const int *limit = nullptr)
+                     const double *src_norm, SolveOut *so, bool zero_start, const int *limit = nullptr,
+                     bool mean_set = false)
 {
     int e = group_bind(G);
     if (e)
@@ -734,7 +737,8 @@ static int solve_f64(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool n
         fmg = 1;
     } else {
         // exact mean of Lq on the fine level for the first half-sweep
-        launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st, H.tiled);
+        if (!mean_set)
+            launch_fas_tau<double>(H.L[0], H.xr(0), H.xb(0), H.csum_cur(0), C.rs, sc, nl, true, C.st, H.tiled);
         H.fresh(0);
     }
     std::vector<double> out(4 * (size_t)G.m);
@@ -958,7 +962,7 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
     for (int s : to_f64)
         limit[s] = o.max_vcycles - cyc_of[s];
     G.active = to_f64;
-    e = solve_f64(C, G, master, sc, nl, o, src_norm, s64.data(), false, limit.data());
+    e = solve_f64(C, G, master, sc, nl, o, src_norm, s64.data(), false, limit.data(), true);
     if (e)
         return e;
     for (int s : to_f64) {

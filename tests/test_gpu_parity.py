@@ -668,6 +668,37 @@ def test_grouped_batch_equals_single_solves_bitwise(P, precision, guess):
     assert float(probs[2]["chi"].abs().max()) == 0.0  # no scalar source
 
 
+def test_grouped_batch_256_mixed_equals_single_solves_bitwise(P):
+    """From 256^3 up the mixed solve applies each FP32 correction inside the
+    next outer residual and writes the corrected FP64 iterate to the level's
+    second buffer, so a member's field sits in either buffer when it leaves
+    the FP32 phase (converged, or switching to FP64) and is copied back per
+    slot.  Members that leave after different numbers of outer steps (and a
+    linear member, screening off) each equal their own single solve bit for
+    bit, with the same report."""
+    from workloads import lognormal_density
+
+    pars = [(-0.2, 0.0, 1), (-0.6, 0.1, 1), (-0.05, 0.0, 1), (-0.4, 0.0, 0)]
+    probs = []
+    for k, (ab, am, scr) in enumerate(pars):
+        rho = torch.from_numpy(lognormal_density(256, 500.0, seed=5200 + k)).to("cuda", torch.float32)
+        probs.append(dict(rho=rho, chi=torch.zeros_like(rho),
+                          params=dict(omega_m0=0.3071, alpha_b0=ab, alpha_m0=am, a=1.0, screening=scr)))
+    opts = P.MgOpts(rel_tol=1e-9, max_vcycles=60, precision="mixed", guess="zero")
+    reps = P.mg_scalar_solve_batched(probs, opts)
+    hists = set()
+    for k, pr in enumerate(probs):
+        single = torch.zeros_like(pr["rho"])
+        rep = P.mg_scalar_solve(pr["rho"], pr["params"], opts, single)
+        assert rep["status"] == 0, (k, rep["status"])
+        assert torch.equal(single, pr["chi"]), k
+        for key in ("status", "vcycles", "rel_residual", "clamped_cells", "mean_shift"):
+            assert reps[k][key] == rep[key], (k, key)
+        assert reps[k]["residual_hist"] == rep["residual_hist"], k
+        hists.add(len(rep["residual_hist"]))
+    assert len(hists) >= 2  # the members left the FP32 phase at different outer steps
+
+
 def test_batched_rejects_learned_and_bad_sizes(P):
     rho = torch.ones((32, 32, 32), dtype=torch.float64, device="cuda")
     prm = dict(omega_m0=0.3071, alpha_b0=-0.2, alpha_m0=0.0, a=1.0)
