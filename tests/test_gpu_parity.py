@@ -628,6 +628,36 @@ def test_batched_equals_single_solves_bitwise(P):
         assert rel(got, ref) < 1e-5, n
 
 
+def test_scan_192_members_equal_single_solves_and_the_oracle(P):
+    """The 192^3 group of the parameter scan (levels down to a 6^3 coarsest
+    grid): two members with the scan's parameter draws equal their single
+    solves bit for bit, and the first agrees with the oracle (mixed
+    precision at 1e-9: chi within 1e-5 relative)."""
+    import oracle
+    from workloads import lognormal_density, scan_params
+
+    n = 192
+    prms = scan_params(2, seed=9, a=1.0)
+    probs = [dict(rho=torch.from_numpy(lognormal_density(n, 500.0 * n / 256, seed=4900 + k)).to("cuda", torch.float32),
+                  chi=torch.zeros((n, n, n), dtype=torch.float32, device="cuda"), params=prm)
+             for k, prm in enumerate(prms)]
+    opts = P.MgOpts(rel_tol=1e-9, max_vcycles=60, precision="mixed")
+    reps = P.mg_scalar_solve_batched(probs, opts)
+    for k, pr in enumerate(probs):
+        single = torch.zeros_like(pr["chi"])
+        rep = P.mg_scalar_solve(pr["rho"], pr["params"], opts, single)
+        assert rep["status"] == 0 and reps[k]["status"] == 0, k
+        assert torch.equal(single, pr["chi"]), k
+        assert reps[k]["vcycles"] == rep["vcycles"] and reps[k]["rel_residual"] == rep["rel_residual"], k
+    pr = probs[0]
+    c = oracle.eft_coefficients(**pr["params"])
+    ref, _ = oracle.solve_chi(oracle.density_contrast(pr["rho"].cpu().numpy().astype(np.float64)), c, 1.0 / n,
+                              tol=1e-10)
+    err = rel(_mean_free(pr["chi"].cpu().numpy().astype(np.float64)), ref)
+    print(f"scan 192^3 member vs oracle: chi rel err {err:.2e}")
+    assert err < 1e-5
+
+
 @pytest.mark.parametrize("precision,guess", [("mixed", "zero"), ("f64", "zero"), ("mixed", "linear"),
                                              ("mixed", "given")])
 def test_grouped_batch_equals_single_solves_bitwise(P, precision, guess):
