@@ -1850,22 +1850,32 @@ int side_stream(SideStream **out)
 // change; the latency-bound coarse levels of one overlap the other's large
 // levels.
 // Also writes psi_out (natural order, mean removed) right after the Poisson
-// solve, while the scalar solve still runs.
+// solve, while the scalar solve still runs, and chi_out on the side stream
+// right after the scalar solve: the caller's stream then waits only for the
+// solve itself (its force pass overlaps the conversion) and gets *conv, an
+// event after the conversion, to wait on before it ends (null: the
+// conversion was not issued, and the caller converts).
 // forward_done: the warm start's forward pass is already on the side stream.
 static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, const pm_mg_opts &po,
-                      const pm_mg_opts &so, double dsq, void *psi_out, pm_dtype dtype, SolveOut &sp, SolveOut &sx,
-                      float &ms_p, float &ms_x, bool forward_done)
+                      const pm_mg_opts &so, double dsq, void *psi_out, void *chi_out, pm_dtype dtype, SolveOut &sp,
+                      SolveOut &sx, float &ms_p, float &ms_x, bool forward_done, hipEvent_t *conv)
 {
+    *conv = nullptr;
     SideStream *S = nullptr;
     int e = side_stream(&S);
     if (e)
         return e;
     int dev = 0;
     PM_HIP(hipGetDevice(&dev));
-    hipEvent_t ready = nullptr, done = nullptr;
+    hipEvent_t ready = nullptr, done = nullptr, cdone = nullptr;
     PM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
         (void)hipEventDestroy(ready);
+        return PM_EHIP;
+    }
+    if (hipEventCreateWithFlags(&cdone, hipEventDisableTiming) != hipSuccess) {
+        (void)hipEventDestroy(ready);
+        (void)hipEventDestroy(done);
         return PM_EHIP;
     }
     Ctx C1 = C;
@@ -1880,6 +1890,7 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
     }
     bind_solve(C1);
     int ex = PM_OK;
+    bool converted = false;  // chi_out issued on the side stream, done recorded before it
     auto scalar_job = [&]() {
         if (hipSetDevice(dev) != hipSuccess) {
             ex = PM_EHIP;
@@ -1887,8 +1898,20 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
         }
         Timer tx(C1.st);
         ex = scalar_core(C1, p, cf, so, sx, dsq, forward_done, true);
+        if (ex)
+            return;
+        ms_x = tx.stop();
+        if (hipEventRecord(done, C1.st) != hipSuccess) {
+            ex = PM_EHIP;
+            return;
+        }
+        double *ch = C1.at<double>(C1.P.chi64);
+        launch_field_sum(ch, C1.P.N, C1.rs, C1.st);
+        launch_packed_to_natural(ch, chi_out, dtype, C1.P.ng, 0.0, C1.rs.out, C1.st);
+        ex = launched();
         if (!ex)
-            ms_x = tx.stop();
+            ex = hipEventRecord(cdone, C1.st) == hipSuccess ? PM_OK : PM_EHIP;
+        converted = !ex;
     };
     std::thread worker;
     bool threaded = true;
@@ -1912,14 +1935,25 @@ static int solve_both(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf, c
     }
     if (threaded)
         worker.join();
-    // on every path: the caller's stream waits for the scalar solve's work
-    const bool waited = hipEventRecord(done, C1.st) == hipSuccess && hipStreamWaitEvent(C.st, done, 0) == hipSuccess;
-    (void)hipEventDestroy(ready);
-    (void)hipEventDestroy(done);
+    // on every path the caller's stream waits for the scalar solve's work:
+    // for the solve now and the conversion through *conv, or (the conversion
+    // not issued) for everything now
+    bool waited = (converted || hipEventRecord(done, C1.st) == hipSuccess) &&
+                  hipStreamWaitEvent(C.st, done, 0) == hipSuccess;
     if (!e)
         e = ex;
     if (!e && !waited)
         e = PM_EHIP;
+    if (converted) {
+        if (!e)
+            *conv = cdone;  // the caller waits on it after its force pass
+        else                // an error: the caller's stream covers the conversion now
+            (void)hipStreamWaitEvent(C.st, cdone, 0);
+    }
+    if (!*conv)
+        (void)hipEventDestroy(cdone);
+    (void)hipEventDestroy(ready);
+    (void)hipEventDestroy(done);
     return e;
 }
 
@@ -2021,6 +2055,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         launch_natural_to_packed(chi, dtype, ch, ng, 1.0, 0.0, C.st);
     SolveOut sp, sx;
     float ms_p = 0.0f, ms_x = 0.0f;
+    hipEvent_t conv = nullptr;  // chi's conversion issued on the side stream (solve_both)
     if (cf.K == 0.0) {
         // Linearised option (screening off) or no scalar field: chi obeys
         // nu lap chi = xi s delta with the same 7-point Laplacian as Psi_N,
@@ -2057,7 +2092,7 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
         if (!e)
             ms_x = tx.stop();
     } else {
-        e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, dtype, sp, sx, ms_p, ms_x, fwd);
+        e = solve_both(C, *p, cf, *poisson_opts, *scalar_opts, dsq, psi, chi, dtype, sp, sx, ms_p, ms_x, fwd, &conv);
     }
     if (e) {
         wait_network();  // (solve_both waits itself once its worker has started)
@@ -2068,8 +2103,15 @@ int pm_step(void *pos, void *vel, long long np, int ng, pm_dtype dtype, const pm
     launch_gradient(ps, ch, cf.xi, ng, g4, dtype, C.st);
     launch_interp_kick(g4, ng, dtype, pos, np, vel, dt_kick, dt_drift, nullptr, C.st);
     tf.mark();
-    launch_field_sum(ch, C.P.N, C.rs, C.st);
-    launch_packed_to_natural(ch, chi, dtype, ng, 0.0, C.rs.out, C.st);
+    if (conv) {  // chi was converted on the side stream beside the force pass
+        const bool w = hipStreamWaitEvent(C.st, conv, 0) == hipSuccess;
+        (void)hipEventDestroy(conv);
+        if (!w)
+            return PM_EHIP;
+    } else {
+        launch_field_sum(ch, C.P.N, C.rs, C.st);
+        launch_packed_to_natural(ch, chi, dtype, ng, 0.0, C.rs.out, C.st);
+    }
     e = launched();
     if (e)
         return e;
