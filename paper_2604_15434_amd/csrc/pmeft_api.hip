@@ -854,7 +854,9 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
     double *cur = master, *alt = C.at<double>(C.P.q64[0]);
     const bool fuse = (C.P.precs & kPrecF64) && C.P.n[0] >= 256 && mixed_outer_tiles(C.P.n[0], H.tiled);
     bool pending = false;
-    auto to_master = [&](int s) { return cur == master ? PM_OK : slot_copy(C, G, s, master, cur, sizeof(double) * 2 * half); };
+    auto to_master = [&](int s) {
+        return cur == master ? PM_OK : slot_copy(C, G, s, master, cur, sizeof(double) * 2 * half);
+    };
     for (int it = 0;; it++) {
         if (!final_residual && it > 0 && cyc >= o.max_vcycles) {
             if (pending)
