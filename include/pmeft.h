@@ -330,12 +330,15 @@ int pm_sort_particles(void *pos, void *vel, long long *ids, long long np, int ng
  * iterating (grid rows select the member), so small grids fill the GPU
  * together; a member leaves at its own convergence test, and the mixed-
  * precision members that finish in FP64 do so together.  Members with
- * screening off (linear) are solved one after another.  Groups run largest
- * grid first, all on `stream` (no host threads); the call returns when every
- * problem is solved (all output arrays complete).  opts apply to every
- * problem (PM_GUESS_LEARNED is not accepted here).  Workspace
- * (mg_batched_workspace_bytes, 256-byte aligned): the largest group's
- * members' solver workspaces side by side, plus a small control area.
+ * screening off (linear) are solved one after another.  The largest grid's
+ * group runs on `stream`; the other groups, one after another, run beside it
+ * from a library worker thread on the library's second stream (the one
+ * pm_step uses), ordered by events after the work already on `stream`, and
+ * `stream` waits for them before anything enqueued after the call.  The call
+ * returns when every problem is solved (all output arrays complete).  opts
+ * apply to every problem (PM_GUESS_LEARNED is not accepted here).  Workspace
+ * (mg_batched_workspace_bytes, 256-byte aligned): every group's members'
+ * solver workspaces side by side, each group with a small control area.
  * Returns PM_OK, PM_ENOCONV if some problem stopped at max_vcycles, or the
  * first hard error; reps (HOST, nprob entries, nullable) receive the
  * per-problem reports (ms: the time of the problem's group). */

@@ -1379,11 +1379,40 @@ int ws_unet_guess(const float *params, const void *rho, int ng, pm_dtype dtype, 
 }
 
 // ---- grouped batched solves ----------------------------------------------
+// The library's second stream (one per device, created on first use, default
+// priority, non-blocking): pm_step runs its scalar-field solve on it while the
+// Poisson solve runs on the caller's stream, and a batched solve its smaller
+// grids' groups beside the largest.  Overlapping calls on one device share
+// it, which stays correct (each call orders its work with events of its own)
+// but serialises their work on it.
+namespace {
+struct SideStream {
+    hipStream_t s = nullptr;
+};
+std::mutex g_side_mu;
+SideStream g_side[64];
+
+int side_stream(SideStream **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return PM_EHIP;
+    std::lock_guard<std::mutex> g(g_side_mu);
+    SideStream &S = g_side[dev];
+    if (!S.s && hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
+        return PM_EHIP;
+    *out = &S;
+    return PM_OK;
+}
+}  // namespace
+
 // The problems are grouped by (grid, dtype of their arrays), largest grid
 // first, and each group is solved in lockstep: one launch per kernel of the
 // solve covers every problem of the group still iterating (Group), each in
-// its own workspace slot.  The groups run one after another on the caller's
-// stream and share one region of the workspace.
+// its own workspace slot.  The largest group runs on the caller's stream;
+// the others, one after another, beside it on the library's second stream
+// (their latency-bound small grids fill the large group's gaps).  Each group
+// has its own region and control area of the workspace.
 namespace {
 struct BatchGroup {
     int ng = 0;
@@ -1422,15 +1451,17 @@ bool batch_groups(const pm_problem *probs, int nprob, int precision, std::vector
     return true;
 }
 
-size_t batch_region_bytes(const std::vector<BatchGroup> &gs)
-{
-    size_t r = 0;
-    for (const auto &g : gs)
-        r = std::max(r, g.slice * g.idx.size());
-    return r;
-}
-
 size_t batch_ctl_bytes(int nprob) { return ((size_t)nprob * kBatchCtlPerSlot + 4 * 256 + 255) & ~(size_t)255; }
+
+// Workspace layout of a batch: group k's region (slots) then its control
+// area, groups one after another; off[k] is group k's region offset and
+// off[gs.size()] the total.
+void batch_layout(const std::vector<BatchGroup> &gs, std::vector<size_t> &off)
+{
+    off.assign(gs.size() + 1, 0);
+    for (size_t k = 0; k < gs.size(); k++)
+        off[k + 1] = off[k] + gs[k].slice * gs[k].idx.size() + batch_ctl_bytes((int)gs[k].idx.size());
+}
 
 struct GroupReset {
     ~GroupReset() { set_cur_group(Group()); }
@@ -1609,7 +1640,9 @@ size_t mg_batched_workspace_bytes(const pm_problem *probs, int nprob, int precis
     std::vector<BatchGroup> gs;
     if (!batch_groups(probs, nprob, precision, gs))
         return 0;
-    return batch_region_bytes(gs) + batch_ctl_bytes(nprob);
+    std::vector<size_t> off;
+    batch_layout(gs, off);
+    return off.back();
 }
 
 int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts *opts, pm_mg_report *reps, void *ws,
@@ -1628,17 +1661,71 @@ int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts
     std::vector<BatchGroup> gs;
     if (!batch_groups(probs, nprob, opts->precision, gs))
         return PM_EINVAL;
-    char *region = (char *)ws;
-    char *ctl = region + batch_region_bytes(gs);
-    std::vector<int> codes(nprob, PM_OK);
+    std::vector<size_t> off;
+    batch_layout(gs, off);
+    std::vector<int> codes(nprob, PM_OK);  // (the groups write disjoint entries)
+    auto run = [&](size_t k, hipStream_t st) {
+        char *region = (char *)ws + off[k];
+        return solve_group(probs, gs[k], *opts, reps, codes, region, region + gs[k].slice * gs[k].idx.size(), st);
+    };
     if (reps)
         for (int i = 0; i < nprob; i++)
             memset(&reps[i], 0, sizeof(reps[i]));
-    for (const auto &g : gs) {
-        const int e = solve_group(probs, g, *opts, reps, codes, region, ctl, (hipStream_t)stream);
-        if (e)
+    int e = PM_OK;
+    if (gs.size() == 1) {
+        e = run(0, (hipStream_t)stream);
+    } else {
+        // the smaller groups on the second stream, in a worker thread (each
+        // group reads back its norms from the host between its steps)
+        SideStream *S = nullptr;
+        if ((e = side_stream(&S)))
             return e;
+        int dev = 0;
+        PM_HIP(hipGetDevice(&dev));
+        hipEvent_t ready = nullptr, done = nullptr;
+        PM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(ready);
+            return PM_EHIP;
+        }
+        if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess || hipStreamWaitEvent(S->s, ready, 0) != hipSuccess) {
+            (void)hipEventDestroy(ready);
+            (void)hipEventDestroy(done);
+            return PM_EHIP;
+        }
+        int ex = PM_OK;
+        auto rest = [&]() {
+            if (hipSetDevice(dev) != hipSuccess) {
+                ex = PM_EHIP;
+                return;
+            }
+            for (size_t k = 1; k < gs.size() && !ex; k++)
+                ex = run(k, S->s);
+        };
+        std::thread worker;
+        bool threaded = true;
+        try {
+            worker = std::thread(rest);
+        } catch (...) {  // no thread: the same work from this thread, after the largest group's
+            threaded = false;
+        }
+        e = run(0, (hipStream_t)stream);
+        if (threaded)
+            worker.join();
+        else
+            rest();
+        // on every path the caller's stream waits for the second stream's work
+        const bool waited =
+            hipEventRecord(done, S->s) == hipSuccess && hipStreamWaitEvent((hipStream_t)stream, done, 0) == hipSuccess;
+        (void)hipEventDestroy(ready);
+        (void)hipEventDestroy(done);
+        if (!e)
+            e = ex;
+        if (!e && !waited)
+            e = PM_EHIP;
     }
+    if (e)
+        return e;
     int rc = PM_OK;
     for (int i = 0; i < nprob; i++) {
         if (codes[i] != PM_OK && codes[i] != PM_ENOCONV && (rc == PM_OK || rc == PM_ENOCONV))
@@ -1817,31 +1904,6 @@ int pm_force_interp(const void *psi, const void *chi, int ng, pm_dtype dtype, co
     return launched();
 }
 
-// The library's second stream (one per device, created on first use, default
-// priority, non-blocking): pm_step runs its scalar-field solve on it while the
-// Poisson solve runs on the caller's stream.  Overlapping pm_step calls on one
-// device share it, which stays correct (each call orders its work with events
-// of its own) but serialises their scalar solves.
-namespace {
-struct SideStream {
-    hipStream_t s = nullptr;
-};
-std::mutex g_side_mu;
-SideStream g_side[64];
-
-int side_stream(SideStream **out)
-{
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-        return PM_EHIP;
-    std::lock_guard<std::mutex> g(g_side_mu);
-    SideStream &S = g_side[dev];
-    if (!S.s && hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
-        return PM_EHIP;
-    *out = &S;
-    return PM_OK;
-}
-}  // namespace
 
 // The Poisson and scalar-field solves of a step depend on delta only, so they
 // run side by side: the scalar field (after the warm start's network and
