@@ -331,10 +331,11 @@ int pm_sort_particles(void *pos, void *vel, long long *ids, long long np, int ng
  * together; a member leaves at its own convergence test, and the mixed-
  * precision members that finish in FP64 do so together.  Members with
  * screening off (linear) are solved one after another.  The largest grid's
- * group runs on `stream`; the other groups, one after another, run beside it
- * from a library worker thread on the library's second stream (the one
- * pm_step uses), ordered by events after the work already on `stream`, and
- * `stream` waits for them before anything enqueued after the call.  The call
+ * group runs on `stream`; beside it, from library worker threads, the second
+ * largest on the library's second stream (the one pm_step uses) and the
+ * others, one after another, on a third library stream, ordered by events
+ * after the work already on `stream`; `stream` waits for them before
+ * anything enqueued after the call.  The call
  * returns when every problem is solved (all output arrays complete).  opts
  * apply to every problem (PM_GUESS_LEARNED is not accepted here).  Workspace
  * (mg_batched_workspace_bytes, 256-byte aligned): every group's members'

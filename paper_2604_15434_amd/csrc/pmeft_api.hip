@@ -1390,15 +1390,16 @@ struct SideStream {
     hipStream_t s = nullptr;
 };
 std::mutex g_side_mu;
-SideStream g_side[64];
+SideStream g_side[64][2];
 
-int side_stream(SideStream **out)
+// which: 0 the second stream, 1 a third one (batched solves only)
+int side_stream(SideStream **out, int which = 0)
 {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || which < 0 || which > 1)
         return PM_EHIP;
     std::lock_guard<std::mutex> g(g_side_mu);
-    SideStream &S = g_side[dev];
+    SideStream &S = g_side[dev][which];
     if (!S.s && hipStreamCreateWithFlags(&S.s, hipStreamNonBlocking) != hipSuccess)
         return PM_EHIP;
     *out = &S;
@@ -1410,9 +1411,10 @@ int side_stream(SideStream **out)
 // first, and each group is solved in lockstep: one launch per kernel of the
 // solve covers every problem of the group still iterating (Group), each in
 // its own workspace slot.  The largest group runs on the caller's stream;
-// the others, one after another, beside it on the library's second stream
-// (their latency-bound small grids fill the large group's gaps).  Each group
-// has its own region and control area of the workspace.
+// beside it the second largest on the library's second stream and the
+// others, one after another, on a third (their latency-bound small grids fill
+// the large group's gaps).  Each group has its own region and control area
+// of the workspace.
 namespace {
 struct BatchGroup {
     int ng = 0;
@@ -1675,11 +1677,14 @@ int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts
     if (gs.size() == 1) {
         e = run(0, (hipStream_t)stream);
     } else {
-        // the smaller groups on the second stream, in a worker thread (each
-        // group reads back its norms from the host between its steps)
-        SideStream *S = nullptr;
-        if ((e = side_stream(&S)))
-            return e;
+        // the second largest group on the second stream, the rest one after
+        // another on a third, each from a worker thread (a group reads back
+        // its norms from the host between its steps)
+        const int nside = gs.size() > 2 ? 2 : 1;
+        SideStream *S[2] = {nullptr, nullptr};
+        for (int q = 0; q < nside; q++)
+            if ((e = side_stream(&S[q], q)))
+                return e;
         int dev = 0;
         PM_HIP(hipGetDevice(&dev));
         hipEvent_t ready = nullptr, done = nullptr;
@@ -1688,39 +1693,49 @@ int mg_scalar_solve_batched(const pm_problem *probs, int nprob, const pm_mg_opts
             (void)hipEventDestroy(ready);
             return PM_EHIP;
         }
-        if (hipEventRecord(ready, (hipStream_t)stream) != hipSuccess || hipStreamWaitEvent(S->s, ready, 0) != hipSuccess) {
+        bool ordered = hipEventRecord(ready, (hipStream_t)stream) == hipSuccess;
+        for (int q = 0; q < nside; q++)
+            ordered = ordered && hipStreamWaitEvent(S[q]->s, ready, 0) == hipSuccess;
+        if (!ordered) {
             (void)hipEventDestroy(ready);
             (void)hipEventDestroy(done);
             return PM_EHIP;
         }
-        int ex = PM_OK;
-        auto rest = [&]() {
+        int ex[2] = {PM_OK, PM_OK};
+        auto rest = [&](int q) {
             if (hipSetDevice(dev) != hipSuccess) {
-                ex = PM_EHIP;
+                ex[q] = PM_EHIP;
                 return;
             }
-            for (size_t k = 1; k < gs.size() && !ex; k++)
-                ex = run(k, S->s);
+            const size_t k0 = 1 + (size_t)q, k1 = q == 0 && nside == 2 ? 2 : gs.size();
+            for (size_t k = k0; k < k1 && !ex[q]; k++)
+                ex[q] = run(k, S[q]->s);
         };
-        std::thread worker;
-        bool threaded = true;
-        try {
-            worker = std::thread(rest);
-        } catch (...) {  // no thread: the same work from this thread, after the largest group's
-            threaded = false;
+        std::thread worker[2];
+        bool threaded[2] = {false, false};
+        for (int q = 0; q < nside; q++) {
+            try {
+                worker[q] = std::thread(rest, q);
+                threaded[q] = true;
+            } catch (...) {  // no thread: the same work from this thread, after the largest group's
+            }
         }
         e = run(0, (hipStream_t)stream);
-        if (threaded)
-            worker.join();
-        else
-            rest();
-        // on every path the caller's stream waits for the second stream's work
-        const bool waited =
-            hipEventRecord(done, S->s) == hipSuccess && hipStreamWaitEvent((hipStream_t)stream, done, 0) == hipSuccess;
+        for (int q = 0; q < nside; q++) {
+            if (threaded[q])
+                worker[q].join();
+            else
+                rest(q);
+        }
+        // on every path the caller's stream waits for the side streams' work
+        bool waited = true;
+        for (int q = 0; q < nside; q++)
+            waited = waited && hipEventRecord(done, S[q]->s) == hipSuccess &&
+                     hipStreamWaitEvent((hipStream_t)stream, done, 0) == hipSuccess;
         (void)hipEventDestroy(ready);
         (void)hipEventDestroy(done);
-        if (!e)
-            e = ex;
+        for (int q = 0; q < nside && !e; q++)
+            e = ex[q];
         if (!e && !waited)
             e = PM_EHIP;
     }
