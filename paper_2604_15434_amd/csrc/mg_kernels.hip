@@ -300,11 +300,11 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau(LevelView<R> C, const R *__r
 
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled)
+                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled, bool zero_iterate)
 {
     const int acc_only = (accumulate_only || C.tr == nullptr) ? 1 : 0;
     Span spt;
-    if (launch_fas_tau_tiled<R>(C, xr, xb, rs, sc, nonlinear, acc_only, st, tiled, &spt)) {
+    if (launch_fas_tau_tiled<R>(C, xr, xb, rs, sc, nonlinear, acc_only, st, tiled, &spt, zero_iterate)) {
         launch_finalize(rs, spt, 2, csum, st);
         return;
     }
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer(LevelView<double> F, con
 bool launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                                  const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs,
                                  SolveConsts sc, bool nonlinear, hipStream_t st, int tiled, double *lag64,
-                                 double *lag32, const MixedCorr *corr)
+                                 double *lag32, const MixedCorr *corr, bool zero_iterate)
 {
     auto finish = [&](const Span &s) {
         if (lag64 && lag32)
@@ -893,7 +893,8 @@ bool launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr,
             launch_finalize(rs, s, 6, rs.out, st);
     };
     Span spt;
-    if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt, corr)) {
+    if (launch_mixed_outer_tiled(F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, nonlinear, st, tiled, &spt, corr,
+                                 zero_iterate)) {
         finish(spt);
         return true;
     }
@@ -1111,9 +1112,9 @@ template void launch_residual_restrict<float>(const LevelView<float> &, const fl
                                               const LevelView<float> &, float *, float *, ReduceSlot, SolveConsts,
                                               bool, hipStream_t, bool, int);
 template void launch_fas_tau<double>(const LevelView<double> &, const double *, const double *, double *, ReduceSlot,
-                                     SolveConsts, bool, bool, hipStream_t, int);
+                                     SolveConsts, bool, bool, hipStream_t, int, bool);
 template void launch_fas_tau<float>(const LevelView<float> &, const float *, const float *, double *, ReduceSlot,
-                                    SolveConsts, bool, bool, hipStream_t, int);
+                                    SolveConsts, bool, bool, hipStream_t, int, bool);
 template void launch_prolong_correct<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
                                              const double *, const double *, hipStream_t, int);
 template void launch_prolong_correct<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,

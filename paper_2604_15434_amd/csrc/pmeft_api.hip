@@ -814,7 +814,9 @@ constexpr double kMixedStall = 0.36;  // an outer step must reduce the residual 
 
 // final_residual = false: once the cycle budget is spent, the last outer
 // residual (which changes nothing but the report) and its readback are
-// skipped; for callers that read no residual.  For every active slot of G
+// skipped; for callers that read no residual.  zero_start: the master
+// iterate holds zeros (every caller clears it first) and the first V-cycle
+// is a full-multigrid start.  For every active slot of G
 // (see solve_f64); slots that finish in FP64 do so together, after the FP32
 // phase of the whole group.
 static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool nl, const pm_mg_opts &o,
@@ -830,8 +832,9 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
     const long long N = C.P.N;
     LevelView<double> F64 = make_view<double>(C.P.n[0], 1.0 / C.P.n[0], C.at<double>(C.P.delta64[0]), nullptr, nullptr);
     const long long half = F64.half;
-    // exact initial mean of Lq64
-    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, true, C.st, H.tiled);
+    // exact initial mean of Lq64 (zero_start: the master iterate is zero,
+    // which the level's tiled kernels then take without reading it)
+    launch_fas_tau<double>(F64, master, master + half, C.csum64, C.rs, sc, nl, true, C.st, H.tiled, zero_start);
     ReduceSlot ro = C.rs;
     ro.out = C.outer_out;
     // the FP32 correction equation of a linear problem has no source term
@@ -888,7 +891,8 @@ static int solve_mixed(Ctx &C, GroupRun &G, double *master, SolveConsts sc, bool
         // (its final stage also sets the lagged means for the next outer
         // residual and the FP32 level 0)
         if (!launch_mixed_outer_residual(F64, cur, cur + half, C.csum64, H.L[0], H.xr(0), H.xb(0), ro, sc, nl, C.st,
-                                         H.tiled, C.csum64, H.csum_cur(0), fused ? &mc : nullptr))
+                                         H.tiled, C.csum64, H.csum_cur(0), fused ? &mc : nullptr,
+                                         zero_start && it == 0))
             return PM_EINVAL;
         if (fused)
             std::swap(cur, alt);

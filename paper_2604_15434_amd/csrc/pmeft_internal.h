@@ -286,9 +286,11 @@ void launch_residual_restrict(const LevelView<R> &F, const R *xr, const R *xb, c
 
 // Coarse FAS source: tau += lap x - Lq(x) (unless accumulate_only or the
 // level has no tau); writes sum(Lq + tau) per colour into csum[0..1].
+// zero_iterate: x is known to be zero (nothing of it is read where the
+// level tiles; the sums are bitwise those of reading the zeros).
 template <typename R>
 void launch_fas_tau(const LevelView<R> &C, const R *xr, const R *xb, double *csum, ReduceSlot rs, SolveConsts sc,
-                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled = 0);
+                    bool nonlinear, bool accumulate_only, hipStream_t st, int tiled = 0, bool zero_iterate = false);
 
 // The 2.5D-tiled variants (tile_kernels.hip): return false, launching
 // nothing, where the level is too small or its shape does not tile; else
@@ -299,10 +301,12 @@ bool launch_residual_restrict_tiled(const LevelView<R> &F, const R *xr, const R 
                                     bool nonlinear, hipStream_t st, int tiled, Span *sp_out);
 template <typename R>
 bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, ReduceSlot rs, SolveConsts sc,
-                          bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out);
+                          bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out,
+                          bool zero_iterate = false);
 bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                               const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs, SolveConsts sc,
-                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr);
+                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr,
+                              bool zero_iterate);
 // Whether the mixed outer residual of a level of n cells per side runs tiled
 // (and can therefore take a pending correction).
 bool mixed_outer_tiles(int n, int tiled);
@@ -355,7 +359,8 @@ void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int 
 bool launch_mixed_outer_residual(const LevelView<double> &F64, const double *xr, const double *xb,
                                  const double *csum64, const LevelView<float> &F32, float *x32r, float *x32b,
                                  ReduceSlot rs, SolveConsts sc, bool nonlinear, hipStream_t st, int tiled = 0,
-                                 double *lag64 = nullptr, double *lag32 = nullptr, const MixedCorr *corr = nullptr);
+                                 double *lag64 = nullptr, double *lag32 = nullptr, const MixedCorr *corr = nullptr,
+                                 bool zero_iterate = false);
 // The correction of MixedCorr applied on its own: x64 += fl32(x32 - fl32(x64))
 // (nonlinear) or x64 += x32 (linear).
 void launch_mixed_correct(double *x64, const float *x32r, const float *x32b, long long half, bool nonlinear,

@@ -171,8 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_residual_restrict_tile(LevelView<R> 
 
 // --------------------------------------------------------- coarse FAS source
 // As k_fas_tau: tau += lap x - Lq(x) (in FP64, stored as R) unless
-// accumulate_only; acc[colour] += Lq + tau.
-template <typename R, bool NL, int TK, int PL>
+// accumulate_only; acc[colour] += Lq + tau.  ZX: x is zero (nothing of it is
+// loaded; its stencil terms are the zeros the general path computes).
+template <typename R, bool NL, int TK, int PL, bool ZX>
 __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R *__restrict__ xr,
                                                          const R *__restrict__ xb, ReduceSlot rs, SolveConsts sc,
                                                          Span sp, unsigned ntiles, int accumulate_only, Group grp)
@@ -188,14 +189,17 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
     const int n = L.n, nh = L.nh, nI = n / PL, nK = nh / TK;
     const double ih2 = 1.0 / (L.h * L.h);
     const int tp = threadIdx.x / TK, tk = threadIdx.x % TK;
+    const unsigned plane = (unsigned)n * nh;
     double acc[2] = {0.0, 0.0};
     PlaneRing<R, TK, TJ> ring;
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
         int ib, kb, jb;
         tile_coords(tile, nI, nK, ib, kb, jb);
         const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
-        ring.setup(xr, xb, n, nh, j0, k0);
-        ring.prime(win, i0);
+        if constexpr (!ZX) {
+            ring.setup(xr, xb, n, nh, j0, k0);
+            ring.prime(win, i0);
+        }
         const unsigned e00 = ((unsigned)i0 * n + j0 + 2 * tp) * nh + k0 + tk;
         R dcur[2][2], tcur[2][2], dnxt[2][2], tnxt[2][2];
 #pragma unroll
@@ -213,12 +217,13 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
             const int i = i0 + t;
             const int sm = t & 3, s0 = (t + 1) & 3, sp1 = (t + 2) & 3;
             if (t + 1 < PL) {
-                ring.fetch(i + 2);
+                if constexpr (!ZX)
+                    ring.fetch(i + 2);
 #pragma unroll
                 for (int b = 0; b < 2; b++)
 #pragma unroll
                     for (int c = 0; c < 2; c++) {
-                        const unsigned e = e00 + (unsigned)(t + 1) * ring.plane + b * nh;
+                        const unsigned e = e00 + (unsigned)(t + 1) * plane + b * nh;
                         dnxt[b][c] = (c ? L.db : L.dr)[e];
                         const R *tc = c ? L.tb : L.tr;
                         tnxt[b][c] = tc ? tc[e] : (R)0;
@@ -230,14 +235,15 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     const int p = (i + j + c) & 1;
-                    double tsh;
-                    const double S = ring_stencil<double, R, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, NL, tsh);
+                    double tsh = 0.0, S = 0.0;
+                    if constexpr (!ZX)
+                        S = ring_stencil<double, R, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, NL, tsh);
                     const double bsrc = sc.beta * (double)dcur[b][c];
                     int isv;
                     const double lq = root_lap<double>(bsrc, tsh * ih2 * ih2, sc, NL, isv);
                     double tv = (double)tcur[b][c];
                     if (!accumulate_only) {
-                        const double lap = (S - 6.0 * (double)win[c][s0][a][tk + 1]) * ih2;
+                        const double lap = (S - 6.0 * (ZX ? 0.0 : (double)win[c][s0][a][tk + 1])) * ih2;
                         tv += lap - lq;
                         (c ? L.tb : L.tr)[((unsigned)i * n + j) * nh + k0 + tk] = (R)tv;
                         tv = (double)(R)tv;
@@ -246,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
                 }
             }
             if (t + 1 < PL) {
-                ring.store(win, (t + 3) & 3);
+                if constexpr (!ZX)
+                    ring.store(win, (t + 3) & 3);
 #pragma unroll
                 for (int b = 0; b < 2; b++)
 #pragma unroll
@@ -268,8 +275,10 @@ __global__ __launch_bounds__(kBlock) void k_fas_tau_tile(LevelView<R> L, const R
 // x32 = 0 (linear); acc[4 + colour] += Lq32 + tau32.  CORR: the iterate is
 // first corrected by the FP32 result of the previous V-cycles (MixedCorr),
 // value by value as the window loads it, with k_mixed_correct's arithmetic;
-// the corrected values of the tile's own cells go to cr.yr / cr.yb.
-template <bool NL, int TK, int PL, bool CORR>
+// the corrected values of the tile's own cells go to cr.yr / cr.yb.  ZX: the
+// iterate is zero (a solve's first step from a zero start), so nothing of it
+// is loaded and its stencil terms are the zeros the general path computes.
+template <bool NL, int TK, int PL, bool CORR, bool ZX>
 __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F, const double *__restrict__ xr,
                                                              const double *__restrict__ xb,
                                                              const double *__restrict__ csum64, LevelView<float> G,
@@ -305,7 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
     // the ring's), loaded with them and folded in just before the LDS store
     const float *vsrc[Ring::PER];
     float vpre[Ring::PER];
+    const unsigned plane = (unsigned)n * nh;
     auto fetch = [&](int ii) {
+        if constexpr (ZX)
+            return;
         ring.fetch(ii);
         if constexpr (CORR) {
             const int iw = ii < 0 ? ii + n : (ii >= n ? ii - n : ii);
@@ -326,13 +338,15 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                     ring.pre[u] = x + (double)d;
                 }
         }
-        ring.store(win, slot);
+        if constexpr (!ZX)
+            ring.store(win, slot);
     };
     for (unsigned tile = span_block(sp); tile < ntiles; tile += sp.nblocks) {
         int ib, kb, jb;
         tile_coords(tile, nI, nK, ib, kb, jb);
         const int i0 = ib * PL, j0 = jb * TJ, k0 = kb * TK;
-        ring.setup(xr, xb, n, nh, j0, k0);
+        if constexpr (!ZX)
+            ring.setup(xr, xb, n, nh, j0, k0);
         if constexpr (CORR) {
 #pragma unroll
             for (int u = 0; u < Ring::PER; u++) {
@@ -366,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                 for (int b = 0; b < 2; b++)
 #pragma unroll
                     for (int c = 0; c < 2; c++)
-                        dnxt[b][c] = (c ? F.db : F.dr)[e00 + (unsigned)(t + 1) * ring.plane + b * nh];
+                        dnxt[b][c] = (c ? F.db : F.dr)[e00 + (unsigned)(t + 1) * plane + b * nh];
             }
 #pragma unroll
             for (int b = 0; b < 2; b++) {
@@ -375,9 +389,11 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
 #pragma unroll
                 for (int c = 0; c < 2; c++) {
                     const int p = (i + j + c) & 1;
-                    double tsh;
-                    const double S = ring_stencil<double, double, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, NL, tsh);
-                    const double x64 = win[c][s0][a][tk + 1];
+                    double tsh = 0.0, S = 0.0, x64 = 0.0;
+                    if constexpr (!ZX) {
+                        S = ring_stencil<double, double, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, NL, tsh);
+                        x64 = win[c][s0][a][tk + 1];
+                    }
                     if constexpr (CORR)
                         (c ? cr.yb : cr.yr)[e] = x64;
                     int isv;
@@ -392,9 +408,9 @@ __global__ __launch_bounds__(kBlock) void k_mixed_outer_tile(LevelView<double> F
                         (c ? G.tb : G.tr)[e] = (float)r;
                         acc[4 + c] += (double)(float)r;
                     } else {
-                        float tsh32;
-                        const float S32 =
-                            ring_stencil<float, double, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, true, tsh32);
+                        float tsh32 = 0.0f, S32 = 0.0f;
+                        if constexpr (!ZX)
+                            S32 = ring_stencil<float, double, TK, TJ>(win, c, sm, s0, sp1, a, tk, p, true, tsh32);
                         const float x32 = (float)x64;
                         int isv32;
                         const float lq32 =
@@ -582,22 +598,29 @@ bool launch_residual_restrict_tiled(const LevelView<R> &F, const R *xr, const R 
 
 template <typename R>
 bool launch_fas_tau_tiled(const LevelView<R> &L, const R *xr, const R *xb, ReduceSlot rs, SolveConsts sc,
-                          bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out)
+                          bool nonlinear, int accumulate_only, hipStream_t st, int tiled, Span *sp_out,
+                          bool zero_iterate)
 {
     PairTiles g;
     if (!pair_tiles(L.n, tiled, g))
         return false;
+#define PM_FT1(NLV, TKV, PLV, ZV)                                                                                      \
+    hipLaunchKernelGGL((k_fas_tau_tile<R, NLV, TKV, PLV, ZV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, L, xr,  \
+                       xb, rs, sc, g.sp, g.ntiles, accumulate_only, cur_group())
 #define PM_FT(TKV, PLV)                                                                                                \
     do {                                                                                                               \
-        if (nonlinear)                                                                                                 \
-            hipLaunchKernelGGL((k_fas_tau_tile<R, true, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, L,  \
-                               xr, xb, rs, sc, g.sp, g.ntiles, accumulate_only, cur_group());                          \
+        if (nonlinear && zero_iterate)                                                                                 \
+            PM_FT1(true, TKV, PLV, true);                                                                              \
+        else if (nonlinear)                                                                                            \
+            PM_FT1(true, TKV, PLV, false);                                                                             \
+        else if (zero_iterate)                                                                                         \
+            PM_FT1(false, TKV, PLV, true);                                                                             \
         else                                                                                                           \
-            hipLaunchKernelGGL((k_fas_tau_tile<R, false, TKV, PLV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, L, \
-                               xr, xb, rs, sc, g.sp, g.ntiles, accumulate_only, cur_group());                          \
+            PM_FT1(false, TKV, PLV, false);                                                                            \
     } while (0)
     PM_PAIR_DISPATCH(PM_FT)
 #undef PM_FT
+#undef PM_FT1
     *sp_out = g.sp;
     return true;
 }
@@ -610,28 +633,35 @@ bool mixed_outer_tiles(int n, int tiled)
 
 bool launch_mixed_outer_tiled(const LevelView<double> &F64, const double *xr, const double *xb, const double *csum64,
                               const LevelView<float> &F32, float *x32r, float *x32b, ReduceSlot rs, SolveConsts sc,
-                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr)
+                              bool nonlinear, hipStream_t st, int tiled, Span *sp_out, const MixedCorr *corr,
+                              bool zero_iterate)
 {
     PairTiles g;
     if (!pair_tiles(F64.n, tiled, g))
         return false;
     const MixedCorr cr = corr ? *corr : MixedCorr{};
-#define PM_MO1(NLV, TKV, PLV, CV)                                                                                      \
-    hipLaunchKernelGGL((k_mixed_outer_tile<NLV, TKV, PLV, CV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st, F64,   \
-                       xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cr, cur_group())
+#define PM_MO1(NLV, TKV, PLV, CV, ZV)                                                                                  \
+    hipLaunchKernelGGL((k_mixed_outer_tile<NLV, TKV, PLV, CV, ZV>), group_grid(g.sp.nblocks), dim3(kBlock), 0, st,    \
+                       F64, xr, xb, csum64, F32, x32r, x32b, rs, sc, g.sp, g.ntiles, cr, cur_group())
+#define PM_MO2(NLV, TKV, PLV)                                                                                          \
+    do {                                                                                                               \
+        if (corr)                                                                                                      \
+            PM_MO1(NLV, TKV, PLV, true, false);                                                                        \
+        else if (zero_iterate)                                                                                         \
+            PM_MO1(NLV, TKV, PLV, false, true);                                                                        \
+        else                                                                                                           \
+            PM_MO1(NLV, TKV, PLV, false, false);                                                                       \
+    } while (0)
 #define PM_MO(TKV, PLV)                                                                                                \
     do {                                                                                                               \
-        if (nonlinear && corr)                                                                                         \
-            PM_MO1(true, TKV, PLV, true);                                                                              \
-        else if (nonlinear)                                                                                            \
-            PM_MO1(true, TKV, PLV, false);                                                                             \
-        else if (corr)                                                                                                 \
-            PM_MO1(false, TKV, PLV, true);                                                                             \
+        if (nonlinear)                                                                                                 \
+            PM_MO2(true, TKV, PLV);                                                                                    \
         else                                                                                                           \
-            PM_MO1(false, TKV, PLV, false);                                                                            \
+            PM_MO2(false, TKV, PLV);                                                                                   \
     } while (0)
     PM_PAIR_DISPATCH(PM_MO)
 #undef PM_MO
+#undef PM_MO2
 #undef PM_MO1
     *sp_out = g.sp;
     return true;
@@ -688,12 +718,12 @@ template bool launch_residual_restrict_tiled<float>(const LevelView<float> &, co
                                                     const double *, const LevelView<float> &, float *, float *,
                                                     ReduceSlot, SolveConsts, bool, hipStream_t, int, Span *);
 template bool launch_fas_tau_tiled<double>(const LevelView<double> &, const double *, const double *, ReduceSlot,
-                                           SolveConsts, bool, int, hipStream_t, int, Span *);
+                                           SolveConsts, bool, int, hipStream_t, int, Span *, bool);
 template bool launch_prolong_tiled<double>(const LevelView<double> &, double *, double *, const LevelView<double> &,
                                            const double *, const double *, bool, hipStream_t, int);
 template bool launch_prolong_tiled<float>(const LevelView<float> &, float *, float *, const LevelView<float> &,
                                           const float *, const float *, bool, hipStream_t, int);
 template bool launch_fas_tau_tiled<float>(const LevelView<float> &, const float *, const float *, ReduceSlot,
-                                          SolveConsts, bool, int, hipStream_t, int, Span *);
+                                          SolveConsts, bool, int, hipStream_t, int, Span *, bool);
 
 }  // namespace pmeft
