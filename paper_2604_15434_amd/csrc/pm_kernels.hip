@@ -212,8 +212,8 @@ void launch_deposit_fixed(const void *pos, long long np, pm_dtype dt, int ng, un
 // integer atomics, the same 2^-40 rounding of every weight as the scatter,
 // so the grid is bitwise the scatter's) and writes each cell once: no global
 // atomics and no clearing of the grid.  k_row_index finds the rows' first
-// particles and flags input that is not in base-row order (or has unusable
-// coordinates); then the scatter deposits instead.  The choice is made on
+// particles and flags input that is not in base-row order (or has an
+// unusable x or y coordinate); then the scatter deposits instead.  The choice is made on
 // the device, so the deposit still only enqueues.
 template <typename Tp>
 __device__ __forceinline__ int base_row(const Tp *__restrict__ pos, unsigned np, unsigned p, int ng)
@@ -289,7 +289,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit_gather(const Tp *__restrict_
                     double fx, fy, fz;
                     cic_axis((double)pos[p], ng, x0, x1, fx);
                     cic_axis((double)pos[np + p], ng, y0, y1, fy);
-                    cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz);
+                    // (x and y were checked by k_row_index; a particle whose
+                    // z is unusable is skipped, as the scatter skips it)
+                    if (!cic_axis((double)pos[2 * (size_t)np + p], ng, z0, z1, fz))
+                        continue;
                     // the scatter's weight products, in its order
                     const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
 #pragma unroll

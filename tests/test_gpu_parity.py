@@ -86,6 +86,35 @@ def test_sorted_deposit_gathers_the_same_grid(P, ng, dtype):
     assert torch.equal(rho_swapped, rho_scatter)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_sorted_deposit_skips_unusable_z_like_the_scatter(P, dtype):
+    """Base-row order depends on x and y only, so sorted particles whose z is
+    NaN or infinite still take the gather; the gather skips them as the
+    scatter does, and both grids equal the oracle's deposit of the other
+    particles (normalised by the full particle count)."""
+    ng = 32
+    pos_np, _ = lognormal_particles(ng, 500.0 * ng / 256, seed=5)
+    pos = torch.from_numpy(pos_np).to("cuda", dtype)
+    P.pm_sort_particles(pos, ng)
+    bad = [7, 1000, pos.shape[1] - 3]
+    pos[2, bad[0]] = float("nan")
+    pos[2, bad[1]] = float("inf")
+    pos[2, bad[2]] = -float("inf")
+    rho_gather = torch.empty((ng, ng, ng), dtype=dtype, device="cuda")
+    P.pm_deposit(pos, ng, rho_gather)
+    swapped = pos.clone()
+    swapped[:, [10, pos.shape[1] - 10]] = swapped[:, [pos.shape[1] - 10, 10]]
+    rho_scatter = torch.empty_like(rho_gather)
+    P.pm_deposit(swapped, ng, rho_scatter)
+    assert torch.equal(rho_gather, rho_scatter)
+    keep = np.ones(pos.shape[1], dtype=bool)
+    keep[bad] = False
+    host = pos.cpu().numpy().astype(np.float64)
+    ref = oracle.cic_deposit(host[:, keep], ng) * (keep.sum() / keep.size)
+    tol = 1e-10 if dtype == torch.float64 else 2e-5 * max(1.0, ref.max())
+    assert np.abs(rho_gather.cpu().numpy() - ref).max() < tol
+
+
 # ------------------------------------------------------------------ Poisson
 @pytest.mark.parametrize("ng", [32, 48])
 def test_poisson_matches_fft_solution(P, ng):
