@@ -335,7 +335,9 @@ void launch_deposit_auto(const void *pos, long long np, pm_dtype dt, int ng, uns
     if (nb >= 8)
         nb -= nb % 8;
     const unsigned nrows = (unsigned)ng * ng;
-    unsigned gb = nrows < 4096u ? nrows : 4096u;
+    // 16384 blocks (4 target rows each at 256^3): the gather at 256^3 takes
+    // 8 % less time than with 4096 blocks of 16 rows
+    unsigned gb = nrows < 16384u ? nrows : 16384u;
     if (gb >= 8)
         gb -= gb % 8;
     const unsigned rpb = (nrows + gb - 1) / gb;
