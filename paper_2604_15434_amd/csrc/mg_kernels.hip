@@ -682,7 +682,9 @@ void launch_cast_f64_f32(const double *src, float *dst, long long n, hipStream_t
     hipLaunchKernelGGL(k_cast_f64_f32, group_grid(sp.nblocks), dim3(kBlock), 0, st, src, dst, sp, cur_group());
 }
 
-// natural [i][j][k] (float or double) -> packed double, y = scale * x + shift
+// natural [i][j][k] (float or double) -> packed double, y = scale * x + shift.
+// A thread takes the natural pair k = 2 kh, 2 kh + 1 of row (i, j): one red
+// and one black cell, both halves of a cache line read at once.
 template <typename Tn>
 __global__ __launch_bounds__(kBlock) void k_nat_to_packed(const Tn *__restrict__ nat, double *__restrict__ packed, int n,
                                                           double scale, double shift, Span sp, Group grp)
@@ -692,21 +694,22 @@ __global__ __launch_bounds__(kBlock) void k_nat_to_packed(const Tn *__restrict__
     packed = gshift(packed, go);
     const int nh = n / 2;
     const unsigned half = (unsigned)n * n * nh;
-    PM_SPAN_LOOP(e, sp)
+    PM_SPAN_LOOP(ec, sp)
     {
-        const int c = e >= half;
-        const unsigned ec = e - (c ? half : 0u);
         int i, j, kh;
         split(ec, nh, n, i, j, kh);
-        const int k = 2 * kh + ((i + j + c) & 1);
-        packed[e] = scale * (double)nat[((unsigned)i * n + j) * n + k] + shift;
+        const Tn *in = nat + ((unsigned)i * n + j) * n + 2 * kh;
+        const double v0 = scale * (double)in[0] + shift, v1 = scale * (double)in[1] + shift;
+        const bool red_even = ((i + j) & 1) == 0;  // the red cell of the pair sits at k = 2 kh + ((i + j) & 1)
+        packed[ec] = red_even ? v0 : v1;
+        packed[half + ec] = red_even ? v1 : v0;
     }
 }
 
 void launch_natural_to_packed(const void *nat, pm_dtype dt, double *packed, int n, double scale, double shift,
                               hipStream_t st)
 {
-    const Span sp = make_span((unsigned long long)n * n * n);
+    const Span sp = make_span((unsigned long long)n * n * (n / 2));
     if (dt == PM_F64)
         hipLaunchKernelGGL((k_nat_to_packed<double>), group_grid(sp.nblocks), dim3(kBlock), 0, st,
                            (const double *)nat, packed, n, scale, shift, sp, cur_group());
@@ -716,7 +719,10 @@ void launch_natural_to_packed(const void *nat, pm_dtype dt, double *packed, int 
 }
 
 // packed double -> natural, subtracting sum_ptr[0] / n^3 (the mean) if given
-// and adding `add`
+// and adding `add`.  A thread writes the natural pair k = 2 kh, 2 kh + 1 of
+// row (i, j) from its red and its black cell, so both halves of a cache line
+// are written together (red and black a half-array apart in time left the
+// writes of each line split).
 template <typename Tn>
 __global__ __launch_bounds__(kBlock) void k_packed_to_nat(const double *__restrict__ packed, Tn *__restrict__ nat, int n,
                                                           const double *sum_ptr, double add, Span sp, Group grp)
@@ -728,21 +734,22 @@ __global__ __launch_bounds__(kBlock) void k_packed_to_nat(const double *__restri
     const int nh = n / 2;
     const unsigned half = (unsigned)n * n * nh;
     const double shift = sum_ptr ? sum_ptr[0] / (2.0 * (double)half) : 0.0;
-    PM_SPAN_LOOP(e, sp)
+    PM_SPAN_LOOP(ec, sp)
     {
-        const int c = e >= half;
-        const unsigned ec = e - (c ? half : 0u);
         int i, j, kh;
         split(ec, nh, n, i, j, kh);
-        const int k = 2 * kh + ((i + j + c) & 1);
-        nat[((unsigned)i * n + j) * n + k] = (Tn)(packed[e] - shift + add);
+        const Tn r = (Tn)(packed[ec] - shift + add), b = (Tn)(packed[half + ec] - shift + add);
+        const bool red_even = ((i + j) & 1) == 0;  // the red cell of the pair sits at k = 2 kh + ((i + j) & 1)
+        Tn *out = nat + ((unsigned)i * n + j) * n + 2 * kh;
+        out[0] = red_even ? r : b;
+        out[1] = red_even ? b : r;
     }
 }
 
 void launch_packed_to_natural(const double *packed, void *nat, pm_dtype dt, int n, double add, const double *sum_ptr,
                               hipStream_t st)
 {
-    const Span sp = make_span((unsigned long long)n * n * n);
+    const Span sp = make_span((unsigned long long)n * n * (n / 2));
     if (dt == PM_F64)
         hipLaunchKernelGGL((k_packed_to_nat<double>), group_grid(sp.nblocks), dim3(kBlock), 0, st, packed,
                            (double *)nat, n, sum_ptr, add, sp, cur_group());
