@@ -23,6 +23,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace pmeft {
 
 namespace {
@@ -680,6 +682,29 @@ void launch_cast_f64_f32(const double *src, float *dst, long long n, hipStream_t
 {
     const Span sp = make_span(n);
     hipLaunchKernelGGL(k_cast_f64_f32, group_grid(sp.nblocks), dim3(kBlock), 0, st, src, dst, sp, cur_group());
+}
+
+// Device-to-device copy in 16-byte words: the runtime's copy kernel moved
+// about 2.6 TB/s at 128 MiB and 1.6 TB/s at 1 GiB here.  Unaligned or
+// ragged copies go to hipMemcpyAsync.
+__global__ __launch_bounds__(kBlock) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   unsigned long long n)
+{
+    for (unsigned long long q = (unsigned long long)blockIdx.x * kBlock + threadIdx.x; q < n;
+         q += (unsigned long long)gridDim.x * kBlock)
+        dst[q] = src[q];
+}
+
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0)
+        return hipSuccess;
+    if ((((uintptr_t)dst) | ((uintptr_t)src) | bytes) & 15u)
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st);
+    const unsigned long long n = bytes / 16;
+    const unsigned nb = (unsigned)std::min<unsigned long long>((n + kBlock - 1) / kBlock, 65536ull);
+    hipLaunchKernelGGL(k_copy16, dim3(nb), dim3(kBlock), 0, st, (const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
 }
 
 // natural [i][j][k] (float or double) -> packed double, y = scale * x + shift.

@@ -710,7 +710,7 @@ static int read_group(Ctx &C, const GroupRun &G, const double *dev, double *host
 static int slot_copy(Ctx &C, const GroupRun &G, int s, void *dst, const void *src, size_t bytes)
 {
     const long long o = (long long)s * G.stride;
-    PM_HIP(hipMemcpyAsync((char *)dst + o, (const char *)src + o, bytes, hipMemcpyDeviceToDevice, C.st));
+    PM_HIP(launch_copy_bytes((char *)dst + o, (const char *)src + o, bytes, C.st));
     return PM_OK;
 }
 
@@ -1140,8 +1140,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
             G.P.delta64[l] = C.P.dalt64[l];
             G.P.d32[l] = C.P.dalt32[l];
         }
-        PM_HIP(hipMemcpyAsync(G.at<double>(G.P.delta64[0]), save, sizeof(double) * C.P.N, hipMemcpyDeviceToDevice,
-                              C.st));
+        PM_HIP(launch_copy_bytes(G.at<double>(G.P.delta64[0]), save, sizeof(double) * C.P.N, C.st));
     }
     e = unet_add_learned_source(o.learned_ws, ng, G.at<double>(G.P.delta64[0]), C.st);
     if (e)
@@ -1156,7 +1155,7 @@ static int learned_guess(Ctx &C, const pm_eft_params &p, const pm_eft_coeffs &cf
         return e;
     if (separate)
         return launched();
-    PM_HIP(hipMemcpyAsync(d0, save, sizeof(double) * C.P.N, hipMemcpyDeviceToDevice, C.st));
+    PM_HIP(launch_copy_bytes(d0, save, sizeof(double) * C.P.N, C.st));
     delta_levels(C);
     return launched();
 }

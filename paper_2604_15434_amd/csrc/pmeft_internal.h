@@ -336,6 +336,8 @@ void launch_restrict_field(int nc, const R *fr, const R *fb, R *cr, R *cb, hipSt
 
 // FP64 fine delta -> FP32 copy (mixed precision hierarchy).
 void launch_cast_f64_f32(const double *src, float *dst, long long n, hipStream_t st);
+// device-to-device copy (16-byte words where aligned, else hipMemcpyAsync)
+hipError_t launch_copy_bytes(void *dst, const void *src, size_t bytes, hipStream_t st);
 
 // Natural [i][j][k] <-> packed red/black conversion; dtype of the natural
 // array is float or double, the packed array is double.
